@@ -1,0 +1,489 @@
+"""Pins of the FP64 oracle against facts fixed outside the oracle itself.
+
+Each test names what pins it: a closed form of the potential on a perfect
+crystal, published crystal properties, the mathematics of forces and virials
+(F = -grad E, W = -dE/dstrain, invariances), or brute-force enumeration.
+All of these run on the CPU.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_1607_02904_amd import inputs
+from oracle import params
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+F = params.IDX
+EV_A3_TO_GPA = 160.21766208
+
+
+# ---------------------------------------------------------------------------
+# closed forms (written from the Tersoff forms, independent of the oracle code)
+# ---------------------------------------------------------------------------
+
+def _fc(r, R, D):
+    if r < R - D:
+        return 1.0
+    if r > R + D:
+        return 0.0
+    return 0.5 - 0.5 * math.sin(math.pi / 2 * (r - R) / D)
+
+
+def _g(cos, p):
+    return p["gamma"] * (1 + p["c"] ** 2 / p["d"] ** 2 - p["c"] ** 2 / (p["d"] ** 2 + (p["h"] - cos) ** 2))
+
+
+def _b(z, beta, n):
+    return (1.0 + (beta * z) ** n) ** (-1.0 / (2.0 * n))
+
+
+def diamond_energy(a, el, R, D):
+    """Energy per atom of the perfect diamond lattice: four neighbours at
+    r1 = a sqrt(3)/4, every bond angle with cos = -1/3, equal bond lengths so
+    the exponential factor is 1; second neighbours (a/sqrt 2) outside cutoff."""
+    r1 = a * math.sqrt(3.0) / 4.0
+    assert R + D < a / math.sqrt(2.0)
+    fc = _fc(r1, R, D)
+    zeta = 3.0 * fc * _g(-1.0 / 3.0, el)
+    v = fc * (el["A"] * math.exp(-el["lam1"] * r1) - _b(zeta, el["beta"], el["n"]) * el["B"] * math.exp(-el["lam2"] * r1))
+    return 0.5 * 4.0 * v
+
+
+def zincblende_energy(a):
+    """Energy per atom of perfect zincblende SiC (Tersoff 1989 mixing): each
+    atom has four unlike neighbours; its zeta uses its own angular parameters
+    and its own beta, n; A, B (times chi), lambda1, lambda2 are mixed."""
+    si, c = params.SI_C, params.CARBON
+    r1 = a * math.sqrt(3.0) / 4.0
+    A = math.sqrt(si["A"] * c["A"])
+    B = params.CHI_SIC * math.sqrt(si["B"] * c["B"])
+    l1 = 0.5 * (si["lam1"] + c["lam1"])
+    l2 = 0.5 * (si["lam2"] + c["lam2"])
+    Rt, St = math.sqrt(si["Rt"] * c["Rt"]), math.sqrt(si["St"] * c["St"])
+    fc = _fc(r1, 0.5 * (Rt + St), 0.5 * (St - Rt))
+    e = 0.0
+    for el in (si, c):
+        zeta = 3.0 * fc * _g(-1.0 / 3.0, el)
+        v = fc * (A * math.exp(-l1 * r1) - _b(zeta, el["beta"], el["n"]) * B * math.exp(-l2 * r1))
+        e += 0.5 * 4.0 * v
+    return 0.5 * e
+
+
+def _minimise(f, lo, hi):
+    gr = (math.sqrt(5) - 1) / 2
+    a, b = lo, hi
+    for _ in range(200):
+        c, d = b - gr * (b - a), a + gr * (b - a)
+        if f(c) < f(d):
+            b = d
+        else:
+            a = c
+    x = 0.5 * (a + b)
+    return x, f(x)
+
+
+def _el(name):
+    return {"Si_B": params.SI_B, "Si_C": params.SI_C, "C": params.CARBON}[name]
+
+
+def _elem_RD(el):
+    return 0.5 * (el["Rt"] + el["St"]), 0.5 * (el["St"] - el["Rt"])
+
+
+def _load_published():
+    rows = []
+    with open(os.path.join(GOLDEN, "published_crystals.txt")) as fh:
+        for line in fh:
+            if line.startswith("#") or not line.strip():
+                continue
+            p = line.split()
+            rows.append((p[0], p[1], float(p[2]), float(p[3]), float(p[4]), float(p[5])))
+    return rows
+
+
+# ---------------------------------------------------------------------------
+# P-a: closed form and published crystal data
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name,a", [("Si_B", 5.431), ("Si_C", 5.431), ("C", 3.566)])
+def test_perfect_diamond_matches_closed_form(orc, name, a):
+    el = _el(name)
+    tab = params.single(el)
+    x, box = inputs.diamond(4, a)
+    t = np.zeros(len(x), dtype=np.int32)
+    e, f, w, ea = orc.compute(x, t, box, tab)
+    R, D = _elem_RD(el)
+    ref = diamond_energy(a, el, R, D)
+    assert abs(e / len(x) - ref) <= 1e-12 * abs(ref)
+    assert np.max(np.abs(ea - ref)) <= 1e-12 * abs(ref)
+    assert np.max(np.abs(f)) < 1e-10  # P-b on a perfect lattice
+
+
+def test_perfect_si_b_value():
+    # closed form of Si(B) at a = 5.431 A, to 12 digits
+    R, D = _elem_RD(params.SI_B)
+    assert abs(diamond_energy(5.431, params.SI_B, R, D) - (-4.630412064213)) < 5e-12
+
+
+def test_perfect_zincblende_matches_closed_form(orc):
+    x, box = inputs.diamond(4, 4.36)
+    t = inputs.zincblende_types(len(x))
+    e, f, w, ea = orc.compute(x, t, box, params.sic())
+    ref = zincblende_energy(4.36)
+    assert abs(e / len(x) - ref) <= 1e-12 * abs(ref)
+    assert np.max(np.abs(f)) < 1e-10
+
+
+@pytest.mark.parametrize("row", _load_published(), ids=lambda r: r[0])
+def test_published_lattice_constant_and_cohesive_energy(row):
+    name, struct, a_pub, e_pub, a_tol, e_tol = row
+    if struct == "diamond":
+        el = _el(name)
+        R, D = _elem_RD(el)
+        a0, e0 = _minimise(lambda a: diamond_energy(a, el, R, D), 0.8 * a_pub, 1.2 * a_pub)
+    else:
+        a0, e0 = _minimise(zincblende_energy, 0.9 * a_pub, 1.1 * a_pub)
+    assert abs(a0 - a_pub) <= a_tol
+    assert abs(e0 - e_pub) <= e_tol
+
+
+def test_si_bulk_modulus_published():
+    # Tersoff 1988: B = 0.98 Mbar for diamond Si
+    el = params.SI_B
+    R, D = _elem_RD(el)
+    a0, _ = _minimise(lambda a: diamond_energy(a, el, R, D), 5.0, 6.0)
+    h = 1e-3
+    d2 = (diamond_energy(a0 + h, el, R, D) - 2 * diamond_energy(a0, el, R, D) + diamond_energy(a0 - h, el, R, D)) / h ** 2
+    bulk = 8.0 * d2 / (9.0 * a0) * EV_A3_TO_GPA
+    assert abs(bulk - 98.0) < 2.0
+
+
+def test_four_neighbours_per_atom_on_benchmark_lattice(orc):
+    # the paper: every atom of the Si benchmark has exactly four nearest neighbours
+    with open(os.path.join(GOLDEN, "paper_benchmark_facts.txt")) as fh:
+        want = [int(l.split()[1]) for l in fh if l.startswith("nearest")][0]
+    x, t, box = inputs.si_small()
+    tab = params.single(params.SI_B, R=2.85, D=0.15)
+    count, lst = orc.neighbours(x, box, 3.0)
+    assert np.all(count == want)
+
+
+# ---------------------------------------------------------------------------
+# P-trW, P-strain: virial
+# ---------------------------------------------------------------------------
+
+def test_virial_trace_perfect_diamond(orc):
+    el = params.SI_B
+    R, D = _elem_RD(el)
+    a = 5.431
+    x, box = inputs.diamond(4, a)
+    t = np.zeros(len(x), dtype=np.int32)
+    _, _, w, _ = orc.compute(x, t, box, params.single(el))
+    h = 1e-5
+    dEda = (diamond_energy(a + h, el, R, D) - diamond_energy(a - h, el, R, D)) / (2 * h)
+    want = -a * dEda  # per atom
+    assert abs((w[0] + w[1] + w[2]) / len(x) - want) < 1e-9
+    assert abs(want - 4.674e-3) < 1e-6
+
+
+@pytest.mark.parametrize("which", ["si", "sic"])
+def test_virial_is_minus_strain_derivative(orc, which):
+    if which == "si":
+        x, t, box = inputs.si_small(sigma=0.15, ncell=2, seed=11)
+        tab = params.single(params.SI_B)
+    else:
+        cfg = inputs.sic_liquid_batch(nconf=1, nmin=200, nmax=220, seed=5)[0]
+        x, t, box = cfg
+        tab = params.sic()
+    _, _, w, _ = orc.compute(x, t, box, tab)
+    comp = [(0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2)]
+    h = 1e-5
+    for c, (al, be) in enumerate(comp):
+        def energy(eps):
+            M = np.eye(3)
+            # symmetric strain: x_beta += eps * x_alpha (and vice versa)
+            M[be, al] += eps if al == be else 0.5 * eps
+            if al != be:
+                M[al, be] += 0.5 * eps
+            xs = x @ M.T
+            bs = box * np.diag(M)  # orthorhombic boxes: only diagonal strain changes the box
+            if al != be:
+                return None
+            return orc.compute(xs, t, bs, tab)[0]
+        if al != be:
+            continue
+        d = (energy(h) - energy(-h)) / (2 * h)
+        assert abs(w[c] + d) <= 1e-7 * max(1.0, abs(d)), (c, w[c], -d)
+
+
+def test_virial_shear_from_cluster_in_vacuum(orc):
+    """Off-diagonal components: for an isolated cluster (no periodic images in
+    range) a shear of the coordinates is a pure deformation of the cluster."""
+    x, t, box = inputs.si_small(sigma=0.15, ncell=2, seed=12)
+    sel = np.linalg.norm(x - x.mean(0), axis=1) < 5.0
+    xc = x[sel] - x[sel].mean(0) + 20.0
+    tc = t[sel]
+    bigbox = np.array([40.0, 40.0, 40.0])
+    tab = params.single(params.SI_B)
+    _, _, w, _ = orc.compute(xc, tc, bigbox, tab)
+    h = 1e-5
+    for c, (al, be) in enumerate([(0, 1), (0, 2), (1, 2)]):
+        def energy(eps):
+            M = np.eye(3)
+            M[al, be] += 0.5 * eps
+            M[be, al] += 0.5 * eps
+            return orc.compute((xc - 20.0) @ M.T + 20.0, tc, bigbox, tab)[0]
+        d = (energy(h) - energy(-h)) / (2 * h)
+        assert abs(w[3 + c] + d) <= 1e-7 * max(1.0, abs(d))
+
+
+# ---------------------------------------------------------------------------
+# P-b, P-c: forces
+# ---------------------------------------------------------------------------
+
+def _fd_forces(orc, x, t, box, tab, atoms, h=1e-4):
+    out = np.zeros((len(atoms), 3))
+    for q, a in enumerate(atoms):
+        for c in range(3):
+            def E(s):
+                y = x.copy()
+                y[a, c] += s
+                return orc.compute(y, t, box, tab)[0]
+            out[q, c] = -(E(-2 * h) - 8 * E(-h) + 8 * E(h) - E(2 * h)) / (12 * h)
+    return out
+
+
+@pytest.mark.parametrize("which", ["si_b", "si_b_m1", "sic_liquid"])
+def test_forces_are_minus_energy_gradient(orc, which):
+    if which.startswith("si_b"):
+        x, t, box = inputs.si_small(sigma=0.1, ncell=2, seed=21)
+        tab = params.single(params.SI_B)
+        if which == "si_b_m1":
+            tab[..., F["m"]] = 1.0
+        # compress a little so that some pairs sit in the cutoff transition
+        x, box = x * 0.86, box * 0.86
+    else:
+        x, t, box = inputs.sic_liquid_batch(nconf=1, nmin=100, nmax=120, seed=7)[0]
+        tab = params.sic()
+    e, f, w, _ = orc.compute(x, t, box, tab)
+    rng = np.random.default_rng(3)
+    atoms = rng.choice(len(x), size=8, replace=False)
+    fd = _fd_forces(orc, x, t, box, tab, atoms)
+    err = np.linalg.norm(fd - f[atoms]) / np.linalg.norm(f[atoms])
+    assert err < 1e-8, err
+
+
+def test_transition_region_is_exercised(orc):
+    x, t, box = inputs.sic_liquid_batch(nconf=1, nmin=100, nmax=120, seed=7)[0]
+    tab = params.sic()
+    cnt, lst = orc.neighbours(x, box, 3.0)
+    frac = 0
+    tot = 0
+    for i in range(len(x)):
+        for j in lst[i, :cnt[i]]:
+            d = x[j] - x[i]
+            d -= box * np.round(d / box)
+            r = np.linalg.norm(d)
+            p = tab[t[i], t[j], t[j]]
+            R, D = p[F["R"]], p[F["D"]]
+            if r < R + D:
+                tot += 1
+                frac += (r > R - D)
+    assert tot > 0 and frac / tot > 0.1
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_net_force_is_zero(orc, seed):
+    x, t, box = inputs.sic_liquid_batch(nconf=1, nmin=300, nmax=400, seed=seed)[0]
+    _, f, _, _ = orc.compute(x, t, box, params.sic())
+    assert np.linalg.norm(f.sum(0)) <= 1e-12 * np.abs(f).max() * len(x)
+
+
+# ---------------------------------------------------------------------------
+# P-d: invariances
+# ---------------------------------------------------------------------------
+
+def _rotation(rng):
+    q, r = np.linalg.qr(rng.normal(size=(3, 3)))
+    q *= np.sign(np.diag(r))
+    if np.linalg.det(q) < 0:
+        q[:, 0] *= -1
+    return q
+
+
+def test_rotation_invariance_cluster(orc):
+    rng = np.random.default_rng(5)
+    x, t, box = inputs.sic_liquid_batch(nconf=1, nmin=300, nmax=400, seed=9)[0]
+    sel = np.linalg.norm(x - x.mean(0), axis=1) < 6.0
+    xc = x[sel] - x[sel].mean(0)
+    tc = t[sel]
+    bigbox = np.array([60.0, 60.0, 60.0])
+    tab = params.sic()
+    e0, f0, _, _ = orc.compute(xc + 30.0, tc, bigbox, tab)
+    Q = _rotation(rng)
+    e1, f1, _, _ = orc.compute(xc @ Q.T + 30.0, tc, bigbox, tab)
+    assert abs(e1 - e0) <= 1e-12 * abs(e0)
+    assert np.max(np.abs(f1 - f0 @ Q.T)) <= 1e-11 * np.abs(f0).max()
+
+
+def test_translation_and_axis_permutation(orc):
+    x, t, box = inputs.si_small(sigma=0.1, ncell=3, seed=31)
+    box = box * np.array([1.0, 1.0, 1.0])
+    tab = params.single(params.SI_B)
+    e0, f0, w0, _ = orc.compute(x, t, box, tab)
+    shift = np.array([1.7, -13.2, 40.1])
+    xs = inputs.wrap(x + shift, box)
+    e1, f1, w1, _ = orc.compute(xs, t, box, tab)
+    assert abs(e1 - e0) <= 1e-12 * abs(e0)
+    assert np.max(np.abs(f1 - f0)) <= 1e-11
+    perm = [2, 0, 1]
+    e2, f2, w2, _ = orc.compute(x[:, perm], t, box[perm], tab)
+    assert abs(e2 - e0) <= 1e-12 * abs(e0)
+    assert np.max(np.abs(f2 - f0[:, perm])) <= 1e-11
+    # atom relabelling
+    rng = np.random.default_rng(0)
+    p = rng.permutation(len(x))
+    e3, f3, _, _ = orc.compute(x[p], t[p], box, tab)
+    assert abs(e3 - e0) <= 1e-12 * abs(e0)
+    assert np.max(np.abs(f3 - f0[p])) <= 1e-11
+
+
+# ---------------------------------------------------------------------------
+# P-e: brute force with explicit images; neighbour list and skin
+# ---------------------------------------------------------------------------
+
+def test_bruteforce_images_vs_list_si(orc):
+    x, t, box = inputs.si_small(sigma=0.1, ncell=2, seed=41)
+    tab = params.single(params.SI_B)
+    e0, f0, w0, ea0 = orc.compute(x, t, box, tab)
+    e1, f1, w1, ea1 = orc.compute_images(x, t, box, tab, nimg=1)
+    assert abs(e1 - e0) <= 1e-13 * abs(e0)
+    assert np.max(np.abs(f1 - f0)) <= 1e-12
+    assert np.max(np.abs(w1 - w0)) <= 1e-12 * np.abs(w0).max()
+    assert np.max(np.abs(ea1 - ea0)) <= 1e-12
+
+
+def test_bruteforce_images_vs_list_sic(orc):
+    x, t, box = inputs.sic_liquid_batch(nconf=1, nmin=64, nmax=64, seed=43)[0]
+    tab = params.sic()
+    e0, f0, w0, _ = orc.compute(x, t, box, tab)
+    e1, f1, w1, _ = orc.compute_images(x, t, box, tab, nimg=1)
+    assert abs(e1 - e0) <= 1e-13 * abs(e0)
+    assert np.max(np.abs(f1 - f0)) <= 1e-12 * max(1.0, np.abs(f0).max())
+
+
+def test_single_cell_with_images_equals_replicated(orc):
+    """One conventional cell (8 atoms, box smaller than twice the cutoff, so
+    only explicit images work) equals 1/8 of the 2x2x2 replica."""
+    rng = np.random.default_rng(2)
+    x1, box1 = inputs.diamond(1, 5.431)
+    x1 = x1 + rng.normal(0, 0.1, size=x1.shape)
+    t1 = np.zeros(8, dtype=np.int32)
+    tab = params.single(params.SI_B)
+    e1, f1, w1, _ = orc.compute_images(x1, t1, box1, tab, nimg=1)
+    shifts = np.array([[i, j, k] for k in range(2) for j in range(2) for i in range(2)]) * 5.431
+    x8 = (x1[None, :, :] + shifts[:, None, :]).reshape(-1, 3)
+    e8, f8, w8, _ = orc.compute(x8, np.zeros(64, dtype=np.int32), box1 * 2, tab)
+    assert abs(e8 - 8 * e1) <= 1e-12 * abs(e8)
+    assert np.max(np.abs(f8[:8] - f1)) <= 1e-11
+    assert np.max(np.abs(w8 - 8 * w1)) <= 1e-11 * np.abs(w8).max()
+
+
+def test_neighbour_lists_cells_equal_brute(orc):
+    x, t, box = inputs.sic_liquid_batch(nconf=1, nmin=900, nmax=1000, seed=3)[0]
+    c0, l0 = orc.neighbours(x, box, 3.0, method="brute")
+    c1, l1 = orc.neighbours(x, box, 3.0, method="cells", cap=l0.shape[1])
+    assert np.array_equal(c0, c1)
+    for i in range(len(x)):
+        assert np.array_equal(l0[i, :c0[i]], l1[i, :c1[i]])
+
+
+def test_skin_entries_change_nothing(orc):
+    x, t, box = inputs.sic_liquid_batch(nconf=1, nmin=500, nmax=600, seed=4)[0]
+    tab = params.sic()
+    rc = params.max_cutoff(tab)
+    e0, f0, w0, _ = orc.compute(x, t, box, tab, rlist=rc)
+    e1, f1, w1, _ = orc.compute(x, t, box, tab, rlist=rc + 0.5)
+    assert abs(e1 - e0) <= 1e-13 * abs(e0)
+    assert np.max(np.abs(f1 - f0)) <= 1e-12 * np.abs(f0).max()
+
+
+def test_forces_on_sampled_atoms_are_exact(orc):
+    x, t, box = inputs.sic_liquid_batch(nconf=1, nmin=700, nmax=800, seed=6)[0]
+    tab = params.sic()
+    e, f, w, ea = orc.compute(x, t, box, tab)
+    atoms = [0, 5, 17, len(x) - 1]
+    fs, es = orc.forces_on(x, t, box, tab, atoms)
+    assert np.max(np.abs(fs - f[atoms])) <= 1e-12 * np.abs(f).max()
+    assert np.max(np.abs(es - ea[atoms])) <= 1e-13
+
+
+# ---------------------------------------------------------------------------
+# P-dimer, P-trimer: clusters in vacuum
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("r", [2.3, 2.95, 3.1, 3.25])
+def test_dimer(orc, r):
+    tab = params.single(params.SI_B)
+    el = params.SI_B
+    R, D = _elem_RD(el)
+    box = np.array([30.0, 30.0, 30.0])
+    x = np.array([[10.0, 10.0, 10.0], [10.0 + r, 10.0, 10.0]])
+    e, f, _, _ = orc.compute(x, np.zeros(2, np.int32), box, tab)
+    want = _fc(r, R, D) * (el["A"] * math.exp(-el["lam1"] * r) - el["B"] * math.exp(-el["lam2"] * r))
+    assert abs(e - want) <= 1e-13 * max(1.0, abs(want))
+
+
+@pytest.mark.parametrize("m", [1.0, 3.0])
+def test_scalene_trimer(orc, m):
+    el = dict(params.SI_B)
+    el["m"] = m
+    tab = params.single(el)
+    tab[0, 0, 0, F["m"]] = m
+    R, D = _elem_RD(el)
+    pos = np.array([[0.0, 0.0, 0.0], [2.3, 0.0, 0.0], [0.9, 2.6, 0.3]]) + 10.0
+    box = np.array([30.0, 30.0, 30.0])
+    e, _, _, ea = orc.compute(pos, np.zeros(3, np.int32), box, tab)
+
+    def dist(a, b):
+        return float(np.linalg.norm(pos[a] - pos[b]))
+
+    want = 0.0
+    for i in range(3):
+        for j in range(3):
+            if j == i:
+                continue
+            k = 3 - i - j
+            rij, rik = dist(i, j), dist(i, k)
+            cos = float(np.dot(pos[j] - pos[i], pos[k] - pos[i])) / (rij * rik)
+            zeta = _fc(rik, R, D) * _g(cos, el) * math.exp((el["lam3"] * (rij - rik)) ** int(m))
+            b = _b(zeta, el["beta"], el["n"])
+            want += 0.5 * _fc(rij, R, D) * (el["A"] * math.exp(-el["lam1"] * rij) - b * el["B"] * math.exp(-el["lam2"] * rij))
+    assert abs(e - want) <= 1e-13 * abs(want)
+    assert abs(ea.sum() - e) <= 1e-13 * abs(e)
+
+
+def test_equilateral_trimer_closed_form(orc):
+    el = params.SI_B
+    R, D = _elem_RD(el)
+    r = 2.4
+    tab = params.single(el)
+    h = r * math.sqrt(3) / 2
+    pos = np.array([[0.0, 0.0, 0.0], [r, 0.0, 0.0], [r / 2, h, 0.0]]) + 10.0
+    e, f, _, _ = orc.compute(pos, np.zeros(3, np.int32), np.array([30.0] * 3), tab)
+    zeta = _fc(r, R, D) * _g(0.5, el)
+    want = 3.0 * _fc(r, R, D) * (el["A"] * math.exp(-el["lam1"] * r) - _b(zeta, el["beta"], el["n"]) * el["B"] * math.exp(-el["lam2"] * r))
+    assert abs(e - want) <= 1e-13 * abs(want)
+    # forces point along the medians by symmetry and sum to zero
+    assert np.linalg.norm(f.sum(0)) < 1e-12
+
+
+def test_isolated_atom_and_zeta_zero(orc):
+    tab = params.single(params.SI_C)  # n < 1: db/dzeta is singular at zeta -> 0
+    box = np.array([30.0] * 3)
+    x = np.array([[5.0, 5.0, 5.0], [7.3, 5.0, 5.0], [20.0, 20.0, 20.0]])
+    e, f, w, ea = orc.compute(x, np.zeros(3, np.int32), box, tab)
+    assert np.all(np.isfinite(f)) and np.isfinite(e)
+    assert ea[2] == 0.0 and np.all(f[2] == 0.0)
