@@ -1,0 +1,223 @@
+/*
+ * libtersoff: Tersoff multi-body potential on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI.  Plain pointers and sizes only.  Unless stated otherwise:
+ *   - "device" pointers are HIP device memory (hipMalloc, or torch CUDA tensors
+ *     on ROCm) owned by the caller; the library never frees them;
+ *   - "host" pointers are ordinary host memory, read during the call only;
+ *   - every call is asynchronous on the context's HIP stream unless it says
+ *     it synchronises;
+ *   - positions are FP64 [n][3] row-major (x, y, z of atom 0, then atom 1 ...),
+ *     species are int32 [n] in [0, ntypes), and every output is FP64;
+ *   - units are Angstrom, eV, eV/Angstrom, amu, ps ("metal" units);
+ *   - boxes are orthorhombic, periodic in x, y and z, given as three side
+ *     lengths (host memory).  Positions may lie outside [0, L): they are
+ *     folded internally.
+ * Errors are returned as ters_status; ters_last_error() gives a message.  No
+ * C++ exception crosses this interface.
+ *
+ * The potential (the paper, Section III, Eqs. ters-1..ters-3):
+ *   E = 1/2 sum_i sum_{j in N_i} f_C(r_ij) [f_R(r_ij) + b_ij f_A(r_ij)],
+ *   b_ij = (1 + (beta zeta_ij)^n)^(-1/(2n)),
+ *   zeta_ij = sum_{k in N_i \ {j}} f_C(r_ik) g(theta_ijk) exp(lambda3^m (r_ij - r_ik)^m),
+ * with Tersoff's forms f_R = A exp(-lambda1 r), f_A = -B exp(-lambda2 r),
+ * g = gamma (1 + c^2/d^2 - c^2/(d^2 + (cos theta - h)^2)), and f_C the sine
+ * switch from 1 at R-D to 0 at R+D.  Forces are F = -dE/dx (Eq. pot-force);
+ * the virial is W = sum over terms of (x_a - x_i) (x) f_a, six values
+ * xx, yy, zz, xy, xz, yz, in eV.
+ */
+#ifndef TERSOFF_H
+#define TERSOFF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ters_ctx ters_ctx;
+typedef struct ters_plan ters_plan;
+
+typedef enum {
+  TERS_OK = 0,
+  TERS_ERR_INVALID_ARG = 1,    /* null pointer, negative size, bad enum */
+  TERS_ERR_BOX_TOO_SMALL = 2,  /* a box side is below twice the list cutoff */
+  TERS_ERR_NLIST_OVERFLOW = 3, /* an atom has more neighbours than supported */
+  TERS_ERR_PARAMS = 4,         /* parameter table fails validation */
+  TERS_ERR_NOT_FINITE = 5,     /* non-finite position or result */
+  TERS_ERR_HIP = 6,            /* a HIP runtime call failed */
+  TERS_ERR_UNSUPPORTED = 7,    /* valid request this build does not handle */
+  TERS_ERR_NO_LIST = 8         /* compute before ters_build_nlist, or n changed */
+} ters_status;
+
+/* precision modes */
+enum {
+  TERS_FP64 = 0, /* all arithmetic in FP64 */
+  TERS_MIXED = 1 /* FP32 arithmetic; FP64 displacements x_j - x_i (rounded
+                    to FP32 afterwards), FP64 rebuild check, FP64 force,
+                    energy, virial and gradient accumulators (the paper,
+                    Section V-F, mode Opt-M) */
+};
+
+/* output selection for ters_compute */
+enum {
+  TERS_ENERGY = 1u,
+  TERS_FORCES = 2u,
+  TERS_VIRIAL = 4u,
+  TERS_PER_ATOM_E = 8u,  /* e_i = 1/2 sum_j V_ij */
+  TERS_ACCUMULATE = 16u, /* add to the outputs instead of overwriting them */
+  TERS_PARAM_GRAD = 32u  /* also dE/dtable into param_grad (ters_compute_ex) */
+};
+
+/* Parameter-table layout: table[ti][tj][tk][14] (FP64, host) with fields
+ *   0 m  1 gamma  2 lambda3  3 c  4 d  5 h(=cos theta0)  6 n  7 beta
+ *   8 lambda2  9 B  10 R  11 D  12 lambda1  13 A
+ * Pair quantities of (i,j) (A, B, lambda1, lambda2, beta, n and the cutoff of
+ * r_ij) are read from entry [ti][tj][tj]; three-body quantities of (i,j,k)
+ * (m, gamma, lambda3, c, d, h and the cutoff of r_ik) from [ti][tj][tk]. */
+#define TERS_NFIELD 14
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Create a context on HIP device `device`, issuing work on `hip_stream`
+ * (a hipStream_t, or NULL for the default stream).  The context owns all
+ * internal scratch (cell bins, neighbour list, partial sums).  One context
+ * per stream; not safe to use from two host threads at once. */
+ters_status ters_create(ters_ctx **out, int device, void *hip_stream);
+ters_status ters_destroy(ters_ctx *ctx);
+ters_status ters_set_stream(ters_ctx *ctx, void *hip_stream);
+/* Wait for the context's stream; report any error latched by a kernel. */
+ters_status ters_sync(ters_ctx *ctx);
+/* Message for the last error on this context (never NULL). */
+const char *ters_last_error(const ters_ctx *ctx);
+
+/* ---- parameters (the paper, Section III: per-species parameters) ---------
+ * Copy a parameter table (host, [ntypes]^3 x 14 FP64, layout above) and the
+ * per-species masses (host, [ntypes] amu, may be NULL if no MD is run) to
+ * the device.  Validation: 1 <= ntypes <= 8; n > 0, beta > 0, d != 0, D > 0,
+ * R > D, A, B, lambda1, lambda2 finite; m in {1, 3}.  Fails with
+ * TERS_ERR_PARAMS otherwise.  Synchronises. */
+ters_status ters_set_params(ters_ctx *ctx, int32_t ntypes, const double *table_host,
+                            const double *mass_host);
+
+/* ---- neighbour list (the paper, Section II Eq. neigh and Section III skin)
+ * Build the full list N_i = { j != i : |x_j - x_i| <= r_list } with
+ * r_list = (largest R + D in the table) + skin, by binning atoms into cells of
+ * side >= r_list (minimum image).  x: device [n][3]; type: device [n];
+ * box: host [3].  Stores the list and a copy of x (the reference for the
+ * rebuild check) in the context.  Fails with TERS_ERR_BOX_TOO_SMALL if a side
+ * is below 2 r_list.  Grows the list capacity and retries when an atom has
+ * more entries than fit (synchronises to read the largest row length). */
+ters_status ters_build_nlist(ters_ctx *ctx, int32_t n, const double *x, const int32_t *type,
+                             const double *box, double skin);
+
+/* Largest displacement since the last build above skin/2 (FP64, minimum
+ * image)?  Writes 1 or 0 to flag_dev (device int32[1]).  No synchronisation. */
+ters_status ters_needs_rebuild(ters_ctx *ctx, const double *x, int32_t *flag_dev);
+
+/* Neighbour-list statistics from the last build (synchronises):
+ * out[0] = n, out[1] = total entries, out[2] = longest row, out[3] = capacity. */
+ters_status ters_nlist_stats(ters_ctx *ctx, int64_t *out4);
+
+/* ---- energy, forces, virial (the paper, Algorithm 3 over the list) --------
+ * Evaluate the potential for the n atoms (device x, type; host box) with the
+ * context's current list, which must have been built for n atoms with
+ * positions within skin/2 of x.  precision: TERS_FP64 or TERS_MIXED.
+ * flags: any of TERS_ENERGY, TERS_FORCES, TERS_VIRIAL, TERS_PER_ATOM_E,
+ * TERS_ACCUMULATE.  Outputs (device, FP64, caller-owned; NULL allowed when the
+ * matching flag is off): energy[1], forces[n][3], virial[6], e_atom[n]. */
+ters_status ters_compute(ters_ctx *ctx, int32_t n, const double *x, const int32_t *type,
+                         const double *box, int precision, uint32_t flags, double *energy,
+                         double *forces, double *virial, double *e_atom);
+
+/* As ters_compute, plus with TERS_PARAM_GRAD the derivative of E with
+ * respect to every table entry: param_grad device [ntypes^3][14], accumulated
+ * into (the caller zeroes it unless accumulating on purpose). */
+ters_status ters_compute_ex(ters_ctx *ctx, int32_t n, const double *x, const int32_t *type,
+                            const double *box, int precision, uint32_t flags, double *energy,
+                            double *forces, double *virial, double *e_atom, double *param_grad);
+
+/* ---- adjoint (vector-Jacobian product of (E, F) wrt (x, table)) ----------
+ * Given cotangents e_bar (host scalar) and f_bar (device [n][3]) of the
+ * outputs E and F, writes
+ *   x_grad     = e_bar dE/dx + sum_a f_bar_a dF_a/dx      (device [n][3])
+ *   param_grad = e_bar dE/dtheta + sum_a f_bar_a dF_a/dtheta (device [ntypes^3][14])
+ * Both are overwritten.  Computed by one pass of the force kernel in
+ * forward-mode dual arithmetic along f_bar; zeta is recomputed, no triplet
+ * is stored.  The derivative with respect to the integer m uses the
+ * continuation sgn(u)|u|^m, u = lambda3 (r_ij - r_ik).  Needs a current list. */
+ters_status ters_backward(ters_ctx *ctx, int32_t n, const double *x, const int32_t *type,
+                          const double *box, int precision, double e_bar, const double *f_bar,
+                          double *x_grad, double *param_grad);
+
+/* ---- molecular dynamics ---------------------------------------------------
+ * nsteps velocity-Verlet steps (dt_ps in ps) on device x, v, f ([n][3] FP64,
+ * updated in place; f must hold the forces at x on entry, e.g. from
+ * ters_compute).  The list is rebuilt on the device whenever the largest
+ * displacement since the last build exceeds skin/2; no host synchronisation
+ * inside the loop.  energy_trace: device [nsteps] potential energy after
+ * each step, or NULL.  Needs masses (ters_set_params) and a list built with
+ * the same skin.  When use_graph is non-zero one step is captured into a
+ * hipGraph once and replayed. */
+ters_status ters_md_run(ters_ctx *ctx, int32_t n, double *x, double *v, double *f,
+                        const int32_t *type, const double *box, double dt_ps, int32_t nsteps,
+                        double skin, int precision, double *energy_trace, int use_graph);
+/* Number of list rebuilds done by ters_md_run calls so far (synchronises). */
+ters_status ters_md_rebuilds(ters_ctx *ctx, int64_t *out);
+
+/* ---- batches of independent configurations -------------------------------
+ * A plan covers nconf configurations concatenated along the atom axis:
+ * natoms_host[c] atoms each (config c occupies rows off_c .. off_c+n_c-1 with
+ * off_c = sum of earlier n), boxes_host [nconf][3].  Lists are built with
+ * skin 0.  The plan owns device scratch, the autotuned schedule and a hipGraph
+ * of the whole evaluation.  ters_batch_run evaluates all configurations with
+ * one graph launch: energies e[nconf], forces f_cat[N][3], virials w[nconf][6]
+ * (device, FP64; any may be NULL).  If f_bar is non-NULL the graph also runs
+ * the adjoint with per-configuration e_bar[nconf] (device) and f_bar_cat
+ * [N][3] (device), writing x_grad_cat [N][3] and param_grad (summed over
+ * configurations) [ntypes^3][14].  x_cat, type_cat device.  Pointers given
+ * to the first run are baked into the graph; later runs with other pointers
+ * re-capture it. */
+ters_status ters_batch_plan(ters_ctx *ctx, int32_t nconf, const int32_t *natoms_host,
+                            const double *boxes_host, int precision, uint32_t flags,
+                            ters_plan **out);
+ters_status ters_batch_run(ters_plan *plan, const double *x_cat, const int32_t *type_cat,
+                           double *e, double *f_cat, double *w, const double *e_bar,
+                           const double *f_bar_cat, double *x_grad_cat, double *param_grad);
+ters_status ters_plan_destroy(ters_plan *plan);
+/* Schedule chosen by the plan's autotuner: out[0] = atoms per workgroup,
+ * out[1] = workgroup size, out[2] = measured microseconds of the best. */
+ters_status ters_plan_schedule(const ters_plan *plan, double *out3);
+
+/* ---- schedule control ------------------------------------------------------
+ * Atoms per workgroup of the force kernel (0 = automatic) and the number of
+ * stored dzeta/dx_k per pair before the kernel falls back to recomputing them
+ * (the paper's k_max, Section IV-A; 0 = automatic, i.e. store all). */
+ters_status ters_set_schedule(ters_ctx *ctx, int32_t atoms_per_block, int32_t kmax);
+/* Time the candidate schedules on the current list and keep the fastest
+ * (synchronises).  out_us (host, may be NULL) gets the best time. */
+ters_status ters_autotune(ters_ctx *ctx, int32_t n, const double *x, const int32_t *type,
+                          const double *box, int precision, double *out_us);
+
+/* Average duration in microseconds of the force kernel alone (energy, forces
+ * and virial, no output zeroing or final reduction), from HIP events around
+ * `reps` back-to-back launches on the context's stream, with the current list
+ * (synchronises).  Forces go to internal scratch. */
+ters_status ters_profile_forward(ters_ctx *ctx, int32_t n, const double *x, const int32_t *type,
+                                 const double *box, int precision, int32_t reps, double *avg_us);
+
+/* ---- parameter tables (Si/C mixing rules, Tersoff 1989) -------------------
+ * Fill a host table [2][2][2][14] for species 0 = Si (Tersoff's Si(C) set),
+ * 1 = C, with Si-C cross terms by the geometric/arithmetic mixing rules and
+ * chi = 0.9776.  Fill a [1][1][1][14] table for one of the element sets
+ * 0 = Si(B), 1 = Si(C), 2 = C. */
+ters_status ters_table_sic(double *table_host);
+ters_status ters_table_element(int32_t which, double *table_host);
+
+/* Library version string. */
+const char *ters_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TERSOFF_H */

@@ -74,19 +74,28 @@ static double gang_d(double cs, const double *p) {
   return p[F_GAMMA] * 2.0 * c2 * t / (den * den);
 }
 
-/* exp(lambda3^m (dr)^m) for integer m in {1, 3}, and its derivative wrt dr. */
+/* exp(lambda3^m (dr)^m) and its derivative wrt dr.  For the published
+ * integer exponents m = 1, 3 this is (lambda3 dr)^m; any other m (used only
+ * to differentiate with respect to m by finite differences) takes the
+ * continuation sgn(u)|u|^m, u = lambda3 dr, which equals u^m at m = 1, 3. */
+static double expo_arg(double u, double m) {
+  if (m == 3.0) return u * u * u;
+  if (m == 1.0) return u;
+  if (u == 0.0) return 0.0;
+  return copysign(pow(fabs(u), m), u);
+}
 static double expo(double dr, const double *p) {
-  double u = p[F_LAM3] * dr;
-  double m = p[F_M];
-  double t = (m == 3.0) ? u * u * u : u;
-  return exp(t);
+  return exp(expo_arg(p[F_LAM3] * dr, p[F_M]));
 }
 static double expo_d(double dr, const double *p) {
   double l = p[F_LAM3];
   double u = l * dr;
   double m = p[F_M];
-  if (m == 3.0) return 3.0 * l * u * u * exp(u * u * u);
-  return l * exp(u);
+  double e = exp(expo_arg(u, m));
+  if (m == 3.0) return 3.0 * l * u * u * e;
+  if (m == 1.0) return l * e;
+  if (u == 0.0) return 0.0;
+  return m * l * pow(fabs(u), m - 1.0) * e;
 }
 
 /* Bond order b(zeta) and db/dzeta.  b = 1 when zeta == 0 (no third atom),

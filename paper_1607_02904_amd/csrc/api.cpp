@@ -1,0 +1,901 @@
+// C-ABI layer of libtersoff: context, parameter derivation and validation,
+// neighbour-list management, force evaluation, adjoint, molecular dynamics,
+// batched evaluation with graph capture, and the schedule autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <exception>
+#include <string>
+#include <vector>
+
+#include "tersoff.h"
+#include "ters_device.h"
+#include "ters_internal.h"
+
+using namespace ters;
+
+struct ters_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  hipStream_t capture_stream = nullptr;
+  std::string err;
+  int ntypes = 0;
+  std::vector<double> table;
+  double rc_max = 0.0;
+  int cut_consistent = 1;
+  bool has_mass = false;
+  DevBuf kp64, kp32, filt2, mass;
+  NList nl;
+  DevBuf partials, errw, flag, rebuilds, step, escratch;
+  int A[2] = {0, 0};  // atoms per workgroup per precision (0 = kernel default)
+  int kmax = 1 << 20;
+  // molecular-dynamics step graph
+  hipGraphExec_t md_exec = nullptr;
+  std::vector<const void *> md_key;
+};
+
+struct ters_plan {
+  ters_ctx *ctx = nullptr;
+  int nconf = 0, N = 0, precision = 0;
+  uint32_t flags = 0;
+  std::vector<int32_t> natoms, off;
+  NList nl;
+  DevBuf partials, ebuf, errw;
+  int A = 0;
+  double best_us = 0.0;
+  bool tuned = false;
+  hipGraphExec_t exec = nullptr;
+  std::vector<const void *> key;
+};
+
+namespace {
+
+const char *kVersion = "libtersoff 0.1 (gfx950)";
+
+template <class F>
+ters_status guard(ters_ctx *c, F &&f) {
+  try {
+    if (c) TERS_HIP_TRY(hipSetDevice(c->device));
+    return f();
+  } catch (const HipError &e) {
+    if (c) c->err = e.what;
+    return TERS_ERR_HIP;
+  } catch (const StatusError &e) {
+    if (c) c->err = e.what;
+    return e.code;
+  } catch (const std::exception &e) {
+    if (c) c->err = e.what();
+    return TERS_ERR_HIP;
+  }
+}
+
+[[noreturn]] void fail(ters_status s, const std::string &msg) { throw StatusError(s, msg); }
+
+void require(bool cond, ters_status s, const char *msg) {
+  if (!cond) fail(s, msg);
+}
+
+inline size_t ent(int nt, int a, int b, int c) { return ((size_t)a * nt + b) * nt + c; }
+
+template <class B>
+KParam<B> derive(const double *p) {
+  KParam<B> k{};
+  const double R = p[FR], D = p[FDC];
+  k.R = (B)R;
+  k.D = (B)D;
+  k.rcut = (B)(R + D);
+  k.rin = (B)(R - D);
+  k.pi2d = (B)(M_PI / (2.0 * D));
+  k.pi4d = (B)(M_PI / (4.0 * D));
+  k.A = (B)p[FA];
+  k.lam1 = (B)p[FLAM1];
+  k.Bc = (B)p[FB];
+  k.lam2 = (B)p[FLAM2];
+  k.beta = (B)p[FBETA];
+  k.n = (B)p[FN];
+  k.inv2n = (B)(1.0 / (2.0 * p[FN]));
+  k.gamma = (B)p[FGAMMA];
+  k.c2 = (B)(p[FC] * p[FC]);
+  k.d2 = (B)(p[FD] * p[FD]);
+  k.h = (B)p[FH];
+  k.gc2 = (B)(p[FGAMMA] * p[FC] * p[FC]);
+  k.c2d2 = (B)(p[FC] * p[FC] / (p[FD] * p[FD]));
+  k.lam3 = (B)p[FLAM3];
+  k.c = (B)p[FC];
+  k.d = (B)p[FD];
+  k.m3 = p[FM] == 3.0 ? 1 : 0;
+  k.pad = 0;
+  // what rounding to B dropped (all zero for FP64); set after every hi part
+  k.A_lo = (B)(p[FA] - (double)k.A);
+  k.lam1_lo = (B)(p[FLAM1] - (double)k.lam1);
+  k.B_lo = (B)(p[FB] - (double)k.Bc);
+  k.lam2_lo = (B)(p[FLAM2] - (double)k.lam2);
+  k.R_lo = (B)(R - (double)k.R);
+  k.h_lo = (B)(p[FH] - (double)k.h);
+  return k;
+}
+
+void sync(ters_ctx *c) { TERS_HIP_TRY(hipStreamSynchronize(c->stream)); }
+
+uint32_t read_err(ters_ctx *c, DevBuf &w) {
+  uint32_t e = 0;
+  TERS_HIP_TRY(hipMemcpyAsync(&e, w.p, sizeof(e), hipMemcpyDeviceToHost, c->stream));
+  sync(c);
+  return e;
+}
+
+void check_err_word(uint32_t e) {
+  if (e & kErrNotFinite) fail(TERS_ERR_NOT_FINITE, "non-finite position");
+  if (e & kErrNlistOverflow) fail(TERS_ERR_NLIST_OVERFLOW, "neighbour list capacity exceeded");
+  if (e & kErrTooManyInCutoff)
+    fail(TERS_ERR_NLIST_OVERFLOW, "an atom has more than 32 neighbours inside the cutoff");
+}
+
+int next_pow2(int v) {
+  int p = 4;
+  while (p < v) p <<= 1;
+  return p;
+}
+
+// Geometry of a configuration set; allocates the list buffers.
+void nl_setup(NList &nl, int nconf, const int32_t *natoms, const double *boxes, double rlist,
+              double skin, const std::vector<int32_t> *conf_of_h, hipStream_t s) {
+  nl.nconf = nconf;
+  nl.rlist = rlist;
+  nl.skin = skin;
+  nl.conf_h.resize(nconf);
+  int64_t cells = 0, atoms = 0;
+  for (int c = 0; c < nconf; ++c) {
+    ConfDesc d{};
+    for (int a = 0; a < 3; ++a) {
+      const double L = boxes[3 * c + a];
+      if (!(std::isfinite(L) && L > 0.0)) fail(TERS_ERR_INVALID_ARG, "box sides must be finite and > 0");
+      if (L < 2.0 * rlist)
+        fail(TERS_ERR_BOX_TOO_SMALL, "box side below twice the list cutoff (minimum image)");
+      d.box[a] = L;
+      d.inv_box[a] = 1.0 / L;
+      int k = (int)std::floor(L / rlist);
+      d.nc[a] = k >= 3 ? k : 1;
+    }
+    d.cell_off = (int32_t)cells;
+    d.atom_off = (int32_t)atoms;
+    d.natoms = natoms[c];
+    cells += (int64_t)d.nc[0] * d.nc[1] * d.nc[2];
+    atoms += natoms[c];
+    nl.conf_h[c] = d;
+  }
+  if (cells > (int64_t)1 << 30) fail(TERS_ERR_UNSUPPORTED, "too many cells");
+  nl.n = (int32_t)atoms;
+  nl.ncell = cells;
+  if (nl.cap == 0) nl.cap = 16;
+  const int n = nl.n;
+  nl.conf.ensure(sizeof(ConfDesc) * nconf);
+  TERS_HIP_TRY(hipMemcpyAsync(nl.conf.p, nl.conf_h.data(), sizeof(ConfDesc) * nconf,
+                              hipMemcpyHostToDevice, s));
+  if (nconf > 1) {
+    nl.conf_of.ensure(sizeof(int32_t) * std::max(n, 1));
+    TERS_HIP_TRY(hipMemcpyAsync(nl.conf_of.p, conf_of_h->data(), sizeof(int32_t) * n,
+                                hipMemcpyHostToDevice, s));
+  }
+  const size_t nn = (size_t)std::max(n, 1);
+  nl.count.ensure(sizeof(int32_t) * nn);
+  nl.list.ensure(sizeof(int32_t) * nn * nl.cap);
+  nl.order.ensure(sizeof(int32_t) * nn);
+  nl.cell_of.ensure(sizeof(int32_t) * nn);
+  nl.cell_count.ensure(sizeof(int32_t) * (cells + 1));
+  nl.cell_start.ensure(sizeof(int32_t) * (cells + 1));
+  nl.scan_tmp.ensure(sizeof(int32_t) * ((cells + 1) / 1024 + 2));
+  nl.xref.ensure(sizeof(double) * 3 * nn);
+  nl.maxcount.ensure(sizeof(int32_t));
+}
+
+// Build with capacity growth (synchronises).
+void nl_build_sync(ters_ctx *c, NList &nl, const double *x, DevBuf &errw) {
+  for (int attempt = 0; attempt < 6; ++attempt) {
+    launch_fill_i32(errw.as<int32_t>(), 0, 1, nullptr, c->stream);
+    nlist_build(nl, x, nullptr, errw.as<uint32_t>(), c->stream);
+    int32_t mx = 0;
+    TERS_HIP_TRY(hipMemcpyAsync(&mx, nl.maxcount.p, sizeof(mx), hipMemcpyDeviceToHost, c->stream));
+    uint32_t e = read_err(c, errw);
+    if (e & kErrNotFinite) fail(TERS_ERR_NOT_FINITE, "non-finite position");
+    if (mx <= nl.cap) {
+      nl.valid = true;
+      return;
+    }
+    const int cap = next_pow2(mx);
+    if (cap > 64) fail(TERS_ERR_NLIST_OVERFLOW, "an atom has more than 64 list neighbours");
+    nl.cap = cap;
+    nl.list.ensure(sizeof(int32_t) * (size_t)std::max(nl.n, 1) * cap);
+  }
+  fail(TERS_ERR_NLIST_OVERFLOW, "neighbour list did not converge");
+}
+
+FwdArgs base_args(ters_ctx *c, const NList &nl, int precision, int n, const double *x,
+                  const int32_t *type, bool batch = false) {
+  FwdArgs a{};
+  a.n = n;
+  a.x = x;
+  a.type = type;
+  a.conf = nl.conf.as<ConfDesc>();
+  a.conf_of = batch ? nl.conf_of.as<int32_t>() : nullptr;
+  a.order = nl.order.as<int32_t>();
+  a.count = nl.count.as<int32_t>();
+  a.list = nl.list.as<int32_t>();
+  a.cap = nl.cap;
+  a.ntypes = c->ntypes;
+  a.kparam = precision == TERS_FP64 ? c->kp64.p : c->kp32.p;
+  a.filt2 = c->filt2.p;
+  a.cut_consistent = c->cut_consistent;
+  a.kmax = c->kmax;
+  return a;
+}
+
+void check_ready(ters_ctx *c, const NList &nl, int n, const double *box) {
+  require(c->ntypes > 0, TERS_ERR_PARAMS, "parameters not set");
+  require(nl.valid && nl.n == n && nl.nconf == 1, TERS_ERR_NO_LIST,
+          "no neighbour list for this system (call ters_build_nlist)");
+  if (box)
+    for (int a = 0; a < 3; ++a)
+      require(box[a] == nl.conf_h[0].box[a], TERS_ERR_INVALID_ARG,
+              "box differs from the one the neighbour list was built for");
+}
+
+// one force evaluation (forces zeroed unless accumulating); returns #blocks
+int run_forward(ters_ctx *c, const FwdArgs &a0, int precision, hipStream_t s) {
+  FwdArgs a = a0;
+  int nb = forward_blocks(a.n, c->A[precision] > 0 ? c->A[precision] : 64);
+  c->partials.ensure(sizeof(double) * 8 * (size_t)std::max(nb, 1));
+  a.partials = c->partials.as<double>();
+  a.err = c->errw.as<uint32_t>();
+  if (a.forces && !(a.flags & TERS_ACCUMULATE)) launch_fill_f64(a.forces, 0.0, 3 * (int64_t)a.n, s);
+  int nbo[1] = {0};
+  launch_forward(a, precision, c->A[precision], nbo, s);
+  return nbo[0];
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *ters_version(void) { return kVersion; }
+
+ters_status ters_create(ters_ctx **out, int device, void *stream) {
+  if (!out) return TERS_ERR_INVALID_ARG;
+  *out = nullptr;
+  ters_ctx *c = new ters_ctx();
+  c->device = device;
+  c->stream = (hipStream_t)stream;
+  ters_status st = guard(c, [&]() {
+    int ndev = 0;
+    TERS_HIP_TRY(hipGetDeviceCount(&ndev));
+    require(device >= 0 && device < ndev, TERS_ERR_INVALID_ARG, "no such device");
+    c->errw.ensure(64);
+    c->flag.ensure(64);
+    c->rebuilds.ensure(64);
+    c->step.ensure(64);
+    c->escratch.ensure(64);
+    TERS_HIP_TRY(hipMemsetAsync(c->errw.p, 0, 64, c->stream));
+    TERS_HIP_TRY(hipMemsetAsync(c->rebuilds.p, 0, 64, c->stream));
+    sync(c);
+    return TERS_OK;
+  });
+  if (st != TERS_OK) {
+    delete c;
+    return st;
+  }
+  *out = c;
+  return TERS_OK;
+}
+
+ters_status ters_destroy(ters_ctx *c) {
+  if (!c) return TERS_ERR_INVALID_ARG;
+  hipSetDevice(c->device);
+  hipStreamSynchronize(c->stream);
+  if (c->md_exec) hipGraphExecDestroy(c->md_exec);
+  if (c->capture_stream) hipStreamDestroy(c->capture_stream);
+  DevBuf *bufs[] = {&c->kp64, &c->kp32, &c->filt2, &c->mass, &c->partials, &c->errw, &c->flag,
+                    &c->rebuilds, &c->step, &c->escratch, &c->nl.conf, &c->nl.conf_of,
+                    &c->nl.count, &c->nl.list, &c->nl.order, &c->nl.cell_of, &c->nl.cell_count,
+                    &c->nl.cell_start, &c->nl.scan_tmp, &c->nl.xref, &c->nl.maxcount};
+  for (DevBuf *b : bufs) b->release();
+  delete c;
+  return TERS_OK;
+}
+
+ters_status ters_set_stream(ters_ctx *c, void *stream) {
+  if (!c) return TERS_ERR_INVALID_ARG;
+  c->stream = (hipStream_t)stream;
+  return TERS_OK;
+}
+
+ters_status ters_sync(ters_ctx *c) {
+  if (!c) return TERS_ERR_INVALID_ARG;
+  return guard(c, [&]() {
+    check_err_word(read_err(c, c->errw));
+    return TERS_OK;
+  });
+}
+
+const char *ters_last_error(const ters_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+ters_status ters_set_params(ters_ctx *c, int32_t nt, const double *tab, const double *mass) {
+  if (!c) return TERS_ERR_INVALID_ARG;
+  return guard(c, [&]() {
+    require(nt >= 1 && nt <= 8 && tab != nullptr, TERS_ERR_INVALID_ARG, "need 1 <= ntypes <= 8 and a table");
+    const size_t ne = (size_t)nt * nt * nt;
+    for (size_t e = 0; e < ne; ++e) {
+      const double *p = tab + e * kNField;
+      for (int f = 0; f < kNField; ++f)
+        require(std::isfinite(p[f]), TERS_ERR_PARAMS, "non-finite parameter");
+      require(p[FM] == 1.0 || p[FM] == 3.0, TERS_ERR_PARAMS, "m must be 1 or 3");
+      require(p[FN] > 0.0, TERS_ERR_PARAMS, "n must be > 0");
+      require(p[FBETA] > 0.0, TERS_ERR_PARAMS, "beta must be > 0");
+      require(p[FD] != 0.0, TERS_ERR_PARAMS, "d must be non-zero");
+      require(p[FDC] > 0.0, TERS_ERR_PARAMS, "D must be > 0");
+      require(p[FR] > p[FDC], TERS_ERR_PARAMS, "R must exceed D");
+      require(p[FA] != 0.0 && p[FB] != 0.0, TERS_ERR_PARAMS, "A and B must be non-zero");
+    }
+    if (mass) {
+      for (int t = 0; t < nt; ++t)
+        require(std::isfinite(mass[t]) && mass[t] > 0.0, TERS_ERR_PARAMS, "masses must be > 0");
+    }
+    c->table.assign(tab, tab + ne * kNField);
+    std::vector<KParam<double>> k64(ne);
+    std::vector<KParam<float>> k32(ne);
+    double rc = 0.0;
+    for (size_t e = 0; e < ne; ++e) {
+      k64[e] = derive<double>(tab + e * kNField);
+      k32[e] = derive<float>(tab + e * kNField);
+      rc = std::max(rc, tab[e * kNField + FR] + tab[e * kNField + FDC]);
+    }
+    int consistent = 1;
+    std::vector<double> f2((size_t)nt * nt, 0.0);
+    for (int i = 0; i < nt; ++i)
+      for (int k = 0; k < nt; ++k) {
+        const double *pk = tab + ent(nt, i, k, k) * kNField;
+        double r = pk[FR] + pk[FDC];
+        for (int j = 0; j < nt; ++j) {
+          const double *pj = tab + ent(nt, i, j, k) * kNField;
+          r = std::max(r, pj[FR] + pj[FDC]);
+          if (pj[FR] != pk[FR] || pj[FDC] != pk[FDC]) consistent = 0;
+        }
+        f2[(size_t)i * nt + k] = r * r;
+      }
+    c->kp64.ensure(sizeof(KParam<double>) * ne);
+    c->kp32.ensure(sizeof(KParam<float>) * ne);
+    c->filt2.ensure(sizeof(double) * nt * nt);
+    TERS_HIP_TRY(hipMemcpyAsync(c->kp64.p, k64.data(), sizeof(KParam<double>) * ne, hipMemcpyHostToDevice, c->stream));
+    TERS_HIP_TRY(hipMemcpyAsync(c->kp32.p, k32.data(), sizeof(KParam<float>) * ne, hipMemcpyHostToDevice, c->stream));
+    TERS_HIP_TRY(hipMemcpyAsync(c->filt2.p, f2.data(), sizeof(double) * nt * nt, hipMemcpyHostToDevice, c->stream));
+    if (mass) {
+      c->mass.ensure(sizeof(double) * nt);
+      TERS_HIP_TRY(hipMemcpyAsync(c->mass.p, mass, sizeof(double) * nt, hipMemcpyHostToDevice, c->stream));
+      c->has_mass = true;
+    }
+    sync(c);
+    if (nt != c->ntypes || rc != c->rc_max) c->nl.valid = false;
+    c->ntypes = nt;
+    c->rc_max = rc;
+    c->cut_consistent = consistent;
+    return TERS_OK;
+  });
+}
+
+ters_status ters_build_nlist(ters_ctx *c, int32_t n, const double *x, const int32_t *type,
+                             const double *box, double skin) {
+  if (!c) return TERS_ERR_INVALID_ARG;
+  return guard(c, [&]() {
+    require(c->ntypes > 0, TERS_ERR_PARAMS, "parameters not set");
+    require(n >= 0 && box && (n == 0 || (x && type)), TERS_ERR_INVALID_ARG, "bad arguments");
+    require(std::isfinite(skin) && skin >= 0.0, TERS_ERR_INVALID_ARG, "skin must be >= 0");
+    c->nl.valid = false;
+    nl_setup(c->nl, 1, &n, box, c->rc_max + skin, skin, nullptr, c->stream);
+    nl_build_sync(c, c->nl, x, c->errw);
+    return TERS_OK;
+  });
+}
+
+ters_status ters_needs_rebuild(ters_ctx *c, const double *x, int32_t *flag) {
+  if (!c || !flag) return TERS_ERR_INVALID_ARG;
+  return guard(c, [&]() {
+    require(c->nl.valid, TERS_ERR_NO_LIST, "no neighbour list");
+    launch_fill_i32(flag, 0, 1, nullptr, c->stream);
+    nlist_check(c->nl, x, flag, c->stream);
+    return TERS_OK;
+  });
+}
+
+ters_status ters_nlist_stats(ters_ctx *c, int64_t *out) {
+  if (!c || !out) return TERS_ERR_INVALID_ARG;
+  return guard(c, [&]() {
+    require(c->nl.valid, TERS_ERR_NO_LIST, "no neighbour list");
+    const int n = c->nl.n;
+    std::vector<int32_t> cnt(n);
+    int32_t mx = 0;
+    if (n) TERS_HIP_TRY(hipMemcpyAsync(cnt.data(), c->nl.count.p, sizeof(int32_t) * n, hipMemcpyDeviceToHost, c->stream));
+    TERS_HIP_TRY(hipMemcpyAsync(&mx, c->nl.maxcount.p, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+    sync(c);
+    int64_t tot = 0;
+    for (int v : cnt) tot += v;
+    out[0] = n;
+    out[1] = tot;
+    out[2] = mx;
+    out[3] = c->nl.cap;
+    return TERS_OK;
+  });
+}
+
+ters_status ters_compute_ex(ters_ctx *c, int32_t n, const double *x, const int32_t *type,
+                            const double *box, int precision, uint32_t flags, double *energy,
+                            double *forces, double *virial, double *e_atom, double *param_grad) {
+  if (!c) return TERS_ERR_INVALID_ARG;
+  return guard(c, [&]() {
+    require(precision == TERS_FP64 || precision == TERS_MIXED, TERS_ERR_INVALID_ARG, "bad precision");
+    require(n >= 0 && (n == 0 || (x && type)), TERS_ERR_INVALID_ARG, "bad arguments");
+    require(!(flags & TERS_ENERGY) || energy, TERS_ERR_INVALID_ARG, "energy output missing");
+    require(!(flags & TERS_FORCES) || forces || n == 0, TERS_ERR_INVALID_ARG, "forces output missing");
+    require(!(flags & TERS_VIRIAL) || virial, TERS_ERR_INVALID_ARG, "virial output missing");
+    require(!(flags & TERS_PER_ATOM_E) || e_atom || n == 0, TERS_ERR_INVALID_ARG,
+            "per-atom energy output missing");
+    require(!(flags & TERS_PARAM_GRAD) || param_grad, TERS_ERR_INVALID_ARG, "param_grad output missing");
+    check_ready(c, c->nl, n, box);
+    FwdArgs a = base_args(c, c->nl, precision, n, x, type);
+    a.flags = flags;
+    a.forces = (flags & TERS_FORCES) ? forces : nullptr;
+    a.e_atom = (flags & TERS_PER_ATOM_E) ? e_atom : nullptr;
+    a.pgrad = (flags & TERS_PARAM_GRAD) ? param_grad : nullptr;
+    int nb = run_forward(c, a, precision, c->stream);
+    if (flags & (TERS_ENERGY | TERS_VIRIAL)) {
+      launch_reduce_partials(c->partials.as<double>(), nb, 8,
+                             (flags & TERS_ENERGY) ? energy : nullptr,
+                             (flags & TERS_VIRIAL) ? virial : nullptr,
+                             (flags & TERS_ACCUMULATE) ? 1 : 0, c->stream);
+    }
+    return TERS_OK;
+  });
+}
+
+ters_status ters_compute(ters_ctx *c, int32_t n, const double *x, const int32_t *type,
+                         const double *box, int precision, uint32_t flags, double *energy,
+                         double *forces, double *virial, double *e_atom) {
+  return ters_compute_ex(c, n, x, type, box, precision, flags & ~TERS_PARAM_GRAD, energy, forces,
+                         virial, e_atom, nullptr);
+}
+
+ters_status ters_backward(ters_ctx *c, int32_t n, const double *x, const int32_t *type,
+                          const double *box, int precision, double e_bar, const double *f_bar,
+                          double *x_grad, double *param_grad) {
+  if (!c) return TERS_ERR_INVALID_ARG;
+  return guard(c, [&]() {
+    require(precision == TERS_FP64 || precision == TERS_MIXED, TERS_ERR_INVALID_ARG, "bad precision");
+    require(n >= 0 && (n == 0 || (x && type && f_bar && x_grad)) && param_grad, TERS_ERR_INVALID_ARG,
+            "bad arguments");
+    require(std::isfinite(e_bar), TERS_ERR_INVALID_ARG, "e_bar must be finite");
+    check_ready(c, c->nl, n, box);
+    FwdArgs a = base_args(c, c->nl, precision, n, x, type);
+    a.fbar = f_bar;
+    a.ebar = e_bar;
+    a.xgrad = x_grad;
+    a.pgrad = param_grad;
+    a.flags = TERS_PARAM_GRAD;
+    a.err = c->errw.as<uint32_t>();
+    a.kmax = 0;
+    const int nt = c->ntypes;
+    launch_fill_f64(x_grad, 0.0, 3 * (int64_t)n, c->stream);
+    launch_fill_f64(param_grad, 0.0, (int64_t)nt * nt * nt * kNField, c->stream);
+    launch_adjoint(a, precision, 0, c->stream);
+    return TERS_OK;
+  });
+}
+
+ters_status ters_set_schedule(ters_ctx *c, int32_t apb, int32_t kmax) {
+  if (!c) return TERS_ERR_INVALID_ARG;
+  if (apb < 0 || apb > 64 || kmax < 0) return TERS_ERR_INVALID_ARG;
+  c->A[0] = c->A[1] = apb;
+  c->kmax = kmax == 0 ? (1 << 20) : kmax;
+  return TERS_OK;
+}
+
+ters_status ters_autotune(ters_ctx *c, int32_t n, const double *x, const int32_t *type,
+                          const double *box, int precision, double *out_us) {
+  if (!c) return TERS_ERR_INVALID_ARG;
+  return guard(c, [&]() {
+    require(precision == TERS_FP64 || precision == TERS_MIXED, TERS_ERR_INVALID_ARG, "bad precision");
+    check_ready(c, c->nl, n, box);
+    DevBuf f;
+    f.ensure(sizeof(double) * 3 * (size_t)std::max(n, 1));
+    hipEvent_t e0, e1;
+    TERS_HIP_TRY(hipEventCreate(&e0));
+    TERS_HIP_TRY(hipEventCreate(&e1));
+    const int cands[] = {16, 24, 32, 40, 48, 56, 64};
+    double best = 1e300;
+    int bestA = 64;
+    const int save = c->A[precision];
+    for (int A : cands) {
+      c->A[precision] = A;
+      FwdArgs a = base_args(c, c->nl, precision, n, x, type);
+      a.flags = TERS_FORCES | TERS_ENERGY | TERS_VIRIAL;
+      a.forces = f.as<double>();
+      run_forward(c, a, precision, c->stream);  // warm-up
+      TERS_HIP_TRY(hipEventRecord(e0, c->stream));
+      const int reps = 5;
+      for (int r = 0; r < reps; ++r) run_forward(c, a, precision, c->stream);
+      TERS_HIP_TRY(hipEventRecord(e1, c->stream));
+      TERS_HIP_TRY(hipEventSynchronize(e1));
+      float ms = 0.f;
+      TERS_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+      const double us = 1000.0 * ms / reps;
+      if (us < best) {
+        best = us;
+        bestA = A;
+      }
+    }
+    (void)save;
+    c->A[precision] = bestA;
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    f.release();
+    if (out_us) *out_us = best;
+    return TERS_OK;
+  });
+}
+
+ters_status ters_profile_forward(ters_ctx *c, int32_t n, const double *x, const int32_t *type,
+                                 const double *box, int precision, int32_t reps, double *avg_us) {
+  if (!c || !avg_us) return TERS_ERR_INVALID_ARG;
+  return guard(c, [&]() {
+    require(precision == TERS_FP64 || precision == TERS_MIXED, TERS_ERR_INVALID_ARG, "bad precision");
+    require(reps >= 1, TERS_ERR_INVALID_ARG, "reps must be >= 1");
+    check_ready(c, c->nl, n, box);
+    DevBuf f;
+    f.ensure(sizeof(double) * 3 * (size_t)std::max(n, 1));
+    FwdArgs a = base_args(c, c->nl, precision, n, x, type);
+    a.flags = TERS_FORCES | TERS_ENERGY | TERS_VIRIAL | TERS_ACCUMULATE;
+    a.forces = f.as<double>();
+    const int nb = forward_blocks(n, c->A[precision] > 0 ? c->A[precision] : 64);
+    c->partials.ensure(sizeof(double) * 8 * (size_t)std::max(nb, 1));
+    a.partials = c->partials.as<double>();
+    a.err = c->errw.as<uint32_t>();
+    hipEvent_t e0, e1;
+    TERS_HIP_TRY(hipEventCreate(&e0));
+    TERS_HIP_TRY(hipEventCreate(&e1));
+    int nbo[1];
+    launch_forward(a, precision, c->A[precision], nbo, c->stream);  // warm-up
+    TERS_HIP_TRY(hipEventRecord(e0, c->stream));
+    for (int r = 0; r < reps; ++r) launch_forward(a, precision, c->A[precision], nbo, c->stream);
+    TERS_HIP_TRY(hipEventRecord(e1, c->stream));
+    TERS_HIP_TRY(hipEventSynchronize(e1));
+    float ms = 0.f;
+    TERS_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    sync(c);
+    f.release();
+    *avg_us = 1000.0 * ms / reps;
+    return TERS_OK;
+  });
+}
+
+ters_status ters_md_run(ters_ctx *c, int32_t n, double *x, double *v, double *f,
+                        const int32_t *type, const double *box, double dt, int32_t nsteps,
+                        double skin, int precision, double *trace, int use_graph) {
+  if (!c) return TERS_ERR_INVALID_ARG;
+  return guard(c, [&]() {
+    require(precision == TERS_FP64 || precision == TERS_MIXED, TERS_ERR_INVALID_ARG, "bad precision");
+    require(n >= 0 && nsteps >= 0 && (n == 0 || (x && v && f && type)), TERS_ERR_INVALID_ARG, "bad arguments");
+    require(std::isfinite(dt) && dt > 0.0, TERS_ERR_INVALID_ARG, "dt must be > 0");
+    require(c->has_mass, TERS_ERR_PARAMS, "masses not set");
+    check_ready(c, c->nl, n, box);
+    require(std::fabs(skin - c->nl.skin) < 1e-12, TERS_ERR_INVALID_ARG,
+            "skin differs from the one the list was built with");
+    const int nb = forward_blocks(n, c->A[precision] > 0 ? c->A[precision] : 64);
+    c->partials.ensure(sizeof(double) * 8 * (size_t)std::max(nb, 1));
+    auto step = [&](hipStream_t s) {
+      int32_t *flag = c->flag.as<int32_t>();
+      launch_fill_i32(flag, 0, 1, nullptr, s);
+      launch_vv_first(n, x, v, f, type, c->mass.as<double>(), dt, c->nl, flag, s);
+      nlist_build(c->nl, x, flag, c->errw.as<uint32_t>(), s);
+      launch_count_rebuild(flag, c->rebuilds.as<int64_t>(), s);
+      FwdArgs a = base_args(c, c->nl, precision, n, x, type);
+      a.flags = TERS_FORCES | TERS_ENERGY;
+      a.forces = f;
+      run_forward(c, a, precision, s);
+      if (trace) {
+        launch_reduce_partials(c->partials.as<double>(), nb, 8, c->escratch.as<double>(), nullptr, 0, s);
+        launch_store_trace(c->escratch.as<double>(), trace, c->step.as<int32_t>(), s);
+      }
+      launch_vv_second(n, v, f, type, c->mass.as<double>(), dt, s);
+    };
+    launch_fill_i32(c->step.as<int32_t>(), 0, 1, nullptr, c->stream);
+    if (!use_graph) {
+      for (int s = 0; s < nsteps; ++s) step(c->stream);
+    } else if (nsteps > 0) {
+      std::vector<const void *> key = {x, v, f, type, trace, (const void *)(intptr_t)n,
+                                       (const void *)(intptr_t)precision, c->nl.list.p,
+                                       c->partials.p, (const void *)(intptr_t)c->A[precision]};
+      if (!c->md_exec || key != c->md_key) {
+        if (c->md_exec) {
+          TERS_HIP_TRY(hipGraphExecDestroy(c->md_exec));
+          c->md_exec = nullptr;
+        }
+        if (!c->capture_stream) TERS_HIP_TRY(hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
+        sync(c);
+        hipGraph_t g;
+        TERS_HIP_TRY(hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal));
+        step(c->capture_stream);
+        TERS_HIP_TRY(hipStreamEndCapture(c->capture_stream, &g));
+        TERS_HIP_TRY(hipGraphInstantiate(&c->md_exec, g, nullptr, nullptr, 0));
+        TERS_HIP_TRY(hipGraphDestroy(g));
+        c->md_key = key;
+      }
+      for (int s = 0; s < nsteps; ++s) TERS_HIP_TRY(hipGraphLaunch(c->md_exec, c->stream));
+    }
+    return TERS_OK;
+  });
+}
+
+ters_status ters_md_rebuilds(ters_ctx *c, int64_t *out) {
+  if (!c || !out) return TERS_ERR_INVALID_ARG;
+  return guard(c, [&]() {
+    TERS_HIP_TRY(hipMemcpyAsync(out, c->rebuilds.p, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
+    sync(c);
+    return TERS_OK;
+  });
+}
+
+// ---------------------------------------------------------------------------
+// batches
+// ---------------------------------------------------------------------------
+
+namespace {
+
+__global__ void k_split_partials(const double *partials, int nconf, double *e, double *w) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nconf) return;
+  if (e) e[c] = partials[(int64_t)c * 8];
+  if (w)
+    for (int k = 0; k < 6; ++k) w[(int64_t)c * 6 + k] = partials[(int64_t)c * 8 + 1 + k];
+}
+
+void batch_enqueue(ters_plan *p, const double *x, const int32_t *type, double *e, double *f,
+                   double *w, const double *e_bar, const double *f_bar, double *xg, double *pg,
+                   hipStream_t s) {
+  ters_ctx *c = p->ctx;
+  NList &nl = p->nl;
+  nlist_build(nl, x, nullptr, p->errw.as<uint32_t>(), s);
+  FwdArgs a = base_args(c, nl, p->precision, p->N, x, type, true);
+  a.flags = (f ? TERS_FORCES : 0u) | TERS_ENERGY | TERS_VIRIAL;
+  a.forces = f;
+  a.partials = p->partials.as<double>();
+  a.err = p->errw.as<uint32_t>();
+  launch_fill_f64(p->partials.as<double>(), 0.0, 8 * (int64_t)p->nconf, s);
+  if (f) launch_fill_f64(f, 0.0, 3 * (int64_t)p->N, s);
+  int nbo[1];
+  launch_forward(a, p->precision, p->A, nbo, s);
+  if (e || w)
+    k_split_partials<<<(p->nconf + 255) / 256, 256, 0, s>>>(p->partials.as<double>(), p->nconf, e, w);
+  if (f_bar) {
+    FwdArgs b = base_args(c, nl, p->precision, p->N, x, type, true);
+    b.fbar = f_bar;
+    b.ebar = 0.0;
+    b.ebar_conf = e_bar;
+    b.xgrad = xg;
+    b.pgrad = pg;
+    b.flags = TERS_PARAM_GRAD;
+    b.err = p->errw.as<uint32_t>();
+    b.kmax = 0;
+    const int nt = c->ntypes;
+    launch_fill_f64(xg, 0.0, 3 * (int64_t)p->N, s);
+    launch_fill_f64(pg, 0.0, (int64_t)nt * nt * nt * kNField, s);
+    launch_adjoint(b, p->precision, 0, s);
+  }
+}
+
+}  // namespace
+
+ters_status ters_batch_plan(ters_ctx *c, int32_t nconf, const int32_t *natoms,
+                            const double *boxes, int precision, uint32_t flags, ters_plan **out) {
+  if (!c || !out) return TERS_ERR_INVALID_ARG;
+  *out = nullptr;
+  ters_plan *p = new ters_plan();
+  ters_status st = guard(c, [&]() {
+    require(c->ntypes > 0, TERS_ERR_PARAMS, "parameters not set");
+    require(nconf >= 1 && natoms && boxes, TERS_ERR_INVALID_ARG, "bad arguments");
+    require(precision == TERS_FP64 || precision == TERS_MIXED, TERS_ERR_INVALID_ARG, "bad precision");
+    p->ctx = c;
+    p->nconf = nconf;
+    p->precision = precision;
+    p->flags = flags;
+    p->natoms.assign(natoms, natoms + nconf);
+    p->off.resize(nconf + 1);
+    int64_t tot = 0;
+    for (int i = 0; i < nconf; ++i) {
+      require(natoms[i] >= 1, TERS_ERR_INVALID_ARG, "every configuration needs atoms");
+      p->off[i] = (int32_t)tot;
+      tot += natoms[i];
+    }
+    require(tot < (1ll << 31), TERS_ERR_UNSUPPORTED, "too many atoms");
+    p->off[nconf] = (int32_t)tot;
+    p->N = (int)tot;
+    std::vector<int32_t> conf_of(p->N);
+    for (int i = 0; i < nconf; ++i)
+      for (int k = p->off[i]; k < p->off[i + 1]; ++k) conf_of[k] = i;
+    p->nl.cap = 16;
+    nl_setup(p->nl, nconf, natoms, boxes, c->rc_max, 0.0,
+             nconf > 1 ? &conf_of : nullptr, c->stream);
+    if (nconf == 1) {
+      // a batch of one still uses the per-configuration attribution path
+      p->nl.conf_of.ensure(sizeof(int32_t) * std::max(p->N, 1));
+      TERS_HIP_TRY(hipMemcpyAsync(p->nl.conf_of.p, conf_of.data(), sizeof(int32_t) * p->N,
+                                  hipMemcpyHostToDevice, c->stream));
+    }
+    p->partials.ensure(sizeof(double) * 8 * nconf);
+    p->errw.ensure(64);
+    TERS_HIP_TRY(hipMemsetAsync(p->errw.p, 0, 64, c->stream));
+    sync(c);
+    return TERS_OK;
+  });
+  if (st != TERS_OK) {
+    delete p;
+    return st;
+  }
+  *out = p;
+  return TERS_OK;
+}
+
+ters_status ters_batch_run(ters_plan *p, const double *x, const int32_t *type, double *e,
+                           double *f, double *w, const double *e_bar, const double *f_bar,
+                           double *xg, double *pg) {
+  if (!p || !p->ctx) return TERS_ERR_INVALID_ARG;
+  ters_ctx *c = p->ctx;
+  return guard(c, [&]() {
+    require(x && type, TERS_ERR_INVALID_ARG, "x and type required");
+    require(!f_bar || (e_bar && xg && pg), TERS_ERR_INVALID_ARG, "adjoint needs e_bar, x_grad, param_grad");
+    NList &nl = p->nl;
+    if (!p->tuned) {
+      // size the list, then pick the schedule on this data (eager, synchronising)
+      nl_build_sync(c, nl, x, p->errw);
+      DevBuf ft;
+      ft.ensure(sizeof(double) * 3 * (size_t)p->N);
+      hipEvent_t e0, e1;
+      TERS_HIP_TRY(hipEventCreate(&e0));
+      TERS_HIP_TRY(hipEventCreate(&e1));
+      const int cands[] = {16, 32, 48, 64};
+      double best = 1e300;
+      int bestA = 32;
+      for (int A : cands) {
+        FwdArgs a = base_args(c, nl, p->precision, p->N, x, type, true);
+        a.flags = TERS_FORCES | TERS_ENERGY | TERS_VIRIAL;
+        a.forces = ft.as<double>();
+        a.partials = p->partials.as<double>();
+        a.err = p->errw.as<uint32_t>();
+        int nbo[1];
+        launch_forward(a, p->precision, A, nbo, c->stream);
+        TERS_HIP_TRY(hipEventRecord(e0, c->stream));
+        for (int r = 0; r < 3; ++r) launch_forward(a, p->precision, A, nbo, c->stream);
+        TERS_HIP_TRY(hipEventRecord(e1, c->stream));
+        TERS_HIP_TRY(hipEventSynchronize(e1));
+        float ms = 0.f;
+        TERS_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        if (1000.0 * ms / 3 < best) {
+          best = 1000.0 * ms / 3;
+          bestA = A;
+        }
+      }
+      hipEventDestroy(e0);
+      hipEventDestroy(e1);
+      ft.release();
+      p->A = bestA;
+      p->best_us = best;
+      p->tuned = true;
+    }
+    std::vector<const void *> key = {x, type, e, f, w, e_bar, f_bar, xg, pg};
+    if (!p->exec || key != p->key) {
+      if (p->exec) {
+        TERS_HIP_TRY(hipGraphExecDestroy(p->exec));
+        p->exec = nullptr;
+      }
+      if (!c->capture_stream) TERS_HIP_TRY(hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
+      sync(c);
+      hipGraph_t g;
+      TERS_HIP_TRY(hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal));
+      batch_enqueue(p, x, type, e, f, w, e_bar, f_bar, xg, pg, c->capture_stream);
+      TERS_HIP_TRY(hipStreamEndCapture(c->capture_stream, &g));
+      TERS_HIP_TRY(hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0));
+      TERS_HIP_TRY(hipGraphDestroy(g));
+      p->key = key;
+    }
+    TERS_HIP_TRY(hipGraphLaunch(p->exec, c->stream));
+    return TERS_OK;
+  });
+}
+
+ters_status ters_plan_destroy(ters_plan *p) {
+  if (!p) return TERS_ERR_INVALID_ARG;
+  if (p->ctx) {
+    hipSetDevice(p->ctx->device);
+    hipStreamSynchronize(p->ctx->stream);
+  }
+  if (p->exec) hipGraphExecDestroy(p->exec);
+  DevBuf *bufs[] = {&p->partials, &p->ebuf, &p->errw, &p->nl.conf, &p->nl.conf_of, &p->nl.count,
+                    &p->nl.list, &p->nl.order, &p->nl.cell_of, &p->nl.cell_count,
+                    &p->nl.cell_start, &p->nl.scan_tmp, &p->nl.xref, &p->nl.maxcount};
+  for (DevBuf *b : bufs) b->release();
+  delete p;
+  return TERS_OK;
+}
+
+ters_status ters_plan_schedule(const ters_plan *p, double *out3) {
+  if (!p || !out3) return TERS_ERR_INVALID_ARG;
+  out3[0] = p->A;
+  out3[1] = p->precision == TERS_FP64 ? 256 : 256;
+  out3[2] = p->best_us;
+  return TERS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// parameter tables
+// ---------------------------------------------------------------------------
+
+namespace {
+
+// element sets in Tersoff's notation; cutoff given as Tersoff's R, S
+struct Elem {
+  double A, B, lam1, lam2, beta, n, c, d, h, lam3, m, gamma, Rt, St;
+};
+const Elem kSiB = {3264.7, 95.373, 3.2394, 1.3258, 0.33675, 22.956, 4.8381, 2.0417, 0.0, 1.3258, 3.0, 1.0, 2.8, 3.2};
+const Elem kSiC = {1830.8, 471.18, 2.4799, 1.7322, 1.1e-6, 0.78734, 1.0039e5, 16.217, -0.59825, 0.0, 3.0, 1.0, 2.7, 3.0};
+const Elem kC = {1393.6, 346.74, 3.4879, 2.2119, 1.5724e-7, 0.72751, 3.8049e4, 4.3484, -0.57058, 0.0, 3.0, 1.0, 1.8, 2.1};
+const double kChiSiC = 0.9776;
+
+void put_entry(double *row, const Elem &ei, double A, double B, double l1, double l2, double Rt, double St) {
+  row[FM] = ei.m;
+  row[FGAMMA] = ei.gamma;
+  row[FLAM3] = ei.lam3;
+  row[FC] = ei.c;
+  row[FD] = ei.d;
+  row[FH] = ei.h;
+  row[FN] = ei.n;
+  row[FBETA] = ei.beta;
+  row[FLAM2] = l2;
+  row[FB] = B;
+  row[FR] = 0.5 * (Rt + St);
+  row[FDC] = 0.5 * (St - Rt);
+  row[FLAM1] = l1;
+  row[FA] = A;
+}
+
+}  // namespace
+
+ters_status ters_table_element(int32_t which, double *t) {
+  if (!t || which < 0 || which > 2) return TERS_ERR_INVALID_ARG;
+  const Elem &e = which == 0 ? kSiB : (which == 1 ? kSiC : kC);
+  put_entry(t, e, e.A, e.B, e.lam1, e.lam2, e.Rt, e.St);
+  return TERS_OK;
+}
+
+ters_status ters_table_sic(double *t) {
+  if (!t) return TERS_ERR_INVALID_ARG;
+  const Elem *el[2] = {&kSiC, &kC};
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j)
+      for (int k = 0; k < 2; ++k) {
+        const Elem &a = *el[i], &b = *el[j], &q = *el[k];
+        // (i,j) pair: geometric A and B (B scaled by chi for unlike pairs),
+        // arithmetic lambda1, lambda2; the zeta cutoff is the (i,k) one
+        const bool same = i == j;
+        const double A = same ? a.A : std::sqrt(a.A * b.A);
+        const double B = same ? a.B : kChiSiC * std::sqrt(a.B * b.B);
+        const double l1 = same ? a.lam1 : 0.5 * (a.lam1 + b.lam1);
+        const double l2 = same ? a.lam2 : 0.5 * (a.lam2 + b.lam2);
+        const double Rt = i == k ? a.Rt : std::sqrt(a.Rt * q.Rt);
+        const double St = i == k ? a.St : std::sqrt(a.St * q.St);
+        put_entry(t + ((i * 2 + j) * 2 + k) * kNField, a, A, B, l1, l2, Rt, St);
+      }
+  return TERS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,90 @@
+// Velocity-Verlet integration (metal units) with the list-rebuild test folded
+// into the position update, so that one molecular-dynamics step needs no host
+// synchronisation and can be captured in a graph.
+#include "ters_device.h"
+#include "ters_internal.h"
+
+namespace ters {
+
+namespace {
+
+constexpr double kFtm2v = 9648.533212331;  // eV/(Angstrom amu) -> Angstrom/ps^2
+constexpr int kBS = 256;
+
+// v += dt/2 F/m; x += dt v; flag = 1 if any atom moved more than skin/2 since
+// the last list build (FP64, minimum image)
+__global__ void k_vv_first(int n, double *__restrict__ x, double *__restrict__ v,
+                           const double *__restrict__ f, const int32_t *__restrict__ type,
+                           const double *__restrict__ mass, double dt,
+                           const double *__restrict__ xref, const ConfDesc *__restrict__ conf,
+                           double lim2, int32_t *flag) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  bool over = false;
+  if (i < n) {
+    const double s = 0.5 * dt * kFtm2v / mass[type[i]];
+    const ConfDesc &c = conf[0];
+    double r2 = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      double vv = v[3 * i + a] + s * f[3 * i + a];
+      double xx = x[3 * i + a] + dt * vv;
+      v[3 * i + a] = vv;
+      x[3 * i + a] = xx;
+      double d = xx - xref[3 * i + a];
+      d -= c.box[a] * rint(d * c.inv_box[a]);
+      r2 += d * d;
+    }
+    over = !(r2 <= lim2);
+  }
+  if (__ballot(over) != 0ull && lane_id() == 0) *flag = 1;
+}
+
+// v += dt/2 F/m
+__global__ void k_vv_second(int n, double *__restrict__ v, const double *__restrict__ f,
+                            const int32_t *__restrict__ type, const double *__restrict__ mass,
+                            double dt) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double s = 0.5 * dt * kFtm2v / mass[type[i]];
+  v[3 * i + 0] += s * f[3 * i + 0];
+  v[3 * i + 1] += s * f[3 * i + 1];
+  v[3 * i + 2] += s * f[3 * i + 2];
+}
+
+__global__ void k_count_rebuild(const int32_t *flag, int64_t *counter) {
+  if (*flag) *counter += 1;
+}
+
+// trace[*step] = *e; ++*step   (a device-side step counter keeps a captured
+// step graph replayable)
+__global__ void k_store_trace(const double *e, double *trace, int32_t *step) {
+  trace[*step] = *e;
+  *step += 1;
+}
+
+}  // namespace
+
+void launch_vv_first(int n, double *x, double *v, const double *f, const int32_t *type,
+                     const double *mass, double dt, const NList &nl, int32_t *flag,
+                     hipStream_t s) {
+  if (n <= 0) return;
+  const double half = 0.5 * nl.skin;
+  k_vv_first<<<(n + kBS - 1) / kBS, kBS, 0, s>>>(n, x, v, f, type, mass, dt, nl.xref.as<double>(),
+                                                 nl.conf.as<ConfDesc>(), half * half, flag);
+}
+
+void launch_vv_second(int n, double *v, const double *f, const int32_t *type, const double *mass,
+                      double dt, hipStream_t s) {
+  if (n <= 0) return;
+  k_vv_second<<<(n + kBS - 1) / kBS, kBS, 0, s>>>(n, v, f, type, mass, dt);
+}
+
+void launch_count_rebuild(const int32_t *flag, int64_t *counter, hipStream_t s) {
+  k_count_rebuild<<<1, 1, 0, s>>>(flag, counter);
+}
+
+void launch_store_trace(const double *e, double *trace, int32_t *step, hipStream_t s) {
+  k_store_trace<<<1, 1, 0, s>>>(e, trace, step);
+}
+
+}  // namespace ters

@@ -1,0 +1,162 @@
+// Device-side building blocks of the Tersoff kernels (gfx950, wave64).
+//
+//  * scalar types: double (FP64 path), float (mixed path), and Dual<B>, a
+//    forward-mode dual number (value + one tangent) used by the adjoint;
+//  * math on those types (exp, log, log1p, sqrt, sin, cos, reciprocal);
+//  * the per-entry kernel parameter record derived from the 14-field table;
+//  * wave-level reductions (the paper's in-register reductions, Section V-A)
+//    and hardware FP64 atomics.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define DEV __device__ __forceinline__
+
+namespace ters {
+
+constexpr int kWave = 64;
+constexpr int kNField = 14;
+enum Field {
+  FM = 0, FGAMMA, FLAM3, FC, FD, FH, FN, FBETA, FLAM2, FB, FR, FDC, FLAM1, FA
+};
+
+// ---------------------------------------------------------------------------
+// dual numbers
+// ---------------------------------------------------------------------------
+template <class B>
+struct Dual {
+  B v, d;
+  Dual() = default;
+  DEV Dual(B a) : v(a), d(B(0)) {}
+  DEV Dual(B a, B b) : v(a), d(b) {}
+};
+
+template <class T> struct Base { using type = T; };
+template <class B> struct Base<Dual<B>> { using type = B; };
+template <class T> using base_t = typename Base<T>::type;
+template <class T> struct IsDual { static constexpr bool value = false; };
+template <class B> struct IsDual<Dual<B>> { static constexpr bool value = true; };
+
+DEV double val(double a) { return a; }
+DEV float val(float a) { return a; }
+template <class B> DEV B val(const Dual<B> &a) { return a.v; }
+DEV double tan_of(double) { return 0.0; }
+DEV float tan_of(float) { return 0.0f; }
+template <class B> DEV B tan_of(const Dual<B> &a) { return a.d; }
+
+template <class B> DEV Dual<B> operator+(Dual<B> a, Dual<B> b) { return {a.v + b.v, a.d + b.d}; }
+template <class B> DEV Dual<B> operator-(Dual<B> a, Dual<B> b) { return {a.v - b.v, a.d - b.d}; }
+template <class B> DEV Dual<B> operator*(Dual<B> a, Dual<B> b) { return {a.v * b.v, a.d * b.v + a.v * b.d}; }
+template <class B> DEV Dual<B> operator-(Dual<B> a) { return {-a.v, -a.d}; }
+template <class B> DEV Dual<B> operator+(Dual<B> a, B b) { return {a.v + b, a.d}; }
+template <class B> DEV Dual<B> operator+(B b, Dual<B> a) { return {a.v + b, a.d}; }
+template <class B> DEV Dual<B> operator-(Dual<B> a, B b) { return {a.v - b, a.d}; }
+template <class B> DEV Dual<B> operator-(B b, Dual<B> a) { return {b - a.v, -a.d}; }
+template <class B> DEV Dual<B> operator*(Dual<B> a, B b) { return {a.v * b, a.d * b}; }
+template <class B> DEV Dual<B> operator*(B b, Dual<B> a) { return {a.v * b, a.d * b}; }
+template <class B> DEV Dual<B> &operator+=(Dual<B> &a, Dual<B> b) { a.v += b.v; a.d += b.d; return a; }
+template <class B> DEV Dual<B> &operator-=(Dual<B> &a, Dual<B> b) { a.v -= b.v; a.d -= b.d; return a; }
+
+// reciprocal: FP64 uses IEEE division; FP32 uses the hardware reciprocal
+// (1 ulp), which the mixed path's error budget allows.
+DEV double rcp(double a) { return 1.0 / a; }
+DEV float rcp(float a) { return __builtin_amdgcn_rcpf(a); }
+template <class B> DEV Dual<B> rcp(Dual<B> a) { B r = rcp(a.v); return {r, -a.d * r * r}; }
+template <class B> DEV Dual<B> operator/(Dual<B> a, Dual<B> b) { return a * rcp(b); }
+template <class B> DEV Dual<B> operator/(Dual<B> a, B b) { return {a.v / b, a.d / b}; }
+
+DEV double t_exp(double a) { return exp(a); }
+DEV float t_exp(float a) { return expf(a); }
+DEV double t_log(double a) { return log(a); }
+DEV float t_log(float a) { return logf(a); }
+DEV double t_log1p(double a) { return log1p(a); }
+DEV float t_log1p(float a) { return log1pf(a); }
+DEV double t_sqrt(double a) { return sqrt(a); }
+DEV float t_sqrt(float a) { return sqrtf(a); }
+DEV double t_sin(double a) { return sin(a); }
+DEV float t_sin(float a) { return sinf(a); }
+DEV double t_cos(double a) { return cos(a); }
+DEV float t_cos(float a) { return cosf(a); }
+
+template <class B> DEV Dual<B> t_exp(Dual<B> a) { B e = t_exp(a.v); return {e, a.d * e}; }
+template <class B> DEV Dual<B> t_log(Dual<B> a) { return {t_log(a.v), a.d * rcp(a.v)}; }
+template <class B> DEV Dual<B> t_log1p(Dual<B> a) { return {t_log1p(a.v), a.d * rcp(B(1) + a.v)}; }
+template <class B> DEV Dual<B> t_sqrt(Dual<B> a) { B s = t_sqrt(a.v); return {s, a.d * B(0.5) * rcp(s)}; }
+template <class B> DEV Dual<B> t_sin(Dual<B> a) { return {t_sin(a.v), a.d * t_cos(a.v)}; }
+template <class B> DEV Dual<B> t_cos(Dual<B> a) { return {t_cos(a.v), -a.d * t_sin(a.v)}; }
+
+// conversion of an FP64 value (with optional FP64 tangent) to the compute type
+template <class T> struct Conv;
+template <> struct Conv<double> { static DEV double from(double v, double) { return v; } };
+template <> struct Conv<float> { static DEV float from(double v, double) { return (float)v; } };
+template <class B> struct Conv<Dual<B>> {
+  static DEV Dual<B> from(double v, double d) { return {(B)v, (B)d}; }
+};
+
+// widen to FP64 accumulators
+template <class T> struct Acc { using type = double; };
+template <class B> struct Acc<Dual<B>> { using type = Dual<double>; };
+template <class T> using acc_t = typename Acc<T>::type;
+DEV double widen(double a) { return a; }
+DEV double widen(float a) { return (double)a; }
+template <class B> DEV Dual<double> widen(Dual<B> a) { return {(double)a.v, (double)a.d}; }
+
+// ---------------------------------------------------------------------------
+// kernel parameter record (derived once per table entry on the host)
+// ---------------------------------------------------------------------------
+template <class B>
+struct KParam {
+  // cutoff of the distance this entry is used for: R +- D, pi/(2D), pi/(4D)
+  B R, D, rcut, rin, pi2d, pi4d;
+  // pair part (valid for entries [ti][tj][tj]); *_lo hold what rounding the
+  // FP64 value to B dropped (0 for FP64), so FP32 exponentials stay unbiased
+  B A, lam1, Bc, lam2, beta, n, inv2n;
+  B A_lo, lam1_lo, B_lo, lam2_lo, R_lo, h_lo;
+  // three-body part: gamma, c^2, d^2, h, gamma c^2, c^2/d^2, lambda3, c, d
+  B gamma, c2, d2, h, gc2, c2d2, lam3, c, d;
+  int32_t m3;   // 1 when m == 3, 0 when m == 1
+  int32_t pad;
+};
+
+// c * exp(-lam * r) with c = c_hi + c_lo and lam = lam_hi + lam_lo.  In FP32 the
+// rounding of lam to single precision would shift every exponent by lam*r*eps
+// (r ~ 2.4 A, lam*r ~ 8): a systematic bias of the pair energy.  The product
+// lam*r is therefore formed exactly (fma residual plus the lo part) and the
+// residual applied to first order.
+// r = r_hi + r_lo likewise carries the FP64 distance into the FP32 path.
+DEV double scaled_exp(double c, double, double lam, double, double r, double) {
+  return c * exp(-lam * r);
+}
+DEV float scaled_exp(float c, float c_lo, float lam, float lam_lo, float r, float r_lo) {
+  float p = lam * r;
+  float corr = fmaf(lam, r, -p) + (lam_lo * r + lam * r_lo);
+  float e = expf(-p);
+  return e * (c + (c_lo - c * corr));
+}
+template <class B>
+DEV Dual<B> scaled_exp(B c, B c_lo, B lam, B lam_lo, Dual<B> r, B r_lo) {
+  B v = scaled_exp(c, c_lo, lam, lam_lo, r.v, r_lo);
+  return {v, -(lam + lam_lo) * v * r.d};
+}
+
+// replace the value part of a scalar (keeps a dual number's tangent)
+DEV void set_val(double &a, double v) { a = v; }
+DEV void set_val(float &a, double v) { a = (float)v; }
+template <class B> DEV void set_val(Dual<B> &a, double v) { a.v = (B)v; }
+
+// ---------------------------------------------------------------------------
+// wave-level helpers
+// ---------------------------------------------------------------------------
+DEV int lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }
+
+DEV double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+DEV Dual<double> wave_sum(Dual<double> v) { return {wave_sum(v.v), wave_sum(v.d)}; }
+
+// hardware FP64 atomic add to global memory (global_atomic_add_f64)
+DEV void atomic_add(double *p, double v) { unsafeAtomicAdd(p, v); }
+
+}  // namespace ters

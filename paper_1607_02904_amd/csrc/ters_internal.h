@@ -1,0 +1,134 @@
+// Host-side internals of libtersoff shared by the C-ABI layer and the kernel
+// launchers.  Not part of the public interface.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "tersoff.h"
+
+namespace ters {
+
+#define TERS_HIP_TRY(expr)                                              \
+  do {                                                                  \
+    hipError_t e_ = (expr);                                             \
+    if (e_ != hipSuccess) throw HipError(e_, #expr, __FILE__, __LINE__); \
+  } while (0)
+
+struct HipError {
+  hipError_t code;
+  std::string what;
+  HipError(hipError_t c, const char *expr, const char *file, int line)
+      : code(c), what(std::string(hipGetErrorString(c)) + " in " + expr + " (" + file + ":" +
+                      std::to_string(line) + ")") {}
+};
+
+struct StatusError {
+  ters_status code;
+  std::string what;
+  StatusError(ters_status c, std::string w) : code(c), what(std::move(w)) {}
+};
+
+// Grow-only device buffer.
+struct DevBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+  void ensure(size_t b) {
+    if (b <= bytes) return;
+    if (p) TERS_HIP_TRY(hipFree(p));
+    p = nullptr;
+    bytes = 0;
+    TERS_HIP_TRY(hipMalloc(&p, b));
+    bytes = b;
+  }
+  void release() {
+    if (p) hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  template <class T> T *as() const { return static_cast<T *>(p); }
+};
+
+// Per-configuration geometry for neighbour binning (device copy).
+struct ConfDesc {
+  double box[3];
+  double inv_box[3];
+  int32_t nc[3];      // cells per axis (1, or >= 3)
+  int32_t cell_off;   // first global cell of this configuration
+  int32_t atom_off;   // first atom
+  int32_t natoms;
+};
+
+// Device error word bits (latched by kernels, read at sync points).
+enum : uint32_t { kErrNlistOverflow = 1u, kErrNotFinite = 2u, kErrTooManyInCutoff = 4u };
+
+// Neighbour list state.  One list per configuration set (a single system is
+// a set of one).
+struct NList {
+  int32_t n = 0, cap = 0, nconf = 0;
+  int64_t ncell = 0;
+  double rlist = 0.0, skin = 0.0;
+  bool valid = false;
+  std::vector<ConfDesc> conf_h;
+  DevBuf conf;        // ConfDesc[nconf]
+  DevBuf conf_of;     // int32[n] (only for nconf > 1)
+  DevBuf count;       // int32[n]
+  DevBuf list;        // int32[n][cap]
+  DevBuf order;       // int32[n]: atoms in cell order
+  DevBuf cell_of;     // int32[n]
+  DevBuf cell_count;  // int32[ncell + 1]
+  DevBuf cell_start;  // int32[ncell + 1]
+  DevBuf scan_tmp;    // int32 block sums
+  DevBuf xref;        // double[n][3]
+  DevBuf maxcount;    // int32[1]
+};
+
+// Forward / adjoint launch description.
+struct FwdArgs {
+  int32_t n;
+  const double *x;
+  const int32_t *type;
+  const double *fbar;      // adjoint direction (dual kernels) or null
+  const ConfDesc *conf;    // device
+  const int32_t *conf_of;  // device int32[n] or null (single configuration)
+  const int32_t *order;    // processing order (cell order)
+  const int32_t *count;
+  const int32_t *list;
+  int32_t cap;
+  int32_t ntypes;
+  const void *kparam;      // KParam<B>[ntypes^3]
+  const void *filt2;       // B[ntypes^2]: squared filter radius per (ti, tk)
+  int32_t cut_consistent;  // 1 if the k-cutoff never depends on tj
+  int32_t kmax;
+  uint32_t flags;
+  double *forces;          // [n][3] (atomic accumulate) or null
+  double *e_atom;          // [n] or null
+  double *partials;        // [nblocks][partial_stride] energy / virial (per config if batched)
+  double *pgrad;           // [ntypes^3][14] accumulated, or null
+  double ebar;             // adjoint: scalar cotangent of E (single system)
+  const double *ebar_conf; // adjoint: per-configuration cotangent (batch) or null
+  double *xgrad;           // adjoint output [n][3]
+  uint32_t *err;
+};
+
+// launchers (implemented in the .hip files)
+void launch_fill_i32(int32_t *p, int32_t v, int64_t n, const int32_t *cond, hipStream_t s);
+void launch_fill_f64(double *p, double v, int64_t n, hipStream_t s);
+void nlist_build(NList &nl, const double *x, const int32_t *cond, uint32_t *err, hipStream_t s);
+void nlist_check(const NList &nl, const double *x, int32_t *flag, hipStream_t s);
+void launch_forward(const FwdArgs &a, int precision, int atoms_per_block, int nblocks_out[1],
+                    hipStream_t s);
+void launch_adjoint(const FwdArgs &a, int precision, int atoms_per_block, hipStream_t s);
+int forward_blocks(int n, int atoms_per_block);
+void launch_reduce_partials(const double *partials, int nblocks, int stride, double *energy,
+                            double *virial, int accumulate, hipStream_t s);
+void launch_vv_first(int n, double *x, double *v, const double *f, const int32_t *type,
+                     const double *mass, double dt, const NList &nl, int32_t *flag, hipStream_t s);
+void launch_vv_second(int n, double *v, const double *f, const int32_t *type, const double *mass,
+                      double dt, hipStream_t s);
+void launch_count_rebuild(const int32_t *flag, int64_t *counter, hipStream_t s);
+void launch_store_trace(const double *e, double *trace, int32_t *step, hipStream_t s);
+
+}  // namespace ters

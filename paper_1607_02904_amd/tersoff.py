@@ -1,0 +1,344 @@
+"""Python binding of libtersoff (ctypes over torch device tensors).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  Torch supplies device memory and the current stream.  If the shared
+library is missing, loading fails with an error; there is no fallback.
+
+Units: Angstrom, eV, amu, ps.  Positions float64 [n, 3] on the GPU, species
+int32 [n] on the GPU, box: three side lengths (host sequence).
+"""
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtersoff.so")
+
+FP64 = 0
+MIXED = 1
+ENERGY, FORCES, VIRIAL, PER_ATOM_E, ACCUMULATE, PARAM_GRAD = 1, 2, 4, 8, 16, 32
+NFIELD = 14
+FIELDS = ("m", "gamma", "lam3", "c", "d", "h", "n", "beta", "lam2", "B", "R", "D", "lam1", "A")
+
+STATUS = {0: "TERS_OK", 1: "TERS_ERR_INVALID_ARG", 2: "TERS_ERR_BOX_TOO_SMALL",
+          3: "TERS_ERR_NLIST_OVERFLOW", 4: "TERS_ERR_PARAMS", 5: "TERS_ERR_NOT_FINITE",
+          6: "TERS_ERR_HIP", 7: "TERS_ERR_UNSUPPORTED", 8: "TERS_ERR_NO_LIST"}
+
+EXPORTS = ("ters_create", "ters_destroy", "ters_set_stream", "ters_sync", "ters_last_error",
+           "ters_set_params", "ters_build_nlist", "ters_needs_rebuild", "ters_nlist_stats",
+           "ters_compute", "ters_compute_ex", "ters_backward", "ters_md_run", "ters_md_rebuilds",
+           "ters_batch_plan", "ters_batch_run", "ters_plan_destroy", "ters_plan_schedule",
+           "ters_set_schedule", "ters_autotune", "ters_profile_forward", "ters_table_sic",
+           "ters_table_element", "ters_version")
+
+_lib = None
+
+
+class TersoffError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s: %s" % (STATUS.get(code, code), msg))
+        self.code = code
+        self.name = STATUS.get(code, str(code))
+
+
+def load_library(path=LIB_PATH):
+    """Load libtersoff.so and declare its signatures (no GPU needed)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError("libtersoff.so not built (run python -m paper_1607_02904_amd.build)")
+    L = ctypes.CDLL(path)
+    P, I32, U32, D, I64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32, ctypes.c_double, ctypes.c_int64
+    PP = ctypes.POINTER(ctypes.c_void_p)
+    sig = {
+        "ters_create": [PP, ctypes.c_int, P],
+        "ters_destroy": [P],
+        "ters_set_stream": [P, P],
+        "ters_sync": [P],
+        "ters_set_params": [P, I32, P, P],
+        "ters_build_nlist": [P, I32, P, P, P, D],
+        "ters_needs_rebuild": [P, P, P],
+        "ters_nlist_stats": [P, P],
+        "ters_compute": [P, I32, P, P, P, ctypes.c_int, U32, P, P, P, P],
+        "ters_compute_ex": [P, I32, P, P, P, ctypes.c_int, U32, P, P, P, P, P],
+        "ters_backward": [P, I32, P, P, P, ctypes.c_int, D, P, P, P],
+        "ters_md_run": [P, I32, P, P, P, P, P, D, I32, D, ctypes.c_int, P, ctypes.c_int],
+        "ters_md_rebuilds": [P, P],
+        "ters_batch_plan": [P, I32, P, P, ctypes.c_int, U32, PP],
+        "ters_batch_run": [P, P, P, P, P, P, P, P, P, P],
+        "ters_plan_destroy": [P],
+        "ters_plan_schedule": [P, P],
+        "ters_set_schedule": [P, I32, I32],
+        "ters_autotune": [P, I32, P, P, P, ctypes.c_int, P],
+        "ters_profile_forward": [P, I32, P, P, P, ctypes.c_int, I32, P],
+        "ters_table_sic": [P],
+        "ters_table_element": [I32, P],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    L.ters_last_error.argtypes = [P]
+    L.ters_last_error.restype = ctypes.c_char_p
+    L.ters_version.argtypes = []
+    L.ters_version.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _hostbuf(a, dtype):
+    a = np.ascontiguousarray(a, dtype=dtype)
+    return a, a.ctypes.data_as(ctypes.c_void_p)
+
+
+def table_sic():
+    """2-species Si/C table (Si(C) set, Tersoff 1989 mixing) from the library."""
+    t = np.zeros((2, 2, 2, NFIELD))
+    _check(None, load_library().ters_table_sic(t.ctypes.data_as(ctypes.c_void_p)))
+    return t
+
+
+def table_element(which):
+    """One-species table: 'Si(B)', 'Si(C)' or 'C'."""
+    idx = {"Si(B)": 0, "Si(C)": 1, "C": 2}[which]
+    t = np.zeros((1, 1, 1, NFIELD))
+    _check(None, load_library().ters_table_element(idx, t.ctypes.data_as(ctypes.c_void_p)))
+    return t
+
+
+def _check(ctx, code):
+    if code != 0:
+        msg = load_library().ters_last_error(ctx).decode() if ctx else ""
+        raise TersoffError(code, msg)
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Tersoff:
+    """One library context on one GPU, with its parameter table and list."""
+
+    def __init__(self, table, masses=None, device=0):
+        self._L = load_library()
+        self.device = torch.device("cuda", device)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(None, self._L.ters_create(ctypes.byref(h), device, _stream()))
+        self._h = h
+        self.set_params(table, masses)
+        self.skin = 0.0
+        self.box = None
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.ters_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _chk(self, code):
+        _check(self._h, code)
+
+    def _bind_stream(self):
+        self._L.ters_set_stream(self._h, _stream())
+
+    def set_params(self, table, masses=None):
+        t = np.ascontiguousarray(table, dtype=np.float64)
+        nt = t.shape[0]
+        assert t.shape == (nt, nt, nt, NFIELD), t.shape
+        self.table = t
+        self.ntypes = nt
+        m = None if masses is None else np.ascontiguousarray(masses, dtype=np.float64)
+        self._chk(self._L.ters_set_params(self._h, nt, t.ctypes.data_as(ctypes.c_void_p),
+                                          None if m is None else m.ctypes.data_as(ctypes.c_void_p)))
+
+    # -- neighbour list ---------------------------------------------------------
+    def build_nlist(self, x, types, box, skin=0.0):
+        self._bind_stream()
+        b, bp = _hostbuf(box, np.float64)
+        self._chk(self._L.ters_build_nlist(self._h, x.shape[0], _ptr(x), _ptr(types), bp, float(skin)))
+        self.skin = float(skin)
+        self.box = b.copy()
+
+    def needs_rebuild(self, x, flag=None):
+        self._bind_stream()
+        if flag is None:
+            flag = torch.zeros(1, dtype=torch.int32, device=x.device)
+        self._chk(self._L.ters_needs_rebuild(self._h, _ptr(x), _ptr(flag)))
+        return flag
+
+    def nlist_stats(self):
+        out = np.zeros(4, dtype=np.int64)
+        self._chk(self._L.ters_nlist_stats(self._h, out.ctypes.data_as(ctypes.c_void_p)))
+        return dict(n=int(out[0]), entries=int(out[1]), longest=int(out[2]), capacity=int(out[3]))
+
+    def set_schedule(self, atoms_per_block=0, kmax=0):
+        self._chk(self._L.ters_set_schedule(self._h, int(atoms_per_block), int(kmax)))
+
+    def autotune(self, x, types, box, precision=FP64):
+        self._bind_stream()
+        b, bp = _hostbuf(box, np.float64)
+        us = ctypes.c_double()
+        self._chk(self._L.ters_autotune(self._h, x.shape[0], _ptr(x), _ptr(types), bp, precision,
+                                        ctypes.byref(us)))
+        return us.value
+
+    def profile_forward(self, x, types, box, precision=FP64, reps=20):
+        """Average force-kernel duration in microseconds (HIP events)."""
+        self._bind_stream()
+        b, bp = _hostbuf(box, np.float64)
+        us = ctypes.c_double()
+        self._chk(self._L.ters_profile_forward(self._h, x.shape[0], _ptr(x), _ptr(types), bp, precision,
+                                               int(reps), ctypes.byref(us)))
+        return us.value
+
+    # -- evaluation --------------------------------------------------------------
+    def compute(self, x, types, box, precision=FP64, energy=True, forces=True, virial=True,
+                per_atom=False, param_grad=False, out=None):
+        """Energy [1], forces [n,3], virial [6], per-atom energy [n] and
+        dE/dtable as float64 device tensors (a dict)."""
+        self._bind_stream()
+        n = x.shape[0]
+        dev = x.device
+        o = dict(out or {})
+        flags = 0
+        if energy:
+            flags |= ENERGY
+            o.setdefault("energy", torch.empty(1, dtype=torch.float64, device=dev))
+        if forces:
+            flags |= FORCES
+            o.setdefault("forces", torch.empty((n, 3), dtype=torch.float64, device=dev))
+        if virial:
+            flags |= VIRIAL
+            o.setdefault("virial", torch.empty(6, dtype=torch.float64, device=dev))
+        if per_atom:
+            flags |= PER_ATOM_E
+            o.setdefault("e_atom", torch.empty(n, dtype=torch.float64, device=dev))
+        if param_grad:
+            flags |= PARAM_GRAD
+            o.setdefault("param_grad", torch.zeros(self.table.shape, dtype=torch.float64, device=dev))
+        b, bp = _hostbuf(box, np.float64)
+        self._chk(self._L.ters_compute_ex(self._h, n, _ptr(x), _ptr(types), bp, precision, flags,
+                                          _ptr(o.get("energy")), _ptr(o.get("forces")),
+                                          _ptr(o.get("virial")), _ptr(o.get("e_atom")),
+                                          _ptr(o.get("param_grad"))))
+        return o
+
+    def backward(self, x, types, box, e_bar, f_bar, precision=FP64):
+        """Vector-Jacobian product of (E, F) with cotangents (e_bar, f_bar):
+        returns (x_grad [n,3], param_grad [nt,nt,nt,14])."""
+        self._bind_stream()
+        n = x.shape[0]
+        xg = torch.empty((n, 3), dtype=torch.float64, device=x.device)
+        pg = torch.empty(self.table.shape, dtype=torch.float64, device=x.device)
+        b, bp = _hostbuf(box, np.float64)
+        fb = f_bar.contiguous()
+        self._chk(self._L.ters_backward(self._h, n, _ptr(x), _ptr(types), bp, precision,
+                                        float(e_bar), _ptr(fb), _ptr(xg), _ptr(pg)))
+        return xg, pg
+
+    def md_run(self, x, v, f, types, box, dt, nsteps, skin, precision=FP64, trace=None,
+               use_graph=True):
+        """Velocity Verlet in place on x, v, f; returns the energy trace."""
+        self._bind_stream()
+        if trace is None:
+            trace = torch.empty(max(nsteps, 1), dtype=torch.float64, device=x.device)
+        b, bp = _hostbuf(box, np.float64)
+        self._chk(self._L.ters_md_run(self._h, x.shape[0], _ptr(x), _ptr(v), _ptr(f), _ptr(types), bp,
+                                      float(dt), int(nsteps), float(skin), precision, _ptr(trace),
+                                      1 if use_graph else 0))
+        return trace
+
+    def sync(self):
+        self._chk(self._L.ters_sync(self._h))
+
+    def rebuilds(self):
+        out = np.zeros(1, dtype=np.int64)
+        self._chk(self._L.ters_md_rebuilds(self._h, out.ctypes.data_as(ctypes.c_void_p)))
+        return int(out[0])
+
+
+class BatchPlan:
+    """Many independent configurations evaluated with one graph launch."""
+
+    def __init__(self, model, natoms, boxes, precision=MIXED):
+        self.model = model
+        L = model._L
+        self._L = L
+        model._bind_stream()
+        na = np.ascontiguousarray(natoms, dtype=np.int32)
+        bx = np.ascontiguousarray(boxes, dtype=np.float64).reshape(-1, 3)
+        self.nconf = na.size
+        self.natoms = na
+        self.offsets = np.concatenate([[0], np.cumsum(na)])
+        h = ctypes.c_void_p()
+        _check(model._h, L.ters_batch_plan(model._h, self.nconf, na.ctypes.data_as(ctypes.c_void_p),
+                                           bx.ctypes.data_as(ctypes.c_void_p), precision, 0,
+                                           ctypes.byref(h)))
+        self._h = h
+
+    def run(self, x, types, e=None, f=None, w=None, e_bar=None, f_bar=None, x_grad=None,
+            param_grad=None):
+        self.model._bind_stream()
+        _check(self.model._h, self._L.ters_batch_run(self._h, _ptr(x), _ptr(types), _ptr(e), _ptr(f),
+                                                     _ptr(w), _ptr(e_bar), _ptr(f_bar), _ptr(x_grad),
+                                                     _ptr(param_grad)))
+
+    def schedule(self):
+        out = np.zeros(3)
+        _check(self.model._h, self._L.ters_plan_schedule(self._h, out.ctypes.data_as(ctypes.c_void_p)))
+        return dict(atoms_per_block=int(out[0]), block=int(out[1]), us=float(out[2]))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.ters_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class TersoffEF(torch.autograd.Function):
+    """(E, F) = Tersoff(x; table) with a hand-written adjoint.
+
+    forward(model, x, table, types, box, precision) -> (E [1], F [n,3])
+    backward returns dL/dx and dL/dtable from one dual-number pass of the
+    force kernel (zeta recomputed, no stored triplets)."""
+
+    @staticmethod
+    def forward(ctx, model, x, table, types, box, precision=FP64):
+        tab = table.detach().cpu().numpy()
+        if not np.array_equal(tab, model.table):
+            model.set_params(tab)
+        o = model.compute(x.detach(), types, box, precision, energy=True, forces=True, virial=False)
+        ctx.model = model
+        ctx.types = types
+        ctx.box = np.asarray(box, dtype=np.float64)
+        ctx.precision = precision
+        ctx.table_device = table.device
+        ctx.save_for_backward(x)
+        return o["energy"], o["forces"]
+
+    @staticmethod
+    def backward(ctx, e_bar, f_bar):
+        (x,) = ctx.saved_tensors
+        eb = 0.0 if e_bar is None else float(e_bar.reshape(-1)[0].item())
+        if f_bar is None:
+            f_bar = torch.zeros_like(x)
+        xg, pg = ctx.model.backward(x.detach(), ctx.types, ctx.box, eb, f_bar, ctx.precision)
+        return None, xg, pg.to(ctx.table_device), None, None, None
