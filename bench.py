@@ -45,6 +45,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--quick", action="store_true")
     ap.add_argument("--ncell", type=int, default=40)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain 256 MiB device copy (counter calibration)")
+    ap.add_argument("--md-only", action="store_true", help="only the headline MD workload")
     return ap.parse_args()
 
 
@@ -83,6 +86,14 @@ def main():
                                               table_sic)
 
     dev = "cuda"
+    if args.copy_probe:
+        # plain copy of known size: 256 MiB read + 256 MiB written per launch
+        a = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     print("bench: building inputs", file=sys.stderr, flush=True)
     x, t, box = inputs.si_bulk(args.ncell)
     n = len(x)
@@ -158,7 +169,7 @@ def main():
     }
 
     # ---- two-species SiC, 1,000,000 atoms, one mixed evaluation ----------------
-    if not args.quick:
+    if not args.quick and not args.md_only:
         print("bench: SiC 1M", file=sys.stderr, flush=True)
         xs, ts, bs = inputs.sic_bulk(50)
         ms = Tersoff(table_sic(), masses=[28.0855, 12.011])
@@ -180,6 +191,38 @@ def main():
         del xsd, tsd
 
     # ---- batched: 1,024 uneven SiC configurations, forward + adjoint ----------
+    if not args.md_only:
+        run_batch(args, out, dev)
+
+    # ---- CPU baseline: the FP64 oracle on the host ----------------------------
+    if not args.no_cpu:
+        print("bench: cpu baseline", file=sys.stderr, flush=True)
+        from oracle import oracle as orc
+        from oracle import params as oparams
+        otab = oparams.single(oparams.SI_B)
+        nl = orc.neighbours(x, box, 3.2 + skin)
+        reps = 0
+        t0 = time.perf_counter()
+        while True:
+            orc.compute(x, t, box, otab, nlist=nl)
+            reps += 1
+            if time.perf_counter() - t0 > 10.0 or reps >= 50:
+                break
+        elc = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": n * reps / elc, "unit": "atom-steps/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": "%d full FP64 force evaluations (Algorithm 2) of the same "
+                                         "%d-atom configuration over a prebuilt skin list; list "
+                                         "build and integration not timed" % (reps, n)}
+    model.close()
+    print(json.dumps(out), flush=True)
+
+
+def run_batch(args, out, dev):
+    import torch
+
+    from paper_1607_02904_amd import inputs
+    from paper_1607_02904_amd.tersoff import MIXED, BatchPlan, Tersoff, table_sic
     print("bench: batch", file=sys.stderr, flush=True)
     nconf = 256 if args.quick else 1024
     confs = inputs.sic_liquid_batch(nconf=nconf)
@@ -210,29 +253,6 @@ def main():
                       "atoms": N, "ms_per_launch": elb * 1e3, "schedule": plan.schedule()}
     plan.close()
     mb.close()
-
-    # ---- CPU baseline: the FP64 oracle on the host ----------------------------
-    if not args.no_cpu:
-        print("bench: cpu baseline", file=sys.stderr, flush=True)
-        from oracle import oracle as orc
-        from oracle import params as oparams
-        otab = oparams.single(oparams.SI_B)
-        nl = orc.neighbours(x, box, 3.2 + skin)
-        reps = 0
-        t0 = time.perf_counter()
-        while True:
-            orc.compute(x, t, box, otab, nlist=nl)
-            reps += 1
-            if time.perf_counter() - t0 > 10.0 or reps >= 50:
-                break
-        elc = time.perf_counter() - t0
-        out["cpu_baseline"] = {"value": n * reps / elc, "unit": "atom-steps/s", "cores": 1,
-                               "kind": "oracle",
-                               "sample": "%d full FP64 force evaluations (Algorithm 2) of the same "
-                                         "%d-atom configuration over a prebuilt skin list; list "
-                                         "build and integration not timed" % (reps, n)}
-    model.close()
-    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

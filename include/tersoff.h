@@ -184,6 +184,9 @@ ters_status ters_batch_plan(ters_ctx *ctx, int32_t nconf, const int32_t *natoms_
 ters_status ters_batch_run(ters_plan *plan, const double *x_cat, const int32_t *type_cat,
                            double *e, double *f_cat, double *w, const double *e_bar,
                            const double *f_bar_cat, double *x_grad_cat, double *param_grad);
+/* Destroying a context releases the device resources of its plans; such a
+ * plan then fails ters_batch_run with TERS_ERR_INVALID_ARG, and
+ * ters_plan_destroy still frees it. */
 ters_status ters_plan_destroy(ters_plan *plan);
 /* Schedule chosen by the plan's autotuner: out[0] = atoms per workgroup,
  * out[1] = workgroup size, out[2] = measured microseconds of the best. */

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstring>
 #include <exception>
+#include <iterator>
 #include <string>
 #include <vector>
 
@@ -35,6 +36,8 @@ struct ters_ctx {
   // molecular-dynamics step graph
   hipGraphExec_t md_exec = nullptr;
   std::vector<const void *> md_key;
+  // plans created on this context (released when the context is destroyed)
+  std::vector<ters_plan *> plans;
 };
 
 struct ters_plan {
@@ -243,6 +246,26 @@ void check_ready(ters_ctx *c, const NList &nl, int n, const double *box) {
               "box differs from the one the neighbour list was built for");
 }
 
+const void *bits(double v) {
+  intptr_t b;
+  std::memcpy(&b, &v, sizeof(b));
+  return (const void *)b;
+}
+
+// Everything a captured graph bakes in from the context and a list: buffer
+// addresses, sizes, cutoffs and schedule.  A graph is replayed only while its
+// key is unchanged (device addresses alone are not enough: a caching
+// allocator hands the same addresses to new tensors).
+std::vector<const void *> graph_key(const ters_ctx *c, const NList &nl) {
+  return {nl.conf.p, nl.conf_of.p, nl.count.p, nl.list.p, nl.order.p, nl.cell_of.p,
+          nl.cell_count.p, nl.cell_start.p, nl.scan_tmp.p, nl.xref.p, nl.maxcount.p,
+          (const void *)(intptr_t)nl.n, (const void *)(intptr_t)nl.cap,
+          (const void *)(intptr_t)nl.ncell, (const void *)(intptr_t)nl.nconf, bits(nl.rlist),
+          bits(nl.skin), c->kp64.p, c->kp32.p, c->filt2.p, (const void *)(intptr_t)c->ntypes,
+          (const void *)(intptr_t)c->cut_consistent, (const void *)(intptr_t)c->kmax,
+          c->partials.p, c->errw.p, c->flag.p, c->rebuilds.p, c->step.p, c->escratch.p};
+}
+
 // one force evaluation (forces zeroed unless accumulating); returns #blocks
 int run_forward(ters_ctx *c, const FwdArgs &a0, int precision, hipStream_t s) {
   FwdArgs a = a0;
@@ -290,10 +313,16 @@ ters_status ters_create(ters_ctx **out, int device, void *stream) {
   return TERS_OK;
 }
 
+static void plan_release_device(ters_plan *p);
+
 ters_status ters_destroy(ters_ctx *c) {
   if (!c) return TERS_ERR_INVALID_ARG;
   hipSetDevice(c->device);
   hipStreamSynchronize(c->stream);
+  // plans still alive lose their device resources and their context; a later
+  // ters_plan_destroy on them only frees the host record
+  for (ters_plan *p : c->plans) plan_release_device(p);
+  c->plans.clear();
   if (c->md_exec) hipGraphExecDestroy(c->md_exec);
   if (c->capture_stream) hipStreamDestroy(c->capture_stream);
   DevBuf *bufs[] = {&c->kp64, &c->kp32, &c->filt2, &c->mass, &c->partials, &c->errw, &c->flag,
@@ -593,29 +622,31 @@ ters_status ters_md_run(ters_ctx *c, int32_t n, double *x, double *v, double *f,
             "skin differs from the one the list was built with");
     const int nb = forward_blocks(n, c->A[precision] > 0 ? c->A[precision] : 64);
     c->partials.ensure(sizeof(double) * 8 * (size_t)std::max(nb, 1));
+    // one step: kick + drift + zero F + rebuild test | conditional rebuild |
+    // forces | energy (trace) | kick + clear the flag
     auto step = [&](hipStream_t s) {
       int32_t *flag = c->flag.as<int32_t>();
-      launch_fill_i32(flag, 0, 1, nullptr, s);
       launch_vv_first(n, x, v, f, type, c->mass.as<double>(), dt, c->nl, flag, s);
-      nlist_build(c->nl, x, flag, c->errw.as<uint32_t>(), s);
-      launch_count_rebuild(flag, c->rebuilds.as<int64_t>(), s);
+      nlist_build(c->nl, x, flag, c->errw.as<uint32_t>(), s, c->rebuilds.as<int64_t>());
       FwdArgs a = base_args(c, c->nl, precision, n, x, type);
-      a.flags = TERS_FORCES | TERS_ENERGY;
+      a.flags = TERS_FORCES | TERS_ENERGY | TERS_ACCUMULATE;  // F was zeroed by the kick
       a.forces = f;
       run_forward(c, a, precision, s);
-      if (trace) {
-        launch_reduce_partials(c->partials.as<double>(), nb, 8, c->escratch.as<double>(), nullptr, 0, s);
-        launch_store_trace(c->escratch.as<double>(), trace, c->step.as<int32_t>(), s);
-      }
-      launch_vv_second(n, v, f, type, c->mass.as<double>(), dt, s);
+      if (trace)
+        launch_reduce_partials(c->partials.as<double>(), nb, 8, c->escratch.as<double>(), nullptr,
+                               0, s, trace, c->step.as<int32_t>());
+      launch_vv_second(n, v, f, type, c->mass.as<double>(), dt, flag, s);
     };
     launch_fill_i32(c->step.as<int32_t>(), 0, 1, nullptr, c->stream);
+    launch_fill_i32(c->flag.as<int32_t>(), 0, 1, nullptr, c->stream);
     if (!use_graph) {
       for (int s = 0; s < nsteps; ++s) step(c->stream);
     } else if (nsteps > 0) {
-      std::vector<const void *> key = {x, v, f, type, trace, (const void *)(intptr_t)n,
-                                       (const void *)(intptr_t)precision, c->nl.list.p,
-                                       c->partials.p, (const void *)(intptr_t)c->A[precision]};
+      std::vector<const void *> key = graph_key(c, c->nl);
+      const void *extra[] = {x, v, f, type, trace, bits(dt), (const void *)(intptr_t)n,
+                             (const void *)(intptr_t)precision, c->mass.p,
+                             (const void *)(intptr_t)c->A[precision]};
+      key.insert(key.end(), std::begin(extra), std::end(extra));
       if (!c->md_exec || key != c->md_key) {
         if (c->md_exec) {
           TERS_HIP_TRY(hipGraphExecDestroy(c->md_exec));
@@ -739,9 +770,12 @@ ters_status ters_batch_plan(ters_ctx *c, int32_t nconf, const int32_t *natoms,
     return TERS_OK;
   });
   if (st != TERS_OK) {
+    p->ctx = c;
+    plan_release_device(p);
     delete p;
     return st;
   }
+  c->plans.push_back(p);
   *out = p;
   return TERS_OK;
 }
@@ -749,7 +783,7 @@ ters_status ters_batch_plan(ters_ctx *c, int32_t nconf, const int32_t *natoms,
 ters_status ters_batch_run(ters_plan *p, const double *x, const int32_t *type, double *e,
                            double *f, double *w, const double *e_bar, const double *f_bar,
                            double *xg, double *pg) {
-  if (!p || !p->ctx) return TERS_ERR_INVALID_ARG;
+  if (!p || !p->ctx) return TERS_ERR_INVALID_ARG;  // no plan, or its context is gone
   ters_ctx *c = p->ctx;
   return guard(c, [&]() {
     require(x && type, TERS_ERR_INVALID_ARG, "x and type required");
@@ -792,7 +826,10 @@ ters_status ters_batch_run(ters_plan *p, const double *x, const int32_t *type, d
       p->best_us = best;
       p->tuned = true;
     }
-    std::vector<const void *> key = {x, type, e, f, w, e_bar, f_bar, xg, pg};
+    std::vector<const void *> key = graph_key(c, nl);
+    const void *extra[] = {x, type, e, f, w, e_bar, f_bar, xg, pg, p->partials.p, p->errw.p,
+                           (const void *)(intptr_t)p->A, (const void *)(intptr_t)p->precision};
+    key.insert(key.end(), std::begin(extra), std::end(extra));
     if (!p->exec || key != p->key) {
       if (p->exec) {
         TERS_HIP_TRY(hipGraphExecDestroy(p->exec));
@@ -813,17 +850,26 @@ ters_status ters_batch_run(ters_plan *p, const double *x, const int32_t *type, d
   });
 }
 
-ters_status ters_plan_destroy(ters_plan *p) {
-  if (!p) return TERS_ERR_INVALID_ARG;
-  if (p->ctx) {
-    hipSetDevice(p->ctx->device);
-    hipStreamSynchronize(p->ctx->stream);
-  }
+static void plan_release_device(ters_plan *p) {
+  if (!p->ctx) return;
+  hipSetDevice(p->ctx->device);
+  hipStreamSynchronize(p->ctx->stream);
   if (p->exec) hipGraphExecDestroy(p->exec);
+  p->exec = nullptr;
   DevBuf *bufs[] = {&p->partials, &p->ebuf, &p->errw, &p->nl.conf, &p->nl.conf_of, &p->nl.count,
                     &p->nl.list, &p->nl.order, &p->nl.cell_of, &p->nl.cell_count,
                     &p->nl.cell_start, &p->nl.scan_tmp, &p->nl.xref, &p->nl.maxcount};
   for (DevBuf *b : bufs) b->release();
+  p->ctx = nullptr;
+}
+
+ters_status ters_plan_destroy(ters_plan *p) {
+  if (!p) return TERS_ERR_INVALID_ARG;
+  if (p->ctx) {
+    auto &v = p->ctx->plans;
+    v.erase(std::remove(v.begin(), v.end(), p), v.end());
+    plan_release_device(p);
+  }
   delete p;
   return TERS_OK;
 }

@@ -473,14 +473,16 @@ __global__ __launch_bounds__(BS) void k_force(FwdArgs a, int A) {
         bond<T, B, PG>(pp, zeta, b, db, dbb, dbn);
         const T fcij = s_fc[p], dfcij = s_dfc[p];
         const T vr = fr + b * fa;
-        const T V = fcij * vr;
+        // the energy itself is assembled in FP64 from the factors (the FP32
+        // path's large repulsive and attractive parts cancel at close contacts)
+        const AT V = widen(fcij) * (widen(fr) + widen(b) * widen(fa));
         const T dVdr = dfcij * vr + fcij * (-pp.lam1 * fr - pp.lam2 * b * fa);
         dzeta = B(0.5) * fcij * fa * db;
         const T hp = B(0.5) * dVdr;
         f0 = widen(-(hp * u[0]) - dzeta * gj[0]);
         f1 = widen(-(hp * u[1]) - dzeta * gj[1]);
         f2 = widen(-(hp * u[2]) - dzeta * gj[2]);
-        ev = val(widen(B(0.5) * V));
+        ev = 0.5 * val(V);
         if (!DUAL && straddle && a.partials) atomic_add(&a.partials[(int64_t)s_conf[at] * 8], ev);
         else eacc += ev;
         if (PG) {
@@ -653,8 +655,11 @@ __global__ __launch_bounds__(BS) void k_force(FwdArgs a, int A) {
   }
 }
 
+// Fixed-order sum of the per-workgroup partials.  With a trace, the energy is
+// also stored at trace[*step] and the device step counter advanced (keeps a
+// captured molecular-dynamics step replayable).
 __global__ void k_reduce_partials(const double *partials, int nblocks, int stride, double *energy,
-                                  double *virial, int accumulate) {
+                                  double *virial, int accumulate, double *trace, int32_t *step) {
   __shared__ double red[256];
   int k = blockIdx.x;  // 0 = energy, 1..6 virial
   double s = 0.0;
@@ -668,6 +673,10 @@ __global__ void k_reduce_partials(const double *partials, int nblocks, int strid
   if (threadIdx.x == 0) {
     double *dst = k == 0 ? energy : (virial ? virial + (k - 1) : nullptr);
     if (dst) *dst = accumulate ? *dst + red[0] : red[0];
+    if (k == 0 && trace) {
+      trace[*step] = red[0];
+      *step += 1;
+    }
   }
 }
 
@@ -714,9 +723,10 @@ void launch_adjoint(const FwdArgs &a, int precision, int A, hipStream_t s) {
 }
 
 void launch_reduce_partials(const double *partials, int nblocks, int stride, double *energy,
-                            double *virial, int accumulate, hipStream_t s) {
+                            double *virial, int accumulate, hipStream_t s, double *trace,
+                            int32_t *step) {
   k_reduce_partials<<<virial ? 7 : 1, 256, 0, s>>>(partials, nblocks, stride, energy, virial,
-                                                   accumulate);
+                                                   accumulate, trace, step);
 }
 
 }  // namespace ters

@@ -4,6 +4,8 @@
 #include "ters_device.h"
 #include "ters_internal.h"
 
+#include <algorithm>
+
 namespace ters {
 
 namespace {
@@ -11,10 +13,11 @@ namespace {
 constexpr double kFtm2v = 9648.533212331;  // eV/(Angstrom amu) -> Angstrom/ps^2
 constexpr int kBS = 256;
 
-// v += dt/2 F/m; x += dt v; flag = 1 if any atom moved more than skin/2 since
-// the last list build (FP64, minimum image)
+// v += dt/2 F/m; x += dt v; F = 0 (the force kernel accumulates into it);
+// flag = 1 if any atom moved more than skin/2 since the last list build (FP64,
+// minimum image)
 __global__ void k_vv_first(int n, double *__restrict__ x, double *__restrict__ v,
-                           const double *__restrict__ f, const int32_t *__restrict__ type,
+                           double *__restrict__ f, const int32_t *__restrict__ type,
                            const double *__restrict__ mass, double dt,
                            const double *__restrict__ xref, const ConfDesc *__restrict__ conf,
                            double lim2, int32_t *flag) {
@@ -30,6 +33,7 @@ __global__ void k_vv_first(int n, double *__restrict__ x, double *__restrict__ v
       double xx = x[3 * i + a] + dt * vv;
       v[3 * i + a] = vv;
       x[3 * i + a] = xx;
+      f[3 * i + a] = 0.0;
       double d = xx - xref[3 * i + a];
       d -= c.box[a] * rint(d * c.inv_box[a]);
       r2 += d * d;
@@ -39,11 +43,12 @@ __global__ void k_vv_first(int n, double *__restrict__ x, double *__restrict__ v
   if (__ballot(over) != 0ull && lane_id() == 0) *flag = 1;
 }
 
-// v += dt/2 F/m
+// v += dt/2 F/m; the rebuild flag is cleared for the next step
 __global__ void k_vv_second(int n, double *__restrict__ v, const double *__restrict__ f,
                             const int32_t *__restrict__ type, const double *__restrict__ mass,
-                            double dt) {
+                            double dt, int32_t *flag) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0 && flag) *flag = 0;
   if (i >= n) return;
   const double s = 0.5 * dt * kFtm2v / mass[type[i]];
   v[3 * i + 0] += s * f[3 * i + 0];
@@ -51,20 +56,10 @@ __global__ void k_vv_second(int n, double *__restrict__ v, const double *__restr
   v[3 * i + 2] += s * f[3 * i + 2];
 }
 
-__global__ void k_count_rebuild(const int32_t *flag, int64_t *counter) {
-  if (*flag) *counter += 1;
-}
-
-// trace[*step] = *e; ++*step   (a device-side step counter keeps a captured
-// step graph replayable)
-__global__ void k_store_trace(const double *e, double *trace, int32_t *step) {
-  trace[*step] = *e;
-  *step += 1;
-}
 
 }  // namespace
 
-void launch_vv_first(int n, double *x, double *v, const double *f, const int32_t *type,
+void launch_vv_first(int n, double *x, double *v, double *f, const int32_t *type,
                      const double *mass, double dt, const NList &nl, int32_t *flag,
                      hipStream_t s) {
   if (n <= 0) return;
@@ -74,17 +69,8 @@ void launch_vv_first(int n, double *x, double *v, const double *f, const int32_t
 }
 
 void launch_vv_second(int n, double *v, const double *f, const int32_t *type, const double *mass,
-                      double dt, hipStream_t s) {
-  if (n <= 0) return;
-  k_vv_second<<<(n + kBS - 1) / kBS, kBS, 0, s>>>(n, v, f, type, mass, dt);
-}
-
-void launch_count_rebuild(const int32_t *flag, int64_t *counter, hipStream_t s) {
-  k_count_rebuild<<<1, 1, 0, s>>>(flag, counter);
-}
-
-void launch_store_trace(const double *e, double *trace, int32_t *step, hipStream_t s) {
-  k_store_trace<<<1, 1, 0, s>>>(e, trace, step);
+                      double dt, int32_t *flag, hipStream_t s) {
+  k_vv_second<<<(std::max(n, 1) + kBS - 1) / kBS, kBS, 0, s>>>(n, v, f, type, mass, dt, flag);
 }
 
 }  // namespace ters

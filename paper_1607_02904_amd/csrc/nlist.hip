@@ -33,6 +33,14 @@ __global__ void k_fill_i32(int32_t *p, int32_t v, int64_t n, const int32_t *cond
     p[i] = v;
 }
 
+// zero the cell counts and the longest-row register in one launch
+__global__ void k_zero_cells(int32_t *cell_count, int64_t m, int32_t *maxcount, const int32_t *cond) {
+  if (skip(cond)) return;
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i == 0) *maxcount = 0;
+  for (; i < m; i += (int64_t)gridDim.x * blockDim.x) cell_count[i] = 0;
+}
+
 __global__ void k_fill_f64(double *p, double v, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
@@ -135,10 +143,38 @@ __global__ __launch_bounds__(kBS) void k_scan_tile_sums(int32_t *tile_sum, int n
   }
 }
 
-__global__ void k_scan_add(int32_t *out, int64_t m, const int32_t *tile_sum, const int32_t *cond) {
+// adds the tile offsets and clears the counts (they become the placement cursors)
+__global__ void k_scan_add(int32_t *out, int64_t m, const int32_t *tile_sum, int32_t *counts,
+                           const int32_t *cond) {
   if (skip(cond)) return;
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i < m) out[i] += tile_sum[i / kScanTile];
+  if (i < m) {
+    out[i] += tile_sum[i / kScanTile];
+    counts[i] = 0;
+  }
+}
+
+// whole exclusive scan in one workgroup (used when the cell count is moderate):
+// contiguous chunks per thread, one block scan of the chunk sums; the counts
+// are cleared on the way (they become the placement cursors)
+constexpr int kScan1Max = 8192;  // above this the three-kernel parallel scan wins
+__global__ __launch_bounds__(kBS) void k_scan_single(int32_t *__restrict__ counts,
+                                                     int32_t *__restrict__ out, int64_t m,
+                                                     const int32_t *cond) {
+  if (skip(cond)) return;
+  const int64_t per = (m + kBS - 1) / kBS;
+  const int64_t b = threadIdx.x * per;
+  const int64_t e = b + per < m ? b + per : m;
+  int s = 0;
+  for (int64_t i = b; i < e; ++i) s += counts[i];
+  int tot;
+  int off = block_excl_scan(s, &tot);
+  for (int64_t i = b; i < e; ++i) {
+    int c = counts[i];
+    out[i] = off;
+    off += c;
+    counts[i] = 0;
+  }
 }
 
 __global__ void k_place(int n, const double *__restrict__ x, const int32_t *__restrict__ cell_of,
@@ -182,9 +218,11 @@ __global__ __launch_bounds__(kBS) void k_build(int n, const double *__restrict__
                                                double rl2, int cap, int32_t *__restrict__ count,
                                                int32_t *__restrict__ list,
                                                int32_t *__restrict__ maxcount,
-                                               const int32_t *cond, uint32_t *err) {
+                                               const int32_t *cond, uint32_t *err,
+                                               int64_t *rebuilds) {
   if (skip(cond)) return;
   int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t == 0 && rebuilds) *rebuilds += 1;
   int cnt = 0;
   if (t < n) {
     int i = order[t];
@@ -279,24 +317,31 @@ void launch_fill_f64(double *p, double v, int64_t n, hipStream_t s) {
 // Build the list for the configuration set described by nl (geometry already
 // filled in by the caller).  cond: device flag (may be null); when non-null
 // and zero every kernel returns immediately.
-void nlist_build(NList &nl, const double *x, const int32_t *cond, uint32_t *err, hipStream_t s) {
+void nlist_build(NList &nl, const double *x, const int32_t *cond, uint32_t *err, hipStream_t s,
+                 int64_t *rebuild_counter) {
   const int n = nl.n;
   const int64_t ncell = nl.ncell;
   int32_t *cell_count = nl.cell_count.as<int32_t>();
   int32_t *cell_start = nl.cell_start.as<int32_t>();
   const ConfDesc *conf = nl.conf.as<ConfDesc>();
   const int32_t *conf_of = nl.nconf > 1 ? nl.conf_of.as<int32_t>() : nullptr;
-  launch_fill_i32(cell_count, 0, ncell + 1, cond, s);
-  launch_fill_i32(nl.maxcount.as<int32_t>(), 0, 1, cond, s);
+  const int64_t m = ncell + 1;
+  {
+    int g = grid_for(m, kBS);
+    k_zero_cells<<<g > 4096 ? 4096 : g, kBS, 0, s>>>(cell_count, m, nl.maxcount.as<int32_t>(), cond);
+  }
   if (n > 0)
     k_bin<<<grid_for(n, kBS), kBS, 0, s>>>(n, x, conf, conf_of, nl.cell_of.as<int32_t>(),
                                            cell_count, cond, err);
-  const int64_t m = ncell + 1;
-  const int ntile = grid_for(m, kScanTile);
-  k_scan_tiles<<<ntile, kBS, 0, s>>>(cell_count, cell_start, m, nl.scan_tmp.as<int32_t>(), cond);
-  k_scan_tile_sums<<<1, kBS, 0, s>>>(nl.scan_tmp.as<int32_t>(), ntile, cond);
-  k_scan_add<<<grid_for(m, kBS), kBS, 0, s>>>(cell_start, m, nl.scan_tmp.as<int32_t>(), cond);
-  launch_fill_i32(cell_count, 0, ncell + 1, cond, s);
+  if (m <= kScan1Max) {
+    k_scan_single<<<1, kBS, 0, s>>>(cell_count, cell_start, m, cond);
+  } else {
+    const int ntile = grid_for(m, kScanTile);
+    k_scan_tiles<<<ntile, kBS, 0, s>>>(cell_count, cell_start, m, nl.scan_tmp.as<int32_t>(), cond);
+    k_scan_tile_sums<<<1, kBS, 0, s>>>(nl.scan_tmp.as<int32_t>(), ntile, cond);
+    k_scan_add<<<grid_for(m, kBS), kBS, 0, s>>>(cell_start, m, nl.scan_tmp.as<int32_t>(),
+                                                cell_count, cond);
+  }
   if (n > 0) {
     k_place<<<grid_for(n, kBS), kBS, 0, s>>>(n, x, nl.cell_of.as<int32_t>(), cell_start,
                                              cell_count, nl.order.as<int32_t>(),
@@ -307,7 +352,7 @@ void nlist_build(NList &nl, const double *x, const int32_t *cond, uint32_t *err,
                                              nl.cell_of.as<int32_t>(), cell_start,
                                              nl.rlist * nl.rlist, nl.cap, nl.count.as<int32_t>(),
                                              nl.list.as<int32_t>(), nl.maxcount.as<int32_t>(),
-                                             cond, err);
+                                             cond, err, rebuild_counter);
   }
 }
 

@@ -116,19 +116,19 @@ struct FwdArgs {
 // launchers (implemented in the .hip files)
 void launch_fill_i32(int32_t *p, int32_t v, int64_t n, const int32_t *cond, hipStream_t s);
 void launch_fill_f64(double *p, double v, int64_t n, hipStream_t s);
-void nlist_build(NList &nl, const double *x, const int32_t *cond, uint32_t *err, hipStream_t s);
+void nlist_build(NList &nl, const double *x, const int32_t *cond, uint32_t *err, hipStream_t s,
+                 int64_t *rebuild_counter = nullptr);
 void nlist_check(const NList &nl, const double *x, int32_t *flag, hipStream_t s);
 void launch_forward(const FwdArgs &a, int precision, int atoms_per_block, int nblocks_out[1],
                     hipStream_t s);
 void launch_adjoint(const FwdArgs &a, int precision, int atoms_per_block, hipStream_t s);
 int forward_blocks(int n, int atoms_per_block);
 void launch_reduce_partials(const double *partials, int nblocks, int stride, double *energy,
-                            double *virial, int accumulate, hipStream_t s);
-void launch_vv_first(int n, double *x, double *v, const double *f, const int32_t *type,
+                            double *virial, int accumulate, hipStream_t s,
+                            double *trace = nullptr, int32_t *step = nullptr);
+void launch_vv_first(int n, double *x, double *v, double *f, const int32_t *type,
                      const double *mass, double dt, const NList &nl, int32_t *flag, hipStream_t s);
 void launch_vv_second(int n, double *v, const double *f, const int32_t *type, const double *mass,
-                      double dt, hipStream_t s);
-void launch_count_rebuild(const int32_t *flag, int64_t *counter, hipStream_t s);
-void launch_store_trace(const double *e, double *trace, int32_t *step, hipStream_t s);
+                      double dt, int32_t *flag, hipStream_t s);
 
 }  // namespace ters

@@ -9,6 +9,7 @@ int32 [n] on the GPU, box: three side lengths (host sequence).
 """
 import ctypes
 import os
+import sys
 
 import numpy as np
 import torch
@@ -34,6 +35,7 @@ EXPORTS = ("ters_create", "ters_destroy", "ters_set_stream", "ters_sync", "ters_
            "ters_table_element", "ters_version")
 
 _lib = None
+_finalizing = sys.is_finalizing  # kept: module globals are cleared at shutdown
 
 
 class TersoffError(RuntimeError):
@@ -143,6 +145,9 @@ class Tersoff:
             self._h = None
 
     def __del__(self):
+        # during interpreter shutdown the HIP runtime may already be gone
+        if _finalizing is None or _finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -307,6 +312,8 @@ class BatchPlan:
             self._h = None
 
     def __del__(self):
+        if _finalizing is None or _finalizing():
+            return
         try:
             self.close()
         except Exception:

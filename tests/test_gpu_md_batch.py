@@ -61,16 +61,36 @@ def test_md_graph_equals_eager_and_rebuilds_happen(si_model):
     assert np.max(np.abs(a[0] - c[0])) < 1e-10
 
 
-def test_md_energy_conservation(si_model):
-    x, t, box = inputs.si_bulk(ncell=6, seed=23)
+def _total_energy_deviation(model, x, t, box, dt, total_time, chunk):
+    """Largest |E_kin + E_pot - E_0| per atom along a trajectory, sampled
+    every `chunk` steps (list rebuilt on the device as needed)."""
     n = len(t)
-    xg, vg, fg, tr = _md_gpu(si_model, x, t, box, 200, 0.5)
-    ke = 0.5 * MASS_SI * np.sum(vg ** 2) / O.FTM2V
-    e0 = tr[0]  # not the initial state: use the trace and the final KE
-    # initial total energy: potential at t=0 with v = 0
-    e_init = O.compute(x, t, box, params.single(params.SI_B))[0]
-    drift = abs((tr[-1] + ke) - e_init) / n
-    assert drift < 1e-4, drift
+    xd = torch.as_tensor(x, device="cuda").clone()
+    td = torch.as_tensor(t, device="cuda")
+    v = torch.zeros_like(xd)
+    f = torch.empty_like(xd)
+    model.build_nlist(xd, td, box, 0.5)
+    o = model.compute(xd, td, box, 0, virial=False, out={"forces": f})
+    e0 = float(o["energy"].item())
+    dev = 0.0
+    for _ in range(int(round(total_time / dt / chunk))):
+        tr = model.md_run(xd, v, f, td, box, dt, chunk, 0.5, 0)
+        torch.cuda.synchronize()
+        ke = 0.5 * MASS_SI * float((v ** 2).sum().item()) / O.FTM2V
+        dev = max(dev, abs(float(tr[chunk - 1].item()) + ke - e0) / n)
+    model.sync()
+    return dev
+
+
+def test_md_energy_conservation(si_model):
+    """Velocity Verlet conserves the total energy up to an O(dt^2)
+    oscillation: halving dt divides the largest deviation by about four, and
+    the deviation stays small."""
+    x, t, box = inputs.si_bulk(ncell=6, seed=23)
+    d1 = _total_energy_deviation(si_model, x, t, box, 0.001, 0.2, 10)
+    d2 = _total_energy_deviation(si_model, x, t, box, 0.0005, 0.2, 20)
+    assert d1 < 1e-3
+    assert 3.0 < d1 / d2 < 5.5, (d1, d2)
 
 
 def test_md_mixed_runs_and_tracks_fp64(si_model):
@@ -119,10 +139,12 @@ def test_batch_forward_matches_oracle(orc, batch_setup, precision):
     model.sync()
     e, f, w = e.cpu().numpy(), f.cpu().numpy(), w.cpu().numpy()
     off = plan.offsets
-    tol_e, tol_f = (1e-12, 1e-12) if precision == 0 else (1e-6, 1e-5)
+    tol_e, tol_f = (1e-12, 1e-12) if precision == 0 else (1e-7, 1e-5)
     for c, (xc, tc, bc) in enumerate(confs):
-        er, fr, wr, _ = orc.compute(xc, tc, bc, params.sic())
-        assert abs(e[c] - er) <= tol_e * abs(er), (c, e[c], er)
+        er, fr, wr, ear = orc.compute(xc, tc, bc, params.sic())
+        # FP64: relative to |E|; mixed: relative to the per-atom scale sum |e_i|
+        scale = abs(er) if precision == 0 else np.abs(ear).sum()
+        assert abs(e[c] - er) <= tol_e * scale, (c, e[c], er)
         fc = f[off[c]:off[c + 1]]
         assert np.linalg.norm(fc - fr) <= tol_f * np.linalg.norm(fr), c
         assert np.linalg.norm(w[c] - wr) <= tol_f * np.linalg.norm(wr), c
