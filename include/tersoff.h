@@ -188,17 +188,31 @@ ters_status ters_batch_run(ters_plan *plan, const double *x_cat, const int32_t *
  * plan then fails ters_batch_run with TERS_ERR_INVALID_ARG, and
  * ters_plan_destroy still frees it. */
 ters_status ters_plan_destroy(ters_plan *plan);
-/* Schedule chosen by the plan's autotuner: out[0] = atoms per workgroup,
- * out[1] = workgroup size, out[2] = measured microseconds of the best. */
+/* Schedule chosen by the plan's autotuner: out[0] = atoms per workgroup
+ * (kernel 1) or per wavefront (kernel 2), out[1] = kernel (see
+ * ters_set_schedule), out[2] = measured microseconds of the best. */
 ters_status ters_plan_schedule(const ters_plan *plan, double *out3);
 
 /* ---- schedule control ------------------------------------------------------
- * Atoms per workgroup of the force kernel (0 = automatic) and the number of
- * stored dzeta/dx_k per pair before the kernel falls back to recomputing them
- * (the paper's k_max, Section IV-A; 0 = automatic, i.e. store all). */
-ters_status ters_set_schedule(ters_ctx *ctx, int32_t atoms_per_block, int32_t kmax);
-/* Time the candidate schedules on the current list and keep the fastest
- * (synchronises).  out_us (host, may be NULL) gets the best time. */
+ * kernel: 1 = workgroup schedule (a workgroup of 256 lanes stages a run of
+ * atoms' pairs in LDS and keeps dzeta/dx_k of up to k_max neighbours per pair,
+ * the paper's Algorithm 3), 2 = wavefront schedule (each wavefront works alone,
+ * pair data in registers exchanged by cross-lane permutes, the two K loops of
+ * Algorithm 2), 0 = default (1).  atoms: atoms per workgroup (kernel 1,
+ * <= 64) or per wavefront (kernel 2, <= 32); 0 = default.  kmax (kernel 1):
+ * stored dzeta/dx_k per pair before falling back to recomputing them (the
+ * paper's k_max, Section IV-A); 0 = store all that fit.  Applies to both
+ * precisions. */
+ters_status ters_set_schedule(ters_ctx *ctx, int32_t kernel, int32_t atoms, int32_t kmax);
+/* How forces reach their atoms: 1 (default) = owner gather: the force kernel
+ * stores, for every list slot (i, j), the force that atom i's terms exert on
+ * j, and a second pass sums each atom's incoming slots in a fixed order
+ * through a reverse-slot map built with the list (no atomics; results are
+ * bitwise reproducible); 0 = scatter with FP64 atomic adds. */
+ters_status ters_set_force_mode(ters_ctx *ctx, int32_t mode);
+/* Time the candidate schedules (both kernels, several atom counts) on the
+ * current list and keep the fastest for this precision (synchronises).
+ * out_us (host, may be NULL) gets the best time. */
 ters_status ters_autotune(ters_ctx *ctx, int32_t n, const double *x, const int32_t *type,
                           const double *box, int precision, double *out_us);
 

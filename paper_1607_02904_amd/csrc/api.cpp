@@ -31,8 +31,11 @@ struct ters_ctx {
   DevBuf kp64, kp32, filt2, mass;
   NList nl;
   DevBuf partials, errw, flag, rebuilds, step, escratch;
-  int A[2] = {0, 0};  // atoms per workgroup per precision (0 = kernel default)
+  int A[2] = {0, 0};     // atoms per workgroup / wavefront per precision (0 = default)
+  int kern[2] = {1, 1};  // force kernel per precision: 1 workgroup, 2 wavefront schedule
   int kmax = 1 << 20;
+  int gather = 1;        // 1: owner-gather forces (deterministic), 0: FP64 atomic scatter
+  DevBuf fslot, fown;    // owner-gather buffers
   // molecular-dynamics step graph
   hipGraphExec_t md_exec = nullptr;
   std::vector<const void *> md_key;
@@ -46,8 +49,8 @@ struct ters_plan {
   uint32_t flags = 0;
   std::vector<int32_t> natoms, off;
   NList nl;
-  DevBuf partials, ebuf, errw;
-  int A = 0;
+  DevBuf partials, ebuf, errw, fslot, fown;
+  int A = 0, kern = 1, gather = 1;
   double best_us = 0.0;
   bool tuned = false;
   hipGraphExec_t exec = nullptr;
@@ -193,6 +196,7 @@ void nl_setup(NList &nl, int nconf, const int32_t *natoms, const double *boxes, 
   nl.scan_tmp.ensure(sizeof(int32_t) * ((cells + 1) / 1024 + 2));
   nl.xref.ensure(sizeof(double) * 3 * nn);
   nl.maxcount.ensure(sizeof(int32_t));
+  nl.rev.ensure(sizeof(int32_t) * nn * nl.cap);
 }
 
 // Build with capacity growth (synchronises).
@@ -204,6 +208,7 @@ void nl_build_sync(ters_ctx *c, NList &nl, const double *x, DevBuf &errw) {
     TERS_HIP_TRY(hipMemcpyAsync(&mx, nl.maxcount.p, sizeof(mx), hipMemcpyDeviceToHost, c->stream));
     uint32_t e = read_err(c, errw);
     if (e & kErrNotFinite) fail(TERS_ERR_NOT_FINITE, "non-finite position");
+    if ((e & kErrListAsymmetric) && mx <= nl.cap) fail(TERS_ERR_HIP, "neighbour list not symmetric");
     if (mx <= nl.cap) {
       nl.valid = true;
       return;
@@ -212,6 +217,7 @@ void nl_build_sync(ters_ctx *c, NList &nl, const double *x, DevBuf &errw) {
     if (cap > 64) fail(TERS_ERR_NLIST_OVERFLOW, "an atom has more than 64 list neighbours");
     nl.cap = cap;
     nl.list.ensure(sizeof(int32_t) * (size_t)std::max(nl.n, 1) * cap);
+    nl.rev.ensure(sizeof(int32_t) * (size_t)std::max(nl.n, 1) * cap);
   }
   fail(TERS_ERR_NLIST_OVERFLOW, "neighbour list did not converge");
 }
@@ -263,20 +269,59 @@ std::vector<const void *> graph_key(const ters_ctx *c, const NList &nl) {
           (const void *)(intptr_t)nl.ncell, (const void *)(intptr_t)nl.nconf, bits(nl.rlist),
           bits(nl.skin), c->kp64.p, c->kp32.p, c->filt2.p, (const void *)(intptr_t)c->ntypes,
           (const void *)(intptr_t)c->cut_consistent, (const void *)(intptr_t)c->kmax,
-          c->partials.p, c->errw.p, c->flag.p, c->rebuilds.p, c->step.p, c->escratch.p};
+          c->partials.p, c->errw.p, c->flag.p, c->rebuilds.p, c->step.p, c->escratch.p,
+          nl.rev.p, c->fslot.p, c->fown.p, (const void *)(intptr_t)c->gather};
+}
+
+// Force-kernel dispatch: workgroup schedule (kern 1, atoms per workgroup) or
+// wavefront schedule (kern 2, atoms per wavefront).  Returns the number of
+// per-workgroup partial records written (single-system mode).
+int kernel_blocks(int kern, int n, int A) {
+  return kern == 2 ? wave_blocks(n, A) : forward_blocks(n, (A > 0 && A <= 64) ? A : 64);
+}
+void launch_fwd(int kern, const FwdArgs &a, int precision, int A, hipStream_t s) {
+  if (kern == 2) {
+    launch_forward_wave(a, precision, A, s);
+  } else {
+    int nbo[1];
+    launch_forward(a, precision, A, nbo, s);
+  }
+}
+void launch_adj(int kern, const FwdArgs &a, int precision, int A, hipStream_t s) {
+  if (kern == 2) launch_adjoint_wave(a, precision, A, s);
+  else launch_adjoint(a, precision, 0, s);
+}
+
+int ctx_blocks(const ters_ctx *c, int precision, int n) {
+  return kernel_blocks(c->kern[precision], n, c->A[precision]);
+}
+
+// owner-gather buffers for n atoms with the list's capacity
+void ensure_gather(DevBuf &fslot, DevBuf &fown, const NList &nl) {
+  const size_t n = (size_t)std::max(nl.n, 1);
+  fslot.ensure(sizeof(double) * 3 * n * nl.cap);
+  fown.ensure(sizeof(double) * 3 * n);
 }
 
 // one force evaluation (forces zeroed unless accumulating); returns #blocks
 int run_forward(ters_ctx *c, const FwdArgs &a0, int precision, hipStream_t s) {
   FwdArgs a = a0;
-  int nb = forward_blocks(a.n, c->A[precision] > 0 ? c->A[precision] : 64);
+  const int nb = ctx_blocks(c, precision, a.n);
   c->partials.ensure(sizeof(double) * 8 * (size_t)std::max(nb, 1));
   a.partials = c->partials.as<double>();
   a.err = c->errw.as<uint32_t>();
-  if (a.forces && !(a.flags & TERS_ACCUMULATE)) launch_fill_f64(a.forces, 0.0, 3 * (int64_t)a.n, s);
-  int nbo[1] = {0};
-  launch_forward(a, precision, c->A[precision], nbo, s);
-  return nbo[0];
+  const bool gather = c->gather && a.forces;
+  if (gather) {
+    ensure_gather(c->fslot, c->fown, c->nl);
+    a.fslot = c->fslot.as<double>();
+    a.fown = c->fown.as<double>();
+  } else if (a.forces && !(a.flags & TERS_ACCUMULATE)) {
+    launch_fill_f64(a.forces, 0.0, 3 * (int64_t)a.n, s);
+  }
+  launch_fwd(c->kern[precision], a, precision, c->A[precision], s);
+  if (gather)
+    launch_gather(c->nl, a.fslot, a.fown, a.forces, (a.flags & TERS_ACCUMULATE) ? 1 : 0, s);
+  return nb;
 }
 
 }  // namespace
@@ -326,9 +371,10 @@ ters_status ters_destroy(ters_ctx *c) {
   if (c->md_exec) hipGraphExecDestroy(c->md_exec);
   if (c->capture_stream) hipStreamDestroy(c->capture_stream);
   DevBuf *bufs[] = {&c->kp64, &c->kp32, &c->filt2, &c->mass, &c->partials, &c->errw, &c->flag,
-                    &c->rebuilds, &c->step, &c->escratch, &c->nl.conf, &c->nl.conf_of,
-                    &c->nl.count, &c->nl.list, &c->nl.order, &c->nl.cell_of, &c->nl.cell_count,
-                    &c->nl.cell_start, &c->nl.scan_tmp, &c->nl.xref, &c->nl.maxcount};
+                    &c->rebuilds, &c->step, &c->escratch, &c->fslot, &c->fown, &c->nl.conf,
+                    &c->nl.conf_of, &c->nl.count, &c->nl.list, &c->nl.order, &c->nl.cell_of,
+                    &c->nl.cell_count, &c->nl.cell_start, &c->nl.scan_tmp, &c->nl.xref,
+                    &c->nl.maxcount, &c->nl.rev};
   for (DevBuf *b : bufs) b->release();
   delete c;
   return TERS_OK;
@@ -513,18 +559,34 @@ ters_status ters_backward(ters_ctx *c, int32_t n, const double *x, const int32_t
     a.err = c->errw.as<uint32_t>();
     a.kmax = 0;
     const int nt = c->ntypes;
-    launch_fill_f64(x_grad, 0.0, 3 * (int64_t)n, c->stream);
     launch_fill_f64(param_grad, 0.0, (int64_t)nt * nt * nt * kNField, c->stream);
-    launch_adjoint(a, precision, 0, c->stream);
+    if (c->gather) {
+      ensure_gather(c->fslot, c->fown, c->nl);
+      a.fslot = c->fslot.as<double>();
+      a.fown = c->fown.as<double>();
+    } else {
+      launch_fill_f64(x_grad, 0.0, 3 * (int64_t)n, c->stream);
+    }
+    launch_adj(c->kern[precision], a, precision, c->A[precision], c->stream);
+    if (c->gather) launch_gather(c->nl, a.fslot, a.fown, x_grad, 0, c->stream);
     return TERS_OK;
   });
 }
 
-ters_status ters_set_schedule(ters_ctx *c, int32_t apb, int32_t kmax) {
+ters_status ters_set_schedule(ters_ctx *c, int32_t kernel, int32_t atoms, int32_t kmax) {
   if (!c) return TERS_ERR_INVALID_ARG;
-  if (apb < 0 || apb > 64 || kmax < 0) return TERS_ERR_INVALID_ARG;
-  c->A[0] = c->A[1] = apb;
+  if (kernel < 0 || kernel > 2 || kmax < 0) return TERS_ERR_INVALID_ARG;
+  if (atoms < 0 || atoms > (kernel == 2 ? 32 : 64)) return TERS_ERR_INVALID_ARG;
+  const int k = kernel == 0 ? 1 : kernel;
+  c->kern[0] = c->kern[1] = k;
+  c->A[0] = c->A[1] = atoms;
   c->kmax = kmax == 0 ? (1 << 20) : kmax;
+  return TERS_OK;
+}
+
+ters_status ters_set_force_mode(ters_ctx *c, int32_t mode) {
+  if (!c || mode < 0 || mode > 1) return TERS_ERR_INVALID_ARG;
+  c->gather = mode;
   return TERS_OK;
 }
 
@@ -539,12 +601,15 @@ ters_status ters_autotune(ters_ctx *c, int32_t n, const double *x, const int32_t
     hipEvent_t e0, e1;
     TERS_HIP_TRY(hipEventCreate(&e0));
     TERS_HIP_TRY(hipEventCreate(&e1));
-    const int cands[] = {16, 24, 32, 40, 48, 56, 64};
+    struct Cand { int kern, A; };
+    const Cand cands[] = {{1, 16}, {1, 32}, {1, 48}, {1, 64}, {2, 8}, {2, 12}, {2, 16},
+                          {2, 20}, {2, 24}, {2, 32}};
     double best = 1e300;
-    int bestA = 64;
-    const int save = c->A[precision];
-    for (int A : cands) {
+    int bestA = 64, bestK = 1;
+    for (const Cand &cd : cands) {
+      const int A = cd.A;
       c->A[precision] = A;
+      c->kern[precision] = cd.kern;
       FwdArgs a = base_args(c, c->nl, precision, n, x, type);
       a.flags = TERS_FORCES | TERS_ENERGY | TERS_VIRIAL;
       a.forces = f.as<double>();
@@ -560,10 +625,11 @@ ters_status ters_autotune(ters_ctx *c, int32_t n, const double *x, const int32_t
       if (us < best) {
         best = us;
         bestA = A;
+        bestK = cd.kern;
       }
     }
-    (void)save;
     c->A[precision] = bestA;
+    c->kern[precision] = bestK;
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     f.release();
@@ -584,17 +650,22 @@ ters_status ters_profile_forward(ters_ctx *c, int32_t n, const double *x, const 
     FwdArgs a = base_args(c, c->nl, precision, n, x, type);
     a.flags = TERS_FORCES | TERS_ENERGY | TERS_VIRIAL | TERS_ACCUMULATE;
     a.forces = f.as<double>();
-    const int nb = forward_blocks(n, c->A[precision] > 0 ? c->A[precision] : 64);
+    if (c->gather) {
+      ensure_gather(c->fslot, c->fown, c->nl);
+      a.fslot = c->fslot.as<double>();
+      a.fown = c->fown.as<double>();
+    }
+    const int nb = ctx_blocks(c, precision, n);
     c->partials.ensure(sizeof(double) * 8 * (size_t)std::max(nb, 1));
     a.partials = c->partials.as<double>();
     a.err = c->errw.as<uint32_t>();
     hipEvent_t e0, e1;
     TERS_HIP_TRY(hipEventCreate(&e0));
     TERS_HIP_TRY(hipEventCreate(&e1));
-    int nbo[1];
-    launch_forward(a, precision, c->A[precision], nbo, c->stream);  // warm-up
+    const int kern = c->kern[precision], A = c->A[precision];
+    launch_fwd(kern, a, precision, A, c->stream);  // warm-up
     TERS_HIP_TRY(hipEventRecord(e0, c->stream));
-    for (int r = 0; r < reps; ++r) launch_forward(a, precision, c->A[precision], nbo, c->stream);
+    for (int r = 0; r < reps; ++r) launch_fwd(kern, a, precision, A, c->stream);
     TERS_HIP_TRY(hipEventRecord(e1, c->stream));
     TERS_HIP_TRY(hipEventSynchronize(e1));
     float ms = 0.f;
@@ -620,8 +691,9 @@ ters_status ters_md_run(ters_ctx *c, int32_t n, double *x, double *v, double *f,
     check_ready(c, c->nl, n, box);
     require(std::fabs(skin - c->nl.skin) < 1e-12, TERS_ERR_INVALID_ARG,
             "skin differs from the one the list was built with");
-    const int nb = forward_blocks(n, c->A[precision] > 0 ? c->A[precision] : 64);
+    const int nb = ctx_blocks(c, precision, n);
     c->partials.ensure(sizeof(double) * 8 * (size_t)std::max(nb, 1));
+    if (c->gather) ensure_gather(c->fslot, c->fown, c->nl);  // no allocation inside a capture
     // one step: kick + drift + zero F + rebuild test | conditional rebuild |
     // forces | energy (trace) | kick + clear the flag
     auto step = [&](hipStream_t s) {
@@ -645,7 +717,8 @@ ters_status ters_md_run(ters_ctx *c, int32_t n, double *x, double *v, double *f,
       std::vector<const void *> key = graph_key(c, c->nl);
       const void *extra[] = {x, v, f, type, trace, bits(dt), (const void *)(intptr_t)n,
                              (const void *)(intptr_t)precision, c->mass.p,
-                             (const void *)(intptr_t)c->A[precision]};
+                             (const void *)(intptr_t)c->A[precision],
+                             (const void *)(intptr_t)c->kern[precision]};
       key.insert(key.end(), std::begin(extra), std::end(extra));
       if (!c->md_exec || key != c->md_key) {
         if (c->md_exec) {
@@ -703,9 +776,14 @@ void batch_enqueue(ters_plan *p, const double *x, const int32_t *type, double *e
   a.partials = p->partials.as<double>();
   a.err = p->errw.as<uint32_t>();
   launch_fill_f64(p->partials.as<double>(), 0.0, 8 * (int64_t)p->nconf, s);
-  if (f) launch_fill_f64(f, 0.0, 3 * (int64_t)p->N, s);
-  int nbo[1];
-  launch_forward(a, p->precision, p->A, nbo, s);
+  if (f && p->gather) {
+    a.fslot = p->fslot.as<double>();
+    a.fown = p->fown.as<double>();
+  } else if (f) {
+    launch_fill_f64(f, 0.0, 3 * (int64_t)p->N, s);
+  }
+  launch_fwd(p->kern, a, p->precision, p->A, s);
+  if (f && p->gather) launch_gather(nl, a.fslot, a.fown, f, 0, s);
   if (e || w)
     k_split_partials<<<(p->nconf + 255) / 256, 256, 0, s>>>(p->partials.as<double>(), p->nconf, e, w);
   if (f_bar) {
@@ -719,9 +797,15 @@ void batch_enqueue(ters_plan *p, const double *x, const int32_t *type, double *e
     b.err = p->errw.as<uint32_t>();
     b.kmax = 0;
     const int nt = c->ntypes;
-    launch_fill_f64(xg, 0.0, 3 * (int64_t)p->N, s);
     launch_fill_f64(pg, 0.0, (int64_t)nt * nt * nt * kNField, s);
-    launch_adjoint(b, p->precision, 0, s);
+    if (p->gather) {
+      b.fslot = p->fslot.as<double>();
+      b.fown = p->fown.as<double>();
+    } else {
+      launch_fill_f64(xg, 0.0, 3 * (int64_t)p->N, s);
+    }
+    launch_adj(p->kern, b, p->precision, p->A, s);
+    if (p->gather) launch_gather(nl, b.fslot, b.fown, xg, 0, s);
   }
 }
 
@@ -792,24 +876,27 @@ ters_status ters_batch_run(ters_plan *p, const double *x, const int32_t *type, d
     if (!p->tuned) {
       // size the list, then pick the schedule on this data (eager, synchronising)
       nl_build_sync(c, nl, x, p->errw);
+      p->gather = c->gather;
+      if (p->gather) ensure_gather(p->fslot, p->fown, nl);
       DevBuf ft;
       ft.ensure(sizeof(double) * 3 * (size_t)p->N);
       hipEvent_t e0, e1;
       TERS_HIP_TRY(hipEventCreate(&e0));
       TERS_HIP_TRY(hipEventCreate(&e1));
-      const int cands[] = {16, 32, 48, 64};
+      struct Cand { int kern, A; };
+      const Cand cands[] = {{1, 16}, {1, 32}, {1, 48}, {1, 64}, {2, 8}, {2, 12}, {2, 16}, {2, 24}};
       double best = 1e300;
-      int bestA = 32;
-      for (int A : cands) {
+      int bestA = 32, bestK = 1;
+      for (const Cand &cd : cands) {
+        const int A = cd.A;
         FwdArgs a = base_args(c, nl, p->precision, p->N, x, type, true);
         a.flags = TERS_FORCES | TERS_ENERGY | TERS_VIRIAL;
         a.forces = ft.as<double>();
         a.partials = p->partials.as<double>();
         a.err = p->errw.as<uint32_t>();
-        int nbo[1];
-        launch_forward(a, p->precision, A, nbo, c->stream);
+        launch_fwd(cd.kern, a, p->precision, A, c->stream);
         TERS_HIP_TRY(hipEventRecord(e0, c->stream));
-        for (int r = 0; r < 3; ++r) launch_forward(a, p->precision, A, nbo, c->stream);
+        for (int r = 0; r < 3; ++r) launch_fwd(cd.kern, a, p->precision, A, c->stream);
         TERS_HIP_TRY(hipEventRecord(e1, c->stream));
         TERS_HIP_TRY(hipEventSynchronize(e1));
         float ms = 0.f;
@@ -817,18 +904,22 @@ ters_status ters_batch_run(ters_plan *p, const double *x, const int32_t *type, d
         if (1000.0 * ms / 3 < best) {
           best = 1000.0 * ms / 3;
           bestA = A;
+          bestK = cd.kern;
         }
       }
       hipEventDestroy(e0);
       hipEventDestroy(e1);
       ft.release();
       p->A = bestA;
+      p->kern = bestK;
       p->best_us = best;
       p->tuned = true;
     }
     std::vector<const void *> key = graph_key(c, nl);
     const void *extra[] = {x, type, e, f, w, e_bar, f_bar, xg, pg, p->partials.p, p->errw.p,
-                           (const void *)(intptr_t)p->A, (const void *)(intptr_t)p->precision};
+                           (const void *)(intptr_t)p->A, (const void *)(intptr_t)p->precision,
+                           (const void *)(intptr_t)p->kern, p->fslot.p, p->fown.p,
+                           (const void *)(intptr_t)p->gather};
     key.insert(key.end(), std::begin(extra), std::end(extra));
     if (!p->exec || key != p->key) {
       if (p->exec) {
@@ -856,9 +947,10 @@ static void plan_release_device(ters_plan *p) {
   hipStreamSynchronize(p->ctx->stream);
   if (p->exec) hipGraphExecDestroy(p->exec);
   p->exec = nullptr;
-  DevBuf *bufs[] = {&p->partials, &p->ebuf, &p->errw, &p->nl.conf, &p->nl.conf_of, &p->nl.count,
-                    &p->nl.list, &p->nl.order, &p->nl.cell_of, &p->nl.cell_count,
-                    &p->nl.cell_start, &p->nl.scan_tmp, &p->nl.xref, &p->nl.maxcount};
+  DevBuf *bufs[] = {&p->partials, &p->ebuf, &p->errw, &p->fslot, &p->fown, &p->nl.conf,
+                    &p->nl.conf_of, &p->nl.count, &p->nl.list, &p->nl.order, &p->nl.cell_of,
+                    &p->nl.cell_count, &p->nl.cell_start, &p->nl.scan_tmp, &p->nl.xref,
+                    &p->nl.maxcount, &p->nl.rev};
   for (DevBuf *b : bufs) b->release();
   p->ctx = nullptr;
 }
@@ -877,7 +969,7 @@ ters_status ters_plan_destroy(ters_plan *p) {
 ters_status ters_plan_schedule(const ters_plan *p, double *out3) {
   if (!p || !out3) return TERS_ERR_INVALID_ARG;
   out3[0] = p->A;
-  out3[1] = p->precision == TERS_FP64 ? 256 : 256;
+  out3[1] = p->kern;
   out3[2] = p->best_us;
   return TERS_OK;
 }

@@ -1,0 +1,499 @@
+// Tersoff force kernel, wavefront schedule.
+//
+// Every wavefront works alone (no workgroup barriers) on a run of atoms in
+// cell order.  Its lanes hold one in-cutoff pair (i, j) each; the neighbours
+// of an atom occupy consecutive lanes.  The data of neighbour k that the pair
+// (i, j) needs in its K loops is read from lane (i, k) with a cross-lane
+// permute, so per-pair data stays in registers.  The two K loops follow the
+// paper's Algorithm 2: the first accumulates zeta_ij, the pair term gives
+// dV/dzeta, the second evaluates dzeta(i,j,k)/dx and distributes the forces.
+// In the second loop the lanes of one atom walk their neighbours cyclically
+// (lane q visits k = q + s mod n in step s), so the force that pair (i, j)
+// produces for atom k in step s is exactly what lane (i, k) pulls from lane
+// (i, k - s) in that step: every pair slot gathers all contributions of atom
+// i's terms to its atom in a fixed order, without atomics in LDS.
+//
+// Scalar types and precision handling are those of the workgroup schedule
+// (FP64, mixed FP32 with FP64 displacements/accumulators, dual numbers).
+#include "ters_device.h"
+#include "ters_internal.h"
+#include "ters_math.h"
+
+namespace ters {
+
+namespace {
+
+constexpr int kNMax = 32;  // most in-cutoff neighbours of one atom
+constexpr int kWPB = 4;    // wavefronts per workgroup
+constexpr int kAMax = 32;  // most atoms per wavefront
+
+// --- cross-lane reads (ds_bpermute); every lane of the wave must take part --
+DEV int lane_read(int v, int src) { return __builtin_amdgcn_ds_bpermute(src << 2, v); }
+DEV float lane_read(float v, int src) {
+  return __int_as_float(__builtin_amdgcn_ds_bpermute(src << 2, __float_as_int(v)));
+}
+DEV double lane_read(double v, int src) {
+  int2 u = *reinterpret_cast<int2 *>(&v);
+  u.x = __builtin_amdgcn_ds_bpermute(src << 2, u.x);
+  u.y = __builtin_amdgcn_ds_bpermute(src << 2, u.y);
+  return *reinterpret_cast<double *>(&u);
+}
+template <class B> DEV Dual<B> lane_read(const Dual<B> &v, int src) {
+  return {lane_read(v.v, src), lane_read(v.d, src)};
+}
+
+DEV void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <class T, bool NT1, bool PG>
+__global__ __launch_bounds__(kWPB * kWave) void k_force_wave(FwdArgs a, int A) {
+  using B = base_t<T>;
+  using KP = KParam<B>;
+  using AT = acc_t<T>;
+  constexpr bool DUAL = IsDual<T>::value;
+  constexpr int NTL = 27;
+
+  // per-wavefront scratch (no sharing between wavefronts)
+  __shared__ int s_stage[kWPB][kAMax * kNMax];
+  __shared__ unsigned char s_slot[kWPB][kAMax * kNMax];  // list slot of each staged neighbour
+  __shared__ int s_cnt[kWPB][kAMax];
+  __shared__ unsigned char s_pa[kWPB][kWave], s_pq[kWPB][kWave];
+  __shared__ KP s_kp[NT1 ? 1 : NTL];
+  __shared__ double s_g[PG && !NT1 ? NTL * kNField : 1];
+  __shared__ double s_red[kWPB][8];
+
+  const int tid = threadIdx.x;
+  const int w = tid / kWave;
+  const int lane = lane_id();
+  const int nt = a.ntypes;
+
+  const KP *P;
+  if (NT1) {
+    P = (const KP *)a.kparam;
+  } else if (nt * nt * nt <= NTL) {
+    for (int e = tid; e < nt * nt * nt; e += kWPB * kWave) s_kp[e] = ((const KP *)a.kparam)[e];
+    P = s_kp;
+  } else {
+    P = (const KP *)a.kparam;
+  }
+  const bool grad_in_lds = !NT1 && PG && nt * nt * nt <= NTL;
+  if (grad_in_lds)
+    for (int e = tid; e < NTL * kNField; e += kWPB * kWave) s_g[e] = 0.0;
+  __syncthreads();  // the only workgroup barrier before the final reductions
+
+  auto param = [&](int ti, int tj, int tk) -> const KP & {
+    return NT1 ? P[0] : P[(ti * nt + tj) * nt + tk];
+  };
+  const double *filt2 = (const double *)a.filt2;
+  double gacc[NT1 && PG ? kNField : 1];
+  if (NT1 && PG) {
+#pragma unroll
+    for (int f = 0; f < kNField; ++f) gacc[f] = 0.0;
+  }
+  auto add_grad = [&](int ti, int tj, int tk, int field, double v) {
+    if (NT1) gacc[field] += v;
+    else if (grad_in_lds) unsafeAtomicAdd(&s_g[((ti * nt + tj) * nt + tk) * kNField + field], v);
+    else atomic_add(&a.pgrad[((ti * nt + tj) * nt + tk) * kNField + field], v);
+  };
+
+  double eacc = 0.0, wacc[6] = {0, 0, 0, 0, 0, 0};
+  const uint32_t flags = a.flags;
+  const bool want_f = DUAL ? (a.xgrad != nullptr) : ((flags & TERS_FORCES) && a.forces);
+  const bool want_w = !DUAL && (flags & TERS_VIRIAL);
+  const bool want_ea = !DUAL && (flags & TERS_PER_ATOM_E) && a.e_atom;
+
+  const int64_t first = ((int64_t)blockIdx.x * kWPB + w) * A;
+  const int na = (int)max((int64_t)0, min((int64_t)A, (int64_t)a.n - first));
+  // chunk atoms: lane `lane` < na holds atom `lane` of the chunk (A <= 64)
+  int my_i = 0, my_t = 0, my_lc = 0, my_cf = 0;
+  if (lane < na) {
+    my_i = a.order[first + lane];
+    my_t = NT1 ? 0 : a.type[my_i];
+    my_lc = min(a.count[my_i], a.cap);
+    my_cf = a.conf_of ? a.conf_of[my_i] : 0;
+  }
+
+  // ---- filter: compact the in-cutoff neighbours of every atom of the chunk --
+  if (na > 0) {
+    const int cap = a.cap;
+    const int lsh = __ffs(cap) - 1;
+    const uint64_t segbits = cap == 64 ? ~0ull : ((1ull << cap) - 1ull);
+    const int total = na * cap;
+    for (int base = 0; base < total; base += kWave) {
+      const int t = base + lane;
+      const int at = t >> lsh;
+      const int s = t & (cap - 1);
+      const int src = at < kWave ? at : 0;
+      const int i = lane_read(my_i, src), ti = lane_read(my_t, src);
+      const int lc = lane_read(my_lc, src), cf = lane_read(my_cf, src);
+      bool pass = false;
+      int j = 0;
+      if (at < na && s < lc) {
+        j = a.list[(int64_t)i * cap + s];
+        const ConfDesc &c = a.conf[cf];
+        double dx = a.x[3 * j] - a.x[3 * i];
+        double dy = a.x[3 * j + 1] - a.x[3 * i + 1];
+        double dz = a.x[3 * j + 2] - a.x[3 * i + 2];
+        dx -= c.box[0] * rint(dx * c.inv_box[0]);
+        dy -= c.box[1] * rint(dy * c.inv_box[1]);
+        dz -= c.box[2] * rint(dz * c.inv_box[2]);
+        const int tj = NT1 ? 0 : a.type[j];
+        pass = dx * dx + dy * dy + dz * dz < filt2[NT1 ? 0 : ti * nt + tj];
+      }
+      const uint64_t m = __ballot(pass);
+      const uint64_t seg = segbits << (lane & ~(cap - 1));
+      const int pos = __popcll(m & seg & ((1ull << lane) - 1ull));
+      if (pass) {
+        if (pos < kNMax) {
+          s_stage[w][at * kNMax + pos] = j;
+          s_slot[w][at * kNMax + pos] = (unsigned char)s;
+        } else {
+          atomicOr(a.err, kErrTooManyInCutoff);
+        }
+      } else if (a.fslot && at < na && s < lc) {
+        double *fs = a.fslot + 3 * ((int64_t)i * cap + s);
+        fs[0] = 0.0;
+        fs[1] = 0.0;
+        fs[2] = 0.0;
+      }
+      if (at < na && s == cap - 1) s_cnt[w][at] = min(__popcll(m & seg), kNMax);
+    }
+  }
+  wave_sync();
+  const int my_n = lane < na ? s_cnt[w][lane] : 0;
+  int incl = my_n;  // inclusive prefix of pair counts over the chunk's atoms
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int u = __shfl_up(incl, o, kWave);
+    if (lane >= o) incl += u;
+  }
+
+  // ---- rounds: consecutive atoms whose pairs fill at most one wavefront ------
+  int a0 = 0;
+  while (a0 < na) {
+    const int base = a0 > 0 ? __shfl(incl, a0 - 1, kWave) : 0;
+    const uint64_t fits = __ballot(lane >= a0 && lane < na && incl - base <= kWave);
+    const int a1 = a0 + __popcll(fits);  // >= a0 + 1: one atom has at most 32 pairs
+    const int np = __shfl(incl, a1 - 1, kWave) - base;
+    // pair map of this round
+    if (lane >= a0 && lane < a1) {
+      const int b = incl - my_n - base;
+      for (int q = 0; q < my_n; ++q) {
+        s_pa[w][b + q] = (unsigned char)lane;
+        s_pq[w][b + q] = (unsigned char)q;
+      }
+    }
+    wave_sync();
+    const bool act = lane < np;
+    const int at = act ? s_pa[w][lane] : a0;
+    const int q = act ? s_pq[w][lane] : 0;
+    const int n_i = lane_read(my_n, at);
+    const int seg0 = lane - q;  // first lane of this atom's pairs
+    const int i = lane_read(my_i, at), ti = lane_read(my_t, at), cf = lane_read(my_cf, at);
+    const int j = act ? s_stage[w][at * kNMax + q] : i;
+    const int tj = NT1 ? 0 : (act ? a.type[j] : 0);
+
+    // pair data in registers
+    T dx, dy, dz, r, ri, fc, dfc;
+    B rlo;
+    {
+      const ConfDesc &c = a.conf[cf];
+      double d[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        double dd = a.x[3 * j + k] - a.x[3 * i + k];
+        d[k] = dd - c.box[k] * rint(dd * c.inv_box[k]);
+      }
+      if (!act) {
+        d[0] = 1.0;
+        d[1] = 0.0;
+        d[2] = 0.0;
+      }
+      T dT[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+        dT[k] = Conv<T>::from(d[k], (DUAL && act) ? (a.fbar[3 * j + k] - a.fbar[3 * i + k]) : 0.0);
+      const double r64 = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+      r = t_sqrt(dT[0] * dT[0] + dT[1] * dT[1] + dT[2] * dT[2]);
+      set_val(r, r64);
+      ri = rcp(r);
+      fcut64(param(ti, tj, tj), r, r64, fc, dfc);
+      rlo = (B)(r64 - (double)val(r));
+      dx = dT[0];
+      dy = dT[1];
+      dz = dT[2];
+    }
+    const T u[3] = {dx * ri, dy * ri, dz * ri};
+    // largest neighbour count in this round (uniform loop bound)
+    int nmax = n_i;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) nmax = max(nmax, __shfl_xor(nmax, o, kWave));
+
+    // ---- first K loop: zeta_ij -----------------------------------------------
+    const KP &pp = param(ti, tj, tj);
+    const bool in_pair = act && val(r) < pp.rcut;
+    T zeta = Zero<T>::get();
+    for (int s = 1; s < nmax; ++s) {
+      const int kq = q + s < n_i ? q + s : q + s - n_i;
+      const int src = act && s < n_i ? seg0 + kq : lane;
+      const T kx = lane_read(dx, src), ky = lane_read(dy, src), kz = lane_read(dz, src);
+      const T kr = lane_read(r, src), kri = lane_read(ri, src);
+      const T kfc = lane_read(fc, src), kdfc = lane_read(dfc, src);
+      const int tk = NT1 ? 0 : lane_read(tj, src);
+      if (in_pair && s < n_i) {
+        const KP &pk = param(ti, tj, tk);
+        if (val(kr) < pk.rcut) {
+          T fck = kfc, dfck = kdfc;
+          if (!a.cut_consistent) fcut(pk, kr, fck, dfck);
+          const T v[3] = {kx * kri, ky * kri, kz * kri};
+          zeta += zeta_value<T, B>(pk, r, u, kr, v, fck);
+        }
+      }
+    }
+    // pair term V(i, j, zeta)
+    T dzeta = Zero<T>::get();
+    AT f0 = Zero<AT>::get(), f1 = Zero<AT>::get(), f2 = Zero<AT>::get();
+    double ev = 0.0;
+    const double eb = DUAL ? (a.ebar_conf ? a.ebar_conf[cf] : a.ebar) : 1.0;
+    if (in_pair) {
+      const T fr = scaled_exp(pp.A, pp.A_lo, pp.lam1, pp.lam1_lo, r, rlo);
+      const T fa = -scaled_exp(pp.Bc, pp.B_lo, pp.lam2, pp.lam2_lo, r, rlo);
+      T b, db, dbb, dbn;
+      bond<T, B, PG>(pp, zeta, b, db, dbb, dbn);
+      const T vr = fr + b * fa;
+      const AT V = widen(fc) * (widen(fr) + widen(b) * widen(fa));
+      const T dVdr = dfc * vr + fc * (-pp.lam1 * fr - pp.lam2 * b * fa);
+      dzeta = B(0.5) * fc * fa * db;
+      const T hp = B(0.5) * dVdr;
+      f0 = widen(-(hp * u[0]));
+      f1 = widen(-(hp * u[1]));
+      f2 = widen(-(hp * u[2]));
+      ev = 0.5 * val(V);
+      if (PG) {
+        const T h = T(B(0.5)) * fc;
+        T dp[8];
+        dp[0] = h * fr * (B(1) / pp.A);
+        dp[1] = -h * r * fr;
+        dp[2] = h * b * fa * (B(1) / pp.Bc);
+        dp[3] = -h * b * r * fa;
+        dp[4] = h * fa * dbb;
+        dp[5] = h * fa * dbn;
+        dp[6] = -B(0.5) * dfc * vr;
+        dp[7] = -B(0.5) * dfc * (r - pp.R) * (B(1) / pp.D) * vr;
+#pragma unroll
+        for (int f = 0; f < 8; ++f) add_grad(ti, tj, tj, GradSlots::pair[f], out_of(widen(dp[f]), eb));
+      }
+    }
+    // ---- second K loop: dzeta/dx, forces on j (kept) and on k (sent) -----------
+    for (int s = 1; s < nmax; ++s) {
+      const bool live = act && s < n_i;
+      const int kq = q + s < n_i ? q + s : q + s - n_i;      // k this lane treats
+      const int bq = q - s >= 0 ? q - s : q - s + n_i;       // lane whose k is me
+      const int src = live ? seg0 + kq : lane;
+      const int bsrc = live ? seg0 + bq : lane;
+      const T kx = lane_read(dx, src), ky = lane_read(dy, src), kz = lane_read(dz, src);
+      const T kr = lane_read(r, src), kri = lane_read(ri, src);
+      const T kfc = lane_read(fc, src), kdfc = lane_read(dfc, src);
+      const int tk = NT1 ? 0 : lane_read(tj, src);
+      T cx = Zero<T>::get(), cy = Zero<T>::get(), cz = Zero<T>::get();  // force sent to k
+      if (live && in_pair && val(dzeta) != B(0)) {
+        const KP &pk = param(ti, tj, tk);
+        if (val(kr) < pk.rcut) {
+          T fck = kfc, dfck = kdfc;
+          if (!a.cut_consistent) fcut(pk, kr, fck, dfck);
+          const T v[3] = {kx * kri, ky * kri, kz * kri};
+          T gj[3], gk[3], dp[8];
+          zeta_term<T, B, PG>(pk, r, ri, u, kr, kri, v, fck, dfck, gj, gk, dp);
+          f0 -= widen(dzeta * gj[0]);
+          f1 -= widen(dzeta * gj[1]);
+          f2 -= widen(dzeta * gj[2]);
+          cx = -(dzeta * gk[0]);
+          cy = -(dzeta * gk[1]);
+          cz = -(dzeta * gk[2]);
+          if (PG) {
+#pragma unroll
+            for (int fl = 0; fl < 8; ++fl)
+              add_grad(ti, tj, tk, GradSlots::three[fl], out_of(widen(dzeta * dp[fl]), eb));
+          }
+        }
+      }
+      // pull the force that lane (i, bq) computed for my atom in this step
+      const T rx = lane_read(cx, bsrc), ry = lane_read(cy, bsrc), rz = lane_read(cz, bsrc);
+      if (live) {
+        f0 += widen(rx);
+        f1 += widen(ry);
+        f2 += widen(rz);
+      }
+    }
+
+    // ---- f_im complete: virial, scatter to j, own force of i ------------------
+    if (!DUAL && a.partials) {
+      double wv[7] = {ev, 0, 0, 0, 0, 0, 0};
+      if (act && want_w) {
+        const double ddx = val(widen(dx)), ddy = val(widen(dy)), ddz = val(widen(dz));
+        const double fx = val(f0), fy = val(f1), fz = val(f2);
+        wv[1] = ddx * fx;
+        wv[2] = ddy * fy;
+        wv[3] = ddz * fz;
+        wv[4] = ddx * fy;
+        wv[5] = ddx * fz;
+        wv[6] = ddy * fz;
+      }
+      if (a.conf_of) {
+        // batches: per-configuration energy and virial; one atomic per value
+        // when the round belongs to one configuration, per lane otherwise
+        const int cf0 = __shfl(cf, 0, kWave);
+        if (__ballot(act && cf != cf0) == 0ull) {
+#pragma unroll
+          for (int k = 0; k < 7; ++k) {
+            const double sum = wave_sum(wv[k]);
+            if (lane == 0) atomic_add(&a.partials[(int64_t)cf0 * 8 + k], sum);
+          }
+        } else if (act) {
+#pragma unroll
+          for (int k = 0; k < 7; ++k) atomic_add(&a.partials[(int64_t)cf * 8 + k], wv[k]);
+        }
+      } else {
+        eacc += wv[0];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) wacc[k] += wv[k + 1];
+      }
+    }
+    if (act) {
+      if (want_f) {
+        const double o0 = DUAL ? -out_of(f0, eb) : val(f0);
+        const double o1 = DUAL ? -out_of(f1, eb) : val(f1);
+        const double o2 = DUAL ? -out_of(f2, eb) : val(f2);
+        if (a.fslot) {
+          double *fs = a.fslot + 3 * ((int64_t)i * a.cap + s_slot[w][at * kNMax + q]);
+          fs[0] = o0;
+          fs[1] = o1;
+          fs[2] = o2;
+        } else {
+          double *dst = DUAL ? a.xgrad : a.forces;
+          atomic_add(&dst[3 * j + 0], o0);
+          atomic_add(&dst[3 * j + 1], o1);
+          atomic_add(&dst[3 * j + 2], o2);
+        }
+      }
+    }
+    // own force of i = - sum of its f_im (segmented sum over the atom's lanes),
+    // per-atom energy; taken by the atom's first lane
+    AT sx = f0, sy = f1, sz = f2;
+    double se = ev;
+    for (int s = 1; s < nmax; ++s) {
+      const int src = (act && s < n_i) ? seg0 + s : lane;
+      const AT tx = lane_read(f0, src), ty = lane_read(f1, src), tz = lane_read(f2, src);
+      const double te = lane_read(ev, src);
+      if (act && q == 0 && s < n_i) {
+        sx += tx;
+        sy += ty;
+        sz += tz;
+        se += te;
+      }
+    }
+    if (act && q == 0) {
+      if (want_f) {
+        // own force of i is -sum; x gradient is -out(own) = +out(sum)
+        const double o0 = DUAL ? out_of(sx, eb) : -val(sx);
+        const double o1 = DUAL ? out_of(sy, eb) : -val(sy);
+        const double o2 = DUAL ? out_of(sz, eb) : -val(sz);
+        if (a.fown) {
+          a.fown[3 * i + 0] = o0;
+          a.fown[3 * i + 1] = o1;
+          a.fown[3 * i + 2] = o2;
+        } else {
+          double *dst = DUAL ? a.xgrad : a.forces;
+          atomic_add(&dst[3 * i + 0], o0);
+          atomic_add(&dst[3 * i + 1], o1);
+          atomic_add(&dst[3 * i + 2], o2);
+        }
+      }
+      if (want_ea) {
+        if (flags & TERS_ACCUMULATE) a.e_atom[i] += se;
+        else a.e_atom[i] = se;
+      }
+    }
+    // atoms of the chunk without any in-cutoff neighbour: zero per-atom energy
+    // and, in owner-gather mode, zero own force
+    if (lane >= a0 && lane < a1 && my_n == 0) {
+      if (want_ea && !(flags & TERS_ACCUMULATE)) a.e_atom[my_i] = 0.0;
+      if (want_f && a.fown) {
+        a.fown[3 * my_i + 0] = 0.0;
+        a.fown[3 * my_i + 1] = 0.0;
+        a.fown[3 * my_i + 2] = 0.0;
+      }
+    }
+    wave_sync();
+    a0 = a1;
+  }
+
+  // ---- workgroup reductions ------------------------------------------------------
+  if (!DUAL && a.partials && !a.conf_of) {
+    double vals[7] = {eacc, wacc[0], wacc[1], wacc[2], wacc[3], wacc[4], wacc[5]};
+#pragma unroll
+    for (int k = 0; k < 7; ++k) {
+      double sum = wave_sum(vals[k]);
+      if (lane == 0) s_red[w][k] = sum;
+    }
+    __syncthreads();
+    if (tid < 7) {
+      double sum = 0.0;
+      for (int q2 = 0; q2 < kWPB; ++q2) sum += s_red[q2][tid];
+      a.partials[(int64_t)blockIdx.x * 8 + tid] = sum;
+    }
+  }
+  if (PG) {
+    if (NT1) {
+#pragma unroll
+      for (int f = 0; f < kNField; ++f) {
+        double sum = wave_sum(gacc[f]);
+        if (lane == 0) atomic_add(&a.pgrad[f], sum);
+      }
+    } else if (grad_in_lds) {
+      __syncthreads();
+      for (int e = tid; e < nt * nt * nt * kNField; e += kWPB * kWave)
+        if (s_g[e] != 0.0) atomic_add(&a.pgrad[e], s_g[e]);
+    }
+  }
+}
+
+template <class T, bool PG>
+void launch_wave_t(const FwdArgs &a, int A, hipStream_t s) {
+  if (A <= 0 || A > kAMax) A = 16;
+  const int64_t per_block = (int64_t)kWPB * A;
+  const int nb = (int)((a.n + per_block - 1) / per_block);
+  if (nb == 0) return;
+  if (a.ntypes == 1)
+    k_force_wave<T, true, PG><<<nb, kWPB * kWave, 0, s>>>(a, A);
+  else
+    k_force_wave<T, false, PG><<<nb, kWPB * kWave, 0, s>>>(a, A);
+}
+
+}  // namespace
+
+int wave_blocks(int n, int A) {
+  if (A <= 0 || A > kAMax) A = 16;
+  return (int)((n + (int64_t)kWPB * A - 1) / ((int64_t)kWPB * A));
+}
+
+void launch_forward_wave(const FwdArgs &a, int precision, int A, hipStream_t s) {
+  const bool pg = (a.flags & TERS_PARAM_GRAD) && a.pgrad;
+  if (precision == TERS_FP64) {
+    if (pg) launch_wave_t<double, true>(a, A, s);
+    else launch_wave_t<double, false>(a, A, s);
+  } else {
+    if (pg) launch_wave_t<float, true>(a, A, s);
+    else launch_wave_t<float, false>(a, A, s);
+  }
+}
+
+void launch_adjoint_wave(const FwdArgs &a, int precision, int A, hipStream_t s) {
+  if (precision == TERS_FP64) launch_wave_t<Dual<double>, true>(a, A, s);
+  else launch_wave_t<Dual<float>, true>(a, A, s);
+}
+
+}  // namespace ters

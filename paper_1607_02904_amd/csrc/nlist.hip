@@ -277,6 +277,57 @@ __global__ __launch_bounds__(kBS) void k_build(int n, const double *__restrict__
   }
 }
 
+// rev[i*cap + s] = slot of i in the row of j = list[i*cap + s].  The list is
+// symmetric by construction (r_ij and r_ji are computed from exactly negated
+// displacements), so the slot exists; a missing one is latched as an error.
+__global__ void k_reverse(int n, int cap, const int32_t *__restrict__ count,
+                          const int32_t *__restrict__ list, int32_t *__restrict__ rev,
+                          const int32_t *cond, uint32_t *err) {
+  if (skip(cond)) return;
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int ci = min(count[i], cap);
+  for (int s = 0; s < ci; ++s) {
+    const int j = list[(int64_t)i * cap + s];
+    const int cj = min(count[j], cap);
+    int found = -1;
+    for (int t = 0; t < cj; ++t)
+      if (list[(int64_t)j * cap + t] == i) {
+        found = t;
+        break;
+      }
+    if (found < 0) atomicOr(err, kErrListAsymmetric);
+    rev[(int64_t)i * cap + s] = found < 0 ? -1 : j * cap + found;
+  }
+}
+
+// owner gather: fixed-order sum of the forces that every neighbour's terms put
+// on atom a, plus a's own part
+__global__ void k_gather(int n, int cap, const int32_t *__restrict__ count,
+                         const int32_t *__restrict__ rev, const double *__restrict__ fslot,
+                         const double *__restrict__ fown, double *__restrict__ F, int accumulate) {
+  int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= n) return;
+  double fx = fown[3 * a], fy = fown[3 * a + 1], fz = fown[3 * a + 2];
+  const int ca = min(count[a], cap);
+  for (int s = 0; s < ca; ++s) {
+    const int r = rev[(int64_t)a * cap + s];
+    if (r < 0) continue;
+    fx += fslot[3 * (int64_t)r];
+    fy += fslot[3 * (int64_t)r + 1];
+    fz += fslot[3 * (int64_t)r + 2];
+  }
+  if (accumulate) {
+    F[3 * a] += fx;
+    F[3 * a + 1] += fy;
+    F[3 * a + 2] += fz;
+  } else {
+    F[3 * a] = fx;
+    F[3 * a + 1] = fy;
+    F[3 * a + 2] = fz;
+  }
+}
+
 __global__ void k_check(int n, const double *__restrict__ x, const double *__restrict__ xref,
                         const ConfDesc *__restrict__ conf, const int32_t *__restrict__ conf_of,
                         double lim2, int32_t *flag) {
@@ -353,7 +404,18 @@ void nlist_build(NList &nl, const double *x, const int32_t *cond, uint32_t *err,
                                              nl.rlist * nl.rlist, nl.cap, nl.count.as<int32_t>(),
                                              nl.list.as<int32_t>(), nl.maxcount.as<int32_t>(),
                                              cond, err, rebuild_counter);
+    if (nl.rev.p)
+      k_reverse<<<grid_for(n, kBS), kBS, 0, s>>>(n, nl.cap, nl.count.as<int32_t>(),
+                                                 nl.list.as<int32_t>(), nl.rev.as<int32_t>(), cond,
+                                                 err);
   }
+}
+
+void launch_gather(const NList &nl, const double *fslot, const double *fown, double *F,
+                   int accumulate, hipStream_t s) {
+  if (nl.n <= 0) return;
+  k_gather<<<grid_for(nl.n, kBS), kBS, 0, s>>>(nl.n, nl.cap, nl.count.as<int32_t>(),
+                                               nl.rev.as<int32_t>(), fslot, fown, F, accumulate);
 }
 
 void nlist_check(const NList &nl, const double *x, int32_t *flag, hipStream_t s) {

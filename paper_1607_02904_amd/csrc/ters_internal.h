@@ -62,7 +62,12 @@ struct ConfDesc {
 };
 
 // Device error word bits (latched by kernels, read at sync points).
-enum : uint32_t { kErrNlistOverflow = 1u, kErrNotFinite = 2u, kErrTooManyInCutoff = 4u };
+enum : uint32_t {
+  kErrNlistOverflow = 1u,
+  kErrNotFinite = 2u,
+  kErrTooManyInCutoff = 4u,
+  kErrListAsymmetric = 8u
+};
 
 // Neighbour list state.  One list per configuration set (a single system is
 // a set of one).
@@ -83,6 +88,7 @@ struct NList {
   DevBuf scan_tmp;    // int32 block sums
   DevBuf xref;        // double[n][3]
   DevBuf maxcount;    // int32[1]
+  DevBuf rev;         // int32[n][cap]: slot of (j, i) in j's row for slot (i, j)
 };
 
 // Forward / adjoint launch description.
@@ -110,6 +116,12 @@ struct FwdArgs {
   double ebar;             // adjoint: scalar cotangent of E (single system)
   const double *ebar_conf; // adjoint: per-configuration cotangent (batch) or null
   double *xgrad;           // adjoint output [n][3]
+  // owner-gather mode (no atomics): when fslot is set, the force that the
+  // terms rooted at atom i exert on its list neighbour in slot s goes to
+  // fslot[(i*cap + s)*3 ..] (zero for slots outside the cutoff) and the force
+  // on i itself to fown[i*3 ..]; a gather kernel then sums them per atom.
+  double *fslot;
+  double *fown;
   uint32_t *err;
 };
 
@@ -119,10 +131,18 @@ void launch_fill_f64(double *p, double v, int64_t n, hipStream_t s);
 void nlist_build(NList &nl, const double *x, const int32_t *cond, uint32_t *err, hipStream_t s,
                  int64_t *rebuild_counter = nullptr);
 void nlist_check(const NList &nl, const double *x, int32_t *flag, hipStream_t s);
+// F[a] (+)= fown[a] + sum over a's list slots s of fslot[rev[a*cap + s]]
+// (sign -1 negates the sum; used by the adjoint, whose outputs are x gradients)
+void launch_gather(const NList &nl, const double *fslot, const double *fown, double *F,
+                   int accumulate, hipStream_t s);
 void launch_forward(const FwdArgs &a, int precision, int atoms_per_block, int nblocks_out[1],
                     hipStream_t s);
 void launch_adjoint(const FwdArgs &a, int precision, int atoms_per_block, hipStream_t s);
 int forward_blocks(int n, int atoms_per_block);
+// wavefront schedule: atoms per wavefront (<= 32), 4 wavefronts per workgroup
+void launch_forward_wave(const FwdArgs &a, int precision, int atoms_per_wave, hipStream_t s);
+void launch_adjoint_wave(const FwdArgs &a, int precision, int atoms_per_wave, hipStream_t s);
+int wave_blocks(int n, int atoms_per_wave);
 void launch_reduce_partials(const double *partials, int nblocks, int stride, double *energy,
                             double *virial, int accumulate, hipStream_t s,
                             double *trace = nullptr, int32_t *step = nullptr);

@@ -1,0 +1,179 @@
+// The Tersoff functions on the scalar types of the kernels (double, float,
+// dual numbers): cutoff switch, bond order, the three-body term and its
+// gradients, and the parameter partials used by the adjoint.
+//
+//   f_C(r)      = 1 below R-D, 0 above R+D, 1/2 - 1/2 sin(pi (r-R) / (2D)) between
+//   b(zeta)     = (1 + (beta zeta)^n)^(-1/(2n))
+//   zeta(i,j,k) = f_C(r_ik) g(cos theta_ijk) exp(lambda3^m (r_ij - r_ik)^m)
+//   g(cos)      = gamma (1 + c^2 t^2 / (d^2 (d^2 + t^2))),  t = cos - h
+// (the paper, Section III, Eqs. ters-2 and ters-3, with Tersoff's forms).
+#pragma once
+#include "ters_device.h"
+
+namespace ters {
+
+// f_C and f_C' (sine switch from 1 at R-D to 0 at R+D)
+template <class T, class B>
+DEV void fcut(const KParam<B> &p, T r, T &fc, T &dfc) {
+  B rv = val(r);
+  if (rv <= p.rin) {
+    fc = T(B(1));
+    dfc = T(B(0));
+  } else if (rv >= p.rcut) {
+    fc = T(B(0));
+    dfc = T(B(0));
+  } else {
+    T arg = ((r - p.R) - p.R_lo) * p.pi2d;
+    fc = B(0.5) - B(0.5) * t_sin(arg);
+    dfc = -p.pi4d * t_cos(arg);
+  }
+}
+
+// the same, with the FP64 distance at hand: the switch argument is formed in
+// FP64 before rounding (keeps the FP32 path unbiased in the transition region)
+template <class T, class B>
+DEV void fcut64(const KParam<B> &p, T r, double r64, T &fc, T &dfc) {
+  B rv = val(r);
+  if (rv <= p.rin) {
+    fc = T(B(1));
+    dfc = T(B(0));
+  } else if (rv >= p.rcut) {
+    fc = T(B(0));
+    dfc = T(B(0));
+  } else {
+    T arg = r * p.pi2d;  // tangent part
+    set_val(arg, (r64 - (double)p.R - (double)p.R_lo) * (double)p.pi2d);
+    fc = B(0.5) - B(0.5) * t_sin(arg);
+    dfc = -p.pi4d * t_cos(arg);
+  }
+}
+
+// b(zeta) = (1 + (beta zeta)^n)^(-1/(2n)) and db/dzeta, in a form that cannot
+// overflow: with s = n ln(beta zeta), ln(1 + e^s) = s + ln(1 + e^-s) for s > 0.
+// Also d b / d beta and d b / d n for the parameter gradient.
+template <class T, class B, bool PG>
+DEV void bond(const KParam<B> &p, T z, T &b, T &db, T &dbeta, T &dn) {
+  if (val(z) <= B(0)) {
+    b = T(B(1));
+    db = T(B(0));
+    dbeta = T(B(0));
+    dn = T(B(0));
+    return;
+  }
+  T lz = t_log(p.beta * z);
+  T s = p.n * lz;
+  T l1p, w;  // ln(1 + y), y / (1 + y)
+  if (val(s) > B(0)) {
+    T em = t_exp(-s);
+    l1p = s + t_log1p(em);
+    w = rcp(B(1) + em);
+  } else {
+    T ep = t_exp(s);
+    l1p = t_log1p(ep);
+    w = ep * rcp(B(1) + ep);
+  }
+  b = t_exp(-l1p * p.inv2n);
+  T bw = b * w;
+  db = -B(0.5) * bw * rcp(z);
+  if (PG) {
+    dbeta = -B(0.5) * bw * rcp(T(p.beta));
+    dn = b * p.inv2n * (l1p * rcp(T(p.n)) - w * lz);
+  } else {
+    dbeta = T(B(0));
+    dn = T(B(0));
+  }
+}
+
+// zeta(i,j,k) alone (the first K loop of Algorithm 2 needs only the value).
+template <class T, class B>
+DEV T zeta_value(const KParam<B> &p, T rij, const T *u, T rik, const T *v, T fck) {
+  T cs = u[0] * v[0] + u[1] * v[1] + u[2] * v[2];
+  T t = (cs - p.h) - p.h_lo;
+  T t2 = t * t;
+  T g = p.gamma * (B(1) + p.c2d2 * t2 * rcp(p.d2 + t2));
+  if (p.lam3 == B(0)) return fck * g;
+  T uu = p.lam3 * (rij - rik);
+  T arg = p.m3 ? uu * uu * uu : uu;
+  return fck * g * t_exp(arg);
+}
+
+// zeta(i,j,k) = f_C(r_ik) g(cos) exp(lambda3^m (r_ij - r_ik)^m) and its
+// gradients wrt x_j and x_k (the one wrt x_i is minus their sum).  With PG,
+// also the partials wrt gamma, c, d, h, lambda3, m, R, D of this entry.
+template <class T, class B, bool PG>
+DEV T zeta_term(const KParam<B> &p, T rij, T rinv_ij, const T *u, T rik, T rinv_ik, const T *v,
+                T fck, T dfck, T *gj, T *gk, T *dpar) {
+  T cs = u[0] * v[0] + u[1] * v[1] + u[2] * v[2];
+  T t = (cs - p.h) - p.h_lo;
+  T t2 = t * t;
+  T iden = rcp(p.d2 + t2);
+  T gn = B(1) + p.c2d2 * t2 * iden;  // g / gamma
+  T g = p.gamma * gn;
+  T dg = B(2) * p.gc2 * t * iden * iden;
+  T e, de;  // exponential factor and its derivative wrt dr = r_ij - r_ik
+  T dr = rij - rik;
+  T uu = p.lam3 * dr;
+  T arg;
+  if (p.lam3 == B(0)) {  // exponential factor is exactly 1 (e.g. the Si/C sets)
+    e = T(B(1));
+    de = T(B(0));
+    arg = T(B(0));
+  } else if (p.m3) {
+    arg = uu * uu * uu;
+    e = t_exp(arg);
+    de = B(3) * p.lam3 * uu * uu * e;
+  } else {
+    arg = uu;
+    e = t_exp(arg);
+    de = p.lam3 * e;
+  }
+  T fge = fck * g;
+  T z = fge * e;
+  T s1 = fck * dg * e;
+  T s2 = fge * de;
+  T s3 = dfck * g * e;
+  T s32 = s3 - s2;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    T dcj = (v[c] - cs * u[c]) * rinv_ij;
+    T dck = (u[c] - cs * v[c]) * rinv_ik;
+    gj[c] = s1 * dcj + s2 * u[c];
+    gk[c] = s1 * dck + s32 * v[c];
+  }
+  if (PG) {
+    T fe = fck * e;
+    T ge = g * e;
+    dpar[0] = fe * gn;                                            // gamma
+    dpar[1] = fe * (B(2) * p.gamma * p.c * t2 * iden / p.d2);     // c
+    dpar[2] = fe * (B(2) * p.gc2 * (p.d * iden * iden - B(1) / (p.d2 * p.d)));  // d
+    dpar[3] = -fe * dg;                                           // h
+    if (p.m3) dpar[4] = fge * e * (B(3) * uu * uu * dr);          // lambda3
+    else dpar[4] = fge * e * dr;
+    B au = val(uu) < B(0) ? -val(uu) : val(uu);
+    if (p.lam3 == B(0) || au == B(0)) {
+      dpar[5] = T(B(0));                                          // m
+    } else {
+      T lu = val(uu) < B(0) ? t_log(-uu) : t_log(uu);
+      dpar[5] = fge * e * arg * lu;
+    }
+    dpar[6] = -ge * dfck;                                         // R (of r_ik)
+    dpar[7] = -ge * dfck * (rik - p.R) * (B(1) / p.D);            // D (of r_ik)
+  }
+  return z;
+}
+
+// ---------------------------------------------------------------------------
+// output combination: forward writes values; the adjoint writes
+// e_bar * value - tangent (parameter gradient) and its negative (x gradient)
+// ---------------------------------------------------------------------------
+DEV double out_of(double c, double) { return c; }
+DEV double out_of(const Dual<double> &c, double ebar) { return ebar * c.v - c.d; }
+
+template <class T> struct Zero { static DEV T get() { return T(base_t<T>(0)); } };
+
+struct GradSlots {  // field index of each parameter partial
+  static constexpr int three[8] = {FGAMMA, FC, FD, FH, FLAM3, FM, FR, FDC};
+  static constexpr int pair[8] = {FA, FLAM1, FB, FLAM2, FBETA, FN, FR, FDC};
+};
+
+}  // namespace ters

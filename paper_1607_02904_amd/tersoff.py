@@ -31,7 +31,8 @@ EXPORTS = ("ters_create", "ters_destroy", "ters_set_stream", "ters_sync", "ters_
            "ters_set_params", "ters_build_nlist", "ters_needs_rebuild", "ters_nlist_stats",
            "ters_compute", "ters_compute_ex", "ters_backward", "ters_md_run", "ters_md_rebuilds",
            "ters_batch_plan", "ters_batch_run", "ters_plan_destroy", "ters_plan_schedule",
-           "ters_set_schedule", "ters_autotune", "ters_profile_forward", "ters_table_sic",
+           "ters_set_schedule", "ters_set_force_mode", "ters_autotune", "ters_profile_forward",
+           "ters_table_sic",
            "ters_table_element", "ters_version")
 
 _lib = None
@@ -73,7 +74,8 @@ def load_library(path=LIB_PATH):
         "ters_batch_run": [P, P, P, P, P, P, P, P, P, P],
         "ters_plan_destroy": [P],
         "ters_plan_schedule": [P, P],
-        "ters_set_schedule": [P, I32, I32],
+        "ters_set_schedule": [P, I32, I32, I32],
+        "ters_set_force_mode": [P, I32],
         "ters_autotune": [P, I32, P, P, P, ctypes.c_int, P],
         "ters_profile_forward": [P, I32, P, P, P, ctypes.c_int, I32, P],
         "ters_table_sic": [P],
@@ -189,8 +191,14 @@ class Tersoff:
         self._chk(self._L.ters_nlist_stats(self._h, out.ctypes.data_as(ctypes.c_void_p)))
         return dict(n=int(out[0]), entries=int(out[1]), longest=int(out[2]), capacity=int(out[3]))
 
-    def set_schedule(self, atoms_per_block=0, kmax=0):
-        self._chk(self._L.ters_set_schedule(self._h, int(atoms_per_block), int(kmax)))
+    def set_schedule(self, kernel=0, atoms=0, kmax=0):
+        """kernel 1: workgroup schedule (atoms per workgroup <= 64, k_max);
+        kernel 2: wavefront schedule (atoms per wavefront <= 32); 0: default."""
+        self._chk(self._L.ters_set_schedule(self._h, int(kernel), int(atoms), int(kmax)))
+
+    def set_force_mode(self, gather=True):
+        """gather=True: owner-gather (deterministic, no atomics); False: FP64 atomics."""
+        self._chk(self._L.ters_set_force_mode(self._h, 1 if gather else 0))
 
     def autotune(self, x, types, box, precision=FP64):
         self._bind_stream()
@@ -304,7 +312,7 @@ class BatchPlan:
     def schedule(self):
         out = np.zeros(3)
         _check(self.model._h, self._L.ters_plan_schedule(self._h, out.ctypes.data_as(ctypes.c_void_p)))
-        return dict(atoms_per_block=int(out[0]), block=int(out[1]), us=float(out[2]))
+        return dict(atoms=int(out[0]), kernel=int(out[1]), us=float(out[2]))
 
     def close(self):
         if getattr(self, "_h", None):

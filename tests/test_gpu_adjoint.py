@@ -103,9 +103,14 @@ def si_setup(orc):
     model.close()
 
 
-def test_si_parameter_gradient_fp64(orc, si_setup):
+@pytest.mark.parametrize("kernel", [1, 2])
+def test_si_parameter_gradient_fp64(orc, si_setup, kernel):
     frames, table, refs, model = si_setup
-    pg, _ = _gpu_grad(model, frames, refs, 0)
+    model.set_schedule(kernel, 0, 0)
+    try:
+        pg, _ = _gpu_grad(model, frames, refs, 0)
+    finally:
+        model.set_schedule(0, 0, 0)
     fd = _fd_params(orc, frames, table, refs, [(0, 0, 0)])
     _check_params(pg, fd, 1e-6)
 
@@ -127,13 +132,15 @@ def test_si_position_gradient_fp64(orc, si_setup):
             assert abs(g - fd) <= 1e-6 * max(abs(fd), 1e-2 * np.abs(xgs[0]).max()), (a, c, g, fd)
 
 
-def test_sic_parameter_gradient_fp64(orc):
+@pytest.mark.parametrize("kernel", [1, 2])
+def test_sic_parameter_gradient_fp64(orc, kernel):
     from paper_1607_02904_amd.tersoff import Tersoff, table_sic
     frames = inputs.sic_liquid_batch(nconf=2, nmin=200, nmax=300, seed=77)
     table = params.sic()
     ref_tab = _perturbed(table, seed=5)
     refs = [orc.compute(x, t, b, ref_tab)[:2] for x, t, b in frames]
     model = Tersoff(table_sic())
+    model.set_schedule(kernel, 0, 0)
     try:
         pg, _ = _gpu_grad(model, frames, refs, 0)
     finally:

@@ -105,17 +105,34 @@ def test_sic_liquid(orc, sic_model, precision, seed):
     _check(gpu_eval(sic_model, x, t, box, precision), ref, precision)
 
 
-@pytest.mark.parametrize("apb,kmax", [(8, 0), (13, 0), (32, 1), (64, 2), (40, 0), (1, 0)])
-def test_schedules_and_kmax_fallback(orc, sic_model, apb, kmax):
-    """Every atoms-per-workgroup choice and the k_max fallback (recompute
-    dzeta/dx_k beyond k_max) reach the same result."""
+SCHEDULES = [(1, 8, 0), (1, 13, 0), (1, 32, 1), (1, 64, 2), (1, 40, 0), (1, 1, 0),
+             (2, 1, 0), (2, 7, 0), (2, 16, 0), (2, 32, 0)]
+
+
+@pytest.mark.parametrize("kernel,atoms,kmax", SCHEDULES)
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
+def test_schedules_and_kmax_fallback(orc, sic_model, kernel, atoms, kmax, precision):
+    """Both force kernels, every atoms-per-workgroup/wavefront choice and the
+    k_max fallback (recompute dzeta/dx_k beyond k_max) reach the same result."""
     x, t, box = inputs.sic_liquid_batch(nconf=1, nmin=600, nmax=700, seed=7)[0]
     ref = orc.compute(x, t, box, params.sic())
-    sic_model.set_schedule(apb, kmax)
+    sic_model.set_schedule(kernel, atoms, kmax)
     try:
-        _check(gpu_eval(sic_model, x, t, box, 0), ref, 0)
+        _check(gpu_eval(sic_model, x, t, box, precision), ref, precision)
     finally:
-        sic_model.set_schedule(0, 0)
+        sic_model.set_schedule(0, 0, 0)
+
+
+@pytest.mark.parametrize("kernel", [1, 2])
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
+def test_si_512_both_kernels(orc, si_model, kernel, precision):
+    x, t, box = inputs.si_small()
+    ref = orc.compute(x, t, box, _si_table_oracle())
+    si_model.set_schedule(kernel, 0, 0)
+    try:
+        _check(gpu_eval(si_model, x, t, box, precision), ref, precision)
+    finally:
+        si_model.set_schedule(0, 0, 0)
 
 
 def test_perfect_lattice_zero_force(si_model):
@@ -246,3 +263,25 @@ def test_sic_1m_full_size(orc, sic_model):
     e64, f64, _, _ = gpu_eval(sic_model, x, t, box, 0, skin=0.5)
     assert abs(e64 - eref) <= FP64_TOL * abs(eref)
     assert _rel(f64[sample], fs) <= FP64_TOL
+
+
+@pytest.mark.parametrize("kernel", [1, 2])
+def test_force_modes_agree_and_gather_is_reproducible(orc, sic_model, kernel):
+    """Owner-gather (no atomics) and atomic scatter give the same forces; the
+    gather mode is bitwise reproducible run to run."""
+    x, t, box = inputs.sic_liquid_batch(nconf=1, nmin=900, nmax=1200, seed=12)[0]
+    ref = orc.compute(x, t, box, params.sic())
+    sic_model.set_schedule(kernel, 0, 0)
+    try:
+        sic_model.set_force_mode(gather=False)
+        scat = gpu_eval(sic_model, x, t, box, 0)
+        sic_model.set_force_mode(gather=True)
+        g1 = gpu_eval(sic_model, x, t, box, 0)
+        g2 = gpu_eval(sic_model, x, t, box, 0)
+    finally:
+        sic_model.set_force_mode(gather=True)
+        sic_model.set_schedule(0, 0, 0)
+    _check(scat, ref, 0)
+    _check(g1, ref, 0)
+    assert np.array_equal(g1[1], g2[1])
+    assert _rel(scat[1], g1[1]) <= 1e-14

@@ -34,13 +34,17 @@ def _md_gpu(model, x, t, box, nsteps, skin, precision=0, use_graph=True, dt=0.00
     return xd.cpu().numpy(), v.cpu().numpy(), f.cpu().numpy(), tr.cpu().numpy()[:nsteps]
 
 
-@pytest.mark.parametrize("use_graph", [True, False])
-def test_md_matches_oracle_verlet(orc, si_model, use_graph):
+@pytest.mark.parametrize("use_graph,kernel", [(True, 1), (False, 1), (True, 2)])
+def test_md_matches_oracle_verlet(orc, si_model, use_graph, kernel):
     """30 steps of 1 fs on a 1000-atom Si cell (sigma 0.1, v0 = 0), list with
     skin 0.5 rebuilt on the device when due, against the oracle's velocity
     Verlet that rebuilds its list at every step."""
     x, t, box = inputs.si_bulk(ncell=5, seed=21)
-    xg, vg, fg, trg = _md_gpu(si_model, x, t, box, 30, 0.5, use_graph=use_graph)
+    si_model.set_schedule(kernel, 0, 0)
+    try:
+        xg, vg, fg, trg = _md_gpu(si_model, x, t, box, 30, 0.5, use_graph=use_graph)
+    finally:
+        si_model.set_schedule(0, 0, 0)
     xo, vo, fo, tro = orc.velocity_verlet(x, np.zeros_like(x), t, box, params.single(params.SI_B),
                                           [MASS_SI], 0.001, 30)
     assert np.max(np.abs(xg - xo)) < 1e-10
