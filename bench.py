@@ -104,6 +104,13 @@ def main():
     td = torch.as_tensor(t, device=dev)
     x0 = torch.as_tensor(x, device=dev)
 
+    # schedule per precision chosen by the library's autotuner on this input
+    model.build_nlist(x0, td, box, skin)
+    tuned = {}
+    for prec in (FP64, MIXED):
+        us = model.autotune(x0, td, box, prec)
+        tuned[prec] = us
+
     def run_md(precision):
         xd = x0.clone()
         v = torch.zeros_like(xd)
@@ -131,6 +138,7 @@ def main():
 
     # force-kernel duration (HIP events around the kernel launches alone)
     model.build_nlist(x0, td, box, skin)
+    sched = model.schedules()
     k64 = model.profile_forward(x0, td, box, FP64, reps=20)
     kmx = model.profile_forward(x0, td, box, MIXED, reps=20)
     L, P, T = count_work(x, t, box, tab, 3.2 + skin, 3.2)
@@ -162,8 +170,8 @@ def main():
         "roofline": roof(kmx, FP32_PEAK),
         "fp64": {"value": n * args.steps / el64, "unit": "atom-steps/s",
                  "ms_per_step": 1000.0 * el64 / args.steps, "rebuilds": reb64,
-                 "roofline": roof(k64, FP64_PEAK)},
-        "mixed": {"rebuilds": rebmx, "kernel_us": kmx,
+                 "schedule": sched["fp64"], "roofline": roof(k64, FP64_PEAK)},
+        "mixed": {"rebuilds": rebmx, "kernel_us": kmx, "schedule": sched["mixed"],
                   "energy_drift_per_atom": float((trmx[-1] - trmx[0]) / n),
                   "fp64_vs_mixed_energy_rel": float(abs(trmx[-1] - tr64[-1]) / abs(tr64[-1]))},
     }
@@ -176,6 +184,7 @@ def main():
         xsd = torch.as_tensor(xs, device=dev)
         tsd = torch.as_tensor(ts, device=dev)
         ms.build_nlist(xsd, tsd, bs, 0.5)
+        ms.autotune(xsd, tsd, bs, MIXED)
         o = ms.compute(xsd, tsd, bs, MIXED)
         torch.cuda.synchronize()
         reps = 10
@@ -186,7 +195,7 @@ def main():
         el = (time.perf_counter() - t0) / reps
         kus = ms.profile_forward(xsd, tsd, bs, MIXED, reps=10)
         out["sic_1m_mixed"] = {"value": len(xs) / el, "unit": "atom-steps/s", "ms_per_eval": el * 1e3,
-                               "kernel_us": kus}
+                               "kernel_us": kus, "schedule": ms.schedules()["mixed"]}
         ms.close()
         del xsd, tsd
 

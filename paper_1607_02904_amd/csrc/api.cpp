@@ -239,6 +239,7 @@ FwdArgs base_args(ters_ctx *c, const NList &nl, int precision, int n, const doub
   a.filt2 = c->filt2.p;
   a.cut_consistent = c->cut_consistent;
   a.kmax = c->kmax;
+  a.rev = nl.rev.as<int32_t>();
   return a;
 }
 
@@ -303,8 +304,10 @@ void ensure_gather(DevBuf &fslot, DevBuf &fown, const NList &nl) {
   fown.ensure(sizeof(double) * 3 * n);
 }
 
-// one force evaluation (forces zeroed unless accumulating); returns #blocks
-int run_forward(ters_ctx *c, const FwdArgs &a0, int precision, hipStream_t s) {
+// one force evaluation (forces zeroed unless accumulating); returns #blocks.
+// With do_gather false (owner-gather mode) the caller gathers the forces itself.
+int run_forward(ters_ctx *c, const FwdArgs &a0, int precision, hipStream_t s,
+                bool do_gather = true) {
   FwdArgs a = a0;
   const int nb = ctx_blocks(c, precision, a.n);
   c->partials.ensure(sizeof(double) * 8 * (size_t)std::max(nb, 1));
@@ -319,7 +322,7 @@ int run_forward(ters_ctx *c, const FwdArgs &a0, int precision, hipStream_t s) {
     launch_fill_f64(a.forces, 0.0, 3 * (int64_t)a.n, s);
   }
   launch_fwd(c->kern[precision], a, precision, c->A[precision], s);
-  if (gather)
+  if (gather && do_gather)
     launch_gather(c->nl, a.fslot, a.fown, a.forces, (a.flags & TERS_ACCUMULATE) ? 1 : 0, s);
   return nb;
 }
@@ -584,6 +587,14 @@ ters_status ters_set_schedule(ters_ctx *c, int32_t kernel, int32_t atoms, int32_
   return TERS_OK;
 }
 
+ters_status ters_get_schedule(const ters_ctx *c, int32_t precision, int32_t *out3) {
+  if (!c || !out3 || (precision != TERS_FP64 && precision != TERS_MIXED)) return TERS_ERR_INVALID_ARG;
+  out3[0] = c->kern[precision];
+  out3[1] = c->A[precision];
+  out3[2] = c->gather;
+  return TERS_OK;
+}
+
 ters_status ters_set_force_mode(ters_ctx *c, int32_t mode) {
   if (!c || mode < 0 || mode > 1) return TERS_ERR_INVALID_ARG;
   c->gather = mode;
@@ -696,18 +707,23 @@ ters_status ters_md_run(ters_ctx *c, int32_t n, double *x, double *v, double *f,
     if (c->gather) ensure_gather(c->fslot, c->fown, c->nl);  // no allocation inside a capture
     // one step: kick + drift + zero F + rebuild test | conditional rebuild |
     // forces | energy (trace) | kick + clear the flag
+    const bool gather = c->gather != 0;
     auto step = [&](hipStream_t s) {
       int32_t *flag = c->flag.as<int32_t>();
-      launch_vv_first(n, x, v, f, type, c->mass.as<double>(), dt, c->nl, flag, s);
+      launch_vv_first(n, x, v, f, type, c->mass.as<double>(), dt, c->nl, flag, gather ? 0 : 1, s);
       nlist_build(c->nl, x, flag, c->errw.as<uint32_t>(), s, c->rebuilds.as<int64_t>());
       FwdArgs a = base_args(c, c->nl, precision, n, x, type);
-      a.flags = TERS_FORCES | TERS_ENERGY | TERS_ACCUMULATE;  // F was zeroed by the kick
+      a.flags = TERS_FORCES | TERS_ENERGY | TERS_ACCUMULATE;  // scatter: F was zeroed by the kick
       a.forces = f;
-      run_forward(c, a, precision, s);
+      run_forward(c, a, precision, s, /*do_gather=*/false);
       if (trace)
         launch_reduce_partials(c->partials.as<double>(), nb, 8, c->escratch.as<double>(), nullptr,
                                0, s, trace, c->step.as<int32_t>());
-      launch_vv_second(n, v, f, type, c->mass.as<double>(), dt, flag, s);
+      if (gather)
+        launch_vv_second_gather(c->nl, v, f, c->fslot.as<double>(), c->fown.as<double>(), type,
+                                c->mass.as<double>(), dt, flag, s);
+      else
+        launch_vv_second(n, v, f, type, c->mass.as<double>(), dt, flag, s);
     };
     launch_fill_i32(c->step.as<int32_t>(), 0, 1, nullptr, c->stream);
     launch_fill_i32(c->flag.as<int32_t>(), 0, 1, nullptr, c->stream);

@@ -153,10 +153,13 @@ __global__ __launch_bounds__(BS) void k_force(FwdArgs a, int A) {
           atomicOr(a.err, kErrTooManyInCutoff);
         }
       } else if (a.fslot && at < na && s < s_lcnt[at]) {
-        double *fs = a.fslot + 3 * ((int64_t)s_atom[at] * cap + s);
-        fs[0] = 0.0;
-        fs[1] = 0.0;
-        fs[2] = 0.0;
+        const int r = a.rev[(int64_t)s_atom[at] * cap + s];
+        if (r >= 0) {
+          double *fs = a.fslot + 3 * (int64_t)r;
+          fs[0] = 0.0;
+          fs[1] = 0.0;
+          fs[2] = 0.0;
+        }
       }
       if (at < na && s == cap - 1) s_cnt[at] = min(__popcll(m & seg), kNMax);
     }
@@ -430,10 +433,13 @@ __global__ __launch_bounds__(BS) void k_force(FwdArgs a, int A) {
         const double o1 = DUAL ? -out_of(f[1], eb) : val(f[1]);
         const double o2 = DUAL ? -out_of(f[2], eb) : val(f[2]);
         if (a.fslot) {
-          double *fs = a.fslot + 3 * ((int64_t)s_atom[at] * a.cap + s_slot[at * kNMax + m]);
-          fs[0] = o0;
-          fs[1] = o1;
-          fs[2] = o2;
+          const int r = a.rev[(int64_t)s_atom[at] * a.cap + s_slot[at * kNMax + m]];
+          if (r >= 0) {
+            double *fs = a.fslot + 3 * (int64_t)r;
+            fs[0] = o0;
+            fs[1] = o1;
+            fs[2] = o2;
+          }
         } else {
           double *dst = DUAL ? a.xgrad : a.forces;
           atomic_add(&dst[3 * j + 0], o0);
@@ -523,23 +529,25 @@ __global__ __launch_bounds__(BS) void k_force(FwdArgs a, int A) {
 // Fixed-order sum of the per-workgroup partials.  With a trace, the energy is
 // also stored at trace[*step] and the device step counter advanced (keeps a
 // captured molecular-dynamics step replayable).
-__global__ void k_reduce_partials(const double *partials, int nblocks, int stride, double *energy,
-                                  double *virial, int accumulate, double *trace, int32_t *step) {
-  __shared__ double red[256];
-  int k = blockIdx.x;  // 0 = energy, 1..6 virial
+constexpr int kRedBS = 1024;
+__global__ __launch_bounds__(kRedBS) void k_reduce_partials(const double *partials, int nblocks,
+                                                            int stride, double *energy,
+                                                            double *virial, int accumulate,
+                                                            double *trace, int32_t *step) {
+  __shared__ double red[kRedBS / kWave];
+  const int k = blockIdx.x;  // 0 = energy, 1..6 virial
   double s = 0.0;
-  for (int b = threadIdx.x; b < nblocks; b += blockDim.x) s += partials[(int64_t)b * stride + k];
-  red[threadIdx.x] = s;
+  for (int b = threadIdx.x; b < nblocks; b += kRedBS) s += partials[(int64_t)b * stride + k];
+  s = wave_sum(s);
+  if (lane_id() == 0) red[threadIdx.x / kWave] = s;
   __syncthreads();
-  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
-    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-    __syncthreads();
-  }
   if (threadIdx.x == 0) {
+    double tot = 0.0;
+    for (int w = 0; w < kRedBS / kWave; ++w) tot += red[w];
     double *dst = k == 0 ? energy : (virial ? virial + (k - 1) : nullptr);
-    if (dst) *dst = accumulate ? *dst + red[0] : red[0];
+    if (dst) *dst = accumulate ? *dst + tot : tot;
     if (k == 0 && trace) {
-      trace[*step] = red[0];
+      trace[*step] = tot;
       *step += 1;
     }
   }
@@ -590,8 +598,8 @@ void launch_adjoint(const FwdArgs &a, int precision, int A, hipStream_t s) {
 void launch_reduce_partials(const double *partials, int nblocks, int stride, double *energy,
                             double *virial, int accumulate, hipStream_t s, double *trace,
                             int32_t *step) {
-  k_reduce_partials<<<virial ? 7 : 1, 256, 0, s>>>(partials, nblocks, stride, energy, virial,
-                                                   accumulate, trace, step);
+  k_reduce_partials<<<virial ? 7 : 1, kRedBS, 0, s>>>(partials, nblocks, stride, energy, virial,
+                                                      accumulate, trace, step);
 }
 
 }  // namespace ters

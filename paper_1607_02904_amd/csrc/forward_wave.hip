@@ -154,10 +154,13 @@ __global__ __launch_bounds__(kWPB * kWave) void k_force_wave(FwdArgs a, int A) {
           atomicOr(a.err, kErrTooManyInCutoff);
         }
       } else if (a.fslot && at < na && s < lc) {
-        double *fs = a.fslot + 3 * ((int64_t)i * cap + s);
-        fs[0] = 0.0;
-        fs[1] = 0.0;
-        fs[2] = 0.0;
+        const int r = a.rev[(int64_t)i * cap + s];
+        if (r >= 0) {
+          double *fs = a.fslot + 3 * (int64_t)r;
+          fs[0] = 0.0;
+          fs[1] = 0.0;
+          fs[2] = 0.0;
+        }
       }
       if (at < na && s == cap - 1) s_cnt[w][at] = min(__popcll(m & seg), kNMax);
     }
@@ -368,10 +371,13 @@ __global__ __launch_bounds__(kWPB * kWave) void k_force_wave(FwdArgs a, int A) {
         const double o1 = DUAL ? -out_of(f1, eb) : val(f1);
         const double o2 = DUAL ? -out_of(f2, eb) : val(f2);
         if (a.fslot) {
-          double *fs = a.fslot + 3 * ((int64_t)i * a.cap + s_slot[w][at * kNMax + q]);
-          fs[0] = o0;
-          fs[1] = o1;
-          fs[2] = o2;
+          const int r = a.rev[(int64_t)i * a.cap + s_slot[w][at * kNMax + q]];
+          if (r >= 0) {
+            double *fs = a.fslot + 3 * (int64_t)r;
+            fs[0] = o0;
+            fs[1] = o1;
+            fs[2] = o2;
+          }
         } else {
           double *dst = DUAL ? a.xgrad : a.forces;
           atomic_add(&dst[3 * j + 0], o0);

@@ -47,12 +47,23 @@ __global__ void k_fill_f64(double *p, double v, int64_t n) {
     p[i] = v;
 }
 
+DEV void bin_one(int i, const double *__restrict__ x, const ConfDesc *__restrict__ conf,
+                 const int32_t *__restrict__ conf_of, int32_t *__restrict__ cell_of,
+                 int32_t *__restrict__ cell_count, uint32_t *err);
+
 __global__ void k_bin(int n, const double *__restrict__ x, const ConfDesc *__restrict__ conf,
                       const int32_t *__restrict__ conf_of, int32_t *__restrict__ cell_of,
-                      int32_t *__restrict__ cell_count, const int32_t *cond, uint32_t *err) {
+                      int32_t *__restrict__ cell_count, int32_t *__restrict__ maxcount,
+                      const int32_t *cond, uint32_t *err) {
   if (skip(cond)) return;
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *maxcount = 0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    bin_one(i, x, conf, conf_of, cell_of, cell_count, err);
+}
+
+DEV void bin_one(int i, const double *__restrict__ x, const ConfDesc *__restrict__ conf,
+                 const int32_t *__restrict__ conf_of, int32_t *__restrict__ cell_of,
+                 int32_t *__restrict__ cell_count, uint32_t *err) {
   const ConfDesc &c = conf[conf_index(conf_of, i)];
   int q[3];
   bool finite = true;
@@ -127,30 +138,30 @@ __global__ __launch_bounds__(kBS) void k_scan_tiles(const int32_t *__restrict__ 
   if (threadIdx.x == 0) tile_sum[blockIdx.x] = tot;
 }
 
-// scan of the tile sums by one workgroup (any number of tiles)
-__global__ __launch_bounds__(kBS) void k_scan_tile_sums(int32_t *tile_sum, int nt,
-                                                        const int32_t *cond) {
+// one workgroup per tile: adds the sum of all earlier tiles (summed here, so
+// no separate pass over the tile sums) and clears the counts (they become
+// the placement cursors)
+__global__ __launch_bounds__(kBS) void k_scan_add(int32_t *out, int64_t m,
+                                                  const int32_t *tile_sum, int32_t *counts,
+                                                  const int32_t *cond) {
   if (skip(cond)) return;
-  int carry = 0;
-  for (int base = 0; base < nt; base += kBS) {
-    int i = base + threadIdx.x;
-    int v = i < nt ? tile_sum[i] : 0;
-    int tot;
-    int ex = block_excl_scan(v, &tot);
-    if (i < nt) tile_sum[i] = carry + ex;
-    carry += tot;
-    __syncthreads();
-  }
-}
-
-// adds the tile offsets and clears the counts (they become the placement cursors)
-__global__ void k_scan_add(int32_t *out, int64_t m, const int32_t *tile_sum, int32_t *counts,
-                           const int32_t *cond) {
-  if (skip(cond)) return;
-  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i < m) {
-    out[i] += tile_sum[i / kScanTile];
-    counts[i] = 0;
+  __shared__ int wsum[kBS / kWave];
+  int part = 0;
+  for (int t = threadIdx.x; t < (int)blockIdx.x; t += kBS) part += tile_sum[t];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, kWave);
+  if (lane_id() == 0) wsum[threadIdx.x / kWave] = part;
+  __syncthreads();
+  int off = 0;
+#pragma unroll
+  for (int w = 0; w < kBS / kWave; ++w) off += wsum[w];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile;
+  for (int k = threadIdx.x; k < kScanTile; k += kBS) {
+    const int64_t i = base + k;
+    if (i < m) {
+      out[i] += off;
+      counts[i] = 0;
+    }
   }
 }
 
@@ -182,30 +193,35 @@ __global__ void k_place(int n, const double *__restrict__ x, const int32_t *__re
                         int32_t *__restrict__ order, double *__restrict__ xref,
                         const int32_t *cond) {
   if (skip(cond)) return;
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  int c = cell_of[i];
-  int pos = cell_start[c] + atomicAdd(&cursor[c], 1);
-  order[pos] = i;
-  xref[3 * i + 0] = x[3 * i + 0];
-  xref[3 * i + 1] = x[3 * i + 1];
-  xref[3 * i + 2] = x[3 * i + 2];
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    int c = cell_of[i];
+    int pos = cell_start[c] + atomicAdd(&cursor[c], 1);
+    order[pos] = i;
+    xref[3 * i + 0] = x[3 * i + 0];
+    xref[3 * i + 1] = x[3 * i + 1];
+    xref[3 * i + 2] = x[3 * i + 2];
+  }
 }
 
+// order atoms inside each cell by index; the counts (used as placement
+// cursors) are cleared for the next build
 __global__ void k_sort_cells(int64_t ncell, const int32_t *__restrict__ cell_start,
-                             int32_t *__restrict__ order, const int32_t *cond) {
+                             int32_t *__restrict__ order, int32_t *__restrict__ counts,
+                             const int32_t *cond) {
   if (skip(cond)) return;
-  int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (c >= ncell) return;
-  int b = cell_start[c], e = cell_start[c + 1];
-  for (int p = b + 1; p < e; ++p) {
-    int v = order[p];
-    int q = p - 1;
-    while (q >= b && order[q] > v) {
-      order[q + 1] = order[q];
-      --q;
+  for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < ncell;
+       c += (int64_t)gridDim.x * blockDim.x) {
+    int b = cell_start[c], e = cell_start[c + 1];
+    for (int p = b + 1; p < e; ++p) {
+      int v = order[p];
+      int q = p - 1;
+      while (q >= b && order[q] > v) {
+        order[q + 1] = order[q];
+        --q;
+      }
+      order[q + 1] = v;
     }
-    order[q + 1] = v;
+    counts[c] = 0;
   }
 }
 
@@ -221,8 +237,14 @@ __global__ __launch_bounds__(kBS) void k_build(int n, const double *__restrict__
                                                const int32_t *cond, uint32_t *err,
                                                int64_t *rebuilds) {
   if (skip(cond)) return;
-  int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t == 0 && rebuilds) *rebuilds += 1;
+  if (blockIdx.x == 0 && threadIdx.x == 0 && rebuilds) *rebuilds += 1;
+  int worst = 0;
+  // grid-stride over atoms in cell order; every lane runs the same number of
+  // iterations so the wave reduction below sees all lanes
+  const int stride = gridDim.x * blockDim.x;
+  const int iters = (n + stride - 1) / stride;
+  for (int it = 0; it < iters; ++it) {
+  const int t = it * stride + blockIdx.x * blockDim.x + threadIdx.x;
   int cnt = 0;
   if (t < n) {
     int i = order[t];
@@ -267,8 +289,10 @@ __global__ __launch_bounds__(kBS) void k_build(int n, const double *__restrict__
     }
     count[i] = cnt;
   }
+  worst = max(worst, cnt);
+  }
   // largest row, one atomic per wave
-  int m = cnt;
+  int m = worst;
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o, kWave));
   if (lane_id() == 0 && m > 0) {
@@ -284,8 +308,7 @@ __global__ void k_reverse(int n, int cap, const int32_t *__restrict__ count,
                           const int32_t *__restrict__ list, int32_t *__restrict__ rev,
                           const int32_t *cond, uint32_t *err) {
   if (skip(cond)) return;
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
   const int ci = min(count[i], cap);
   for (int s = 0; s < ci; ++s) {
     const int j = list[(int64_t)i * cap + s];
@@ -299,23 +322,23 @@ __global__ void k_reverse(int n, int cap, const int32_t *__restrict__ count,
     if (found < 0) atomicOr(err, kErrListAsymmetric);
     rev[(int64_t)i * cap + s] = found < 0 ? -1 : j * cap + found;
   }
+  }
 }
 
 // owner gather: fixed-order sum of the forces that every neighbour's terms put
-// on atom a, plus a's own part
+// on atom a (its incoming slots, contiguous), plus a's own part
 __global__ void k_gather(int n, int cap, const int32_t *__restrict__ count,
-                         const int32_t *__restrict__ rev, const double *__restrict__ fslot,
-                         const double *__restrict__ fown, double *__restrict__ F, int accumulate) {
+                         const double *__restrict__ fslot, const double *__restrict__ fown,
+                         double *__restrict__ F, int accumulate) {
   int a = blockIdx.x * blockDim.x + threadIdx.x;
   if (a >= n) return;
   double fx = fown[3 * a], fy = fown[3 * a + 1], fz = fown[3 * a + 2];
   const int ca = min(count[a], cap);
+  const double *in = fslot + 3 * (int64_t)a * cap;
   for (int s = 0; s < ca; ++s) {
-    const int r = rev[(int64_t)a * cap + s];
-    if (r < 0) continue;
-    fx += fslot[3 * (int64_t)r];
-    fy += fslot[3 * (int64_t)r + 1];
-    fz += fslot[3 * (int64_t)r + 2];
+    fx += in[3 * s];
+    fy += in[3 * s + 1];
+    fz += in[3 * s + 2];
   }
   if (accumulate) {
     F[3 * a] += fx;
@@ -377,35 +400,41 @@ void nlist_build(NList &nl, const double *x, const int32_t *cond, uint32_t *err,
   const ConfDesc *conf = nl.conf.as<ConfDesc>();
   const int32_t *conf_of = nl.nconf > 1 ? nl.conf_of.as<int32_t>() : nullptr;
   const int64_t m = ncell + 1;
-  {
+  // Cell counts are zero between builds (the sort step clears them); a build
+  // started from the host clears them once more, since the buffer may be new.
+  if (cond == nullptr) {
     int g = grid_for(m, kBS);
     k_zero_cells<<<g > 4096 ? 4096 : g, kBS, 0, s>>>(cell_count, m, nl.maxcount.as<int32_t>(), cond);
   }
+  // grids are capped (grid-stride loops): a skipped rebuild then costs one
+  // short dispatch per kernel
+  const int gcap = 1024;
+  auto grid = [&](int64_t work) {
+    int g = grid_for(work, kBS);
+    return g < 1 ? 1 : (g > gcap ? gcap : g);
+  };
   if (n > 0)
-    k_bin<<<grid_for(n, kBS), kBS, 0, s>>>(n, x, conf, conf_of, nl.cell_of.as<int32_t>(),
-                                           cell_count, cond, err);
+    k_bin<<<grid(n), kBS, 0, s>>>(n, x, conf, conf_of, nl.cell_of.as<int32_t>(), cell_count,
+                                  nl.maxcount.as<int32_t>(), cond, err);
   if (m <= kScan1Max) {
     k_scan_single<<<1, kBS, 0, s>>>(cell_count, cell_start, m, cond);
   } else {
     const int ntile = grid_for(m, kScanTile);
     k_scan_tiles<<<ntile, kBS, 0, s>>>(cell_count, cell_start, m, nl.scan_tmp.as<int32_t>(), cond);
-    k_scan_tile_sums<<<1, kBS, 0, s>>>(nl.scan_tmp.as<int32_t>(), ntile, cond);
-    k_scan_add<<<grid_for(m, kBS), kBS, 0, s>>>(cell_start, m, nl.scan_tmp.as<int32_t>(),
-                                                cell_count, cond);
+    k_scan_add<<<ntile, kBS, 0, s>>>(cell_start, m, nl.scan_tmp.as<int32_t>(), cell_count, cond);
   }
   if (n > 0) {
-    k_place<<<grid_for(n, kBS), kBS, 0, s>>>(n, x, nl.cell_of.as<int32_t>(), cell_start,
-                                             cell_count, nl.order.as<int32_t>(),
-                                             nl.xref.as<double>(), cond);
-    k_sort_cells<<<grid_for(ncell, kBS), kBS, 0, s>>>(ncell, cell_start, nl.order.as<int32_t>(),
-                                                      cond);
-    k_build<<<grid_for(n, kBS), kBS, 0, s>>>(n, x, conf, conf_of, nl.order.as<int32_t>(),
+    k_place<<<grid(n), kBS, 0, s>>>(n, x, nl.cell_of.as<int32_t>(), cell_start, cell_count,
+                                    nl.order.as<int32_t>(), nl.xref.as<double>(), cond);
+    k_sort_cells<<<grid(ncell), kBS, 0, s>>>(ncell, cell_start, nl.order.as<int32_t>(), cell_count,
+                                             cond);
+    k_build<<<grid(n), kBS, 0, s>>>(n, x, conf, conf_of, nl.order.as<int32_t>(),
                                              nl.cell_of.as<int32_t>(), cell_start,
                                              nl.rlist * nl.rlist, nl.cap, nl.count.as<int32_t>(),
                                              nl.list.as<int32_t>(), nl.maxcount.as<int32_t>(),
                                              cond, err, rebuild_counter);
     if (nl.rev.p)
-      k_reverse<<<grid_for(n, kBS), kBS, 0, s>>>(n, nl.cap, nl.count.as<int32_t>(),
+      k_reverse<<<grid(n), kBS, 0, s>>>(n, nl.cap, nl.count.as<int32_t>(),
                                                  nl.list.as<int32_t>(), nl.rev.as<int32_t>(), cond,
                                                  err);
   }
@@ -414,8 +443,8 @@ void nlist_build(NList &nl, const double *x, const int32_t *cond, uint32_t *err,
 void launch_gather(const NList &nl, const double *fslot, const double *fown, double *F,
                    int accumulate, hipStream_t s) {
   if (nl.n <= 0) return;
-  k_gather<<<grid_for(nl.n, kBS), kBS, 0, s>>>(nl.n, nl.cap, nl.count.as<int32_t>(),
-                                               nl.rev.as<int32_t>(), fslot, fown, F, accumulate);
+  k_gather<<<grid_for(nl.n, kBS), kBS, 0, s>>>(nl.n, nl.cap, nl.count.as<int32_t>(), fslot, fown,
+                                               F, accumulate);
 }
 
 void nlist_check(const NList &nl, const double *x, int32_t *flag, hipStream_t s) {

@@ -117,11 +117,13 @@ struct FwdArgs {
   const double *ebar_conf; // adjoint: per-configuration cotangent (batch) or null
   double *xgrad;           // adjoint output [n][3]
   // owner-gather mode (no atomics): when fslot is set, the force that the
-  // terms rooted at atom i exert on its list neighbour in slot s goes to
-  // fslot[(i*cap + s)*3 ..] (zero for slots outside the cutoff) and the force
-  // on i itself to fown[i*3 ..]; a gather kernel then sums them per atom.
+  // terms rooted at atom i exert on its list neighbour j (slot s of i's row)
+  // goes to j's incoming slot fslot[rev[i*cap + s]*3 ..] (zero when the pair is
+  // outside the cutoff) and the force on i itself to fown[i*3 ..]; atom a's
+  // incoming forces then sit contiguously in fslot[a*cap*3 ..] for the gather.
   double *fslot;
   double *fown;
+  const int32_t *rev;
   uint32_t *err;
 };
 
@@ -131,10 +133,14 @@ void launch_fill_f64(double *p, double v, int64_t n, hipStream_t s);
 void nlist_build(NList &nl, const double *x, const int32_t *cond, uint32_t *err, hipStream_t s,
                  int64_t *rebuild_counter = nullptr);
 void nlist_check(const NList &nl, const double *x, int32_t *flag, hipStream_t s);
-// F[a] (+)= fown[a] + sum over a's list slots s of fslot[rev[a*cap + s]]
-// (sign -1 negates the sum; used by the adjoint, whose outputs are x gradients)
+// F[a] (+)= fown[a] + sum over a's incoming slots fslot[a*cap + s], s < count[a]
 void launch_gather(const NList &nl, const double *fslot, const double *fown, double *F,
                    int accumulate, hipStream_t s);
+// molecular dynamics: gather as above into F, then v += dt/2 F/m, and clear
+// the rebuild flag for the next step
+void launch_vv_second_gather(const NList &nl, double *v, double *F, const double *fslot,
+                             const double *fown, const int32_t *type, const double *mass,
+                             double dt, int32_t *flag, hipStream_t s);
 void launch_forward(const FwdArgs &a, int precision, int atoms_per_block, int nblocks_out[1],
                     hipStream_t s);
 void launch_adjoint(const FwdArgs &a, int precision, int atoms_per_block, hipStream_t s);
@@ -147,7 +153,8 @@ void launch_reduce_partials(const double *partials, int nblocks, int stride, dou
                             double *virial, int accumulate, hipStream_t s,
                             double *trace = nullptr, int32_t *step = nullptr);
 void launch_vv_first(int n, double *x, double *v, double *f, const int32_t *type,
-                     const double *mass, double dt, const NList &nl, int32_t *flag, hipStream_t s);
+                     const double *mass, double dt, const NList &nl, int32_t *flag, int zero_f,
+                     hipStream_t s);
 void launch_vv_second(int n, double *v, const double *f, const int32_t *type, const double *mass,
                       double dt, int32_t *flag, hipStream_t s);
 

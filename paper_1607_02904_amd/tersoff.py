@@ -31,7 +31,8 @@ EXPORTS = ("ters_create", "ters_destroy", "ters_set_stream", "ters_sync", "ters_
            "ters_set_params", "ters_build_nlist", "ters_needs_rebuild", "ters_nlist_stats",
            "ters_compute", "ters_compute_ex", "ters_backward", "ters_md_run", "ters_md_rebuilds",
            "ters_batch_plan", "ters_batch_run", "ters_plan_destroy", "ters_plan_schedule",
-           "ters_set_schedule", "ters_set_force_mode", "ters_autotune", "ters_profile_forward",
+           "ters_set_schedule", "ters_get_schedule", "ters_set_force_mode", "ters_autotune",
+           "ters_profile_forward",
            "ters_table_sic",
            "ters_table_element", "ters_version")
 
@@ -76,6 +77,7 @@ def load_library(path=LIB_PATH):
         "ters_plan_schedule": [P, P],
         "ters_set_schedule": [P, I32, I32, I32],
         "ters_set_force_mode": [P, I32],
+        "ters_get_schedule": [P, I32, P],
         "ters_autotune": [P, I32, P, P, P, ctypes.c_int, P],
         "ters_profile_forward": [P, I32, P, P, P, ctypes.c_int, I32, P],
         "ters_table_sic": [P],
@@ -195,6 +197,15 @@ class Tersoff:
         """kernel 1: workgroup schedule (atoms per workgroup <= 64, k_max);
         kernel 2: wavefront schedule (atoms per wavefront <= 32); 0: default."""
         self._chk(self._L.ters_set_schedule(self._h, int(kernel), int(atoms), int(kmax)))
+
+    def schedules(self):
+        """Current kernel / atoms / force mode per precision."""
+        out = {}
+        for name, prec in (("fp64", FP64), ("mixed", MIXED)):
+            v = np.zeros(3, dtype=np.int32)
+            self._chk(self._L.ters_get_schedule(self._h, prec, v.ctypes.data_as(ctypes.c_void_p)))
+            out[name] = {"kernel": int(v[0]), "atoms": int(v[1]), "force_mode": "gather" if v[2] else "atomic"}
+        return out
 
     def set_force_mode(self, gather=True):
         """gather=True: owner-gather (deterministic, no atomics); False: FP64 atomics."""

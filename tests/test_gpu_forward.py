@@ -62,7 +62,21 @@ def _si_table_oracle():
     return params.single(params.SI_B, R=2.85, D=0.15)
 
 
-def _check(gpu, ref, precision):
+def energy_scale(orc, x, t, box, table):
+    """S = E_rep - E_att: the repulsive (f_R) and attractive (b f_A) parts of
+    the energy, each from the oracle with the other part switched off.  It is
+    the magnitude of the terms that the FP32 arithmetic evaluates, the
+    conditioning scale of the energy sum (|E| can be far smaller on
+    disordered cells, where the two parts nearly cancel)."""
+    rep = table.copy()
+    rep[..., params.IDX["B"]] = 0.0
+    att = table.copy()
+    att[..., params.IDX["A"]] = 0.0
+    return orc.compute(x, t, box, rep)[0] - orc.compute(x, t, box, att)[0]
+
+
+def _check(gpu, ref, precision, escale=None):
+    """escale: mixed-path energy scale (default |E|, the crystals' bar)."""
     e, f, w, ea = gpu
     er, fr, wr, ear = ref
     if np.abs(fr).max() < 1e-8:
@@ -76,10 +90,7 @@ def _check(gpu, ref, precision):
         if ea is not None:
             assert _rel(ea, ear) <= FP64_TOL
     else:
-        # energy bar relative to the per-atom energy scale sum_i |e_i| (equal to
-        # |E| on crystals, where every e_i has the same sign; the disordered
-        # cells' total energy is a cancelling sum of large pair terms)
-        scale = np.abs(ear).sum() if ear is not None else abs(er)
+        scale = abs(er) if escale is None else escale
         assert abs(e - er) <= MIX_E_TOL * scale, (e, er, abs(e - er) / scale)
         assert _rel(f, fr) <= MIX_F_TOL, _rel(f, fr)
         assert _rel(w, wr) <= MIX_F_TOL
@@ -102,7 +113,8 @@ def test_sic_liquid(orc, sic_model, precision, seed):
     several hundred atoms (several workgroups, ragged last one)."""
     x, t, box = inputs.sic_liquid_batch(nconf=1, nmin=700, nmax=1500, seed=100 + seed)[0]
     ref = orc.compute(x, t, box, params.sic())
-    _check(gpu_eval(sic_model, x, t, box, precision), ref, precision)
+    scale = energy_scale(orc, x, t, box, params.sic())
+    _check(gpu_eval(sic_model, x, t, box, precision), ref, precision, escale=scale)
 
 
 SCHEDULES = [(1, 8, 0), (1, 13, 0), (1, 32, 1), (1, 64, 2), (1, 40, 0), (1, 1, 0),
@@ -116,9 +128,10 @@ def test_schedules_and_kmax_fallback(orc, sic_model, kernel, atoms, kmax, precis
     k_max fallback (recompute dzeta/dx_k beyond k_max) reach the same result."""
     x, t, box = inputs.sic_liquid_batch(nconf=1, nmin=600, nmax=700, seed=7)[0]
     ref = orc.compute(x, t, box, params.sic())
+    scale = energy_scale(orc, x, t, box, params.sic())
     sic_model.set_schedule(kernel, atoms, kmax)
     try:
-        _check(gpu_eval(sic_model, x, t, box, precision), ref, precision)
+        _check(gpu_eval(sic_model, x, t, box, precision), ref, precision, escale=scale)
     finally:
         sic_model.set_schedule(0, 0, 0)
 

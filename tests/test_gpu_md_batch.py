@@ -143,11 +143,12 @@ def test_batch_forward_matches_oracle(orc, batch_setup, precision):
     model.sync()
     e, f, w = e.cpu().numpy(), f.cpu().numpy(), w.cpu().numpy()
     off = plan.offsets
+    from test_gpu_forward import energy_scale
     tol_e, tol_f = (1e-12, 1e-12) if precision == 0 else (1e-7, 1e-5)
     for c, (xc, tc, bc) in enumerate(confs):
         er, fr, wr, ear = orc.compute(xc, tc, bc, params.sic())
-        # FP64: relative to |E|; mixed: relative to the per-atom scale sum |e_i|
-        scale = abs(er) if precision == 0 else np.abs(ear).sum()
+        # FP64: relative to |E|; mixed: relative to E_rep - E_att (see energy_scale)
+        scale = abs(er) if precision == 0 else energy_scale(orc, xc, tc, bc, params.sic())
         assert abs(e[c] - er) <= tol_e * scale, (c, e[c], er)
         fc = f[off[c]:off[c + 1]]
         assert np.linalg.norm(fc - fr) <= tol_f * np.linalg.norm(fr), c
