@@ -73,6 +73,24 @@ def flops_of(L, P, T):
     return FLOPS_PER_ENTRY * L + FLOPS_PER_NEIGH * P + FLOPS_PER_PAIR * P + FLOPS_PER_TRIPLET * T
 
 
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "force_wave_si512k_%s_traffic.txt")
+
+
+def traffic_of(sched, tname, n):
+    """HBM bytes per launch of the force kernel from the committed counter
+    summary, or None when there is none for this kernel and launch shape or
+    the kernel's sources have changed since it was taken."""
+    from paper_1607_02904_amd import profsum
+    path = TRAFFIC_SUMMARY % tname
+    if sched["kernel"] != 2 or not os.path.exists(path):
+        return None
+    s = profsum.read_summary(path)
+    grid = 64 * ((n + sched["atoms"] - 1) // sched["atoms"])
+    if s.get("kernel_sources_sha256") != profsum.kernel_hash() or int(s.get("grid", -1)) != grid:
+        return None
+    return float(s["traffic_bytes_per_launch"])
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -129,14 +147,19 @@ def main():
         model.sync()
         reb = model.rebuilds() - r0
         tr = trace[:args.steps].cpu().numpy()
-        return el, reb, tr, xd
+        # force-kernel duration: HIP events on the library's stream around every
+        # force launch of K further steps of the same trajectory (launched one
+        # by one; the timed region above replays the captured step)
+        _, fus = model.md_run_timed(xd, v, f, td, box, dt, args.steps, skin, precision, trace=trace)
+        torch.cuda.synchronize()
+        return el, reb, tr, fus
 
     print("bench: MD fp64", file=sys.stderr, flush=True)
-    el64, reb64, tr64, _ = run_md(FP64)
+    el64, reb64, tr64, f64us = run_md(FP64)
     print("bench: MD mixed", file=sys.stderr, flush=True)
-    elmx, rebmx, trmx, xfin = run_md(MIXED)
+    elmx, rebmx, trmx, fmxus = run_md(MIXED)
 
-    # force-kernel duration (HIP events around the kernel launches alone)
+    # back-to-back launches of the force kernel alone on the start configuration
     model.build_nlist(x0, td, box, skin)
     sched = model.schedules()
     k64 = model.profile_forward(x0, td, box, FP64, reps=20)
@@ -144,10 +167,14 @@ def main():
     L, P, T = count_work(x, t, box, tab, 3.2 + skin, 3.2)
     fl = flops_of(L, P, T)
 
-    def roof(us, peak):
+    def roof(us, us_b2b, peak, sch, tname):
         ach = fl / (us * 1e-6)
         return {"bound": "alu", "achieved": ach / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
-                "frac": ach / peak, "traffic": None, "kernel_us": us,
+                "frac": ach / peak, "traffic": traffic_of(sch, tname, n),
+                "kernel": "k_force_wave<%s>" % tname if sch["kernel"] == 2 else "k_force<%s>" % tname,
+                "kernel_us": us, "kernel_us_timing": "HIP events around each force launch of %d MD "
+                                                     "steps" % args.steps,
+                "kernel_us_back_to_back": us_b2b,
                 "flops_per_launch": fl, "units": {"entries": L, "pairs": P, "triplets": T}}
 
     value = n * args.steps / elmx
@@ -167,11 +194,12 @@ def main():
         "config": {"workload": "Si diamond 40^3 cells = %d atoms, Si(B), skin 0.5 A, "
                                "velocity Verlet dt 1 fs, mixed precision" % n,
                    "atoms": n, "skin": skin, "dt_fs": 1.0, "precision": "mixed"},
-        "roofline": roof(kmx, FP32_PEAK),
+        "roofline": roof(fmxus, kmx, FP32_PEAK, sched["mixed"], "float"),
         "fp64": {"value": n * args.steps / el64, "unit": "atom-steps/s",
                  "ms_per_step": 1000.0 * el64 / args.steps, "rebuilds": reb64,
-                 "schedule": sched["fp64"], "roofline": roof(k64, FP64_PEAK)},
-        "mixed": {"rebuilds": rebmx, "kernel_us": kmx, "schedule": sched["mixed"],
+                 "schedule": sched["fp64"], "roofline": roof(f64us, k64, FP64_PEAK, sched["fp64"],
+                                                              "double")},
+        "mixed": {"rebuilds": rebmx, "schedule": sched["mixed"],
                   "energy_drift_per_atom": float((trmx[-1] - trmx[0]) / n),
                   "fp64_vs_mixed_energy_rel": float(abs(trmx[-1] - tr64[-1]) / abs(tr64[-1]))},
     }

@@ -162,6 +162,14 @@ ters_status ters_backward(ters_ctx *ctx, int32_t n, const double *x, const int32
 ters_status ters_md_run(ters_ctx *ctx, int32_t n, double *x, double *v, double *f,
                         const int32_t *type, const double *box, double dt_ps, int32_t nsteps,
                         double skin, int precision, double *energy_trace, int use_graph);
+/* The same steps as ters_md_run, launched one by one (no graph), with a pair
+ * of HIP events recorded on the context's stream around every force-kernel
+ * launch.  force_us (host, required) gets the average force-kernel duration
+ * in microseconds over the nsteps steps (synchronises).  For measurement. */
+ters_status ters_md_run_timed(ters_ctx *ctx, int32_t n, double *x, double *v, double *f,
+                              const int32_t *type, const double *box, double dt_ps,
+                              int32_t nsteps, double skin, int precision, double *energy_trace,
+                              double *force_us);
 /* Number of list rebuilds done by ters_md_run calls so far (synchronises). */
 ters_status ters_md_rebuilds(ters_ctx *ctx, int64_t *out);
 

@@ -277,8 +277,8 @@ std::vector<const void *> graph_key(const ters_ctx *c, const NList &nl) {
 // Force-kernel dispatch: workgroup schedule (kern 1, atoms per workgroup) or
 // wavefront schedule (kern 2, atoms per wavefront).  Returns the number of
 // per-workgroup partial records written (single-system mode).
-int kernel_blocks(int kern, int n, int A) {
-  return kern == 2 ? wave_blocks(n, A) : forward_blocks(n, (A > 0 && A <= 64) ? A : 64);
+int kernel_blocks(int kern, int n, int A, bool pg = false) {
+  return kern == 2 ? wave_blocks(n, A, pg) : forward_blocks(n, (A > 0 && A <= 64) ? A : 64);
 }
 void launch_fwd(int kern, const FwdArgs &a, int precision, int A, hipStream_t s) {
   if (kern == 2) {
@@ -293,8 +293,8 @@ void launch_adj(int kern, const FwdArgs &a, int precision, int A, hipStream_t s)
   else launch_adjoint(a, precision, 0, s);
 }
 
-int ctx_blocks(const ters_ctx *c, int precision, int n) {
-  return kernel_blocks(c->kern[precision], n, c->A[precision]);
+int ctx_blocks(const ters_ctx *c, int precision, int n, bool pg = false) {
+  return kernel_blocks(c->kern[precision], n, c->A[precision], pg);
 }
 
 // owner-gather buffers for n atoms with the list's capacity
@@ -309,7 +309,7 @@ void ensure_gather(DevBuf &fslot, DevBuf &fown, const NList &nl) {
 int run_forward(ters_ctx *c, const FwdArgs &a0, int precision, hipStream_t s,
                 bool do_gather = true) {
   FwdArgs a = a0;
-  const int nb = ctx_blocks(c, precision, a.n);
+  const int nb = ctx_blocks(c, precision, a.n, (a.flags & TERS_PARAM_GRAD) && a.pgrad);
   c->partials.ensure(sizeof(double) * 8 * (size_t)std::max(nb, 1));
   a.partials = c->partials.as<double>();
   a.err = c->errw.as<uint32_t>();
@@ -690,9 +690,14 @@ ters_status ters_profile_forward(ters_ctx *c, int32_t n, const double *x, const 
   });
 }
 
-ters_status ters_md_run(ters_ctx *c, int32_t n, double *x, double *v, double *f,
+namespace {
+
+// nsteps velocity-Verlet steps; with force_us set the steps are launched
+// eagerly and every force-kernel launch is bracketed by HIP events
+ters_status md_run_impl(ters_ctx *c, int32_t n, double *x, double *v, double *f,
                         const int32_t *type, const double *box, double dt, int32_t nsteps,
-                        double skin, int precision, double *trace, int use_graph) {
+                        double skin, int precision, double *trace, int use_graph,
+                        double *force_us) {
   if (!c) return TERS_ERR_INVALID_ARG;
   return guard(c, [&]() {
     require(precision == TERS_FP64 || precision == TERS_MIXED, TERS_ERR_INVALID_ARG, "bad precision");
@@ -708,14 +713,21 @@ ters_status ters_md_run(ters_ctx *c, int32_t n, double *x, double *v, double *f,
     // one step: kick + drift + zero F + rebuild test | conditional rebuild |
     // forces | energy (trace) | kick + clear the flag
     const bool gather = c->gather != 0;
-    auto step = [&](hipStream_t s) {
+    std::vector<hipEvent_t> ev;
+    if (force_us) {
+      ev.resize(2 * (size_t)nsteps, nullptr);
+      for (hipEvent_t &e : ev) TERS_HIP_TRY(hipEventCreate(&e));
+    }
+    auto step = [&](hipStream_t s, int k) {
       int32_t *flag = c->flag.as<int32_t>();
       launch_vv_first(n, x, v, f, type, c->mass.as<double>(), dt, c->nl, flag, gather ? 0 : 1, s);
       nlist_build(c->nl, x, flag, c->errw.as<uint32_t>(), s, c->rebuilds.as<int64_t>());
       FwdArgs a = base_args(c, c->nl, precision, n, x, type);
       a.flags = TERS_FORCES | TERS_ENERGY | TERS_ACCUMULATE;  // scatter: F was zeroed by the kick
       a.forces = f;
+      if (force_us) TERS_HIP_TRY(hipEventRecord(ev[2 * k], s));
       run_forward(c, a, precision, s, /*do_gather=*/false);
+      if (force_us) TERS_HIP_TRY(hipEventRecord(ev[2 * k + 1], s));
       if (trace)
         launch_reduce_partials(c->partials.as<double>(), nb, 8, c->escratch.as<double>(), nullptr,
                                0, s, trace, c->step.as<int32_t>());
@@ -727,8 +739,19 @@ ters_status ters_md_run(ters_ctx *c, int32_t n, double *x, double *v, double *f,
     };
     launch_fill_i32(c->step.as<int32_t>(), 0, 1, nullptr, c->stream);
     launch_fill_i32(c->flag.as<int32_t>(), 0, 1, nullptr, c->stream);
-    if (!use_graph) {
-      for (int s = 0; s < nsteps; ++s) step(c->stream);
+    if (!use_graph || force_us) {
+      for (int s = 0; s < nsteps; ++s) step(c->stream, s);
+      if (force_us) {
+        double tot = 0.0;
+        for (int s = 0; s < nsteps; ++s) {
+          TERS_HIP_TRY(hipEventSynchronize(ev[2 * s + 1]));
+          float ms = 0.f;
+          TERS_HIP_TRY(hipEventElapsedTime(&ms, ev[2 * s], ev[2 * s + 1]));
+          tot += ms;
+        }
+        for (hipEvent_t e : ev) hipEventDestroy(e);
+        *force_us = nsteps > 0 ? 1000.0 * tot / nsteps : 0.0;
+      }
     } else if (nsteps > 0) {
       std::vector<const void *> key = graph_key(c, c->nl);
       const void *extra[] = {x, v, f, type, trace, bits(dt), (const void *)(intptr_t)n,
@@ -745,7 +768,7 @@ ters_status ters_md_run(ters_ctx *c, int32_t n, double *x, double *v, double *f,
         sync(c);
         hipGraph_t g;
         TERS_HIP_TRY(hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal));
-        step(c->capture_stream);
+        step(c->capture_stream, 0);
         TERS_HIP_TRY(hipStreamEndCapture(c->capture_stream, &g));
         TERS_HIP_TRY(hipGraphInstantiate(&c->md_exec, g, nullptr, nullptr, 0));
         TERS_HIP_TRY(hipGraphDestroy(g));
@@ -755,6 +778,22 @@ ters_status ters_md_run(ters_ctx *c, int32_t n, double *x, double *v, double *f,
     }
     return TERS_OK;
   });
+}
+
+}  // namespace
+
+ters_status ters_md_run(ters_ctx *c, int32_t n, double *x, double *v, double *f,
+                        const int32_t *type, const double *box, double dt, int32_t nsteps,
+                        double skin, int precision, double *trace, int use_graph) {
+  return md_run_impl(c, n, x, v, f, type, box, dt, nsteps, skin, precision, trace, use_graph,
+                     nullptr);
+}
+
+ters_status ters_md_run_timed(ters_ctx *c, int32_t n, double *x, double *v, double *f,
+                              const int32_t *type, const double *box, double dt, int32_t nsteps,
+                              double skin, int precision, double *trace, double *force_us) {
+  if (!force_us) return TERS_ERR_INVALID_ARG;
+  return md_run_impl(c, n, x, v, f, type, box, dt, nsteps, skin, precision, trace, 0, force_us);
 }
 
 ters_status ters_md_rebuilds(ters_ctx *c, int64_t *out) {

@@ -68,7 +68,7 @@ __global__ __launch_bounds__(BS) void k_force(FwdArgs a, int A) {
   const int tid = threadIdx.x;
   const int lane = lane_id();
   const int nt = a.ntypes;
-  const int64_t first = (int64_t)blockIdx.x * A;
+  const int64_t first = (int64_t)xcd_block(blockIdx.x, gridDim.x) * A;
   const int na = (int)min((int64_t)A, (int64_t)a.n - first);
   if (na <= 0) return;
 

@@ -24,8 +24,20 @@ namespace ters {
 namespace {
 
 constexpr int kNMax = 32;  // most in-cutoff neighbours of one atom
-constexpr int kWPB = 4;    // wavefronts per workgroup
 constexpr int kAMax = 32;  // most atoms per wavefront
+
+// Wavefronts per workgroup.  One: the wavefronts share nothing, so each starts
+// and retires on its own instead of holding its workgroup's registers until
+// the slowest of several has finished.  The parameter-gradient kernels keep
+// four, so that their LDS gradient table is flushed with a quarter of the
+// atomics.
+template <bool PG> constexpr int waves_per_group() { return PG ? 4 : 1; }
+
+// Register budget of the forward kernels: three wavefronts per SIMD for FP64
+// (at most 168 VGPRs), four for FP32 (128); the others take what they need.
+template <class T, bool PG> struct WavesPerEu { static constexpr int value = 1; };
+template <> struct WavesPerEu<double, false> { static constexpr int value = 3; };
+template <> struct WavesPerEu<float, false> { static constexpr int value = 4; };
 
 // --- cross-lane reads (ds_bpermute); every lane of the wave must take part --
 DEV int lane_read(int v, int src) { return __builtin_amdgcn_ds_bpermute(src << 2, v); }
@@ -49,7 +61,9 @@ DEV void wave_sync() {
 }
 
 template <class T, bool NT1, bool PG>
-__global__ __launch_bounds__(kWPB * kWave) void k_force_wave(FwdArgs a, int A) {
+__global__ __launch_bounds__(waves_per_group<PG>() * kWave)
+__attribute__((amdgpu_waves_per_eu(WavesPerEu<T, PG>::value))) void k_force_wave(FwdArgs a, int A) {
+  constexpr int kWPB = waves_per_group<PG>();
   using B = base_t<T>;
   using KP = KParam<B>;
   using AT = acc_t<T>;
@@ -59,7 +73,7 @@ __global__ __launch_bounds__(kWPB * kWave) void k_force_wave(FwdArgs a, int A) {
   // per-wavefront scratch (no sharing between wavefronts)
   __shared__ int s_stage[kWPB][kAMax * kNMax];
   __shared__ unsigned char s_slot[kWPB][kAMax * kNMax];  // list slot of each staged neighbour
-  __shared__ int s_cnt[kWPB][kAMax];
+  __shared__ unsigned short s_map[kWPB][kWave];  // filter window: (atom << 8) | slot
   __shared__ unsigned char s_pa[kWPB][kWave], s_pq[kWPB][kWave];
   __shared__ KP s_kp[NT1 ? 1 : NTL];
   __shared__ double s_g[PG && !NT1 ? NTL * kNField : 1];
@@ -82,7 +96,7 @@ __global__ __launch_bounds__(kWPB * kWave) void k_force_wave(FwdArgs a, int A) {
   const bool grad_in_lds = !NT1 && PG && nt * nt * nt <= NTL;
   if (grad_in_lds)
     for (int e = tid; e < NTL * kNField; e += kWPB * kWave) s_g[e] = 0.0;
-  __syncthreads();  // the only workgroup barrier before the final reductions
+  if (!NT1) __syncthreads();  // the only workgroup barrier before the final reductions
 
   auto param = [&](int ti, int tj, int tk) -> const KP & {
     return NT1 ? P[0] : P[(ti * nt + tj) * nt + tk];
@@ -105,7 +119,7 @@ __global__ __launch_bounds__(kWPB * kWave) void k_force_wave(FwdArgs a, int A) {
   const bool want_w = !DUAL && (flags & TERS_VIRIAL);
   const bool want_ea = !DUAL && (flags & TERS_PER_ATOM_E) && a.e_atom;
 
-  const int64_t first = ((int64_t)blockIdx.x * kWPB + w) * A;
+  const int64_t first = ((int64_t)xcd_block(blockIdx.x, gridDim.x) * kWPB + w) * A;
   const int na = (int)max((int64_t)0, min((int64_t)A, (int64_t)a.n - first));
   // chunk atoms: lane `lane` < na holds atom `lane` of the chunk (A <= 64)
   int my_i = 0, my_t = 0, my_lc = 0, my_cf = 0;
@@ -117,56 +131,70 @@ __global__ __launch_bounds__(kWPB * kWave) void k_force_wave(FwdArgs a, int A) {
   }
 
   // ---- filter: compact the in-cutoff neighbours of every atom of the chunk --
-  if (na > 0) {
-    const int cap = a.cap;
-    const int lsh = __ffs(cap) - 1;
-    const uint64_t segbits = cap == 64 ? ~0ull : ((1ull << cap) - 1ull);
-    const int total = na * cap;
-    for (int base = 0; base < total; base += kWave) {
-      const int t = base + lane;
-      const int at = t >> lsh;
-      const int s = t & (cap - 1);
-      const int src = at < kWave ? at : 0;
-      const int i = lane_read(my_i, src), ti = lane_read(my_t, src);
-      const int lc = lane_read(my_lc, src), cf = lane_read(my_cf, src);
-      bool pass = false;
-      int j = 0;
-      if (at < na && s < lc) {
-        j = a.list[(int64_t)i * cap + s];
-        const ConfDesc &c = a.conf[cf];
-        double dx = a.x[3 * j] - a.x[3 * i];
-        double dy = a.x[3 * j + 1] - a.x[3 * i + 1];
-        double dz = a.x[3 * j + 2] - a.x[3 * i + 2];
-        dx -= c.box[0] * rint(dx * c.inv_box[0]);
-        dy -= c.box[1] * rint(dy * c.inv_box[1]);
-        dz -= c.box[2] * rint(dz * c.inv_box[2]);
-        const int tj = NT1 ? 0 : a.type[j];
-        pass = dx * dx + dy * dy + dz * dz < filt2[NT1 ? 0 : ti * nt + tj];
-      }
-      const uint64_t m = __ballot(pass);
-      const uint64_t seg = segbits << (lane & ~(cap - 1));
-      const int pos = __popcll(m & seg & ((1ull << lane) - 1ull));
-      if (pass) {
-        if (pos < kNMax) {
-          s_stage[w][at * kNMax + pos] = j;
-          s_slot[w][at * kNMax + pos] = (unsigned char)s;
-        } else {
-          atomicOr(a.err, kErrTooManyInCutoff);
-        }
-      } else if (a.fslot && at < na && s < lc) {
-        const int r = a.rev[(int64_t)i * cap + s];
-        if (r >= 0) {
-          double *fs = a.fslot + 3 * (int64_t)r;
-          fs[0] = 0.0;
-          fs[1] = 0.0;
-          fs[2] = 0.0;
-        }
-      }
-      if (at < na && s == cap - 1) s_cnt[w][at] = min(__popcll(m & seg), kNMax);
-    }
+  // The chunk's list entries are numbered without the row padding (atom a's
+  // entries follow those of atoms 0..a-1) and visited a wavefront at a time.
+  int my_e = my_lc;  // exclusive prefix of the list counts, below
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int u = __shfl_up(my_e, o, kWave);
+    if (lane >= o) my_e += u;
   }
-  wave_sync();
-  const int my_n = lane < na ? s_cnt[w][lane] : 0;
+  const int total = __shfl(my_e, kWave - 1, kWave);
+  my_e -= my_lc;
+  int my_cnt = 0;  // in-cutoff neighbours found so far (atom lanes)
+  for (int base = 0; base < total; base += kWave) {
+    // entry of this window -> (atom, slot), written by the atoms' lanes
+    const int lo = max(my_e, base), hi = min(my_e + my_lc, base + kWave);
+    for (int t = lo; t < hi; ++t) s_map[w][t - base] = (unsigned short)((lane << 8) | (t - my_e));
+    wave_sync();
+    const bool valid = base + lane < total;
+    const int code = valid ? s_map[w][lane] : 0;
+    const int at = code >> 8, s = code & 0xff;
+    const int i = lane_read(my_i, at), ti = lane_read(my_t, at), cf = lane_read(my_cf, at);
+    const int e_at = lane_read(my_e, at), c_at = lane_read(my_cnt, at);
+    bool pass = false;
+    int j = 0;
+    if (valid) {
+      j = a.list[(int64_t)i * a.cap + s];
+      const ConfDesc &c = a.conf[cf];
+      double dx = a.x[3 * j] - a.x[3 * i];
+      double dy = a.x[3 * j + 1] - a.x[3 * i + 1];
+      double dz = a.x[3 * j + 2] - a.x[3 * i + 2];
+      dx -= c.box[0] * rint(dx * c.inv_box[0]);
+      dy -= c.box[1] * rint(dy * c.inv_box[1]);
+      dz -= c.box[2] * rint(dz * c.inv_box[2]);
+      const int tj = NT1 ? 0 : a.type[j];
+      pass = dx * dx + dy * dy + dz * dz < filt2[NT1 ? 0 : ti * nt + tj];
+    }
+    const uint64_t m = __ballot(pass);
+    // passes of the same atom in lower lanes of this window (e_at <= base + lane)
+    const int lo_lane = max(e_at - base, 0);
+    const uint64_t below = ((1ull << lane) - 1ull) & ~((1ull << lo_lane) - 1ull);
+    const int pos = c_at + __popcll(m & below);
+    if (pass) {
+      if (pos < kNMax) {
+        s_stage[w][at * kNMax + pos] = j;
+        s_slot[w][at * kNMax + pos] = (unsigned char)s;
+      } else {
+        atomicOr(a.err, kErrTooManyInCutoff);
+      }
+    } else if (a.fslot && valid) {
+      const int r = a.rev[(int64_t)i * a.cap + s];
+      if (r >= 0) {
+        double *fs = a.fslot + 3 * (int64_t)r;
+        fs[0] = 0.0;
+        fs[1] = 0.0;
+        fs[2] = 0.0;
+      }
+    }
+    if (hi > lo) {
+      const int l0 = lo - base, l1 = hi - base;  // this atom's lanes [l0, l1)
+      const uint64_t mine = (l1 == kWave ? ~0ull : (1ull << l1) - 1ull) & ~((1ull << l0) - 1ull);
+      my_cnt += __popcll(m & mine);
+    }
+    wave_sync();  // s_map is rewritten by the next window
+  }
+  const int my_n = lane < na ? min(my_cnt, kNMax) : 0;
   int incl = my_n;  // inclusive prefix of pair counts over the chunk's atoms
 #pragma unroll
   for (int o = 1; o < kWave; o <<= 1) {
@@ -440,16 +468,24 @@ __global__ __launch_bounds__(kWPB * kWave) void k_force_wave(FwdArgs a, int A) {
   // ---- workgroup reductions ------------------------------------------------------
   if (!DUAL && a.partials && !a.conf_of) {
     double vals[7] = {eacc, wacc[0], wacc[1], wacc[2], wacc[3], wacc[4], wacc[5]};
+    if (kWPB == 1) {
 #pragma unroll
-    for (int k = 0; k < 7; ++k) {
-      double sum = wave_sum(vals[k]);
-      if (lane == 0) s_red[w][k] = sum;
-    }
-    __syncthreads();
-    if (tid < 7) {
-      double sum = 0.0;
-      for (int q2 = 0; q2 < kWPB; ++q2) sum += s_red[q2][tid];
-      a.partials[(int64_t)blockIdx.x * 8 + tid] = sum;
+      for (int k = 0; k < 7; ++k) {
+        const double sum = wave_sum(vals[k]);  // every lane holds the sum
+        if (lane == k) a.partials[(int64_t)blockIdx.x * 8 + k] = sum;
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < 7; ++k) {
+        double sum = wave_sum(vals[k]);
+        if (lane == 0) s_red[w][k] = sum;
+      }
+      __syncthreads();
+      if (tid < 7) {
+        double sum = 0.0;
+        for (int q2 = 0; q2 < kWPB; ++q2) sum += s_red[q2][tid];
+        a.partials[(int64_t)blockIdx.x * 8 + tid] = sum;
+      }
     }
   }
   if (PG) {
@@ -469,6 +505,7 @@ __global__ __launch_bounds__(kWPB * kWave) void k_force_wave(FwdArgs a, int A) {
 
 template <class T, bool PG>
 void launch_wave_t(const FwdArgs &a, int A, hipStream_t s) {
+  constexpr int kWPB = waves_per_group<PG>();
   if (A <= 0 || A > kAMax) A = 16;
   const int64_t per_block = (int64_t)kWPB * A;
   const int nb = (int)((a.n + per_block - 1) / per_block);
@@ -481,9 +518,10 @@ void launch_wave_t(const FwdArgs &a, int A, hipStream_t s) {
 
 }  // namespace
 
-int wave_blocks(int n, int A) {
+int wave_blocks(int n, int A, bool pg) {
   if (A <= 0 || A > kAMax) A = 16;
-  return (int)((n + (int64_t)kWPB * A - 1) / ((int64_t)kWPB * A));
+  const int64_t per_block = (int64_t)(pg ? waves_per_group<true>() : waves_per_group<false>()) * A;
+  return (int)((n + per_block - 1) / per_block);
 }
 
 void launch_forward_wave(const FwdArgs &a, int precision, int A, hipStream_t s) {

@@ -239,12 +239,13 @@ __global__ __launch_bounds__(kBS) void k_build(int n, const double *__restrict__
   if (skip(cond)) return;
   if (blockIdx.x == 0 && threadIdx.x == 0 && rebuilds) *rebuilds += 1;
   int worst = 0;
-  // grid-stride over atoms in cell order; every lane runs the same number of
-  // iterations so the wave reduction below sees all lanes
+  // grid-stride over atoms in cell order (each XCD takes one contiguous range
+  // per pass, so neighbouring cells share its L2); every lane runs the same
+  // number of iterations so the wave reduction below sees all lanes
   const int stride = gridDim.x * blockDim.x;
   const int iters = (n + stride - 1) / stride;
   for (int it = 0; it < iters; ++it) {
-  const int t = it * stride + blockIdx.x * blockDim.x + threadIdx.x;
+  const int t = it * stride + xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   int cnt = 0;
   if (t < n) {
     int i = order[t];
@@ -308,7 +309,8 @@ __global__ void k_reverse(int n, int cap, const int32_t *__restrict__ count,
                           const int32_t *__restrict__ list, int32_t *__restrict__ rev,
                           const int32_t *cond, uint32_t *err) {
   if (skip(cond)) return;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+  for (int i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x; i < n;
+       i += gridDim.x * blockDim.x) {
   const int ci = min(count[i], cap);
   for (int s = 0; s < ci; ++s) {
     const int j = list[(int64_t)i * cap + s];

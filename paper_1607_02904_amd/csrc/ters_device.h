@@ -156,6 +156,17 @@ DEV double wave_sum(double v) {
 }
 DEV Dual<double> wave_sum(Dual<double> v) { return {wave_sum(v.v), wave_sum(v.d)}; }
 
+// Workgroups of a launch are dealt to the GPU's eight XCDs in turn
+// (workgroup b runs on XCD b mod 8), and each XCD has its own L2.  This
+// bijection of [0, G) gives every XCD one contiguous range of logical block
+// ids instead, so spatially close atoms (cell order) and the neighbour data
+// they share stay in one L2.
+DEV int xcd_block(int b, int G) {
+  constexpr int kXcd = 8;
+  const int x = b % kXcd, q = G / kXcd, r = G % kXcd;
+  return x * q + min(x, r) + b / kXcd;
+}
+
 // hardware FP64 atomic add to global memory (global_atomic_add_f64)
 DEV void atomic_add(double *p, double v) { unsafeAtomicAdd(p, v); }
 

@@ -148,7 +148,7 @@ int forward_blocks(int n, int atoms_per_block);
 // wavefront schedule: atoms per wavefront (<= 32), 4 wavefronts per workgroup
 void launch_forward_wave(const FwdArgs &a, int precision, int atoms_per_wave, hipStream_t s);
 void launch_adjoint_wave(const FwdArgs &a, int precision, int atoms_per_wave, hipStream_t s);
-int wave_blocks(int n, int atoms_per_wave);
+int wave_blocks(int n, int atoms_per_wave, bool param_grad);
 void launch_reduce_partials(const double *partials, int nblocks, int stride, double *energy,
                             double *virial, int accumulate, hipStream_t s,
                             double *trace = nullptr, int32_t *step = nullptr);

@@ -1,0 +1,120 @@
+"""Summaries of rocprofv3 output for the force kernel.
+
+Two reports, both plain text:
+
+* ``stats``: the rows of a ``--kernel-trace --stats`` kernel_stats.csv for the
+  kernels whose names contain the given filters;
+* ``traffic``: HBM bytes per launch of one kernel from two ``--pmc`` runs
+  (``FETCH_SIZE``, then ``WRITE_SIZE``, KiB per dispatch), each scaled by what
+  the same counter reads for a plain device copy of known size in the same
+  run, with the hash of the kernel's sources so that a reader can tell whether
+  the figure still applies to the kernel as built.
+
+    python -m paper_1607_02904_amd.profsum stats STATS_CSV [FILTER ...]
+    python -m paper_1607_02904_amd.profsum traffic FETCH_CSV WRITE_CSV \\
+        --kernel NAME_PART --grid GRID --copy-bytes BYTES
+
+The copy kernel is the dispatch whose name contains ``copyBuffer`` and whose
+``FETCH_SIZE`` is largest.
+"""
+import argparse
+import csv
+import hashlib
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+# sources of the wavefront force kernel (the dominant kernel of a step)
+KERNEL_SOURCES = ("forward_wave.hip", "ters_math.h", "ters_device.h", "ters_internal.h")
+
+
+def kernel_hash(sources=KERNEL_SOURCES):
+    """SHA-256 over the force kernel's source files, in a fixed order."""
+    h = hashlib.sha256()
+    for name in sources:
+        with open(os.path.join(HERE, "csrc", name), "rb") as f:
+            h.update(name.encode())
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def stats(path, filters):
+    lines = []
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            if filters and not any(flt in r["Name"] for flt in filters):
+                continue
+            lines.append("%-90s calls %6s  avg_us %9.2f  min_us %9.2f  max_us %9.2f  total_%% %6s"
+                         % (r["Name"][:90], r["Calls"], float(r["AverageNs"]) / 1e3,
+                            float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3, r["Percentage"]))
+    return lines
+
+
+def _per_dispatch(path, counter):
+    """{dispatch id: (kernel name, grid size, summed counter value)}"""
+    out = {}
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            if r["Counter_Name"] != counter:
+                continue
+            d = int(r["Dispatch_Id"])
+            name, grid, v = out.get(d, (r["Kernel_Name"], int(r["Grid_Size"]), 0.0))
+            out[d] = (name, grid, v + float(r["Counter_Value"]))
+    return out
+
+
+def traffic(fetch_csv, write_csv, kernel, grid, copy_bytes):
+    res = {}
+    for key, path, counter in (("fetch", fetch_csv, "FETCH_SIZE"), ("write", write_csv, "WRITE_SIZE")):
+        disp = _per_dispatch(path, counter)
+        vals = [v for (name, g, v) in disp.values() if kernel in name and g == grid]
+        copies = [v for (name, g, v) in disp.values() if "copyBuffer" in name]
+        if not vals or not copies:
+            raise SystemExit("no %s dispatches of %r (grid %d) or no copy kernel in %s"
+                             % (counter, kernel, grid, path))
+        copy_kib = max(copies)
+        res[key + "_kib_per_launch"] = sum(vals) / len(vals)
+        res[key + "_dispatches"] = len(vals)
+        res["copy_" + key + "_kib"] = copy_kib
+        res[key + "_scale"] = copy_bytes / 1024.0 / copy_kib
+    res["traffic_bytes_per_launch"] = 1024.0 * (res["fetch_kib_per_launch"] * res["fetch_scale"]
+                                                + res["write_kib_per_launch"] * res["write_scale"])
+    return res
+
+
+def read_summary(path):
+    """key: value lines of a summary file (values as strings)."""
+    out = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                out[k.strip()] = v.strip()
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("csv")
+    s.add_argument("filters", nargs="*")
+    t = sub.add_parser("traffic")
+    t.add_argument("fetch_csv")
+    t.add_argument("write_csv")
+    t.add_argument("--kernel", required=True)
+    t.add_argument("--grid", type=int, required=True)
+    t.add_argument("--copy-bytes", type=float, required=True)
+    a = ap.parse_args()
+    if a.cmd == "stats":
+        print("\n".join(stats(a.csv, a.filters)))
+    else:
+        r = traffic(a.fetch_csv, a.write_csv, a.kernel, a.grid, a.copy_bytes)
+        print("kernel: %s" % a.kernel)
+        print("grid: %d" % a.grid)
+        print("kernel_sources_sha256: %s" % kernel_hash())
+        for k in sorted(r):
+            print("%s: %.6g" % (k, r[k]))
+
+
+if __name__ == "__main__":
+    main()

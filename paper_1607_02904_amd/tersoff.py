@@ -29,7 +29,8 @@ STATUS = {0: "TERS_OK", 1: "TERS_ERR_INVALID_ARG", 2: "TERS_ERR_BOX_TOO_SMALL",
 
 EXPORTS = ("ters_create", "ters_destroy", "ters_set_stream", "ters_sync", "ters_last_error",
            "ters_set_params", "ters_build_nlist", "ters_needs_rebuild", "ters_nlist_stats",
-           "ters_compute", "ters_compute_ex", "ters_backward", "ters_md_run", "ters_md_rebuilds",
+           "ters_compute", "ters_compute_ex", "ters_backward", "ters_md_run", "ters_md_run_timed",
+           "ters_md_rebuilds",
            "ters_batch_plan", "ters_batch_run", "ters_plan_destroy", "ters_plan_schedule",
            "ters_set_schedule", "ters_get_schedule", "ters_set_force_mode", "ters_autotune",
            "ters_profile_forward",
@@ -70,6 +71,7 @@ def load_library(path=LIB_PATH):
         "ters_compute_ex": [P, I32, P, P, P, ctypes.c_int, U32, P, P, P, P, P],
         "ters_backward": [P, I32, P, P, P, ctypes.c_int, D, P, P, P],
         "ters_md_run": [P, I32, P, P, P, P, P, D, I32, D, ctypes.c_int, P, ctypes.c_int],
+        "ters_md_run_timed": [P, I32, P, P, P, P, P, D, I32, D, ctypes.c_int, P, P],
         "ters_md_rebuilds": [P, P],
         "ters_batch_plan": [P, I32, P, P, ctypes.c_int, U32, PP],
         "ters_batch_run": [P, P, P, P, P, P, P, P, P, P],
@@ -284,6 +286,19 @@ class Tersoff:
                                       float(dt), int(nsteps), float(skin), precision, _ptr(trace),
                                       1 if use_graph else 0))
         return trace
+
+    def md_run_timed(self, x, v, f, types, box, dt, nsteps, skin, precision=FP64, trace=None):
+        """md_run launched step by step with HIP events around every force-kernel
+        launch; returns (trace, average force-kernel microseconds)."""
+        self._bind_stream()
+        if trace is None:
+            trace = torch.empty(max(nsteps, 1), dtype=torch.float64, device=x.device)
+        b, bp = _hostbuf(box, np.float64)
+        us = np.zeros(1, dtype=np.float64)
+        self._chk(self._L.ters_md_run_timed(self._h, x.shape[0], _ptr(x), _ptr(v), _ptr(f), _ptr(types),
+                                            bp, float(dt), int(nsteps), float(skin), precision,
+                                            _ptr(trace), us.ctypes.data_as(ctypes.c_void_p)))
+        return trace, float(us[0])
 
     def sync(self):
         self._chk(self._L.ters_sync(self._h))
