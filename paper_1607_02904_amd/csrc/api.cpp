@@ -174,6 +174,7 @@ void nl_setup(NList &nl, int nconf, const int32_t *natoms, const double *boxes, 
     nl.conf_h[c] = d;
   }
   if (cells > (int64_t)1 << 30) fail(TERS_ERR_UNSUPPORTED, "too many cells");
+  if (atoms > ((int64_t)1 << 24)) fail(TERS_ERR_UNSUPPORTED, "more than 2^24 atoms");
   nl.n = (int32_t)atoms;
   nl.ncell = cells;
   if (nl.cap == 0) nl.cap = 16;
@@ -195,6 +196,10 @@ void nl_setup(NList &nl, int nconf, const int32_t *natoms, const double *boxes, 
   nl.cell_start.ensure(sizeof(int32_t) * (cells + 1));
   nl.scan_tmp.ensure(sizeof(int32_t) * ((cells + 1) / 1024 + 2));
   nl.xref.ensure(sizeof(double) * 3 * nn);
+  nl.xs.ensure(sizeof(double) * 3 * nn);
+  nl.soff.ensure(sizeof(int32_t) * (nn + 1));
+  nl.loff.ensure(sizeof(int32_t) * nn);
+  nl.bsum.ensure(sizeof(int32_t) * 2 * 4096);
   nl.maxcount.ensure(sizeof(int32_t));
   nl.rev.ensure(sizeof(int32_t) * nn * nl.cap);
 }
@@ -271,7 +276,8 @@ std::vector<const void *> graph_key(const ters_ctx *c, const NList &nl) {
           bits(nl.skin), c->kp64.p, c->kp32.p, c->filt2.p, (const void *)(intptr_t)c->ntypes,
           (const void *)(intptr_t)c->cut_consistent, (const void *)(intptr_t)c->kmax,
           c->partials.p, c->errw.p, c->flag.p, c->rebuilds.p, c->step.p, c->escratch.p,
-          nl.rev.p, c->fslot.p, c->fown.p, (const void *)(intptr_t)c->gather};
+          nl.rev.p, nl.xs.p, nl.soff.p, nl.loff.p, nl.bsum.p, c->fslot.p, c->fown.p,
+          (const void *)(intptr_t)c->gather};
 }
 
 // Force-kernel dispatch: workgroup schedule (kern 1, atoms per workgroup) or
@@ -316,14 +322,15 @@ int run_forward(ters_ctx *c, const FwdArgs &a0, int precision, hipStream_t s,
   const bool gather = c->gather && a.forces;
   if (gather) {
     ensure_gather(c->fslot, c->fown, c->nl);
-    a.fslot = c->fslot.as<double>();
+    a.fslot = c->fslot.p;
     a.fown = c->fown.as<double>();
   } else if (a.forces && !(a.flags & TERS_ACCUMULATE)) {
     launch_fill_f64(a.forces, 0.0, 3 * (int64_t)a.n, s);
   }
   launch_fwd(c->kern[precision], a, precision, c->A[precision], s);
   if (gather && do_gather)
-    launch_gather(c->nl, a.fslot, a.fown, a.forces, (a.flags & TERS_ACCUMULATE) ? 1 : 0, s);
+    launch_gather(c->nl, a.fslot, precision == TERS_MIXED, a.fown, a.forces,
+                  (a.flags & TERS_ACCUMULATE) ? 1 : 0, s);
   return nb;
 }
 
@@ -377,7 +384,8 @@ ters_status ters_destroy(ters_ctx *c) {
                     &c->rebuilds, &c->step, &c->escratch, &c->fslot, &c->fown, &c->nl.conf,
                     &c->nl.conf_of, &c->nl.count, &c->nl.list, &c->nl.order, &c->nl.cell_of,
                     &c->nl.cell_count, &c->nl.cell_start, &c->nl.scan_tmp, &c->nl.xref,
-                    &c->nl.maxcount, &c->nl.rev};
+                    &c->nl.maxcount, &c->nl.rev, &c->nl.xs, &c->nl.soff,
+                    &c->nl.loff, &c->nl.bsum};
   for (DevBuf *b : bufs) b->release();
   delete c;
   return TERS_OK;
@@ -565,13 +573,14 @@ ters_status ters_backward(ters_ctx *c, int32_t n, const double *x, const int32_t
     launch_fill_f64(param_grad, 0.0, (int64_t)nt * nt * nt * kNField, c->stream);
     if (c->gather) {
       ensure_gather(c->fslot, c->fown, c->nl);
-      a.fslot = c->fslot.as<double>();
+      a.fslot = c->fslot.p;
       a.fown = c->fown.as<double>();
     } else {
       launch_fill_f64(x_grad, 0.0, 3 * (int64_t)n, c->stream);
     }
     launch_adj(c->kern[precision], a, precision, c->A[precision], c->stream);
-    if (c->gather) launch_gather(c->nl, a.fslot, a.fown, x_grad, 0, c->stream);
+    if (c->gather)
+      launch_gather(c->nl, a.fslot, precision == TERS_MIXED, a.fown, x_grad, 0, c->stream);
     return TERS_OK;
   });
 }
@@ -663,7 +672,7 @@ ters_status ters_profile_forward(ters_ctx *c, int32_t n, const double *x, const 
     a.forces = f.as<double>();
     if (c->gather) {
       ensure_gather(c->fslot, c->fown, c->nl);
-      a.fslot = c->fslot.as<double>();
+      a.fslot = c->fslot.p;
       a.fown = c->fown.as<double>();
     }
     const int nb = ctx_blocks(c, precision, n);
@@ -732,8 +741,8 @@ ters_status md_run_impl(ters_ctx *c, int32_t n, double *x, double *v, double *f,
         launch_reduce_partials(c->partials.as<double>(), nb, 8, c->escratch.as<double>(), nullptr,
                                0, s, trace, c->step.as<int32_t>());
       if (gather)
-        launch_vv_second_gather(c->nl, v, f, c->fslot.as<double>(), c->fown.as<double>(), type,
-                                c->mass.as<double>(), dt, flag, s);
+        launch_vv_second_gather(c->nl, v, f, c->fslot.p, precision == TERS_MIXED,
+                                c->fown.as<double>(), type, c->mass.as<double>(), dt, flag, s);
       else
         launch_vv_second(n, v, f, type, c->mass.as<double>(), dt, flag, s);
     };
@@ -832,13 +841,13 @@ void batch_enqueue(ters_plan *p, const double *x, const int32_t *type, double *e
   a.err = p->errw.as<uint32_t>();
   launch_fill_f64(p->partials.as<double>(), 0.0, 8 * (int64_t)p->nconf, s);
   if (f && p->gather) {
-    a.fslot = p->fslot.as<double>();
+    a.fslot = p->fslot.p;
     a.fown = p->fown.as<double>();
   } else if (f) {
     launch_fill_f64(f, 0.0, 3 * (int64_t)p->N, s);
   }
   launch_fwd(p->kern, a, p->precision, p->A, s);
-  if (f && p->gather) launch_gather(nl, a.fslot, a.fown, f, 0, s);
+  if (f && p->gather) launch_gather(nl, a.fslot, p->precision == TERS_MIXED, a.fown, f, 0, s);
   if (e || w)
     k_split_partials<<<(p->nconf + 255) / 256, 256, 0, s>>>(p->partials.as<double>(), p->nconf, e, w);
   if (f_bar) {
@@ -854,13 +863,13 @@ void batch_enqueue(ters_plan *p, const double *x, const int32_t *type, double *e
     const int nt = c->ntypes;
     launch_fill_f64(pg, 0.0, (int64_t)nt * nt * nt * kNField, s);
     if (p->gather) {
-      b.fslot = p->fslot.as<double>();
+      b.fslot = p->fslot.p;
       b.fown = p->fown.as<double>();
     } else {
       launch_fill_f64(xg, 0.0, 3 * (int64_t)p->N, s);
     }
     launch_adj(p->kern, b, p->precision, p->A, s);
-    if (p->gather) launch_gather(nl, b.fslot, b.fown, xg, 0, s);
+    if (p->gather) launch_gather(nl, b.fslot, p->precision == TERS_MIXED, b.fown, xg, 0, s);
   }
 }
 
@@ -1005,7 +1014,8 @@ static void plan_release_device(ters_plan *p) {
   DevBuf *bufs[] = {&p->partials, &p->ebuf, &p->errw, &p->fslot, &p->fown, &p->nl.conf,
                     &p->nl.conf_of, &p->nl.count, &p->nl.list, &p->nl.order, &p->nl.cell_of,
                     &p->nl.cell_count, &p->nl.cell_start, &p->nl.scan_tmp, &p->nl.xref,
-                    &p->nl.maxcount, &p->nl.rev};
+                    &p->nl.maxcount, &p->nl.rev, &p->nl.xs, &p->nl.soff,
+                    &p->nl.loff, &p->nl.bsum};
   for (DevBuf *b : bufs) b->release();
   p->ctx = nullptr;
 }

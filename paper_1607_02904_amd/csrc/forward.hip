@@ -155,10 +155,10 @@ __global__ __launch_bounds__(BS) void k_force(FwdArgs a, int A) {
       } else if (a.fslot && at < na && s < s_lcnt[at]) {
         const int r = a.rev[(int64_t)s_atom[at] * cap + s];
         if (r >= 0) {
-          double *fs = a.fslot + 3 * (int64_t)r;
-          fs[0] = 0.0;
-          fs[1] = 0.0;
-          fs[2] = 0.0;
+          B *fs = (B *)a.fslot + 3 * (int64_t)r;  // slots hold the base type
+          fs[0] = B(0);
+          fs[1] = B(0);
+          fs[2] = B(0);
         }
       }
       if (at < na && s == cap - 1) s_cnt[at] = min(__popcll(m & seg), kNMax);
@@ -432,13 +432,20 @@ __global__ __launch_bounds__(BS) void k_force(FwdArgs a, int A) {
         const double o0 = DUAL ? -out_of(f[0], eb) : val(f[0]);
         const double o1 = DUAL ? -out_of(f[1], eb) : val(f[1]);
         const double o2 = DUAL ? -out_of(f[2], eb) : val(f[2]);
+        if (!DUAL && a.fslot) {
+          // i's own force below sums the slot values as stored, so that the
+          // forces of every term cancel exactly in the gathered total
+          set_val(f[0], (double)(B)o0);
+          set_val(f[1], (double)(B)o1);
+          set_val(f[2], (double)(B)o2);
+        }
         if (a.fslot) {
           const int r = a.rev[(int64_t)s_atom[at] * a.cap + s_slot[at * kNMax + m]];
           if (r >= 0) {
-            double *fs = a.fslot + 3 * (int64_t)r;
-            fs[0] = o0;
-            fs[1] = o1;
-            fs[2] = o2;
+            B *fs = (B *)a.fslot + 3 * (int64_t)r;
+            fs[0] = (B)o0;
+            fs[1] = (B)o1;
+            fs[2] = (B)o2;
           }
         } else {
           double *dst = DUAL ? a.xgrad : a.forces;
@@ -470,10 +477,11 @@ __global__ __launch_bounds__(BS) void k_force(FwdArgs a, int A) {
         const double o0 = DUAL ? -out_of(fx, eb) : val(fx);
         const double o1 = DUAL ? -out_of(fy, eb) : val(fy);
         const double o2 = DUAL ? -out_of(fz, eb) : val(fz);
-        if (a.fown) {
-          a.fown[3 * i + 0] = o0;
-          a.fown[3 * i + 1] = o1;
-          a.fown[3 * i + 2] = o2;
+        if (a.fown) {  // indexed by position in cell order
+          double *fo = a.fown + 3 * (first + at);
+          fo[0] = o0;
+          fo[1] = o1;
+          fo[2] = o2;
         } else {
           double *dst = DUAL ? a.xgrad : a.forces;
           atomic_add(&dst[3 * i + 0], o0);
@@ -530,21 +538,44 @@ __global__ __launch_bounds__(BS) void k_force(FwdArgs a, int A) {
 // also stored at trace[*step] and the device step counter advanced (keeps a
 // captured molecular-dynamics step replayable).
 constexpr int kRedBS = 1024;
+template <int NK>
 __global__ __launch_bounds__(kRedBS) void k_reduce_partials(const double *partials, int nblocks,
                                                             int stride, double *energy,
                                                             double *virial, int accumulate,
                                                             double *trace, int32_t *step) {
-  __shared__ double red[kRedBS / kWave];
-  const int k = blockIdx.x;  // 0 = energy, 1..6 virial
-  double s = 0.0;
-  for (int b = threadIdx.x; b < nblocks; b += kRedBS) s += partials[(int64_t)b * stride + k];
-  s = wave_sum(s);
-  if (lane_id() == 0) red[threadIdx.x / kWave] = s;
+  // one workgroup; thread t sums records t, t + 1024, ... (contiguous across
+  // the threads, fetched CH at a time so that the loads overlap), then a fixed
+  // tree over the workgroup: the order of the sum is fixed
+  constexpr int CH = NK == 1 ? 16 : 4;
+  __shared__ double red[kRedBS / kWave][NK];
+  double acc[NK];
+#pragma unroll
+  for (int k = 0; k < NK; ++k) acc[k] = 0.0;
+  for (int b0 = threadIdx.x; b0 < nblocks; b0 += CH * kRedBS) {
+    double v[CH][NK];
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      const int b = b0 + c * kRedBS;
+#pragma unroll
+      for (int k = 0; k < NK; ++k) v[c][k] = b < nblocks ? partials[(int64_t)b * stride + k] : 0.0;
+    }
+#pragma unroll
+    for (int c = 0; c < CH; ++c)
+#pragma unroll
+      for (int k = 0; k < NK; ++k) acc[k] += v[c][k];
+  }
+  const int w = threadIdx.x / kWave;
+#pragma unroll
+  for (int k = 0; k < NK; ++k) {
+    const double v = wave_sum(acc[k]);
+    if (lane_id() == 0) red[w][k] = v;
+  }
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if (threadIdx.x < NK) {
+    const int k = threadIdx.x;
     double tot = 0.0;
-    for (int w = 0; w < kRedBS / kWave; ++w) tot += red[w];
-    double *dst = k == 0 ? energy : (virial ? virial + (k - 1) : nullptr);
+    for (int q = 0; q < kRedBS / kWave; ++q) tot += red[q][k];
+    double *dst = k == 0 ? energy : virial + (k - 1);
     if (dst) *dst = accumulate ? *dst + tot : tot;
     if (k == 0 && trace) {
       trace[*step] = tot;
@@ -598,8 +629,12 @@ void launch_adjoint(const FwdArgs &a, int precision, int A, hipStream_t s) {
 void launch_reduce_partials(const double *partials, int nblocks, int stride, double *energy,
                             double *virial, int accumulate, hipStream_t s, double *trace,
                             int32_t *step) {
-  k_reduce_partials<<<virial ? 7 : 1, kRedBS, 0, s>>>(partials, nblocks, stride, energy, virial,
-                                                      accumulate, trace, step);
+  if (virial)
+    k_reduce_partials<7><<<1, kRedBS, 0, s>>>(partials, nblocks, stride, energy, virial,
+                                              accumulate, trace, step);
+  else
+    k_reduce_partials<1><<<1, kRedBS, 0, s>>>(partials, nblocks, stride, energy, virial,
+                                              accumulate, trace, step);
 }
 
 }  // namespace ters

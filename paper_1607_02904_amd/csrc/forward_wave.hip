@@ -181,10 +181,10 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEu<T, PG>::value))) void k_force_wave
     } else if (a.fslot && valid) {
       const int r = a.rev[(int64_t)i * a.cap + s];
       if (r >= 0) {
-        double *fs = a.fslot + 3 * (int64_t)r;
-        fs[0] = 0.0;
-        fs[1] = 0.0;
-        fs[2] = 0.0;
+        B *fs = (B *)a.fslot + 3 * (int64_t)r;  // slots hold the base type
+        fs[0] = B(0);
+        fs[1] = B(0);
+        fs[2] = B(0);
       }
     }
     if (hi > lo) {
@@ -393,34 +393,38 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEu<T, PG>::value))) void k_force_wave
         for (int k = 0; k < 6; ++k) wacc[k] += wv[k + 1];
       }
     }
-    if (act) {
-      if (want_f) {
-        const double o0 = DUAL ? -out_of(f0, eb) : val(f0);
-        const double o1 = DUAL ? -out_of(f1, eb) : val(f1);
-        const double o2 = DUAL ? -out_of(f2, eb) : val(f2);
-        if (a.fslot) {
-          const int r = a.rev[(int64_t)i * a.cap + s_slot[w][at * kNMax + q]];
-          if (r >= 0) {
-            double *fs = a.fslot + 3 * (int64_t)r;
-            fs[0] = o0;
-            fs[1] = o1;
-            fs[2] = o2;
-          }
-        } else {
-          double *dst = DUAL ? a.xgrad : a.forces;
-          atomic_add(&dst[3 * j + 0], o0);
-          atomic_add(&dst[3 * j + 1], o1);
-          atomic_add(&dst[3 * j + 2], o2);
+    // the force this slot hands to j as stored (rounded to the slot type in
+    // owner-gather mode); i's own force is minus the sum of these, so the
+    // forces of every term cancel exactly in the gathered total
+    double o0 = 0.0, o1 = 0.0, o2 = 0.0;
+    if (act && want_f) {
+      o0 = DUAL ? -out_of(f0, eb) : val(f0);
+      o1 = DUAL ? -out_of(f1, eb) : val(f1);
+      o2 = DUAL ? -out_of(f2, eb) : val(f2);
+      if (a.fslot) {
+        o0 = (double)(B)o0;
+        o1 = (double)(B)o1;
+        o2 = (double)(B)o2;
+        const int r = a.rev[(int64_t)i * a.cap + s_slot[w][at * kNMax + q]];
+        if (r >= 0) {
+          B *fs = (B *)a.fslot + 3 * (int64_t)r;
+          fs[0] = (B)o0;
+          fs[1] = (B)o1;
+          fs[2] = (B)o2;
         }
+      } else {
+        double *dst = DUAL ? a.xgrad : a.forces;
+        atomic_add(&dst[3 * j + 0], o0);
+        atomic_add(&dst[3 * j + 1], o1);
+        atomic_add(&dst[3 * j + 2], o2);
       }
     }
-    // own force of i = - sum of its f_im (segmented sum over the atom's lanes),
-    // per-atom energy; taken by the atom's first lane
-    AT sx = f0, sy = f1, sz = f2;
-    double se = ev;
+    // own force of i (minus the sum of its slot forces; segmented sum over the
+    // atom's lanes) and per-atom energy, taken by the atom's first lane
+    double sx = o0, sy = o1, sz = o2, se = ev;
     for (int s = 1; s < nmax; ++s) {
       const int src = (act && s < n_i) ? seg0 + s : lane;
-      const AT tx = lane_read(f0, src), ty = lane_read(f1, src), tz = lane_read(f2, src);
+      const double tx = lane_read(o0, src), ty = lane_read(o1, src), tz = lane_read(o2, src);
       const double te = lane_read(ev, src);
       if (act && q == 0 && s < n_i) {
         sx += tx;
@@ -431,19 +435,16 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEu<T, PG>::value))) void k_force_wave
     }
     if (act && q == 0) {
       if (want_f) {
-        // own force of i is -sum; x gradient is -out(own) = +out(sum)
-        const double o0 = DUAL ? out_of(sx, eb) : -val(sx);
-        const double o1 = DUAL ? out_of(sy, eb) : -val(sy);
-        const double o2 = DUAL ? out_of(sz, eb) : -val(sz);
-        if (a.fown) {
-          a.fown[3 * i + 0] = o0;
-          a.fown[3 * i + 1] = o1;
-          a.fown[3 * i + 2] = o2;
+        if (a.fown) {  // indexed by position in cell order
+          double *fo = a.fown + 3 * (first + at);
+          fo[0] = -sx;
+          fo[1] = -sy;
+          fo[2] = -sz;
         } else {
           double *dst = DUAL ? a.xgrad : a.forces;
-          atomic_add(&dst[3 * i + 0], o0);
-          atomic_add(&dst[3 * i + 1], o1);
-          atomic_add(&dst[3 * i + 2], o2);
+          atomic_add(&dst[3 * i + 0], -sx);
+          atomic_add(&dst[3 * i + 1], -sy);
+          atomic_add(&dst[3 * i + 2], -sz);
         }
       }
       if (want_ea) {
@@ -456,9 +457,10 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEu<T, PG>::value))) void k_force_wave
     if (lane >= a0 && lane < a1 && my_n == 0) {
       if (want_ea && !(flags & TERS_ACCUMULATE)) a.e_atom[my_i] = 0.0;
       if (want_f && a.fown) {
-        a.fown[3 * my_i + 0] = 0.0;
-        a.fown[3 * my_i + 1] = 0.0;
-        a.fown[3 * my_i + 2] = 0.0;
+        double *fo = a.fown + 3 * (first + lane);
+        fo[0] = 0.0;
+        fo[1] = 0.0;
+        fo[2] = 0.0;
       }
     }
     wave_sync();

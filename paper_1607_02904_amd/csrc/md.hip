@@ -57,24 +57,22 @@ __global__ void k_vv_second(int n, double *__restrict__ v, const double *__restr
 }
 
 
-// owner gather of the forces into F (fixed order), then v += dt/2 F/m; the
-// rebuild flag is cleared for the next step
-__global__ void k_vv_second_gather(int n, int cap, const int32_t *__restrict__ count,
-                                   const double *__restrict__ fslot,
+// owner gather of the forces into F (fixed order, FP64 sums of the incoming
+// slots [soff[t], soff[t + 1]) of the atom at position t in cell order), then
+// v += dt/2 F/m; the rebuild flag is cleared for the next step
+template <class S>
+__global__ void k_vv_second_gather(int n, const int32_t *__restrict__ order,
+                                   const int32_t *__restrict__ soff, const S *__restrict__ fslot,
                                    const double *__restrict__ fown, double *__restrict__ F,
                                    double *__restrict__ v, const int32_t *__restrict__ type,
                                    const double *__restrict__ mass, double dt, int32_t *flag) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i == 0 && flag) *flag = 0;
-  if (i >= n) return;
-  double fx = fown[3 * i], fy = fown[3 * i + 1], fz = fown[3 * i + 2];
-  const int ci = min(count[i], cap);
-  const double *in = fslot + 3 * (int64_t)i * cap;
-  for (int s = 0; s < ci; ++s) {
-    fx += in[3 * s];
-    fy += in[3 * s + 1];
-    fz += in[3 * s + 2];
-  }
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t == 0 && flag) *flag = 0;
+  if (t >= n) return;
+  const int i = order[t];
+  const int s0 = soff[t], s1 = soff[t + 1];
+  double fx = fown[3 * t], fy = fown[3 * t + 1], fz = fown[3 * t + 2];
+  sum_slots(fslot, s0, s1, fx, fy, fz);
   F[3 * i] = fx;
   F[3 * i + 1] = fy;
   F[3 * i + 2] = fz;
@@ -86,12 +84,19 @@ __global__ void k_vv_second_gather(int n, int cap, const int32_t *__restrict__ c
 
 }  // namespace
 
-void launch_vv_second_gather(const NList &nl, double *v, double *F, const double *fslot,
-                             const double *fown, const int32_t *type, const double *mass,
-                             double dt, int32_t *flag, hipStream_t s) {
+void launch_vv_second_gather(const NList &nl, double *v, double *F, const void *fslot,
+                             bool slot_f32, const double *fown, const int32_t *type,
+                             const double *mass, double dt, int32_t *flag, hipStream_t s) {
   const int n = nl.n;
-  k_vv_second_gather<<<(std::max(n, 1) + kBS - 1) / kBS, kBS, 0, s>>>(
-      n, nl.cap, nl.count.as<int32_t>(), fslot, fown, F, v, type, mass, dt, flag);
+  const int g = (std::max(n, 1) + kBS - 1) / kBS;
+  if (slot_f32)
+    k_vv_second_gather<float><<<g, kBS, 0, s>>>(n, nl.order.as<int32_t>(), nl.soff.as<int32_t>(),
+                                                (const float *)fslot, fown, F, v, type, mass, dt,
+                                                flag);
+  else
+    k_vv_second_gather<double><<<g, kBS, 0, s>>>(n, nl.order.as<int32_t>(), nl.soff.as<int32_t>(),
+                                                 (const double *)fslot, fown, F, v, type, mass, dt,
+                                                 flag);
 }
 
 void launch_vv_first(int n, double *x, double *v, double *f, const int32_t *type,

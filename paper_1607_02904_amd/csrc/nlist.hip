@@ -4,12 +4,16 @@
 //   bin     atom -> cell of side >= r_list in its own configuration's grid,
 //           count atoms per cell
 //   scan    exclusive prefix sum of the cell counts (cell_start)
-//   place   counting-sort the atoms into cells; keep a cell-ordered copy of
-//           the positions and the reference positions of the rebuild check
+//   place   counting-sort the atoms into cells; keep the reference positions
+//           of the rebuild check
 //   sort    order atoms inside each cell by index (run-to-run determinism)
+//           and keep a cell-ordered copy of the positions
 //   build   for each atom scan the 27 surrounding cells (1 along an axis that
 //           holds fewer than 3 cells) and keep j != i with minimum-image
-//           r_ij <= r_list, in a padded row of `cap` entries
+//           r_ij <= r_list, in a padded row of `cap` entries; hand out each
+//           atom's range of incoming force slots (compact, no row padding)
+//   reverse for every row entry (i, j), the slot of i's force on j among j's
+//           incoming slots
 //
 // Every kernel takes an optional device flag: when it is non-null and zero the
 // kernel returns at once, so a molecular-dynamics step can keep the rebuild
@@ -53,10 +57,8 @@ DEV void bin_one(int i, const double *__restrict__ x, const ConfDesc *__restrict
 
 __global__ void k_bin(int n, const double *__restrict__ x, const ConfDesc *__restrict__ conf,
                       const int32_t *__restrict__ conf_of, int32_t *__restrict__ cell_of,
-                      int32_t *__restrict__ cell_count, int32_t *__restrict__ maxcount,
-                      const int32_t *cond, uint32_t *err) {
+                      int32_t *__restrict__ cell_count, const int32_t *cond, uint32_t *err) {
   if (skip(cond)) return;
-  if (blockIdx.x == 0 && threadIdx.x == 0) *maxcount = 0;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
     bin_one(i, x, conf, conf_of, cell_of, cell_count, err);
 }
@@ -97,16 +99,17 @@ DEV int wave_incl_scan(int v) {
   return v;
 }
 
-// exclusive block scan of one value per thread (blockDim == kBS)
-DEV int block_excl_scan(int v, int *total) {
-  __shared__ int wsum[kBS / kWave];
+// exclusive block scan of one value per thread (blockDim == BS)
+template <int BS>
+DEV int block_excl_scan_t(int v, int *total) {
+  __shared__ int wsum[BS / kWave];
   int lane = lane_id(), w = threadIdx.x / kWave;
   int inc = wave_incl_scan(v);
   if (lane == kWave - 1) wsum[w] = inc;
   __syncthreads();
   int off = 0, tot = 0;
 #pragma unroll
-  for (int k = 0; k < kBS / kWave; ++k) {
+  for (int k = 0; k < BS / kWave; ++k) {
     if (k < w) off += wsum[k];
     tot += wsum[k];
   }
@@ -114,6 +117,7 @@ DEV int block_excl_scan(int v, int *total) {
   if (total) *total = tot;
   return off + inc - v;
 }
+DEV int block_excl_scan(int v, int *total) { return block_excl_scan_t<kBS>(v, total); }
 
 __global__ __launch_bounds__(kBS) void k_scan_tiles(const int32_t *__restrict__ in,
                                                     int32_t *__restrict__ out, int64_t m,
@@ -168,18 +172,20 @@ __global__ __launch_bounds__(kBS) void k_scan_add(int32_t *out, int64_t m,
 // whole exclusive scan in one workgroup (used when the cell count is moderate):
 // contiguous chunks per thread, one block scan of the chunk sums; the counts
 // are cleared on the way (they become the placement cursors)
-constexpr int kScan1Max = 8192;  // above this the three-kernel parallel scan wins
-__global__ __launch_bounds__(kBS) void k_scan_single(int32_t *__restrict__ counts,
-                                                     int32_t *__restrict__ out, int64_t m,
-                                                     const int32_t *cond) {
+constexpr int kScan1BS = 1024;
+constexpr int64_t kScan1Max = 8192;  // above this the two-launch parallel scan wins
+__global__ __launch_bounds__(kScan1BS) void k_scan_single(int32_t *__restrict__ counts,
+                                                          int32_t *__restrict__ out, int64_t m,
+                                                          const int32_t *cond) {
   if (skip(cond)) return;
-  const int64_t per = (m + kBS - 1) / kBS;
+  const int64_t per = (m + kScan1BS - 1) / kScan1BS;
   const int64_t b = threadIdx.x * per;
   const int64_t e = b + per < m ? b + per : m;
   int s = 0;
+#pragma unroll 8
   for (int64_t i = b; i < e; ++i) s += counts[i];
   int tot;
-  int off = block_excl_scan(s, &tot);
+  int off = block_excl_scan_t<kScan1BS>(s, &tot);
   for (int64_t i = b; i < e; ++i) {
     int c = counts[i];
     out[i] = off;
@@ -203,10 +209,12 @@ __global__ void k_place(int n, const double *__restrict__ x, const int32_t *__re
   }
 }
 
-// order atoms inside each cell by index; the counts (used as placement
-// cursors) are cleared for the next build
+// order atoms inside each cell by index and copy their positions in that
+// order (xs); the counts (used as placement cursors) are cleared for the next
+// build
 __global__ void k_sort_cells(int64_t ncell, const int32_t *__restrict__ cell_start,
                              int32_t *__restrict__ order, int32_t *__restrict__ counts,
+                             const double *__restrict__ x, double *__restrict__ xs,
                              const int32_t *cond) {
   if (skip(cond)) return;
   for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < ncell;
@@ -221,11 +229,37 @@ __global__ void k_sort_cells(int64_t ncell, const int32_t *__restrict__ cell_sta
       }
       order[q + 1] = v;
     }
+    for (int p = b; p < e; ++p) {
+      const int i = order[p];
+      xs[3 * p] = x[3 * i];
+      xs[3 * p + 1] = x[3 * i + 1];
+      xs[3 * p + 2] = x[3 * i + 2];
+    }
     counts[c] = 0;
   }
 }
 
-__global__ __launch_bounds__(kBS) void k_build(int n, const double *__restrict__ x,
+DEV int wrap_cell(int q, int nc) { return q < 0 ? q + nc : (q >= nc ? q - nc : q); }
+
+// Seven atoms per wavefront (cell order), nine lanes per atom: lane r of an
+// atom takes the row (oz, oy) = (r / 3 - 1, r % 3 - 1) of neighbour cells
+// (z-major, the order the rows of the list keep; one offset along an axis with
+// fewer than 3 cells).  The cells ox = -1, 0, +1 of a row are consecutive cell
+// indices except across the periodic seam, so their atoms form at most two
+// runs of the cell-ordered position copy xs.  A first pass counts each lane's
+// hits (the first 64 also as a bit mask), an exclusive scan over the atom's
+// nine lanes gives every lane its first position in the row, and a second pass
+// writes the hits there.
+//
+// Incoming force slots (min(count, cap) per atom) are laid out without row
+// padding: each workgroup numbers its atoms' slots from 0 in processing order
+// (loff, packed with the workgroup's id) and leaves its total and its longest
+// row in bsum; k_reverse turns these into global offsets.  No atomics.
+constexpr int kRows = 9;
+constexpr int kAtomsPerWave = kWave / kRows;  // 7
+constexpr int kBuildMaxBlocks = 4096;         // bsum holds 2 ints per block
+constexpr int kLoffBits = 19;                 // slots numbered within a workgroup
+__global__ __launch_bounds__(kBS) void k_build(int n, const double *__restrict__ xs,
                                                const ConfDesc *__restrict__ conf,
                                                const int32_t *__restrict__ conf_of,
                                                const int32_t *__restrict__ order,
@@ -233,115 +267,284 @@ __global__ __launch_bounds__(kBS) void k_build(int n, const double *__restrict__
                                                const int32_t *__restrict__ cell_start,
                                                double rl2, int cap, int32_t *__restrict__ count,
                                                int32_t *__restrict__ list,
-                                               int32_t *__restrict__ maxcount,
-                                               const int32_t *cond, uint32_t *err,
-                                               int64_t *rebuilds) {
+                                               int32_t *__restrict__ loff,
+                                               int32_t *__restrict__ bsum, const int32_t *cond,
+                                               uint32_t *err, int64_t *rebuilds) {
   if (skip(cond)) return;
   if (blockIdx.x == 0 && threadIdx.x == 0 && rebuilds) *rebuilds += 1;
-  int worst = 0;
-  // grid-stride over atoms in cell order (each XCD takes one contiguous range
-  // per pass, so neighbouring cells share its L2); every lane runs the same
-  // number of iterations so the wave reduction below sees all lanes
-  const int stride = gridDim.x * blockDim.x;
-  const int iters = (n + stride - 1) / stride;
+  __shared__ int s_wmax[kBS / kWave];
+  const int lane = lane_id(), w = threadIdx.x / kWave;
+  const int la = lane / kRows, r = lane - kRows * la;  // atom of the wave (7 = idle lane), row
+  const int last = min(kRows * la + kRows - 1, kWave - 1);  // the atom's row-8 lane
+  constexpr int kWPB = kBS / kWave;
+  const int blk = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t ngroups = (n + kAtomsPerWave - 1) / kAtomsPerWave;
+  // each workgroup takes one contiguous range of groups of atoms in cell order
+  // (so slot numbers, and off, increase along the cell order, and each XCD
+  // works on one contiguous range whose neighbour cells share its L2); every
+  // lane runs the same number of passes (workgroup scan below)
+  const int64_t per_blk = (ngroups + gridDim.x - 1) / gridDim.x;
+  const int iters = (int)((per_blk + kWPB - 1) / kWPB);
+  const int64_t gend = min((int64_t)(blk + 1) * per_blk, ngroups);
+  int worst = 0, run = 0;  // longest row; slots numbered so far in this workgroup
   for (int it = 0; it < iters; ++it) {
-  const int t = it * stride + xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-  int cnt = 0;
-  if (t < n) {
-    int i = order[t];
-    const ConfDesc &c = conf[conf_index(conf_of, i)];
-    double xi = x[3 * i], yi = x[3 * i + 1], zi = x[3 * i + 2];
-    int lc = cell_of[i] - c.cell_off;
-    int cx = lc % c.nc[0], cy = (lc / c.nc[0]) % c.nc[1], cz = lc / (c.nc[0] * c.nc[1]);
-    int lo[3], hi[3];
-    for (int a = 0; a < 3; ++a) {
-      lo[a] = c.nc[a] >= 3 ? -1 : 0;
-      hi[a] = c.nc[a] >= 3 ? 1 : 0;
-    }
-    int32_t *row = list + (int64_t)i * cap;
-    for (int oz = lo[2]; oz <= hi[2]; ++oz) {
-      int qz = cz + oz;
-      qz += (qz < 0) ? c.nc[2] : 0;
-      qz -= (qz >= c.nc[2]) ? c.nc[2] : 0;
-      for (int oy = lo[1]; oy <= hi[1]; ++oy) {
-        int qy = cy + oy;
-        qy += (qy < 0) ? c.nc[1] : 0;
-        qy -= (qy >= c.nc[1]) ? c.nc[1] : 0;
-        for (int ox = lo[0]; ox <= hi[0]; ++ox) {
-          int qx = cx + ox;
-          qx += (qx < 0) ? c.nc[0] : 0;
-          qx -= (qx >= c.nc[0]) ? c.nc[0] : 0;
-          int cell = c.cell_off + (qz * c.nc[1] + qy) * c.nc[0] + qx;
-          int b = cell_start[cell], e = cell_start[cell + 1];
-          for (int p = b; p < e; ++p) {
-            int j = order[p];
-            if (j == i) continue;
-            double dx = x[3 * j] - xi, dy = x[3 * j + 1] - yi, dz = x[3 * j + 2] - zi;
-            dx -= c.box[0] * rint(dx * c.inv_box[0]);
-            dy -= c.box[1] * rint(dy * c.inv_box[1]);
-            dz -= c.box[2] * rint(dz * c.inv_box[2]);
-            if (dx * dx + dy * dy + dz * dz <= rl2) {
-              if (cnt < cap) row[cnt] = j;
-              ++cnt;
-            }
-          }
+    const int64_t g = (int64_t)blk * per_blk + (int64_t)it * kWPB + w;
+    const int64_t t64 = g * kAtomsPerWave + la;
+    const bool act = g < gend && la < kAtomsPerWave && t64 < n;
+    const int t = act ? (int)t64 : -1;
+    int i = 0, b0 = 0, e0 = 0, b1 = 0, e1 = 0;
+    double xi = 0.0, yi = 0.0, zi = 0.0;
+    const ConfDesc *c = conf;
+    if (act) {
+      i = order[t];
+      c = conf + conf_index(conf_of, i);
+      xi = xs[3 * t];
+      yi = xs[3 * t + 1];
+      zi = xs[3 * t + 2];
+      const int lc = cell_of[i] - c->cell_off;
+      const int nx = c->nc[0], ny = c->nc[1], nz = c->nc[2];
+      const int cx = lc % nx, cy = (lc / nx) % ny, cz = lc / (nx * ny);
+      const int oz = r / 3 - 1, oy = r % 3 - 1;
+      if ((nz >= 3 || oz == 0) && (ny >= 3 || oy == 0)) {
+        const int rc = c->cell_off + (wrap_cell(cz + oz, nz) * ny + wrap_cell(cy + oy, ny)) * nx;
+        int c0, c1, c2 = 0, c3 = 0;  // runs [c0, c1) and [c2, c3) of cells
+        if (nx < 3) {
+          c0 = rc + cx;
+          c1 = c0 + 1;
+        } else if (cx == 0) {
+          c0 = rc + nx - 1;
+          c1 = rc + nx;
+          c2 = rc;
+          c3 = rc + 2;
+        } else if (cx == nx - 1) {
+          c0 = rc + cx - 1;
+          c1 = rc + nx;
+          c2 = rc;
+          c3 = rc + 1;
+        } else {
+          c0 = rc + cx - 1;
+          c1 = rc + cx + 2;
+        }
+        b0 = cell_start[c0];
+        e0 = cell_start[c1];
+        if (c3 > c2) {
+          b1 = cell_start[c2];
+          e1 = cell_start[c3];
         }
       }
     }
-    count[i] = cnt;
+    const int len0 = e0 - b0, len = len0 + (e1 - b1);
+    const double bx = c->box[0], by = c->box[1], bz = c->box[2];
+    const double ibx = c->inv_box[0], iby = c->inv_box[1], ibz = c->inv_box[2];
+    // minimum image (positions need not lie inside the box); exactly negated
+    // for (j, i), so the list is symmetric
+    auto within_at = [&](int p, double px, double py, double pz) {
+      double dx = px - xi, dy = py - yi, dz = pz - zi;
+      dx -= bx * rint(dx * ibx);
+      dy -= by * rint(dy * iby);
+      dz -= bz * rint(dz * ibz);
+      return p != t && dx * dx + dy * dy + dz * dz <= rl2;
+    };
+    auto within = [&](int p) { return within_at(p, xs[3 * p], xs[3 * p + 1], xs[3 * p + 2]); };
+    // pass 1: count (the first 64 hits of the runs also as a mask); the
+    // positions of four candidates are fetched before any is tested
+    int nhit = 0;
+    uint64_t mask = 0;
+    for (int k0 = 0; k0 < len; k0 += 4) {
+      double px[4], py[4], pz[4];
+      int pp[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int k = min(k0 + u, len - 1);
+        pp[u] = k < len0 ? b0 + k : b1 + (k - len0);
+        px[u] = xs[3 * pp[u]];
+        py[u] = xs[3 * pp[u] + 1];
+        pz[u] = xs[3 * pp[u] + 2];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int k = k0 + u;
+        if (k < len && within_at(pp[u], px[u], py[u], pz[u])) {
+          ++nhit;
+          if (k < 64) mask |= 1ull << k;
+        }
+      }
+    }
+    // exclusive scan over the atom's nine lanes
+    int incl = nhit;
+#pragma unroll
+    for (int o = 1; o < 16; o <<= 1) {
+      const int u = __shfl_up(incl, o, kWave);
+      if (r >= o) incl += u;
+    }
+    const int total = __shfl(incl, last, kWave);
+    // pass 2: write the hits from the row position of this lane on
+    if (act) {
+      int32_t *row = list + (int64_t)i * cap;
+      int pos = incl - nhit;
+      while (mask) {
+        const int k = __ffsll((unsigned long long)mask) - 1;
+        mask &= mask - 1ull;
+        const int p = k < len0 ? b0 + k : b1 + (k - len0);
+        if (pos < cap) row[pos] = order[p];
+        ++pos;
+      }
+      for (int k = 64; k < len; ++k) {  // rows of more than 64 candidates
+        const int p = k < len0 ? b0 + k : b1 + (k - len0);
+        if (within(p)) {
+          if (pos < cap) row[pos] = order[p];
+          ++pos;
+        }
+      }
+    }
+    const bool owner = act && r == kRows - 1;
+    if (owner) {
+      count[i] = total;
+      if (total > cap) atomicOr(err, kErrNlistOverflow);
+    }
+    worst = max(worst, owner ? total : 0);
+    // slots of this pass, numbered after those of the earlier passes
+    int tot;
+    const int ex = block_excl_scan(owner ? min(total, cap) : 0, &tot);
+    if (owner) loff[i] = (int32_t)(((uint32_t)blk << kLoffBits) | (uint32_t)(run + ex));
+    run += tot;
   }
-  worst = max(worst, cnt);
-  }
-  // largest row, one atomic per wave
+  // the workgroup's slot total and longest row
   int m = worst;
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o, kWave));
-  if (lane_id() == 0 && m > 0) {
-    atomicMax(maxcount, m);
-    if (m > cap) atomicOr(err, kErrNlistOverflow);
+  if (lane == 0) s_wmax[w] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int bm = 0;
+    for (int k = 0; k < kWPB; ++k) bm = max(bm, s_wmax[k]);
+    bsum[2 * blk] = run;
+    bsum[2 * blk + 1] = bm;
   }
 }
 
-// rev[i*cap + s] = slot of i in the row of j = list[i*cap + s].  The list is
-// symmetric by construction (r_ij and r_ji are computed from exactly negated
-// displacements), so the slot exists; a missing one is latched as an error.
-__global__ void k_reverse(int n, int cap, const int32_t *__restrict__ count,
-                          const int32_t *__restrict__ list, int32_t *__restrict__ rev,
-                          const int32_t *cond, uint32_t *err) {
+// Global slot offsets and the reverse map.  Every workgroup first scans the
+// build's per-workgroup slot totals (nb <= kBuildMaxBlocks, in LDS), so the
+// first slot of atom a is off(a) = (slots of earlier build workgroups) + (a's
+// number within its own); workgroup 0 also stores the longest row.  Then, per
+// atom i (at position t in cell order): soff[t] = off(i) (slots increase along
+// the cell order, so atom t's are [soff[t], soff[t + 1])), and
+// rev[i*cap + s] = incoming force slot at atom j = list[i*cap + s] that holds
+// the force of i's terms on j: off(j) + (position of i in j's row).  The list
+// is symmetric by construction (r_ij and r_ji are computed from exactly
+// negated displacements), so the position exists; a missing one is latched as
+// an error.  The rows of 4 neighbours are searched together with 16-byte
+// loads (rows start 16-byte aligned: cap is a multiple of 4).
+__global__ __launch_bounds__(kBS) void k_reverse(int n, int cap, const int32_t *__restrict__ order,
+                                                 const int32_t *__restrict__ count,
+                                                 const int32_t *__restrict__ list,
+                                                 const int32_t *__restrict__ loff,
+                                                 const int32_t *__restrict__ bsum, int nb,
+                                                 int32_t *__restrict__ soff,
+                                                 int32_t *__restrict__ rev,
+                                                 int32_t *__restrict__ maxcount, const int32_t *cond,
+                                                 uint32_t *err) {
   if (skip(cond)) return;
-  for (int i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x; i < n;
-       i += gridDim.x * blockDim.x) {
-  const int ci = min(count[i], cap);
-  for (int s = 0; s < ci; ++s) {
-    const int j = list[(int64_t)i * cap + s];
-    const int cj = min(count[j], cap);
-    int found = -1;
-    for (int t = 0; t < cj; ++t)
-      if (list[(int64_t)j * cap + t] == i) {
-        found = t;
-        break;
-      }
-    if (found < 0) atomicOr(err, kErrListAsymmetric);
-    rev[(int64_t)i * cap + s] = found < 0 ? -1 : j * cap + found;
+  __shared__ int s_pre[kBuildMaxBlocks];
+  {
+    constexpr int kPer = kBuildMaxBlocks / kBS;
+    const int b0 = threadIdx.x * kPer;
+    int v[kPer];
+    int sum = 0, mx = 0;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const bool in = b0 + k < nb;
+      v[k] = in ? bsum[2 * (b0 + k)] : 0;
+      mx = max(mx, in ? bsum[2 * (b0 + k) + 1] : 0);
+      sum += v[k];
+    }
+    int tot;
+    int run = block_excl_scan(sum, &tot);
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      s_pre[b0 + k] = run;
+      run += v[k];
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) mx = max(mx, __shfl_xor(mx, o, kWave));
+    __shared__ int s_mx[kBS / kWave];
+    if (lane_id() == 0) s_mx[threadIdx.x / kWave] = mx;
+    __syncthreads();
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      int m = 0;
+      for (int k = 0; k < kBS / kWave; ++k) m = max(m, s_mx[k]);
+      *maxcount = m;
+    }
   }
+  auto offset_of = [&](int a) {
+    const uint32_t v = (uint32_t)loff[a];
+    return s_pre[v >> kLoffBits] + (int)(v & ((1u << kLoffBits) - 1u));
+  };
+  for (int t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x; t < n;
+       t += gridDim.x * blockDim.x) {
+    const int i = order[t];
+    const int ci = min(count[i], cap);
+    const int oi = offset_of(i);
+    soff[t] = oi;  // slots of the atom at position t: [soff[t], soff[t + 1])
+    if (t == n - 1) soff[n] = oi + ci;
+    const int32_t *row_i = list + (int64_t)i * cap;
+    for (int s0 = 0; s0 < ci; s0 += 4) {
+      int j[4], cj[4], oj[4], found[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) j[u] = s0 + u < ci ? row_i[s0 + u] : i;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const bool live = s0 + u < ci;
+        cj[u] = live ? min(count[j[u]], cap) : 0;
+        oj[u] = live ? offset_of(j[u]) : 0;
+        found[u] = -1;
+      }
+      for (int k = 0; k < cap; k += 4) {
+        int4 v[4];
+        bool any = false;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if (found[u] < 0 && k < cj[u]) {
+            v[u] = *reinterpret_cast<const int4 *>(list + (int64_t)j[u] * cap + k);
+            any = true;
+          }
+        }
+        if (!any) break;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if (found[u] < 0 && k < cj[u]) {
+            if (v[u].x == i) found[u] = k;
+            else if (k + 1 < cj[u] && v[u].y == i) found[u] = k + 1;
+            else if (k + 2 < cj[u] && v[u].z == i) found[u] = k + 2;
+            else if (k + 3 < cj[u] && v[u].w == i) found[u] = k + 3;
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (s0 + u < ci) {
+          if (found[u] < 0) atomicOr(err, kErrListAsymmetric);
+          rev[(int64_t)i * cap + s0 + u] = found[u] < 0 ? -1 : oj[u] + found[u];
+        }
+      }
+    }
   }
 }
 
 // owner gather: fixed-order sum of the forces that every neighbour's terms put
-// on atom a (its incoming slots, contiguous), plus a's own part
-__global__ void k_gather(int n, int cap, const int32_t *__restrict__ count,
-                         const double *__restrict__ fslot, const double *__restrict__ fown,
-                         double *__restrict__ F, int accumulate) {
-  int a = blockIdx.x * blockDim.x + threadIdx.x;
-  if (a >= n) return;
-  double fx = fown[3 * a], fy = fown[3 * a + 1], fz = fown[3 * a + 2];
-  const int ca = min(count[a], cap);
-  const double *in = fslot + 3 * (int64_t)a * cap;
-  for (int s = 0; s < ca; ++s) {
-    fx += in[3 * s];
-    fy += in[3 * s + 1];
-    fz += in[3 * s + 2];
-  }
+// on atom a (its incoming slots [soff[t], soff[t + 1]) for a = order[t]; FP32
+// in the mixed path), plus a's own part, in FP64.  Thread per position t in
+// cell order: a wavefront reads one contiguous run of slots.
+template <class S>
+__global__ void k_gather(int n, const int32_t *__restrict__ order,
+                         const int32_t *__restrict__ soff, const S *__restrict__ fslot,
+                         const double *__restrict__ fown, double *__restrict__ F, int accumulate) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const int a = order[t];
+  const int s0 = soff[t], s1 = soff[t + 1];
+  double fx = fown[3 * t], fy = fown[3 * t + 1], fz = fown[3 * t + 2];
+  sum_slots(fslot, s0, s1, fx, fy, fz);
   if (accumulate) {
     F[3 * a] += fx;
     F[3 * a + 1] += fy;
@@ -416,10 +619,10 @@ void nlist_build(NList &nl, const double *x, const int32_t *cond, uint32_t *err,
     return g < 1 ? 1 : (g > gcap ? gcap : g);
   };
   if (n > 0)
-    k_bin<<<grid(n), kBS, 0, s>>>(n, x, conf, conf_of, nl.cell_of.as<int32_t>(), cell_count,
-                                  nl.maxcount.as<int32_t>(), cond, err);
+    k_bin<<<grid(n), kBS, 0, s>>>(n, x, conf, conf_of, nl.cell_of.as<int32_t>(), cell_count, cond,
+                                  err);
   if (m <= kScan1Max) {
-    k_scan_single<<<1, kBS, 0, s>>>(cell_count, cell_start, m, cond);
+    k_scan_single<<<1, kScan1BS, 0, s>>>(cell_count, cell_start, m, cond);
   } else {
     const int ntile = grid_for(m, kScanTile);
     k_scan_tiles<<<ntile, kBS, 0, s>>>(cell_count, cell_start, m, nl.scan_tmp.as<int32_t>(), cond);
@@ -429,24 +632,33 @@ void nlist_build(NList &nl, const double *x, const int32_t *cond, uint32_t *err,
     k_place<<<grid(n), kBS, 0, s>>>(n, x, nl.cell_of.as<int32_t>(), cell_start, cell_count,
                                     nl.order.as<int32_t>(), nl.xref.as<double>(), cond);
     k_sort_cells<<<grid(ncell), kBS, 0, s>>>(ncell, cell_start, nl.order.as<int32_t>(), cell_count,
-                                             cond);
-    k_build<<<grid(n), kBS, 0, s>>>(n, x, conf, conf_of, nl.order.as<int32_t>(),
-                                             nl.cell_of.as<int32_t>(), cell_start,
-                                             nl.rlist * nl.rlist, nl.cap, nl.count.as<int32_t>(),
-                                             nl.list.as<int32_t>(), nl.maxcount.as<int32_t>(),
-                                             cond, err, rebuild_counter);
-    if (nl.rev.p)
-      k_reverse<<<grid(n), kBS, 0, s>>>(n, nl.cap, nl.count.as<int32_t>(),
-                                                 nl.list.as<int32_t>(), nl.rev.as<int32_t>(), cond,
-                                                 err);
+                                             x, nl.xs.as<double>(), cond);
+    // the list build is latency-bound: a larger grid than the other kernels
+    const int64_t groups = (n + kAtomsPerWave - 1) / kAtomsPerWave;
+    const int gb = (int)std::min<int64_t>(
+        std::max<int64_t>((groups + kBS / kWave - 1) / (kBS / kWave), 1), kBuildMaxBlocks);
+    k_build<<<gb, kBS, 0, s>>>(n, nl.xs.as<double>(), conf, conf_of, nl.order.as<int32_t>(),
+                               nl.cell_of.as<int32_t>(), cell_start, nl.rlist * nl.rlist, nl.cap,
+                               nl.count.as<int32_t>(), nl.list.as<int32_t>(), nl.loff.as<int32_t>(),
+                               nl.bsum.as<int32_t>(), cond, err, rebuild_counter);
+    k_reverse<<<grid(n), kBS, 0, s>>>(n, nl.cap, nl.order.as<int32_t>(), nl.count.as<int32_t>(),
+                                      nl.list.as<int32_t>(), nl.loff.as<int32_t>(),
+                                      nl.bsum.as<int32_t>(), gb, nl.soff.as<int32_t>(),
+                                      nl.rev.as<int32_t>(), nl.maxcount.as<int32_t>(), cond, err);
   }
 }
 
-void launch_gather(const NList &nl, const double *fslot, const double *fown, double *F,
-                   int accumulate, hipStream_t s) {
+void launch_gather(const NList &nl, const void *fslot, bool slot_f32, const double *fown,
+                   double *F, int accumulate, hipStream_t s) {
   if (nl.n <= 0) return;
-  k_gather<<<grid_for(nl.n, kBS), kBS, 0, s>>>(nl.n, nl.cap, nl.count.as<int32_t>(), fslot, fown,
-                                               F, accumulate);
+  if (slot_f32)
+    k_gather<float><<<grid_for(nl.n, kBS), kBS, 0, s>>>(
+        nl.n, nl.order.as<int32_t>(), nl.soff.as<int32_t>(), (const float *)fslot, fown, F,
+        accumulate);
+  else
+    k_gather<double><<<grid_for(nl.n, kBS), kBS, 0, s>>>(
+        nl.n, nl.order.as<int32_t>(), nl.soff.as<int32_t>(), (const double *)fslot, fown, F,
+        accumulate);
 }
 
 void nlist_check(const NList &nl, const double *x, int32_t *flag, hipStream_t s) {

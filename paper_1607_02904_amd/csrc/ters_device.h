@@ -167,6 +167,31 @@ DEV int xcd_block(int b, int G) {
   return x * q + min(x, r) + b / kXcd;
 }
 
+// Sum in FP64, in slot order, of the force slots [s0, s1) (3 values each); the
+// slots are fetched four at a time so that their loads are in flight together.
+template <class S>
+DEV void sum_slots(const S *__restrict__ fslot, int s0, int s1, double &fx, double &fy,
+                   double &fz) {
+  for (int s = s0; s < s1; s += 4) {
+    S v[12];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t q = 3 * (int64_t)min(s + u, s1 - 1);
+      v[3 * u] = fslot[q];
+      v[3 * u + 1] = fslot[q + 1];
+      v[3 * u + 2] = fslot[q + 2];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (s + u < s1) {
+        fx += (double)v[3 * u];
+        fy += (double)v[3 * u + 1];
+        fz += (double)v[3 * u + 2];
+      }
+    }
+  }
+}
+
 // hardware FP64 atomic add to global memory (global_atomic_add_f64)
 DEV void atomic_add(double *p, double v) { unsafeAtomicAdd(p, v); }
 

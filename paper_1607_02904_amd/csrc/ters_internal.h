@@ -88,7 +88,11 @@ struct NList {
   DevBuf scan_tmp;    // int32 block sums
   DevBuf xref;        // double[n][3]
   DevBuf maxcount;    // int32[1]
-  DevBuf rev;         // int32[n][cap]: slot of (j, i) in j's row for slot (i, j)
+  DevBuf rev;         // int32[n][cap]: incoming force slot at j of row entry (i, j)
+  DevBuf xs;          // double[n][3]: positions at build time, in cell order
+  DevBuf soff;        // int32[n + 1]: first incoming force slot of the atom at each cell-order position
+  DevBuf loff;        // int32[n]: build workgroup (high bits) and slot number within it
+  DevBuf bsum;        // int32[2 * 4096]: slot total and longest row per build workgroup
 };
 
 // Forward / adjoint launch description.
@@ -119,9 +123,11 @@ struct FwdArgs {
   // owner-gather mode (no atomics): when fslot is set, the force that the
   // terms rooted at atom i exert on its list neighbour j (slot s of i's row)
   // goes to j's incoming slot fslot[rev[i*cap + s]*3 ..] (zero when the pair is
-  // outside the cutoff) and the force on i itself to fown[i*3 ..]; atom a's
-  // incoming forces then sit contiguously in fslot[a*cap*3 ..] for the gather.
-  double *fslot;
+  // outside the cutoff) and the force on i itself to fown[t*3 ..], t = i's
+  // position in cell order; the incoming forces of the atom at position t then
+  // sit contiguously in slots [soff[t], soff[t + 1]) for the gather.
+  // Slots hold the kernel's base type: FP64, or FP32 in the mixed path.
+  void *fslot;
   double *fown;
   const int32_t *rev;
   uint32_t *err;
@@ -133,14 +139,15 @@ void launch_fill_f64(double *p, double v, int64_t n, hipStream_t s);
 void nlist_build(NList &nl, const double *x, const int32_t *cond, uint32_t *err, hipStream_t s,
                  int64_t *rebuild_counter = nullptr);
 void nlist_check(const NList &nl, const double *x, int32_t *flag, hipStream_t s);
-// F[a] (+)= fown[a] + sum over a's incoming slots fslot[a*cap + s], s < count[a]
-void launch_gather(const NList &nl, const double *fslot, const double *fown, double *F,
-                   int accumulate, hipStream_t s);
+// F[a] (+)= fown[t] + sum of the incoming slots fslot[soff[t] .. soff[t + 1]), a = order[t]
+// (FP32 slots when slot_f32), summed in FP64 in slot order
+void launch_gather(const NList &nl, const void *fslot, bool slot_f32, const double *fown,
+                   double *F, int accumulate, hipStream_t s);
 // molecular dynamics: gather as above into F, then v += dt/2 F/m, and clear
 // the rebuild flag for the next step
-void launch_vv_second_gather(const NList &nl, double *v, double *F, const double *fslot,
-                             const double *fown, const int32_t *type, const double *mass,
-                             double dt, int32_t *flag, hipStream_t s);
+void launch_vv_second_gather(const NList &nl, double *v, double *F, const void *fslot,
+                             bool slot_f32, const double *fown, const int32_t *type,
+                             const double *mass, double dt, int32_t *flag, hipStream_t s);
 void launch_forward(const FwdArgs &a, int precision, int atoms_per_block, int nblocks_out[1],
                     hipStream_t s);
 void launch_adjoint(const FwdArgs &a, int precision, int atoms_per_block, hipStream_t s);
