@@ -197,6 +197,7 @@ void nl_setup(NList &nl, int nconf, const int32_t *natoms, const double *boxes, 
   nl.scan_tmp.ensure(sizeof(int32_t) * ((cells + 1) / 1024 + 2));
   nl.xref.ensure(sizeof(double) * 3 * nn);
   nl.xs.ensure(sizeof(double) * 3 * nn);
+  nl.pos.ensure(sizeof(int32_t) * nn);
   nl.soff.ensure(sizeof(int32_t) * (nn + 1));
   nl.loff.ensure(sizeof(int32_t) * nn);
   nl.bsum.ensure(sizeof(int32_t) * 2 * 4096);
@@ -276,7 +277,7 @@ std::vector<const void *> graph_key(const ters_ctx *c, const NList &nl) {
           bits(nl.skin), c->kp64.p, c->kp32.p, c->filt2.p, (const void *)(intptr_t)c->ntypes,
           (const void *)(intptr_t)c->cut_consistent, (const void *)(intptr_t)c->kmax,
           c->partials.p, c->errw.p, c->flag.p, c->rebuilds.p, c->step.p, c->escratch.p,
-          nl.rev.p, nl.xs.p, nl.soff.p, nl.loff.p, nl.bsum.p, c->fslot.p, c->fown.p,
+          nl.rev.p, nl.xs.p, nl.pos.p, nl.soff.p, nl.loff.p, nl.bsum.p, c->fslot.p, c->fown.p,
           (const void *)(intptr_t)c->gather};
 }
 
@@ -384,7 +385,7 @@ ters_status ters_destroy(ters_ctx *c) {
                     &c->rebuilds, &c->step, &c->escratch, &c->fslot, &c->fown, &c->nl.conf,
                     &c->nl.conf_of, &c->nl.count, &c->nl.list, &c->nl.order, &c->nl.cell_of,
                     &c->nl.cell_count, &c->nl.cell_start, &c->nl.scan_tmp, &c->nl.xref,
-                    &c->nl.maxcount, &c->nl.rev, &c->nl.xs, &c->nl.soff,
+                    &c->nl.maxcount, &c->nl.rev, &c->nl.xs, &c->nl.pos, &c->nl.soff,
                     &c->nl.loff, &c->nl.bsum};
   for (DevBuf *b : bufs) b->release();
   delete c;
@@ -727,13 +728,21 @@ ters_status md_run_impl(ters_ctx *c, int32_t n, double *x, double *v, double *f,
       ev.resize(2 * (size_t)nsteps, nullptr);
       for (hipEvent_t &e : ev) TERS_HIP_TRY(hipEventCreate(&e));
     }
-    auto step = [&](hipStream_t s, int k) {
+    // Owner-gather mode: the first half kick and drift of step 1 run before
+    // the loop; a step is then | conditional rebuild | forces (clear the
+    // flag) | energy (trace) | gather + second half kick + first half kick,
+    // drift and rebuild test of the next step |, the last step without the
+    // next step's half.  Atomic-scatter mode: | kick + drift + zero F +
+    // rebuild test | conditional rebuild | forces | energy | kick + clear |.
+    auto step = [&](hipStream_t s, int k, bool last) {
       int32_t *flag = c->flag.as<int32_t>();
-      launch_vv_first(n, x, v, f, type, c->mass.as<double>(), dt, c->nl, flag, gather ? 0 : 1, s);
+      if (!gather)
+        launch_vv_first(n, x, v, f, type, c->mass.as<double>(), dt, c->nl, flag, 1, s);
       nlist_build(c->nl, x, flag, c->errw.as<uint32_t>(), s, c->rebuilds.as<int64_t>());
       FwdArgs a = base_args(c, c->nl, precision, n, x, type);
       a.flags = TERS_FORCES | TERS_ENERGY | TERS_ACCUMULATE;  // scatter: F was zeroed by the kick
       a.forces = f;
+      if (gather) a.clear_flag = flag;
       if (force_us) TERS_HIP_TRY(hipEventRecord(ev[2 * k], s));
       run_forward(c, a, precision, s, /*do_gather=*/false);
       if (force_us) TERS_HIP_TRY(hipEventRecord(ev[2 * k + 1], s));
@@ -741,15 +750,19 @@ ters_status md_run_impl(ters_ctx *c, int32_t n, double *x, double *v, double *f,
         launch_reduce_partials(c->partials.as<double>(), nb, 8, c->escratch.as<double>(), nullptr,
                                0, s, trace, c->step.as<int32_t>());
       if (gather)
-        launch_vv_second_gather(c->nl, v, f, c->fslot.p, precision == TERS_MIXED,
-                                c->fown.as<double>(), type, c->mass.as<double>(), dt, flag, s);
+        launch_vv_gather_kick_drift(c->nl, x, v, f, c->fslot.p, precision == TERS_MIXED,
+                                    c->fown.as<double>(), type, c->mass.as<double>(), dt, flag,
+                                    last ? 0 : 1, s);
       else
         launch_vv_second(n, v, f, type, c->mass.as<double>(), dt, flag, s);
     };
     launch_fill_i32(c->step.as<int32_t>(), 0, 1, nullptr, c->stream);
     launch_fill_i32(c->flag.as<int32_t>(), 0, 1, nullptr, c->stream);
+    if (gather && nsteps > 0)
+      launch_vv_first(n, x, v, f, type, c->mass.as<double>(), dt, c->nl, c->flag.as<int32_t>(), 0,
+                      c->stream);
     if (!use_graph || force_us) {
-      for (int s = 0; s < nsteps; ++s) step(c->stream, s);
+      for (int s = 0; s < nsteps; ++s) step(c->stream, s, s == nsteps - 1);
       if (force_us) {
         double tot = 0.0;
         for (int s = 0; s < nsteps; ++s) {
@@ -777,13 +790,17 @@ ters_status md_run_impl(ters_ctx *c, int32_t n, double *x, double *v, double *f,
         sync(c);
         hipGraph_t g;
         TERS_HIP_TRY(hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal));
-        step(c->capture_stream, 0);
+        step(c->capture_stream, 0, false);
         TERS_HIP_TRY(hipStreamEndCapture(c->capture_stream, &g));
         TERS_HIP_TRY(hipGraphInstantiate(&c->md_exec, g, nullptr, nullptr, 0));
         TERS_HIP_TRY(hipGraphDestroy(g));
         c->md_key = key;
       }
-      for (int s = 0; s < nsteps; ++s) TERS_HIP_TRY(hipGraphLaunch(c->md_exec, c->stream));
+      // the captured step carries the next step's half kick and drift; in
+      // owner-gather mode the last step is launched directly without it
+      const int replays = gather ? nsteps - 1 : nsteps;
+      for (int s = 0; s < replays; ++s) TERS_HIP_TRY(hipGraphLaunch(c->md_exec, c->stream));
+      if (gather) step(c->stream, nsteps - 1, true);
     }
     return TERS_OK;
   });
@@ -1014,7 +1031,7 @@ static void plan_release_device(ters_plan *p) {
   DevBuf *bufs[] = {&p->partials, &p->ebuf, &p->errw, &p->fslot, &p->fown, &p->nl.conf,
                     &p->nl.conf_of, &p->nl.count, &p->nl.list, &p->nl.order, &p->nl.cell_of,
                     &p->nl.cell_count, &p->nl.cell_start, &p->nl.scan_tmp, &p->nl.xref,
-                    &p->nl.maxcount, &p->nl.rev, &p->nl.xs, &p->nl.soff,
+                    &p->nl.maxcount, &p->nl.rev, &p->nl.xs, &p->nl.pos, &p->nl.soff,
                     &p->nl.loff, &p->nl.bsum};
   for (DevBuf *b : bufs) b->release();
   p->ctx = nullptr;

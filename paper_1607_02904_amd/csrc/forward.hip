@@ -66,6 +66,9 @@ __global__ __launch_bounds__(BS) void k_force(FwdArgs a, int A) {
   __shared__ double s_red[BS / kWave][8];
 
   const int tid = threadIdx.x;
+  // molecular dynamics: the list kernels of this step have read the rebuild
+  // flag; it is cleared here and set again by the drift of the next step
+  if (a.clear_flag && blockIdx.x == 0 && tid == 0) *a.clear_flag = 0;
   const int lane = lane_id();
   const int nt = a.ntypes;
   const int64_t first = (int64_t)xcd_block(blockIdx.x, gridDim.x) * A;

@@ -80,6 +80,9 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEu<T, PG>::value))) void k_force_wave
   __shared__ double s_red[kWPB][8];
 
   const int tid = threadIdx.x;
+  // molecular dynamics: the list kernels of this step have read the rebuild
+  // flag; it is cleared here and set again by the drift of the next step
+  if (a.clear_flag && blockIdx.x == 0 && tid == 0) *a.clear_flag = 0;
   const int w = tid / kWave;
   const int lane = lane_id();
   const int nt = a.ntypes;

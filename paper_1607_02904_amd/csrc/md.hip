@@ -57,46 +57,68 @@ __global__ void k_vv_second(int n, double *__restrict__ v, const double *__restr
 }
 
 
-// owner gather of the forces into F (fixed order, FP64 sums of the incoming
-// slots [soff[t], soff[t + 1]) of the atom at position t in cell order), then
-// v += dt/2 F/m; the rebuild flag is cleared for the next step
+// Owner gather of the forces into F (FP64 sums, in slot order, of the
+// incoming slots of the atom, [soff[t], soff[t + 1]) with t = pos[i]), the
+// second half kick of this step and, with do_next, the first half kick, drift
+// and rebuild test of the next one (the operations of k_vv_first, in the same
+// order).  Thread per atom.
 template <class S>
-__global__ void k_vv_second_gather(int n, const int32_t *__restrict__ order,
-                                   const int32_t *__restrict__ soff, const S *__restrict__ fslot,
-                                   const double *__restrict__ fown, double *__restrict__ F,
-                                   double *__restrict__ v, const int32_t *__restrict__ type,
-                                   const double *__restrict__ mass, double dt, int32_t *flag) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t == 0 && flag) *flag = 0;
-  if (t >= n) return;
-  const int i = order[t];
-  const int s0 = soff[t], s1 = soff[t + 1];
-  double fx = fown[3 * t], fy = fown[3 * t + 1], fz = fown[3 * t + 2];
-  sum_slots(fslot, s0, s1, fx, fy, fz);
-  F[3 * i] = fx;
-  F[3 * i + 1] = fy;
-  F[3 * i + 2] = fz;
-  const double s = 0.5 * dt * kFtm2v / mass[type[i]];
-  v[3 * i + 0] += s * fx;
-  v[3 * i + 1] += s * fy;
-  v[3 * i + 2] += s * fz;
+__global__ void k_vv_gather_kick_drift(int n, const int32_t *__restrict__ pos,
+                                       const int32_t *__restrict__ soff,
+                                       const S *__restrict__ fslot,
+                                       const double *__restrict__ fown, double *__restrict__ F,
+                                       double *__restrict__ v, double *__restrict__ x,
+                                       const int32_t *__restrict__ type,
+                                       const double *__restrict__ mass, double dt,
+                                       const double *__restrict__ xref,
+                                       const ConfDesc *__restrict__ conf, double lim2,
+                                       int32_t *flag, int do_next) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  bool over = false;
+  if (i < n) {
+    const int t = pos[i];
+    const int s0 = soff[t], s1 = soff[t + 1];
+    double fv[3] = {fown[3 * t], fown[3 * t + 1], fown[3 * t + 2]};
+    sum_slots(fslot, s0, s1, fv[0], fv[1], fv[2]);
+    const double s = 0.5 * dt * kFtm2v / mass[type[i]];
+    const ConfDesc &c = conf[0];
+    double r2 = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      F[3 * i + a] = fv[a];
+      double vv = v[3 * i + a] + s * fv[a];
+      if (do_next) {
+        vv = vv + s * fv[a];
+        const double xx = x[3 * i + a] + dt * vv;
+        x[3 * i + a] = xx;
+        double d = xx - xref[3 * i + a];
+        d -= c.box[a] * rint(d * c.inv_box[a]);
+        r2 += d * d;
+      }
+      v[3 * i + a] = vv;
+    }
+    over = do_next && !(r2 <= lim2);  // NaN counts as moved
+  }
+  if (__ballot(over) != 0ull && lane_id() == 0) *flag = 1;
 }
 
 }  // namespace
 
-void launch_vv_second_gather(const NList &nl, double *v, double *F, const void *fslot,
-                             bool slot_f32, const double *fown, const int32_t *type,
-                             const double *mass, double dt, int32_t *flag, hipStream_t s) {
+void launch_vv_gather_kick_drift(const NList &nl, double *x, double *v, double *F,
+                                 const void *fslot, bool slot_f32, const double *fown,
+                                 const int32_t *type, const double *mass, double dt,
+                                 int32_t *flag, int do_next, hipStream_t s) {
   const int n = nl.n;
   const int g = (std::max(n, 1) + kBS - 1) / kBS;
+  const double half = 0.5 * nl.skin;
   if (slot_f32)
-    k_vv_second_gather<float><<<g, kBS, 0, s>>>(n, nl.order.as<int32_t>(), nl.soff.as<int32_t>(),
-                                                (const float *)fslot, fown, F, v, type, mass, dt,
-                                                flag);
+    k_vv_gather_kick_drift<float><<<g, kBS, 0, s>>>(
+        n, nl.pos.as<int32_t>(), nl.soff.as<int32_t>(), (const float *)fslot, fown, F, v, x,
+        type, mass, dt, nl.xref.as<double>(), nl.conf.as<ConfDesc>(), half * half, flag, do_next);
   else
-    k_vv_second_gather<double><<<g, kBS, 0, s>>>(n, nl.order.as<int32_t>(), nl.soff.as<int32_t>(),
-                                                 (const double *)fslot, fown, F, v, type, mass, dt,
-                                                 flag);
+    k_vv_gather_kick_drift<double><<<g, kBS, 0, s>>>(
+        n, nl.pos.as<int32_t>(), nl.soff.as<int32_t>(), (const double *)fslot, fown, F, v, x,
+        type, mass, dt, nl.xref.as<double>(), nl.conf.as<ConfDesc>(), half * half, flag, do_next);
 }
 
 void launch_vv_first(int n, double *x, double *v, double *f, const int32_t *type,

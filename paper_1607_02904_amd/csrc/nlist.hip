@@ -209,13 +209,13 @@ __global__ void k_place(int n, const double *__restrict__ x, const int32_t *__re
   }
 }
 
-// order atoms inside each cell by index and copy their positions in that
-// order (xs); the counts (used as placement cursors) are cleared for the next
-// build
+// order atoms inside each cell by index, record each atom's position in the
+// cell order (pos, the inverse of order) and copy the positions in that order
+// (xs); the counts (used as placement cursors) are cleared for the next build
 __global__ void k_sort_cells(int64_t ncell, const int32_t *__restrict__ cell_start,
                              int32_t *__restrict__ order, int32_t *__restrict__ counts,
                              const double *__restrict__ x, double *__restrict__ xs,
-                             const int32_t *cond) {
+                             int32_t *__restrict__ pos, const int32_t *cond) {
   if (skip(cond)) return;
   for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < ncell;
        c += (int64_t)gridDim.x * blockDim.x) {
@@ -231,6 +231,7 @@ __global__ void k_sort_cells(int64_t ncell, const int32_t *__restrict__ cell_sta
     }
     for (int p = b; p < e; ++p) {
       const int i = order[p];
+      pos[i] = p;
       xs[3 * p] = x[3 * i];
       xs[3 * p + 1] = x[3 * i + 1];
       xs[3 * p + 2] = x[3 * i + 2];
@@ -532,16 +533,16 @@ __global__ __launch_bounds__(kBS) void k_reverse(int n, int cap, const int32_t *
 }
 
 // owner gather: fixed-order sum of the forces that every neighbour's terms put
-// on atom a (its incoming slots [soff[t], soff[t + 1]) for a = order[t]; FP32
-// in the mixed path), plus a's own part, in FP64.  Thread per position t in
-// cell order: a wavefront reads one contiguous run of slots.
+// on atom a (its incoming slots [soff[t], soff[t + 1]) for t = pos[a], the
+// position of a in cell order; FP32 in the mixed path), plus a's own part, in
+// FP64.  Thread per atom: the outputs are written contiguously.
 template <class S>
-__global__ void k_gather(int n, const int32_t *__restrict__ order,
+__global__ void k_gather(int n, const int32_t *__restrict__ pos,
                          const int32_t *__restrict__ soff, const S *__restrict__ fslot,
                          const double *__restrict__ fown, double *__restrict__ F, int accumulate) {
-  int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n) return;
-  const int a = order[t];
+  int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= n) return;
+  const int t = pos[a];
   const int s0 = soff[t], s1 = soff[t + 1];
   double fx = fown[3 * t], fy = fown[3 * t + 1], fz = fown[3 * t + 2];
   sum_slots(fslot, s0, s1, fx, fy, fz);
@@ -632,7 +633,7 @@ void nlist_build(NList &nl, const double *x, const int32_t *cond, uint32_t *err,
     k_place<<<grid(n), kBS, 0, s>>>(n, x, nl.cell_of.as<int32_t>(), cell_start, cell_count,
                                     nl.order.as<int32_t>(), nl.xref.as<double>(), cond);
     k_sort_cells<<<grid(ncell), kBS, 0, s>>>(ncell, cell_start, nl.order.as<int32_t>(), cell_count,
-                                             x, nl.xs.as<double>(), cond);
+                                             x, nl.xs.as<double>(), nl.pos.as<int32_t>(), cond);
     // the list build is latency-bound: a larger grid than the other kernels
     const int64_t groups = (n + kAtomsPerWave - 1) / kAtomsPerWave;
     const int gb = (int)std::min<int64_t>(
@@ -653,11 +654,11 @@ void launch_gather(const NList &nl, const void *fslot, bool slot_f32, const doub
   if (nl.n <= 0) return;
   if (slot_f32)
     k_gather<float><<<grid_for(nl.n, kBS), kBS, 0, s>>>(
-        nl.n, nl.order.as<int32_t>(), nl.soff.as<int32_t>(), (const float *)fslot, fown, F,
+        nl.n, nl.pos.as<int32_t>(), nl.soff.as<int32_t>(), (const float *)fslot, fown, F,
         accumulate);
   else
     k_gather<double><<<grid_for(nl.n, kBS), kBS, 0, s>>>(
-        nl.n, nl.order.as<int32_t>(), nl.soff.as<int32_t>(), (const double *)fslot, fown, F,
+        nl.n, nl.pos.as<int32_t>(), nl.soff.as<int32_t>(), (const double *)fslot, fown, F,
         accumulate);
 }
 

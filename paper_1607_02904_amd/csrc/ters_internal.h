@@ -90,6 +90,7 @@ struct NList {
   DevBuf maxcount;    // int32[1]
   DevBuf rev;         // int32[n][cap]: incoming force slot at j of row entry (i, j)
   DevBuf xs;          // double[n][3]: positions at build time, in cell order
+  DevBuf pos;         // int32[n]: position of each atom in the cell order (inverse of order)
   DevBuf soff;        // int32[n + 1]: first incoming force slot of the atom at each cell-order position
   DevBuf loff;        // int32[n]: build workgroup (high bits) and slot number within it
   DevBuf bsum;        // int32[2 * 4096]: slot total and longest row per build workgroup
@@ -130,6 +131,7 @@ struct FwdArgs {
   void *fslot;
   double *fown;
   const int32_t *rev;
+  int32_t *clear_flag;     // set to 0 by the kernel (molecular dynamics) or null
   uint32_t *err;
 };
 
@@ -139,20 +141,15 @@ void launch_fill_f64(double *p, double v, int64_t n, hipStream_t s);
 void nlist_build(NList &nl, const double *x, const int32_t *cond, uint32_t *err, hipStream_t s,
                  int64_t *rebuild_counter = nullptr);
 void nlist_check(const NList &nl, const double *x, int32_t *flag, hipStream_t s);
-// F[a] (+)= fown[t] + sum of the incoming slots fslot[soff[t] .. soff[t + 1]), a = order[t]
+// F[a] (+)= fown[t] + sum of the incoming slots fslot[soff[t] .. soff[t + 1]), t = pos[a]
 // (FP32 slots when slot_f32), summed in FP64 in slot order
 void launch_gather(const NList &nl, const void *fslot, bool slot_f32, const double *fown,
                    double *F, int accumulate, hipStream_t s);
-// molecular dynamics: gather as above into F, then v += dt/2 F/m, and clear
-// the rebuild flag for the next step
-void launch_vv_second_gather(const NList &nl, double *v, double *F, const void *fslot,
-                             bool slot_f32, const double *fown, const int32_t *type,
-                             const double *mass, double dt, int32_t *flag, hipStream_t s);
 void launch_forward(const FwdArgs &a, int precision, int atoms_per_block, int nblocks_out[1],
                     hipStream_t s);
 void launch_adjoint(const FwdArgs &a, int precision, int atoms_per_block, hipStream_t s);
 int forward_blocks(int n, int atoms_per_block);
-// wavefront schedule: atoms per wavefront (<= 32), 4 wavefronts per workgroup
+// wavefront schedule: atoms per wavefront (<= 32)
 void launch_forward_wave(const FwdArgs &a, int precision, int atoms_per_wave, hipStream_t s);
 void launch_adjoint_wave(const FwdArgs &a, int precision, int atoms_per_wave, hipStream_t s);
 int wave_blocks(int n, int atoms_per_wave, bool param_grad);
@@ -164,5 +161,12 @@ void launch_vv_first(int n, double *x, double *v, double *f, const int32_t *type
                      hipStream_t s);
 void launch_vv_second(int n, double *v, const double *f, const int32_t *type, const double *mass,
                       double dt, int32_t *flag, hipStream_t s);
+// molecular dynamics, owner-gather mode: the gather above and the second half
+// kick of this step, then (do_next) the first half kick, drift and rebuild test
+// of the next
+void launch_vv_gather_kick_drift(const NList &nl, double *x, double *v, double *F,
+                                 const void *fslot, bool slot_f32, const double *fown,
+                                 const int32_t *type, const double *mass, double dt,
+                                 int32_t *flag, int do_next, hipStream_t s);
 
 }  // namespace ters
