@@ -730,8 +730,8 @@ ters_status md_run_impl(ters_ctx *c, int32_t n, double *x, double *v, double *f,
     }
     // Owner-gather mode: the first half kick and drift of step 1 run before
     // the loop; a step is then | conditional rebuild | forces (clear the
-    // flag) | energy (trace) | gather + second half kick + first half kick,
-    // drift and rebuild test of the next step |, the last step without the
+    // flag) | gather + second half kick + first half kick, drift and rebuild
+    // test of the next step, energy (trace) |, the last step without the
     // next step's half.  Atomic-scatter mode: | kick + drift + zero F +
     // rebuild test | conditional rebuild | forces | energy | kick + clear |.
     auto step = [&](hipStream_t s, int k, bool last) {
@@ -746,15 +746,17 @@ ters_status md_run_impl(ters_ctx *c, int32_t n, double *x, double *v, double *f,
       if (force_us) TERS_HIP_TRY(hipEventRecord(ev[2 * k], s));
       run_forward(c, a, precision, s, /*do_gather=*/false);
       if (force_us) TERS_HIP_TRY(hipEventRecord(ev[2 * k + 1], s));
-      if (trace)
-        launch_reduce_partials(c->partials.as<double>(), nb, 8, c->escratch.as<double>(), nullptr,
-                               0, s, trace, c->step.as<int32_t>());
-      if (gather)
+      if (gather) {
         launch_vv_gather_kick_drift(c->nl, x, v, f, c->fslot.p, precision == TERS_MIXED,
                                     c->fown.as<double>(), type, c->mass.as<double>(), dt, flag,
-                                    last ? 0 : 1, s);
-      else
+                                    last ? 0 : 1, c->partials.as<double>(), nb,
+                                    c->escratch.as<double>(), trace, c->step.as<int32_t>(), s);
+      } else {
+        if (trace)
+          launch_reduce_partials(c->partials.as<double>(), nb, 8, c->escratch.as<double>(),
+                                 nullptr, 0, s, trace, c->step.as<int32_t>());
         launch_vv_second(n, v, f, type, c->mass.as<double>(), dt, flag, s);
+      }
     };
     launch_fill_i32(c->step.as<int32_t>(), 0, 1, nullptr, c->stream);
     launch_fill_i32(c->flag.as<int32_t>(), 0, 1, nullptr, c->stream);

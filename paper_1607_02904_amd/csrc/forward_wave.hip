@@ -425,10 +425,15 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEu<T, PG>::value))) void k_force_wave
     // own force of i (minus the sum of its slot forces; segmented sum over the
     // atom's lanes) and per-atom energy, taken by the atom's first lane
     double sx = o0, sy = o1, sz = o2, se = ev;
-    for (int s = 1; s < nmax; ++s) {
+    for (int s = 1; s < nmax && (want_f || want_ea); ++s) {
       const int src = (act && s < n_i) ? seg0 + s : lane;
-      const double tx = lane_read(o0, src), ty = lane_read(o1, src), tz = lane_read(o2, src);
-      const double te = lane_read(ev, src);
+      double tx = 0.0, ty = 0.0, tz = 0.0, te = 0.0;
+      if (want_f) {
+        tx = lane_read(o0, src);
+        ty = lane_read(o1, src);
+        tz = lane_read(o2, src);
+      }
+      if (want_ea) te = lane_read(ev, src);
       if (act && q == 0 && s < n_i) {
         sx += tx;
         sy += ty;

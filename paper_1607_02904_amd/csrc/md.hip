@@ -57,11 +57,41 @@ __global__ void k_vv_second(int n, double *__restrict__ v, const double *__restr
 }
 
 
+// Energy partials of the force kernel summed by one workgroup of kBS lanes
+// (fixed order), stored at energy and trace[*step]; *step advances.
+DEV void reduce_energy(const double *__restrict__ partials, int nblocks, double *energy,
+                       double *trace, int32_t *step) {
+  __shared__ double red[kBS / kWave];
+  constexpr int CH = 16;
+  double acc = 0.0;
+  for (int b0 = threadIdx.x; b0 < nblocks; b0 += CH * kBS) {
+    double v[CH];
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      const int b = b0 + c * kBS;
+      v[c] = b < nblocks ? partials[(int64_t)b * 8] : 0.0;
+    }
+#pragma unroll
+    for (int c = 0; c < CH; ++c) acc += v[c];
+  }
+  acc = wave_sum(acc);
+  if (lane_id() == 0) red[threadIdx.x / kWave] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double tot = 0.0;
+    for (int w = 0; w < kBS / kWave; ++w) tot += red[w];
+    *energy = tot;
+    trace[*step] = tot;
+    *step += 1;
+  }
+}
+
 // Owner gather of the forces into F (FP64 sums, in slot order, of the
 // incoming slots of the atom, [soff[t], soff[t + 1]) with t = pos[i]), the
 // second half kick of this step and, with do_next, the first half kick, drift
 // and rebuild test of the next one (the operations of k_vv_first, in the same
-// order).  Thread per atom.
+// order).  Thread per atom.  With a trace, workgroup 0 also sums the force
+// kernel's energy partials.
 template <class S>
 __global__ void k_vv_gather_kick_drift(int n, const int32_t *__restrict__ pos,
                                        const int32_t *__restrict__ soff,
@@ -72,7 +102,9 @@ __global__ void k_vv_gather_kick_drift(int n, const int32_t *__restrict__ pos,
                                        const double *__restrict__ mass, double dt,
                                        const double *__restrict__ xref,
                                        const ConfDesc *__restrict__ conf, double lim2,
-                                       int32_t *flag, int do_next) {
+                                       int32_t *flag, int do_next,
+                                       const double *__restrict__ partials, int nblocks,
+                                       double *energy, double *trace, int32_t *step) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   bool over = false;
   if (i < n) {
@@ -100,6 +132,7 @@ __global__ void k_vv_gather_kick_drift(int n, const int32_t *__restrict__ pos,
     over = do_next && !(r2 <= lim2);  // NaN counts as moved
   }
   if (__ballot(over) != 0ull && lane_id() == 0) *flag = 1;
+  if (blockIdx.x == 0 && trace) reduce_energy(partials, nblocks, energy, trace, step);
 }
 
 }  // namespace
@@ -107,18 +140,21 @@ __global__ void k_vv_gather_kick_drift(int n, const int32_t *__restrict__ pos,
 void launch_vv_gather_kick_drift(const NList &nl, double *x, double *v, double *F,
                                  const void *fslot, bool slot_f32, const double *fown,
                                  const int32_t *type, const double *mass, double dt,
-                                 int32_t *flag, int do_next, hipStream_t s) {
+                                 int32_t *flag, int do_next, const double *partials, int nblocks,
+                                 double *energy, double *trace, int32_t *step, hipStream_t s) {
   const int n = nl.n;
   const int g = (std::max(n, 1) + kBS - 1) / kBS;
   const double half = 0.5 * nl.skin;
   if (slot_f32)
     k_vv_gather_kick_drift<float><<<g, kBS, 0, s>>>(
         n, nl.pos.as<int32_t>(), nl.soff.as<int32_t>(), (const float *)fslot, fown, F, v, x,
-        type, mass, dt, nl.xref.as<double>(), nl.conf.as<ConfDesc>(), half * half, flag, do_next);
+        type, mass, dt, nl.xref.as<double>(), nl.conf.as<ConfDesc>(), half * half, flag, do_next,
+        partials, nblocks, energy, trace, step);
   else
     k_vv_gather_kick_drift<double><<<g, kBS, 0, s>>>(
         n, nl.pos.as<int32_t>(), nl.soff.as<int32_t>(), (const double *)fslot, fown, F, v, x,
-        type, mass, dt, nl.xref.as<double>(), nl.conf.as<ConfDesc>(), half * half, flag, do_next);
+        type, mass, dt, nl.xref.as<double>(), nl.conf.as<ConfDesc>(), half * half, flag, do_next,
+        partials, nblocks, energy, trace, step);
 }
 
 void launch_vv_first(int n, double *x, double *v, double *f, const int32_t *type,

@@ -163,10 +163,12 @@ void launch_vv_second(int n, double *v, const double *f, const int32_t *type, co
                       double dt, int32_t *flag, hipStream_t s);
 // molecular dynamics, owner-gather mode: the gather above and the second half
 // kick of this step, then (do_next) the first half kick, drift and rebuild test
-// of the next
+// of the next; when trace is set, the force kernel's energy partials are also
+// summed (fixed order) into energy and trace[*step], and *step advances
 void launch_vv_gather_kick_drift(const NList &nl, double *x, double *v, double *F,
                                  const void *fslot, bool slot_f32, const double *fown,
                                  const int32_t *type, const double *mass, double dt,
-                                 int32_t *flag, int do_next, hipStream_t s);
+                                 int32_t *flag, int do_next, const double *partials, int nblocks,
+                                 double *energy, double *trace, int32_t *step, hipStream_t s);
 
 }  // namespace ters
