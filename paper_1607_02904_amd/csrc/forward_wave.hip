@@ -74,7 +74,6 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEu<T, PG>::value))) void k_force_wave
   __shared__ int s_stage[kWPB][kAMax * kNMax];
   __shared__ unsigned char s_slot[kWPB][kAMax * kNMax];  // list slot of each staged neighbour
   __shared__ unsigned short s_map[kWPB][kWave];  // filter window: (atom << 8) | slot
-  __shared__ unsigned char s_pa[kWPB][kWave], s_pq[kWPB][kWave];
   __shared__ KP s_kp[NT1 ? 1 : NTL];
   __shared__ double s_g[PG && !NT1 ? NTL * kNField : 1];
   __shared__ double s_red[kWPB][8];
@@ -212,18 +211,27 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEu<T, PG>::value))) void k_force_wave
     const uint64_t fits = __ballot(lane >= a0 && lane < na && incl - base <= kWave);
     const int a1 = a0 + __popcll(fits);  // >= a0 + 1: one atom has at most 32 pairs
     const int np = __shfl(incl, a1 - 1, kWave) - base;
-    // pair map of this round
-    if (lane >= a0 && lane < a1) {
+    // pair map of this round: an atom's pairs occupy the slots from its start
+    // on, so the atom of slot p is the last one starting at or before p; each
+    // atom marks its start with (start << 8 | atom + 1) and a prefix maximum
+    // over the slots recovers both
+    s_map[w][lane] = 0;
+    wave_sync();
+    if (lane >= a0 && lane < a1 && my_n > 0) {
       const int b = incl - my_n - base;
-      for (int q = 0; q < my_n; ++q) {
-        s_pa[w][b + q] = (unsigned char)lane;
-        s_pq[w][b + q] = (unsigned char)q;
-      }
+      s_map[w][b] = (unsigned short)((b << 8) | (lane + 1));
     }
     wave_sync();
+    int pm = s_map[w][lane];
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      const int u = __shfl_up(pm, o, kWave);
+      if (lane >= o) pm = max(pm, u);
+    }
+    wave_sync();  // s_map is rewritten in the next round
     const bool act = lane < np;
-    const int at = act ? s_pa[w][lane] : a0;
-    const int q = act ? s_pq[w][lane] : 0;
+    const int at = act ? (pm & 0xff) - 1 : a0;
+    const int q = act ? lane - (pm >> 8) : 0;
     const int n_i = lane_read(my_n, at);
     const int seg0 = lane - q;  // first lane of this atom's pairs
     const int i = lane_read(my_i, at), ti = lane_read(my_t, at), cf = lane_read(my_cf, at);
