@@ -100,8 +100,12 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEu<T, PG>::value))) void k_force_wave
     for (int e = tid; e < NTL * kNField; e += kWPB * kWave) s_g[e] = 0.0;
   if (!NT1) __syncthreads();  // the only workgroup barrier before the final reductions
 
+  // one species: the record is read once into registers (uniform, scalar
+  // loads) instead of from memory inside the K loops
+  KP kp0;
+  if (NT1) kp0 = P[0];
   auto param = [&](int ti, int tj, int tk) -> const KP & {
-    return NT1 ? P[0] : P[(ti * nt + tj) * nt + tk];
+    return NT1 ? kp0 : P[(ti * nt + tj) * nt + tk];
   };
   const double *filt2 = (const double *)a.filt2;
   double gacc[NT1 && PG ? kNField : 1];
