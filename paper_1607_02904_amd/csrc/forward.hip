@@ -84,8 +84,12 @@ __global__ __launch_bounds__(BS) void k_force(FwdArgs a, int A) {
   } else {
     P = (const KP *)a.kparam;
   }
+  // one species: the record is read once into registers (uniform, scalar
+  // loads) instead of from memory in the inner loops
+  KP kp0;
+  if (NT1) kp0 = P[0];
   auto param = [&](int ti, int tj, int tk) -> const KP & {
-    return NT1 ? P[0] : P[(ti * nt + tj) * nt + tk];
+    return NT1 ? kp0 : P[(ti * nt + tj) * nt + tk];
   };
   const double *filt2 = (const double *)a.filt2;
 
