@@ -19,6 +19,8 @@
 #include "ters_internal.h"
 #include "ters_math.h"
 
+#include <type_traits>
+
 namespace ters {
 
 namespace {
@@ -67,6 +69,11 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEu<T, PG>::value))) void k_force_wave
   using B = base_t<T>;
   using KP = KParam<B>;
   using AT = acc_t<T>;
+  // the force of atom i's terms on one neighbour (a sum of a few terms, stored
+  // in one slot) is accumulated in the kernel's arithmetic type in the mixed
+  // path, in FP64 otherwise; atom forces, energy and virial stay FP64
+  using FA = typename std::conditional<std::is_same<T, float>::value, float, AT>::type;
+  auto to_fa = [](const auto &v) -> FA { return (FA)v; };
   constexpr bool DUAL = IsDual<T>::value;
   constexpr int NTL = 27;
 
@@ -301,7 +308,7 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEu<T, PG>::value))) void k_force_wave
     }
     // pair term V(i, j, zeta)
     T dzeta = Zero<T>::get();
-    AT f0 = Zero<AT>::get(), f1 = Zero<AT>::get(), f2 = Zero<AT>::get();
+    FA f0 = Zero<FA>::get(), f1 = Zero<FA>::get(), f2 = Zero<FA>::get();
     double ev = 0.0;
     const double eb = DUAL ? (a.ebar_conf ? a.ebar_conf[cf] : a.ebar) : 1.0;
     if (in_pair) {
@@ -314,9 +321,9 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEu<T, PG>::value))) void k_force_wave
       const T dVdr = dfc * vr + fc * (-pp.lam1 * fr - pp.lam2 * b * fa);
       dzeta = B(0.5) * fc * fa * db;
       const T hp = B(0.5) * dVdr;
-      f0 = widen(-(hp * u[0]));
-      f1 = widen(-(hp * u[1]));
-      f2 = widen(-(hp * u[2]));
+      f0 = to_fa(widen(-(hp * u[0])));
+      f1 = to_fa(widen(-(hp * u[1])));
+      f2 = to_fa(widen(-(hp * u[2])));
       ev = 0.5 * val(V);
       if (PG) {
         const T h = T(B(0.5)) * fc;
@@ -353,9 +360,9 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEu<T, PG>::value))) void k_force_wave
           const T v[3] = {kx * kri, ky * kri, kz * kri};
           T gj[3], gk[3], dp[8];
           zeta_term<T, B, PG>(pk, r, ri, u, kr, kri, v, fck, dfck, gj, gk, dp);
-          f0 -= widen(dzeta * gj[0]);
-          f1 -= widen(dzeta * gj[1]);
-          f2 -= widen(dzeta * gj[2]);
+          f0 -= to_fa(widen(dzeta * gj[0]));
+          f1 -= to_fa(widen(dzeta * gj[1]));
+          f2 -= to_fa(widen(dzeta * gj[2]));
           cx = -(dzeta * gk[0]);
           cy = -(dzeta * gk[1]);
           cz = -(dzeta * gk[2]);
@@ -369,9 +376,9 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEu<T, PG>::value))) void k_force_wave
       // pull the force that lane (i, bq) computed for my atom in this step
       const T rx = lane_read(cx, bsrc), ry = lane_read(cy, bsrc), rz = lane_read(cz, bsrc);
       if (live) {
-        f0 += widen(rx);
-        f1 += widen(ry);
-        f2 += widen(rz);
+        f0 += to_fa(widen(rx));
+        f1 += to_fa(widen(ry));
+        f2 += to_fa(widen(rz));
       }
     }
 
