@@ -355,7 +355,8 @@ ters_status ters_create(ters_ctx **out, int device, void *stream) {
     c->flag.ensure(64);
     c->rebuilds.ensure(64);
     c->step.ensure(64);
-    c->escratch.ensure(64);
+    c->escratch.ensure(256);  // energy, per-workgroup energy sums, completion counter
+    TERS_HIP_TRY(hipMemsetAsync(c->escratch.p, 0, 256, c->stream));
     TERS_HIP_TRY(hipMemsetAsync(c->errw.p, 0, 64, c->stream));
     TERS_HIP_TRY(hipMemsetAsync(c->rebuilds.p, 0, 64, c->stream));
     sync(c);

@@ -57,32 +57,40 @@ __global__ void k_vv_second(int n, double *__restrict__ v, const double *__restr
 }
 
 
-// Energy partials of the force kernel summed by one workgroup of kBS lanes
-// (fixed order), stored at energy and trace[*step]; *step advances.
-DEV void reduce_energy(const double *__restrict__ partials, int nblocks, double *energy,
-                       double *trace, int32_t *step) {
+// Energy partials of the force kernel summed by the first kRedBlocks
+// workgroups: workgroup b sums slice b (fixed order) into esum[b]; the last of
+// them to finish (a counter, no waiting) adds esum[0..kRedBlocks) in index
+// order, stores the energy at energy and trace[*step], advances *step and
+// resets the counter.  The result does not depend on which workgroup is last.
+constexpr int kRedBlocks = 16;
+DEV void reduce_energy(const double *__restrict__ partials, int nblocks, double *esum,
+                       int32_t *count, double *energy, double *trace, int32_t *step) {
   __shared__ double red[kBS / kWave];
-  constexpr int CH = 16;
+  __shared__ int s_last;
+  const int b = blockIdx.x;
+  const int per = (nblocks + kRedBlocks - 1) / kRedBlocks;
+  const int lo = b * per, hi = min(nblocks, lo + per);
   double acc = 0.0;
-  for (int b0 = threadIdx.x; b0 < nblocks; b0 += CH * kBS) {
-    double v[CH];
-#pragma unroll
-    for (int c = 0; c < CH; ++c) {
-      const int b = b0 + c * kBS;
-      v[c] = b < nblocks ? partials[(int64_t)b * 8] : 0.0;
-    }
-#pragma unroll
-    for (int c = 0; c < CH; ++c) acc += v[c];
-  }
+  for (int k = lo + (int)threadIdx.x; k < hi; k += kBS) acc += partials[(int64_t)k * 8];
   acc = wave_sum(acc);
   if (lane_id() == 0) red[threadIdx.x / kWave] = acc;
   __syncthreads();
   if (threadIdx.x == 0) {
     double tot = 0.0;
     for (int w = 0; w < kBS / kWave; ++w) tot += red[w];
-    *energy = tot;
-    trace[*step] = tot;
-    *step += 1;
+    __hip_atomic_store(&esum[b], tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __threadfence();
+    s_last = atomicAdd(count, 1) == kRedBlocks - 1;
+    if (s_last) {
+      __threadfence();
+      double e = 0.0;
+      for (int k = 0; k < kRedBlocks; ++k)
+        e += __hip_atomic_load(&esum[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      *energy = e;
+      trace[*step] = e;
+      *step += 1;
+      *count = 0;
+    }
   }
 }
 
@@ -90,8 +98,8 @@ DEV void reduce_energy(const double *__restrict__ partials, int nblocks, double 
 // incoming slots of the atom, [soff[t], soff[t + 1]) with t = pos[i]), the
 // second half kick of this step and, with do_next, the first half kick, drift
 // and rebuild test of the next one (the operations of k_vv_first, in the same
-// order).  Thread per atom.  With a trace, workgroup 0 also sums the force
-// kernel's energy partials.
+// order).  Thread per atom.  With a trace, the first workgroups also sum the
+// force kernel's energy partials.
 template <class S>
 __global__ void k_vv_gather_kick_drift(int n, const int32_t *__restrict__ pos,
                                        const int32_t *__restrict__ soff,
@@ -104,7 +112,8 @@ __global__ void k_vv_gather_kick_drift(int n, const int32_t *__restrict__ pos,
                                        const ConfDesc *__restrict__ conf, double lim2,
                                        int32_t *flag, int do_next,
                                        const double *__restrict__ partials, int nblocks,
-                                       double *energy, double *trace, int32_t *step) {
+                                       double *esum, int32_t *count, double *energy,
+                                       double *trace, int32_t *step) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   bool over = false;
   if (i < n) {
@@ -132,7 +141,8 @@ __global__ void k_vv_gather_kick_drift(int n, const int32_t *__restrict__ pos,
     over = do_next && !(r2 <= lim2);  // NaN counts as moved
   }
   if (__ballot(over) != 0ull && lane_id() == 0) *flag = 1;
-  if (blockIdx.x == 0 && trace) reduce_energy(partials, nblocks, energy, trace, step);
+  if (blockIdx.x < kRedBlocks && trace)
+    reduce_energy(partials, nblocks, esum, count, energy, trace, step);
 }
 
 }  // namespace
@@ -143,18 +153,20 @@ void launch_vv_gather_kick_drift(const NList &nl, double *x, double *v, double *
                                  int32_t *flag, int do_next, const double *partials, int nblocks,
                                  double *energy, double *trace, int32_t *step, hipStream_t s) {
   const int n = nl.n;
-  const int g = (std::max(n, 1) + kBS - 1) / kBS;
+  const int g = std::max((std::max(n, 1) + kBS - 1) / kBS, kRedBlocks);
   const double half = 0.5 * nl.skin;
+  double *esum = energy + 8;  // the energy scratch holds 8 + kRedBlocks doubles
+  int32_t *count = (int32_t *)(energy + 8 + kRedBlocks);
   if (slot_f32)
     k_vv_gather_kick_drift<float><<<g, kBS, 0, s>>>(
         n, nl.pos.as<int32_t>(), nl.soff.as<int32_t>(), (const float *)fslot, fown, F, v, x,
         type, mass, dt, nl.xref.as<double>(), nl.conf.as<ConfDesc>(), half * half, flag, do_next,
-        partials, nblocks, energy, trace, step);
+        partials, nblocks, esum, count, energy, trace, step);
   else
     k_vv_gather_kick_drift<double><<<g, kBS, 0, s>>>(
         n, nl.pos.as<int32_t>(), nl.soff.as<int32_t>(), (const double *)fslot, fown, F, v, x,
         type, mass, dt, nl.xref.as<double>(), nl.conf.as<ConfDesc>(), half * half, flag, do_next,
-        partials, nblocks, energy, trace, step);
+        partials, nblocks, esum, count, energy, trace, step);
 }
 
 void launch_vv_first(int n, double *x, double *v, double *f, const int32_t *type,

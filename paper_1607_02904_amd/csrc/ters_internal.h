@@ -164,7 +164,8 @@ void launch_vv_second(int n, double *v, const double *f, const int32_t *type, co
 // molecular dynamics, owner-gather mode: the gather above and the second half
 // kick of this step, then (do_next) the first half kick, drift and rebuild test
 // of the next; when trace is set, the force kernel's energy partials are also
-// summed (fixed order) into energy and trace[*step], and *step advances
+// summed (fixed order) into energy[0] and trace[*step], and *step advances;
+// energy points to a zero-initialised scratch of 8 + 16 doubles and a counter
 void launch_vv_gather_kick_drift(const NList &nl, double *x, double *v, double *F,
                                  const void *fslot, bool slot_f32, const double *fown,
                                  const int32_t *type, const double *mass, double dt,
