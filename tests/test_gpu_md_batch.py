@@ -197,3 +197,22 @@ def test_batch_graph_replays_and_adjoint(batch_setup):
         assert np.allclose(xg_all[off[c]:off[c + 1]], xgc.cpu().numpy(), rtol=1e-11, atol=1e-12)
     assert np.allclose(outs[0][4], pg_sum, rtol=1e-11, atol=1e-12)
     plan.close()
+
+
+def test_md_run_timed_matches_md_run(si_model):
+    """The timed MD entry point runs the same steps (launched one by one, with
+    events around the force kernel) and reports a positive kernel time."""
+    x, t, box = inputs.si_bulk(ncell=5, seed=25)
+    a = _md_gpu(si_model, x, t, box, 12, 0.3, use_graph=True)
+    xd = torch.as_tensor(x, device="cuda").clone()
+    td = torch.as_tensor(t, device="cuda")
+    v = torch.zeros_like(xd)
+    f = torch.empty_like(xd)
+    si_model.build_nlist(xd, td, box, 0.3)
+    si_model.compute(xd, td, box, 0, energy=False, virial=False, out={"forces": f})
+    tr, us = si_model.md_run_timed(xd, v, f, td, box, 0.001, 12, 0.3, 0)
+    torch.cuda.synchronize()
+    si_model.sync()
+    assert us > 0.0
+    assert np.array_equal(xd.cpu().numpy(), a[0])
+    assert np.array_equal(tr.cpu().numpy()[:12], a[3])
