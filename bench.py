@@ -6,8 +6,9 @@ dt = 1 fs.  One step = one velocity-Verlet step: half kick + drift (with the
 rebuild test), neighbour rebuild when due, one full energy/force evaluation,
 half kick.  `value` is the mixed-precision path (FP32 arithmetic, FP64
 accumulators); the FP64 path is measured in the same run.  Also reported:
-two-species SiC 1,000,000 atoms (one mixed evaluation), and a batch of 1,024
-uneven SiC configurations evaluated forward + adjoint in one graph launch.
+two-species SiC 1,000,000 atoms (one mixed evaluation), a batch of 1,024
+uneven SiC configurations evaluated forward + adjoint in one graph launch, and
+the total energy along a 100,000-step NVE run (32,768 atoms) in FP64 and mixed.
 
 Prints one JSON line.  Options: --gpus N (only 1 is supported), --steps K,
 --warmup W, --no-cpu (skip the CPU baseline), --quick (smaller extras).
@@ -231,6 +232,10 @@ def main():
     if not args.md_only:
         run_batch(args, out, dev)
 
+    # ---- long NVE run: mixed vs FP64 energy (the paper's accuracy check) ------
+    if not args.md_only:
+        run_accuracy(args, out, dev)
+
     # ---- CPU baseline: the FP64 oracle on the host ----------------------------
     if not args.no_cpu:
         print("bench: cpu baseline", file=sys.stderr, flush=True)
@@ -253,6 +258,55 @@ def main():
                                          "build and integration not timed" % (reps, n)}
     model.close()
     print(json.dumps(out), flush=True)
+
+
+FTM2V = 9648.533212331  # eV/(Angstrom amu) -> Angstrom/ps^2 (metal units)
+
+
+def run_accuracy(args, out, dev):
+    """Total energy along a long NVE trajectory of Si diamond 16^3 cells
+    (32,768 atoms, sigma 0.1 A, v0 = 0, dt 1 fs, skin 0.5 A) in FP64 and in the
+    mixed precision: the largest relative difference of the mixed total energy
+    from the FP64 one, and each path's largest total-energy deviation per atom
+    from its start.  The paper checks its mixed mode the same way (a long run
+    of about 32,000 Si atoms, FP64 as reference)."""
+    import torch
+
+    from paper_1607_02904_amd import inputs
+    from paper_1607_02904_amd.tersoff import FP64, MIXED, Tersoff, table_element
+    print("bench: accuracy run", file=sys.stderr, flush=True)
+    steps = 10000 if args.quick else 100000
+    chunk = 2000
+    x, t, box = inputs.si_bulk(16, seed=inputs.seed_for(6))
+    n = len(x)
+    mass = 28.0855
+    m = Tersoff(table_element("Si(B)"), masses=[mass])
+    td = torch.as_tensor(t, device=dev)
+    series = {}
+    t0 = time.perf_counter()
+    for prec in (FP64, MIXED):
+        xd = torch.as_tensor(x, device=dev).clone()
+        v = torch.zeros_like(xd)
+        f = torch.empty_like(xd)
+        m.build_nlist(xd, td, box, 0.5)
+        e0 = m.compute(xd, td, box, prec, virial=False, out={"forces": f})["energy"]
+        etot = [float(e0.item())]
+        trace = torch.empty(chunk, dtype=torch.float64, device=dev)
+        for _ in range(steps // chunk):
+            m.md_run(xd, v, f, td, box, 0.001, chunk, 0.5, prec, trace=trace)
+            ke = 0.5 * mass * float((v * v).sum().item()) / FTM2V
+            etot.append(float(trace[chunk - 1].item()) + ke)
+        series[prec] = np.array(etot)
+    el = time.perf_counter() - t0
+    m.close()
+    e64, emx = series[FP64], series[MIXED]
+    out["accuracy"] = {
+        "atoms": n, "steps": steps, "dt_fs": 1.0, "sample_every": chunk,
+        "max_rel_dev_mixed_vs_fp64": float(np.max(np.abs(emx - e64) / np.abs(e64))),
+        "max_drift_per_atom_fp64_eV": float(np.max(np.abs(e64 - e64[0])) / n),
+        "max_drift_per_atom_mixed_eV": float(np.max(np.abs(emx - emx[0])) / n),
+        "seconds": el,
+    }
 
 
 def run_batch(args, out, dev):
