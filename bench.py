@@ -130,7 +130,7 @@ def main():
         us = model.autotune(x0, td, box, prec)
         tuned[prec] = us
 
-    def run_md(precision):
+    def run_md(precision, skin=skin, kernel_times=True):
         xd = x0.clone()
         v = torch.zeros_like(xd)
         f = torch.empty_like(xd)
@@ -148,6 +148,8 @@ def main():
         model.sync()
         reb = model.rebuilds() - r0
         tr = trace[:args.steps].cpu().numpy()
+        if not kernel_times:
+            return el, reb, tr, None
         # force-kernel duration: HIP events on the library's stream around every
         # force launch of K further steps of the same trajectory (launched one
         # by one; the timed region above replays the captured step)
@@ -178,6 +180,32 @@ def main():
                 "kernel_us_back_to_back": us_b2b,
                 "flops_per_launch": fl, "units": {"entries": L, "pairs": P, "triplets": T}}
 
+    # ablation of the paper's design choices on this hardware: time to forces
+    # (force kernel, plus the gather pass in owner-gather mode; back-to-back
+    # launches on the start configuration) for the workgroup schedule (Alg. 3
+    # with k_max) and the wavefront schedule (the cyclic-K order of Alg. 2),
+    # owner gather vs FP64 atomic scatter; and whole MD steps with skin 0
+    # (rebuild every step) vs the skin of the headline run
+    ablation = None
+    if not args.md_only:
+        print("bench: ablation", file=sys.stderr, flush=True)
+        fk = {}
+        for prec, tag in ((MIXED, "mixed"), (FP64, "fp64")):
+            for kern, atoms, name in ((1, 64, "workgroup_64"), (2, 32, "wavefront_32")):
+                for gather in (True, False):
+                    model.set_schedule(kern, atoms, 0)
+                    model.set_force_mode(gather)
+                    fk["%s_%s_%s" % (tag, name, "gather" if gather else "atomic")] = \
+                        model.profile_forward(x0, td, box, prec, reps=10, with_gather=True)
+        model.set_force_mode(True)
+        model.set_schedule(sched["mixed"]["kernel"], sched["mixed"]["atoms"], 0)
+        el0, reb0, _, _ = run_md(MIXED, skin=0.0, kernel_times=False)
+        ablation = {"time_to_forces_us": fk,
+                    "md_mixed_atom_steps_per_s": {"skin_0": n * args.steps / el0,
+                                                  "skin_%g" % skin: n * args.steps / elmx},
+                    "md_mixed_rebuilds": {"skin_0": reb0, "skin_%g" % skin: rebmx},
+                    "schedule_in_md_runs": sched["mixed"]}
+
     value = n * args.steps / elmx
     out = {
         "metric": "Tersoff atom-steps/s: FP64 vs mixed vs batched on 1 MI355X; % vector peak",
@@ -200,6 +228,7 @@ def main():
                  "ms_per_step": 1000.0 * el64 / args.steps, "rebuilds": reb64,
                  "schedule": sched["fp64"], "roofline": roof(f64us, k64, FP64_PEAK, sched["fp64"],
                                                               "double")},
+        "ablation": ablation,
         "mixed": {"rebuilds": rebmx, "schedule": sched["mixed"],
                   "energy_drift_per_atom": float((trmx[-1] - trmx[0]) / n),
                   "fp64_vs_mixed_energy_rel": float(abs(trmx[-1] - tr64[-1]) / abs(tr64[-1]))},

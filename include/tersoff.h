@@ -230,9 +230,13 @@ ters_status ters_autotune(ters_ctx *ctx, int32_t n, const double *x, const int32
 /* Average duration in microseconds of the force kernel alone (energy, forces
  * and virial, no output zeroing or final reduction), from HIP events around
  * `reps` back-to-back launches on the context's stream, with the current list
- * (synchronises).  Forces go to internal scratch. */
+ * (synchronises).  with_gather != 0 adds, in owner-gather mode, the pass that
+ * sums each atom's slots into its force, so that the time covers all work up
+ * to the forces (it has no effect in scatter mode).  Forces go to internal
+ * scratch. */
 ters_status ters_profile_forward(ters_ctx *ctx, int32_t n, const double *x, const int32_t *type,
-                                 const double *box, int precision, int32_t reps, double *avg_us);
+                                 const double *box, int precision, int32_t reps,
+                                 int32_t with_gather, double *avg_us);
 
 /* ---- parameter tables (Si/C mixing rules, Tersoff 1989) -------------------
  * Fill a host table [2][2][2][14] for species 0 = Si (Tersoff's Si(C) set),

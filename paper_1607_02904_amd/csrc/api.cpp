@@ -661,7 +661,8 @@ ters_status ters_autotune(ters_ctx *c, int32_t n, const double *x, const int32_t
 }
 
 ters_status ters_profile_forward(ters_ctx *c, int32_t n, const double *x, const int32_t *type,
-                                 const double *box, int precision, int32_t reps, double *avg_us) {
+                                 const double *box, int precision, int32_t reps,
+                                 int32_t with_gather, double *avg_us) {
   if (!c || !avg_us) return TERS_ERR_INVALID_ARG;
   return guard(c, [&]() {
     require(precision == TERS_FP64 || precision == TERS_MIXED, TERS_ERR_INVALID_ARG, "bad precision");
@@ -685,9 +686,14 @@ ters_status ters_profile_forward(ters_ctx *c, int32_t n, const double *x, const 
     TERS_HIP_TRY(hipEventCreate(&e0));
     TERS_HIP_TRY(hipEventCreate(&e1));
     const int kern = c->kern[precision], A = c->A[precision];
-    launch_fwd(kern, a, precision, A, c->stream);  // warm-up
+    const bool gath = with_gather && c->gather;
+    auto one = [&]() {
+      launch_fwd(kern, a, precision, A, c->stream);
+      if (gath) launch_gather(c->nl, a.fslot, precision == TERS_MIXED, a.fown, a.forces, 1, c->stream);
+    };
+    one();  // warm-up
     TERS_HIP_TRY(hipEventRecord(e0, c->stream));
-    for (int r = 0; r < reps; ++r) launch_fwd(kern, a, precision, A, c->stream);
+    for (int r = 0; r < reps; ++r) one();
     TERS_HIP_TRY(hipEventRecord(e1, c->stream));
     TERS_HIP_TRY(hipEventSynchronize(e1));
     float ms = 0.f;

@@ -84,6 +84,14 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEu<T, PG>::value))) void k_force_wave
   __shared__ KP s_kp[NT1 ? 1 : NTL];
   __shared__ double s_g[PG && !NT1 ? NTL * kNField : 1];
   __shared__ double s_red[kWPB][8];
+  // Without the parameter gradient the first K loop already evaluates the
+  // whole three-body term (value and both gradients); the gradient wrt x_k of
+  // the first kKeep steps waits here, per lane, for dV/dzeta, and the one wrt
+  // x_j is summed over k.  Later steps (atoms with more neighbours) evaluate
+  // the term again in the second loop.
+  constexpr bool kOnePass = !PG && !DUAL;
+  constexpr int kKeep = 4;
+  __shared__ T s_gk[kOnePass ? kWPB : 1][kOnePass ? kKeep : 1][3][kWave];
 
   const int tid = threadIdx.x;
   // molecular dynamics: the list kernels of this step have read the rebuild
@@ -289,21 +297,35 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEu<T, PG>::value))) void k_force_wave
     const KP &pp = param(ti, tj, tj);
     const bool in_pair = act && val(r) < pp.rcut;
     T zeta = Zero<T>::get();
+    T gs[3] = {Zero<T>::get(), Zero<T>::get(), Zero<T>::get()};  // sum over kept k of dzeta/dx_j
     for (int s = 1; s < nmax; ++s) {
+      const bool keep = kOnePass && s <= kKeep;  // uniform
       const int kq = q + s < n_i ? q + s : q + s - n_i;
       const int src = act && s < n_i ? seg0 + kq : lane;
       const T kx = lane_read(dx, src), ky = lane_read(dy, src), kz = lane_read(dz, src);
       const T kr = lane_read(r, src), kri = lane_read(ri, src);
       const T kfc = lane_read(fc, src), kdfc = lane_read(dfc, src);
       const int tk = NT1 ? 0 : lane_read(tj, src);
+      T gk[3] = {Zero<T>::get(), Zero<T>::get(), Zero<T>::get()};
       if (in_pair && s < n_i) {
         const KP &pk = param(ti, tj, tk);
         if (val(kr) < pk.rcut) {
           T fck = kfc, dfck = kdfc;
           if (!a.cut_consistent) fcut(pk, kr, fck, dfck);
           const T v[3] = {kx * kri, ky * kri, kz * kri};
-          zeta += zeta_value<T, B>(pk, r, u, kr, v, fck);
+          if (keep) {
+            T gj[3], dp[8];
+            zeta += zeta_term<T, B, false>(pk, r, ri, u, kr, kri, v, fck, dfck, gj, gk, dp);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) gs[c] += gj[c];
+          } else {
+            zeta += zeta_value<T, B>(pk, r, u, kr, v, fck);
+          }
         }
+      }
+      if (keep) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) s_gk[kOnePass ? w : 0][keep ? s - 1 : 0][c][lane] = gk[c];
       }
     }
     // pair term V(i, j, zeta)
@@ -324,6 +346,11 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEu<T, PG>::value))) void k_force_wave
       f0 = to_fa(widen(-(hp * u[0])));
       f1 = to_fa(widen(-(hp * u[1])));
       f2 = to_fa(widen(-(hp * u[2])));
+      if (kOnePass) {
+        f0 -= to_fa(widen(dzeta * gs[0]));
+        f1 -= to_fa(widen(dzeta * gs[1]));
+        f2 -= to_fa(widen(dzeta * gs[2]));
+      }
       ev = 0.5 * val(V);
       if (PG) {
         const T h = T(B(0.5)) * fc;
@@ -347,11 +374,19 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEu<T, PG>::value))) void k_force_wave
       const int bq = q - s >= 0 ? q - s : q - s + n_i;       // lane whose k is me
       const int src = live ? seg0 + kq : lane;
       const int bsrc = live ? seg0 + bq : lane;
+      T cx = Zero<T>::get(), cy = Zero<T>::get(), cz = Zero<T>::get();  // force sent to k
+      if (kOnePass && s <= kKeep) {  // uniform: the term was evaluated in the first loop
+        if (live && in_pair && val(dzeta) != B(0)) {
+          const int sk = kOnePass && s <= kKeep ? s - 1 : 0;
+          cx = -(dzeta * s_gk[kOnePass ? w : 0][sk][0][lane]);
+          cy = -(dzeta * s_gk[kOnePass ? w : 0][sk][1][lane]);
+          cz = -(dzeta * s_gk[kOnePass ? w : 0][sk][2][lane]);
+        }
+      } else {
       const T kx = lane_read(dx, src), ky = lane_read(dy, src), kz = lane_read(dz, src);
       const T kr = lane_read(r, src), kri = lane_read(ri, src);
       const T kfc = lane_read(fc, src), kdfc = lane_read(dfc, src);
       const int tk = NT1 ? 0 : lane_read(tj, src);
-      T cx = Zero<T>::get(), cy = Zero<T>::get(), cz = Zero<T>::get();  // force sent to k
       if (live && in_pair && val(dzeta) != B(0)) {
         const KP &pk = param(ti, tj, tk);
         if (val(kr) < pk.rcut) {
@@ -372,6 +407,7 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEu<T, PG>::value))) void k_force_wave
               add_grad(ti, tj, tk, GradSlots::three[fl], out_of(widen(dzeta * dp[fl]), eb));
           }
         }
+      }
       }
       // pull the force that lane (i, bq) computed for my atom in this step
       const T rx = lane_read(cx, bsrc), ry = lane_read(cy, bsrc), rz = lane_read(cz, bsrc);

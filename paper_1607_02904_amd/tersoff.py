@@ -81,7 +81,7 @@ def load_library(path=LIB_PATH):
         "ters_set_force_mode": [P, I32],
         "ters_get_schedule": [P, I32, P],
         "ters_autotune": [P, I32, P, P, P, ctypes.c_int, P],
-        "ters_profile_forward": [P, I32, P, P, P, ctypes.c_int, I32, P],
+        "ters_profile_forward": [P, I32, P, P, P, ctypes.c_int, I32, I32, P],
         "ters_table_sic": [P],
         "ters_table_element": [I32, P],
     }
@@ -221,13 +221,14 @@ class Tersoff:
                                         ctypes.byref(us)))
         return us.value
 
-    def profile_forward(self, x, types, box, precision=FP64, reps=20):
-        """Average force-kernel duration in microseconds (HIP events)."""
+    def profile_forward(self, x, types, box, precision=FP64, reps=20, with_gather=False):
+        """Average force-kernel duration in microseconds (HIP events); with
+        with_gather the owner-gather pass is included."""
         self._bind_stream()
         b, bp = _hostbuf(box, np.float64)
         us = ctypes.c_double()
         self._chk(self._L.ters_profile_forward(self._h, x.shape[0], _ptr(x), _ptr(types), bp, precision,
-                                               int(reps), ctypes.byref(us)))
+                                               int(reps), int(bool(with_gather)), ctypes.byref(us)))
         return us.value
 
     # -- evaluation --------------------------------------------------------------
