@@ -113,7 +113,7 @@ __global__ __launch_bounds__(BS) void k_force(FwdArgs a, int A) {
 
   // ---- 0: atoms of this workgroup ----------------------------------------
   for (int at = tid; at < na; at += BS) {
-    int i = a.order[first + at];
+    int i = (int)(first + at);  // cell-order position
     s_atom[at] = i;
     s_type[at] = NT1 ? 0 : a.type[i];
     s_lcnt[at] = min(a.count[i], a.cap);
@@ -456,9 +456,10 @@ __global__ __launch_bounds__(BS) void k_force(FwdArgs a, int A) {
           }
         } else {
           double *dst = DUAL ? a.xgrad : a.forces;
-          atomic_add(&dst[3 * j + 0], o0);
-          atomic_add(&dst[3 * j + 1], o1);
-          atomic_add(&dst[3 * j + 2], o2);
+          const int64_t aj = a.order[j];
+          atomic_add(&dst[3 * aj + 0], o0);
+          atomic_add(&dst[3 * aj + 1], o1);
+          atomic_add(&dst[3 * aj + 2], o2);
         }
       }
       s_fx[p] = f[0];
@@ -491,14 +492,15 @@ __global__ __launch_bounds__(BS) void k_force(FwdArgs a, int A) {
           fo[2] = o2;
         } else {
           double *dst = DUAL ? a.xgrad : a.forces;
-          atomic_add(&dst[3 * i + 0], o0);
-          atomic_add(&dst[3 * i + 1], o1);
-          atomic_add(&dst[3 * i + 2], o2);
+          const int64_t ai = a.order[i];
+          atomic_add(&dst[3 * ai + 0], o0);
+          atomic_add(&dst[3 * ai + 1], o1);
+          atomic_add(&dst[3 * ai + 2], o2);
         }
       }
       if (want_ea) {
-        if (flags & TERS_ACCUMULATE) a.e_atom[i] += e;
-        else a.e_atom[i] = e;
+        if (flags & TERS_ACCUMULATE) a.e_atom[a.order[i]] += e;
+        else a.e_atom[a.order[i]] = e;
       }
     }
     __syncthreads();

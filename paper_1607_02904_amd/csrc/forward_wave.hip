@@ -27,6 +27,7 @@ namespace {
 
 constexpr int kNMax = 32;  // most in-cutoff neighbours of one atom
 constexpr int kAMax = 32;  // most atoms per wavefront
+constexpr int kBatch = 4;  // filter windows whose loads are issued together
 
 // Wavefronts per workgroup.  One: the wavefronts share nothing, so each starts
 // and retires on its own instead of holding its workgroup's registers until
@@ -80,7 +81,7 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEu<T, PG>::value))) void k_force_wave
   // per-wavefront scratch (no sharing between wavefronts)
   __shared__ int s_stage[kWPB][kAMax * kNMax];
   __shared__ unsigned char s_slot[kWPB][kAMax * kNMax];  // list slot of each staged neighbour
-  __shared__ unsigned short s_map[kWPB][kWave];  // filter window: (atom << 8) | slot
+  __shared__ unsigned short s_map[kWPB][kBatch * kWave];  // filter: (atom << 8) | slot
   __shared__ KP s_kp[NT1 ? 1 : NTL];
   __shared__ double s_g[PG && !NT1 ? NTL * kNField : 1];
   __shared__ double s_red[kWPB][8];
@@ -144,12 +145,36 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEu<T, PG>::value))) void k_force_wave
   const int na = (int)max((int64_t)0, min((int64_t)A, (int64_t)a.n - first));
   // chunk atoms: lane `lane` < na holds atom `lane` of the chunk (A <= 64)
   int my_i = 0, my_t = 0, my_lc = 0, my_cf = 0;
+  double my_x[3] = {0.0, 0.0, 0.0};  // position of the lane's atom
   if (lane < na) {
-    my_i = a.order[first + lane];
+    my_i = (int)(first + lane);  // cell-order position
     my_t = NT1 ? 0 : a.type[my_i];
     my_lc = min(a.count[my_i], a.cap);
     my_cf = a.conf_of ? a.conf_of[my_i] : 0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) my_x[k] = a.x[3 * (int64_t)my_i + k];
   }
+  // periodic box: one record for a single system (uniform, read once),
+  // the configuration's own record per lane for a batch
+  double box0[3], ibox0[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    box0[k] = a.conf[0].box[k];
+    ibox0[k] = a.conf[0].inv_box[k];
+  }
+  const bool one_conf = a.conf_of == nullptr;
+  // d <- minimum image of d in configuration cf
+  auto min_image = [&](double *d, int cf) {
+    if (one_conf) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) d[k] -= box0[k] * rint(d[k] * ibox0[k]);
+    } else {
+      const ConfDesc &c = a.conf[cf];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) d[k] -= c.box[k] * rint(d[k] * c.inv_box[k]);
+    }
+  };
+  const double filt2_0 = ((const double *)a.filt2)[0];
 
   // ---- filter: compact the in-cutoff neighbours of every atom of the chunk --
   // The chunk's list entries are numbered without the row padding (atom a's
@@ -163,57 +188,82 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEu<T, PG>::value))) void k_force_wave
   const int total = __shfl(my_e, kWave - 1, kWave);
   my_e -= my_lc;
   int my_cnt = 0;  // in-cutoff neighbours found so far (atom lanes)
-  for (int base = 0; base < total; base += kWave) {
-    // entry of this window -> (atom, slot), written by the atoms' lanes
-    const int lo = max(my_e, base), hi = min(my_e + my_lc, base + kWave);
-    for (int t = lo; t < hi; ++t) s_map[w][t - base] = (unsigned short)((lane << 8) | (t - my_e));
-    wave_sync();
-    const bool valid = base + lane < total;
-    const int code = valid ? s_map[w][lane] : 0;
-    const int at = code >> 8, s = code & 0xff;
-    const int i = lane_read(my_i, at), ti = lane_read(my_t, at), cf = lane_read(my_cf, at);
-    const int e_at = lane_read(my_e, at), c_at = lane_read(my_cnt, at);
-    bool pass = false;
-    int j = 0;
-    if (valid) {
-      j = a.list[(int64_t)i * a.cap + s];
-      const ConfDesc &c = a.conf[cf];
-      double dx = a.x[3 * j] - a.x[3 * i];
-      double dy = a.x[3 * j + 1] - a.x[3 * i + 1];
-      double dz = a.x[3 * j + 2] - a.x[3 * i + 2];
-      dx -= c.box[0] * rint(dx * c.inv_box[0]);
-      dy -= c.box[1] * rint(dy * c.inv_box[1]);
-      dz -= c.box[2] * rint(dz * c.inv_box[2]);
-      const int tj = NT1 ? 0 : a.type[j];
-      pass = dx * dx + dy * dy + dz * dz < filt2[NT1 ? 0 : ti * nt + tj];
+  // Windows are taken kBatch at a time: the list entries of all windows of a
+  // batch are loaded first, then the neighbours' positions, so that a
+  // wavefront has all these loads in flight at once; the tests follow window
+  // by window (the staging position of a pass depends on the earlier ones).
+  for (int base0 = 0; base0 < total; base0 += kBatch * kWave) {
+    // entry -> (atom, slot), written by the atoms' lanes
+    {
+      const int lo = max(my_e, base0), hi = min(my_e + my_lc, base0 + kBatch * kWave);
+      for (int t = lo; t < hi; ++t) s_map[w][t - base0] = (unsigned short)((lane << 8) | (t - my_e));
     }
-    const uint64_t m = __ballot(pass);
-    // passes of the same atom in lower lanes of this window (e_at <= base + lane)
-    const int lo_lane = max(e_at - base, 0);
-    const uint64_t below = ((1ull << lane) - 1ull) & ~((1ull << lo_lane) - 1ull);
-    const int pos = c_at + __popcll(m & below);
-    if (pass) {
-      if (pos < kNMax) {
-        s_stage[w][at * kNMax + pos] = j;
-        s_slot[w][at * kNMax + pos] = (unsigned char)s;
-      } else {
-        atomicOr(a.err, kErrTooManyInCutoff);
+    wave_sync();
+    int cw[kBatch], jw[kBatch], rw[kBatch];
+    double xw[kBatch][3];
+    // (no branches around the loads: lanes past the end read entry 0 and
+    // atom 0 and discard them, so that the loads issue back to back)
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const bool valid = base0 + u * kWave + lane < total;
+      cw[u] = valid ? (int)s_map[w][u * kWave + lane] : -1;
+      const int at = valid ? cw[u] >> 8 : 0;
+      const int i = lane_read(my_i, at);
+      const int64_t e = valid ? (int64_t)i * a.cap + (cw[u] & 0xff) : 0;
+      const int jl = a.list[e];
+      const int rl = a.rev[e];  // the reverse map exists in both force modes
+      jw[u] = valid ? jl : 0;
+      rw[u] = (valid && a.fslot) ? rl : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) xw[u][k] = a.x[3 * (int64_t)jw[u] + k];
+    }
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const int base = base0 + u * kWave;
+      if (base >= total) break;  // uniform
+      const bool valid = cw[u] >= 0;
+      const int at = valid ? cw[u] >> 8 : 0, s = cw[u] & 0xff;
+      const int ti = lane_read(my_t, at), cf = lane_read(my_cf, at);
+      const int e_at = lane_read(my_e, at), c_at = lane_read(my_cnt, at);
+      double d[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) d[k] = xw[u][k] - lane_read(my_x[k], at);
+      bool pass = false;
+      const int j = jw[u];
+      if (valid) {
+        min_image(d, cf);
+        const int tj = NT1 ? 0 : a.type[j];
+        pass = d[0] * d[0] + d[1] * d[1] + d[2] * d[2] < (NT1 ? filt2_0 : filt2[ti * nt + tj]);
       }
-    } else if (a.fslot && valid) {
-      const int r = a.rev[(int64_t)i * a.cap + s];
-      if (r >= 0) {
-        B *fs = (B *)a.fslot + 3 * (int64_t)r;  // slots hold the base type
+      const uint64_t m = __ballot(pass);
+      // passes of the same atom in lower lanes of this window (e_at <= base + lane)
+      const int lo_lane = max(e_at - base, 0);
+      const uint64_t below = ((1ull << lane) - 1ull) & ~((1ull << lo_lane) - 1ull);
+      const int pos = c_at + __popcll(m & below);
+      if (pass) {
+        if (pos < kNMax) {
+          s_stage[w][at * kNMax + pos] = j;
+          s_slot[w][at * kNMax + pos] = (unsigned char)s;
+        } else {
+          atomicOr(a.err, kErrTooManyInCutoff);
+        }
+      } else if (valid && rw[u] >= 0) {
+        B *fs = (B *)a.fslot + 3 * (int64_t)rw[u];  // slots hold the base type
         fs[0] = B(0);
         fs[1] = B(0);
         fs[2] = B(0);
       }
+      const int lo = max(my_e, base), hi = min(my_e + my_lc, base + kWave);
+      if (hi > lo) {
+        const int l0 = lo - base, l1 = hi - base;  // this atom's lanes [l0, l1)
+        const uint64_t mine = (l1 == kWave ? ~0ull : (1ull << l1) - 1ull) & ~((1ull << l0) - 1ull);
+        my_cnt += __popcll(m & mine);
+      }
     }
-    if (hi > lo) {
-      const int l0 = lo - base, l1 = hi - base;  // this atom's lanes [l0, l1)
-      const uint64_t mine = (l1 == kWave ? ~0ull : (1ull << l1) - 1ull) & ~((1ull << l0) - 1ull);
-      my_cnt += __popcll(m & mine);
-    }
-    wave_sync();  // s_map is rewritten by the next window
+    wave_sync();  // s_map is rewritten by the next batch
   }
   const int my_n = lane < na ? min(my_cnt, kNMax) : 0;
   int incl = my_n;  // inclusive prefix of pair counts over the chunk's atoms
@@ -256,18 +306,20 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEu<T, PG>::value))) void k_force_wave
     const int i = lane_read(my_i, at), ti = lane_read(my_t, at), cf = lane_read(my_cf, at);
     const int j = act ? s_stage[w][at * kNMax + q] : i;
     const int tj = NT1 ? 0 : (act ? a.type[j] : 0);
+    // incoming slot at j for this pair's force on j, fetched now so that the
+    // load is complete when the force is stored
+    const int r_out = a.rev[act ? (int64_t)i * a.cap + s_slot[w][at * kNMax + q] : 0];
 
     // pair data in registers
     T dx, dy, dz, r, ri, fc, dfc;
     B rlo;
     {
-      const ConfDesc &c = a.conf[cf];
       double d[3];
 #pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        double dd = a.x[3 * j + k] - a.x[3 * i + k];
-        d[k] = dd - c.box[k] * rint(dd * c.inv_box[k]);
-      }
+      for (int k = 0; k < 3; ++k) d[k] = lane_read(my_x[k], at);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) d[k] = a.x[3 * (int64_t)j + k] - d[k];
+      min_image(d, cf);
       if (!act) {
         d[0] = 1.0;
         d[1] = 0.0;
@@ -463,18 +515,18 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEu<T, PG>::value))) void k_force_wave
         o0 = (double)(B)o0;
         o1 = (double)(B)o1;
         o2 = (double)(B)o2;
-        const int r = a.rev[(int64_t)i * a.cap + s_slot[w][at * kNMax + q]];
-        if (r >= 0) {
-          B *fs = (B *)a.fslot + 3 * (int64_t)r;
+        if (r_out >= 0) {
+          B *fs = (B *)a.fslot + 3 * (int64_t)r_out;
           fs[0] = (B)o0;
           fs[1] = (B)o1;
           fs[2] = (B)o2;
         }
       } else {
         double *dst = DUAL ? a.xgrad : a.forces;
-        atomic_add(&dst[3 * j + 0], o0);
-        atomic_add(&dst[3 * j + 1], o1);
-        atomic_add(&dst[3 * j + 2], o2);
+        const int64_t aj = a.order[j];
+        atomic_add(&dst[3 * aj + 0], o0);
+        atomic_add(&dst[3 * aj + 1], o1);
+        atomic_add(&dst[3 * aj + 2], o2);
       }
     }
     // own force of i (minus the sum of its slot forces; segmented sum over the
@@ -505,20 +557,21 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEu<T, PG>::value))) void k_force_wave
           fo[2] = -sz;
         } else {
           double *dst = DUAL ? a.xgrad : a.forces;
-          atomic_add(&dst[3 * i + 0], -sx);
-          atomic_add(&dst[3 * i + 1], -sy);
-          atomic_add(&dst[3 * i + 2], -sz);
+          const int64_t ai = a.order[i];
+          atomic_add(&dst[3 * ai + 0], -sx);
+          atomic_add(&dst[3 * ai + 1], -sy);
+          atomic_add(&dst[3 * ai + 2], -sz);
         }
       }
       if (want_ea) {
-        if (flags & TERS_ACCUMULATE) a.e_atom[i] += se;
-        else a.e_atom[i] = se;
+        if (flags & TERS_ACCUMULATE) a.e_atom[a.order[i]] += se;
+        else a.e_atom[a.order[i]] = se;
       }
     }
     // atoms of the chunk without any in-cutoff neighbour: zero per-atom energy
     // and, in owner-gather mode, zero own force
     if (lane >= a0 && lane < a1 && my_n == 0) {
-      if (want_ea && !(flags & TERS_ACCUMULATE)) a.e_atom[my_i] = 0.0;
+      if (want_ea && !(flags & TERS_ACCUMULATE)) a.e_atom[a.order[my_i]] = 0.0;
       if (want_f && a.fown) {
         double *fo = a.fown + 3 * (first + lane);
         fo[0] = 0.0;

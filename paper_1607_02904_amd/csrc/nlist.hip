@@ -210,12 +210,15 @@ __global__ void k_place(int n, const double *__restrict__ x, const int32_t *__re
 }
 
 // order atoms inside each cell by index, record each atom's position in the
-// cell order (pos, the inverse of order) and copy the positions in that order
-// (xs); the counts (used as placement cursors) are cleared for the next build
+// cell order (pos, the inverse of order) and copy the positions, and the types
+// and configuration ids when given, in that order (xs, ts, cs); the counts
+// (used as placement cursors) are cleared for the next build
 __global__ void k_sort_cells(int64_t ncell, const int32_t *__restrict__ cell_start,
                              int32_t *__restrict__ order, int32_t *__restrict__ counts,
                              const double *__restrict__ x, double *__restrict__ xs,
-                             int32_t *__restrict__ pos, const int32_t *cond) {
+                             int32_t *__restrict__ pos, const int32_t *__restrict__ type,
+                             int32_t *__restrict__ ts, const int32_t *__restrict__ conf_of,
+                             int32_t *__restrict__ cs, const int32_t *cond) {
   if (skip(cond)) return;
   for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < ncell;
        c += (int64_t)gridDim.x * blockDim.x) {
@@ -235,6 +238,8 @@ __global__ void k_sort_cells(int64_t ncell, const int32_t *__restrict__ cell_sta
       xs[3 * p] = x[3 * i];
       xs[3 * p + 1] = x[3 * i + 1];
       xs[3 * p + 2] = x[3 * i + 2];
+      if (type) ts[p] = type[i];
+      if (conf_of) cs[p] = conf_of[i];
     }
     counts[c] = 0;
   }
@@ -251,6 +256,11 @@ DEV int wrap_cell(int q, int nc) { return q < 0 ? q + nc : (q >= nc ? q - nc : q
 // hits (the first 64 also as a bit mask), an exclusive scan over the atom's
 // nine lanes gives every lane its first position in the row, and a second pass
 // writes the hits there.
+//
+// Rows, counts and entries are in cell-order positions: row t lists the
+// atom at position t, its entries are the positions of its neighbours (the
+// force kernels read positions, types and rows in that order, so that the
+// data of a run of atoms and of their neighbours is contiguous).
 //
 // Incoming force slots (min(count, cap) per atom) are laid out without row
 // padding: each workgroup numbers its atoms' slots from 0 in processing order
@@ -381,33 +391,33 @@ __global__ __launch_bounds__(kBS) void k_build(int n, const double *__restrict__
     const int total = __shfl(incl, last, kWave);
     // pass 2: write the hits from the row position of this lane on
     if (act) {
-      int32_t *row = list + (int64_t)i * cap;
+      int32_t *row = list + (int64_t)t * cap;
       int pos = incl - nhit;
       while (mask) {
         const int k = __ffsll((unsigned long long)mask) - 1;
         mask &= mask - 1ull;
         const int p = k < len0 ? b0 + k : b1 + (k - len0);
-        if (pos < cap) row[pos] = order[p];
+        if (pos < cap) row[pos] = p;
         ++pos;
       }
       for (int k = 64; k < len; ++k) {  // rows of more than 64 candidates
         const int p = k < len0 ? b0 + k : b1 + (k - len0);
         if (within(p)) {
-          if (pos < cap) row[pos] = order[p];
+          if (pos < cap) row[pos] = p;
           ++pos;
         }
       }
     }
     const bool owner = act && r == kRows - 1;
     if (owner) {
-      count[i] = total;
+      count[t] = total;
       if (total > cap) atomicOr(err, kErrNlistOverflow);
     }
     worst = max(worst, owner ? total : 0);
     // slots of this pass, numbered after those of the earlier passes
     int tot;
     const int ex = block_excl_scan(owner ? min(total, cap) : 0, &tot);
-    if (owner) loff[i] = (int32_t)(((uint32_t)blk << kLoffBits) | (uint32_t)(run + ex));
+    if (owner) loff[t] = (int32_t)(((uint32_t)blk << kLoffBits) | (uint32_t)(run + ex));
     run += tot;
   }
   // the workgroup's slot total and longest row
@@ -424,20 +434,19 @@ __global__ __launch_bounds__(kBS) void k_build(int n, const double *__restrict__
   }
 }
 
-// Global slot offsets and the reverse map.  Every workgroup first scans the
-// build's per-workgroup slot totals (nb <= kBuildMaxBlocks, in LDS), so the
-// first slot of atom a is off(a) = (slots of earlier build workgroups) + (a's
-// number within its own); workgroup 0 also stores the longest row.  Then, per
-// atom i (at position t in cell order): soff[t] = off(i) (slots increase along
-// the cell order, so atom t's are [soff[t], soff[t + 1])), and
-// rev[i*cap + s] = incoming force slot at atom j = list[i*cap + s] that holds
-// the force of i's terms on j: off(j) + (position of i in j's row).  The list
+// Global slot offsets and the reverse map (all indices are cell-order
+// positions).  Every workgroup first scans the build's per-workgroup slot
+// totals (nb <= kBuildMaxBlocks, in LDS), so the first slot of atom t is
+// off(t) = (slots of earlier build workgroups) + (t's number within its own);
+// workgroup 0 also stores the longest row.  Then, per atom t: soff[t] = off(t)
+// (slots increase along the cell order, so atom t's are [soff[t], soff[t + 1])),
+// and rev[t*cap + s] = incoming force slot at atom j = list[t*cap + s] that
+// holds the force of t's terms on j: off(j) + (position of t in j's row).  The list
 // is symmetric by construction (r_ij and r_ji are computed from exactly
 // negated displacements), so the position exists; a missing one is latched as
 // an error.  The rows of 4 neighbours are searched together with 16-byte
 // loads (rows start 16-byte aligned: cap is a multiple of 4).
-__global__ __launch_bounds__(kBS) void k_reverse(int n, int cap, const int32_t *__restrict__ order,
-                                                 const int32_t *__restrict__ count,
+__global__ __launch_bounds__(kBS) void k_reverse(int n, int cap, const int32_t *__restrict__ count,
                                                  const int32_t *__restrict__ list,
                                                  const int32_t *__restrict__ loff,
                                                  const int32_t *__restrict__ bsum, int nb,
@@ -483,7 +492,7 @@ __global__ __launch_bounds__(kBS) void k_reverse(int n, int cap, const int32_t *
   };
   for (int t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x; t < n;
        t += gridDim.x * blockDim.x) {
-    const int i = order[t];
+    const int i = t;
     const int ci = min(count[i], cap);
     const int oi = offset_of(i);
     soff[t] = oi;  // slots of the atom at position t: [soff[t], soff[t + 1])
@@ -557,6 +566,25 @@ __global__ void k_gather(int n, const int32_t *__restrict__ pos,
   }
 }
 
+// positions and types (when x is given) and an adjoint direction (when fbar
+// is given) in cell order
+__global__ void k_to_cells(int n, const int32_t *__restrict__ order, const double *__restrict__ x,
+                           const int32_t *__restrict__ type, const double *__restrict__ fbar,
+                           double *__restrict__ xs, int32_t *__restrict__ ts,
+                           double *__restrict__ fbs) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const int i = order[t];
+  if (x) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) xs[3 * t + k] = x[3 * i + k];
+    ts[t] = type[i];
+  }
+  if (fbar)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) fbs[3 * t + k] = fbar[3 * i + k];
+}
+
 __global__ void k_check(int n, const double *__restrict__ x, const double *__restrict__ xref,
                         const ConfDesc *__restrict__ conf, const int32_t *__restrict__ conf_of,
                         double lim2, int32_t *flag) {
@@ -597,8 +625,8 @@ void launch_fill_f64(double *p, double v, int64_t n, hipStream_t s) {
 // Build the list for the configuration set described by nl (geometry already
 // filled in by the caller).  cond: device flag (may be null); when non-null
 // and zero every kernel returns immediately.
-void nlist_build(NList &nl, const double *x, const int32_t *cond, uint32_t *err, hipStream_t s,
-                 int64_t *rebuild_counter) {
+void nlist_build(NList &nl, const double *x, const int32_t *type, const int32_t *cond,
+                 uint32_t *err, hipStream_t s, int64_t *rebuild_counter) {
   const int n = nl.n;
   const int64_t ncell = nl.ncell;
   int32_t *cell_count = nl.cell_count.as<int32_t>();
@@ -633,7 +661,10 @@ void nlist_build(NList &nl, const double *x, const int32_t *cond, uint32_t *err,
     k_place<<<grid(n), kBS, 0, s>>>(n, x, nl.cell_of.as<int32_t>(), cell_start, cell_count,
                                     nl.order.as<int32_t>(), nl.xref.as<double>(), cond);
     k_sort_cells<<<grid(ncell), kBS, 0, s>>>(ncell, cell_start, nl.order.as<int32_t>(), cell_count,
-                                             x, nl.xs.as<double>(), nl.pos.as<int32_t>(), cond);
+                                             x, nl.xs.as<double>(), nl.pos.as<int32_t>(), type,
+                                             nl.ts.as<int32_t>(),
+                                             nl.conf_of.p ? nl.conf_of.as<int32_t>() : nullptr,
+                                             nl.cs.as<int32_t>(), cond);
     // the list build is latency-bound: a larger grid than the other kernels
     const int64_t groups = (n + kAtomsPerWave - 1) / kAtomsPerWave;
     const int gb = (int)std::min<int64_t>(
@@ -642,7 +673,7 @@ void nlist_build(NList &nl, const double *x, const int32_t *cond, uint32_t *err,
                                nl.cell_of.as<int32_t>(), cell_start, nl.rlist * nl.rlist, nl.cap,
                                nl.count.as<int32_t>(), nl.list.as<int32_t>(), nl.loff.as<int32_t>(),
                                nl.bsum.as<int32_t>(), cond, err, rebuild_counter);
-    k_reverse<<<grid(n), kBS, 0, s>>>(n, nl.cap, nl.order.as<int32_t>(), nl.count.as<int32_t>(),
+    k_reverse<<<grid(n), kBS, 0, s>>>(n, nl.cap, nl.count.as<int32_t>(),
                                       nl.list.as<int32_t>(), nl.loff.as<int32_t>(),
                                       nl.bsum.as<int32_t>(), gb, nl.soff.as<int32_t>(),
                                       nl.rev.as<int32_t>(), nl.maxcount.as<int32_t>(), cond, err);
@@ -660,6 +691,14 @@ void launch_gather(const NList &nl, const void *fslot, bool slot_f32, const doub
     k_gather<double><<<grid_for(nl.n, kBS), kBS, 0, s>>>(
         nl.n, nl.pos.as<int32_t>(), nl.soff.as<int32_t>(), (const double *)fslot, fown, F,
         accumulate);
+}
+
+void launch_to_cells(NList &nl, const double *x, const int32_t *type, const double *fbar,
+                     hipStream_t s) {
+  if (nl.n <= 0) return;
+  k_to_cells<<<grid_for(nl.n, kBS), kBS, 0, s>>>(nl.n, nl.order.as<int32_t>(), x, type, fbar,
+                                                 nl.xs.as<double>(), nl.ts.as<int32_t>(),
+                                                 fbar ? nl.fbs.as<double>() : nullptr);
 }
 
 void nlist_check(const NList &nl, const double *x, int32_t *flag, hipStream_t s) {

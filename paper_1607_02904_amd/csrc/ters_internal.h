@@ -79,8 +79,8 @@ struct NList {
   std::vector<ConfDesc> conf_h;
   DevBuf conf;        // ConfDesc[nconf]
   DevBuf conf_of;     // int32[n] (only for nconf > 1)
-  DevBuf count;       // int32[n]
-  DevBuf list;        // int32[n][cap]
+  DevBuf count;       // int32[n]: row lengths, by cell-order position
+  DevBuf list;        // int32[n][cap]: row t = neighbours (cell-order positions) of the atom at t
   DevBuf order;       // int32[n]: atoms in cell order
   DevBuf cell_of;     // int32[n]
   DevBuf cell_count;  // int32[ncell + 1]
@@ -88,8 +88,11 @@ struct NList {
   DevBuf scan_tmp;    // int32 block sums
   DevBuf xref;        // double[n][3]
   DevBuf maxcount;    // int32[1]
-  DevBuf rev;         // int32[n][cap]: incoming force slot at j of row entry (i, j)
-  DevBuf xs;          // double[n][3]: positions at build time, in cell order
+  DevBuf rev;         // int32[n][cap]: incoming force slot at j of row entry (t, j)
+  DevBuf xs;          // double[n][3]: positions in cell order (the force kernels' input)
+  DevBuf ts;          // int32[n]: types in cell order
+  DevBuf cs;          // int32[n]: configuration ids in cell order (when conf_of is set)
+  DevBuf fbs;         // double[n][3]: adjoint direction in cell order (adjoint only)
   DevBuf pos;         // int32[n]: position of each atom in the cell order (inverse of order)
   DevBuf soff;        // int32[n + 1]: first incoming force slot of the atom at each cell-order position
   DevBuf loff;        // int32[n]: build workgroup (high bits) and slot number within it
@@ -97,14 +100,17 @@ struct NList {
 };
 
 // Forward / adjoint launch description.
+// Inputs are indexed by cell-order position (the list's numbering): x, type,
+// fbar, conf_of, count, list and rev; order maps a position to the atom, for
+// the outputs indexed by atom (per-atom energy, atomic-scatter forces).
 struct FwdArgs {
   int32_t n;
-  const double *x;
-  const int32_t *type;
-  const double *fbar;      // adjoint direction (dual kernels) or null
+  const double *x;         // [n][3] positions in cell order
+  const int32_t *type;     // [n] types in cell order
+  const double *fbar;      // adjoint direction in cell order (dual kernels) or null
   const ConfDesc *conf;    // device
-  const int32_t *conf_of;  // device int32[n] or null (single configuration)
-  const int32_t *order;    // processing order (cell order)
+  const int32_t *conf_of;  // configuration id in cell order, or null (single configuration)
+  const int32_t *order;    // cell-order position -> atom
   const int32_t *count;
   const int32_t *list;
   int32_t cap;
@@ -122,10 +128,10 @@ struct FwdArgs {
   const double *ebar_conf; // adjoint: per-configuration cotangent (batch) or null
   double *xgrad;           // adjoint output [n][3]
   // owner-gather mode (no atomics): when fslot is set, the force that the
-  // terms rooted at atom i exert on its list neighbour j (slot s of i's row)
-  // goes to j's incoming slot fslot[rev[i*cap + s]*3 ..] (zero when the pair is
-  // outside the cutoff) and the force on i itself to fown[t*3 ..], t = i's
-  // position in cell order; the incoming forces of the atom at position t then
+  // terms rooted at the atom at position t exert on its list neighbour j
+  // (slot s of row t) goes to j's incoming slot fslot[rev[t*cap + s]*3 ..]
+  // (zero when the pair is outside the cutoff) and the force on the atom
+  // itself to fown[t*3 ..]; the incoming forces of the atom at position t then
   // sit contiguously in slots [soff[t], soff[t + 1]) for the gather.
   // Slots hold the kernel's base type: FP64, or FP32 in the mixed path.
   void *fslot;
@@ -138,8 +144,13 @@ struct FwdArgs {
 // launchers (implemented in the .hip files)
 void launch_fill_i32(int32_t *p, int32_t v, int64_t n, const int32_t *cond, hipStream_t s);
 void launch_fill_f64(double *p, double v, int64_t n, hipStream_t s);
-void nlist_build(NList &nl, const double *x, const int32_t *cond, uint32_t *err, hipStream_t s,
-                 int64_t *rebuild_counter = nullptr);
+// type (may be null) is copied into nl.ts in the new cell order
+void nlist_build(NList &nl, const double *x, const int32_t *type, const int32_t *cond,
+                 uint32_t *err, hipStream_t s, int64_t *rebuild_counter = nullptr);
+// nl.xs and nl.ts (when x is given) and nl.fbs (when fbar is given) from
+// atom-ordered arrays
+void launch_to_cells(NList &nl, const double *x, const int32_t *type, const double *fbar,
+                     hipStream_t s);
 void nlist_check(const NList &nl, const double *x, int32_t *flag, hipStream_t s);
 // F[a] (+)= fown[t] + sum of the incoming slots fslot[soff[t] .. soff[t + 1]), t = pos[a]
 // (FP32 slots when slot_f32), summed in FP64 in slot order
