@@ -197,8 +197,6 @@ void nl_setup(NList &nl, int nconf, const int32_t *natoms, const double *boxes, 
   nl.scan_tmp.ensure(sizeof(int32_t) * ((cells + 1) / 1024 + 2));
   nl.xref.ensure(sizeof(double) * 3 * nn);
   nl.xs.ensure(sizeof(double) * 3 * nn);
-  nl.ts.ensure(sizeof(int32_t) * nn);
-  nl.cs.ensure(sizeof(int32_t) * nn);
   nl.pos.ensure(sizeof(int32_t) * nn);
   nl.soff.ensure(sizeof(int32_t) * (nn + 1));
   nl.loff.ensure(sizeof(int32_t) * nn);
@@ -208,10 +206,10 @@ void nl_setup(NList &nl, int nconf, const int32_t *natoms, const double *boxes, 
 }
 
 // Build with capacity growth (synchronises).
-void nl_build_sync(ters_ctx *c, NList &nl, const double *x, const int32_t *type, DevBuf &errw) {
+void nl_build_sync(ters_ctx *c, NList &nl, const double *x, DevBuf &errw) {
   for (int attempt = 0; attempt < 6; ++attempt) {
     launch_fill_i32(errw.as<int32_t>(), 0, 1, nullptr, c->stream);
-    nlist_build(nl, x, type, nullptr, errw.as<uint32_t>(), c->stream);
+    nlist_build(nl, x, nullptr, errw.as<uint32_t>(), c->stream);
     int32_t mx = 0;
     TERS_HIP_TRY(hipMemcpyAsync(&mx, nl.maxcount.p, sizeof(mx), hipMemcpyDeviceToHost, c->stream));
     uint32_t e = read_err(c, errw);
@@ -233,15 +231,11 @@ void nl_build_sync(ters_ctx *c, NList &nl, const double *x, const int32_t *type,
 FwdArgs base_args(ters_ctx *c, const NList &nl, int precision, int n, const double *x,
                   const int32_t *type, bool batch = false) {
   FwdArgs a{};
-  // the kernels read positions and types in cell order (nl.xs, nl.ts: kept
-  // current by launch_to_cells, by the list build and by the MD drift)
-  (void)x;
-  (void)type;
   a.n = n;
-  a.x = nl.xs.as<double>();
-  a.type = nl.ts.as<int32_t>();
+  a.x = x;
+  a.type = type;
   a.conf = nl.conf.as<ConfDesc>();
-  a.conf_of = batch ? nl.cs.as<int32_t>() : nullptr;
+  a.conf_of = batch ? nl.conf_of.as<int32_t>() : nullptr;
   a.order = nl.order.as<int32_t>();
   a.count = nl.count.as<int32_t>();
   a.list = nl.list.as<int32_t>();
@@ -283,8 +277,7 @@ std::vector<const void *> graph_key(const ters_ctx *c, const NList &nl) {
           bits(nl.skin), c->kp64.p, c->kp32.p, c->filt2.p, (const void *)(intptr_t)c->ntypes,
           (const void *)(intptr_t)c->cut_consistent, (const void *)(intptr_t)c->kmax,
           c->partials.p, c->errw.p, c->flag.p, c->rebuilds.p, c->step.p, c->escratch.p,
-          nl.rev.p, nl.xs.p, nl.ts.p, nl.cs.p, nl.fbs.p, nl.pos.p, nl.soff.p, nl.loff.p,
-          nl.bsum.p, c->fslot.p, c->fown.p,
+          nl.rev.p, nl.xs.p, nl.pos.p, nl.soff.p, nl.loff.p, nl.bsum.p, c->fslot.p, c->fown.p,
           (const void *)(intptr_t)c->gather};
 }
 
@@ -393,8 +386,7 @@ ters_status ters_destroy(ters_ctx *c) {
                     &c->rebuilds, &c->step, &c->escratch, &c->fslot, &c->fown, &c->nl.conf,
                     &c->nl.conf_of, &c->nl.count, &c->nl.list, &c->nl.order, &c->nl.cell_of,
                     &c->nl.cell_count, &c->nl.cell_start, &c->nl.scan_tmp, &c->nl.xref,
-                    &c->nl.maxcount, &c->nl.rev, &c->nl.xs, &c->nl.ts, &c->nl.cs, &c->nl.fbs,
-                    &c->nl.pos, &c->nl.soff,
+                    &c->nl.maxcount, &c->nl.rev, &c->nl.xs, &c->nl.pos, &c->nl.soff,
                     &c->nl.loff, &c->nl.bsum};
   for (DevBuf *b : bufs) b->release();
   delete c;
@@ -489,7 +481,7 @@ ters_status ters_build_nlist(ters_ctx *c, int32_t n, const double *x, const int3
     require(std::isfinite(skin) && skin >= 0.0, TERS_ERR_INVALID_ARG, "skin must be >= 0");
     c->nl.valid = false;
     nl_setup(c->nl, 1, &n, box, c->rc_max + skin, skin, nullptr, c->stream);
-    nl_build_sync(c, c->nl, x, type, c->errw);
+    nl_build_sync(c, c->nl, x, c->errw);
     return TERS_OK;
   });
 }
@@ -538,7 +530,6 @@ ters_status ters_compute_ex(ters_ctx *c, int32_t n, const double *x, const int32
             "per-atom energy output missing");
     require(!(flags & TERS_PARAM_GRAD) || param_grad, TERS_ERR_INVALID_ARG, "param_grad output missing");
     check_ready(c, c->nl, n, box);
-    launch_to_cells(c->nl, x, type, nullptr, c->stream);
     FwdArgs a = base_args(c, c->nl, precision, n, x, type);
     a.flags = flags;
     a.forces = (flags & TERS_FORCES) ? forces : nullptr;
@@ -572,10 +563,8 @@ ters_status ters_backward(ters_ctx *c, int32_t n, const double *x, const int32_t
             "bad arguments");
     require(std::isfinite(e_bar), TERS_ERR_INVALID_ARG, "e_bar must be finite");
     check_ready(c, c->nl, n, box);
-    c->nl.fbs.ensure(sizeof(double) * 3 * (size_t)std::max(n, 1));
-    launch_to_cells(c->nl, x, type, f_bar, c->stream);
     FwdArgs a = base_args(c, c->nl, precision, n, x, type);
-    a.fbar = c->nl.fbs.as<double>();
+    a.fbar = f_bar;
     a.ebar = e_bar;
     a.xgrad = x_grad;
     a.pgrad = param_grad;
@@ -629,7 +618,6 @@ ters_status ters_autotune(ters_ctx *c, int32_t n, const double *x, const int32_t
   return guard(c, [&]() {
     require(precision == TERS_FP64 || precision == TERS_MIXED, TERS_ERR_INVALID_ARG, "bad precision");
     check_ready(c, c->nl, n, box);
-    launch_to_cells(c->nl, x, type, nullptr, c->stream);
     DevBuf f;
     f.ensure(sizeof(double) * 3 * (size_t)std::max(n, 1));
     hipEvent_t e0, e1;
@@ -680,7 +668,6 @@ ters_status ters_profile_forward(ters_ctx *c, int32_t n, const double *x, const 
     require(precision == TERS_FP64 || precision == TERS_MIXED, TERS_ERR_INVALID_ARG, "bad precision");
     require(reps >= 1, TERS_ERR_INVALID_ARG, "reps must be >= 1");
     check_ready(c, c->nl, n, box);
-    launch_to_cells(c->nl, x, type, nullptr, c->stream);
     DevBuf f;
     f.ensure(sizeof(double) * 3 * (size_t)std::max(n, 1));
     FwdArgs a = base_args(c, c->nl, precision, n, x, type);
@@ -758,7 +745,7 @@ ters_status md_run_impl(ters_ctx *c, int32_t n, double *x, double *v, double *f,
       int32_t *flag = c->flag.as<int32_t>();
       if (!gather)
         launch_vv_first(n, x, v, f, type, c->mass.as<double>(), dt, c->nl, flag, 1, s);
-      nlist_build(c->nl, x, type, flag, c->errw.as<uint32_t>(), s, c->rebuilds.as<int64_t>());
+      nlist_build(c->nl, x, flag, c->errw.as<uint32_t>(), s, c->rebuilds.as<int64_t>());
       FwdArgs a = base_args(c, c->nl, precision, n, x, type);
       a.flags = TERS_FORCES | TERS_ENERGY | TERS_ACCUMULATE;  // scatter: F was zeroed by the kick
       a.forces = f;
@@ -780,9 +767,6 @@ ters_status md_run_impl(ters_ctx *c, int32_t n, double *x, double *v, double *f,
     };
     launch_fill_i32(c->step.as<int32_t>(), 0, 1, nullptr, c->stream);
     launch_fill_i32(c->flag.as<int32_t>(), 0, 1, nullptr, c->stream);
-    // positions and types in cell order for the first force evaluation; the
-    // drift and the rebuilds keep them current from here on
-    launch_to_cells(c->nl, x, type, nullptr, c->stream);
     if (gather && nsteps > 0)
       launch_vv_first(n, x, v, f, type, c->mass.as<double>(), dt, c->nl, c->flag.as<int32_t>(), 0,
                       c->stream);
@@ -875,7 +859,7 @@ void batch_enqueue(ters_plan *p, const double *x, const int32_t *type, double *e
                    hipStream_t s) {
   ters_ctx *c = p->ctx;
   NList &nl = p->nl;
-  nlist_build(nl, x, type, nullptr, p->errw.as<uint32_t>(), s);
+  nlist_build(nl, x, nullptr, p->errw.as<uint32_t>(), s);
   FwdArgs a = base_args(c, nl, p->precision, p->N, x, type, true);
   a.flags = (f ? TERS_FORCES : 0u) | TERS_ENERGY | TERS_VIRIAL;
   a.forces = f;
@@ -894,8 +878,7 @@ void batch_enqueue(ters_plan *p, const double *x, const int32_t *type, double *e
     k_split_partials<<<(p->nconf + 255) / 256, 256, 0, s>>>(p->partials.as<double>(), p->nconf, e, w);
   if (f_bar) {
     FwdArgs b = base_args(c, nl, p->precision, p->N, x, type, true);
-    launch_to_cells(nl, nullptr, nullptr, f_bar, s);
-    b.fbar = nl.fbs.as<double>();
+    b.fbar = f_bar;
     b.ebar = 0.0;
     b.ebar_conf = e_bar;
     b.xgrad = xg;
@@ -982,8 +965,7 @@ ters_status ters_batch_run(ters_plan *p, const double *x, const int32_t *type, d
     NList &nl = p->nl;
     if (!p->tuned) {
       // size the list, then pick the schedule on this data (eager, synchronising)
-      nl_build_sync(c, nl, x, type, p->errw);
-      nl.fbs.ensure(sizeof(double) * 3 * (size_t)std::max(p->N, 1));  // no allocation in the capture
+      nl_build_sync(c, nl, x, p->errw);
       p->gather = c->gather;
       if (p->gather) ensure_gather(p->fslot, p->fown, nl);
       DevBuf ft;
@@ -1058,8 +1040,7 @@ static void plan_release_device(ters_plan *p) {
   DevBuf *bufs[] = {&p->partials, &p->ebuf, &p->errw, &p->fslot, &p->fown, &p->nl.conf,
                     &p->nl.conf_of, &p->nl.count, &p->nl.list, &p->nl.order, &p->nl.cell_of,
                     &p->nl.cell_count, &p->nl.cell_start, &p->nl.scan_tmp, &p->nl.xref,
-                    &p->nl.maxcount, &p->nl.rev, &p->nl.xs, &p->nl.ts, &p->nl.cs, &p->nl.fbs,
-                    &p->nl.pos, &p->nl.soff,
+                    &p->nl.maxcount, &p->nl.rev, &p->nl.xs, &p->nl.pos, &p->nl.soff,
                     &p->nl.loff, &p->nl.bsum};
   for (DevBuf *b : bufs) b->release();
   p->ctx = nullptr;

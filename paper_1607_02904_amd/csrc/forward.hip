@@ -47,7 +47,8 @@ __global__ __launch_bounds__(BS) void k_force(FwdArgs a, int A) {
   static_assert(AMAX <= kWave, "sub-chunk planning runs on one wave");
   static_assert(BS % kWave == 0, "whole waves");
 
-  __shared__ int s_atom[AMAX], s_type[AMAX], s_lcnt[AMAX], s_cnt[AMAX], s_kmx[AMAX];
+  // s_atom: cell-order position (list row); s_aid: its atom (per-atom arrays)
+  __shared__ int s_atom[AMAX], s_aid[AMAX], s_type[AMAX], s_lcnt[AMAX], s_cnt[AMAX], s_kmx[AMAX];
   __shared__ int s_pst[AMAX], s_tst[AMAX], s_conf[AMAX];
   __shared__ int s_stage[AMAX * kNMax];
   __shared__ unsigned char s_slot[AMAX * kNMax];  // list slot of each staged neighbour
@@ -113,11 +114,13 @@ __global__ __launch_bounds__(BS) void k_force(FwdArgs a, int A) {
 
   // ---- 0: atoms of this workgroup ----------------------------------------
   for (int at = tid; at < na; at += BS) {
-    int i = (int)(first + at);  // cell-order position
+    const int i = (int)(first + at);
+    const int ia = a.order[i];
     s_atom[at] = i;
-    s_type[at] = NT1 ? 0 : a.type[i];
+    s_aid[at] = ia;
+    s_type[at] = NT1 ? 0 : a.type[ia];
     s_lcnt[at] = min(a.count[i], a.cap);
-    s_conf[at] = a.conf_of ? a.conf_of[i] : 0;
+    s_conf[at] = a.conf_of ? a.conf_of[ia] : 0;
   }
   __syncthreads();
 
@@ -134,8 +137,8 @@ __global__ __launch_bounds__(BS) void k_force(FwdArgs a, int A) {
       bool pass = false;
       int j = 0;
       if (at < na && s < s_lcnt[at]) {
-        int i = s_atom[at];
-        j = a.list[(int64_t)i * cap + s];
+        const int i = s_aid[at];
+        j = a.order[a.list[(int64_t)s_atom[at] * cap + s]];  // neighbour's atom
         const ConfDesc &cf = a.conf[s_conf[at]];
         double dx = a.x[3 * j] - a.x[3 * i];
         double dy = a.x[3 * j + 1] - a.x[3 * i + 1];
@@ -252,7 +255,7 @@ __global__ __launch_bounds__(BS) void k_force(FwdArgs a, int A) {
     __syncthreads();
     for (int p = tid; p < np; p += BS) {
       int at = s_pa[p], q = s_pq[p];
-      int i = s_atom[at];
+      int i = s_aid[at];
       int j = s_stage[at * kNMax + q];
       int ti = s_type[at];
       int tj = NT1 ? 0 : a.type[j];
@@ -456,10 +459,9 @@ __global__ __launch_bounds__(BS) void k_force(FwdArgs a, int A) {
           }
         } else {
           double *dst = DUAL ? a.xgrad : a.forces;
-          const int64_t aj = a.order[j];
-          atomic_add(&dst[3 * aj + 0], o0);
-          atomic_add(&dst[3 * aj + 1], o1);
-          atomic_add(&dst[3 * aj + 2], o2);
+          atomic_add(&dst[3 * (int64_t)j + 0], o0);
+          atomic_add(&dst[3 * (int64_t)j + 1], o1);
+          atomic_add(&dst[3 * (int64_t)j + 2], o2);
         }
       }
       s_fx[p] = f[0];
@@ -479,7 +481,7 @@ __global__ __launch_bounds__(BS) void k_force(FwdArgs a, int A) {
         fz -= s_fz[b + q];
         e += s_ev[b + q];
       }
-      const int i = s_atom[at];
+      const int i = s_aid[at];
       if (want_f) {
         const double eb = DUAL ? (a.ebar_conf ? a.ebar_conf[s_conf[at]] : a.ebar) : 1.0;
         const double o0 = DUAL ? -out_of(fx, eb) : val(fx);
@@ -492,15 +494,14 @@ __global__ __launch_bounds__(BS) void k_force(FwdArgs a, int A) {
           fo[2] = o2;
         } else {
           double *dst = DUAL ? a.xgrad : a.forces;
-          const int64_t ai = a.order[i];
-          atomic_add(&dst[3 * ai + 0], o0);
-          atomic_add(&dst[3 * ai + 1], o1);
-          atomic_add(&dst[3 * ai + 2], o2);
+          atomic_add(&dst[3 * (int64_t)i + 0], o0);
+          atomic_add(&dst[3 * (int64_t)i + 1], o1);
+          atomic_add(&dst[3 * (int64_t)i + 2], o2);
         }
       }
       if (want_ea) {
-        if (flags & TERS_ACCUMULATE) a.e_atom[a.order[i]] += e;
-        else a.e_atom[a.order[i]] = e;
+        if (flags & TERS_ACCUMULATE) a.e_atom[i] += e;
+        else a.e_atom[i] = e;
       }
     }
     __syncthreads();

@@ -144,15 +144,16 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEu<T, PG>::value))) void k_force_wave
   const int64_t first = ((int64_t)xcd_block(blockIdx.x, gridDim.x) * kWPB + w) * A;
   const int na = (int)max((int64_t)0, min((int64_t)A, (int64_t)a.n - first));
   // chunk atoms: lane `lane` < na holds atom `lane` of the chunk (A <= 64)
-  int my_i = 0, my_t = 0, my_lc = 0, my_cf = 0;
+  int my_i = 0, my_a = 0, my_t = 0, my_lc = 0, my_cf = 0;  // position, atom
   double my_x[3] = {0.0, 0.0, 0.0};  // position of the lane's atom
   if (lane < na) {
-    my_i = (int)(first + lane);  // cell-order position
-    my_t = NT1 ? 0 : a.type[my_i];
+    my_i = (int)(first + lane);  // cell-order position: list row
+    my_a = a.order[my_i];        // the atom: per-atom arrays
+    my_t = NT1 ? 0 : a.type[my_a];
     my_lc = min(a.count[my_i], a.cap);
-    my_cf = a.conf_of ? a.conf_of[my_i] : 0;
+    my_cf = a.conf_of ? a.conf_of[my_a] : 0;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) my_x[k] = a.x[3 * (int64_t)my_i + k];
+    for (int k = 0; k < 3; ++k) my_x[k] = a.x[3 * (int64_t)my_a + k];
   }
   // periodic box: one record for a single system (uniform, read once),
   // the configuration's own record per lane for a batch
@@ -199,7 +200,7 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEu<T, PG>::value))) void k_force_wave
       for (int t = lo; t < hi; ++t) s_map[w][t - base0] = (unsigned short)((lane << 8) | (t - my_e));
     }
     wave_sync();
-    int cw[kBatch], jw[kBatch], rw[kBatch];
+    int cw[kBatch], jw[kBatch], rw[kBatch];  // entry code, neighbour's atom, reverse slot
     double xw[kBatch][3];
     // (no branches around the loads: lanes past the end read entry 0 and
     // atom 0 and discard them, so that the loads issue back to back)
@@ -215,6 +216,8 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEu<T, PG>::value))) void k_force_wave
       jw[u] = valid ? jl : 0;
       rw[u] = (valid && a.fslot) ? rl : -1;
     }
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) jw[u] = a.order[jw[u]];  // position -> atom
 #pragma unroll
     for (int u = 0; u < kBatch; ++u) {
 #pragma unroll
@@ -304,7 +307,8 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEu<T, PG>::value))) void k_force_wave
     const int n_i = lane_read(my_n, at);
     const int seg0 = lane - q;  // first lane of this atom's pairs
     const int i = lane_read(my_i, at), ti = lane_read(my_t, at), cf = lane_read(my_cf, at);
-    const int j = act ? s_stage[w][at * kNMax + q] : i;
+    const int ia = lane_read(my_a, at);  // atom of position i
+    const int j = act ? s_stage[w][at * kNMax + q] : ia;  // neighbour's atom
     const int tj = NT1 ? 0 : (act ? a.type[j] : 0);
     // incoming slot at j for this pair's force on j, fetched now so that the
     // load is complete when the force is stored
@@ -328,7 +332,7 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEu<T, PG>::value))) void k_force_wave
       T dT[3];
 #pragma unroll
       for (int k = 0; k < 3; ++k)
-        dT[k] = Conv<T>::from(d[k], (DUAL && act) ? (a.fbar[3 * j + k] - a.fbar[3 * i + k]) : 0.0);
+        dT[k] = Conv<T>::from(d[k], (DUAL && act) ? (a.fbar[3 * j + k] - a.fbar[3 * ia + k]) : 0.0);
       const double r64 = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
       r = t_sqrt(dT[0] * dT[0] + dT[1] * dT[1] + dT[2] * dT[2]);
       set_val(r, r64);
@@ -523,10 +527,9 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEu<T, PG>::value))) void k_force_wave
         }
       } else {
         double *dst = DUAL ? a.xgrad : a.forces;
-        const int64_t aj = a.order[j];
-        atomic_add(&dst[3 * aj + 0], o0);
-        atomic_add(&dst[3 * aj + 1], o1);
-        atomic_add(&dst[3 * aj + 2], o2);
+        atomic_add(&dst[3 * (int64_t)j + 0], o0);
+        atomic_add(&dst[3 * (int64_t)j + 1], o1);
+        atomic_add(&dst[3 * (int64_t)j + 2], o2);
       }
     }
     // own force of i (minus the sum of its slot forces; segmented sum over the
@@ -557,21 +560,20 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEu<T, PG>::value))) void k_force_wave
           fo[2] = -sz;
         } else {
           double *dst = DUAL ? a.xgrad : a.forces;
-          const int64_t ai = a.order[i];
-          atomic_add(&dst[3 * ai + 0], -sx);
-          atomic_add(&dst[3 * ai + 1], -sy);
-          atomic_add(&dst[3 * ai + 2], -sz);
+          atomic_add(&dst[3 * (int64_t)ia + 0], -sx);
+          atomic_add(&dst[3 * (int64_t)ia + 1], -sy);
+          atomic_add(&dst[3 * (int64_t)ia + 2], -sz);
         }
       }
       if (want_ea) {
-        if (flags & TERS_ACCUMULATE) a.e_atom[a.order[i]] += se;
-        else a.e_atom[a.order[i]] = se;
+        if (flags & TERS_ACCUMULATE) a.e_atom[ia] += se;
+        else a.e_atom[ia] = se;
       }
     }
     // atoms of the chunk without any in-cutoff neighbour: zero per-atom energy
     // and, in owner-gather mode, zero own force
     if (lane >= a0 && lane < a1 && my_n == 0) {
-      if (want_ea && !(flags & TERS_ACCUMULATE)) a.e_atom[a.order[my_i]] = 0.0;
+      if (want_ea && !(flags & TERS_ACCUMULATE)) a.e_atom[my_a] = 0.0;
       if (want_f && a.fown) {
         double *fo = a.fown + 3 * (first + lane);
         fo[0] = 0.0;

@@ -13,22 +13,19 @@ namespace {
 constexpr double kFtm2v = 9648.533212331;  // eV/(Angstrom amu) -> Angstrom/ps^2
 constexpr int kBS = 256;
 
-// v += dt/2 F/m; x += dt v (also into the cell-ordered copy xs at the atom's
-// position of the last build: a rebuild rewrites xs); F = 0 when the force
-// kernel accumulates into it (atomic scatter); flag = 1 if any atom moved
-// more than skin/2 since the last list build (FP64, minimum image)
+// v += dt/2 F/m; x += dt v; F = 0 when the force kernel accumulates into it
+// (atomic scatter); flag = 1 if any atom moved more than skin/2 since the last
+// list build (FP64, minimum image)
 __global__ void k_vv_first(int n, double *__restrict__ x, double *__restrict__ v,
                            double *__restrict__ f, const int32_t *__restrict__ type,
                            const double *__restrict__ mass, double dt,
                            const double *__restrict__ xref, const ConfDesc *__restrict__ conf,
-                           const int32_t *__restrict__ pos, double *__restrict__ xs,
                            double lim2, int32_t *flag, int zero_f) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   bool over = false;
   if (i < n) {
     const double s = 0.5 * dt * kFtm2v / mass[type[i]];
     const ConfDesc &c = conf[0];
-    const int t = pos[i];
     double r2 = 0.0;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -36,7 +33,6 @@ __global__ void k_vv_first(int n, double *__restrict__ x, double *__restrict__ v
       double xx = x[3 * i + a] + dt * vv;
       v[3 * i + a] = vv;
       x[3 * i + a] = xx;
-      xs[3 * t + a] = xx;
       if (zero_f) f[3 * i + a] = 0.0;
       double d = xx - xref[3 * i + a];
       d -= c.box[a] * rint(d * c.inv_box[a]);
@@ -113,8 +109,7 @@ __global__ void k_vv_gather_kick_drift(int n, const int32_t *__restrict__ pos,
                                        const int32_t *__restrict__ type,
                                        const double *__restrict__ mass, double dt,
                                        const double *__restrict__ xref,
-                                       const ConfDesc *__restrict__ conf,
-                                       double *__restrict__ xs, double lim2,
+                                       const ConfDesc *__restrict__ conf, double lim2,
                                        int32_t *flag, int do_next,
                                        const double *__restrict__ partials, int nblocks,
                                        double *esum, int32_t *count, double *energy,
@@ -137,7 +132,6 @@ __global__ void k_vv_gather_kick_drift(int n, const int32_t *__restrict__ pos,
         vv = vv + s * fv[a];
         const double xx = x[3 * i + a] + dt * vv;
         x[3 * i + a] = xx;
-        xs[3 * t + a] = xx;
         double d = xx - xref[3 * i + a];
         d -= c.box[a] * rint(d * c.inv_box[a]);
         r2 += d * d;
@@ -166,14 +160,12 @@ void launch_vv_gather_kick_drift(const NList &nl, double *x, double *v, double *
   if (slot_f32)
     k_vv_gather_kick_drift<float><<<g, kBS, 0, s>>>(
         n, nl.pos.as<int32_t>(), nl.soff.as<int32_t>(), (const float *)fslot, fown, F, v, x,
-        type, mass, dt, nl.xref.as<double>(), nl.conf.as<ConfDesc>(), nl.xs.as<double>(),
-        half * half, flag, do_next,
+        type, mass, dt, nl.xref.as<double>(), nl.conf.as<ConfDesc>(), half * half, flag, do_next,
         partials, nblocks, esum, count, energy, trace, step);
   else
     k_vv_gather_kick_drift<double><<<g, kBS, 0, s>>>(
         n, nl.pos.as<int32_t>(), nl.soff.as<int32_t>(), (const double *)fslot, fown, F, v, x,
-        type, mass, dt, nl.xref.as<double>(), nl.conf.as<ConfDesc>(), nl.xs.as<double>(),
-        half * half, flag, do_next,
+        type, mass, dt, nl.xref.as<double>(), nl.conf.as<ConfDesc>(), half * half, flag, do_next,
         partials, nblocks, esum, count, energy, trace, step);
 }
 
@@ -183,8 +175,8 @@ void launch_vv_first(int n, double *x, double *v, double *f, const int32_t *type
   if (n <= 0) return;
   const double half = 0.5 * nl.skin;
   k_vv_first<<<(n + kBS - 1) / kBS, kBS, 0, s>>>(n, x, v, f, type, mass, dt, nl.xref.as<double>(),
-                                                 nl.conf.as<ConfDesc>(), nl.pos.as<int32_t>(),
-                                                 nl.xs.as<double>(), half * half, flag, zero_f);
+                                                 nl.conf.as<ConfDesc>(), half * half, flag,
+                                                 zero_f);
 }
 
 void launch_vv_second(int n, double *v, const double *f, const int32_t *type, const double *mass,

@@ -210,15 +210,13 @@ __global__ void k_place(int n, const double *__restrict__ x, const int32_t *__re
 }
 
 // order atoms inside each cell by index, record each atom's position in the
-// cell order (pos, the inverse of order) and copy the positions, and the types
-// and configuration ids when given, in that order (xs, ts, cs); the counts
-// (used as placement cursors) are cleared for the next build
+// cell order (pos, the inverse of order) and copy the positions in that order
+// for the build (xs); the counts (used as placement cursors) are cleared for
+// the next build
 __global__ void k_sort_cells(int64_t ncell, const int32_t *__restrict__ cell_start,
                              int32_t *__restrict__ order, int32_t *__restrict__ counts,
                              const double *__restrict__ x, double *__restrict__ xs,
-                             int32_t *__restrict__ pos, const int32_t *__restrict__ type,
-                             int32_t *__restrict__ ts, const int32_t *__restrict__ conf_of,
-                             int32_t *__restrict__ cs, const int32_t *cond) {
+                             int32_t *__restrict__ pos, const int32_t *cond) {
   if (skip(cond)) return;
   for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < ncell;
        c += (int64_t)gridDim.x * blockDim.x) {
@@ -238,8 +236,6 @@ __global__ void k_sort_cells(int64_t ncell, const int32_t *__restrict__ cell_sta
       xs[3 * p] = x[3 * i];
       xs[3 * p + 1] = x[3 * i + 1];
       xs[3 * p + 2] = x[3 * i + 2];
-      if (type) ts[p] = type[i];
-      if (conf_of) cs[p] = conf_of[i];
     }
     counts[c] = 0;
   }
@@ -259,8 +255,8 @@ DEV int wrap_cell(int q, int nc) { return q < 0 ? q + nc : (q >= nc ? q - nc : q
 //
 // Rows, counts and entries are in cell-order positions: row t lists the
 // atom at position t, its entries are the positions of its neighbours (the
-// force kernels read positions, types and rows in that order, so that the
-// data of a run of atoms and of their neighbours is contiguous).
+// rows of a run of atoms that a force wavefront takes are contiguous; the
+// atom of a position is order[position]).
 //
 // Incoming force slots (min(count, cap) per atom) are laid out without row
 // padding: each workgroup numbers its atoms' slots from 0 in processing order
@@ -566,25 +562,6 @@ __global__ void k_gather(int n, const int32_t *__restrict__ pos,
   }
 }
 
-// positions and types (when x is given) and an adjoint direction (when fbar
-// is given) in cell order
-__global__ void k_to_cells(int n, const int32_t *__restrict__ order, const double *__restrict__ x,
-                           const int32_t *__restrict__ type, const double *__restrict__ fbar,
-                           double *__restrict__ xs, int32_t *__restrict__ ts,
-                           double *__restrict__ fbs) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n) return;
-  const int i = order[t];
-  if (x) {
-#pragma unroll
-    for (int k = 0; k < 3; ++k) xs[3 * t + k] = x[3 * i + k];
-    ts[t] = type[i];
-  }
-  if (fbar)
-#pragma unroll
-    for (int k = 0; k < 3; ++k) fbs[3 * t + k] = fbar[3 * i + k];
-}
-
 __global__ void k_check(int n, const double *__restrict__ x, const double *__restrict__ xref,
                         const ConfDesc *__restrict__ conf, const int32_t *__restrict__ conf_of,
                         double lim2, int32_t *flag) {
@@ -625,8 +602,8 @@ void launch_fill_f64(double *p, double v, int64_t n, hipStream_t s) {
 // Build the list for the configuration set described by nl (geometry already
 // filled in by the caller).  cond: device flag (may be null); when non-null
 // and zero every kernel returns immediately.
-void nlist_build(NList &nl, const double *x, const int32_t *type, const int32_t *cond,
-                 uint32_t *err, hipStream_t s, int64_t *rebuild_counter) {
+void nlist_build(NList &nl, const double *x, const int32_t *cond, uint32_t *err, hipStream_t s,
+                 int64_t *rebuild_counter) {
   const int n = nl.n;
   const int64_t ncell = nl.ncell;
   int32_t *cell_count = nl.cell_count.as<int32_t>();
@@ -661,10 +638,7 @@ void nlist_build(NList &nl, const double *x, const int32_t *type, const int32_t 
     k_place<<<grid(n), kBS, 0, s>>>(n, x, nl.cell_of.as<int32_t>(), cell_start, cell_count,
                                     nl.order.as<int32_t>(), nl.xref.as<double>(), cond);
     k_sort_cells<<<grid(ncell), kBS, 0, s>>>(ncell, cell_start, nl.order.as<int32_t>(), cell_count,
-                                             x, nl.xs.as<double>(), nl.pos.as<int32_t>(), type,
-                                             nl.ts.as<int32_t>(),
-                                             nl.conf_of.p ? nl.conf_of.as<int32_t>() : nullptr,
-                                             nl.cs.as<int32_t>(), cond);
+                                             x, nl.xs.as<double>(), nl.pos.as<int32_t>(), cond);
     // the list build is latency-bound: a larger grid than the other kernels
     const int64_t groups = (n + kAtomsPerWave - 1) / kAtomsPerWave;
     const int gb = (int)std::min<int64_t>(
@@ -691,14 +665,6 @@ void launch_gather(const NList &nl, const void *fslot, bool slot_f32, const doub
     k_gather<double><<<grid_for(nl.n, kBS), kBS, 0, s>>>(
         nl.n, nl.pos.as<int32_t>(), nl.soff.as<int32_t>(), (const double *)fslot, fown, F,
         accumulate);
-}
-
-void launch_to_cells(NList &nl, const double *x, const int32_t *type, const double *fbar,
-                     hipStream_t s) {
-  if (nl.n <= 0) return;
-  k_to_cells<<<grid_for(nl.n, kBS), kBS, 0, s>>>(nl.n, nl.order.as<int32_t>(), x, type, fbar,
-                                                 nl.xs.as<double>(), nl.ts.as<int32_t>(),
-                                                 fbar ? nl.fbs.as<double>() : nullptr);
 }
 
 void nlist_check(const NList &nl, const double *x, int32_t *flag, hipStream_t s) {

@@ -89,10 +89,7 @@ struct NList {
   DevBuf xref;        // double[n][3]
   DevBuf maxcount;    // int32[1]
   DevBuf rev;         // int32[n][cap]: incoming force slot at j of row entry (t, j)
-  DevBuf xs;          // double[n][3]: positions in cell order (the force kernels' input)
-  DevBuf ts;          // int32[n]: types in cell order
-  DevBuf cs;          // int32[n]: configuration ids in cell order (when conf_of is set)
-  DevBuf fbs;         // double[n][3]: adjoint direction in cell order (adjoint only)
+  DevBuf xs;          // double[n][3]: positions at build time, in cell order
   DevBuf pos;         // int32[n]: position of each atom in the cell order (inverse of order)
   DevBuf soff;        // int32[n + 1]: first incoming force slot of the atom at each cell-order position
   DevBuf loff;        // int32[n]: build workgroup (high bits) and slot number within it
@@ -100,16 +97,16 @@ struct NList {
 };
 
 // Forward / adjoint launch description.
-// Inputs are indexed by cell-order position (the list's numbering): x, type,
-// fbar, conf_of, count, list and rev; order maps a position to the atom, for
-// the outputs indexed by atom (per-atom energy, atomic-scatter forces).
+// The list (count, list, rev) is indexed by cell-order position and holds
+// positions; order maps a position to its atom, which indexes the per-atom
+// arrays (x, type, fbar, conf_of and the outputs).
 struct FwdArgs {
   int32_t n;
-  const double *x;         // [n][3] positions in cell order
-  const int32_t *type;     // [n] types in cell order
-  const double *fbar;      // adjoint direction in cell order (dual kernels) or null
+  const double *x;         // [n][3] positions, by atom
+  const int32_t *type;     // [n] types, by atom
+  const double *fbar;      // adjoint direction, by atom (dual kernels) or null
   const ConfDesc *conf;    // device
-  const int32_t *conf_of;  // configuration id in cell order, or null (single configuration)
+  const int32_t *conf_of;  // configuration id by atom, or null (single configuration)
   const int32_t *order;    // cell-order position -> atom
   const int32_t *count;
   const int32_t *list;
@@ -144,13 +141,8 @@ struct FwdArgs {
 // launchers (implemented in the .hip files)
 void launch_fill_i32(int32_t *p, int32_t v, int64_t n, const int32_t *cond, hipStream_t s);
 void launch_fill_f64(double *p, double v, int64_t n, hipStream_t s);
-// type (may be null) is copied into nl.ts in the new cell order
-void nlist_build(NList &nl, const double *x, const int32_t *type, const int32_t *cond,
-                 uint32_t *err, hipStream_t s, int64_t *rebuild_counter = nullptr);
-// nl.xs and nl.ts (when x is given) and nl.fbs (when fbar is given) from
-// atom-ordered arrays
-void launch_to_cells(NList &nl, const double *x, const int32_t *type, const double *fbar,
-                     hipStream_t s);
+void nlist_build(NList &nl, const double *x, const int32_t *cond, uint32_t *err, hipStream_t s,
+                 int64_t *rebuild_counter = nullptr);
 void nlist_check(const NList &nl, const double *x, int32_t *flag, hipStream_t s);
 // F[a] (+)= fown[t] + sum of the incoming slots fslot[soff[t] .. soff[t + 1]), t = pos[a]
 // (FP32 slots when slot_f32), summed in FP64 in slot order
