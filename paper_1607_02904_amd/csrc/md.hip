@@ -94,12 +94,13 @@ DEV void reduce_energy(const double *__restrict__ partials, int nblocks, double 
   }
 }
 
-// Owner gather of the forces into F (FP64 sums, in slot order, of the
-// incoming slots of the atom, [soff[t], soff[t + 1]) with t = pos[i]), the
-// second half kick of this step and, with do_next, the first half kick, drift
-// and rebuild test of the next one (the operations of k_vv_first, in the same
-// order).  Thread per atom.  With a trace, the first workgroups also sum the
-// force kernel's energy partials.
+// Owner gather of the forces (FP64 sums, in slot order, of the incoming
+// slots of the atom, [soff[t], soff[t + 1]) with t = pos[i]), the second half
+// kick of this step and, with do_next, the first half kick, drift and rebuild
+// test of the next one (the operations of k_vv_first, in the same order).
+// The forces are stored in F only on the last step (without do_next): the
+// steps in between use them in registers.  Thread per atom.  With a trace,
+// the first workgroups also sum the force kernel's energy partials.
 template <class S>
 __global__ void k_vv_gather_kick_drift(int n, const int32_t *__restrict__ pos,
                                        const int32_t *__restrict__ soff,
@@ -126,7 +127,7 @@ __global__ void k_vv_gather_kick_drift(int n, const int32_t *__restrict__ pos,
     double r2 = 0.0;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      F[3 * i + a] = fv[a];
+      if (!do_next) F[3 * i + a] = fv[a];
       double vv = v[3 * i + a] + s * fv[a];
       if (do_next) {
         vv = vv + s * fv[a];
