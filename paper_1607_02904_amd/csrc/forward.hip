@@ -138,7 +138,7 @@ __global__ __launch_bounds__(BS) void k_force(FwdArgs a, int A) {
       int j = 0;
       if (at < na && s < s_lcnt[at]) {
         const int i = s_aid[at];
-        j = a.order[a.list[(int64_t)s_atom[at] * cap + s]];  // neighbour's atom
+        j = a.list[(int64_t)s_atom[at] * cap + s];  // neighbour's atom
         const ConfDesc &cf = a.conf[s_conf[at]];
         double dx = a.x[3 * j] - a.x[3 * i];
         double dy = a.x[3 * j + 1] - a.x[3 * i + 1];

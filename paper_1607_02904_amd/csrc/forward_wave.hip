@@ -217,8 +217,6 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEu<T, PG>::value))) void k_force_wave
       rw[u] = (valid && a.fslot) ? rl : -1;
     }
 #pragma unroll
-    for (int u = 0; u < kBatch; ++u) jw[u] = a.order[jw[u]];  // position -> atom
-#pragma unroll
     for (int u = 0; u < kBatch; ++u) {
 #pragma unroll
       for (int k = 0; k < 3; ++k) xw[u][k] = a.x[3 * (int64_t)jw[u] + k];

@@ -253,10 +253,9 @@ DEV int wrap_cell(int q, int nc) { return q < 0 ? q + nc : (q >= nc ? q - nc : q
 // nine lanes gives every lane its first position in the row, and a second pass
 // writes the hits there.
 //
-// Rows, counts and entries are in cell-order positions: row t lists the
-// atom at position t, its entries are the positions of its neighbours (the
-// rows of a run of atoms that a force wavefront takes are contiguous; the
-// atom of a position is order[position]).
+// Rows and counts are indexed by cell-order position: row t lists the
+// neighbours (atom indices) of the atom at position t, so that the rows of a
+// run of atoms that a force wavefront takes are contiguous.
 //
 // Incoming force slots (min(count, cap) per atom) are laid out without row
 // padding: each workgroup numbers its atoms' slots from 0 in processing order
@@ -393,13 +392,13 @@ __global__ __launch_bounds__(kBS) void k_build(int n, const double *__restrict__
         const int k = __ffsll((unsigned long long)mask) - 1;
         mask &= mask - 1ull;
         const int p = k < len0 ? b0 + k : b1 + (k - len0);
-        if (pos < cap) row[pos] = p;
+        if (pos < cap) row[pos] = order[p];
         ++pos;
       }
       for (int k = 64; k < len; ++k) {  // rows of more than 64 candidates
         const int p = k < len0 ? b0 + k : b1 + (k - len0);
         if (within(p)) {
-          if (pos < cap) row[pos] = p;
+          if (pos < cap) row[pos] = order[p];
           ++pos;
         }
       }
@@ -430,19 +429,22 @@ __global__ __launch_bounds__(kBS) void k_build(int n, const double *__restrict__
   }
 }
 
-// Global slot offsets and the reverse map (all indices are cell-order
-// positions).  Every workgroup first scans the build's per-workgroup slot
-// totals (nb <= kBuildMaxBlocks, in LDS), so the first slot of atom t is
-// off(t) = (slots of earlier build workgroups) + (t's number within its own);
-// workgroup 0 also stores the longest row.  Then, per atom t: soff[t] = off(t)
-// (slots increase along the cell order, so atom t's are [soff[t], soff[t + 1])),
-// and rev[t*cap + s] = incoming force slot at atom j = list[t*cap + s] that
-// holds the force of t's terms on j: off(j) + (position of t in j's row).  The list
+// Global slot offsets and the reverse map (rows, counts and slot records are
+// indexed by cell-order position, row entries are atoms).  Every workgroup
+// first scans the build's per-workgroup slot totals (nb <= kBuildMaxBlocks,
+// in LDS), so the first slot of the atom at position t is off(t) = (slots of
+// earlier build workgroups) + (t's number within its own); workgroup 0 also
+// stores the longest row.  Then, per position t: soff[t] = off(t) (slots
+// increase along the cell order, so t's are [soff[t], soff[t + 1])), and
+// rev[t*cap + s] = incoming force slot at atom j = list[t*cap + s] that holds
+// the force of t's terms on j: off(pos[j]) + (place of order[t] in row pos[j]).  The list
 // is symmetric by construction (r_ij and r_ji are computed from exactly
 // negated displacements), so the position exists; a missing one is latched as
 // an error.  The rows of 4 neighbours are searched together with 16-byte
 // loads (rows start 16-byte aligned: cap is a multiple of 4).
-__global__ __launch_bounds__(kBS) void k_reverse(int n, int cap, const int32_t *__restrict__ count,
+__global__ __launch_bounds__(kBS) void k_reverse(int n, int cap, const int32_t *__restrict__ order,
+                                                 const int32_t *__restrict__ pos,
+                                                 const int32_t *__restrict__ count,
                                                  const int32_t *__restrict__ list,
                                                  const int32_t *__restrict__ loff,
                                                  const int32_t *__restrict__ bsum, int nb,
@@ -488,16 +490,18 @@ __global__ __launch_bounds__(kBS) void k_reverse(int n, int cap, const int32_t *
   };
   for (int t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x; t < n;
        t += gridDim.x * blockDim.x) {
-    const int i = t;
-    const int ci = min(count[i], cap);
-    const int oi = offset_of(i);
+    const int i = order[t];  // the atom, as it appears in its neighbours' rows
+    const int ci = min(count[t], cap);
+    const int oi = offset_of(t);
     soff[t] = oi;  // slots of the atom at position t: [soff[t], soff[t + 1])
     if (t == n - 1) soff[n] = oi + ci;
-    const int32_t *row_i = list + (int64_t)i * cap;
+    const int32_t *row_i = list + (int64_t)t * cap;
     for (int s0 = 0; s0 < ci; s0 += 4) {
-      int j[4], cj[4], oj[4], found[4];
+      int j[4], cj[4], oj[4], found[4];  // j: neighbour's row (its position)
 #pragma unroll
       for (int u = 0; u < 4; ++u) j[u] = s0 + u < ci ? row_i[s0 + u] : i;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) j[u] = pos[j[u]];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const bool live = s0 + u < ci;
@@ -530,7 +534,7 @@ __global__ __launch_bounds__(kBS) void k_reverse(int n, int cap, const int32_t *
       for (int u = 0; u < 4; ++u) {
         if (s0 + u < ci) {
           if (found[u] < 0) atomicOr(err, kErrListAsymmetric);
-          rev[(int64_t)i * cap + s0 + u] = found[u] < 0 ? -1 : oj[u] + found[u];
+          rev[(int64_t)t * cap + s0 + u] = found[u] < 0 ? -1 : oj[u] + found[u];
         }
       }
     }
@@ -647,7 +651,8 @@ void nlist_build(NList &nl, const double *x, const int32_t *cond, uint32_t *err,
                                nl.cell_of.as<int32_t>(), cell_start, nl.rlist * nl.rlist, nl.cap,
                                nl.count.as<int32_t>(), nl.list.as<int32_t>(), nl.loff.as<int32_t>(),
                                nl.bsum.as<int32_t>(), cond, err, rebuild_counter);
-    k_reverse<<<grid(n), kBS, 0, s>>>(n, nl.cap, nl.count.as<int32_t>(),
+    k_reverse<<<grid(n), kBS, 0, s>>>(n, nl.cap, nl.order.as<int32_t>(), nl.pos.as<int32_t>(),
+                                      nl.count.as<int32_t>(),
                                       nl.list.as<int32_t>(), nl.loff.as<int32_t>(),
                                       nl.bsum.as<int32_t>(), gb, nl.soff.as<int32_t>(),
                                       nl.rev.as<int32_t>(), nl.maxcount.as<int32_t>(), cond, err);

@@ -80,7 +80,7 @@ struct NList {
   DevBuf conf;        // ConfDesc[nconf]
   DevBuf conf_of;     // int32[n] (only for nconf > 1)
   DevBuf count;       // int32[n]: row lengths, by cell-order position
-  DevBuf list;        // int32[n][cap]: row t = neighbours (cell-order positions) of the atom at t
+  DevBuf list;        // int32[n][cap]: row t = neighbours (atoms) of the atom at position t
   DevBuf order;       // int32[n]: atoms in cell order
   DevBuf cell_of;     // int32[n]
   DevBuf cell_count;  // int32[ncell + 1]
@@ -97,8 +97,8 @@ struct NList {
 };
 
 // Forward / adjoint launch description.
-// The list (count, list, rev) is indexed by cell-order position and holds
-// positions; order maps a position to its atom, which indexes the per-atom
+// The list rows (count, list, rev) are indexed by cell-order position and
+// hold atoms; order maps a position to its atom, which indexes the per-atom
 // arrays (x, type, fbar, conf_of and the outputs).
 struct FwdArgs {
   int32_t n;
