@@ -101,8 +101,8 @@ def main():
     import torch
 
     from paper_1607_02904_amd import inputs
-    from paper_1607_02904_amd.tersoff import (FP64, MIXED, BatchPlan, Tersoff, table_element,
-                                              table_sic)
+    from paper_1607_02904_amd.tersoff import (FP64, MIXED, SINGLE, BatchPlan, Tersoff,
+                                              table_element, table_sic)
 
     dev = "cuda"
     if args.copy_probe:
@@ -126,7 +126,7 @@ def main():
     # schedule per precision chosen by the library's autotuner on this input
     model.build_nlist(x0, td, box, skin)
     tuned = {}
-    for prec in (FP64, MIXED):
+    for prec in (FP64, MIXED, SINGLE):
         us = model.autotune(x0, td, box, prec)
         tuned[prec] = us
 
@@ -161,6 +161,10 @@ def main():
     el64, reb64, tr64, f64us = run_md(FP64)
     print("bench: MD mixed", file=sys.stderr, flush=True)
     elmx, rebmx, trmx, fmxus = run_md(MIXED)
+    elsp = None
+    if not args.md_only:
+        print("bench: MD single", file=sys.stderr, flush=True)
+        elsp, rebsp, trsp, fspus = run_md(SINGLE)
 
     # back-to-back launches of the force kernel alone on the start configuration
     model.build_nlist(x0, td, box, skin)
@@ -228,6 +232,10 @@ def main():
                  "ms_per_step": 1000.0 * el64 / args.steps, "rebuilds": reb64,
                  "schedule": sched["fp64"], "roofline": roof(f64us, k64, FP64_PEAK, sched["fp64"],
                                                               "double")},
+        "single": None if elsp is None else {
+            "value": n * args.steps / elsp, "unit": "atom-steps/s",
+            "ms_per_step": 1000.0 * elsp / args.steps, "rebuilds": rebsp, "kernel_us": fspus,
+            "note": "all-FP32 mode (FP32 positions and accumulators), the paper's Opt-S"},
         "ablation": ablation,
         "mixed": {"rebuilds": rebmx, "schedule": sched["mixed"],
                   "energy_drift_per_atom": float((trmx[-1] - trmx[0]) / n),
@@ -294,15 +302,16 @@ FTM2V = 9648.533212331  # eV/(Angstrom amu) -> Angstrom/ps^2 (metal units)
 
 def run_accuracy(args, out, dev):
     """Total energy along a long NVE trajectory of Si diamond 16^3 cells
-    (32,768 atoms, sigma 0.1 A, v0 = 0, dt 1 fs, skin 0.5 A) in FP64 and in the
-    mixed precision: the largest relative difference of the mixed total energy
-    from the FP64 one, and each path's largest total-energy deviation per atom
-    from its start.  The paper checks its mixed mode the same way (a long run
-    of about 32,000 Si atoms, FP64 as reference)."""
+    (32,768 atoms, sigma 0.1 A, v0 = 0, dt 1 fs, skin 0.5 A) in FP64, in the
+    mixed precision and in the single-precision mode: the largest relative
+    difference of each total energy from the FP64 one, and each path's largest
+    total-energy deviation per atom from its start.  The paper checks its
+    precision modes the same way (a long run of about 32,000 Si atoms, FP64
+    as reference)."""
     import torch
 
     from paper_1607_02904_amd import inputs
-    from paper_1607_02904_amd.tersoff import FP64, MIXED, Tersoff, table_element
+    from paper_1607_02904_amd.tersoff import FP64, MIXED, SINGLE, Tersoff, table_element
     print("bench: accuracy run", file=sys.stderr, flush=True)
     steps = 10000 if args.quick else 100000
     chunk = 2000
@@ -313,7 +322,7 @@ def run_accuracy(args, out, dev):
     td = torch.as_tensor(t, device=dev)
     series = {}
     t0 = time.perf_counter()
-    for prec in (FP64, MIXED):
+    for prec in (FP64, MIXED, SINGLE):
         xd = torch.as_tensor(x, device=dev).clone()
         v = torch.zeros_like(xd)
         f = torch.empty_like(xd)
@@ -328,12 +337,14 @@ def run_accuracy(args, out, dev):
         series[prec] = np.array(etot)
     el = time.perf_counter() - t0
     m.close()
-    e64, emx = series[FP64], series[MIXED]
+    e64, emx, esp = series[FP64], series[MIXED], series[SINGLE]
     out["accuracy"] = {
         "atoms": n, "steps": steps, "dt_fs": 1.0, "sample_every": chunk,
         "max_rel_dev_mixed_vs_fp64": float(np.max(np.abs(emx - e64) / np.abs(e64))),
+        "max_rel_dev_single_vs_fp64": float(np.max(np.abs(esp - e64) / np.abs(e64))),
         "max_drift_per_atom_fp64_eV": float(np.max(np.abs(e64 - e64[0])) / n),
         "max_drift_per_atom_mixed_eV": float(np.max(np.abs(emx - emx[0])) / n),
+        "max_drift_per_atom_single_eV": float(np.max(np.abs(esp - esp[0])) / n),
         "seconds": el,
     }
 

@@ -53,10 +53,17 @@ typedef enum {
 /* precision modes */
 enum {
   TERS_FP64 = 0, /* all arithmetic in FP64 */
-  TERS_MIXED = 1 /* FP32 arithmetic; FP64 displacements x_j - x_i (rounded
+  TERS_MIXED = 1, /* FP32 arithmetic; FP64 displacements x_j - x_i (rounded
                     to FP32 afterwards), FP64 rebuild check, FP64 force,
                     energy, virial and gradient accumulators (the paper,
                     Section V-F, mode Opt-M) */
+  TERS_SINGLE = 2 /* everything in FP32: positions rounded to FP32 before the
+                    displacement, FP32 accumulators for the forces, energy and
+                    virial of each wavefront (the paper, Section V-F, mode
+                    Opt-S); the per-wavefront sums, the per-atom force gather
+                    and the integration stay FP64.  Forward only: ters_compute
+                    (without TERS_PARAM_GRAD), ters_md_run, ters_autotune and
+                    ters_profile_forward; TERS_ERR_UNSUPPORTED elsewhere. */
 };
 
 /* output selection for ters_compute */

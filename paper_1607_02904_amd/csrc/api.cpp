@@ -28,11 +28,12 @@ struct ters_ctx {
   double rc_max = 0.0;
   int cut_consistent = 1;
   bool has_mass = false;
-  DevBuf kp64, kp32, filt2, mass;
+  DevBuf kp64, kp32, kp32s, filt2, mass;  // kp32s: FP32 records without hi/lo residuals
   NList nl;
   DevBuf partials, errw, flag, rebuilds, step, escratch;
-  int A[2] = {0, 0};     // atoms per workgroup / wavefront per precision (0 = default)
-  int kern[2] = {1, 1};  // force kernel per precision: 1 workgroup, 2 wavefront schedule
+  int A[3] = {0, 0, 0};     // atoms per workgroup / wavefront per precision (0 = default)
+  int kern[3] = {1, 1, 2};  // force kernel per precision: 1 workgroup, 2 wavefront schedule
+                            // (the single-precision mode has the wavefront schedule only)
   int kmax = 1 << 20;
   int gather = 1;        // 1: owner-gather forces (deterministic), 0: FP64 atomic scatter
   DevBuf fslot, fown;    // owner-gather buffers
@@ -241,7 +242,7 @@ FwdArgs base_args(ters_ctx *c, const NList &nl, int precision, int n, const doub
   a.list = nl.list.as<int32_t>();
   a.cap = nl.cap;
   a.ntypes = c->ntypes;
-  a.kparam = precision == TERS_FP64 ? c->kp64.p : c->kp32.p;
+  a.kparam = precision == TERS_FP64 ? c->kp64.p : (precision == TERS_SINGLE ? c->kp32s.p : c->kp32.p);
   a.filt2 = c->filt2.p;
   a.cut_consistent = c->cut_consistent;
   a.kmax = c->kmax;
@@ -274,7 +275,7 @@ std::vector<const void *> graph_key(const ters_ctx *c, const NList &nl) {
           nl.cell_count.p, nl.cell_start.p, nl.scan_tmp.p, nl.xref.p, nl.maxcount.p,
           (const void *)(intptr_t)nl.n, (const void *)(intptr_t)nl.cap,
           (const void *)(intptr_t)nl.ncell, (const void *)(intptr_t)nl.nconf, bits(nl.rlist),
-          bits(nl.skin), c->kp64.p, c->kp32.p, c->filt2.p, (const void *)(intptr_t)c->ntypes,
+          bits(nl.skin), c->kp64.p, c->kp32.p, c->kp32s.p, c->filt2.p, (const void *)(intptr_t)c->ntypes,
           (const void *)(intptr_t)c->cut_consistent, (const void *)(intptr_t)c->kmax,
           c->partials.p, c->errw.p, c->flag.p, c->rebuilds.p, c->step.p, c->escratch.p,
           nl.rev.p, nl.xs.p, nl.pos.p, nl.soff.p, nl.loff.p, nl.bsum.p, c->fslot.p, c->fown.p,
@@ -288,7 +289,7 @@ int kernel_blocks(int kern, int n, int A, bool pg = false) {
   return kern == 2 ? wave_blocks(n, A, pg) : forward_blocks(n, (A > 0 && A <= 64) ? A : 64);
 }
 void launch_fwd(int kern, const FwdArgs &a, int precision, int A, hipStream_t s) {
-  if (kern == 2) {
+  if (kern == 2 || precision == TERS_SINGLE) {
     launch_forward_wave(a, precision, A, s);
   } else {
     int nbo[1];
@@ -330,7 +331,7 @@ int run_forward(ters_ctx *c, const FwdArgs &a0, int precision, hipStream_t s,
   }
   launch_fwd(c->kern[precision], a, precision, c->A[precision], s);
   if (gather && do_gather)
-    launch_gather(c->nl, a.fslot, precision == TERS_MIXED, a.fown, a.forces,
+    launch_gather(c->nl, a.fslot, precision != TERS_FP64, a.fown, a.forces,
                   (a.flags & TERS_ACCUMULATE) ? 1 : 0, s);
   return nb;
 }
@@ -382,7 +383,7 @@ ters_status ters_destroy(ters_ctx *c) {
   c->plans.clear();
   if (c->md_exec) hipGraphExecDestroy(c->md_exec);
   if (c->capture_stream) hipStreamDestroy(c->capture_stream);
-  DevBuf *bufs[] = {&c->kp64, &c->kp32, &c->filt2, &c->mass, &c->partials, &c->errw, &c->flag,
+  DevBuf *bufs[] = {&c->kp64, &c->kp32, &c->kp32s, &c->filt2, &c->mass, &c->partials, &c->errw, &c->flag,
                     &c->rebuilds, &c->step, &c->escratch, &c->fslot, &c->fown, &c->nl.conf,
                     &c->nl.conf_of, &c->nl.count, &c->nl.list, &c->nl.order, &c->nl.cell_of,
                     &c->nl.cell_count, &c->nl.cell_start, &c->nl.scan_tmp, &c->nl.xref,
@@ -454,9 +455,13 @@ ters_status ters_set_params(ters_ctx *c, int32_t nt, const double *tab, const do
       }
     c->kp64.ensure(sizeof(KParam<double>) * ne);
     c->kp32.ensure(sizeof(KParam<float>) * ne);
+    c->kp32s.ensure(sizeof(KParam<float>) * ne);
+    std::vector<KParam<float>> k32s(k32);  // single precision: no hi/lo residuals
+    for (KParam<float> &k : k32s) k.A_lo = k.lam1_lo = k.B_lo = k.lam2_lo = k.R_lo = k.h_lo = 0.f;
     c->filt2.ensure(sizeof(double) * nt * nt);
     TERS_HIP_TRY(hipMemcpyAsync(c->kp64.p, k64.data(), sizeof(KParam<double>) * ne, hipMemcpyHostToDevice, c->stream));
     TERS_HIP_TRY(hipMemcpyAsync(c->kp32.p, k32.data(), sizeof(KParam<float>) * ne, hipMemcpyHostToDevice, c->stream));
+    TERS_HIP_TRY(hipMemcpyAsync(c->kp32s.p, k32s.data(), sizeof(KParam<float>) * ne, hipMemcpyHostToDevice, c->stream));
     TERS_HIP_TRY(hipMemcpyAsync(c->filt2.p, f2.data(), sizeof(double) * nt * nt, hipMemcpyHostToDevice, c->stream));
     if (mass) {
       c->mass.ensure(sizeof(double) * nt);
@@ -521,7 +526,9 @@ ters_status ters_compute_ex(ters_ctx *c, int32_t n, const double *x, const int32
                             double *forces, double *virial, double *e_atom, double *param_grad) {
   if (!c) return TERS_ERR_INVALID_ARG;
   return guard(c, [&]() {
-    require(precision == TERS_FP64 || precision == TERS_MIXED, TERS_ERR_INVALID_ARG, "bad precision");
+    require(precision >= TERS_FP64 && precision <= TERS_SINGLE, TERS_ERR_INVALID_ARG, "bad precision");
+    require(precision != TERS_SINGLE || !(flags & TERS_PARAM_GRAD), TERS_ERR_UNSUPPORTED,
+            "no parameter gradient in the single-precision mode");
     require(n >= 0 && (n == 0 || (x && type)), TERS_ERR_INVALID_ARG, "bad arguments");
     require(!(flags & TERS_ENERGY) || energy, TERS_ERR_INVALID_ARG, "energy output missing");
     require(!(flags & TERS_FORCES) || forces || n == 0, TERS_ERR_INVALID_ARG, "forces output missing");
@@ -558,7 +565,8 @@ ters_status ters_backward(ters_ctx *c, int32_t n, const double *x, const int32_t
                           double *x_grad, double *param_grad) {
   if (!c) return TERS_ERR_INVALID_ARG;
   return guard(c, [&]() {
-    require(precision == TERS_FP64 || precision == TERS_MIXED, TERS_ERR_INVALID_ARG, "bad precision");
+    require(precision >= TERS_FP64 && precision <= TERS_SINGLE, TERS_ERR_INVALID_ARG, "bad precision");
+    require(precision != TERS_SINGLE, TERS_ERR_UNSUPPORTED, "the single-precision mode is forward only");
     require(n >= 0 && (n == 0 || (x && type && f_bar && x_grad)) && param_grad, TERS_ERR_INVALID_ARG,
             "bad arguments");
     require(std::isfinite(e_bar), TERS_ERR_INVALID_ARG, "e_bar must be finite");
@@ -594,12 +602,13 @@ ters_status ters_set_schedule(ters_ctx *c, int32_t kernel, int32_t atoms, int32_
   const int k = kernel == 0 ? 1 : kernel;
   c->kern[0] = c->kern[1] = k;
   c->A[0] = c->A[1] = atoms;
+  if (k == 2) c->A[TERS_SINGLE] = atoms;  // the single mode runs the wavefront schedule
   c->kmax = kmax == 0 ? (1 << 20) : kmax;
   return TERS_OK;
 }
 
 ters_status ters_get_schedule(const ters_ctx *c, int32_t precision, int32_t *out3) {
-  if (!c || !out3 || (precision != TERS_FP64 && precision != TERS_MIXED)) return TERS_ERR_INVALID_ARG;
+  if (!c || !out3 || precision < TERS_FP64 || precision > TERS_SINGLE) return TERS_ERR_INVALID_ARG;
   out3[0] = c->kern[precision];
   out3[1] = c->A[precision];
   out3[2] = c->gather;
@@ -616,7 +625,7 @@ ters_status ters_autotune(ters_ctx *c, int32_t n, const double *x, const int32_t
                           const double *box, int precision, double *out_us) {
   if (!c) return TERS_ERR_INVALID_ARG;
   return guard(c, [&]() {
-    require(precision == TERS_FP64 || precision == TERS_MIXED, TERS_ERR_INVALID_ARG, "bad precision");
+    require(precision >= TERS_FP64 && precision <= TERS_SINGLE, TERS_ERR_INVALID_ARG, "bad precision");
     check_ready(c, c->nl, n, box);
     DevBuf f;
     f.ensure(sizeof(double) * 3 * (size_t)std::max(n, 1));
@@ -629,6 +638,7 @@ ters_status ters_autotune(ters_ctx *c, int32_t n, const double *x, const int32_t
     double best = 1e300;
     int bestA = 64, bestK = 1;
     for (const Cand &cd : cands) {
+      if (precision == TERS_SINGLE && cd.kern != 2) continue;  // wavefront schedule only
       const int A = cd.A;
       c->A[precision] = A;
       c->kern[precision] = cd.kern;
@@ -665,7 +675,7 @@ ters_status ters_profile_forward(ters_ctx *c, int32_t n, const double *x, const 
                                  int32_t with_gather, double *avg_us) {
   if (!c || !avg_us) return TERS_ERR_INVALID_ARG;
   return guard(c, [&]() {
-    require(precision == TERS_FP64 || precision == TERS_MIXED, TERS_ERR_INVALID_ARG, "bad precision");
+    require(precision >= TERS_FP64 && precision <= TERS_SINGLE, TERS_ERR_INVALID_ARG, "bad precision");
     require(reps >= 1, TERS_ERR_INVALID_ARG, "reps must be >= 1");
     check_ready(c, c->nl, n, box);
     DevBuf f;
@@ -689,7 +699,7 @@ ters_status ters_profile_forward(ters_ctx *c, int32_t n, const double *x, const 
     const bool gath = with_gather && c->gather;
     auto one = [&]() {
       launch_fwd(kern, a, precision, A, c->stream);
-      if (gath) launch_gather(c->nl, a.fslot, precision == TERS_MIXED, a.fown, a.forces, 1, c->stream);
+      if (gath) launch_gather(c->nl, a.fslot, precision != TERS_FP64, a.fown, a.forces, 1, c->stream);
     };
     one();  // warm-up
     TERS_HIP_TRY(hipEventRecord(e0, c->stream));
@@ -717,7 +727,7 @@ ters_status md_run_impl(ters_ctx *c, int32_t n, double *x, double *v, double *f,
                         double *force_us) {
   if (!c) return TERS_ERR_INVALID_ARG;
   return guard(c, [&]() {
-    require(precision == TERS_FP64 || precision == TERS_MIXED, TERS_ERR_INVALID_ARG, "bad precision");
+    require(precision >= TERS_FP64 && precision <= TERS_SINGLE, TERS_ERR_INVALID_ARG, "bad precision");
     require(n >= 0 && nsteps >= 0 && (n == 0 || (x && v && f && type)), TERS_ERR_INVALID_ARG, "bad arguments");
     require(std::isfinite(dt) && dt > 0.0, TERS_ERR_INVALID_ARG, "dt must be > 0");
     require(c->has_mass, TERS_ERR_PARAMS, "masses not set");
@@ -754,7 +764,7 @@ ters_status md_run_impl(ters_ctx *c, int32_t n, double *x, double *v, double *f,
       run_forward(c, a, precision, s, /*do_gather=*/false);
       if (force_us) TERS_HIP_TRY(hipEventRecord(ev[2 * k + 1], s));
       if (gather) {
-        launch_vv_gather_kick_drift(c->nl, x, v, f, c->fslot.p, precision == TERS_MIXED,
+        launch_vv_gather_kick_drift(c->nl, x, v, f, c->fslot.p, precision != TERS_FP64,
                                     c->fown.as<double>(), type, c->mass.as<double>(), dt, flag,
                                     last ? 0 : 1, c->partials.as<double>(), nb,
                                     c->escratch.as<double>(), trace, c->step.as<int32_t>(), s);
@@ -909,7 +919,8 @@ ters_status ters_batch_plan(ters_ctx *c, int32_t nconf, const int32_t *natoms,
   ters_status st = guard(c, [&]() {
     require(c->ntypes > 0, TERS_ERR_PARAMS, "parameters not set");
     require(nconf >= 1 && natoms && boxes, TERS_ERR_INVALID_ARG, "bad arguments");
-    require(precision == TERS_FP64 || precision == TERS_MIXED, TERS_ERR_INVALID_ARG, "bad precision");
+    require(precision >= TERS_FP64 && precision <= TERS_SINGLE, TERS_ERR_INVALID_ARG, "bad precision");
+    require(precision != TERS_SINGLE, TERS_ERR_UNSUPPORTED, "the single-precision mode is forward only");
     p->ctx = c;
     p->nconf = nconf;
     p->precision = precision;

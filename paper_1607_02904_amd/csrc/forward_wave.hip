@@ -63,16 +63,33 @@ DEV void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <class T, bool NT1, bool PG>
+// SP: the single-precision mode (T = float): positions rounded to FP32 before
+// the displacement, no hi/lo compensation (the parameter record passed in has
+// zero residuals), and every accumulator in FP32 as well; the per-wavefront
+// sums leave the kernel as FP64 partials.
+template <class T, bool NT1, bool PG, bool SP = false>
 __global__ __launch_bounds__(waves_per_group<PG>() * kWave)
 __attribute__((amdgpu_waves_per_eu(WavesPerEu<T, PG>::value))) void k_force_wave(FwdArgs a, int A) {
+  static_assert(!SP || (std::is_same<T, float>::value && !PG), "single precision: forward FP32 only");
   constexpr int kWPB = waves_per_group<PG>();
   using B = base_t<T>;
   using KP = KParam<B>;
-  using AT = acc_t<T>;
+  using AT = typename std::conditional<SP, float, acc_t<T>>::type;
+  // energy, virial and own-force accumulators
+  using EA = typename std::conditional<SP, float, double>::type;
+  auto wide = [](const T &v) -> AT {
+    if constexpr (SP) return v;
+    else return widen(v);
+  };
+  // x_j - x_i (in FP32 from FP32-rounded positions in the single mode)
+  auto sp_sub = [](double xj, double xi) -> double {
+    if constexpr (SP) return (double)((float)xj - (float)xi);
+    else return xj - xi;
+  };
   // the force of atom i's terms on one neighbour (a sum of a few terms, stored
   // in one slot) is accumulated in the kernel's arithmetic type in the mixed
-  // path, in FP64 otherwise; atom forces, energy and virial stay FP64
+  // path, in FP64 otherwise; atom forces, energy and virial stay FP64 (FP32 in
+  // the single-precision mode)
   using FA = typename std::conditional<std::is_same<T, float>::value, float, AT>::type;
   auto to_fa = [](const auto &v) -> FA { return (FA)v; };
   constexpr bool DUAL = IsDual<T>::value;
@@ -135,7 +152,7 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEu<T, PG>::value))) void k_force_wave
     else atomic_add(&a.pgrad[((ti * nt + tj) * nt + tk) * kNField + field], v);
   };
 
-  double eacc = 0.0, wacc[6] = {0, 0, 0, 0, 0, 0};
+  EA eacc = 0, wacc[6] = {0, 0, 0, 0, 0, 0};
   const uint32_t flags = a.flags;
   const bool want_f = DUAL ? (a.xgrad != nullptr) : ((flags & TERS_FORCES) && a.forces);
   const bool want_w = !DUAL && (flags & TERS_VIRIAL);
@@ -166,6 +183,15 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEu<T, PG>::value))) void k_force_wave
   const bool one_conf = a.conf_of == nullptr;
   // d <- minimum image of d in configuration cf
   auto min_image = [&](double *d, int cf) {
+    if constexpr (SP) {  // FP32 positions, FP32 displacement and image shift
+      const ConfDesc &c = a.conf[one_conf ? 0 : cf];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const float df = (float)d[k];
+        d[k] = (double)(df - (float)c.box[k] * rintf(df * (float)c.inv_box[k]));
+      }
+      return;
+    }
     if (one_conf) {
 #pragma unroll
       for (int k = 0; k < 3; ++k) d[k] -= box0[k] * rint(d[k] * ibox0[k]);
@@ -231,13 +257,18 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEu<T, PG>::value))) void k_force_wave
       const int e_at = lane_read(my_e, at), c_at = lane_read(my_cnt, at);
       double d[3];
 #pragma unroll
-      for (int k = 0; k < 3; ++k) d[k] = xw[u][k] - lane_read(my_x[k], at);
+      for (int k = 0; k < 3; ++k) d[k] = sp_sub(xw[u][k], lane_read(my_x[k], at));
       bool pass = false;
       const int j = jw[u];
       if (valid) {
         min_image(d, cf);
         const int tj = NT1 ? 0 : a.type[j];
-        pass = d[0] * d[0] + d[1] * d[1] + d[2] * d[2] < (NT1 ? filt2_0 : filt2[ti * nt + tj]);
+        const double f2 = NT1 ? filt2_0 : filt2[ti * nt + tj];
+        if constexpr (SP)
+          pass = (float)d[0] * (float)d[0] + (float)d[1] * (float)d[1] + (float)d[2] * (float)d[2] <
+                 (float)f2;
+        else
+          pass = d[0] * d[0] + d[1] * d[1] + d[2] * d[2] < f2;
       }
       const uint64_t m = __ballot(pass);
       // passes of the same atom in lower lanes of this window (e_at <= base + lane)
@@ -320,7 +351,7 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEu<T, PG>::value))) void k_force_wave
 #pragma unroll
       for (int k = 0; k < 3; ++k) d[k] = lane_read(my_x[k], at);
 #pragma unroll
-      for (int k = 0; k < 3; ++k) d[k] = a.x[3 * (int64_t)j + k] - d[k];
+      for (int k = 0; k < 3; ++k) d[k] = sp_sub(a.x[3 * (int64_t)j + k], d[k]);
       min_image(d, cf);
       if (!act) {
         d[0] = 1.0;
@@ -331,12 +362,18 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEu<T, PG>::value))) void k_force_wave
 #pragma unroll
       for (int k = 0; k < 3; ++k)
         dT[k] = Conv<T>::from(d[k], (DUAL && act) ? (a.fbar[3 * j + k] - a.fbar[3 * ia + k]) : 0.0);
-      const double r64 = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
       r = t_sqrt(dT[0] * dT[0] + dT[1] * dT[1] + dT[2] * dT[2]);
-      set_val(r, r64);
-      ri = rcp(r);
-      fcut64(param(ti, tj, tj), r, r64, fc, dfc);
-      rlo = (B)(r64 - (double)val(r));
+      if constexpr (SP) {
+        ri = rcp(r);
+        fcut(param(ti, tj, tj), r, fc, dfc);
+        rlo = B(0);
+      } else {
+        const double r64 = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        set_val(r, r64);
+        ri = rcp(r);
+        fcut64(param(ti, tj, tj), r, r64, fc, dfc);
+        rlo = (B)(r64 - (double)val(r));
+      }
       dx = dT[0];
       dy = dT[1];
       dz = dT[2];
@@ -385,7 +422,7 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEu<T, PG>::value))) void k_force_wave
     // pair term V(i, j, zeta)
     T dzeta = Zero<T>::get();
     FA f0 = Zero<FA>::get(), f1 = Zero<FA>::get(), f2 = Zero<FA>::get();
-    double ev = 0.0;
+    EA ev = 0;
     const double eb = DUAL ? (a.ebar_conf ? a.ebar_conf[cf] : a.ebar) : 1.0;
     if (in_pair) {
       const T fr = scaled_exp(pp.A, pp.A_lo, pp.lam1, pp.lam1_lo, r, rlo);
@@ -393,17 +430,17 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEu<T, PG>::value))) void k_force_wave
       T b, db, dbb, dbn;
       bond<T, B, PG>(pp, zeta, b, db, dbb, dbn);
       const T vr = fr + b * fa;
-      const AT V = widen(fc) * (widen(fr) + widen(b) * widen(fa));
+      const AT V = wide(fc) * (wide(fr) + wide(b) * wide(fa));
       const T dVdr = dfc * vr + fc * (-pp.lam1 * fr - pp.lam2 * b * fa);
       dzeta = B(0.5) * fc * fa * db;
       const T hp = B(0.5) * dVdr;
-      f0 = to_fa(widen(-(hp * u[0])));
-      f1 = to_fa(widen(-(hp * u[1])));
-      f2 = to_fa(widen(-(hp * u[2])));
+      f0 = to_fa(wide(-(hp * u[0])));
+      f1 = to_fa(wide(-(hp * u[1])));
+      f2 = to_fa(wide(-(hp * u[2])));
       if (kOnePass) {
-        f0 -= to_fa(widen(dzeta * gs[0]));
-        f1 -= to_fa(widen(dzeta * gs[1]));
-        f2 -= to_fa(widen(dzeta * gs[2]));
+        f0 -= to_fa(wide(dzeta * gs[0]));
+        f1 -= to_fa(wide(dzeta * gs[1]));
+        f2 -= to_fa(wide(dzeta * gs[2]));
       }
       ev = 0.5 * val(V);
       if (PG) {
@@ -418,7 +455,7 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEu<T, PG>::value))) void k_force_wave
         dp[6] = -B(0.5) * dfc * vr;
         dp[7] = -B(0.5) * dfc * (r - pp.R) * (B(1) / pp.D) * vr;
 #pragma unroll
-        for (int f = 0; f < 8; ++f) add_grad(ti, tj, tj, GradSlots::pair[f], out_of(widen(dp[f]), eb));
+        for (int f = 0; f < 8; ++f) add_grad(ti, tj, tj, GradSlots::pair[f], out_of(wide(dp[f]), eb));
       }
     }
     // ---- second K loop: dzeta/dx, forces on j (kept) and on k (sent) -----------
@@ -449,16 +486,16 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEu<T, PG>::value))) void k_force_wave
           const T v[3] = {kx * kri, ky * kri, kz * kri};
           T gj[3], gk[3], dp[8];
           zeta_term<T, B, PG>(pk, r, ri, u, kr, kri, v, fck, dfck, gj, gk, dp);
-          f0 -= to_fa(widen(dzeta * gj[0]));
-          f1 -= to_fa(widen(dzeta * gj[1]));
-          f2 -= to_fa(widen(dzeta * gj[2]));
+          f0 -= to_fa(wide(dzeta * gj[0]));
+          f1 -= to_fa(wide(dzeta * gj[1]));
+          f2 -= to_fa(wide(dzeta * gj[2]));
           cx = -(dzeta * gk[0]);
           cy = -(dzeta * gk[1]);
           cz = -(dzeta * gk[2]);
           if (PG) {
 #pragma unroll
             for (int fl = 0; fl < 8; ++fl)
-              add_grad(ti, tj, tk, GradSlots::three[fl], out_of(widen(dzeta * dp[fl]), eb));
+              add_grad(ti, tj, tk, GradSlots::three[fl], out_of(wide(dzeta * dp[fl]), eb));
           }
         }
       }
@@ -466,18 +503,18 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEu<T, PG>::value))) void k_force_wave
       // pull the force that lane (i, bq) computed for my atom in this step
       const T rx = lane_read(cx, bsrc), ry = lane_read(cy, bsrc), rz = lane_read(cz, bsrc);
       if (live) {
-        f0 += to_fa(widen(rx));
-        f1 += to_fa(widen(ry));
-        f2 += to_fa(widen(rz));
+        f0 += to_fa(wide(rx));
+        f1 += to_fa(wide(ry));
+        f2 += to_fa(wide(rz));
       }
     }
 
     // ---- f_im complete: virial, scatter to j, own force of i ------------------
     if (!DUAL && a.partials) {
-      double wv[7] = {ev, 0, 0, 0, 0, 0, 0};
+      EA wv[7] = {ev, 0, 0, 0, 0, 0, 0};
       if (act && want_w) {
-        const double ddx = val(widen(dx)), ddy = val(widen(dy)), ddz = val(widen(dz));
-        const double fx = val(f0), fy = val(f1), fz = val(f2);
+        const EA ddx = val(wide(dx)), ddy = val(wide(dy)), ddz = val(wide(dz));
+        const EA fx = val(f0), fy = val(f1), fz = val(f2);
         wv[1] = ddx * fx;
         wv[2] = ddy * fy;
         wv[3] = ddz * fz;
@@ -493,7 +530,7 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEu<T, PG>::value))) void k_force_wave
 #pragma unroll
           for (int k = 0; k < 7; ++k) {
             const double sum = wave_sum(wv[k]);
-            if (lane == 0) atomic_add(&a.partials[(int64_t)cf0 * 8 + k], sum);
+            if (lane == 0) atomic_add(&a.partials[(int64_t)cf0 * 8 + k], (double)sum);
           }
         } else if (act) {
 #pragma unroll
@@ -532,14 +569,14 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEu<T, PG>::value))) void k_force_wave
     }
     // own force of i (minus the sum of its slot forces; segmented sum over the
     // atom's lanes) and per-atom energy, taken by the atom's first lane
-    double sx = o0, sy = o1, sz = o2, se = ev;
+    EA sx = (EA)o0, sy = (EA)o1, sz = (EA)o2, se = ev;
     for (int s = 1; s < nmax && (want_f || want_ea); ++s) {
       const int src = (act && s < n_i) ? seg0 + s : lane;
-      double tx = 0.0, ty = 0.0, tz = 0.0, te = 0.0;
+      EA tx = 0, ty = 0, tz = 0, te = 0;
       if (want_f) {
-        tx = lane_read(o0, src);
-        ty = lane_read(o1, src);
-        tz = lane_read(o2, src);
+        tx = lane_read((EA)o0, src);
+        ty = lane_read((EA)o1, src);
+        tz = lane_read((EA)o2, src);
       }
       if (want_ea) te = lane_read(ev, src);
       if (act && q == 0 && s < n_i) {
@@ -585,7 +622,7 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEu<T, PG>::value))) void k_force_wave
 
   // ---- workgroup reductions ------------------------------------------------------
   if (!DUAL && a.partials && !a.conf_of) {
-    double vals[7] = {eacc, wacc[0], wacc[1], wacc[2], wacc[3], wacc[4], wacc[5]};
+    EA vals[7] = {eacc, wacc[0], wacc[1], wacc[2], wacc[3], wacc[4], wacc[5]};
     if (kWPB == 1) {
 #pragma unroll
       for (int k = 0; k < 7; ++k) {
@@ -621,7 +658,7 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEu<T, PG>::value))) void k_force_wave
   }
 }
 
-template <class T, bool PG>
+template <class T, bool PG, bool SP = false>
 void launch_wave_t(const FwdArgs &a, int A, hipStream_t s) {
   constexpr int kWPB = waves_per_group<PG>();
   if (A <= 0 || A > kAMax) A = 16;
@@ -629,9 +666,9 @@ void launch_wave_t(const FwdArgs &a, int A, hipStream_t s) {
   const int nb = (int)((a.n + per_block - 1) / per_block);
   if (nb == 0) return;
   if (a.ntypes == 1)
-    k_force_wave<T, true, PG><<<nb, kWPB * kWave, 0, s>>>(a, A);
+    k_force_wave<T, true, PG, SP><<<nb, kWPB * kWave, 0, s>>>(a, A);
   else
-    k_force_wave<T, false, PG><<<nb, kWPB * kWave, 0, s>>>(a, A);
+    k_force_wave<T, false, PG, SP><<<nb, kWPB * kWave, 0, s>>>(a, A);
 }
 
 }  // namespace
@@ -644,7 +681,9 @@ int wave_blocks(int n, int A, bool pg) {
 
 void launch_forward_wave(const FwdArgs &a, int precision, int A, hipStream_t s) {
   const bool pg = (a.flags & TERS_PARAM_GRAD) && a.pgrad;
-  if (precision == TERS_FP64) {
+  if (precision == TERS_SINGLE) {
+    launch_wave_t<float, false, true>(a, A, s);  // no parameter gradient in this mode
+  } else if (precision == TERS_FP64) {
     if (pg) launch_wave_t<double, true>(a, A, s);
     else launch_wave_t<double, false>(a, A, s);
   } else {

@@ -154,6 +154,11 @@ DEV double wave_sum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
   return v;
 }
+DEV float wave_sum(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
 DEV Dual<double> wave_sum(Dual<double> v) { return {wave_sum(v.v), wave_sum(v.d)}; }
 
 // Workgroups of a launch are dealt to the GPU's eight XCDs in turn

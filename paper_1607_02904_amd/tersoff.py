@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libtersoff.so")
 
 FP64 = 0
 MIXED = 1
+SINGLE = 2  # everything in FP32 (forward only)
 ENERGY, FORCES, VIRIAL, PER_ATOM_E, ACCUMULATE, PARAM_GRAD = 1, 2, 4, 8, 16, 32
 NFIELD = 14
 FIELDS = ("m", "gamma", "lam3", "c", "d", "h", "n", "beta", "lam2", "B", "R", "D", "lam1", "A")
@@ -203,7 +204,7 @@ class Tersoff:
     def schedules(self):
         """Current kernel / atoms / force mode per precision."""
         out = {}
-        for name, prec in (("fp64", FP64), ("mixed", MIXED)):
+        for name, prec in (("fp64", FP64), ("mixed", MIXED), ("single", SINGLE)):
             v = np.zeros(3, dtype=np.int32)
             self._chk(self._L.ters_get_schedule(self._h, prec, v.ctypes.data_as(ctypes.c_void_p)))
             out[name] = {"kernel": int(v[0]), "atoms": int(v[1]), "force_mode": "gather" if v[2] else "atomic"}
