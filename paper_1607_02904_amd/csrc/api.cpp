@@ -197,7 +197,7 @@ void nl_setup(NList &nl, int nconf, const int32_t *natoms, const double *boxes, 
   nl.cell_start.ensure(sizeof(int32_t) * (cells + 1));
   nl.scan_tmp.ensure(sizeof(int32_t) * ((cells + 1) / 1024 + 2));
   nl.xref.ensure(sizeof(double) * 3 * nn);
-  nl.xs.ensure(sizeof(double) * 3 * nn);
+  nl.xs.ensure(sizeof(float) * 4 * nn);
   nl.pos.ensure(sizeof(int32_t) * nn);
   nl.soff.ensure(sizeof(int32_t) * (nn + 1));
   nl.loff.ensure(sizeof(int32_t) * nn);

@@ -21,6 +21,9 @@
 #include "ters_device.h"
 #include "ters_internal.h"
 
+#include <algorithm>
+#include <cmath>
+
 namespace ters {
 
 namespace {
@@ -211,11 +214,14 @@ __global__ void k_place(int n, const double *__restrict__ x, const int32_t *__re
 
 // order atoms inside each cell by index, record each atom's position in the
 // cell order (pos, the inverse of order) and copy the positions in that order
-// for the build (xs); the counts (used as placement cursors) are cleared for
+// for the build (xs: FP32, wrapped into the configuration's box; the build's
+// distance test allows for that rounding); the counts (used as placement
+// cursors) are cleared for
 // the next build
 __global__ void k_sort_cells(int64_t ncell, const int32_t *__restrict__ cell_start,
                              int32_t *__restrict__ order, int32_t *__restrict__ counts,
-                             const double *__restrict__ x, double *__restrict__ xs,
+                             const double *__restrict__ x, const ConfDesc *__restrict__ conf,
+                             const int32_t *__restrict__ conf_of, float4 *__restrict__ xs,
                              int32_t *__restrict__ pos, const int32_t *cond) {
   if (skip(cond)) return;
   for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < ncell;
@@ -233,9 +239,14 @@ __global__ void k_sort_cells(int64_t ncell, const int32_t *__restrict__ cell_sta
     for (int p = b; p < e; ++p) {
       const int i = order[p];
       pos[i] = p;
-      xs[3 * p] = x[3 * i];
-      xs[3 * p + 1] = x[3 * i + 1];
-      xs[3 * p + 2] = x[3 * i + 2];
+      const ConfDesc &cf = conf[conf_index(conf_of, i)];
+      float w[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const double v = x[3 * i + a];
+        w[a] = (float)(v - cf.box[a] * floor(v * cf.inv_box[a]));
+      }
+      xs[p] = make_float4(w[0], w[1], w[2], 0.f);
     }
     counts[c] = 0;
   }
@@ -265,13 +276,13 @@ constexpr int kRows = 9;
 constexpr int kAtomsPerWave = kWave / kRows;  // 7
 constexpr int kBuildMaxBlocks = 4096;         // bsum holds 2 ints per block
 constexpr int kLoffBits = 19;                 // slots numbered within a workgroup
-__global__ __launch_bounds__(kBS) void k_build(int n, const double *__restrict__ xs,
+__global__ __launch_bounds__(kBS) void k_build(int n, const float4 *__restrict__ xs,
                                                const ConfDesc *__restrict__ conf,
                                                const int32_t *__restrict__ conf_of,
                                                const int32_t *__restrict__ order,
                                                const int32_t *__restrict__ cell_of,
                                                const int32_t *__restrict__ cell_start,
-                                               double rl2, int cap, int32_t *__restrict__ count,
+                                               float rl2, int cap, int32_t *__restrict__ count,
                                                int32_t *__restrict__ list,
                                                int32_t *__restrict__ loff,
                                                int32_t *__restrict__ bsum, const int32_t *cond,
@@ -299,14 +310,15 @@ __global__ __launch_bounds__(kBS) void k_build(int n, const double *__restrict__
     const bool act = g < gend && la < kAtomsPerWave && t64 < n;
     const int t = act ? (int)t64 : -1;
     int i = 0, b0 = 0, e0 = 0, b1 = 0, e1 = 0;
-    double xi = 0.0, yi = 0.0, zi = 0.0;
+    float xi = 0.f, yi = 0.f, zi = 0.f;
     const ConfDesc *c = conf;
     if (act) {
       i = order[t];
       c = conf + conf_index(conf_of, i);
-      xi = xs[3 * t];
-      yi = xs[3 * t + 1];
-      zi = xs[3 * t + 2];
+      const float4 q = xs[t];
+      xi = q.x;
+      yi = q.y;
+      zi = q.z;
       const int lc = cell_of[i] - c->cell_off;
       const int nx = c->nc[0], ny = c->nc[1], nz = c->nc[2];
       const int cx = lc % nx, cy = (lc / nx) % ny, cz = lc / (nx * ny);
@@ -340,37 +352,39 @@ __global__ __launch_bounds__(kBS) void k_build(int n, const double *__restrict__
       }
     }
     const int len0 = e0 - b0, len = len0 + (e1 - b1);
-    const double bx = c->box[0], by = c->box[1], bz = c->box[2];
-    const double ibx = c->inv_box[0], iby = c->inv_box[1], ibz = c->inv_box[2];
-    // minimum image (positions need not lie inside the box); exactly negated
+    const float bx = (float)c->box[0], by = (float)c->box[1], bz = (float)c->box[2];
+    const float ibx = (float)c->inv_box[0], iby = (float)c->inv_box[1], ibz = (float)c->inv_box[2];
+    // minimum image in FP32 (the squared radius carries a margin for the
+    // rounding, so the list is a superset of the exact one); exactly negated
     // for (j, i), so the list is symmetric
-    auto within_at = [&](int p, double px, double py, double pz) {
-      double dx = px - xi, dy = py - yi, dz = pz - zi;
-      dx -= bx * rint(dx * ibx);
-      dy -= by * rint(dy * iby);
-      dz -= bz * rint(dz * ibz);
+    auto within_at = [&](int p, float px, float py, float pz) {
+      float dx = px - xi, dy = py - yi, dz = pz - zi;
+      dx -= bx * rintf(dx * ibx);
+      dy -= by * rintf(dy * iby);
+      dz -= bz * rintf(dz * ibz);
       return p != t && dx * dx + dy * dy + dz * dz <= rl2;
     };
-    auto within = [&](int p) { return within_at(p, xs[3 * p], xs[3 * p + 1], xs[3 * p + 2]); };
+    auto within = [&](int p) {
+      const float4 q = xs[p];
+      return within_at(p, q.x, q.y, q.z);
+    };
     // pass 1: count (the first 64 hits of the runs also as a mask); the
     // positions of four candidates are fetched before any is tested
     int nhit = 0;
     uint64_t mask = 0;
     for (int k0 = 0; k0 < len; k0 += 4) {
-      double px[4], py[4], pz[4];
+      float4 q[4];
       int pp[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int k = min(k0 + u, len - 1);
         pp[u] = k < len0 ? b0 + k : b1 + (k - len0);
-        px[u] = xs[3 * pp[u]];
-        py[u] = xs[3 * pp[u] + 1];
-        pz[u] = xs[3 * pp[u] + 2];
+        q[u] = xs[pp[u]];
       }
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int k = k0 + u;
-        if (k < len && within_at(pp[u], px[u], py[u], pz[u])) {
+        if (k < len && within_at(pp[u], q[u].x, q[u].y, q[u].z)) {
           ++nhit;
           if (k < 64) mask |= 1ull << k;
         }
@@ -642,13 +656,21 @@ void nlist_build(NList &nl, const double *x, const int32_t *cond, uint32_t *err,
     k_place<<<grid(n), kBS, 0, s>>>(n, x, nl.cell_of.as<int32_t>(), cell_start, cell_count,
                                     nl.order.as<int32_t>(), nl.xref.as<double>(), cond);
     k_sort_cells<<<grid(ncell), kBS, 0, s>>>(ncell, cell_start, nl.order.as<int32_t>(), cell_count,
-                                             x, nl.xs.as<double>(), nl.pos.as<int32_t>(), cond);
+                                             x, conf, conf_of, nl.xs.as<float4>(),
+                                             nl.pos.as<int32_t>(), cond);
     // the list build is latency-bound: a larger grid than the other kernels
     const int64_t groups = (n + kAtomsPerWave - 1) / kAtomsPerWave;
     const int gb = (int)std::min<int64_t>(
         std::max<int64_t>((groups + kBS / kWave - 1) / (kBS / kWave), 1), kBuildMaxBlocks);
-    k_build<<<gb, kBS, 0, s>>>(n, nl.xs.as<double>(), conf, conf_of, nl.order.as<int32_t>(),
-                               nl.cell_of.as<int32_t>(), cell_start, nl.rlist * nl.rlist, nl.cap,
+    // FP32 distance test on positions wrapped into the box: a coordinate is
+    // rounded by at most 2^-24 of the longest side, a squared distance by a
+    // few units in the last place; the radius grows by a bound of both, so no
+    // pair within r_list is missed (the filter applies the exact cutoffs)
+    double lmax = 0.0;
+    for (const ConfDesc &d : nl.conf_h) lmax = std::max({lmax, d.box[0], d.box[1], d.box[2]});
+    const double rl = nl.rlist + 8.0 * std::ldexp(lmax, -24) + std::ldexp(nl.rlist, -18);
+    k_build<<<gb, kBS, 0, s>>>(n, nl.xs.as<float4>(), conf, conf_of, nl.order.as<int32_t>(),
+                               nl.cell_of.as<int32_t>(), cell_start, (float)(rl * rl), nl.cap,
                                nl.count.as<int32_t>(), nl.list.as<int32_t>(), nl.loff.as<int32_t>(),
                                nl.bsum.as<int32_t>(), cond, err, rebuild_counter);
     k_reverse<<<grid(n), kBS, 0, s>>>(n, nl.cap, nl.order.as<int32_t>(), nl.pos.as<int32_t>(),

@@ -89,7 +89,7 @@ struct NList {
   DevBuf xref;        // double[n][3]
   DevBuf maxcount;    // int32[1]
   DevBuf rev;         // int32[n][cap]: incoming force slot at j of row entry (t, j)
-  DevBuf xs;          // double[n][3]: positions at build time, in cell order
+  DevBuf xs;          // float4[n]: positions at build time, in cell order, wrapped into the box (FP32)
   DevBuf pos;         // int32[n]: position of each atom in the cell order (inverse of order)
   DevBuf soff;        // int32[n + 1]: first incoming force slot of the atom at each cell-order position
   DevBuf loff;        // int32[n]: build workgroup (high bits) and slot number within it
