@@ -202,6 +202,12 @@ def main():
                     fk["%s_%s_%s" % (tag, name, "gather" if gather else "atomic")] = \
                         model.profile_forward(x0, td, box, prec, reps=10, with_gather=True)
         model.set_force_mode(True)
+        model.set_schedule(2, 32, 0)
+        model.set_filter(False)  # every skin-list entry takes a lane
+        for prec, tag in ((MIXED, "mixed"), (FP64, "fp64")):
+            fk["%s_wavefront_32_gather_filter_off" % tag] = \
+                model.profile_forward(x0, td, box, prec, reps=10, with_gather=True)
+        model.set_filter(True)
         model.set_schedule(sched["mixed"]["kernel"], sched["mixed"]["atoms"], 0)
         el0, reb0, _, _ = run_md(MIXED, skin=0.0, kernel_times=False)
         ablation = {"time_to_forces_us": fk,

@@ -228,6 +228,13 @@ ters_status ters_get_schedule(const ters_ctx *ctx, int32_t precision, int32_t *o
  * through a reverse-slot map built with the list (no atomics; results are
  * bitwise reproducible); 0 = scatter with FP64 atomic adds. */
 ters_status ters_set_force_mode(ters_ctx *ctx, int32_t mode);
+/* The filter of the paper's Section IV-B/IV-D (only list entries inside the
+ * largest cutoff reach the compute lanes): 1 (default) = on; 0 = off, every
+ * list entry, skin included, takes a lane and the cutoff is applied inside
+ * the K loops.  Results are the same either way; the switch exists to
+ * measure the filter.  The wavefront schedule honours it; the workgroup
+ * schedule always filters.  TERS_ERR_INVALID_ARG for other values. */
+ters_status ters_set_filter(ters_ctx *ctx, int32_t enabled);
 /* Time the candidate schedules (both kernels, several atom counts) on the
  * current list and keep the fastest for this precision (synchronises).
  * out_us (host, may be NULL) gets the best time. */

@@ -35,6 +35,7 @@ struct ters_ctx {
   int kern[3] = {1, 1, 2};  // force kernel per precision: 1 workgroup, 2 wavefront schedule
                             // (the single-precision mode has the wavefront schedule only)
   int kmax = 1 << 20;
+  int filter = 1;        // 0: the wavefront schedule skips the filter (ablation)
   int gather = 1;        // 1: owner-gather forces (deterministic), 0: FP64 atomic scatter
   DevBuf fslot, fown;    // owner-gather buffers
   // molecular-dynamics step graph
@@ -246,6 +247,7 @@ FwdArgs base_args(ters_ctx *c, const NList &nl, int precision, int n, const doub
   a.filt2 = c->filt2.p;
   a.cut_consistent = c->cut_consistent;
   a.kmax = c->kmax;
+  a.no_filter = c->filter ? 0 : 1;
   a.rev = nl.rev.as<int32_t>();
   return a;
 }
@@ -277,6 +279,7 @@ std::vector<const void *> graph_key(const ters_ctx *c, const NList &nl) {
           (const void *)(intptr_t)nl.ncell, (const void *)(intptr_t)nl.nconf, bits(nl.rlist),
           bits(nl.skin), c->kp64.p, c->kp32.p, c->kp32s.p, c->filt2.p, (const void *)(intptr_t)c->ntypes,
           (const void *)(intptr_t)c->cut_consistent, (const void *)(intptr_t)c->kmax,
+          (const void *)(intptr_t)c->filter,
           c->partials.p, c->errw.p, c->flag.p, c->rebuilds.p, c->step.p, c->escratch.p,
           nl.rev.p, nl.xs.p, nl.pos.p, nl.soff.p, nl.loff.p, nl.bsum.p, c->fslot.p, c->fown.p,
           (const void *)(intptr_t)c->gather};
@@ -612,6 +615,12 @@ ters_status ters_get_schedule(const ters_ctx *c, int32_t precision, int32_t *out
   out3[0] = c->kern[precision];
   out3[1] = c->A[precision];
   out3[2] = c->gather;
+  return TERS_OK;
+}
+
+ters_status ters_set_filter(ters_ctx *c, int32_t enabled) {
+  if (!c || enabled < 0 || enabled > 1) return TERS_ERR_INVALID_ARG;
+  c->filter = enabled;
   return TERS_OK;
 }
 

@@ -269,6 +269,7 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEu<T, PG>::value))) void k_force_wave
                  (float)f2;
         else
           pass = d[0] * d[0] + d[1] * d[1] + d[2] * d[2] < f2;
+        pass = pass || a.no_filter;  // without the filter every entry takes a lane
       }
       const uint64_t m = __ballot(pass);
       // passes of the same atom in lower lanes of this window (e_at <= base + lane)

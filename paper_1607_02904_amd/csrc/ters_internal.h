@@ -116,6 +116,7 @@ struct FwdArgs {
   const void *filt2;       // B[ntypes^2]: squared filter radius per (ti, tk)
   int32_t cut_consistent;  // 1 if the k-cutoff never depends on tj
   int32_t kmax;
+  int32_t no_filter;       // wavefront schedule: every list entry takes a lane (ablation)
   uint32_t flags;
   double *forces;          // [n][3] (atomic accumulate) or null
   double *e_atom;          // [n] or null

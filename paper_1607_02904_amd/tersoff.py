@@ -33,7 +33,7 @@ EXPORTS = ("ters_create", "ters_destroy", "ters_set_stream", "ters_sync", "ters_
            "ters_compute", "ters_compute_ex", "ters_backward", "ters_md_run", "ters_md_run_timed",
            "ters_md_rebuilds",
            "ters_batch_plan", "ters_batch_run", "ters_plan_destroy", "ters_plan_schedule",
-           "ters_set_schedule", "ters_get_schedule", "ters_set_force_mode", "ters_autotune",
+           "ters_set_schedule", "ters_get_schedule", "ters_set_force_mode", "ters_set_filter", "ters_autotune",
            "ters_profile_forward",
            "ters_table_sic",
            "ters_table_element", "ters_version")
@@ -80,6 +80,7 @@ def load_library(path=LIB_PATH):
         "ters_plan_schedule": [P, P],
         "ters_set_schedule": [P, I32, I32, I32],
         "ters_set_force_mode": [P, I32],
+        "ters_set_filter": [P, I32],
         "ters_get_schedule": [P, I32, P],
         "ters_autotune": [P, I32, P, P, P, ctypes.c_int, P],
         "ters_profile_forward": [P, I32, P, P, P, ctypes.c_int, I32, I32, P],
@@ -209,6 +210,11 @@ class Tersoff:
             self._chk(self._L.ters_get_schedule(self._h, prec, v.ctypes.data_as(ctypes.c_void_p)))
             out[name] = {"kernel": int(v[0]), "atoms": int(v[1]), "force_mode": "gather" if v[2] else "atomic"}
         return out
+
+    def set_filter(self, enabled=True):
+        """Filter of in-cutoff pairs before the compute lanes (wavefront schedule);
+        off only to measure it."""
+        self._chk(self._L.ters_set_filter(self._h, 1 if enabled else 0))
 
     def set_force_mode(self, gather=True):
         """gather=True: owner-gather (deterministic, no atomics); False: FP64 atomics."""

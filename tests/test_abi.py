@@ -53,6 +53,8 @@ def test_null_arguments_are_rejected_without_a_device():
     assert L.ters_table_sic(None) == 1
     assert L.ters_destroy(None) == 1
     assert L.ters_sync(None) == 1
+    assert L.ters_set_filter(None, 1) == 1
+    assert L.ters_set_force_mode(None, 1) == 1
     out = ctypes.c_void_p()
     assert L.ters_create(None, 0, None) == 1
     assert L.ters_last_error(None) == b"null context"

@@ -343,3 +343,27 @@ def test_single_precision_forward_only(si_model):
     with pytest.raises(TersoffError) as ei:
         si_model.backward(xd, td, box, 1.0, torch.zeros_like(xd), precision=2)
     assert ei.value.code == 7
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
+def test_filter_off_gives_the_same_result(orc, sic_model, precision):
+    """Without the filter (every skin-list entry takes a lane, the cutoff is
+    applied inside the K loops) the wavefront schedule still meets the
+    oracle's bars: the filter changes the speed, not the result."""
+    x, t, box = inputs.sic_liquid_batch(nconf=1, nmin=700, nmax=1500, seed=101)[0]
+    ref = orc.compute(x, t, box, params.sic())
+    scale = energy_scale(orc, x, t, box, params.sic())
+    sic_model.set_schedule(2, 16, 0)
+    sic_model.set_filter(False)
+    try:
+        xd, td = _dev(x), _dev(t, torch.int32)
+        sic_model.build_nlist(xd, td, box, 0.5)  # skin entries present
+        o = sic_model.compute(xd, td, box, precision, per_atom=True)
+        torch.cuda.synchronize()
+        sic_model.sync()
+        got = (float(o["energy"].item()), o["forces"].cpu().numpy(), o["virial"].cpu().numpy(),
+               o["e_atom"].cpu().numpy())
+    finally:
+        sic_model.set_filter(True)
+        sic_model.set_schedule(0, 0, 0)
+    _check(got, ref, precision, escale=scale)
