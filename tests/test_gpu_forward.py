@@ -367,3 +367,25 @@ def test_filter_off_gives_the_same_result(orc, sic_model, precision):
         sic_model.set_filter(True)
         sic_model.set_schedule(0, 0, 0)
     _check(got, ref, precision, escale=scale)
+
+
+@pytest.mark.parametrize("skin", [0.0, 0.5])
+def test_list_is_the_exact_list_up_to_the_rounding_margin(sic_model, skin):
+    """The device list tests distances in FP32 on positions wrapped into the
+    box, with the radius widened by a bound of that rounding: it holds every
+    pair within r_list (counted here in FP64 with a k-d tree, both
+    directions) and nothing beyond r_list + 1e-3 A."""
+    from scipy.spatial import cKDTree
+    x, t, box = inputs.sic_liquid_batch(nconf=1, nmin=1500, nmax=3000, seed=102)[0]
+    xd, td = _dev(x), _dev(t, torch.int32)
+    sic_model.build_nlist(xd, td, box, skin)
+    st = sic_model.nlist_stats()
+    n, entries, longest, cap = st["n"], st["entries"], st["longest"], st["capacity"]
+    tab = params.sic()
+    rlist = float(np.max(tab[..., params.IDX["R"]] + tab[..., params.IDX["D"]])) + skin
+    xw = x - np.floor(x / box) * box
+    tree = cKDTree(xw, boxsize=box)
+    exact = 2 * len(tree.query_pairs(rlist))
+    wide = 2 * len(tree.query_pairs(rlist + 1e-3))
+    assert n == len(x) and longest <= cap
+    assert exact <= entries <= wide, (exact, entries, wide)
