@@ -202,6 +202,10 @@ def main():
                     model.set_force_mode(gather)
                     fk["%s_%s_%s" % (tag, name, "gather" if gather else "atomic")] = \
                         model.profile_forward(x0, td, box, prec, reps=10, with_gather=True)
+        model.set_schedule(3, 0, 0)  # thread per atom (the paper's scheme (c)), atomics
+        for prec, tag in ((MIXED, "mixed"), (FP64, "fp64")):
+            fk["%s_thread_per_atom_atomic" % tag] = \
+                model.profile_forward(x0, td, box, prec, reps=10, with_gather=True)
         model.set_force_mode(True)
         model.set_schedule(2, 32, 0)
         model.set_filter(False)  # every skin-list entry takes a lane

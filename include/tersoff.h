@@ -213,11 +213,16 @@ ters_status ters_plan_schedule(const ters_plan *plan, double *out3);
  * atoms' pairs in LDS and keeps dzeta/dx_k of up to k_max neighbours per pair,
  * the paper's Algorithm 3), 2 = wavefront schedule (each wavefront works alone,
  * pair data in registers exchanged by cross-lane permutes, the two K loops of
- * Algorithm 2), 0 = default (1).  atoms: atoms per workgroup (kernel 1,
- * <= 64) or per wavefront (kernel 2, <= 32); 0 = default.  kmax (kernel 1):
- * stored dzeta/dx_k per pair before falling back to recomputing them (the
- * paper's k_max, Section IV-A); 0 = store all that fit.  Applies to both
- * precisions. */
+ * Algorithm 2 with dzeta/dx_k of the first four k kept), 3 = thread per atom
+ * (the paper's mapping scheme (c), Section IV-B: one thread walks its atom's
+ * j and k; forward only, forces scattered with FP64 atomics whatever the
+ * force mode; kept as a baseline), 0 = default (1).  atoms: atoms per
+ * workgroup (kernel 1, <= 64) or per wavefront (kernel 2, <= 32), ignored by
+ * kernel 3; 0 = default.  kmax (kernel 1): stored dzeta/dx_k per pair before
+ * falling back to recomputing them (the paper's k_max, Section IV-A); 0 =
+ * store all that fit.  Applies to the FP64 and mixed precisions (the single
+ * mode always runs kernel 2).  ters_backward refuses kernel 3 with
+ * TERS_ERR_UNSUPPORTED. */
 ters_status ters_set_schedule(ters_ctx *ctx, int32_t kernel, int32_t atoms, int32_t kmax);
 /* Current schedule for a precision: out3[0] = kernel (1 or 2), out3[1] =
  * atoms per workgroup/wavefront (0 = default), out3[2] = force mode. */

@@ -289,10 +289,13 @@ std::vector<const void *> graph_key(const ters_ctx *c, const NList &nl) {
 // wavefront schedule (kern 2, atoms per wavefront).  Returns the number of
 // per-workgroup partial records written (single-system mode).
 int kernel_blocks(int kern, int n, int A, bool pg = false) {
+  if (kern == 3) return thread_blocks(n);
   return kern == 2 ? wave_blocks(n, A, pg) : forward_blocks(n, (A > 0 && A <= 64) ? A : 64);
 }
 void launch_fwd(int kern, const FwdArgs &a, int precision, int A, hipStream_t s) {
-  if (kern == 2 || precision == TERS_SINGLE) {
+  if (kern == 3 && precision != TERS_SINGLE) {
+    launch_forward_thread(a, precision, s);
+  } else if (kern == 2 || precision == TERS_SINGLE) {
     launch_forward_wave(a, precision, A, s);
   } else {
     int nbo[1];
@@ -324,7 +327,8 @@ int run_forward(ters_ctx *c, const FwdArgs &a0, int precision, hipStream_t s,
   c->partials.ensure(sizeof(double) * 8 * (size_t)std::max(nb, 1));
   a.partials = c->partials.as<double>();
   a.err = c->errw.as<uint32_t>();
-  const bool gather = c->gather && a.forces;
+  // the thread-per-atom schedule scatters with atomics only
+  const bool gather = c->gather && a.forces && c->kern[precision] != 3;
   if (gather) {
     ensure_gather(c->fslot, c->fown, c->nl);
     a.fslot = c->fslot.p;
@@ -573,6 +577,7 @@ ters_status ters_backward(ters_ctx *c, int32_t n, const double *x, const int32_t
     require(n >= 0 && (n == 0 || (x && type && f_bar && x_grad)) && param_grad, TERS_ERR_INVALID_ARG,
             "bad arguments");
     require(std::isfinite(e_bar), TERS_ERR_INVALID_ARG, "e_bar must be finite");
+    require(c->kern[precision] != 3, TERS_ERR_UNSUPPORTED, "the thread-per-atom schedule is forward only");
     check_ready(c, c->nl, n, box);
     FwdArgs a = base_args(c, c->nl, precision, n, x, type);
     a.fbar = f_bar;
@@ -600,7 +605,7 @@ ters_status ters_backward(ters_ctx *c, int32_t n, const double *x, const int32_t
 
 ters_status ters_set_schedule(ters_ctx *c, int32_t kernel, int32_t atoms, int32_t kmax) {
   if (!c) return TERS_ERR_INVALID_ARG;
-  if (kernel < 0 || kernel > 2 || kmax < 0) return TERS_ERR_INVALID_ARG;
+  if (kernel < 0 || kernel > 3 || kmax < 0) return TERS_ERR_INVALID_ARG;
   if (atoms < 0 || atoms > (kernel == 2 ? 32 : 64)) return TERS_ERR_INVALID_ARG;
   const int k = kernel == 0 ? 1 : kernel;
   c->kern[0] = c->kern[1] = k;
@@ -692,7 +697,8 @@ ters_status ters_profile_forward(ters_ctx *c, int32_t n, const double *x, const 
     FwdArgs a = base_args(c, c->nl, precision, n, x, type);
     a.flags = TERS_FORCES | TERS_ENERGY | TERS_VIRIAL | TERS_ACCUMULATE;
     a.forces = f.as<double>();
-    if (c->gather) {
+    const bool gmode = c->gather && c->kern[precision] != 3;  // thread schedule: atomics only
+    if (gmode) {
       ensure_gather(c->fslot, c->fown, c->nl);
       a.fslot = c->fslot.p;
       a.fown = c->fown.as<double>();
@@ -705,7 +711,7 @@ ters_status ters_profile_forward(ters_ctx *c, int32_t n, const double *x, const 
     TERS_HIP_TRY(hipEventCreate(&e0));
     TERS_HIP_TRY(hipEventCreate(&e1));
     const int kern = c->kern[precision], A = c->A[precision];
-    const bool gath = with_gather && c->gather;
+    const bool gath = with_gather && gmode;
     auto one = [&]() {
       launch_fwd(kern, a, precision, A, c->stream);
       if (gath) launch_gather(c->nl, a.fslot, precision != TERS_FP64, a.fown, a.forces, 1, c->stream);
@@ -748,7 +754,7 @@ ters_status md_run_impl(ters_ctx *c, int32_t n, double *x, double *v, double *f,
     if (c->gather) ensure_gather(c->fslot, c->fown, c->nl);  // no allocation inside a capture
     // one step: kick + drift + zero F + rebuild test | conditional rebuild |
     // forces | energy (trace) | kick + clear the flag
-    const bool gather = c->gather != 0;
+    const bool gather = c->gather != 0 && c->kern[precision] != 3;  // thread schedule: atomics
     std::vector<hipEvent_t> ev;
     if (force_us) {
       ev.resize(2 * (size_t)nsteps, nullptr);

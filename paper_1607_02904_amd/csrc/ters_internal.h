@@ -157,6 +157,9 @@ int forward_blocks(int n, int atoms_per_block);
 void launch_forward_wave(const FwdArgs &a, int precision, int atoms_per_wave, hipStream_t s);
 void launch_adjoint_wave(const FwdArgs &a, int precision, int atoms_per_wave, hipStream_t s);
 int wave_blocks(int n, int atoms_per_wave, bool param_grad);
+// thread-per-atom schedule (forward only, FP64 atomic scatter of the forces)
+void launch_forward_thread(const FwdArgs &a, int precision, hipStream_t s);
+int thread_blocks(int n);
 void launch_reduce_partials(const double *partials, int nblocks, int stride, double *energy,
                             double *virial, int accumulate, hipStream_t s,
                             double *trace = nullptr, int32_t *step = nullptr);

@@ -199,7 +199,8 @@ class Tersoff:
 
     def set_schedule(self, kernel=0, atoms=0, kmax=0):
         """kernel 1: workgroup schedule (atoms per workgroup <= 64, k_max);
-        kernel 2: wavefront schedule (atoms per wavefront <= 32); 0: default."""
+        kernel 2: wavefront schedule (atoms per wavefront <= 32); kernel 3:
+        thread per atom (forward only, atomic scatter); 0: default."""
         self._chk(self._L.ters_set_schedule(self._h, int(kernel), int(atoms), int(kmax)))
 
     def schedules(self):

@@ -127,7 +127,7 @@ def test_sic_liquid(orc, sic_model, precision, seed):
 
 
 SCHEDULES = [(1, 8, 0), (1, 13, 0), (1, 32, 1), (1, 64, 2), (1, 40, 0), (1, 1, 0),
-             (2, 1, 0), (2, 7, 0), (2, 16, 0), (2, 32, 0)]
+             (2, 1, 0), (2, 7, 0), (2, 16, 0), (2, 32, 0), (3, 0, 0)]
 
 
 @pytest.mark.parametrize("kernel,atoms,kmax", SCHEDULES)
@@ -145,7 +145,7 @@ def test_schedules_and_kmax_fallback(orc, sic_model, kernel, atoms, kmax, precis
         sic_model.set_schedule(0, 0, 0)
 
 
-@pytest.mark.parametrize("kernel", [1, 2])
+@pytest.mark.parametrize("kernel", [1, 2, 3])
 @pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
 def test_si_512_both_kernels(orc, si_model, kernel, precision):
     x, t, box = inputs.si_small()
@@ -389,3 +389,19 @@ def test_list_is_the_exact_list_up_to_the_rounding_margin(sic_model, skin):
     wide = 2 * len(tree.query_pairs(rlist + 1e-3))
     assert n == len(x) and longest <= cap
     assert exact <= entries <= wide, (exact, entries, wide)
+
+
+def test_thread_schedule_is_forward_only(si_model):
+    """The thread-per-atom schedule has no adjoint: ters_backward refuses it
+    with TERS_ERR_UNSUPPORTED (7)."""
+    from paper_1607_02904_amd.tersoff import TersoffError
+    x, t, box = inputs.si_small()
+    xd, td = _dev(x), _dev(t, torch.int32)
+    si_model.build_nlist(xd, td, box, 0.0)
+    si_model.set_schedule(3, 0, 0)
+    try:
+        with pytest.raises(TersoffError) as ei:
+            si_model.backward(xd, td, box, 1.0, torch.zeros_like(xd), precision=0)
+        assert ei.value.code == 7
+    finally:
+        si_model.set_schedule(0, 0, 0)

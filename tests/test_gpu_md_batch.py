@@ -34,7 +34,7 @@ def _md_gpu(model, x, t, box, nsteps, skin, precision=0, use_graph=True, dt=0.00
     return xd.cpu().numpy(), v.cpu().numpy(), f.cpu().numpy(), tr.cpu().numpy()[:nsteps]
 
 
-@pytest.mark.parametrize("use_graph,kernel", [(True, 1), (False, 1), (True, 2)])
+@pytest.mark.parametrize("use_graph,kernel", [(True, 1), (False, 1), (True, 2), (True, 3)])
 def test_md_matches_oracle_verlet(orc, si_model, use_graph, kernel):
     """30 steps of 1 fs on a 1000-atom Si cell (sigma 0.1, v0 = 0), list with
     skin 0.5 rebuilt on the device when due, against the oracle's velocity
