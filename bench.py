@@ -188,15 +188,18 @@ def main():
     # ablation of the paper's design choices on this hardware: time to forces
     # (force kernel, plus the gather pass in owner-gather mode; back-to-back
     # launches on the start configuration) for the workgroup schedule (Alg. 3
-    # with k_max) and the wavefront schedule (the cyclic-K order of Alg. 2),
-    # owner gather vs FP64 atomic scatter; and whole MD steps with skin 0
-    # (rebuild every step) vs the skin of the headline run
+    # with k_max), the wavefront schedule with 32 atoms per wavefront (the
+    # fused I x J mapping, scheme (b)) and with one (lanes over the j of one
+    # atom, scheme (a)), and thread per atom (scheme (c)); owner gather vs
+    # FP64 atomic scatter; the wavefront schedule without the filter; and
+    # whole MD steps with skin 0 (rebuild every step) vs the headline skin
     ablation = None
     if not args.md_only:
         print("bench: ablation", file=sys.stderr, flush=True)
         fk = {}
         for prec, tag in ((MIXED, "mixed"), (FP64, "fp64")):
-            for kern, atoms, name in ((1, 64, "workgroup_64"), (2, 32, "wavefront_32")):
+            for kern, atoms, name in ((1, 64, "workgroup_64"), (2, 32, "wavefront_32"),
+                                      (2, 1, "wavefront_1_scheme_a")):
                 for gather in (True, False):
                     model.set_schedule(kern, atoms, 0)
                     model.set_force_mode(gather)
