@@ -256,6 +256,25 @@ def main():
                   "fp64_vs_mixed_energy_rel": float(abs(trmx[-1] - tr64[-1]) / abs(tr64[-1]))},
     }
 
+    # ---- a pair potential on the same list (Algorithm 1): Lennard-Jones --------
+    if not args.md_only:
+        print("bench: pair potential", file=sys.stderr, flush=True)
+        model.build_nlist(x0, td, box, skin)
+        pl = {}
+        for prec, tag in ((MIXED, "mixed"), (FP64, "fp64")):
+            model.pair_compute(x0, box, 0.05, 2.1, 3.0, prec)
+            torch.cuda.synchronize()
+            reps = 20
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                model.pair_compute(x0, box, 0.05, 2.1, 3.0, prec)
+            torch.cuda.synchronize()
+            el = (time.perf_counter() - t0) / reps
+            pl[tag] = {"value": n / el, "unit": "atom-steps/s", "ms_per_eval": el * 1e3}
+        out["pair_lj"] = dict(pl, note="truncated Lennard-Jones (eps 0.05 eV, sigma 2.1 A, "
+                                       "r_c 3.0 A) over the Tersoff list of the headline "
+                                       "configuration; one evaluation, outputs allocated per call")
+
     # ---- two-species SiC, 1,000,000 atoms, one mixed evaluation ----------------
     if not args.quick and not args.md_only:
         print("bench: SiC 1M", file=sys.stderr, flush=True)

@@ -144,6 +144,22 @@ ters_status ters_compute_ex(ters_ctx *ctx, int32_t n, const double *x, const int
                             const double *box, int precision, uint32_t flags, double *energy,
                             double *forces, double *virial, double *e_atom, double *param_grad);
 
+/* ---- a pair potential on the same list (the paper, Section II, Algorithm 1)
+ * Truncated Lennard-Jones V(r) = 4 eps ((sigma/r)^12 - (sigma/r)^6) for
+ * r < rc (eV, Angstrom), E = 1/2 sum_i sum_{j in N_i} V(r_ij), over the
+ * context's current list, which must have been built for these n atoms and
+ * this box (ters_build_nlist) with a list radius minus skin of at least rc
+ * (the Tersoff parameters fix that radius).  precision: TERS_FP64 or
+ * TERS_MIXED (FP32 arithmetic, FP64 displacements and accumulators).  flags:
+ * TERS_ENERGY, TERS_FORCES, TERS_VIRIAL, TERS_ACCUMULATE.  Outputs (device,
+ * FP64, caller-owned; NULL allowed when the flag is off): energy[1],
+ * forces[n][3], virial[6] (the convention of ters_compute).  Errors:
+ * TERS_ERR_NO_LIST without a matching list, TERS_ERR_INVALID_ARG for rc
+ * beyond the list, a different box, non-positive sigma or rc. */
+ters_status ters_pair_compute(ters_ctx *ctx, int32_t n, const double *x, const double *box,
+                              double eps, double sigma, double rc, int precision, uint32_t flags,
+                              double *energy, double *forces, double *virial);
+
 /* ---- adjoint (vector-Jacobian product of (E, F) wrt (x, table)) ----------
  * Given cotangents e_bar (host scalar) and f_bar (device [n][3]) of the
  * outputs E and F, writes

@@ -14,7 +14,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OBJDIR = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libtersoff.so")
-SOURCES = ["nlist.hip", "forward.hip", "forward_wave.hip", "forward_thread.hip", "md.hip", "api.cpp"]
+SOURCES = ["nlist.hip", "forward.hip", "forward_wave.hip", "forward_thread.hip", "pair.hip", "md.hip", "api.cpp"]
 ARCH = os.environ.get("TERS_OFFLOAD_ARCH", "gfx950")
 
 # Packed FP32 instructions stay disabled in all device code.

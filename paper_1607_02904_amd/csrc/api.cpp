@@ -560,6 +560,49 @@ ters_status ters_compute_ex(ters_ctx *c, int32_t n, const double *x, const int32
   });
 }
 
+ters_status ters_pair_compute(ters_ctx *c, int32_t n, const double *x, const double *box,
+                              double eps, double sigma, double rc, int precision, uint32_t flags,
+                              double *energy, double *forces, double *virial) {
+  if (!c) return TERS_ERR_INVALID_ARG;
+  return guard(c, [&]() {
+    require(precision == TERS_FP64 || precision == TERS_MIXED, TERS_ERR_INVALID_ARG, "bad precision");
+    require(n >= 0 && (n == 0 || x), TERS_ERR_INVALID_ARG, "bad arguments");
+    require(std::isfinite(eps) && std::isfinite(sigma) && sigma > 0.0 && std::isfinite(rc) && rc > 0.0,
+            TERS_ERR_INVALID_ARG, "bad pair parameters");
+    require(!(flags & TERS_ENERGY) || energy, TERS_ERR_INVALID_ARG, "energy output missing");
+    require(!(flags & TERS_FORCES) || forces || n == 0, TERS_ERR_INVALID_ARG, "forces output missing");
+    require(!(flags & TERS_VIRIAL) || virial, TERS_ERR_INVALID_ARG, "virial output missing");
+    require(c->nl.valid && c->nl.n == n && c->nl.nconf == 1, TERS_ERR_NO_LIST,
+            "no neighbour list for this system (call ters_build_nlist)");
+    for (int k = 0; k < 3; ++k)
+      require(box && box[k] == c->nl.conf_h[0].box[k], TERS_ERR_INVALID_ARG,
+              "box differs from the one the neighbour list was built for");
+    require(rc <= c->nl.rlist - c->nl.skin, TERS_ERR_INVALID_ARG,
+            "pair cutoff beyond the list's cutoff (list radius minus skin)");
+    PairArgs p{};
+    p.n = n;
+    p.x = x;
+    p.conf = c->nl.conf.as<ConfDesc>();
+    p.order = c->nl.order.as<int32_t>();
+    p.count = c->nl.count.as<int32_t>();
+    p.list = c->nl.list.as<int32_t>();
+    p.cap = c->nl.cap;
+    p.eps = eps;
+    p.sigma = sigma;
+    p.rc2 = rc * rc;
+    p.forces = (flags & TERS_FORCES) ? forces : nullptr;
+    p.accumulate = (flags & TERS_ACCUMULATE) ? 1 : 0;
+    const int nb = pair_blocks(n);
+    c->partials.ensure(sizeof(double) * 8 * (size_t)std::max(nb, 1));
+    p.partials = c->partials.as<double>();
+    launch_pair_lj(p, precision, c->stream);
+    if (flags & (TERS_ENERGY | TERS_VIRIAL))
+      launch_reduce_partials(c->partials.as<double>(), nb, 8, (flags & TERS_ENERGY) ? energy : nullptr,
+                             (flags & TERS_VIRIAL) ? virial : nullptr, p.accumulate, c->stream);
+    return TERS_OK;
+  });
+}
+
 ters_status ters_compute(ters_ctx *c, int32_t n, const double *x, const int32_t *type,
                          const double *box, int precision, uint32_t flags, double *energy,
                          double *forces, double *virial, double *e_atom) {

@@ -157,6 +157,21 @@ int forward_blocks(int n, int atoms_per_block);
 void launch_forward_wave(const FwdArgs &a, int precision, int atoms_per_wave, hipStream_t s);
 void launch_adjoint_wave(const FwdArgs &a, int precision, int atoms_per_wave, hipStream_t s);
 int wave_blocks(int n, int atoms_per_wave, bool param_grad);
+// pair potential (truncated Lennard-Jones) over the list: one thread per atom
+// in cell order, own forces only (full list, no atomics)
+struct PairArgs {
+  int32_t n;
+  const double *x;         // [n][3] positions, by atom
+  const ConfDesc *conf;    // the configuration (single system)
+  const int32_t *order, *count, *list;
+  int32_t cap;
+  double eps, sigma, rc2;
+  double *forces;          // [n][3] or null
+  int32_t accumulate;
+  double *partials;        // [blocks][8]: energy, virial
+};
+void launch_pair_lj(const PairArgs &p, int precision, hipStream_t s);
+int pair_blocks(int n);
 // thread-per-atom schedule (forward only, FP64 atomic scatter of the forces)
 void launch_forward_thread(const FwdArgs &a, int precision, hipStream_t s);
 int thread_blocks(int n);

@@ -34,7 +34,7 @@ EXPORTS = ("ters_create", "ters_destroy", "ters_set_stream", "ters_sync", "ters_
            "ters_md_rebuilds",
            "ters_batch_plan", "ters_batch_run", "ters_plan_destroy", "ters_plan_schedule",
            "ters_set_schedule", "ters_get_schedule", "ters_set_force_mode", "ters_set_filter", "ters_autotune",
-           "ters_profile_forward",
+           "ters_profile_forward", "ters_pair_compute",
            "ters_table_sic",
            "ters_table_element", "ters_version")
 
@@ -81,6 +81,7 @@ def load_library(path=LIB_PATH):
         "ters_set_schedule": [P, I32, I32, I32],
         "ters_set_force_mode": [P, I32],
         "ters_set_filter": [P, I32],
+        "ters_pair_compute": [P, I32, P, P, D, D, D, ctypes.c_int, U32, P, P, P],
         "ters_get_schedule": [P, I32, P],
         "ters_autotune": [P, I32, P, P, P, ctypes.c_int, P],
         "ters_profile_forward": [P, I32, P, P, P, ctypes.c_int, I32, I32, P],
@@ -269,6 +270,21 @@ class Tersoff:
                                           _ptr(o.get("energy")), _ptr(o.get("forces")),
                                           _ptr(o.get("virial")), _ptr(o.get("e_atom")),
                                           _ptr(o.get("param_grad"))))
+        return o
+
+    def pair_compute(self, x, box, eps, sigma, rc, precision=FP64):
+        """Truncated Lennard-Jones (the paper's Algorithm 1 over this context's
+        list): energy [1], forces [n,3], virial [6] as float64 device tensors."""
+        self._bind_stream()
+        n = x.shape[0]
+        dev = x.device
+        o = {"energy": torch.empty(1, dtype=torch.float64, device=dev),
+             "forces": torch.empty((n, 3), dtype=torch.float64, device=dev),
+             "virial": torch.empty(6, dtype=torch.float64, device=dev)}
+        b, bp = _hostbuf(box, np.float64)
+        self._chk(self._L.ters_pair_compute(self._h, n, _ptr(x), bp, float(eps), float(sigma),
+                                            float(rc), precision, ENERGY | FORCES | VIRIAL,
+                                            _ptr(o["energy"]), _ptr(o["forces"]), _ptr(o["virial"])))
         return o
 
     def backward(self, x, types, box, e_bar, f_bar, precision=FP64):
