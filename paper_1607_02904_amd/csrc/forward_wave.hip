@@ -5,16 +5,24 @@
 // of an atom occupy consecutive lanes.  The data of neighbour k that the pair
 // (i, j) needs in its K loops is read from lane (i, k) with a cross-lane
 // permute, so per-pair data stays in registers.  The two K loops follow the
-// paper's Algorithm 2: the first accumulates zeta_ij, the pair term gives
-// dV/dzeta, the second evaluates dzeta(i,j,k)/dx and distributes the forces.
+// paper's Algorithms 2 and 3: the first accumulates zeta_ij (and, without the
+// parameter gradient, already evaluates dzeta(i,j,k)/dx_j and /dx_k, keeping
+// the x_k part of the first few k in LDS as Algorithm 3 stores it), the pair
+// term gives dV/dzeta, the second distributes the forces (evaluating the
+// three-body term again for k beyond the stored ones, as Algorithm 2 does).
 // In the second loop the lanes of one atom walk their neighbours cyclically
 // (lane q visits k = q + s mod n in step s), so the force that pair (i, j)
 // produces for atom k in step s is exactly what lane (i, k) pulls from lane
 // (i, k - s) in that step: every pair slot gathers all contributions of atom
 // i's terms to its atom in a fixed order, without atomics in LDS.
 //
+// The wavefront's list rows are contiguous (rows by cell-order position); the
+// filter batches its list, reverse-map and position loads over several
+// windows so that they are in flight together.
+//
 // Scalar types and precision handling are those of the workgroup schedule
-// (FP64, mixed FP32 with FP64 displacements/accumulators, dual numbers).
+// (FP64, mixed FP32 with FP64 displacements/accumulators, dual numbers), plus
+// the all-FP32 single mode (SP).
 #include "ters_device.h"
 #include "ters_internal.h"
 #include "ters_math.h"
