@@ -240,8 +240,9 @@ ters_status ters_plan_schedule(const ters_plan *plan, double *out3);
  * mode always runs kernel 2).  ters_backward refuses kernel 3 with
  * TERS_ERR_UNSUPPORTED. */
 ters_status ters_set_schedule(ters_ctx *ctx, int32_t kernel, int32_t atoms, int32_t kmax);
-/* Current schedule for a precision: out3[0] = kernel (1 or 2), out3[1] =
- * atoms per workgroup/wavefront (0 = default), out3[2] = force mode. */
+/* Current schedule for a precision (TERS_FP64, TERS_MIXED or TERS_SINGLE):
+ * out3[0] = kernel (1, 2 or 3), out3[1] = atoms per workgroup/wavefront
+ * (0 = default), out3[2] = force mode. */
 ters_status ters_get_schedule(const ters_ctx *ctx, int32_t precision, int32_t *out3);
 /* How forces reach their atoms: 1 (default) = owner gather: the force kernel
  * stores, for every list slot (i, j), the force that atom i's terms exert on
