@@ -194,15 +194,21 @@ def test_small_and_degenerate(sic_model, orc):
     _check(gpu_eval(sic_model, x, t, box, 0), ref, 0)
 
 
-def test_empty_system(sic_model):
+@pytest.mark.parametrize("precision", [0, 1, 2], ids=["fp64", "mixed", "single"])
+def test_empty_system(sic_model, precision):
     xd = torch.zeros((0, 3), dtype=torch.float64, device="cuda")
     td = torch.zeros(0, dtype=torch.int32, device="cuda")
     box = np.array([20.0, 20.0, 20.0])
     sic_model.build_nlist(xd, td, box, 0.0)
-    o = sic_model.compute(xd, td, box, 0)
+    o = sic_model.compute(xd, td, box, precision)
     torch.cuda.synchronize()
     assert float(o["energy"].item()) == 0.0
     assert float(o["virial"].abs().sum().item()) == 0.0
+    if precision < 2:
+        p = sic_model.pair_compute(xd, box, 0.05, 2.1, 2.5, precision)
+        torch.cuda.synchronize()
+        assert float(p["energy"].item()) == 0.0
+        assert float(p["virial"].abs().sum().item()) == 0.0
 
 
 def test_accumulate_flag(si_model):
