@@ -330,7 +330,7 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-FTM2V = 9648.533212331  # eV/(Angstrom amu) -> Angstrom/ps^2 (metal units)
+FTM2V = 9648.533215665328  # eV/(Angstrom amu) -> Angstrom/ps^2 (metal units, CODATA 2018)
 
 
 def run_accuracy(args, out, dev):

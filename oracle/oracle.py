@@ -19,8 +19,11 @@ _SRC = os.path.join(_HERE, "tersoff_oracle.c")
 _LIB = os.path.join(_HERE, "_build", "liboracle.so")
 _lib = None
 
-# LAMMPS "metal" units: force/mass in eV/(Angstrom amu) -> Angstrom/ps^2
-FTM2V = 9648.533212331
+# "metal" units: force/mass in eV/(Angstrom amu) -> Angstrom/ps^2, from the
+# SI values of the elementary charge (exact) and the atomic mass constant
+# (CODATA 2018): (1.602176634e-19 J / 1e-10 m) / 1.66053906660e-27 kg in m/s^2,
+# times 1e10 Angstrom/m and 1e-24 s^2/ps^2
+FTM2V = 1.602176634e-19 / 1.66053906660e-27 * 1e-4
 MASS = {"Si": 28.0855, "C": 12.011}
 
 

@@ -10,7 +10,9 @@ namespace ters {
 
 namespace {
 
-constexpr double kFtm2v = 9648.533212331;  // eV/(Angstrom amu) -> Angstrom/ps^2
+// eV/(Angstrom amu) -> Angstrom/ps^2: elementary charge over atomic mass
+// constant (CODATA 2018), 1.602176634e-19 / 1.66053906660e-27 * 1e-4
+constexpr double kFtm2v = 9648.533215665328;
 constexpr int kBS = 256;
 
 // v += dt/2 F/m; x += dt v; F = 0 when the force kernel accumulates into it
