@@ -123,6 +123,14 @@ KParam<B> derive(const double *p) {
   k.lam2_lo = (B)(p[FLAM2] - (double)k.lam2);
   k.R_lo = (B)(R - (double)k.R);
   k.h_lo = (B)(p[FH] - (double)k.h);
+  k.n_lo = (B)(p[FN] - (double)k.n);
+  k.inv2n_lo = (B)(1.0 / (2.0 * p[FN]) - (double)k.inv2n);
+  k.gamma_lo = (B)(p[FGAMMA] - (double)k.gamma);
+  k.c2d2_lo = (B)(p[FC] * p[FC] / (p[FD] * p[FD]) - (double)k.c2d2);
+  k.d2_lo = (B)(p[FD] * p[FD] - (double)k.d2);
+  k.lam3_lo = (B)(p[FLAM3] - (double)k.lam3);
+  k.pi2d_lo = (B)(M_PI / (2.0 * D) - (double)k.pi2d);
+  k.lbeta_lo = (B)(std::log(p[FBETA]) - std::log((double)k.beta));
   return k;
 }
 
@@ -464,7 +472,9 @@ ters_status ters_set_params(ters_ctx *c, int32_t nt, const double *tab, const do
     c->kp32.ensure(sizeof(KParam<float>) * ne);
     c->kp32s.ensure(sizeof(KParam<float>) * ne);
     std::vector<KParam<float>> k32s(k32);  // single precision: no hi/lo residuals
-    for (KParam<float> &k : k32s) k.A_lo = k.lam1_lo = k.B_lo = k.lam2_lo = k.R_lo = k.h_lo = 0.f;
+    for (KParam<float> &k : k32s)
+      k.A_lo = k.lam1_lo = k.B_lo = k.lam2_lo = k.R_lo = k.h_lo = k.n_lo = k.inv2n_lo = k.gamma_lo =
+          k.c2d2_lo = k.d2_lo = k.lam3_lo = k.pi2d_lo = k.lbeta_lo = 0.f;
     c->filt2.ensure(sizeof(double) * nt * nt);
     TERS_HIP_TRY(hipMemcpyAsync(c->kp64.p, k64.data(), sizeof(KParam<double>) * ne, hipMemcpyHostToDevice, c->stream));
     TERS_HIP_TRY(hipMemcpyAsync(c->kp32.p, k32.data(), sizeof(KParam<float>) * ne, hipMemcpyHostToDevice, c->stream));

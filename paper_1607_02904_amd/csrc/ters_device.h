@@ -57,10 +57,15 @@ template <class B> DEV Dual<B> operator*(B b, Dual<B> a) { return {a.v * b, a.d 
 template <class B> DEV Dual<B> &operator+=(Dual<B> &a, Dual<B> b) { a.v += b.v; a.d += b.d; return a; }
 template <class B> DEV Dual<B> &operator-=(Dual<B> &a, Dual<B> b) { a.v -= b.v; a.d -= b.d; return a; }
 
-// reciprocal: FP64 uses IEEE division; FP32 uses the hardware reciprocal
-// (1 ulp), which the mixed path's error budget allows.
+// reciprocal: FP64 uses IEEE division; FP32 refines the hardware reciprocal
+// (1 ulp) by one Newton step, so that its error is a rounding error (below
+// half an ulp but for a tiny fraction) with no systematic sign: the mixed
+// path's energy sums millions of such values.  a must be finite and non-zero.
 DEV double rcp(double a) { return 1.0 / a; }
-DEV float rcp(float a) { return __builtin_amdgcn_rcpf(a); }
+DEV float rcp(float a) {
+  const float r = __builtin_amdgcn_rcpf(a);
+  return fmaf(r, fmaf(-a, r, 1.0f), r);
+}
 template <class B> DEV Dual<B> rcp(Dual<B> a) { B r = rcp(a.v); return {r, -a.d * r * r}; }
 template <class B> DEV Dual<B> operator/(Dual<B> a, Dual<B> b) { return a * rcp(b); }
 template <class B> DEV Dual<B> operator/(Dual<B> a, B b) { return {a.v / b, a.d / b}; }
@@ -104,6 +109,30 @@ template <class B> DEV Dual<double> widen(Dual<B> a) { return {(double)a.v, (dou
 // ---------------------------------------------------------------------------
 // kernel parameter record (derived once per table entry on the host)
 // ---------------------------------------------------------------------------
+// Compensation of FP32-rounded constants.  A constant c kept as c_hi + c_lo
+// (c_lo what rounding to FP32 dropped) enters a product as one FMA,
+// c_hi * x + (c_lo * x), so that the correction is added to the exact product
+// and survives the single rounding; added after the rounding of c_hi * x it
+// would be lost whenever it is below half an ulp, always in the same
+// direction, and every pair of a species pair would carry the same relative
+// bias of up to 6e-8.  The FP64 path has no residuals (c_lo = 0) and takes
+// the plain product.
+DEV double fma_lo(double a, double x, double) { return a * x; }
+DEV float fma_lo(float a, float x, float c) { return fmaf(a, x, c); }
+template <class B> DEV Dual<B> fma_lo(B a, Dual<B> x, Dual<B> c) {
+  return {fma_lo(a, x.v, c.v), a * x.d + c.d};
+}
+template <class T, class B> DEV T mul_lo(B hi, B lo, T x) { return fma_lo(hi, x, lo * x); }
+// (x - lo)^2 for x = v - c_hi and a constant c = c_hi + c_lo: x^2 - 2 lo x in
+// one FMA (FP64: lo = 0)
+DEV double sq_lo(double x, double) { return x * x; }
+DEV float sq_lo(float x, float lo) { return fmaf(x, x, x * (-2.0f * lo)); }
+template <class B> DEV Dual<B> sq_lo(Dual<B> x, B lo) { return {sq_lo(x.v, lo), B(2) * x.v * x.d}; }
+// x + lo for a residual lo (FP64: lo = 0, nothing added)
+DEV double add_lo(double x, double) { return x; }
+DEV float add_lo(float x, float lo) { return x + lo; }
+template <class B> DEV Dual<B> add_lo(Dual<B> x, B lo) { return {add_lo(x.v, lo), x.d}; }
+
 template <class B>
 struct KParam {
   // cutoff of the distance this entry is used for: R +- D, pi/(2D), pi/(4D)
@@ -114,6 +143,9 @@ struct KParam {
   B A_lo, lam1_lo, B_lo, lam2_lo, R_lo, h_lo;
   // three-body part: gamma, c^2, d^2, h, gamma c^2, c^2/d^2, lambda3, c, d
   B gamma, c2, d2, h, gc2, c2d2, lam3, c, d;
+  // further residuals of FP32 rounding (0 for FP64 and in the single mode):
+  // n, 1/(2n), gamma, c^2/d^2, d^2, lambda3, pi/(2D), and ln(beta) - ln(beta_hi)
+  B n_lo, inv2n_lo, gamma_lo, c2d2_lo, d2_lo, lam3_lo, pi2d_lo, lbeta_lo;
   int32_t m3;   // 1 when m == 3, 0 when m == 1
   int32_t pad;
 };
@@ -131,7 +163,7 @@ DEV float scaled_exp(float c, float c_lo, float lam, float lam_lo, float r, floa
   float p = lam * r;
   float corr = fmaf(lam, r, -p) + (lam_lo * r + lam * r_lo);
   float e = expf(-p);
-  return e * (c + (c_lo - c * corr));
+  return fmaf(e, c, e * (c_lo - c * corr));  // e c exact, the correction added before rounding
 }
 template <class B>
 DEV Dual<B> scaled_exp(B c, B c_lo, B lam, B lam_lo, Dual<B> r, B r_lo) {

@@ -23,7 +23,7 @@ DEV void fcut(const KParam<B> &p, T r, T &fc, T &dfc) {
     fc = T(B(0));
     dfc = T(B(0));
   } else {
-    T arg = ((r - p.R) - p.R_lo) * p.pi2d;
+    T arg = mul_lo(p.pi2d, p.pi2d_lo, (r - p.R) - p.R_lo);
     fc = B(0.5) - B(0.5) * t_sin(arg);
     dfc = -p.pi4d * t_cos(arg);
   }
@@ -42,7 +42,7 @@ DEV void fcut64(const KParam<B> &p, T r, double r64, T &fc, T &dfc) {
     dfc = T(B(0));
   } else {
     T arg = r * p.pi2d;  // tangent part
-    set_val(arg, (r64 - (double)p.R - (double)p.R_lo) * (double)p.pi2d);
+    set_val(arg, (r64 - (double)p.R - (double)p.R_lo) * ((double)p.pi2d + (double)p.pi2d_lo));
     fc = B(0.5) - B(0.5) * t_sin(arg);
     dfc = -p.pi4d * t_cos(arg);
   }
@@ -60,8 +60,9 @@ DEV void bond(const KParam<B> &p, T z, T &b, T &db, T &dbeta, T &dn) {
     dn = T(B(0));
     return;
   }
+  // s = n ln(beta zeta), with the residuals of n and beta entering in one FMA
   T lz = t_log(p.beta * z);
-  T s = p.n * lz;
+  T s = fma_lo(p.n, lz, p.n * p.lbeta_lo + p.n_lo * lz);
   T l1p, w;  // ln(1 + y), y / (1 + y)
   if (val(s) > B(0)) {
     T em = t_exp(-s);
@@ -72,12 +73,12 @@ DEV void bond(const KParam<B> &p, T z, T &b, T &db, T &dbeta, T &dn) {
     l1p = t_log1p(ep);
     w = ep * rcp(B(1) + ep);
   }
-  b = t_exp(-l1p * p.inv2n);
+  b = t_exp(-mul_lo(p.inv2n, p.inv2n_lo, l1p));
   T bw = b * w;
   db = -B(0.5) * bw * rcp(z);
   if (PG) {
     dbeta = -B(0.5) * bw * rcp(T(p.beta));
-    dn = b * p.inv2n * (l1p * rcp(T(p.n)) - w * lz);
+    dn = b * p.inv2n * (l1p * rcp(T(p.n)) - w * add_lo(lz, p.lbeta_lo));
   } else {
     dbeta = T(B(0));
     dn = T(B(0));
@@ -88,11 +89,11 @@ DEV void bond(const KParam<B> &p, T z, T &b, T &db, T &dbeta, T &dn) {
 template <class T, class B>
 DEV T zeta_value(const KParam<B> &p, T rij, const T *u, T rik, const T *v, T fck) {
   T cs = u[0] * v[0] + u[1] * v[1] + u[2] * v[2];
-  T t = (cs - p.h) - p.h_lo;
-  T t2 = t * t;
-  T g = p.gamma * (B(1) + p.c2d2 * t2 * rcp(p.d2 + t2));
+  T t2 = sq_lo(cs - p.h, p.h_lo);  // (cos - h)^2
+  T q = t2 * rcp(add_lo(t2, p.d2_lo) + p.d2);
+  T g = mul_lo(p.gamma, p.gamma_lo, B(1) + mul_lo(p.c2d2, p.c2d2_lo, q));
   if (p.lam3 == B(0)) return fck * g;
-  T uu = p.lam3 * (rij - rik);
+  T uu = mul_lo(p.lam3, p.lam3_lo, rij - rik);
   T arg = p.m3 ? uu * uu * uu : uu;
   return fck * g * t_exp(arg);
 }
@@ -104,15 +105,16 @@ template <class T, class B, bool PG>
 DEV T zeta_term(const KParam<B> &p, T rij, T rinv_ij, const T *u, T rik, T rinv_ik, const T *v,
                 T fck, T dfck, T *gj, T *gk, T *dpar) {
   T cs = u[0] * v[0] + u[1] * v[1] + u[2] * v[2];
-  T t = (cs - p.h) - p.h_lo;
-  T t2 = t * t;
-  T iden = rcp(p.d2 + t2);
-  T gn = B(1) + p.c2d2 * t2 * iden;  // g / gamma
-  T g = p.gamma * gn;
+  T x = cs - p.h;
+  T t = x - p.h_lo;     // cos - h
+  T t2 = sq_lo(x, p.h_lo);
+  T iden = rcp(add_lo(t2, p.d2_lo) + p.d2);
+  T gn = B(1) + mul_lo(p.c2d2, p.c2d2_lo, t2 * iden);  // g / gamma
+  T g = mul_lo(p.gamma, p.gamma_lo, gn);
   T dg = B(2) * p.gc2 * t * iden * iden;
   T e, de;  // exponential factor and its derivative wrt dr = r_ij - r_ik
   T dr = rij - rik;
-  T uu = p.lam3 * dr;
+  T uu = mul_lo(p.lam3, p.lam3_lo, dr);
   T arg;
   if (p.lam3 == B(0)) {  // exponential factor is exactly 1 (e.g. the Si/C sets)
     e = T(B(1));
