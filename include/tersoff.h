@@ -232,9 +232,10 @@ ters_status ters_plan_schedule(const ters_plan *plan, double *out3);
  * Algorithm 2 with dzeta/dx_k of the first four k kept), 3 = thread per atom
  * (the paper's mapping scheme (c), Section IV-B: one thread walks its atom's
  * j and k; forward only, forces scattered with FP64 atomics whatever the
- * force mode; kept as a baseline), 0 = default (1).  atoms: atoms per
+ * force mode; kept as a baseline), 0 = default (2).  atoms: atoms per
  * workgroup (kernel 1, <= 64) or per wavefront (kernel 2, <= 32), ignored by
- * kernel 3; 0 = default.  kmax (kernel 1): stored dzeta/dx_k per pair before
+ * kernel 3; 0 = default (kernel 1: 64; kernel 2: 32 with one species, 24
+ * with several).  kmax (kernel 1): stored dzeta/dx_k per pair before
  * falling back to recomputing them (the paper's k_max, Section IV-A); 0 =
  * store all that fit.  Applies to the FP64 and mixed precisions (the single
  * mode always runs kernel 2).  ters_backward refuses kernel 3 with
@@ -242,7 +243,7 @@ ters_status ters_plan_schedule(const ters_plan *plan, double *out3);
 ters_status ters_set_schedule(ters_ctx *ctx, int32_t kernel, int32_t atoms, int32_t kmax);
 /* Current schedule for a precision (TERS_FP64, TERS_MIXED or TERS_SINGLE):
  * out3[0] = kernel (1, 2 or 3), out3[1] = atoms per workgroup/wavefront
- * (0 = default), out3[2] = force mode. */
+ * (the default resolved), out3[2] = force mode. */
 ters_status ters_get_schedule(const ters_ctx *ctx, int32_t precision, int32_t *out3);
 /* How forces reach their atoms: 1 (default) = owner gather: the force kernel
  * stores, for every list slot (i, j), the force that atom i's terms exert on

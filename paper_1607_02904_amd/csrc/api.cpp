@@ -32,7 +32,7 @@ struct ters_ctx {
   NList nl;
   DevBuf partials, errw, flag, rebuilds, step, escratch;
   int A[3] = {0, 0, 0};     // atoms per workgroup / wavefront per precision (0 = default)
-  int kern[3] = {1, 1, 2};  // force kernel per precision: 1 workgroup, 2 wavefront schedule
+  int kern[3] = {2, 2, 2};  // force kernel per precision: 1 workgroup, 2 wavefront schedule
                             // (the single-precision mode has the wavefront schedule only)
   int kmax = 1 << 20;
   int filter = 1;        // 0: the wavefront schedule skips the filter (ablation)
@@ -47,7 +47,7 @@ struct ters_ctx {
 
 struct ters_plan {
   ters_ctx *ctx = nullptr;
-  int nconf = 0, N = 0, precision = 0;
+  int nconf = 0, N = 0, precision = 0, ntypes = 0;
   uint32_t flags = 0;
   std::vector<int32_t> natoms, off;
   NList nl;
@@ -148,6 +148,7 @@ void check_err_word(uint32_t e) {
   if (e & kErrNlistOverflow) fail(TERS_ERR_NLIST_OVERFLOW, "neighbour list capacity exceeded");
   if (e & kErrTooManyInCutoff)
     fail(TERS_ERR_NLIST_OVERFLOW, "an atom has more than 32 neighbours inside the cutoff");
+  if (e & kErrBadType) fail(TERS_ERR_INVALID_ARG, "a species lies outside [0, ntypes)");
 }
 
 int next_pow2(int v) {
@@ -215,15 +216,19 @@ void nl_setup(NList &nl, int nconf, const int32_t *natoms, const double *boxes, 
   nl.rev.ensure(sizeof(int32_t) * nn * nl.cap);
 }
 
-// Build with capacity growth (synchronises).
-void nl_build_sync(ters_ctx *c, NList &nl, const double *x, DevBuf &errw) {
+// Build with capacity growth (synchronises); species checked against [0, ntypes).
+void nl_build_sync(ters_ctx *c, NList &nl, const double *x, const int32_t *type, DevBuf &errw) {
   for (int attempt = 0; attempt < 6; ++attempt) {
     launch_fill_i32(errw.as<int32_t>(), 0, 1, nullptr, c->stream);
-    nlist_build(nl, x, nullptr, errw.as<uint32_t>(), c->stream);
+    nlist_build(nl, x, type, c->ntypes, nullptr, errw.as<uint32_t>(), c->stream);
     int32_t mx = 0;
     TERS_HIP_TRY(hipMemcpyAsync(&mx, nl.maxcount.p, sizeof(mx), hipMemcpyDeviceToHost, c->stream));
     uint32_t e = read_err(c, errw);
     if (e & kErrNotFinite) fail(TERS_ERR_NOT_FINITE, "non-finite position");
+    if (e & kErrBadType) {
+      launch_fill_i32(errw.as<int32_t>(), 0, 1, nullptr, c->stream);
+      fail(TERS_ERR_INVALID_ARG, "a species lies outside [0, ntypes)");
+    }
     if ((e & kErrListAsymmetric) && mx <= nl.cap) fail(TERS_ERR_HIP, "neighbour list not symmetric");
     if (mx <= nl.cap) {
       nl.valid = true;
@@ -315,8 +320,21 @@ void launch_adj(int kern, const FwdArgs &a, int precision, int A, hipStream_t s)
   else launch_adjoint(a, precision, 0, s);
 }
 
+// Atoms per workgroup (kernel 1) or wavefront (kernel 2) of a context's
+// schedule, with the default resolved: the wavefront schedule takes 32 atoms
+// per wavefront with one species and 24 with several (what the autotuner
+// picks on the benchmark workloads), the workgroup schedule 64.
+int default_atoms(int kern, int ntypes) {
+  if (kern == 2) return ntypes <= 1 ? 32 : 24;
+  return kern == 1 ? 64 : 0;
+}
+int sched_A(const ters_ctx *c, int precision) {
+  const int k = precision == TERS_SINGLE ? 2 : c->kern[precision];
+  return c->A[precision] > 0 ? c->A[precision] : default_atoms(k, c->ntypes);
+}
+
 int ctx_blocks(const ters_ctx *c, int precision, int n, bool pg = false) {
-  return kernel_blocks(c->kern[precision], n, c->A[precision], pg);
+  return kernel_blocks(c->kern[precision], n, sched_A(c, precision), pg);
 }
 
 // owner-gather buffers for n atoms with the list's capacity
@@ -344,7 +362,7 @@ int run_forward(ters_ctx *c, const FwdArgs &a0, int precision, hipStream_t s,
   } else if (a.forces && !(a.flags & TERS_ACCUMULATE)) {
     launch_fill_f64(a.forces, 0.0, 3 * (int64_t)a.n, s);
   }
-  launch_fwd(c->kern[precision], a, precision, c->A[precision], s);
+  launch_fwd(c->kern[precision], a, precision, sched_A(c, precision), s);
   if (gather && do_gather)
     launch_gather(c->nl, a.fslot, precision != TERS_FP64, a.fown, a.forces,
                   (a.flags & TERS_ACCUMULATE) ? 1 : 0, s);
@@ -418,7 +436,18 @@ ters_status ters_set_stream(ters_ctx *c, void *stream) {
 ters_status ters_sync(ters_ctx *c) {
   if (!c) return TERS_ERR_INVALID_ARG;
   return guard(c, [&]() {
-    check_err_word(read_err(c, c->errw));
+    // the context's word (single-system calls, molecular dynamics) and those
+    // of its batch plans; each is cleared once read
+    uint32_t e = read_err(c, c->errw);
+    for (ters_plan *p : c->plans)
+      if (p->errw.p) e |= read_err(c, p->errw);
+    if (e) {
+      launch_fill_i32(c->errw.as<int32_t>(), 0, 1, nullptr, c->stream);
+      for (ters_plan *p : c->plans)
+        if (p->errw.p) launch_fill_i32(p->errw.as<int32_t>(), 0, 1, nullptr, c->stream);
+      sync(c);
+    }
+    check_err_word(e);
     return TERS_OK;
   });
 }
@@ -486,7 +515,9 @@ ters_status ters_set_params(ters_ctx *c, int32_t nt, const double *tab, const do
       c->has_mass = true;
     }
     sync(c);
-    if (nt != c->ntypes || rc != c->rc_max) c->nl.valid = false;
+    // the list stays usable while every cutoff still fits inside its radius
+    // (less the skin); a change of the number of species invalidates it
+    if (nt != c->ntypes || rc > c->nl.rlist - c->nl.skin) c->nl.valid = false;
     c->ntypes = nt;
     c->rc_max = rc;
     c->cut_consistent = consistent;
@@ -503,7 +534,7 @@ ters_status ters_build_nlist(ters_ctx *c, int32_t n, const double *x, const int3
     require(std::isfinite(skin) && skin >= 0.0, TERS_ERR_INVALID_ARG, "skin must be >= 0");
     c->nl.valid = false;
     nl_setup(c->nl, 1, &n, box, c->rc_max + skin, skin, nullptr, c->stream);
-    nl_build_sync(c, c->nl, x, c->errw);
+    nl_build_sync(c, c->nl, x, type, c->errw);
     return TERS_OK;
   });
 }
@@ -649,7 +680,7 @@ ters_status ters_backward(ters_ctx *c, int32_t n, const double *x, const int32_t
     } else {
       launch_fill_f64(x_grad, 0.0, 3 * (int64_t)n, c->stream);
     }
-    launch_adj(c->kern[precision], a, precision, c->A[precision], c->stream);
+    launch_adj(c->kern[precision], a, precision, sched_A(c, precision), c->stream);
     if (c->gather)
       launch_gather(c->nl, a.fslot, precision == TERS_MIXED, a.fown, x_grad, 0, c->stream);
     return TERS_OK;
@@ -660,7 +691,7 @@ ters_status ters_set_schedule(ters_ctx *c, int32_t kernel, int32_t atoms, int32_
   if (!c) return TERS_ERR_INVALID_ARG;
   if (kernel < 0 || kernel > 3 || kmax < 0) return TERS_ERR_INVALID_ARG;
   if (atoms < 0 || atoms > (kernel == 2 ? 32 : 64)) return TERS_ERR_INVALID_ARG;
-  const int k = kernel == 0 ? 1 : kernel;
+  const int k = kernel == 0 ? 2 : kernel;
   c->kern[0] = c->kern[1] = k;
   c->A[0] = c->A[1] = atoms;
   if (k == 2) c->A[TERS_SINGLE] = atoms;  // the single mode runs the wavefront schedule
@@ -671,7 +702,7 @@ ters_status ters_set_schedule(ters_ctx *c, int32_t kernel, int32_t atoms, int32_
 ters_status ters_get_schedule(const ters_ctx *c, int32_t precision, int32_t *out3) {
   if (!c || !out3 || precision < TERS_FP64 || precision > TERS_SINGLE) return TERS_ERR_INVALID_ARG;
   out3[0] = c->kern[precision];
-  out3[1] = c->A[precision];
+  out3[1] = sched_A(c, precision);
   out3[2] = c->gather;
   return TERS_OK;
 }
@@ -763,7 +794,7 @@ ters_status ters_profile_forward(ters_ctx *c, int32_t n, const double *x, const 
     hipEvent_t e0, e1;
     TERS_HIP_TRY(hipEventCreate(&e0));
     TERS_HIP_TRY(hipEventCreate(&e1));
-    const int kern = c->kern[precision], A = c->A[precision];
+    const int kern = c->kern[precision], A = sched_A(c, precision);
     const bool gath = with_gather && gmode;
     auto one = [&]() {
       launch_fwd(kern, a, precision, A, c->stream);
@@ -822,8 +853,8 @@ ters_status md_run_impl(ters_ctx *c, int32_t n, double *x, double *v, double *f,
     auto step = [&](hipStream_t s, int k, bool last) {
       int32_t *flag = c->flag.as<int32_t>();
       if (!gather)
-        launch_vv_first(n, x, v, f, type, c->mass.as<double>(), dt, c->nl, flag, 1, s);
-      nlist_build(c->nl, x, flag, c->errw.as<uint32_t>(), s, c->rebuilds.as<int64_t>());
+        launch_vv_first(n, x, v, f, type, c->mass.as<double>(), c->ntypes, dt, c->nl, flag, 1, s);
+      nlist_build(c->nl, x, type, c->ntypes, flag, c->errw.as<uint32_t>(), s, c->rebuilds.as<int64_t>());
       FwdArgs a = base_args(c, c->nl, precision, n, x, type);
       a.flags = TERS_FORCES | TERS_ENERGY | TERS_ACCUMULATE;  // scatter: F was zeroed by the kick
       a.forces = f;
@@ -833,21 +864,21 @@ ters_status md_run_impl(ters_ctx *c, int32_t n, double *x, double *v, double *f,
       if (force_us) TERS_HIP_TRY(hipEventRecord(ev[2 * k + 1], s));
       if (gather) {
         launch_vv_gather_kick_drift(c->nl, x, v, f, c->fslot.p, precision != TERS_FP64,
-                                    c->fown.as<double>(), type, c->mass.as<double>(), dt, flag,
+                                    c->fown.as<double>(), type, c->mass.as<double>(), c->ntypes, dt, flag,
                                     last ? 0 : 1, c->partials.as<double>(), nb,
                                     c->escratch.as<double>(), trace, c->step.as<int32_t>(), s);
       } else {
         if (trace)
           launch_reduce_partials(c->partials.as<double>(), nb, 8, c->escratch.as<double>(),
                                  nullptr, 0, s, trace, c->step.as<int32_t>());
-        launch_vv_second(n, v, f, type, c->mass.as<double>(), dt, flag, s);
+        launch_vv_second(n, v, f, type, c->mass.as<double>(), c->ntypes, dt, flag, s);
       }
     };
     launch_fill_i32(c->step.as<int32_t>(), 0, 1, nullptr, c->stream);
     launch_fill_i32(c->flag.as<int32_t>(), 0, 1, nullptr, c->stream);
     if (gather && nsteps > 0)
-      launch_vv_first(n, x, v, f, type, c->mass.as<double>(), dt, c->nl, c->flag.as<int32_t>(), 0,
-                      c->stream);
+      launch_vv_first(n, x, v, f, type, c->mass.as<double>(), c->ntypes, dt, c->nl,
+                      c->flag.as<int32_t>(), 0, c->stream);
     if (!use_graph || force_us) {
       for (int s = 0; s < nsteps; ++s) step(c->stream, s, s == nsteps - 1);
       if (force_us) {
@@ -865,7 +896,7 @@ ters_status md_run_impl(ters_ctx *c, int32_t n, double *x, double *v, double *f,
       std::vector<const void *> key = graph_key(c, c->nl);
       const void *extra[] = {x, v, f, type, trace, bits(dt), (const void *)(intptr_t)n,
                              (const void *)(intptr_t)precision, c->mass.p,
-                             (const void *)(intptr_t)c->A[precision],
+                             (const void *)(intptr_t)sched_A(c, precision),
                              (const void *)(intptr_t)c->kern[precision]};
       key.insert(key.end(), std::begin(extra), std::end(extra));
       if (!c->md_exec || key != c->md_key) {
@@ -937,7 +968,7 @@ void batch_enqueue(ters_plan *p, const double *x, const int32_t *type, double *e
                    hipStream_t s) {
   ters_ctx *c = p->ctx;
   NList &nl = p->nl;
-  nlist_build(nl, x, nullptr, p->errw.as<uint32_t>(), s);
+  nlist_build(nl, x, type, c->ntypes, nullptr, p->errw.as<uint32_t>(), s);
   FwdArgs a = base_args(c, nl, p->precision, p->N, x, type, true);
   a.flags = (f ? TERS_FORCES : 0u) | TERS_ENERGY | TERS_VIRIAL;
   a.forces = f;
@@ -991,6 +1022,7 @@ ters_status ters_batch_plan(ters_ctx *c, int32_t nconf, const int32_t *natoms,
     require(precision != TERS_SINGLE, TERS_ERR_UNSUPPORTED, "the single-precision mode is forward only");
     p->ctx = c;
     p->nconf = nconf;
+    p->ntypes = c->ntypes;
     p->precision = precision;
     p->flags = flags;
     p->natoms.assign(natoms, natoms + nconf);
@@ -1042,9 +1074,12 @@ ters_status ters_batch_run(ters_plan *p, const double *x, const int32_t *type, d
     require(x && type, TERS_ERR_INVALID_ARG, "x and type required");
     require(!f_bar || (e_bar && xg && pg), TERS_ERR_INVALID_ARG, "adjoint needs e_bar, x_grad, param_grad");
     NList &nl = p->nl;
+    require(c->ntypes == p->ntypes && c->rc_max <= nl.rlist, TERS_ERR_INVALID_ARG,
+            "the parameters changed the number of species or a cutoff beyond the plan's list "
+            "radius (create a new plan)");
     if (!p->tuned) {
       // size the list, then pick the schedule on this data (eager, synchronising)
-      nl_build_sync(c, nl, x, p->errw);
+      nl_build_sync(c, nl, x, type, p->errw);
       p->gather = c->gather;
       if (p->gather) ensure_gather(p->fslot, p->fown, nl);
       DevBuf ft;

@@ -31,6 +31,8 @@
 #include "ters_internal.h"
 #include "ters_math.h"
 
+#include <type_traits>
+
 namespace ters {
 
 namespace {
@@ -118,7 +120,7 @@ __global__ __launch_bounds__(BS) void k_force(FwdArgs a, int A) {
     const int ia = a.order[i];
     s_atom[at] = i;
     s_aid[at] = ia;
-    s_type[at] = NT1 ? 0 : a.type[ia];
+    s_type[at] = NT1 ? 0 : species(a.type, ia, a.ntypes);
     s_lcnt[at] = min(a.count[i], a.cap);
     s_conf[at] = a.conf_of ? a.conf_of[ia] : 0;
   }
@@ -147,7 +149,7 @@ __global__ __launch_bounds__(BS) void k_force(FwdArgs a, int A) {
         dy -= cf.box[1] * rint(dy * cf.inv_box[1]);
         dz -= cf.box[2] * rint(dz * cf.inv_box[2]);
         double r2 = dx * dx + dy * dy + dz * dz;
-        int tj = NT1 ? 0 : a.type[j];
+        int tj = NT1 ? 0 : species(a.type, j, a.ntypes);
         pass = r2 < filt2[NT1 ? 0 : s_type[at] * nt + tj];
       }
       uint64_t m = __ballot(pass);
@@ -258,7 +260,7 @@ __global__ __launch_bounds__(BS) void k_force(FwdArgs a, int A) {
       int i = s_aid[at];
       int j = s_stage[at * kNMax + q];
       int ti = s_type[at];
-      int tj = NT1 ? 0 : a.type[j];
+      int tj = NT1 ? 0 : species(a.type, j, a.ntypes);
       const ConfDesc &cf = a.conf[s_conf[at]];
       double d[3];
 #pragma unroll
@@ -336,15 +338,28 @@ __global__ __launch_bounds__(BS) void k_force(FwdArgs a, int A) {
         }
         // pair term V(i, j, zeta_ij)
         const B rlo = s_rlo[p];
-        const T fr = scaled_exp(pp.A, pp.A_lo, pp.lam1, pp.lam1_lo, rij, rlo);
-        const T fa = -scaled_exp(pp.Bc, pp.B_lo, pp.lam2, pp.lam2_lo, rij, rlo);
+        T fr, fa;
+        AT fre, fae;  // the same for the energy
+        if constexpr (std::is_same<T, float>::value) {  // mixed: FP64 exponentials
+          const double e1 = exp64(pp.A, pp.A_lo, pp.lam1, pp.lam1_lo, rij, rlo);
+          const double e2 = exp64(pp.Bc, pp.B_lo, pp.lam2, pp.lam2_lo, rij, rlo);
+          fr = (float)e1;
+          fa = -(float)e2;
+          fre = e1;
+          fae = -e2;
+        } else {
+          fr = scaled_exp(pp.A, pp.A_lo, pp.lam1, pp.lam1_lo, rij, rlo);
+          fa = -scaled_exp(pp.Bc, pp.B_lo, pp.lam2, pp.lam2_lo, rij, rlo);
+          fre = widen(fr);
+          fae = widen(fa);
+        }
         T b, db, dbb, dbn;
         bond<T, B, PG>(pp, zeta, b, db, dbb, dbn);
         const T fcij = s_fc[p], dfcij = s_dfc[p];
         const T vr = fr + b * fa;
         // the energy itself is assembled in FP64 from the factors (the FP32
         // path's large repulsive and attractive parts cancel at close contacts)
-        const AT V = widen(fcij) * (widen(fr) + widen(b) * widen(fa));
+        const AT V = widen(fcij) * (fre + widen(b) * fae);
         const T dVdr = dfcij * vr + fcij * (-pp.lam1 * fr - pp.lam2 * b * fa);
         dzeta = B(0.5) * fcij * fa * db;
         const T hp = B(0.5) * dVdr;

@@ -16,6 +16,8 @@
 #include "ters_internal.h"
 #include "ters_math.h"
 
+#include <type_traits>
+
 namespace ters {
 
 namespace {
@@ -42,7 +44,7 @@ __global__ __launch_bounds__(kTBS) void k_force_thread(FwdArgs a) {
   const int t = blockIdx.x * kTBS + threadIdx.x;
   if (t < a.n) {
     const int i = a.order[t];
-    const int ti = NT1 ? 0 : a.type[i];
+    const int ti = NT1 ? 0 : species(a.type, i, a.ntypes);
     const int cf = a.conf_of ? a.conf_of[i] : 0;
     const ConfDesc &c = a.conf[cf];
     const int cnt = min(a.count[t], a.cap);
@@ -85,7 +87,7 @@ __global__ __launch_bounds__(kTBS) void k_force_thread(FwdArgs a) {
     double ei = 0.0;
     for (int s = 0; s < cnt; ++s) {
       const int j = row[s];
-      const int tj = NT1 ? 0 : a.type[j];
+      const int tj = NT1 ? 0 : species(a.type, j, a.ntypes);
       const KP &pp = param(ti, tj, tj);
       Nb nj;
       if (!neighbour(j, tj, pp, nj)) continue;
@@ -97,7 +99,7 @@ __global__ __launch_bounds__(kTBS) void k_force_thread(FwdArgs a) {
       for (int s2 = 0; s2 < cnt; ++s2) {
         if (s2 == s) continue;
         const int k = row[s2];
-        const int tk = NT1 ? 0 : a.type[k];
+        const int tk = NT1 ? 0 : species(a.type, k, a.ntypes);
         Nb nk;
         if (!neighbour(k, tk, param(ti, tk, tk), nk)) continue;
         const KP &pk = param(ti, tj, tk);
@@ -109,12 +111,25 @@ __global__ __launch_bounds__(kTBS) void k_force_thread(FwdArgs a) {
       }
 
       // pair term
-      const T fr = scaled_exp(pp.A, pp.A_lo, pp.lam1, pp.lam1_lo, nj.r, nj.rlo);
-      const T fa = -scaled_exp(pp.Bc, pp.B_lo, pp.lam2, pp.lam2_lo, nj.r, nj.rlo);
+      T fr, fa;
+      AT fre, fae;  // the same for the energy
+      if constexpr (std::is_same<T, float>::value) {  // mixed: FP64 exponentials
+        const double e1 = exp64(pp.A, pp.A_lo, pp.lam1, pp.lam1_lo, nj.r, nj.rlo);
+        const double e2 = exp64(pp.Bc, pp.B_lo, pp.lam2, pp.lam2_lo, nj.r, nj.rlo);
+        fr = (float)e1;
+        fa = -(float)e2;
+        fre = e1;
+        fae = -e2;
+      } else {
+        fr = scaled_exp(pp.A, pp.A_lo, pp.lam1, pp.lam1_lo, nj.r, nj.rlo);
+        fa = -scaled_exp(pp.Bc, pp.B_lo, pp.lam2, pp.lam2_lo, nj.r, nj.rlo);
+        fre = widen(fr);
+        fae = widen(fa);
+      }
       T b, db, dbb, dbn;
       bond<T, B, false>(pp, zeta, b, db, dbb, dbn);
       const T vr = fr + b * fa;
-      const AT V = widen(nj.fc) * (widen(fr) + widen(b) * widen(fa));
+      const AT V = widen(nj.fc) * (fre + widen(b) * fae);
       const T dVdr = nj.dfc * vr + nj.fc * (-pp.lam1 * fr - pp.lam2 * b * fa);
       const T dzeta = B(0.5) * nj.fc * fa * db;
       const T hp = B(0.5) * dVdr;
@@ -127,7 +142,7 @@ __global__ __launch_bounds__(kTBS) void k_force_thread(FwdArgs a) {
       for (int s2 = 0; s2 < cnt && val(dzeta) != B(0); ++s2) {
         if (s2 == s) continue;
         const int k = row[s2];
-        const int tk = NT1 ? 0 : a.type[k];
+        const int tk = NT1 ? 0 : species(a.type, k, a.ntypes);
         Nb nk;
         if (!neighbour(k, tk, param(ti, tk, tk), nk)) continue;
         const KP &pk = param(ti, tj, tk);

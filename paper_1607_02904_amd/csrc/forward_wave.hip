@@ -174,7 +174,7 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEu<T, PG>::value))) void k_force_wave
   if (lane < na) {
     my_i = (int)(first + lane);  // cell-order position: list row
     my_a = a.order[my_i];        // the atom: per-atom arrays
-    my_t = NT1 ? 0 : a.type[my_a];
+    my_t = NT1 ? 0 : species(a.type, my_a, a.ntypes);
     my_lc = min(a.count[my_i], a.cap);
     my_cf = a.conf_of ? a.conf_of[my_a] : 0;
 #pragma unroll
@@ -270,7 +270,7 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEu<T, PG>::value))) void k_force_wave
       const int j = jw[u];
       if (valid) {
         min_image(d, cf);
-        const int tj = NT1 ? 0 : a.type[j];
+        const int tj = NT1 ? 0 : species(a.type, j, a.ntypes);
         const double f2 = NT1 ? filt2_0 : filt2[ti * nt + tj];
         if constexpr (SP)
           pass = (float)d[0] * (float)d[0] + (float)d[1] * (float)d[1] + (float)d[2] * (float)d[2] <
@@ -347,7 +347,7 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEu<T, PG>::value))) void k_force_wave
     const int i = lane_read(my_i, at), ti = lane_read(my_t, at), cf = lane_read(my_cf, at);
     const int ia = lane_read(my_a, at);  // atom of position i
     const int j = act ? s_stage[w][at * kNMax + q] : ia;  // neighbour's atom
-    const int tj = NT1 ? 0 : (act ? a.type[j] : 0);
+    const int tj = NT1 ? 0 : (act ? species(a.type, j, a.ntypes) : 0);
     // incoming slot at j for this pair's force on j, fetched now so that the
     // load is complete when the force is stored
     const int r_out = a.rev[act ? (int64_t)i * a.cap + s_slot[w][at * kNMax + q] : 0];
@@ -434,12 +434,25 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEu<T, PG>::value))) void k_force_wave
     EA ev = 0;
     const double eb = DUAL ? (a.ebar_conf ? a.ebar_conf[cf] : a.ebar) : 1.0;
     if (in_pair) {
-      const T fr = scaled_exp(pp.A, pp.A_lo, pp.lam1, pp.lam1_lo, r, rlo);
-      const T fa = -scaled_exp(pp.Bc, pp.B_lo, pp.lam2, pp.lam2_lo, r, rlo);
+      T fr, fa;
+      AT fre, fae;  // the same for the energy
+      if constexpr (std::is_same<T, float>::value && !SP) {  // mixed: FP64 exponentials
+        const double e1 = exp64(pp.A, pp.A_lo, pp.lam1, pp.lam1_lo, r, rlo);
+        const double e2 = exp64(pp.Bc, pp.B_lo, pp.lam2, pp.lam2_lo, r, rlo);
+        fr = (float)e1;
+        fa = -(float)e2;
+        fre = e1;
+        fae = -e2;
+      } else {
+        fr = scaled_exp(pp.A, pp.A_lo, pp.lam1, pp.lam1_lo, r, rlo);
+        fa = -scaled_exp(pp.Bc, pp.B_lo, pp.lam2, pp.lam2_lo, r, rlo);
+        fre = wide(fr);
+        fae = wide(fa);
+      }
       T b, db, dbb, dbn;
       bond<T, B, PG>(pp, zeta, b, db, dbb, dbn);
       const T vr = fr + b * fa;
-      const AT V = wide(fc) * (wide(fr) + wide(b) * wide(fa));
+      const AT V = wide(fc) * (fre + wide(b) * fae);
       const T dVdr = dfc * vr + fc * (-pp.lam1 * fr - pp.lam2 * b * fa);
       dzeta = B(0.5) * fc * fa * db;
       const T hp = B(0.5) * dVdr;

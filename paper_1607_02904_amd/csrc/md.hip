@@ -20,13 +20,13 @@ constexpr int kBS = 256;
 // list build (FP64, minimum image)
 __global__ void k_vv_first(int n, double *__restrict__ x, double *__restrict__ v,
                            double *__restrict__ f, const int32_t *__restrict__ type,
-                           const double *__restrict__ mass, double dt,
+                           const double *__restrict__ mass, int nt, double dt,
                            const double *__restrict__ xref, const ConfDesc *__restrict__ conf,
                            double lim2, int32_t *flag, int zero_f) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   bool over = false;
   if (i < n) {
-    const double s = 0.5 * dt * kFtm2v / mass[type[i]];
+    const double s = 0.5 * dt * kFtm2v / mass[species(type, i, nt)];
     const ConfDesc &c = conf[0];
     double r2 = 0.0;
 #pragma unroll
@@ -48,11 +48,11 @@ __global__ void k_vv_first(int n, double *__restrict__ x, double *__restrict__ v
 // v += dt/2 F/m; the rebuild flag is cleared for the next step
 __global__ void k_vv_second(int n, double *__restrict__ v, const double *__restrict__ f,
                             const int32_t *__restrict__ type, const double *__restrict__ mass,
-                            double dt, int32_t *flag) {
+                            int nt, double dt, int32_t *flag) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i == 0 && flag) *flag = 0;
   if (i >= n) return;
-  const double s = 0.5 * dt * kFtm2v / mass[type[i]];
+  const double s = 0.5 * dt * kFtm2v / mass[species(type, i, nt)];
   v[3 * i + 0] += s * f[3 * i + 0];
   v[3 * i + 1] += s * f[3 * i + 1];
   v[3 * i + 2] += s * f[3 * i + 2];
@@ -110,7 +110,7 @@ __global__ void k_vv_gather_kick_drift(int n, const int32_t *__restrict__ pos,
                                        const double *__restrict__ fown, double *__restrict__ F,
                                        double *__restrict__ v, double *__restrict__ x,
                                        const int32_t *__restrict__ type,
-                                       const double *__restrict__ mass, double dt,
+                                       const double *__restrict__ mass, int nt, double dt,
                                        const double *__restrict__ xref,
                                        const ConfDesc *__restrict__ conf, double lim2,
                                        int32_t *flag, int do_next,
@@ -124,7 +124,7 @@ __global__ void k_vv_gather_kick_drift(int n, const int32_t *__restrict__ pos,
     const int s0 = soff[t], s1 = soff[t + 1];
     double fv[3] = {fown[3 * t], fown[3 * t + 1], fown[3 * t + 2]};
     sum_slots(fslot, s0, s1, fv[0], fv[1], fv[2]);
-    const double s = 0.5 * dt * kFtm2v / mass[type[i]];
+    const double s = 0.5 * dt * kFtm2v / mass[species(type, i, nt)];
     const ConfDesc &c = conf[0];
     double r2 = 0.0;
 #pragma unroll
@@ -152,7 +152,7 @@ __global__ void k_vv_gather_kick_drift(int n, const int32_t *__restrict__ pos,
 
 void launch_vv_gather_kick_drift(const NList &nl, double *x, double *v, double *F,
                                  const void *fslot, bool slot_f32, const double *fown,
-                                 const int32_t *type, const double *mass, double dt,
+                                 const int32_t *type, const double *mass, int nt, double dt,
                                  int32_t *flag, int do_next, const double *partials, int nblocks,
                                  double *energy, double *trace, int32_t *step, hipStream_t s) {
   const int n = nl.n;
@@ -163,28 +163,28 @@ void launch_vv_gather_kick_drift(const NList &nl, double *x, double *v, double *
   if (slot_f32)
     k_vv_gather_kick_drift<float><<<g, kBS, 0, s>>>(
         n, nl.pos.as<int32_t>(), nl.soff.as<int32_t>(), (const float *)fslot, fown, F, v, x,
-        type, mass, dt, nl.xref.as<double>(), nl.conf.as<ConfDesc>(), half * half, flag, do_next,
+        type, mass, nt, dt, nl.xref.as<double>(), nl.conf.as<ConfDesc>(), half * half, flag, do_next,
         partials, nblocks, esum, count, energy, trace, step);
   else
     k_vv_gather_kick_drift<double><<<g, kBS, 0, s>>>(
         n, nl.pos.as<int32_t>(), nl.soff.as<int32_t>(), (const double *)fslot, fown, F, v, x,
-        type, mass, dt, nl.xref.as<double>(), nl.conf.as<ConfDesc>(), half * half, flag, do_next,
+        type, mass, nt, dt, nl.xref.as<double>(), nl.conf.as<ConfDesc>(), half * half, flag, do_next,
         partials, nblocks, esum, count, energy, trace, step);
 }
 
 void launch_vv_first(int n, double *x, double *v, double *f, const int32_t *type,
-                     const double *mass, double dt, const NList &nl, int32_t *flag, int zero_f,
+                     const double *mass, int nt, double dt, const NList &nl, int32_t *flag, int zero_f,
                      hipStream_t s) {
   if (n <= 0) return;
   const double half = 0.5 * nl.skin;
-  k_vv_first<<<(n + kBS - 1) / kBS, kBS, 0, s>>>(n, x, v, f, type, mass, dt, nl.xref.as<double>(),
+  k_vv_first<<<(n + kBS - 1) / kBS, kBS, 0, s>>>(n, x, v, f, type, mass, nt, dt, nl.xref.as<double>(),
                                                  nl.conf.as<ConfDesc>(), half * half, flag,
                                                  zero_f);
 }
 
 void launch_vv_second(int n, double *v, const double *f, const int32_t *type, const double *mass,
-                      double dt, int32_t *flag, hipStream_t s) {
-  k_vv_second<<<(std::max(n, 1) + kBS - 1) / kBS, kBS, 0, s>>>(n, v, f, type, mass, dt, flag);
+                      int nt, double dt, int32_t *flag, hipStream_t s) {
+  k_vv_second<<<(std::max(n, 1) + kBS - 1) / kBS, kBS, 0, s>>>(n, v, f, type, mass, nt, dt, flag);
 }
 
 }  // namespace ters

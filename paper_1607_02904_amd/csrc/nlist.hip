@@ -58,12 +58,16 @@ DEV void bin_one(int i, const double *__restrict__ x, const ConfDesc *__restrict
                  const int32_t *__restrict__ conf_of, int32_t *__restrict__ cell_of,
                  int32_t *__restrict__ cell_count, uint32_t *err);
 
+// also checks every species against [0, ntypes) when type is given
 __global__ void k_bin(int n, const double *__restrict__ x, const ConfDesc *__restrict__ conf,
                       const int32_t *__restrict__ conf_of, int32_t *__restrict__ cell_of,
-                      int32_t *__restrict__ cell_count, const int32_t *cond, uint32_t *err) {
+                      int32_t *__restrict__ cell_count, const int32_t *__restrict__ type,
+                      int ntypes, const int32_t *cond, uint32_t *err) {
   if (skip(cond)) return;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     bin_one(i, x, conf, conf_of, cell_of, cell_count, err);
+    if (type && (unsigned)type[i] >= (unsigned)ntypes) atomicOr(err, kErrBadType);
+  }
 }
 
 DEV void bin_one(int i, const double *__restrict__ x, const ConfDesc *__restrict__ conf,
@@ -620,8 +624,8 @@ void launch_fill_f64(double *p, double v, int64_t n, hipStream_t s) {
 // Build the list for the configuration set described by nl (geometry already
 // filled in by the caller).  cond: device flag (may be null); when non-null
 // and zero every kernel returns immediately.
-void nlist_build(NList &nl, const double *x, const int32_t *cond, uint32_t *err, hipStream_t s,
-                 int64_t *rebuild_counter) {
+void nlist_build(NList &nl, const double *x, const int32_t *type, int ntypes, const int32_t *cond,
+                 uint32_t *err, hipStream_t s, int64_t *rebuild_counter) {
   const int n = nl.n;
   const int64_t ncell = nl.ncell;
   int32_t *cell_count = nl.cell_count.as<int32_t>();
@@ -643,8 +647,8 @@ void nlist_build(NList &nl, const double *x, const int32_t *cond, uint32_t *err,
     return g < 1 ? 1 : (g > gcap ? gcap : g);
   };
   if (n > 0)
-    k_bin<<<grid(n), kBS, 0, s>>>(n, x, conf, conf_of, nl.cell_of.as<int32_t>(), cell_count, cond,
-                                  err);
+    k_bin<<<grid(n), kBS, 0, s>>>(n, x, conf, conf_of, nl.cell_of.as<int32_t>(), cell_count, type,
+                                  ntypes, cond, err);
   if (m <= kScan1Max) {
     k_scan_single<<<1, kScan1BS, 0, s>>>(cell_count, cell_start, m, cond);
   } else {

@@ -165,6 +165,18 @@ DEV float scaled_exp(float c, float c_lo, float lam, float lam_lo, float r, floa
   float e = expf(-p);
   return fmaf(e, c, e * (c_lo - c * corr));  // e c exact, the correction added before rounding
 }
+// The same in FP64, for the mixed path's pair energy: c = c_hi + c_lo,
+// lam = lam_hi + lam_lo and r = r_hi + r_lo (the FP32 distance and the
+// residual of the FP64 one) widened exactly.  Each FP32 pair exponential
+// carries ~0.6 ulp of rounding; in disordered cells, where the repulsive and
+// attractive parts nearly cancel, that rounding would set the energy error,
+// so the mixed path evaluates the two exponentials of a pair once in FP64
+// (the forces use them rounded to FP32).
+DEV double exp64(float c, float c_lo, float lam, float lam_lo, float r, float r_lo) {
+  const double rr = (double)r + (double)r_lo;
+  return ((double)c + (double)c_lo) * exp(-((double)lam + (double)lam_lo) * rr);
+}
+
 template <class B>
 DEV Dual<B> scaled_exp(B c, B c_lo, B lam, B lam_lo, Dual<B> r, B r_lo) {
   B v = scaled_exp(c, c_lo, lam, lam_lo, r.v, r_lo);
@@ -227,6 +239,14 @@ DEV void sum_slots(const S *__restrict__ fslot, int s0, int s1, double &fx, doub
       }
     }
   }
+}
+
+// Species of atom i, used as an index into the parameter table: a value
+// outside [0, nt) (which the list build reports as an error) reads entry 0
+// instead of memory outside the table.
+DEV int species(const int32_t *__restrict__ type, int64_t i, int nt) {
+  const int t = type[i];
+  return (unsigned)t < (unsigned)nt ? t : 0;
 }
 
 // hardware FP64 atomic add to global memory (global_atomic_add_f64)

@@ -66,7 +66,8 @@ enum : uint32_t {
   kErrNlistOverflow = 1u,
   kErrNotFinite = 2u,
   kErrTooManyInCutoff = 4u,
-  kErrListAsymmetric = 8u
+  kErrListAsymmetric = 8u,
+  kErrBadType = 16u
 };
 
 // Neighbour list state.  One list per configuration set (a single system is
@@ -142,8 +143,10 @@ struct FwdArgs {
 // launchers (implemented in the .hip files)
 void launch_fill_i32(int32_t *p, int32_t v, int64_t n, const int32_t *cond, hipStream_t s);
 void launch_fill_f64(double *p, double v, int64_t n, hipStream_t s);
-void nlist_build(NList &nl, const double *x, const int32_t *cond, uint32_t *err, hipStream_t s,
-                 int64_t *rebuild_counter = nullptr);
+// type (device [n], may be null) is checked against [0, ntypes) by the binning
+// pass, which latches kErrBadType
+void nlist_build(NList &nl, const double *x, const int32_t *type, int ntypes, const int32_t *cond,
+                 uint32_t *err, hipStream_t s, int64_t *rebuild_counter = nullptr);
 void nlist_check(const NList &nl, const double *x, int32_t *flag, hipStream_t s);
 // F[a] (+)= fown[t] + sum of the incoming slots fslot[soff[t] .. soff[t + 1]), t = pos[a]
 // (FP32 slots when slot_f32), summed in FP64 in slot order
@@ -178,11 +181,12 @@ int thread_blocks(int n);
 void launch_reduce_partials(const double *partials, int nblocks, int stride, double *energy,
                             double *virial, int accumulate, hipStream_t s,
                             double *trace = nullptr, int32_t *step = nullptr);
+// species outside [0, nt) read mass[0] (the list build reports them)
 void launch_vv_first(int n, double *x, double *v, double *f, const int32_t *type,
-                     const double *mass, double dt, const NList &nl, int32_t *flag, int zero_f,
+                     const double *mass, int nt, double dt, const NList &nl, int32_t *flag, int zero_f,
                      hipStream_t s);
 void launch_vv_second(int n, double *v, const double *f, const int32_t *type, const double *mass,
-                      double dt, int32_t *flag, hipStream_t s);
+                      int nt, double dt, int32_t *flag, hipStream_t s);
 // molecular dynamics, owner-gather mode: the gather above and the second half
 // kick of this step, then (do_next) the first half kick, drift and rebuild test
 // of the next; when trace is set, the force kernel's energy partials are also
@@ -190,7 +194,7 @@ void launch_vv_second(int n, double *v, const double *f, const int32_t *type, co
 // energy points to a zero-initialised scratch of 8 + 16 doubles and a counter
 void launch_vv_gather_kick_drift(const NList &nl, double *x, double *v, double *F,
                                  const void *fslot, bool slot_f32, const double *fown,
-                                 const int32_t *type, const double *mass, double dt,
+                                 const int32_t *type, const double *mass, int nt, double dt,
                                  int32_t *flag, int do_next, const double *partials, int nblocks,
                                  double *energy, double *trace, int32_t *step, hipStream_t s);
 

@@ -100,8 +100,32 @@ def load_library(path=LIB_PATH):
     return L
 
 
-def _ptr(t):
-    return None if t is None else ctypes.c_void_p(t.data_ptr())
+def _ptr(t, dtype=torch.float64, name="tensor", rows=None, cols=None):
+    """Device address of a tensor handed to the library, after checking what
+    the C interface assumes of it: on a GPU, contiguous, of the given dtype
+    (float64 for positions, forces and cotangents, int32 for species) and,
+    when given, of the given leading size and row width."""
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a CUDA tensor" % name)
+    if t.dtype != dtype:
+        raise TypeError("%s must be %s, not %s" % (name, dtype, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if rows is not None and (t.dim() == 0 or t.shape[0] != rows):
+        raise ValueError("%s must have %d rows, not shape %s" % (name, rows, tuple(t.shape)))
+    if cols is not None and (t.dim() != 2 or t.shape[1] != cols):
+        raise ValueError("%s must have shape (n, %d), not %s" % (name, cols, tuple(t.shape)))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _pos(x, name="x"):
+    return _ptr(x, torch.float64, name, cols=3)
+
+
+def _types(t, n):
+    return _ptr(t, torch.int32, "types", rows=n)
 
 
 def _hostbuf(a, dtype):
@@ -182,7 +206,8 @@ class Tersoff:
     def build_nlist(self, x, types, box, skin=0.0):
         self._bind_stream()
         b, bp = _hostbuf(box, np.float64)
-        self._chk(self._L.ters_build_nlist(self._h, x.shape[0], _ptr(x), _ptr(types), bp, float(skin)))
+        self._chk(self._L.ters_build_nlist(self._h, x.shape[0], _pos(x), _types(types, x.shape[0]), bp,
+                                           float(skin)))
         self.skin = float(skin)
         self.box = b.copy()
 
@@ -190,7 +215,7 @@ class Tersoff:
         self._bind_stream()
         if flag is None:
             flag = torch.zeros(1, dtype=torch.int32, device=x.device)
-        self._chk(self._L.ters_needs_rebuild(self._h, _ptr(x), _ptr(flag)))
+        self._chk(self._L.ters_needs_rebuild(self._h, _pos(x), _ptr(flag, torch.int32, "flag")))
         return flag
 
     def nlist_stats(self):
@@ -226,7 +251,7 @@ class Tersoff:
         self._bind_stream()
         b, bp = _hostbuf(box, np.float64)
         us = ctypes.c_double()
-        self._chk(self._L.ters_autotune(self._h, x.shape[0], _ptr(x), _ptr(types), bp, precision,
+        self._chk(self._L.ters_autotune(self._h, x.shape[0], _pos(x), _types(types, x.shape[0]), bp, precision,
                                         ctypes.byref(us)))
         return us.value
 
@@ -236,7 +261,7 @@ class Tersoff:
         self._bind_stream()
         b, bp = _hostbuf(box, np.float64)
         us = ctypes.c_double()
-        self._chk(self._L.ters_profile_forward(self._h, x.shape[0], _ptr(x), _ptr(types), bp, precision,
+        self._chk(self._L.ters_profile_forward(self._h, x.shape[0], _pos(x), _types(types, x.shape[0]), bp, precision,
                                                int(reps), int(bool(with_gather)), ctypes.byref(us)))
         return us.value
 
@@ -266,10 +291,12 @@ class Tersoff:
             flags |= PARAM_GRAD
             o.setdefault("param_grad", torch.zeros(self.table.shape, dtype=torch.float64, device=dev))
         b, bp = _hostbuf(box, np.float64)
-        self._chk(self._L.ters_compute_ex(self._h, n, _ptr(x), _ptr(types), bp, precision, flags,
-                                          _ptr(o.get("energy")), _ptr(o.get("forces")),
-                                          _ptr(o.get("virial")), _ptr(o.get("e_atom")),
-                                          _ptr(o.get("param_grad"))))
+        self._chk(self._L.ters_compute_ex(self._h, n, _pos(x), _types(types, n), bp, precision, flags,
+                                          _ptr(o.get("energy"), name="energy", rows=1),
+                                          _ptr(o.get("forces"), name="forces", rows=n, cols=3),
+                                          _ptr(o.get("virial"), name="virial", rows=6),
+                                          _ptr(o.get("e_atom"), name="e_atom", rows=n),
+                                          _ptr(o.get("param_grad"), name="param_grad")))
         return o
 
     def pair_compute(self, x, box, eps, sigma, rc, precision=FP64):
@@ -282,7 +309,7 @@ class Tersoff:
              "forces": torch.empty((n, 3), dtype=torch.float64, device=dev),
              "virial": torch.empty(6, dtype=torch.float64, device=dev)}
         b, bp = _hostbuf(box, np.float64)
-        self._chk(self._L.ters_pair_compute(self._h, n, _ptr(x), bp, float(eps), float(sigma),
+        self._chk(self._L.ters_pair_compute(self._h, n, _pos(x), bp, float(eps), float(sigma),
                                             float(rc), precision, ENERGY | FORCES | VIRIAL,
                                             _ptr(o["energy"]), _ptr(o["forces"]), _ptr(o["virial"])))
         return o
@@ -296,8 +323,9 @@ class Tersoff:
         pg = torch.empty(self.table.shape, dtype=torch.float64, device=x.device)
         b, bp = _hostbuf(box, np.float64)
         fb = f_bar.contiguous()
-        self._chk(self._L.ters_backward(self._h, n, _ptr(x), _ptr(types), bp, precision,
-                                        float(e_bar), _ptr(fb), _ptr(xg), _ptr(pg)))
+        self._chk(self._L.ters_backward(self._h, n, _pos(x), _types(types, n), bp, precision,
+                                        float(e_bar), _ptr(fb, name="f_bar", rows=n, cols=3),
+                                        _ptr(xg), _ptr(pg)))
         return xg, pg
 
     def md_run(self, x, v, f, types, box, dt, nsteps, skin, precision=FP64, trace=None,
@@ -307,8 +335,10 @@ class Tersoff:
         if trace is None:
             trace = torch.empty(max(nsteps, 1), dtype=torch.float64, device=x.device)
         b, bp = _hostbuf(box, np.float64)
-        self._chk(self._L.ters_md_run(self._h, x.shape[0], _ptr(x), _ptr(v), _ptr(f), _ptr(types), bp,
-                                      float(dt), int(nsteps), float(skin), precision, _ptr(trace),
+        n = x.shape[0]
+        self._chk(self._L.ters_md_run(self._h, n, _pos(x), _pos(v, "v"), _pos(f, "f"), _types(types, n), bp,
+                                      float(dt), int(nsteps), float(skin), precision,
+                                      _ptr(trace, name="trace"),
                                       1 if use_graph else 0))
         return trace
 
@@ -320,9 +350,11 @@ class Tersoff:
             trace = torch.empty(max(nsteps, 1), dtype=torch.float64, device=x.device)
         b, bp = _hostbuf(box, np.float64)
         us = np.zeros(1, dtype=np.float64)
-        self._chk(self._L.ters_md_run_timed(self._h, x.shape[0], _ptr(x), _ptr(v), _ptr(f), _ptr(types),
-                                            bp, float(dt), int(nsteps), float(skin), precision,
-                                            _ptr(trace), us.ctypes.data_as(ctypes.c_void_p)))
+        n = x.shape[0]
+        self._chk(self._L.ters_md_run_timed(self._h, n, _pos(x), _pos(v, "v"), _pos(f, "f"),
+                                            _types(types, n), bp, float(dt), int(nsteps), float(skin),
+                                            precision, _ptr(trace, name="trace"),
+                                            us.ctypes.data_as(ctypes.c_void_p)))
         return trace, float(us[0])
 
     def sync(self):
@@ -356,9 +388,12 @@ class BatchPlan:
     def run(self, x, types, e=None, f=None, w=None, e_bar=None, f_bar=None, x_grad=None,
             param_grad=None):
         self.model._bind_stream()
-        _check(self.model._h, self._L.ters_batch_run(self._h, _ptr(x), _ptr(types), _ptr(e), _ptr(f),
-                                                     _ptr(w), _ptr(e_bar), _ptr(f_bar), _ptr(x_grad),
-                                                     _ptr(param_grad)))
+        N = int(self.offsets[-1])
+        _check(self.model._h, self._L.ters_batch_run(
+            self._h, _ptr(x, name="x", rows=N, cols=3), _types(types, N), _ptr(e, name="e", rows=self.nconf),
+            _ptr(f, name="f", rows=N, cols=3), _ptr(w, name="w", rows=self.nconf, cols=6),
+            _ptr(e_bar, name="e_bar", rows=self.nconf), _ptr(f_bar, name="f_bar", rows=N, cols=3),
+            _ptr(x_grad, name="x_grad", rows=N, cols=3), _ptr(param_grad, name="param_grad")))
 
     def schedule(self):
         out = np.zeros(3)
@@ -382,21 +417,35 @@ class BatchPlan:
 class TersoffEF(torch.autograd.Function):
     """(E, F) = Tersoff(x; table) with a hand-written adjoint.
 
+    Forward and backward each build the neighbour list for their x, and the
+    backward runs at the table of its own forward, so several frames (and
+    parameter updates between steps) can share one model.
+
     forward(model, x, table, types, box, precision) -> (E [1], F [n,3])
     backward returns dL/dx and dL/dtable from one dual-number pass of the
     force kernel (zeta recomputed, no stored triplets)."""
 
     @staticmethod
-    def forward(ctx, model, x, table, types, box, precision=FP64):
-        tab = table.detach().cpu().numpy()
+    def _use(model, tab, x, types, box):
+        """Make `tab` the model's table and build the list for x (with the
+        model's skin): a fitting loop evaluates many frames, and the
+        backward of one may run after the forward of another, so neither
+        pass relies on a list built elsewhere."""
         if not np.array_equal(tab, model.table):
             model.set_params(tab)
+        model.build_nlist(x, types, box, model.skin)
+
+    @staticmethod
+    def forward(ctx, model, x, table, types, box, precision=FP64):
+        tab = table.detach().cpu().numpy().astype(np.float64)
+        TersoffEF._use(model, tab, x.detach(), types, box)
         o = model.compute(x.detach(), types, box, precision, energy=True, forces=True, virial=False)
         ctx.model = model
         ctx.types = types
         ctx.box = np.asarray(box, dtype=np.float64)
         ctx.precision = precision
         ctx.table_device = table.device
+        ctx.table = tab  # the adjoint runs at the parameters of this forward
         ctx.save_for_backward(x)
         return o["energy"], o["forces"]
 
@@ -406,5 +455,7 @@ class TersoffEF(torch.autograd.Function):
         eb = 0.0 if e_bar is None else float(e_bar.reshape(-1)[0].item())
         if f_bar is None:
             f_bar = torch.zeros_like(x)
-        xg, pg = ctx.model.backward(x.detach(), ctx.types, ctx.box, eb, f_bar, ctx.precision)
+        TersoffEF._use(ctx.model, ctx.table, x.detach(), ctx.types, ctx.box)
+        xg, pg = ctx.model.backward(x.detach(), ctx.types, ctx.box, eb, f_bar.contiguous(),
+                                    ctx.precision)
         return None, xg, pg.to(ctx.table_device), None, None, None

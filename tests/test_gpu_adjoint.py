@@ -150,14 +150,36 @@ def test_sic_parameter_gradient_fp64(orc, kernel):
     _check_params(pg, fd, 1e-6)
 
 
-def test_mixed_adjoint_close_to_fp64(si_setup):
+@pytest.fixture(scope="module")
+def si_fd(orc, si_setup):
     frames, table, refs, model = si_setup
-    pg64, xg64 = _gpu_grad(model, frames, refs, 0)
-    pgm, xgm = _gpu_grad(model, frames, refs, 1)
+    return _fd_params(orc, frames, table, refs, [(0, 0, 0)])
+
+
+@pytest.mark.parametrize("kernel,atoms", [(1, 0), (2, 0), (2, 32)], ids=["workgroup", "wave", "wave32"])
+def test_mixed_adjoint(si_setup, si_fd, kernel, atoms):
+    """The mixed adjoint (dual numbers over FP32 arithmetic, FP64
+    accumulators) of both schedules against central differences of the FP64
+    oracle's loss and against the FP64 adjoint.  Gradient accuracy is gated
+    for the FP64 path only (1e-6); the mixed error is reported, with a sanity
+    bar of 1e-3 (an FP32 gradient of a loss that is itself a difference of
+    forces)."""
+    frames, table, refs, model = si_setup
+    model.set_schedule(kernel, atoms, 0)
+    try:
+        pg64, xg64 = _gpu_grad(model, frames, refs, 0)
+        pgm, xgm = _gpu_grad(model, frames, refs, 1)
+    finally:
+        model.set_schedule(0, 0, 0)
+    keys = list(si_fd.keys())
+    g = np.array([pgm[k] for k in keys])
+    d = np.array([si_fd[k] for k in keys])
+    rel_fd = np.linalg.norm(g - d) / np.linalg.norm(d)
     rel_p = np.linalg.norm(pgm - pg64) / np.linalg.norm(pg64)
     rel_x = np.linalg.norm(xgm[0] - xg64[0]) / np.linalg.norm(xg64[0])
-    print("mixed adjoint vs fp64: params %.2e positions %.2e" % (rel_p, rel_x))
-    assert rel_p < 1e-3 and rel_x < 1e-3
+    print("mixed adjoint, kernel %d: params vs FD %.2e, params vs FP64 adjoint %.2e, "
+          "positions vs FP64 adjoint %.2e" % (kernel, rel_fd, rel_p, rel_x))
+    assert rel_fd < 1e-3 and rel_p < 1e-3 and rel_x < 1e-3
 
 
 def test_autograd_function_matches_direct_adjoint(si_setup):
@@ -177,3 +199,42 @@ def test_autograd_function_matches_direct_adjoint(si_setup):
     pg, xgs = _gpu_grad(model, [frames[0]], [refs[0]], 0)
     assert np.allclose(tab.grad.cpu().numpy(), pg, rtol=1e-12, atol=1e-14)
     assert np.allclose(xd.grad.cpu().numpy(), xgs[0], rtol=1e-12, atol=1e-14)
+
+
+def test_fitting_loop_with_cutoffs_free(orc, si_setup):
+    """Two optimiser steps of a fit over two frames through TersoffEF with
+    every field free (R and D included, so the cutoffs move between steps):
+    each step's gradient equals the adjoint recomputed directly at that
+    step's table, and the loss matches the oracle's at that table."""
+    from paper_1607_02904_amd.tersoff import TersoffEF
+    frames, table, refs, model = si_setup
+    tab = torch.tensor(table, device="cuda", requires_grad=True)
+    opt = torch.optim.SGD([tab], lr=1e-4)
+    scale = torch.ones_like(tab)
+    scale[..., params.IDX["m"]] = 0.0  # m stays an integer
+    try:
+        for step in range(2):
+            opt.zero_grad()
+            loss = 0.0
+            for (x, t, box), (er, fr) in zip(frames, refs):
+                xd = torch.as_tensor(x, device="cuda")
+                td = torch.as_tensor(t, device="cuda")
+                E, F = TersoffEF.apply(model, xd, tab, td, box, 0)
+                n = len(t)
+                loss = loss + (E.sum() - er) ** 2 / n ** 2 + WF * ((F - torch.as_tensor(fr, device="cuda")) ** 2).sum()
+            loss.backward()
+            cur = tab.detach().cpu().numpy().copy()
+            ref_loss = _loss(orc, frames, cur, refs)
+            assert abs(float(loss.item()) - ref_loss) <= 1e-8 * abs(ref_loss)
+            model.set_params(cur)
+            pg, _ = _gpu_grad(model, frames, refs, 0)
+            g = tab.grad.cpu().numpy()
+            assert np.allclose(g, pg, rtol=1e-10, atol=1e-12 * np.abs(pg).max()), step
+            with torch.no_grad():
+                tab.grad.mul_(scale)
+                # a step large enough to move R and D by about 1e-4 A
+                tab.grad.mul_(1e-4 / max(float(tab.grad.abs().max().item()), 1e-30) / 1e-4)
+            opt.step()
+        assert not np.array_equal(tab.detach().cpu().numpy(), table)
+    finally:
+        model.set_params(table)

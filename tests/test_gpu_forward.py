@@ -2,7 +2,17 @@
 against the FP64 oracle, through the C ABI.
 
 Bars: FP64 path <= 1e-12 relative (energy, norm-wise forces, Frobenius
-virial); mixed path <= 1e-5 norm-wise on forces and <= 1e-7 on energy.
+virial); mixed path <= 1e-5 norm-wise on forces and <= 1e-7 relative on the
+energy, |dE| <= 1e-7 |E|, with a per-atom floor: where |E|/N is below
+E_FLOOR = 1 eV/atom the bar is 1e-7 eV per atom.  The floor only matters for
+disordered cells whose repulsive and attractive parts cancel to a few per
+cent (|E| -> 0 while each pair term keeps its size): the rounding error of
+the FP32 arithmetic has no systematic sign, so the error of the sum scales
+with the sum of the term magnitudes (about 40 eV/atom in liquid SiC), not
+with |E|, and a relative error of a vanishing energy is not defined.
+Crystals (|E|/N > 4 eV/atom) and liquid cells with |E|/N >= 1 eV/atom are
+held to the plain relative bar.  Every mixed case prints its |dE|/|E| and
+|dE|/N.
 Single-precision mode (positions rounded to FP32, FP32 accumulators): the
 rounding of a coordinate of up to ~30 A costs ~2e-6 A, i.e. ~1e-6 of a bond
 length; the pair exponentials magnify a relative error in r by lambda r ~ 8
@@ -22,6 +32,7 @@ pytestmark = pytest.mark.gpu
 FP64_TOL = 1e-12
 MIX_F_TOL = 1e-5
 MIX_E_TOL = 1e-7
+E_FLOOR = 1.0  # eV/atom, see the module docstring
 SP_F_TOL = 2e-4
 SP_E_TOL = 2e-5
 
@@ -72,10 +83,9 @@ def _si_table_oracle():
 
 def energy_scale(orc, x, t, box, table):
     """S = E_rep - E_att: the repulsive (f_R) and attractive (b f_A) parts of
-    the energy, each from the oracle with the other part switched off.  It is
-    the magnitude of the terms that the FP32 arithmetic evaluates, the
-    conditioning scale of the energy sum (|E| can be far smaller on
-    disordered cells, where the two parts nearly cancel)."""
+    the energy, each from the oracle with the other part switched off.  The
+    single mode's energy bar is taken relative to it (its error comes from
+    rounding the positions to FP32 and scales with the size of the terms)."""
     rep = table.copy()
     rep[..., params.IDX["B"]] = 0.0
     att = table.copy()
@@ -83,10 +93,20 @@ def energy_scale(orc, x, t, box, table):
     return orc.compute(x, t, box, rep)[0] - orc.compute(x, t, box, att)[0]
 
 
-def _check(gpu, ref, precision, escale=None):
-    """escale: mixed-path energy scale (default |E|, the crystals' bar)."""
+def mixed_energy_ok(e, er, n, tag=""):
+    """The mixed-path energy bar: |dE| <= 1e-7 max(|E|, E_FLOOR N); prints
+    the achieved relative and per-atom errors."""
+    d = abs(e - er)
+    print("mixed energy %s: |dE|/|E| = %.2e, |dE|/N = %.2e eV (E/N = %+.3f eV)"
+          % (tag, d / abs(er) if er else float("inf"), d / max(n, 1), er / max(n, 1)))
+    return d <= MIX_E_TOL * max(abs(er), E_FLOOR * n)
+
+
+def _check(gpu, ref, precision, sp_scale=None):
+    """sp_scale: energy scale of the single mode's bar (default |E|)."""
     e, f, w, ea = gpu
     er, fr, wr, ear = ref
+    n = len(f)
     if np.abs(fr).max() < 1e-8:
         # perfect lattice: forces vanish, so the bar is absolute
         assert np.abs(f).max() <= (1e-10 if precision == 0 else 1e-5 if precision == 1 else 1e-4)
@@ -98,9 +118,12 @@ def _check(gpu, ref, precision, escale=None):
         if ea is not None:
             assert _rel(ea, ear) <= FP64_TOL
     else:
-        etol, ftol = (MIX_E_TOL, MIX_F_TOL) if precision == 1 else (SP_E_TOL, SP_F_TOL)
-        scale = abs(er) if escale is None else escale
-        assert abs(e - er) <= etol * scale, (e, er, abs(e - er) / scale)
+        if precision == 1:
+            ftol = MIX_F_TOL
+            assert mixed_energy_ok(e, er, n), (e, er)
+        else:
+            ftol = SP_F_TOL
+            assert abs(e - er) <= SP_E_TOL * (abs(er) if sp_scale is None else sp_scale), (e, er)
         assert _rel(f, fr) <= ftol, _rel(f, fr)
         assert _rel(w, wr) <= ftol, _rel(w, wr)
         if ea is not None:
@@ -122,8 +145,8 @@ def test_sic_liquid(orc, sic_model, precision, seed):
     several hundred atoms (several workgroups, ragged last one)."""
     x, t, box = inputs.sic_liquid_batch(nconf=1, nmin=700, nmax=1500, seed=100 + seed)[0]
     ref = orc.compute(x, t, box, params.sic())
-    scale = energy_scale(orc, x, t, box, params.sic())
-    _check(gpu_eval(sic_model, x, t, box, precision), ref, precision, escale=scale)
+    sp = energy_scale(orc, x, t, box, params.sic()) if precision == 2 else None
+    _check(gpu_eval(sic_model, x, t, box, precision), ref, precision, sp_scale=sp)
 
 
 SCHEDULES = [(1, 8, 0), (1, 13, 0), (1, 32, 1), (1, 64, 2), (1, 40, 0), (1, 1, 0),
@@ -137,10 +160,9 @@ def test_schedules_and_kmax_fallback(orc, sic_model, kernel, atoms, kmax, precis
     k_max fallback (recompute dzeta/dx_k beyond k_max) reach the same result."""
     x, t, box = inputs.sic_liquid_batch(nconf=1, nmin=600, nmax=700, seed=7)[0]
     ref = orc.compute(x, t, box, params.sic())
-    scale = energy_scale(orc, x, t, box, params.sic())
     sic_model.set_schedule(kernel, atoms, kmax)
     try:
-        _check(gpu_eval(sic_model, x, t, box, precision), ref, precision, escale=scale)
+        _check(gpu_eval(sic_model, x, t, box, precision), ref, precision)
     finally:
         sic_model.set_schedule(0, 0, 0)
 
@@ -248,27 +270,67 @@ def test_errors_are_reported(si_model):
     with pytest.raises(TersoffError) as ei:
         si_model.compute(xd[:10], td[:10], box, 0)
     assert ei.value.name == "TERS_ERR_NO_LIST"
+    # a species outside [0, ntypes): the list build refuses it (the force
+    # kernels never see it); a valid build afterwards works again
+    for bad_t in (1, -1):
+        tb = td.clone()
+        tb[7] = bad_t
+        with pytest.raises(TersoffError) as ei:
+            si_model.build_nlist(xd, tb, box, 0.0)
+        assert ei.value.name == "TERS_ERR_INVALID_ARG"
+    si_model.build_nlist(xd, td, box, 0.0)
+    si_model.compute(xd, td, box, 0)
+    si_model.sync()
+    # the binding checks dtypes and layout before anything reaches the library
+    with pytest.raises(TypeError):
+        si_model.build_nlist(xd, td.long(), box, 0.0)
+    with pytest.raises(TypeError):
+        si_model.build_nlist(xd.float(), td, box, 0.0)
+    with pytest.raises(ValueError):
+        si_model.build_nlist(xd.t().contiguous().t(), td, box, 0.0)
+    with pytest.raises(TypeError):
+        si_model.build_nlist(xd.cpu(), td, box, 0.0)
 
 
 # ---------------------------------------------------------------------------
 # full sizes: total energy exact, forces on sampled atoms
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
-def test_si_512k_full_size(orc, si_model, precision):
-    """Si diamond 40^3 cells = 512,000 atoms, sigma 0.1, skin 0.5 (the
-    molecular-dynamics workload), in the benchmark's launch configuration."""
+@pytest.fixture(scope="module")
+def si512k(orc):
+    """Si diamond 40^3 cells = 512,000 atoms, sigma 0.1 (the molecular-dynamics
+    workload) with the published Si(B) table (R = 3.0, D = 0.2), as the
+    benchmark runs it; oracle energy and virial, and forces and per-atom
+    energies of 48 sampled atoms from the oracle's local evaluation."""
+    from paper_1607_02904_amd.tersoff import Tersoff, table_element
     x, t, box = inputs.si_bulk(40)
-    tab = _si_table_oracle()
-    nl = orc.neighbours(x, box, 3.5)
-    rng = np.random.default_rng(5)
-    sample = rng.choice(len(x), size=48, replace=False)
+    tab = params.single(params.SI_B)
+    nl = orc.neighbours(x, box, 3.2 + 0.5)
+    sample = np.random.default_rng(5).choice(len(x), size=48, replace=False)
     fs, es = orc.forces_on(x, t, box, tab, sample, nlist=nl)
     eref, _, wref, _ = orc.compute(x, t, box, tab, nlist=nl)
-    e, f, w, ea = gpu_eval(si_model, x, t, box, precision, skin=0.5)
-    tol_e = FP64_TOL if precision == 0 else MIX_E_TOL
+    m = Tersoff(table_element("Si(B)"), masses=[28.0855])
+    yield x, t, box, sample, fs, es, eref, wref, m
+    m.close()
+
+
+# (kernel, atoms): the workgroup schedule, and the wavefront schedule with 32
+# atoms per wavefront that the autotuner picks for this workload
+@pytest.mark.parametrize("kernel,atoms", [(1, 0), (2, 32)], ids=["workgroup", "wave32"])
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
+def test_si_512k_full_size(si512k, precision, kernel, atoms):
+    """512,000-atom Si in the benchmark's launch configuration (skin 0.5)."""
+    x, t, box, sample, fs, es, eref, wref, m = si512k
+    m.set_schedule(kernel, atoms, 0)
+    try:
+        e, f, w, ea = gpu_eval(m, x, t, box, precision, skin=0.5)
+    finally:
+        m.set_schedule(0, 0, 0)
     tol_f = FP64_TOL if precision == 0 else MIX_F_TOL
-    assert abs(e - eref) <= tol_e * abs(eref)
+    if precision == 0:
+        assert abs(e - eref) <= FP64_TOL * abs(eref)
+    else:
+        assert mixed_energy_ok(e, eref, len(x), "Si 512k")
     assert _rel(f[sample], fs) <= tol_f
     assert _rel(ea[sample], es) <= tol_f
     assert _rel(w, wref) <= tol_f
@@ -276,21 +338,39 @@ def test_si_512k_full_size(orc, si_model, precision):
     assert np.linalg.norm(f.sum(0)) <= 1e-9 * len(x) ** 0.5
 
 
-def test_sic_1m_full_size(orc, sic_model):
+@pytest.fixture(scope="module")
+def sic1m(orc):
     """SiC zincblende 50^3 cells = 1,000,000 atoms, 10 % antisites, sigma 0.1,
-    mixed precision (skin 0.5)."""
+    skin 0.5, with oracle references (32 sampled atoms for the forces)."""
     x, t, box = inputs.sic_bulk(50)
     tab = params.sic()
     nl = orc.neighbours(x, box, 3.0 + 0.5)
     sample = np.random.default_rng(9).choice(len(x), size=32, replace=False)
     fs, es = orc.forces_on(x, t, box, tab, sample, nlist=nl)
-    eref, _, _, _ = orc.compute(x, t, box, tab, nlist=nl)
-    e, f, w, ea = gpu_eval(sic_model, x, t, box, 1, skin=0.5)
-    assert abs(e - eref) <= MIX_E_TOL * abs(eref)
-    assert _rel(f[sample], fs) <= MIX_F_TOL
-    e64, f64, _, _ = gpu_eval(sic_model, x, t, box, 0, skin=0.5)
-    assert abs(e64 - eref) <= FP64_TOL * abs(eref)
-    assert _rel(f64[sample], fs) <= FP64_TOL
+    eref, _, wref, _ = orc.compute(x, t, box, tab, nlist=nl)
+    return x, t, box, sample, fs, es, eref, wref
+
+
+# the wavefront schedule with 24 atoms per wavefront is the autotuner's pick
+@pytest.mark.parametrize("kernel,atoms", [(1, 0), (2, 24)], ids=["workgroup", "wave24"])
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
+def test_sic_1m_full_size(sic1m, sic_model, precision, kernel, atoms):
+    """1,000,000-atom SiC in the benchmark's launch configuration."""
+    x, t, box, sample, fs, es, eref, wref = sic1m
+    sic_model.set_schedule(kernel, atoms, 0)
+    try:
+        e, f, w, ea = gpu_eval(sic_model, x, t, box, precision, skin=0.5)
+    finally:
+        sic_model.set_schedule(0, 0, 0)
+    tol_f = FP64_TOL if precision == 0 else MIX_F_TOL
+    if precision == 0:
+        assert abs(e - eref) <= FP64_TOL * abs(eref)
+    else:
+        assert mixed_energy_ok(e, eref, len(x), "SiC 1M")
+    assert _rel(f[sample], fs) <= tol_f
+    assert _rel(ea[sample], es) <= tol_f
+    assert _rel(w, wref) <= tol_f
+    assert np.linalg.norm(f.sum(0)) <= 1e-9 * len(x) ** 0.5
 
 
 @pytest.mark.parametrize("kernel", [1, 2])
@@ -358,7 +438,6 @@ def test_filter_off_gives_the_same_result(orc, sic_model, precision):
     oracle's bars: the filter changes the speed, not the result."""
     x, t, box = inputs.sic_liquid_batch(nconf=1, nmin=700, nmax=1500, seed=101)[0]
     ref = orc.compute(x, t, box, params.sic())
-    scale = energy_scale(orc, x, t, box, params.sic())
     sic_model.set_schedule(2, 16, 0)
     sic_model.set_filter(False)
     try:
@@ -372,7 +451,7 @@ def test_filter_off_gives_the_same_result(orc, sic_model, precision):
     finally:
         sic_model.set_filter(True)
         sic_model.set_schedule(0, 0, 0)
-    _check(got, ref, precision, escale=scale)
+    _check(got, ref, precision)
 
 
 @pytest.mark.parametrize("skin", [0.0, 0.5])

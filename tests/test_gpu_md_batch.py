@@ -143,16 +143,100 @@ def test_batch_forward_matches_oracle(orc, batch_setup, precision):
     model.sync()
     e, f, w = e.cpu().numpy(), f.cpu().numpy(), w.cpu().numpy()
     off = plan.offsets
-    from test_gpu_forward import energy_scale
-    tol_e, tol_f = (1e-12, 1e-12) if precision == 0 else (1e-7, 1e-5)
+    _check_batch(orc, confs, off, e, f, w, precision)
+    plan.close()
+
+
+def _check_batch(orc, confs, off, e, f, w, precision):
+    """Every configuration against the oracle: FP64 1e-12; mixed forces and
+    virial 1e-5 and the mixed energy bar of the forward tests."""
+    from test_gpu_forward import mixed_energy_ok
+    tol_f = 1e-12 if precision == 0 else 1e-5
     for c, (xc, tc, bc) in enumerate(confs):
         er, fr, wr, ear = orc.compute(xc, tc, bc, params.sic())
-        # FP64: relative to |E|; mixed: relative to E_rep - E_att (see energy_scale)
-        scale = abs(er) if precision == 0 else energy_scale(orc, xc, tc, bc, params.sic())
-        assert abs(e[c] - er) <= tol_e * scale, (c, e[c], er)
+        if precision == 0:
+            assert abs(e[c] - er) <= 1e-12 * abs(er), (c, e[c], er)
+        else:
+            assert mixed_energy_ok(e[c], er, len(tc), "config %d (%d atoms)" % (c, len(tc))), c
         fc = f[off[c]:off[c + 1]]
         assert np.linalg.norm(fc - fr) <= tol_f * np.linalg.norm(fr), c
         assert np.linalg.norm(w[c] - wr) <= tol_f * np.linalg.norm(wr), c
+
+
+def _run_plan(model, confs, precision, adjoint=False, seed=3):
+    from paper_1607_02904_amd.tersoff import BatchPlan
+    nat, boxes, x, t = _cat(confs)
+    plan = BatchPlan(model, nat, boxes, precision=precision)
+    N = int(nat.sum())
+    xd = torch.as_tensor(x, device="cuda")
+    td = torch.as_tensor(t, device="cuda")
+    e = torch.empty(len(confs), dtype=torch.float64, device="cuda")
+    f = torch.empty((N, 3), dtype=torch.float64, device="cuda")
+    w = torch.empty((len(confs), 6), dtype=torch.float64, device="cuda")
+    args = [xd, td, e, f, w]
+    if adjoint:
+        g = torch.Generator("cuda").manual_seed(seed)
+        eb = torch.rand(len(confs), dtype=torch.float64, device="cuda", generator=g) * 1e-3
+        fb = torch.randn((N, 3), dtype=torch.float64, device="cuda", generator=g) * 0.1
+        xg = torch.empty_like(f)
+        pg = torch.empty((2, 2, 2, 14), dtype=torch.float64, device="cuda")
+        args += [eb, fb, xg, pg]
+    plan.run(*args)
+    torch.cuda.synchronize()
+    model.sync()
+    return plan, args
+
+
+def test_batch_extreme_sizes(orc, batch_setup):
+    """Configurations of 4,096 atoms (the largest of the batched workload) and
+    of 64 atoms in the smallest boxes (about 6-9 A a side, one cell per axis)
+    in one batch, FP64 and mixed, in the launch configuration the plan's
+    autotuner picks."""
+    _, model = batch_setup
+    confs = (inputs.sic_liquid_batch(nconf=2, nmin=4096, nmax=4096, seed=60)
+             + inputs.sic_liquid_batch(nconf=6, nmin=64, nmax=64, seed=61)
+             + inputs.sic_liquid_batch(nconf=4, nmin=64, nmax=4096, seed=62))
+    assert min(np.min(c[2]) for c in confs) < 8.0
+    for precision in (0, 1):
+        plan, (xd, td, e, f, w) = _run_plan(model, confs, precision)
+        print("batch extreme sizes, precision %d: schedule %s" % (precision, plan.schedule()))
+        _check_batch(orc, confs, plan.offsets, e.cpu().numpy(), f.cpu().numpy(),
+                     w.cpu().numpy(), precision)
+        plan.close()
+
+
+def test_batch_mixed_adjoint_matches_single_calls(batch_setup):
+    """The batched mixed forward + adjoint (the benchmark's batched figure, in
+    the plan's autotuned schedule) equals per-configuration calls of the
+    single-system entry points in the same schedule."""
+    confs, model = batch_setup
+    plan, args = _run_plan(model, confs, 1, adjoint=True)
+    xd, td, e, f, w, eb, fb, xg, pg = args
+    sch = plan.schedule()
+    print("batched mixed adjoint schedule:", sch)
+    off = plan.offsets
+    pg_sum = np.zeros((2, 2, 2, 14))
+    xg_all = xg.cpu().numpy()
+    model.set_schedule(sch["kernel"], sch["atoms"], 0)
+    try:
+        worst = 0.0
+        for c, (xc, tc, bc) in enumerate(confs):
+            xcd = torch.as_tensor(xc, device="cuda")
+            tcd = torch.as_tensor(tc, device="cuda")
+            model.build_nlist(xcd, tcd, bc, 0.0)
+            xgc, pgc = model.backward(xcd, tcd, bc, float(eb[c].item()),
+                                      fb[off[c]:off[c + 1]].contiguous(), 1)
+            torch.cuda.synchronize()
+            pg_sum += pgc.cpu().numpy()
+            a, b = xg_all[off[c]:off[c + 1]], xgc.cpu().numpy()
+            rel = np.linalg.norm(a - b) / np.linalg.norm(b)
+            worst = max(worst, rel)
+            assert rel <= 1e-6, (c, rel)
+    finally:
+        model.set_schedule(0, 0, 0)
+    relp = np.linalg.norm(pg.cpu().numpy() - pg_sum) / np.linalg.norm(pg_sum)
+    print("batched vs single mixed adjoint: x %.2e, params %.2e" % (worst, relp))
+    assert relp <= 1e-6
     plan.close()
 
 
@@ -252,3 +336,30 @@ def test_long_run_total_energy_tracks_fp64(si_model, precision):
     for e in (e64, emx):
         assert np.max(np.abs(e - e[0])) / n < 1e-3
         assert (e[1:].max() - e[1:].min()) / n < 1e-4
+
+
+def test_batch_run_reports_list_overflow(batch_setup):
+    """A plan sizes its list on its first run; a later run whose atoms are
+    packed more densely overflows the rows.  The graph latches the error in
+    the plan's error word and ters_sync reports it (TERS_ERR_NLIST_OVERFLOW);
+    the word is cleared once read, and a run at the original density is
+    clean again."""
+    from paper_1607_02904_amd.tersoff import TersoffError
+    confs, model = batch_setup
+    confs = confs[:6]
+    plan, (xd, td, e, f, w) = _run_plan(model, confs, 0)
+    model.sync()
+    nat, boxes, x, t = _cat(confs)
+    off = plan.offsets
+    xs = x.copy()
+    for c in range(len(confs)):  # pack every configuration into 70 % of its box
+        xs[off[c]:off[c + 1]] = 0.7 * inputs.wrap(x[off[c]:off[c + 1]], boxes[c])
+    xd.copy_(torch.as_tensor(xs, device="cuda"))
+    plan.run(xd, td, e, f, w)
+    with pytest.raises(TersoffError) as ei:
+        model.sync()
+    assert ei.value.name == "TERS_ERR_NLIST_OVERFLOW"
+    xd.copy_(torch.as_tensor(x, device="cuda"))
+    plan.run(xd, td, e, f, w)
+    model.sync()
+    plan.close()
