@@ -137,6 +137,31 @@ ters_status ters_compute(ters_ctx *ctx, int32_t n, const double *x, const int32_
                          const double *box, int precision, uint32_t flags, double *energy,
                          double *forces, double *virial, double *e_atom);
 
+/* ---- the same without allocation ------------------------------------------
+ * For callers that cannot allocate device memory at call time: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * One call builds the neighbour list (skin 0) of the n atoms and evaluates
+ * them like ters_build_nlist followed by ters_compute (same kernels, the
+ * context's schedule and force mode), with every work buffer (cell bins,
+ * list of at most TERS_STATIC_CAP entries per atom, reverse map, force slots,
+ * partial sums) in one static device array of the library, of fixed size
+ * (about 20 MB), that each GPU holds from the first ters_create on it until
+ * the process ends.  It calls no hipMalloc, hipFree or other allocating
+ * routine and does not synchronise.  Limits: n <= TERS_STATIC_MAX_ATOMS
+ * (TERS_ERR_UNSUPPORTED beyond); at most TERS_STATIC_CAP list entries per
+ * atom, else TERS_ERR_NLIST_OVERFLOW is latched and reported by ters_sync
+ * (the outputs are then not valid); along an axis with many cells, larger
+ * cells are used (results unchanged).  Every call on one GPU shares that
+ * GPU's array, so calls that overlap in time on one GPU (two streams, two
+ * contexts, two host threads) race and must be serialised by the caller.
+ * Arguments, outputs and flags as ters_compute (TERS_PARAM_GRAD refused);
+ * it does not touch the context's own list. */
+#define TERS_STATIC_MAX_ATOMS 16384
+#define TERS_STATIC_CAP 32
+ters_status ters_compute_static(ters_ctx *ctx, int32_t n, const double *x, const int32_t *type,
+                                const double *box, int precision, uint32_t flags, double *energy,
+                                double *forces, double *virial, double *e_atom);
+
 /* As ters_compute, plus with TERS_PARAM_GRAD the derivative of E with
  * respect to every table entry: param_grad device [ntypes^3][14], accumulated
  * into (the caller zeroes it unless accumulating on purpose). */

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -164,6 +165,7 @@ void nl_setup(NList &nl, int nconf, const int32_t *natoms, const double *boxes, 
   nl.rlist = rlist;
   nl.skin = skin;
   nl.conf_h.resize(nconf);
+  nl.box_max = 0.0;
   int64_t cells = 0, atoms = 0;
   for (int c = 0; c < nconf; ++c) {
     ConfDesc d{};
@@ -180,6 +182,7 @@ void nl_setup(NList &nl, int nconf, const int32_t *natoms, const double *boxes, 
     d.cell_off = (int32_t)cells;
     d.atom_off = (int32_t)atoms;
     d.natoms = natoms[c];
+    nl.box_max = std::max({nl.box_max, d.box[0], d.box[1], d.box[2]});
     cells += (int64_t)d.nc[0] * d.nc[1] * d.nc[2];
     atoms += natoms[c];
     nl.conf_h[c] = d;
@@ -371,6 +374,63 @@ int run_forward(ters_ctx *c, const FwdArgs &a0, int precision, hipStream_t s,
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// static scratch of ters_compute_static (no allocation at call time)
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int kStaticCap = TERS_STATIC_CAP;   // list entries per atom
+constexpr int64_t kStaticCells = 32768;       // most cells of the binning grid
+constexpr size_t kAlign = 256;
+constexpr size_t al(size_t b) { return (b + kAlign - 1) / kAlign * kAlign; }
+constexpr size_t kN = TERS_STATIC_MAX_ATOMS;
+// bytes of every scratch buffer at the largest size (layout of carve_static)
+constexpr size_t kStaticBytes =
+    al(sizeof(ConfDesc)) + 5 * al(4 * kN) + al(4 * (kN + 1)) + 2 * al(4 * kN * kStaticCap) +
+    2 * al(4 * (kStaticCells + 1)) + al(4 * ((kStaticCells + 1) / 1024 + 2)) + al(24 * kN) +
+    al(16 * kN) + al(4 * 2 * 4096) + al(4) + al(64 * kN) + al(24 * kN * kStaticCap) + al(24 * kN);
+
+// One copy per GPU, held until the process ends.  In host code this name is
+// only a stand-in: kernels get the device address from hipGetSymbolAddress.
+__device__ __align__(256) unsigned char scratch[kStaticBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch[kMaxDevices] = {};
+
+// device address of this device's scratch copy (the device is current)
+void scratch_init(int device) {
+  require(device >= 0 && device < kMaxDevices, TERS_ERR_UNSUPPORTED, "device index too large");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch[device]) return;
+  void *ptr = nullptr;
+  TERS_HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+  require(ptr != nullptr, TERS_ERR_HIP, "no device address for the static scratch");
+  g_scratch[device] = ptr;
+}
+
+void *scratch_of(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return (device >= 0 && device < kMaxDevices) ? g_scratch[device] : nullptr;
+}
+
+// DevBuf views into the scratch (never released: DevBuf frees only on release())
+struct Carver {
+  unsigned char *base;
+  size_t off = 0;
+  DevBuf take(size_t bytes) {
+    DevBuf b;
+    b.p = base + off;
+    b.bytes = bytes;
+    off += al(bytes);
+    return b;
+  }
+};
+
+__global__ void k_put_conf(ConfDesc d, ConfDesc *dst) { *dst = d; }
+
+}  // namespace
+
 extern "C" {
 
 const char *ters_version(void) { return kVersion; }
@@ -389,6 +449,7 @@ ters_status ters_create(ters_ctx **out, int device, void *stream) {
     c->flag.ensure(64);
     c->rebuilds.ensure(64);
     c->step.ensure(64);
+    scratch_init(device);     // the static scratch of ters_compute_static on this device
     c->escratch.ensure(256);  // energy, per-workgroup energy sums, completion counter
     TERS_HIP_TRY(hipMemsetAsync(c->escratch.p, 0, 256, c->stream));
     TERS_HIP_TRY(hipMemsetAsync(c->errw.p, 0, 64, c->stream));
@@ -649,6 +710,119 @@ ters_status ters_compute(ters_ctx *c, int32_t n, const double *x, const int32_t 
                          double *forces, double *virial, double *e_atom) {
   return ters_compute_ex(c, n, x, type, box, precision, flags & ~TERS_PARAM_GRAD, energy, forces,
                          virial, e_atom, nullptr);
+}
+
+ters_status ters_compute_static(ters_ctx *c, int32_t n, const double *x, const int32_t *type,
+                                const double *box, int precision, uint32_t flags, double *energy,
+                                double *forces, double *virial, double *e_atom) {
+  if (!c) return TERS_ERR_INVALID_ARG;
+  return guard(c, [&]() {
+    require(c->ntypes > 0, TERS_ERR_PARAMS, "parameters not set");
+    require(precision >= TERS_FP64 && precision <= TERS_SINGLE, TERS_ERR_INVALID_ARG, "bad precision");
+    require(!(flags & TERS_PARAM_GRAD), TERS_ERR_UNSUPPORTED, "no parameter gradient here");
+    require(n >= 0 && box && (n == 0 || (x && type)), TERS_ERR_INVALID_ARG, "bad arguments");
+    require(n <= TERS_STATIC_MAX_ATOMS, TERS_ERR_UNSUPPORTED,
+            "n exceeds the static scratch (at most TERS_STATIC_MAX_ATOMS = 16384 atoms)");
+    require(!(flags & TERS_ENERGY) || energy, TERS_ERR_INVALID_ARG, "energy output missing");
+    require(!(flags & TERS_FORCES) || forces || n == 0, TERS_ERR_INVALID_ARG, "forces output missing");
+    require(!(flags & TERS_VIRIAL) || virial, TERS_ERR_INVALID_ARG, "virial output missing");
+    require(!(flags & TERS_PER_ATOM_E) || e_atom || n == 0, TERS_ERR_INVALID_ARG,
+            "per-atom energy output missing");
+    unsigned char *base = (unsigned char *)scratch_of(c->device);
+    require(base != nullptr, TERS_ERR_HIP, "static scratch not initialised on this device");
+    // geometry: cells of side >= r_list; along an axis with more cells than the
+    // scratch holds, fewer and larger cells (still >= r_list, still correct)
+    const double rlist = c->rc_max;
+    ConfDesc d{};
+    int64_t cells = 1;
+    for (int a = 0; a < 3; ++a) {
+      const double L = box[a];
+      require(std::isfinite(L) && L > 0.0, TERS_ERR_INVALID_ARG, "box sides must be finite and > 0");
+      require(L >= 2.0 * rlist, TERS_ERR_BOX_TOO_SMALL,
+              "box side below twice the list cutoff (minimum image)");
+      d.box[a] = L;
+      d.inv_box[a] = 1.0 / L;
+      const int k = (int)std::floor(L / rlist);
+      d.nc[a] = k >= 3 ? k : 1;
+    }
+    for (;;) {
+      cells = (int64_t)d.nc[0] * d.nc[1] * d.nc[2];
+      if (cells <= kStaticCells) break;
+      int a = 0;  // halve the longest axis (keeping 1 or >= 3 cells)
+      for (int b = 1; b < 3; ++b)
+        if (d.nc[b] > d.nc[a]) a = b;
+      d.nc[a] = d.nc[a] / 2 >= 3 ? d.nc[a] / 2 : 1;
+    }
+    d.cell_off = 0;
+    d.atom_off = 0;
+    d.natoms = n;
+    // the list and every work buffer are views of the scratch (layout of kStaticBytes)
+    NList nl;
+    Carver cv{base};
+    const size_t N = kN;
+    nl.conf = cv.take(sizeof(ConfDesc));
+    nl.count = cv.take(4 * N);
+    nl.order = cv.take(4 * N);
+    nl.cell_of = cv.take(4 * N);
+    nl.pos = cv.take(4 * N);
+    nl.loff = cv.take(4 * N);
+    nl.soff = cv.take(4 * (N + 1));
+    nl.list = cv.take(4 * N * kStaticCap);
+    nl.rev = cv.take(4 * N * kStaticCap);
+    nl.cell_count = cv.take(4 * (kStaticCells + 1));
+    nl.cell_start = cv.take(4 * (kStaticCells + 1));
+    nl.scan_tmp = cv.take(4 * ((kStaticCells + 1) / 1024 + 2));
+    nl.xref = cv.take(24 * N);
+    nl.xs = cv.take(16 * N);
+    nl.bsum = cv.take(4 * 2 * 4096);
+    nl.maxcount = cv.take(4);
+    DevBuf partials = cv.take(64 * N);
+    DevBuf fslot = cv.take(24 * N * kStaticCap);
+    DevBuf fown = cv.take(24 * N);
+    if (cv.off > kStaticBytes) fail(TERS_ERR_HIP, "static scratch layout exceeds its size");
+    nl.n = n;
+    nl.cap = kStaticCap;
+    nl.nconf = 1;
+    nl.ncell = cells;
+    nl.rlist = rlist;
+    nl.skin = 0.0;
+    nl.valid = true;
+    nl.box_max = std::max({d.box[0], d.box[1], d.box[2]});
+    hipStream_t s = c->stream;
+    k_put_conf<<<1, 1, 0, s>>>(d, nl.conf.as<ConfDesc>());
+    TERS_HIP_TRY(hipGetLastError());
+    // list build; errors (overflow beyond kStaticCap entries, non-finite
+    // positions, bad species) are latched in the context's error word
+    nlist_build(nl, x, type, c->ntypes, nullptr, c->errw.as<uint32_t>(), s);
+    // force evaluation in the context's schedule for this precision
+    const int kern = precision == TERS_SINGLE ? 2 : c->kern[precision];
+    const int A = sched_A(c, precision);
+    const int nb = kernel_blocks(kern, n, A);
+    require((size_t)std::max(nb, 1) * 64 <= partials.bytes, TERS_ERR_HIP, "partials exceed the scratch");
+    FwdArgs a = base_args(c, nl, precision, n, x, type);
+    a.flags = flags;
+    a.forces = (flags & TERS_FORCES) ? forces : nullptr;
+    a.e_atom = (flags & TERS_PER_ATOM_E) ? e_atom : nullptr;
+    a.partials = partials.as<double>();
+    a.err = c->errw.as<uint32_t>();
+    const bool gather = c->gather && a.forces && kern != 3;
+    if (gather) {
+      a.fslot = fslot.p;
+      a.fown = fown.as<double>();
+    } else if (a.forces && !(flags & TERS_ACCUMULATE)) {
+      launch_fill_f64(a.forces, 0.0, 3 * (int64_t)n, s);
+    }
+    launch_fwd(kern, a, precision, A, s);
+    if (gather)
+      launch_gather(nl, a.fslot, precision != TERS_FP64, a.fown, a.forces,
+                    (flags & TERS_ACCUMULATE) ? 1 : 0, s);
+    if (flags & (TERS_ENERGY | TERS_VIRIAL))
+      launch_reduce_partials(partials.as<double>(), nb, 8, (flags & TERS_ENERGY) ? energy : nullptr,
+                             (flags & TERS_VIRIAL) ? virial : nullptr,
+                             (flags & TERS_ACCUMULATE) ? 1 : 0, s);
+    TERS_HIP_TRY(hipGetLastError());
+    return TERS_OK;
+  });
 }
 
 ters_status ters_backward(ters_ctx *c, int32_t n, const double *x, const int32_t *type,

@@ -670,8 +670,7 @@ void nlist_build(NList &nl, const double *x, const int32_t *type, int ntypes, co
     // rounded by at most 2^-24 of the longest side, a squared distance by a
     // few units in the last place; the radius grows by a bound of both, so no
     // pair within r_list is missed (the filter applies the exact cutoffs)
-    double lmax = 0.0;
-    for (const ConfDesc &d : nl.conf_h) lmax = std::max({lmax, d.box[0], d.box[1], d.box[2]});
+    const double lmax = nl.box_max;
     const double rl = nl.rlist + 8.0 * std::ldexp(lmax, -24) + std::ldexp(nl.rlist, -18);
     k_build<<<gb, kBS, 0, s>>>(n, nl.xs.as<float4>(), conf, conf_of, nl.order.as<int32_t>(),
                                nl.cell_of.as<int32_t>(), cell_start, (float)(rl * rl), nl.cap,

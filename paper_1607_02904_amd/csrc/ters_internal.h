@@ -76,6 +76,7 @@ struct NList {
   int32_t n = 0, cap = 0, nconf = 0;
   int64_t ncell = 0;
   double rlist = 0.0, skin = 0.0;
+  double box_max = 0.0;  // longest box side of the set (rounding margin of the FP32 build)
   bool valid = false;
   std::vector<ConfDesc> conf_h;
   DevBuf conf;        // ConfDesc[nconf]

@@ -34,7 +34,7 @@ EXPORTS = ("ters_create", "ters_destroy", "ters_set_stream", "ters_sync", "ters_
            "ters_md_rebuilds",
            "ters_batch_plan", "ters_batch_run", "ters_plan_destroy", "ters_plan_schedule",
            "ters_set_schedule", "ters_get_schedule", "ters_set_force_mode", "ters_set_filter", "ters_autotune",
-           "ters_profile_forward", "ters_pair_compute",
+           "ters_profile_forward", "ters_pair_compute", "ters_compute_static",
            "ters_table_sic",
            "ters_table_element", "ters_version")
 
@@ -70,6 +70,7 @@ def load_library(path=LIB_PATH):
         "ters_nlist_stats": [P, P],
         "ters_compute": [P, I32, P, P, P, ctypes.c_int, U32, P, P, P, P],
         "ters_compute_ex": [P, I32, P, P, P, ctypes.c_int, U32, P, P, P, P, P],
+        "ters_compute_static": [P, I32, P, P, P, ctypes.c_int, U32, P, P, P, P],
         "ters_backward": [P, I32, P, P, P, ctypes.c_int, D, P, P, P],
         "ters_md_run": [P, I32, P, P, P, P, P, D, I32, D, ctypes.c_int, P, ctypes.c_int],
         "ters_md_run_timed": [P, I32, P, P, P, P, P, D, I32, D, ctypes.c_int, P, P],
@@ -297,6 +298,29 @@ class Tersoff:
                                           _ptr(o.get("virial"), name="virial", rows=6),
                                           _ptr(o.get("e_atom"), name="e_atom", rows=n),
                                           _ptr(o.get("param_grad"), name="param_grad")))
+        return o
+
+    def compute_static(self, x, types, box, precision=FP64, out=None, per_atom=False):
+        """ters_compute_static: list build and evaluation in one call with no
+        device allocation inside the library (outputs as compute(); the
+        caller may pass preallocated ones in `out`)."""
+        self._bind_stream()
+        n = x.shape[0]
+        dev = x.device
+        o = dict(out or {})
+        o.setdefault("energy", torch.empty(1, dtype=torch.float64, device=dev))
+        o.setdefault("forces", torch.empty((n, 3), dtype=torch.float64, device=dev))
+        o.setdefault("virial", torch.empty(6, dtype=torch.float64, device=dev))
+        flags = ENERGY | FORCES | VIRIAL
+        if per_atom:
+            flags |= PER_ATOM_E
+            o.setdefault("e_atom", torch.empty(n, dtype=torch.float64, device=dev))
+        b, bp = _hostbuf(box, np.float64)
+        self._chk(self._L.ters_compute_static(self._h, n, _pos(x), _types(types, n), bp, precision,
+                                              flags, _ptr(o["energy"], name="energy", rows=1),
+                                              _ptr(o["forces"], name="forces", rows=n, cols=3),
+                                              _ptr(o["virial"], name="virial", rows=6),
+                                              _ptr(o.get("e_atom"), name="e_atom", rows=n)))
         return o
 
     def pair_compute(self, x, box, eps, sigma, rc, precision=FP64):
