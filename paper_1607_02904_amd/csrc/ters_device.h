@@ -70,25 +70,148 @@ template <class B> DEV Dual<B> rcp(Dual<B> a) { B r = rcp(a.v); return {r, -a.d 
 template <class B> DEV Dual<B> operator/(Dual<B> a, Dual<B> b) { return a * rcp(b); }
 template <class B> DEV Dual<B> operator/(Dual<B> a, B b) { return {a.v / b, a.d / b}; }
 
-DEV double t_exp(double a) { return exp(a); }
+// ---------------------------------------------------------------------------
+// Elementary functions on the ranges the kernels need, written out from their
+// series (host and device).  The general-purpose library versions carry
+// range reductions and special cases these arguments never need: FP64 log
+// and log1p and FP32 log1p cost about a hundred instructions each, sin and
+// cos over a hundred with their large-argument reduction.
+// ---------------------------------------------------------------------------
+#define HDEV __host__ __device__ __forceinline__
+
+// ln 2 split so that k * kLn2Hi is exact for |k| < 2^21 (Cody and Waite)
+constexpr double kLn2Hi = 0.6931471803691238;
+constexpr double kLn2Lo = 1.9082149292705877e-10;
+constexpr double kLn2 = 0.6931471805599453;
+constexpr double kLog2e = 1.4426950408889634;
+constexpr double kSqrtHalf = 0.7071067811865476;
+constexpr double kSqrt2m1 = 0.41421356237309503;
+
+// e^x (FP64): x = k ln 2 + f with |f| <= ln(2)/2, e^f from its Taylor series
+// to f^13/13! (truncation below 5e-18 relative), then scaled by 2^k.
+// Arguments beyond the FP64 range give 0 or infinity.
+HDEV double exp_d(double x) {
+  x = fmin(fmax(x, -746.0), 710.0);
+  const double k = rint(x * kLog2e);
+  double f = fma(-k, kLn2Hi, x);
+  f = fma(-k, kLn2Lo, f);
+  double p = 1.0 / 6227020800.0;       // 1/13!
+  p = fma(p, f, 1.0 / 479001600.0);    // 1/12!
+  p = fma(p, f, 1.0 / 39916800.0);
+  p = fma(p, f, 1.0 / 3628800.0);
+  p = fma(p, f, 1.0 / 362880.0);
+  p = fma(p, f, 1.0 / 40320.0);
+  p = fma(p, f, 1.0 / 5040.0);
+  p = fma(p, f, 1.0 / 720.0);
+  p = fma(p, f, 1.0 / 120.0);
+  p = fma(p, f, 1.0 / 24.0);
+  p = fma(p, f, 1.0 / 6.0);
+  p = fma(p, f, 0.5);
+  p = fma(p, f, 1.0);
+  p = fma(p, f, 1.0);
+  return ldexp(p, (int)k);
+}
+
+// 2 atanh(s) = ln((1 + s)/(1 - s)) for |s| <= 3 - 2 sqrt(2) (about 0.1716):
+// 2 (s + s^3/3 + ... + s^21/21), truncation below 1e-18 relative (FP64);
+// to s^9/9 in FP32 (below 3e-9 relative)
+HDEV double two_atanh_d(double s) {
+  const double z = s * s;
+  double p = 1.0 / 21.0;
+  p = fma(p, z, 1.0 / 19.0);
+  p = fma(p, z, 1.0 / 17.0);
+  p = fma(p, z, 1.0 / 15.0);
+  p = fma(p, z, 1.0 / 13.0);
+  p = fma(p, z, 1.0 / 11.0);
+  p = fma(p, z, 1.0 / 9.0);
+  p = fma(p, z, 1.0 / 7.0);
+  p = fma(p, z, 1.0 / 5.0);
+  p = fma(p, z, 1.0 / 3.0);
+  const double s2 = s + s;
+  return fma(s2 * z, p, s2);
+}
+HDEV float two_atanh_f(float s) {
+  const float z = s * s;
+  float p = 1.0f / 9.0f;
+  p = fmaf(p, z, 1.0f / 7.0f);
+  p = fmaf(p, z, 1.0f / 5.0f);
+  p = fmaf(p, z, 1.0f / 3.0f);
+  const float s2 = s + s;
+  return fmaf(s2 * z, p, s2);
+}
+
+// ln x (FP64) for finite x > 0 (normal): x = m 2^e with m in [1/sqrt(2), sqrt(2)),
+// ln m = 2 atanh((m - 1)/(m + 1)), ln x = e ln 2 + ln m
+HDEV double log_d(double x) {
+  int e;
+  double m = frexp(x, &e);  // [0.5, 1)
+  if (m < kSqrtHalf) {
+    m += m;
+    e -= 1;
+  }
+  const double t = two_atanh_d((m - 1.0) / (m + 1.0));
+  const double de = (double)e;
+  return fma(de, kLn2Hi, fma(de, kLn2Lo, t));
+}
+
+// ln(1 + y) for 0 <= y <= 1 from y itself (1 + y is never rounded): below
+// sqrt(2) - 1, 2 atanh(y / (2 + y)); above, ln 2 + 2 atanh((y - 1)/(y + 3))
+HDEV double log1p01_d(double y) {
+  const bool big = y > kSqrt2m1;
+  const double num = big ? y - 1.0 : y;
+  const double den = big ? y + 3.0 : y + 2.0;
+  return (big ? kLn2 : 0.0) + two_atanh_d(num / den);
+}
+
+// sin w for 0 <= w <= pi/2 from its Taylor series: to w^21/21! in FP64
+// (truncation below 2e-18), to w^13/13! in FP32 (below 7e-10)
+HDEV double sin_q_d(double w) {
+  const double z = w * w;
+  double p = -1.0 / 51090942171709440000.0;  // -1/21!
+  p = fma(p, z, 1.0 / 121645100408832000.0);  // 1/19!
+  p = fma(p, z, -1.0 / 355687428096000.0);    // -1/17!
+  p = fma(p, z, 1.0 / 1307674368000.0);       // 1/15!
+  p = fma(p, z, -1.0 / 6227020800.0);         // -1/13!
+  p = fma(p, z, 1.0 / 39916800.0);            // 1/11!
+  p = fma(p, z, -1.0 / 362880.0);             // -1/9!
+  p = fma(p, z, 1.0 / 5040.0);                // 1/7!
+  p = fma(p, z, -1.0 / 120.0);                // -1/5!
+  p = fma(p, z, 1.0 / 6.0);                   // 1/3!... with the sign below
+  // p now holds 1/3! - z/5! + ...; sin w = w - w z p
+  return fma(-w * z, p, w);
+}
+HDEV float sin_q_f(float w) {
+  const float z = w * w;
+  float p = -1.0f / 6227020800.0f;          // -1/13!
+  p = fmaf(p, z, 1.0f / 39916800.0f);       // 1/11!
+  p = fmaf(p, z, -1.0f / 362880.0f);        // -1/9!
+  p = fmaf(p, z, 1.0f / 5040.0f);           // 1/7!
+  p = fmaf(p, z, -1.0f / 120.0f);           // -1/5!
+  p = fmaf(p, z, 1.0f / 6.0f);              // 1/3!
+  return fmaf(-w * z, p, w);
+}
+
+DEV double t_exp(double a) { return exp_d(a); }
 DEV float t_exp(float a) { return expf(a); }
-DEV double t_log(double a) { return log(a); }
+DEV double t_log(double a) { return log_d(a); }
 DEV float t_log(float a) { return logf(a); }
-DEV double t_log1p(double a) { return log1p(a); }
-DEV float t_log1p(float a) { return log1pf(a); }
+// ln(1 + y), 0 <= y <= 1
+DEV double t_log1p01(double y) { return log1p01_d(y); }
+DEV float t_log1p01(float y) {
+  const bool big = y > (float)kSqrt2m1;
+  const float num = big ? y - 1.0f : y;
+  const float den = big ? y + 3.0f : y + 2.0f;
+  return (big ? (float)kLn2 : 0.0f) + two_atanh_f(num * rcp(den));
+}
 DEV double t_sqrt(double a) { return sqrt(a); }
 DEV float t_sqrt(float a) { return sqrtf(a); }
-DEV double t_sin(double a) { return sin(a); }
-DEV float t_sin(float a) { return sinf(a); }
-DEV double t_cos(double a) { return cos(a); }
-DEV float t_cos(float a) { return cosf(a); }
+DEV double t_sin_q(double w) { return sin_q_d(w); }
+DEV float t_sin_q(float w) { return sin_q_f(w); }
 
 template <class B> DEV Dual<B> t_exp(Dual<B> a) { B e = t_exp(a.v); return {e, a.d * e}; }
 template <class B> DEV Dual<B> t_log(Dual<B> a) { return {t_log(a.v), a.d * rcp(a.v)}; }
-template <class B> DEV Dual<B> t_log1p(Dual<B> a) { return {t_log1p(a.v), a.d * rcp(B(1) + a.v)}; }
+template <class B> DEV Dual<B> t_log1p01(Dual<B> a) { return {t_log1p01(a.v), a.d * rcp(B(1) + a.v)}; }
 template <class B> DEV Dual<B> t_sqrt(Dual<B> a) { B s = t_sqrt(a.v); return {s, a.d * B(0.5) * rcp(s)}; }
-template <class B> DEV Dual<B> t_sin(Dual<B> a) { return {t_sin(a.v), a.d * t_cos(a.v)}; }
-template <class B> DEV Dual<B> t_cos(Dual<B> a) { return {t_cos(a.v), -a.d * t_sin(a.v)}; }
 
 // conversion of an FP64 value (with optional FP64 tangent) to the compute type
 template <class T> struct Conv;

@@ -12,6 +12,30 @@
 
 namespace ters {
 
+template <class T> struct Zero { static DEV T get() { return T(base_t<T>(0)); } };
+
+// The switch between R - D and R + D, written with w = pi (R + D - r) / (4D)
+// and v = pi (r - R + D) / (4D) (w + v = pi/2, both in [0, pi/2]):
+//   f_C = 1/2 - 1/2 sin(pi (r - R) / (2D)) = sin^2 w,
+//   f_C' = -pi/(4D) cos(pi (r - R) / (2D)) = -pi/(2D) sin w sin v,
+// each sine taken near its own zero, so f_C keeps its relative accuracy up
+// to R + D and f_C' up to R - D.  arg = pi (r - R) / (2D) is given.
+template <class B> DEV void switch_of(B arg, B pi4d, B &fc, B &dfc) {
+  const B q = B(0.78539816339744831);  // pi/4
+  const B sw = t_sin_q(q - B(0.5) * arg), sv = t_sin_q(q + B(0.5) * arg);
+  fc = sw * sw;
+  dfc = -B(2) * pi4d * (sw * sv);
+}
+template <class B> DEV void switch_of(Dual<B> arg, B pi4d, Dual<B> &fc, Dual<B> &dfc) {
+  B f, df;
+  switch_of(arg.v, pi4d, f, df);
+  // d f_C / d arg = -1/2 cos(arg) = df / (2 pi4d); d f_C' / d arg = pi4d sin(arg)
+  const B q = B(0.78539816339744831);
+  const B sw = t_sin_q(q - B(0.5) * arg.v), sv = t_sin_q(q + B(0.5) * arg.v);
+  fc = {f, arg.d * df * (B(0.5) / pi4d)};
+  dfc = {df, arg.d * pi4d * (sv * sv - sw * sw)};
+}
+
 // f_C and f_C' (sine switch from 1 at R-D to 0 at R+D)
 template <class T, class B>
 DEV void fcut(const KParam<B> &p, T r, T &fc, T &dfc) {
@@ -24,8 +48,7 @@ DEV void fcut(const KParam<B> &p, T r, T &fc, T &dfc) {
     dfc = T(B(0));
   } else {
     T arg = mul_lo(p.pi2d, p.pi2d_lo, (r - p.R) - p.R_lo);
-    fc = B(0.5) - B(0.5) * t_sin(arg);
-    dfc = -p.pi4d * t_cos(arg);
+    switch_of(arg, p.pi4d, fc, dfc);
   }
 }
 
@@ -43,8 +66,7 @@ DEV void fcut64(const KParam<B> &p, T r, double r64, T &fc, T &dfc) {
   } else {
     T arg = r * p.pi2d;  // tangent part
     set_val(arg, (r64 - (double)p.R - (double)p.R_lo) * ((double)p.pi2d + (double)p.pi2d_lo));
-    fc = B(0.5) - B(0.5) * t_sin(arg);
-    dfc = -p.pi4d * t_cos(arg);
+    switch_of(arg, p.pi4d, fc, dfc);
   }
 }
 
@@ -63,16 +85,13 @@ DEV void bond(const KParam<B> &p, T z, T &b, T &db, T &dbeta, T &dn) {
   // s = n ln(beta zeta), with the residuals of n and beta entering in one FMA
   T lz = t_log(p.beta * z);
   T s = fma_lo(p.n, lz, p.n * p.lbeta_lo + p.n_lo * lz);
-  T l1p, w;  // ln(1 + y), y / (1 + y)
-  if (val(s) > B(0)) {
-    T em = t_exp(-s);
-    l1p = s + t_log1p(em);
-    w = rcp(B(1) + em);
-  } else {
-    T ep = t_exp(s);
-    l1p = t_log1p(ep);
-    w = ep * rcp(B(1) + ep);
-  }
+  // y = e^s: with e = e^-|s| (in (0, 1]), ln(1 + y) = max(s, 0) + ln(1 + e) and
+  // y / (1 + y) = (s > 0 ? 1 : e) / (1 + e); one path for every lane
+  const bool pos = val(s) > B(0);
+  const T em = t_exp(pos ? -s : s);
+  const T l1p = (pos ? s : Zero<T>::get()) + t_log1p01(em);
+  const T ri = rcp(B(1) + em);
+  const T w = pos ? ri : em * ri;  // ln(1 + y), y / (1 + y)
   b = t_exp(-mul_lo(p.inv2n, p.inv2n_lo, l1p));
   T bw = b * w;
   db = -B(0.5) * bw * rcp(z);
@@ -171,7 +190,6 @@ DEV T zeta_term(const KParam<B> &p, T rij, T rinv_ij, const T *u, T rik, T rinv_
 DEV double out_of(double c, double) { return c; }
 DEV double out_of(const Dual<double> &c, double ebar) { return ebar * c.v - c.d; }
 
-template <class T> struct Zero { static DEV T get() { return T(base_t<T>(0)); } };
 
 struct GradSlots {  // field index of each parameter partial
   static constexpr int three[8] = {FGAMMA, FC, FD, FH, FLAM3, FM, FR, FDC};
