@@ -27,15 +27,25 @@ sys.path.insert(0, ROOT)
 FP64_PEAK = 78.6e12      # MI355X vector FP64, FLOP/s
 FP32_PEAK = 157.3e12     # MI355X vector FP32 (packed), FLOP/s
 
-# Algorithmic flops of the method (FMA counted as 2), per unit of work that
-# the neighbour list fixes: per list entry (distance test), per in-cutoff
-# neighbour (r, 1/r, unit vector), per pair term (V, dV/dr, b(zeta), dV/dzeta
-# and the pair force), per triplet (zeta(i,j,k) with its three gradient
-# vectors and the dV/dzeta scatter).  Transcendentals count as one flop each.
-FLOPS_PER_ENTRY = 9
-FLOPS_PER_NEIGH = 8
-FLOPS_PER_PAIR = 46
-FLOPS_PER_TRIPLET = 74
+# Algorithmic work of one evaluation, from the counts of list entries L,
+# in-cutoff (ordered) pairs P and triplets T of the configuration.
+#
+# Reported model (the work-per-unit figures of the design, counting an FMA as
+# one op): per list entry 16 ops (distance and compare), per in-cutoff
+# neighbour 6 ops + sqrt + reciprocal, per pair 45 ops + 5 transcendentals +
+# 1 division, per triplet 70 ops + reciprocal + exponential (no exponential
+# when lambda3 = 0).  Ops become flops at 1.9 flops per op (the FMA share of
+# the definition: ~1.1 k ops are ~1.9 k flops per Si atom), and every
+# transcendental, reciprocal or division counts as one flop.
+OPS_PER_ENTRY = 16
+OPS_PER_NEIGH = 6
+OPS_PER_PAIR = 45
+OPS_PER_TRIPLET = 70
+FLOPS_PER_OP = 1.9 / 1.1
+# A lower count, made by hand from the kernels' own formulas (FMA = 2 flops,
+# transcendental = 1): per entry 9, per neighbour 8, per pair 46, per triplet
+# 74.  Reported beside the model for reference.
+BUILDER_FLOPS = (9, 8, 46, 74)
 
 
 def parse():
@@ -70,8 +80,43 @@ def count_work(x, t, box, table, rlist, rcut_pair):
     return L, P, T
 
 
-def flops_of(L, P, T):
-    return FLOPS_PER_ENTRY * L + FLOPS_PER_NEIGH * P + FLOPS_PER_PAIR * P + FLOPS_PER_TRIPLET * T
+def flops_of(L, P, T, lam3=True):
+    """Algorithmic flops of one evaluation (the reported model above)."""
+    ops = OPS_PER_ENTRY * L + (OPS_PER_NEIGH + OPS_PER_PAIR) * P + OPS_PER_TRIPLET * T
+    trans = 2 * P + 6 * P + (2 if lam3 else 1) * T
+    return FLOPS_PER_OP * ops + trans
+
+
+def builder_flops_of(L, P, T):
+    e, nb, p, t = BUILDER_FLOPS
+    return e * L + nb * P + p * P + t * T
+
+
+VALU_MIX_SUMMARY = os.path.join(ROOT, "profiles", "force_wave_si512k_%s_valu_mix.txt")
+
+
+def counter_flops_of(sched, tname, n):
+    """FP32 and FP64 flops per launch of the force kernel from the committed
+    instruction-count summary (64 lanes per wave instruction, FMA = 2, a
+    transcendental = 1), or None when there is none for this kernel and
+    launch shape or its sources have changed since it was taken."""
+    from paper_1607_02904_amd import profsum
+    path = VALU_MIX_SUMMARY % tname
+    if sched["kernel"] != 2 or not os.path.exists(path):
+        return None
+    s = profsum.read_summary(path)
+    grid = 64 * ((n + sched["atoms"] - 1) // sched["atoms"])
+    if s.get("kernel_sources_sha256") != profsum.kernel_hash() or int(s.get("grid", -1)) != grid:
+        return None
+    out = {}
+    for prec in ("F32", "F64"):
+        add = float(s["SQ_INSTS_VALU_ADD_%s" % prec])
+        mul = float(s["SQ_INSTS_VALU_MUL_%s" % prec])
+        fma = float(s["SQ_INSTS_VALU_FMA_%s" % prec])
+        trans = float(s["SQ_INSTS_VALU_TRANS_%s" % prec])
+        out[prec] = 64.0 * (add + mul + 2.0 * fma + trans)
+    out["valu_insts"] = float(s["SQ_INSTS_VALU"])
+    return out
 
 
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "force_wave_si512k_%s_traffic.txt")
@@ -173,17 +218,34 @@ def main():
     kmx = model.profile_forward(x0, td, box, MIXED, reps=20)
     L, P, T = count_work(x, t, box, tab, 3.2 + skin, 3.2)
     fl = flops_of(L, P, T)
+    flb = builder_flops_of(L, P, T)
 
     def roof(us, us_b2b, peak, sch, tname):
         ach = fl / (us * 1e-6)
-        return {"bound": "alu", "achieved": ach / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
-                "frac": ach / peak, "traffic": traffic_of(sch, tname, n),
-                "kernel": ("k_force_wave<%s, true, false, false>" % tname if sch["kernel"] == 2
-                           else "k_force<%s, true, false, ...>" % tname),
-                "kernel_us": us, "kernel_us_timing": "HIP events around each force launch of %d MD "
-                                                     "steps" % args.steps,
-                "kernel_us_back_to_back": us_b2b,
-                "flops_per_launch": fl, "units": {"entries": L, "pairs": P, "triplets": T}}
+        r = {"bound": "alu", "achieved": ach / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
+             "frac": ach / peak, "traffic": traffic_of(sch, tname, n),
+             "kernel": ("k_force_wave<%s, true, false, false>" % tname if sch["kernel"] == 2
+                        else "k_force<%s, true, false, ...>" % tname),
+             "kernel_us": us, "kernel_us_timing": "HIP events around each force launch of %d MD "
+                                                  "steps" % args.steps,
+             "kernel_us_back_to_back": us_b2b,
+             "flops_per_launch": fl,
+             "flops_model": "16/6/45/70 ops per entry/neighbour/pair/triplet x 1.9/1.1 flops per "
+                            "op + 8 transcendentals per pair + 2 per triplet",
+             "builder_count": {"flops_per_launch": flb, "achieved": flb / (us * 1e-6) / 1e12,
+                               "frac": flb / (us * 1e-6) / peak},
+             "units": {"entries": L, "pairs": P, "triplets": T}}
+        cf = counter_flops_of(sch, tname, n)
+        if cf is not None:
+            prec = "F32" if tname == "float" else "F64"
+            ca = cf[prec] / (us * 1e-6)
+            r["counter"] = {"flops_per_launch": cf[prec], "achieved": ca / 1e12, "frac": ca / peak,
+                            "other_precision_flops_per_launch": cf["F64" if prec == "F32" else "F32"],
+                            "valu_insts_per_launch": cf["valu_insts"],
+                            "source": os.path.relpath(VALU_MIX_SUMMARY % tname, ROOT)}
+        else:
+            r["counter"] = None
+        return r
 
     # ablation of the paper's design choices on this hardware: time to forces
     # (force kernel, plus the gather pass in owner-gather mode; back-to-back
@@ -216,6 +278,15 @@ def main():
             fk["%s_wavefront_32_gather_filter_off" % tag] = \
                 model.profile_forward(x0, td, box, prec, reps=10, with_gather=True)
         model.set_filter(True)
+        # the paper's Algorithm 2 (every dzeta/dx_k recomputed in the second K
+        # loop) against Algorithm 3 with k_max derivatives stored per pair
+        # (workgroup schedule, 64 atoms per workgroup)
+        for prec, tag in ((MIXED, "mixed"), (FP64, "fp64")):
+            for km, name in ((-1, "alg2"), (1, "alg3_kmax1"), (2, "alg3_kmax2"), (4, "alg3_kmax4"),
+                             (0, "alg3_kmax_all")):
+                model.set_schedule(1, 64, km)
+                fk["%s_workgroup_64_%s" % (tag, name)] = \
+                    model.profile_forward(x0, td, box, prec, reps=10, with_gather=True)
         model.set_schedule(sched["mixed"]["kernel"], sched["mixed"]["atoms"], 0)
         el0, reb0, _, _ = run_md(MIXED, skin=0.0, kernel_times=False)
         ablation = {"time_to_forces_us": fk,
@@ -256,6 +327,21 @@ def main():
                   "fp64_vs_mixed_energy_rel": float(abs(trmx[-1] - tr64[-1]) / abs(tr64[-1]))},
     }
 
+    # ---- the same molecular dynamics at 64,000 atoms (20^3 cells) --------------
+    if not args.md_only:
+        print("bench: MD 64k", file=sys.stderr, flush=True)
+        out["md_64k"] = run_md_size(args, 20, dev)
+
+    # ---- one FP64 evaluation of 512 atoms: latency -----------------------------
+    if not args.md_only:
+        print("bench: latency 512", file=sys.stderr, flush=True)
+        out["latency_512"] = run_latency(dev)
+
+    # ---- fitting: loss and its gradient over 64 frames of 512 atoms -------------
+    if not args.md_only:
+        print("bench: fitting frames", file=sys.stderr, flush=True)
+        out["fitting_64x512"] = run_fitting(dev)
+
     # ---- a pair potential on the same list (Algorithm 1): Lennard-Jones --------
     if not args.md_only:
         print("bench: pair potential", file=sys.stderr, flush=True)
@@ -295,6 +381,17 @@ def main():
         kus = ms.profile_forward(xsd, tsd, bs, MIXED, reps=10)
         out["sic_1m_mixed"] = {"value": len(xs) / el, "unit": "atom-steps/s", "ms_per_eval": el * 1e3,
                                "kernel_us": kus, "schedule": ms.schedules()["mixed"]}
+        ms.autotune(xsd, tsd, bs, FP64)
+        o = ms.compute(xsd, tsd, bs, FP64)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            ms.compute(xsd, tsd, bs, FP64, out=o)
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / reps
+        kus = ms.profile_forward(xsd, tsd, bs, FP64, reps=10)
+        out["sic_1m_fp64"] = {"value": len(xs) / el, "unit": "atom-steps/s", "ms_per_eval": el * 1e3,
+                              "kernel_us": kus, "schedule": ms.schedules()["fp64"]}
         ms.close()
         del xsd, tsd
 
@@ -324,10 +421,207 @@ def main():
         out["cpu_baseline"] = {"value": n * reps / elc, "unit": "atom-steps/s", "cores": 1,
                                "kind": "oracle",
                                "sample": "%d full FP64 force evaluations (Algorithm 2) of the same "
-                                         "%d-atom configuration over a prebuilt skin list; list "
-                                         "build and integration not timed" % (reps, n)}
+                                         "%d-atom configuration over a prebuilt skin list, one "
+                                         "thread, gcc -O2; list build and integration not timed"
+                                         % (reps, n)}
+        # the same oracle with the centres shared among the host's threads
+        # (OpenMP, per-thread force arrays, gcc -O3 -march=native)
+        orc.compute_threads(x, t, box, otab, nl)  # build and warm up
+        reps = 0
+        t0 = time.perf_counter()
+        while True:
+            _, _, _, nthr = orc.compute_threads(x, t, box, otab, nl)
+            reps += 1
+            if time.perf_counter() - t0 > 10.0 or reps >= 200:
+                break
+        elc = time.perf_counter() - t0
+        out["cpu_baseline_all_cores"] = {
+            "value": n * reps / elc, "unit": "atom-steps/s", "cores": nthr, "kind": "oracle",
+            "sample": "%d full FP64 force evaluations of the same %d-atom configuration over a "
+                      "prebuilt skin list, %d OpenMP threads, gcc -O3 -march=native; list build "
+                      "and integration not timed" % (reps, n, nthr)}
     model.close()
     print(json.dumps(out), flush=True)
+
+
+def run_md_size(args, ncell, dev):
+    """Velocity-Verlet MD of Si diamond ncell^3 cells (sigma 0.1 A, skin 0.5 A,
+    dt 1 fs), FP64 and mixed, with the autotuned schedules: atom-steps/s of
+    the whole step over args.steps graph-replayed steps."""
+    import torch
+
+    from paper_1607_02904_amd import inputs
+    from paper_1607_02904_amd.tersoff import FP64, MIXED, Tersoff, table_element
+    x, t, box = inputs.si_bulk(ncell)
+    n = len(x)
+    m = Tersoff(table_element("Si(B)"), masses=[28.0855])
+    td = torch.as_tensor(t, device=dev)
+    x0 = torch.as_tensor(x, device=dev)
+    m.build_nlist(x0, td, box, 0.5)
+    res = {"atoms": n, "unit": "atom-steps/s", "steps": args.steps}
+    for prec, tag in ((FP64, "fp64"), (MIXED, "mixed")):
+        m.autotune(x0, td, box, prec)
+        xd = x0.clone()
+        v = torch.zeros_like(xd)
+        f = torch.empty_like(xd)
+        m.build_nlist(xd, td, box, 0.5)
+        m.compute(xd, td, box, prec, energy=False, virial=False, out={"forces": f})
+        m.md_run(xd, v, f, td, box, 0.001, args.warmup, 0.5, prec)
+        torch.cuda.synchronize()
+        r0 = m.rebuilds()
+        t0 = time.perf_counter()
+        m.md_run(xd, v, f, td, box, 0.001, args.steps, 0.5, prec)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        res[tag] = {"value": n * args.steps / el, "ms_per_step": 1e3 * el / args.steps,
+                    "rebuilds": m.rebuilds() - r0, "schedule": m.schedules()[tag]}
+    m.close()
+    return res
+
+
+def run_latency(dev, reps=50):
+    """Si diamond 4^3 cells = 512 atoms (sigma 0.05 A, Si(B) with R = 2.85,
+    D = 0.15, skin 0): wall time of one FP64 evaluation (energy, forces,
+    virial) on a prebuilt list, and of list build plus evaluation, each the
+    median over `reps` synchronised calls."""
+    import torch
+
+    from paper_1607_02904_amd import inputs
+    from paper_1607_02904_amd.tersoff import FP64, Tersoff, table_element
+    x, t, box = inputs.si_small()
+    tab = table_element("Si(B)")
+    tab[0, 0, 0, 10] = 2.85
+    tab[0, 0, 0, 11] = 0.15
+    m = Tersoff(tab)
+    xd = torch.as_tensor(x, device=dev)
+    td = torch.as_tensor(t, device=dev)
+    m.build_nlist(xd, td, box, 0.0)
+    o = m.compute(xd, td, box, FP64)
+    torch.cuda.synchronize()
+    ev, full = [], []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        m.compute(xd, td, box, FP64, out=o)
+        torch.cuda.synchronize()
+        ev.append(time.perf_counter() - t0)
+        t0 = time.perf_counter()
+        m.build_nlist(xd, td, box, 0.0)
+        m.compute(xd, td, box, FP64, out=o)
+        torch.cuda.synchronize()
+        full.append(time.perf_counter() - t0)
+    m.close()
+    return {"atoms": len(x), "eval_us_median": 1e6 * float(np.median(ev)),
+            "build_and_eval_us_median": 1e6 * float(np.median(full)),
+            "note": "wall time per synchronised call (launch latency included); the list build "
+                    "synchronises to read its longest row"}
+
+
+def run_fitting(dev, nframes=64, reps=5):
+    """The fitting workload: 64 Si frames of 512 atoms (sigma 0.15 A, +-3 %
+    strain), references E_ref, F_ref from the FP64 GPU path at a table whose
+    continuous fields are scaled by (1 + 0.01 N(0,1)) (h shifted), loss
+    sum_f (E_f - E_ref,f)^2 / N^2 + 0.1 sum |F - F_ref|^2.  One evaluation of
+    loss and gradient = a batched forward (energies and forces of all frames)
+    and a batched forward + adjoint with the cotangents of that loss (one
+    plan, graph launches).  Reported per precision: atom-steps/s of the whole
+    loss-and-gradient evaluation, and the largest relative error of the 14
+    parameter gradients against central differences (h = 1e-6 relative) of
+    the same loss evaluated by the FP64 GPU path."""
+    import torch
+
+    from paper_1607_02904_amd import inputs
+    from paper_1607_02904_amd.tersoff import FP64, MIXED, BatchPlan, Tersoff, table_element
+    frames = inputs.si_frames(nframes)
+    nat = np.array([len(f[1]) for f in frames], dtype=np.int32)
+    boxes = np.array([f[2] for f in frames])
+    N = int(nat.sum())
+    xc = torch.as_tensor(np.concatenate([f[0] for f in frames]), device=dev)
+    tc = torch.as_tensor(np.concatenate([f[1] for f in frames]), device=dev)
+    tab = table_element("Si(B)")
+    rng = np.random.default_rng(1607 + 33)
+    ref_tab = tab.copy()
+    for fld in range(14):
+        if fld == 0:
+            continue
+        if ref_tab[0, 0, 0, fld] == 0.0:
+            ref_tab[0, 0, 0, fld] = 0.01 * rng.normal() if fld == 5 else 0.0
+        else:
+            ref_tab[0, 0, 0, fld] *= 1.0 + 0.01 * rng.normal()
+    natd = torch.as_tensor(nat, device=dev, dtype=torch.float64)
+    e = torch.empty(nframes, dtype=torch.float64, device=dev)
+    f = torch.empty((N, 3), dtype=torch.float64, device=dev)
+    w = torch.empty((nframes, 6), dtype=torch.float64, device=dev)
+    eb = torch.empty(nframes, dtype=torch.float64, device=dev)
+    fb = torch.empty((N, 3), dtype=torch.float64, device=dev)
+    xg = torch.empty_like(f)
+    pg = torch.empty((1, 1, 1, 14), dtype=torch.float64, device=dev)
+
+    def model_at(table):
+        return Tersoff(table, masses=[28.0855])
+
+    mref = model_at(ref_tab)
+    pref = BatchPlan(mref, nat, boxes, precision=FP64)
+    pref.run(xc, tc, e, f, w)
+    torch.cuda.synchronize()
+    e_ref, f_ref = e.clone(), f.clone()
+    pref.close()
+    mref.close()
+
+    def loss_of(table, precision=FP64):
+        m = model_at(table)
+        p = BatchPlan(m, nat, boxes, precision=precision)
+        p.run(xc, tc, e, f, w)
+        torch.cuda.synchronize()
+        L = float((((e - e_ref) / natd) ** 2).sum().item() + 0.1 * ((f - f_ref) ** 2).sum().item())
+        p.close()
+        m.close()
+        return L
+
+    res = {"frames": nframes, "atoms": N, "unit": "atom-steps/s (loss + gradient)"}
+    for prec, tag in ((FP64, "fp64"), (MIXED, "mixed")):
+        m = model_at(tab)
+        p = BatchPlan(m, nat, boxes, precision=prec)
+
+        def loss_and_grad():
+            p.run(xc, tc, e, f, w)
+            torch.subtract(e, e_ref, out=eb)
+            eb.mul_(2.0).div_(natd * natd)
+            torch.subtract(f, f_ref, out=fb)
+            fb.mul_(0.2)
+            p.run(xc, tc, e, f, w, eb, fb, xg, pg)
+
+        loss_and_grad()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            loss_and_grad()
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / reps
+        g = pg.cpu().numpy().reshape(14).copy()
+        p.close()
+        m.close()
+        res[tag] = {"value": N / el, "ms_per_loss_and_gradient": 1e3 * el, "gradient": g.tolist()}
+    # central differences of the FP64 loss for the 13 continuous fields (the
+    # library takes m in {1, 3} only; dE/dm is checked against the oracle's
+    # continuation by the tests)
+    fd = np.zeros(14)
+    for fld in range(1, 14):
+        th = tab[0, 0, 0, fld]
+        h = 1e-6 * abs(th) if th != 0.0 else 1e-6
+        tp, tm = tab.copy(), tab.copy()
+        tp[0, 0, 0, fld] += h
+        tm[0, 0, 0, fld] -= h
+        fd[fld] = (loss_of(tp) - loss_of(tm)) / (2.0 * h)
+    scale = np.abs(fd).max()
+    for tag in ("fp64", "mixed"):
+        g = np.array(res[tag].pop("gradient"))[1:]
+        fd_ = fd[1:]
+        err = np.abs(g - fd_) / np.maximum(np.abs(fd_), 1e-3 * scale)
+        res[tag]["fd_max_rel_err"] = float(err.max())
+        res[tag]["fd_norm_rel_err"] = float(np.linalg.norm(g - fd_) / np.linalg.norm(fd_))
+    res["fd"] = "central differences (h = 1e-6 relative, absolute where the field is 0) of the " \
+                "loss evaluated by the FP64 GPU path; m differentiated through its continuation"
+    return res
 
 
 FTM2V = 9648.533215665328  # eV/(Angstrom amu) -> Angstrom/ps^2 (metal units, CODATA 2018)

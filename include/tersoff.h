@@ -231,9 +231,19 @@ ters_status ters_md_rebuilds(ters_ctx *ctx, int64_t *out);
  * (device, FP64; any may be NULL).  If f_bar is non-NULL the graph also runs
  * the adjoint with per-configuration e_bar[nconf] (device) and f_bar_cat
  * [N][3] (device), writing x_grad_cat [N][3] and param_grad (summed over
- * configurations) [ntypes^3][14].  x_cat, type_cat device.  Pointers given
- * to the first run are baked into the graph; later runs with other pointers
- * re-capture it. */
+ * configurations) [ntypes^3][14].  x_cat, type_cat device.  Inside the
+ * graph: the lists of all configurations (one set of launches), then one
+ * persistent launch of the wavefront force kernel whose workgroups (as many
+ * as stay resident on the device) take chunks of atoms, never spanning two
+ * configurations, from eight work queues (one per XCD, atomic counters reset
+ * at the start of the graph) until all are done, and, with f_bar, one such
+ * launch of the adjoint kernel.  The atoms per chunk of each pass are timed
+ * on the data of the first run that needs the pass (synchronising).  Pointers
+ * given to the first run are baked into the graph; later runs with other
+ * pointers re-capture it.  Errors latched by the graph (list overflow,
+ * non-finite positions, species outside the table) are reported by
+ * ters_sync.  A plan refuses runs once ters_set_params changed the number of
+ * species or raised a cutoff beyond the plan's list radius. */
 ters_status ters_batch_plan(ters_ctx *ctx, int32_t nconf, const int32_t *natoms_host,
                             const double *boxes_host, int precision, uint32_t flags,
                             ters_plan **out);
@@ -244,10 +254,12 @@ ters_status ters_batch_run(ters_plan *plan, const double *x_cat, const int32_t *
  * plan then fails ters_batch_run with TERS_ERR_INVALID_ARG, and
  * ters_plan_destroy still frees it. */
 ters_status ters_plan_destroy(ters_plan *plan);
-/* Schedule chosen by the plan's autotuner: out[0] = atoms per workgroup
- * (kernel 1) or per wavefront (kernel 2), out[1] = kernel (see
- * ters_set_schedule), out[2] = measured microseconds of the best. */
-ters_status ters_plan_schedule(const ters_plan *plan, double *out3);
+/* Schedule chosen by the plan's autotuner (host double[6]): out[0] = atoms
+ * per chunk of the forward pass, out[1] = kernel (2: the wavefront schedule,
+ * persistent form), out[2] = measured microseconds of the forward pass,
+ * out[3] = atoms per chunk of the adjoint pass (0 until a run with f_bar),
+ * out[4] = its microseconds, out[5] = workgroups of the forward launch. */
+ters_status ters_plan_schedule(const ters_plan *plan, double *out6);
 
 /* ---- schedule control ------------------------------------------------------
  * kernel: 1 = workgroup schedule (a workgroup of 256 lanes stages a run of
@@ -262,7 +274,8 @@ ters_status ters_plan_schedule(const ters_plan *plan, double *out3);
  * kernel 3; 0 = default (kernel 1: 64; kernel 2: 32 with one species, 24
  * with several).  kmax (kernel 1): stored dzeta/dx_k per pair before
  * falling back to recomputing them (the paper's k_max, Section IV-A); 0 =
- * store all that fit.  Applies to the FP64 and mixed precisions (the single
+ * store all that fit; -1 = store none, so that the second K loop recomputes
+ * every term (the paper's Algorithm 2).  Applies to the FP64 and mixed precisions (the single
  * mode always runs kernel 2).  ters_backward refuses kernel 3 with
  * TERS_ERR_UNSUPPORTED. */
 ters_status ters_set_schedule(ters_ctx *ctx, int32_t kernel, int32_t atoms, int32_t kmax);

@@ -38,6 +38,48 @@ def build(force=True):
     return _LIB
 
 
+_LIB_THREADS = os.path.join(_HERE, "_build", "liboracle_threads.so")
+_lib_threads = None
+
+
+def build_threads():
+    """The same source compiled for timing on all host cores: -O3
+    -march=native -fopenmp (built on the machine that runs it, since
+    -march=native targets that machine's CPU)."""
+    os.makedirs(os.path.dirname(_LIB_THREADS), exist_ok=True)
+    tmp = _LIB_THREADS + ".tmp%d" % os.getpid()
+    subprocess.check_call(["gcc", "-O3", "-march=native", "-fopenmp", "-fPIC", "-shared",
+                           "-std=c99", "-D_GNU_SOURCE", "-o", tmp, _SRC, "-lm"])
+    os.replace(tmp, _LIB_THREADS)
+    return _LIB_THREADS
+
+
+def compute_threads(x, types, box, table, nlist):
+    """Energy, forces and virial over a prebuilt list with the centres shared
+    among the OpenMP threads (OMP_NUM_THREADS); returns (E, F, W, threads)."""
+    global _lib_threads
+    if _lib_threads is None:
+        L = ctypes.CDLL(build_threads())
+        P, I = ctypes.c_void_p, ctypes.c_int
+        L.orc_tersoff_threads.argtypes = [I, P, P, P, I, P, P, P, I, P, P, P]
+        L.orc_tersoff_threads.restype = I
+        _lib_threads = L
+    x = _f64(x, (-1, 3))
+    box = _f64(box, (3,))
+    table = _f64(table)
+    types = np.ascontiguousarray(types, dtype=np.int32)
+    count, lst = nlist
+    n = x.shape[0]
+    e = np.zeros(1)
+    f = np.zeros((n, 3))
+    w = np.zeros(6)
+    nthr = _lib_threads.orc_tersoff_threads(n, _p(x), _p(types), _p(box), table.shape[0], _p(table),
+                                            _p(count), _p(lst), lst.shape[1], _p(e), _p(f), _p(w))
+    if nthr <= 0:
+        raise RuntimeError("oracle threaded compute failed (%d)" % nthr)
+    return float(e[0]), f, w, nthr
+
+
 def lib():
     global _lib
     if _lib is None:

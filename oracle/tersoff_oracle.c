@@ -405,3 +405,70 @@ int orc_tersoff_images(int n, const double *x, const int *type, const double *bo
   free(d); free(fnb); free(tn); free(owner);
   return ORC_OK;
 }
+
+/* ---------------------------------------------------------------------------
+ * The list-based evaluation above, with the centres shared among OpenMP
+ * threads (each thread sums into its own force array, energy and virial,
+ * added up at the end).  Same arithmetic per centre; only the order of the
+ * final sums differs.  Built only for timing the oracle on all host cores
+ * (compiled with -fopenmp); without OpenMP it runs on one thread.  Returns
+ * the number of threads used.
+ * ------------------------------------------------------------------------- */
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+int orc_tersoff_threads(int n, const double *x, const int *type, const double *box, int nt,
+                        const double *table, const int *count, const int *list, int cap,
+                        double *energy, double *forces, double *virial) {
+  if (n < 0 || nt <= 0) return -ORC_ERR_ARG;
+  int nthr = 1;
+#ifdef _OPENMP
+  nthr = omp_get_max_threads();
+#endif
+  double *fth = (double *)calloc((size_t)nthr * 3 * (size_t)(n > 0 ? n : 1), sizeof(double));
+  double *eth = (double *)calloc((size_t)nthr * 7, sizeof(double));
+#ifdef _OPENMP
+#pragma omp parallel num_threads(nthr)
+#endif
+  {
+    int th = 0;
+#ifdef _OPENMP
+    th = omp_get_thread_num();
+#endif
+    double *f = fth + (size_t)th * 3 * (size_t)(n > 0 ? n : 1);
+    double *ew = eth + 7 * th;
+    double *d = (double *)malloc(sizeof(double) * 3 * (size_t)(cap > 0 ? cap : 1));
+    double *fnb = (double *)malloc(sizeof(double) * 3 * (size_t)(cap > 0 ? cap : 1));
+    int *tn = (int *)malloc(sizeof(int) * (size_t)(cap > 0 ? cap : 1));
+#ifdef _OPENMP
+#pragma omp for schedule(static)
+#endif
+    for (int i = 0; i < n; ++i) {
+      int nn = count[i] < cap ? count[i] : cap;
+      for (int s = 0; s < nn; ++s) {
+        int j = list[(size_t)i * cap + s];
+        for (int a = 0; a < 3; ++a) d[3 * s + a] = x[3 * j + a] - x[3 * i + a];
+        min_image(d + 3 * s, box);
+        tn[s] = type[j];
+        fnb[3 * s] = fnb[3 * s + 1] = fnb[3 * s + 2] = 0.0;
+      }
+      double e = 0.0, fi[3] = {0, 0, 0};
+      centre_terms(type[i], nn, d, tn, nt, table, &e, fi, fnb, ew + 1);
+      ew[0] += e;
+      for (int a = 0; a < 3; ++a) f[3 * i + a] += fi[a];
+      for (int s = 0; s < nn; ++s) {
+        int j = list[(size_t)i * cap + s];
+        for (int a = 0; a < 3; ++a) f[3 * j + a] += fnb[3 * s + a];
+      }
+    }
+    free(d); free(fnb); free(tn);
+  }
+  for (int t = 0; t < nthr; ++t) {
+    if (energy) *energy += eth[7 * t];
+    if (virial) for (int a = 0; a < 6; ++a) virial[a] += eth[7 * t + 1 + a];
+    if (forces)
+      for (size_t k = 0; k < 3 * (size_t)n; ++k) forces[k] += fth[(size_t)t * 3 * (size_t)(n > 0 ? n : 1) + k];
+  }
+  free(fth); free(eth);
+  return nthr;
+}

@@ -53,9 +53,12 @@ struct ters_plan {
   std::vector<int32_t> natoms, off;
   NList nl;
   DevBuf partials, ebuf, errw, fslot, fown;
-  int A = 0, kern = 1, gather = 1;
-  double best_us = 0.0;
-  bool tuned = false;
+  // persistent wavefront schedule of the forward (f) and adjoint (a) pass:
+  // atoms per chunk, chunk items with their eight queue ranges, workgroups
+  int A = 0, A_adj = 0, gather = 1, grid_f = 0, grid_a = 0, grab_f = 1, grab_a = 1;
+  DevBuf items_f, qb_f, items_a, qb_a, queue;  // queue: 8 counters per pass
+  double best_us = 0.0, best_adj_us = 0.0;
+  bool tuned = false, tuned_adj = false;
   hipGraphExec_t exec = nullptr;
   std::vector<const void *> key;
 };
@@ -863,13 +866,13 @@ ters_status ters_backward(ters_ctx *c, int32_t n, const double *x, const int32_t
 
 ters_status ters_set_schedule(ters_ctx *c, int32_t kernel, int32_t atoms, int32_t kmax) {
   if (!c) return TERS_ERR_INVALID_ARG;
-  if (kernel < 0 || kernel > 3 || kmax < 0) return TERS_ERR_INVALID_ARG;
+  if (kernel < 0 || kernel > 3 || kmax < -1) return TERS_ERR_INVALID_ARG;
   if (atoms < 0 || atoms > (kernel == 2 ? 32 : 64)) return TERS_ERR_INVALID_ARG;
   const int k = kernel == 0 ? 2 : kernel;
   c->kern[0] = c->kern[1] = k;
   c->A[0] = c->A[1] = atoms;
   if (k == 2) c->A[TERS_SINGLE] = atoms;  // the single mode runs the wavefront schedule
-  c->kmax = kmax == 0 ? (1 << 20) : kmax;
+  c->kmax = kmax == 0 ? (1 << 20) : (kmax < 0 ? 0 : kmax);  // -1: store none (Algorithm 2)
   return TERS_OK;
 }
 
@@ -1137,47 +1140,90 @@ __global__ void k_split_partials(const double *partials, int nconf, double *e, d
     for (int k = 0; k < 6; ++k) w[(int64_t)c * 6 + k] = partials[(int64_t)c * 8 + 1 + k];
 }
 
+// Chunks of A atoms that never straddle two configurations (the atoms of
+// configuration c occupy cell-order positions [off_c, off_c + n_c)), dealt to
+// eight queues as contiguous ranges; uploaded to items / qb.
+void make_items(ters_plan *p, int A, DevBuf &items, DevBuf &qb, hipStream_t s) {
+  std::vector<int2> it;
+  for (int c = 0; c < p->nconf; ++c)
+    for (int k = 0; k < p->natoms[c]; k += A)
+      it.push_back(make_int2(p->off[c] + k, std::min(A, p->natoms[c] - k)));
+  const int ni = (int)it.size();
+  std::vector<int32_t> b(9);
+  for (int x = 0; x <= 8; ++x) b[x] = (int32_t)((int64_t)ni * x / 8);
+  items.ensure(sizeof(int2) * std::max(ni, 1));
+  qb.ensure(sizeof(int32_t) * 9);
+  TERS_HIP_TRY(hipMemcpyAsync(items.p, it.data(), sizeof(int2) * ni, hipMemcpyHostToDevice, s));
+  TERS_HIP_TRY(hipMemcpyAsync(qb.p, b.data(), sizeof(int32_t) * 9, hipMemcpyHostToDevice, s));
+  TERS_HIP_TRY(hipStreamSynchronize(s));  // the host vectors go out of scope
+}
+
+
+
+FwdArgs batch_fwd_args(ters_plan *p, const double *x, const int32_t *type, double *f) {
+  FwdArgs a = base_args(p->ctx, p->nl, p->precision, p->N, x, type, true);
+  a.flags = (f ? TERS_FORCES : 0u) | TERS_ENERGY | TERS_VIRIAL;
+  a.forces = f;
+  a.partials = p->partials.as<double>();
+  a.err = p->errw.as<uint32_t>();
+  if (f && p->gather) {
+    a.fslot = p->fslot.p;
+    a.fown = p->fown.as<double>();
+  }
+  a.items = p->items_f.as<int2>();
+  a.qbound = p->qb_f.as<int32_t>();
+  a.queue = p->queue.as<int32_t>();
+  a.grid = p->grid_f;
+  a.grab = p->grab_f;
+  return a;
+}
+
+FwdArgs batch_adj_args(ters_plan *p, const double *x, const int32_t *type, const double *e_bar,
+                       const double *f_bar, double *xg, double *pg) {
+  FwdArgs b = base_args(p->ctx, p->nl, p->precision, p->N, x, type, true);
+  b.fbar = f_bar;
+  b.ebar = 0.0;
+  b.ebar_conf = e_bar;
+  b.xgrad = xg;
+  b.pgrad = pg;
+  b.flags = TERS_PARAM_GRAD;
+  b.err = p->errw.as<uint32_t>();
+  b.kmax = 0;
+  if (p->gather) {
+    b.fslot = p->fslot.p;
+    b.fown = p->fown.as<double>();
+  }
+  b.items = p->items_a.as<int2>();
+  b.qbound = p->qb_a.as<int32_t>();
+  b.queue = p->queue.as<int32_t>() + 8;
+  b.grid = p->grid_a;
+  b.grab = p->grab_a;
+  return b;
+}
+
+// One batch evaluation: list build, queue reset, the persistent forward
+// launch (and gather), per-configuration energies and virials, then with
+// f_bar the persistent adjoint launch (and gather).  Captured in a graph.
 void batch_enqueue(ters_plan *p, const double *x, const int32_t *type, double *e, double *f,
                    double *w, const double *e_bar, const double *f_bar, double *xg, double *pg,
                    hipStream_t s) {
   ters_ctx *c = p->ctx;
   NList &nl = p->nl;
   nlist_build(nl, x, type, c->ntypes, nullptr, p->errw.as<uint32_t>(), s);
-  FwdArgs a = base_args(c, nl, p->precision, p->N, x, type, true);
-  a.flags = (f ? TERS_FORCES : 0u) | TERS_ENERGY | TERS_VIRIAL;
-  a.forces = f;
-  a.partials = p->partials.as<double>();
-  a.err = p->errw.as<uint32_t>();
+  launch_fill_i32(p->queue.as<int32_t>(), 0, 16, nullptr, s);
+  FwdArgs a = batch_fwd_args(p, x, type, f);
   launch_fill_f64(p->partials.as<double>(), 0.0, 8 * (int64_t)p->nconf, s);
-  if (f && p->gather) {
-    a.fslot = p->fslot.p;
-    a.fown = p->fown.as<double>();
-  } else if (f) {
-    launch_fill_f64(f, 0.0, 3 * (int64_t)p->N, s);
-  }
-  launch_fwd(p->kern, a, p->precision, p->A, s);
+  if (f && !p->gather) launch_fill_f64(f, 0.0, 3 * (int64_t)p->N, s);
+  launch_forward_wave(a, p->precision, p->A, s);
   if (f && p->gather) launch_gather(nl, a.fslot, p->precision == TERS_MIXED, a.fown, f, 0, s);
   if (e || w)
     k_split_partials<<<(p->nconf + 255) / 256, 256, 0, s>>>(p->partials.as<double>(), p->nconf, e, w);
   if (f_bar) {
-    FwdArgs b = base_args(c, nl, p->precision, p->N, x, type, true);
-    b.fbar = f_bar;
-    b.ebar = 0.0;
-    b.ebar_conf = e_bar;
-    b.xgrad = xg;
-    b.pgrad = pg;
-    b.flags = TERS_PARAM_GRAD;
-    b.err = p->errw.as<uint32_t>();
-    b.kmax = 0;
+    FwdArgs b = batch_adj_args(p, x, type, e_bar, f_bar, xg, pg);
     const int nt = c->ntypes;
     launch_fill_f64(pg, 0.0, (int64_t)nt * nt * nt * kNField, s);
-    if (p->gather) {
-      b.fslot = p->fslot.p;
-      b.fown = p->fown.as<double>();
-    } else {
-      launch_fill_f64(xg, 0.0, 3 * (int64_t)p->N, s);
-    }
-    launch_adj(p->kern, b, p->precision, p->A, s);
+    if (!p->gather) launch_fill_f64(xg, 0.0, 3 * (int64_t)p->N, s);
+    launch_adjoint_wave(b, p->precision, p->A_adj, s);
     if (p->gather) launch_gather(nl, b.fslot, p->precision == TERS_MIXED, b.fown, xg, 0, s);
   }
 }
@@ -1251,53 +1297,100 @@ ters_status ters_batch_run(ters_plan *p, const double *x, const int32_t *type, d
     require(c->ntypes == p->ntypes && c->rc_max <= nl.rlist, TERS_ERR_INVALID_ARG,
             "the parameters changed the number of species or a cutoff beyond the plan's list "
             "radius (create a new plan)");
-    if (!p->tuned) {
-      // size the list, then pick the schedule on this data (eager, synchronising)
-      nl_build_sync(c, nl, x, type, p->errw);
-      p->gather = c->gather;
-      if (p->gather) ensure_gather(p->fslot, p->fown, nl);
-      DevBuf ft;
-      ft.ensure(sizeof(double) * 3 * (size_t)p->N);
+    // Candidate atoms per chunk of the persistent wavefront schedule, timed on
+    // this data (eager, synchronising): the forward pass on the first run,
+    // the adjoint pass on the first run that asks for it.
+    // (atoms per chunk, chunks per atomic take)
+    const int cands[][2] = {{8, 1}, {12, 1}, {16, 1}, {24, 1}, {32, 1}, {16, 4}, {24, 4}, {32, 4}};
+    auto time_us = [&](auto &&launch) {
       hipEvent_t e0, e1;
       TERS_HIP_TRY(hipEventCreate(&e0));
       TERS_HIP_TRY(hipEventCreate(&e1));
-      struct Cand { int kern, A; };
-      const Cand cands[] = {{1, 16}, {1, 32}, {1, 48}, {1, 64}, {2, 8}, {2, 12}, {2, 16}, {2, 24}};
+      launch();  // warm-up
+      TERS_HIP_TRY(hipEventRecord(e0, c->stream));
+      for (int r = 0; r < 3; ++r) launch();
+      TERS_HIP_TRY(hipEventRecord(e1, c->stream));
+      TERS_HIP_TRY(hipEventSynchronize(e1));
+      float ms = 0.f;
+      TERS_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      return 1000.0 * ms / 3;
+    };
+    const bool multi = c->ntypes > 1;
+    if (!p->tuned) {
+      // size the list, then pick the forward schedule on this data
+      nl_build_sync(c, nl, x, type, p->errw);
+      p->gather = c->gather;
+      if (p->gather) ensure_gather(p->fslot, p->fown, nl);
+      p->queue.ensure(sizeof(int32_t) * 16);
+      p->grid_f = wave_persistent_grid(p->precision, false, multi);
+      require(p->grid_f > 0, TERS_ERR_HIP, "no occupancy for the persistent forward kernel");
+      DevBuf ft;
+      ft.ensure(sizeof(double) * 3 * (size_t)p->N);
       double best = 1e300;
-      int bestA = 32, bestK = 1;
-      for (const Cand &cd : cands) {
-        const int A = cd.A;
-        FwdArgs a = base_args(c, nl, p->precision, p->N, x, type, true);
-        a.flags = TERS_FORCES | TERS_ENERGY | TERS_VIRIAL;
-        a.forces = ft.as<double>();
-        a.partials = p->partials.as<double>();
-        a.err = p->errw.as<uint32_t>();
-        launch_fwd(cd.kern, a, p->precision, A, c->stream);
-        TERS_HIP_TRY(hipEventRecord(e0, c->stream));
-        for (int r = 0; r < 3; ++r) launch_fwd(cd.kern, a, p->precision, A, c->stream);
-        TERS_HIP_TRY(hipEventRecord(e1, c->stream));
-        TERS_HIP_TRY(hipEventSynchronize(e1));
-        float ms = 0.f;
-        TERS_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-        if (1000.0 * ms / 3 < best) {
-          best = 1000.0 * ms / 3;
+      int bestA = 16, bestG = 1;
+      for (const auto &cd : cands) {
+        const int A = cd[0];
+        make_items(p, A, p->items_f, p->qb_f, c->stream);
+        p->grab_f = cd[1];
+        FwdArgs a = batch_fwd_args(p, x, type, ft.as<double>());
+        const double us = time_us([&]() {
+          launch_fill_i32(p->queue.as<int32_t>(), 0, 8, nullptr, c->stream);
+          launch_forward_wave(a, p->precision, A, c->stream);
+        });
+        if (us < best) {
+          best = us;
           bestA = A;
-          bestK = cd.kern;
+          bestG = cd[1];
         }
       }
-      hipEventDestroy(e0);
-      hipEventDestroy(e1);
       ft.release();
+      make_items(p, bestA, p->items_f, p->qb_f, c->stream);
+      p->grab_f = bestG;
       p->A = bestA;
-      p->kern = bestK;
       p->best_us = best;
       p->tuned = true;
+    }
+    if (f_bar && !p->tuned_adj) {
+      p->grid_a = wave_persistent_grid(p->precision, true, multi);
+      require(p->grid_a > 0, TERS_ERR_HIP, "no occupancy for the persistent adjoint kernel");
+      DevBuf xt, pt;
+      xt.ensure(sizeof(double) * 3 * (size_t)p->N);
+      pt.ensure(sizeof(double) * (size_t)c->ntypes * c->ntypes * c->ntypes * kNField);
+      double best = 1e300;
+      int bestA = 16, bestG = 1;
+      for (const auto &cd : cands) {
+        const int A = cd[0];
+        make_items(p, A, p->items_a, p->qb_a, c->stream);
+        p->grab_a = cd[1];
+        FwdArgs b = batch_adj_args(p, x, type, e_bar, f_bar, xt.as<double>(), pt.as<double>());
+        const double us = time_us([&]() {
+          launch_fill_i32(p->queue.as<int32_t>() + 8, 0, 8, nullptr, c->stream);
+          launch_adjoint_wave(b, p->precision, A, c->stream);
+        });
+        if (us < best) {
+          best = us;
+          bestA = A;
+          bestG = cd[1];
+        }
+      }
+      xt.release();
+      pt.release();
+      make_items(p, bestA, p->items_a, p->qb_a, c->stream);
+      p->grab_a = bestG;
+      p->A_adj = bestA;
+      p->best_adj_us = best;
+      p->tuned_adj = true;
     }
     std::vector<const void *> key = graph_key(c, nl);
     const void *extra[] = {x, type, e, f, w, e_bar, f_bar, xg, pg, p->partials.p, p->errw.p,
                            (const void *)(intptr_t)p->A, (const void *)(intptr_t)p->precision,
-                           (const void *)(intptr_t)p->kern, p->fslot.p, p->fown.p,
-                           (const void *)(intptr_t)p->gather};
+                           (const void *)(intptr_t)p->A_adj, p->fslot.p, p->fown.p,
+                           (const void *)(intptr_t)p->gather, p->items_f.p, p->qb_f.p, p->items_a.p,
+                           p->qb_a.p, p->queue.p, (const void *)(intptr_t)p->grid_f,
+                           (const void *)(intptr_t)p->grid_a, (const void *)(intptr_t)p->grab_f,
+                           (const void *)(intptr_t)p->grab_a};
     key.insert(key.end(), std::begin(extra), std::end(extra));
     if (!p->exec || key != p->key) {
       if (p->exec) {
@@ -1325,7 +1418,8 @@ static void plan_release_device(ters_plan *p) {
   hipStreamSynchronize(p->ctx->stream);
   if (p->exec) hipGraphExecDestroy(p->exec);
   p->exec = nullptr;
-  DevBuf *bufs[] = {&p->partials, &p->ebuf, &p->errw, &p->fslot, &p->fown, &p->nl.conf,
+  DevBuf *bufs[] = {&p->partials, &p->ebuf, &p->errw, &p->fslot, &p->fown, &p->items_f,
+                    &p->qb_f, &p->items_a, &p->qb_a, &p->queue, &p->nl.conf,
                     &p->nl.conf_of, &p->nl.count, &p->nl.list, &p->nl.order, &p->nl.cell_of,
                     &p->nl.cell_count, &p->nl.cell_start, &p->nl.scan_tmp, &p->nl.xref,
                     &p->nl.maxcount, &p->nl.rev, &p->nl.xs, &p->nl.pos, &p->nl.soff,
@@ -1345,11 +1439,14 @@ ters_status ters_plan_destroy(ters_plan *p) {
   return TERS_OK;
 }
 
-ters_status ters_plan_schedule(const ters_plan *p, double *out3) {
-  if (!p || !out3) return TERS_ERR_INVALID_ARG;
-  out3[0] = p->A;
-  out3[1] = p->kern;
-  out3[2] = p->best_us;
+ters_status ters_plan_schedule(const ters_plan *p, double *out6) {
+  if (!p || !out6) return TERS_ERR_INVALID_ARG;
+  out6[0] = p->A;
+  out6[1] = 2;  // the wavefront schedule, persistent form
+  out6[2] = p->best_us;
+  out6[3] = p->A_adj;
+  out6[4] = p->best_adj_us;
+  out6[5] = p->grid_f;
   return TERS_OK;
 }
 

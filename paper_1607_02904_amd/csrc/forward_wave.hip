@@ -27,6 +27,7 @@
 #include "ters_internal.h"
 #include "ters_math.h"
 
+#include <algorithm>
 #include <type_traits>
 
 namespace ters {
@@ -75,7 +76,9 @@ DEV void wave_sync() {
 // the displacement, no hi/lo compensation (the parameter record passed in has
 // zero residuals), and every accumulator in FP32 as well; the per-wavefront
 // sums leave the kernel as FP64 partials.
-template <class T, bool NT1, bool PG, bool SP = false>
+// PERSIST: the persistent form (chunks from work queues, a.items set);
+// otherwise one chunk per wavefront.
+template <class T, bool NT1, bool PG, bool SP = false, bool PERSIST = false>
 __global__ __launch_bounds__(waves_per_group<PG>() * kWave)
 __attribute__((amdgpu_waves_per_eu(WavesPerEu<T, PG>::value))) void k_force_wave(FwdArgs a, int A) {
   static_assert(!SP || (std::is_same<T, float>::value && !PG), "single precision: forward FP32 only");
@@ -166,20 +169,6 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEu<T, PG>::value))) void k_force_wave
   const bool want_w = !DUAL && (flags & TERS_VIRIAL);
   const bool want_ea = !DUAL && (flags & TERS_PER_ATOM_E) && a.e_atom;
 
-  const int64_t first = ((int64_t)xcd_block(blockIdx.x, gridDim.x) * kWPB + w) * A;
-  const int na = (int)max((int64_t)0, min((int64_t)A, (int64_t)a.n - first));
-  // chunk atoms: lane `lane` < na holds atom `lane` of the chunk (A <= 64)
-  int my_i = 0, my_a = 0, my_t = 0, my_lc = 0, my_cf = 0;  // position, atom
-  double my_x[3] = {0.0, 0.0, 0.0};  // position of the lane's atom
-  if (lane < na) {
-    my_i = (int)(first + lane);  // cell-order position: list row
-    my_a = a.order[my_i];        // the atom: per-atom arrays
-    my_t = NT1 ? 0 : species(a.type, my_a, a.ntypes);
-    my_lc = min(a.count[my_i], a.cap);
-    my_cf = a.conf_of ? a.conf_of[my_a] : 0;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) my_x[k] = a.x[3 * (int64_t)my_a + k];
-  }
   // periodic box: one record for a single system (uniform, read once),
   // the configuration's own record per lane for a batch
   double box0[3], ibox0[3];
@@ -211,436 +200,508 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEu<T, PG>::value))) void k_force_wave
   };
   const double filt2_0 = ((const double *)a.filt2)[0];
 
-  // ---- filter: compact the in-cutoff neighbours of every atom of the chunk --
-  // The chunk's list entries are numbered without the row padding (atom a's
-  // entries follow those of atoms 0..a-1) and visited a wavefront at a time.
-  int my_e = my_lc;  // exclusive prefix of the list counts, below
-#pragma unroll
-  for (int o = 1; o < kWave; o <<= 1) {
-    const int u = __shfl_up(my_e, o, kWave);
-    if (lane >= o) my_e += u;
-  }
-  const int total = __shfl(my_e, kWave - 1, kWave);
-  my_e -= my_lc;
-  int my_cnt = 0;  // in-cutoff neighbours found so far (atom lanes)
-  // Windows are taken kBatch at a time: the list entries of all windows of a
-  // batch are loaded first, then the neighbours' positions, so that a
-  // wavefront has all these loads in flight at once; the tests follow window
-  // by window (the staging position of a pass depends on the earlier ones).
-  for (int base0 = 0; base0 < total; base0 += kBatch * kWave) {
-    // entry -> (atom, slot), written by the atoms' lanes
-    {
-      const int lo = max(my_e, base0), hi = min(my_e + my_lc, base0 + kBatch * kWave);
-      for (int t = lo; t < hi; ++t) s_map[w][t - base0] = (unsigned short)((lane << 8) | (t - my_e));
+  // Chunks of atoms (consecutive cell-order positions): one per wavefront
+  // from its workgroup id, or, in the persistent form (a.items set), items
+  // (first position, count) from eight work queues, one per XCD (each a
+  // contiguous range of the items, so that neighbouring chunks share an L2).
+  // A wavefront takes a.grab items at a time with one atomic add, from its
+  // own XCD's queue first and then from the others'; a.grab = 0 instead
+  // deals each XCD's range to its wavefronts in turn (no atomics).
+  const int home = (int)(blockIdx.x % 8u);
+  const int xwave = (int)(blockIdx.x / 8u) * kWPB + w;  // wavefront within its XCD
+  const int xwaves = (int)((gridDim.x + 7u - (unsigned)home) / 8u) * kWPB;
+  int item = 0, run_end = 0, taken = 0;  // current item, end of the run taken
+  auto next_run = [&]() -> bool {  // the next run of items [item, run_end); false when done
+    if (a.grab == 0) {  // this XCD's range, every xwaves-th item from xwave on
+      const int cand = a.qbound[home] + xwave + taken * xwaves;
+      ++taken;
+      item = cand;
+      run_end = cand + 1;
+      return cand < a.qbound[home + 1];
     }
-    wave_sync();
-    int cw[kBatch], jw[kBatch], rw[kBatch];  // entry code, neighbour's atom, reverse slot
-    double xw[kBatch][3];
-    // (no branches around the loads: lanes past the end read entry 0 and
-    // atom 0 and discard them, so that the loads issue back to back)
-#pragma unroll
-    for (int u = 0; u < kBatch; ++u) {
-      const bool valid = base0 + u * kWave + lane < total;
-      cw[u] = valid ? (int)s_map[w][u * kWave + lane] : -1;
-      const int at = valid ? cw[u] >> 8 : 0;
-      const int i = lane_read(my_i, at);
-      const int64_t e = valid ? (int64_t)i * a.cap + (cw[u] & 0xff) : 0;
-      const int jl = a.list[e];
-      const int rl = a.rev[e];  // the reverse map exists in both force modes
-      jw[u] = valid ? jl : 0;
-      rw[u] = (valid && a.fslot) ? rl : -1;
-    }
-#pragma unroll
-    for (int u = 0; u < kBatch; ++u) {
-#pragma unroll
-      for (int k = 0; k < 3; ++k) xw[u][k] = a.x[3 * (int64_t)jw[u] + k];
-    }
-#pragma unroll
-    for (int u = 0; u < kBatch; ++u) {
-      const int base = base0 + u * kWave;
-      if (base >= total) break;  // uniform
-      const bool valid = cw[u] >= 0;
-      const int at = valid ? cw[u] >> 8 : 0, s = cw[u] & 0xff;
-      const int ti = lane_read(my_t, at), cf = lane_read(my_cf, at);
-      const int e_at = lane_read(my_e, at), c_at = lane_read(my_cnt, at);
-      double d[3];
-#pragma unroll
-      for (int k = 0; k < 3; ++k) d[k] = sp_sub(xw[u][k], lane_read(my_x[k], at));
-      bool pass = false;
-      const int j = jw[u];
-      if (valid) {
-        min_image(d, cf);
-        const int tj = NT1 ? 0 : species(a.type, j, a.ntypes);
-        const double f2 = NT1 ? filt2_0 : filt2[ti * nt + tj];
-        if constexpr (SP)
-          pass = (float)d[0] * (float)d[0] + (float)d[1] * (float)d[1] + (float)d[2] * (float)d[2] <
-                 (float)f2;
-        else
-          pass = d[0] * d[0] + d[1] * d[1] + d[2] * d[2] < f2;
-        pass = pass || a.no_filter;  // without the filter every entry takes a lane
-      }
-      const uint64_t m = __ballot(pass);
-      // passes of the same atom in lower lanes of this window (e_at <= base + lane)
-      const int lo_lane = max(e_at - base, 0);
-      const uint64_t below = ((1ull << lane) - 1ull) & ~((1ull << lo_lane) - 1ull);
-      const int pos = c_at + __popcll(m & below);
-      if (pass) {
-        if (pos < kNMax) {
-          s_stage[w][at * kNMax + pos] = j;
-          s_slot[w][at * kNMax + pos] = (unsigned char)s;
-        } else {
-          atomicOr(a.err, kErrTooManyInCutoff);
+    int v = -1, cnt = 0;
+    if (lane == 0) {
+      for (int k = 0; k < 8; ++k) {
+        const int xq = (home + k) & 7;
+        const int len = a.qbound[xq + 1] - a.qbound[xq];
+        if (len <= 0) continue;
+        const int got = atomicAdd(&a.queue[xq], a.grab);
+        if (got < len) {
+          v = a.qbound[xq] + got;
+          cnt = min(a.grab, len - got);
+          break;
         }
-      } else if (valid && rw[u] >= 0) {
-        B *fs = (B *)a.fslot + 3 * (int64_t)rw[u];  // slots hold the base type
-        fs[0] = B(0);
-        fs[1] = B(0);
-        fs[2] = B(0);
-      }
-      const int lo = max(my_e, base), hi = min(my_e + my_lc, base + kWave);
-      if (hi > lo) {
-        const int l0 = lo - base, l1 = hi - base;  // this atom's lanes [l0, l1)
-        const uint64_t mine = (l1 == kWave ? ~0ull : (1ull << l1) - 1ull) & ~((1ull << l0) - 1ull);
-        my_cnt += __popcll(m & mine);
       }
     }
-    wave_sync();  // s_map is rewritten by the next batch
+    v = __shfl(v, 0, kWave);
+    cnt = __shfl(cnt, 0, kWave);
+    item = v;
+    run_end = v + cnt;
+    return v >= 0;
+  };
+  // chunk of this pass: positions [first, first + na)
+  int64_t first = 0;
+  int na = 0;
+  if constexpr (PERSIST) {
+    if (!next_run()) goto done;
+    first = a.items[item].x;
+    na = a.items[item].y;
+  } else {
+    first = ((int64_t)xcd_block(blockIdx.x, gridDim.x) * kWPB + w) * A;
+    na = (int)max((int64_t)0, min((int64_t)A, (int64_t)a.n - first));
   }
-  const int my_n = lane < na ? min(my_cnt, kNMax) : 0;
-  int incl = my_n;  // inclusive prefix of pair counts over the chunk's atoms
+again:
+  {
+    // chunk atoms: lane `lane` < na holds atom `lane` of the chunk (A <= 64)
+    int my_i = 0, my_a = 0, my_t = 0, my_lc = 0, my_cf = 0;  // position, atom
+    double my_x[3] = {0.0, 0.0, 0.0};  // position of the lane's atom
+    if (lane < na) {
+      my_i = (int)(first + lane);  // cell-order position: list row
+      my_a = a.order[my_i];        // the atom: per-atom arrays
+      my_t = NT1 ? 0 : species(a.type, my_a, a.ntypes);
+      my_lc = min(a.count[my_i], a.cap);
+      my_cf = a.conf_of ? a.conf_of[my_a] : 0;
 #pragma unroll
-  for (int o = 1; o < kWave; o <<= 1) {
-    const int u = __shfl_up(incl, o, kWave);
-    if (lane >= o) incl += u;
-  }
-
-  // ---- rounds: consecutive atoms whose pairs fill at most one wavefront ------
-  int a0 = 0;
-  while (a0 < na) {
-    const int base = a0 > 0 ? __shfl(incl, a0 - 1, kWave) : 0;
-    const uint64_t fits = __ballot(lane >= a0 && lane < na && incl - base <= kWave);
-    const int a1 = a0 + __popcll(fits);  // >= a0 + 1: one atom has at most 32 pairs
-    const int np = __shfl(incl, a1 - 1, kWave) - base;
-    // pair map of this round: an atom's pairs occupy the slots from its start
-    // on, so the atom of slot p is the last one starting at or before p; each
-    // atom marks its start with (start << 8 | atom + 1) and a prefix maximum
-    // over the slots recovers both
-    s_map[w][lane] = 0;
-    wave_sync();
-    if (lane >= a0 && lane < a1 && my_n > 0) {
-      const int b = incl - my_n - base;
-      s_map[w][b] = (unsigned short)((b << 8) | (lane + 1));
+      for (int k = 0; k < 3; ++k) my_x[k] = a.x[3 * (int64_t)my_a + k];
     }
-    wave_sync();
-    int pm = s_map[w][lane];
+    // ---- filter: compact the in-cutoff neighbours of every atom of the chunk --
+    // The chunk's list entries are numbered without the row padding (atom a's
+    // entries follow those of atoms 0..a-1) and visited a wavefront at a time.
+    int my_e = my_lc;  // exclusive prefix of the list counts, below
 #pragma unroll
     for (int o = 1; o < kWave; o <<= 1) {
-      const int u = __shfl_up(pm, o, kWave);
-      if (lane >= o) pm = max(pm, u);
+      const int u = __shfl_up(my_e, o, kWave);
+      if (lane >= o) my_e += u;
     }
-    wave_sync();  // s_map is rewritten in the next round
-    const bool act = lane < np;
-    const int at = act ? (pm & 0xff) - 1 : a0;
-    const int q = act ? lane - (pm >> 8) : 0;
-    const int n_i = lane_read(my_n, at);
-    const int seg0 = lane - q;  // first lane of this atom's pairs
-    const int i = lane_read(my_i, at), ti = lane_read(my_t, at), cf = lane_read(my_cf, at);
-    const int ia = lane_read(my_a, at);  // atom of position i
-    const int j = act ? s_stage[w][at * kNMax + q] : ia;  // neighbour's atom
-    const int tj = NT1 ? 0 : (act ? species(a.type, j, a.ntypes) : 0);
-    // incoming slot at j for this pair's force on j, fetched now so that the
-    // load is complete when the force is stored
-    const int r_out = a.rev[act ? (int64_t)i * a.cap + s_slot[w][at * kNMax + q] : 0];
-
-    // pair data in registers
-    T dx, dy, dz, r, ri, fc, dfc;
-    B rlo;
-    {
-      double d[3];
-#pragma unroll
-      for (int k = 0; k < 3; ++k) d[k] = lane_read(my_x[k], at);
-#pragma unroll
-      for (int k = 0; k < 3; ++k) d[k] = sp_sub(a.x[3 * (int64_t)j + k], d[k]);
-      min_image(d, cf);
-      if (!act) {
-        d[0] = 1.0;
-        d[1] = 0.0;
-        d[2] = 0.0;
+    const int total = __shfl(my_e, kWave - 1, kWave);
+    my_e -= my_lc;
+    int my_cnt = 0;  // in-cutoff neighbours found so far (atom lanes)
+    // Windows are taken kBatch at a time: the list entries of all windows of a
+    // batch are loaded first, then the neighbours' positions, so that a
+    // wavefront has all these loads in flight at once; the tests follow window
+    // by window (the staging position of a pass depends on the earlier ones).
+    for (int base0 = 0; base0 < total; base0 += kBatch * kWave) {
+      // entry -> (atom, slot), written by the atoms' lanes
+      {
+        const int lo = max(my_e, base0), hi = min(my_e + my_lc, base0 + kBatch * kWave);
+        for (int t = lo; t < hi; ++t) s_map[w][t - base0] = (unsigned short)((lane << 8) | (t - my_e));
       }
-      T dT[3];
+      wave_sync();
+      int cw[kBatch], jw[kBatch], rw[kBatch];  // entry code, neighbour's atom, reverse slot
+      double xw[kBatch][3];
+      // (no branches around the loads: lanes past the end read entry 0 and
+      // atom 0 and discard them, so that the loads issue back to back)
 #pragma unroll
-      for (int k = 0; k < 3; ++k)
-        dT[k] = Conv<T>::from(d[k], (DUAL && act) ? (a.fbar[3 * j + k] - a.fbar[3 * ia + k]) : 0.0);
-      r = t_sqrt(dT[0] * dT[0] + dT[1] * dT[1] + dT[2] * dT[2]);
-      if constexpr (SP) {
-        ri = rcp(r);
-        fcut(param(ti, tj, tj), r, fc, dfc);
-        rlo = B(0);
-      } else {
-        const double r64 = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-        set_val(r, r64);
-        ri = rcp(r);
-        fcut64(param(ti, tj, tj), r, r64, fc, dfc);
-        rlo = (B)(r64 - (double)val(r));
+      for (int u = 0; u < kBatch; ++u) {
+        const bool valid = base0 + u * kWave + lane < total;
+        cw[u] = valid ? (int)s_map[w][u * kWave + lane] : -1;
+        const int at = valid ? cw[u] >> 8 : 0;
+        const int i = lane_read(my_i, at);
+        const int64_t e = valid ? (int64_t)i * a.cap + (cw[u] & 0xff) : 0;
+        const int jl = a.list[e];
+        const int rl = a.rev[e];  // the reverse map exists in both force modes
+        jw[u] = valid ? jl : 0;
+        rw[u] = (valid && a.fslot) ? rl : -1;
       }
-      dx = dT[0];
-      dy = dT[1];
-      dz = dT[2];
-    }
-    const T u[3] = {dx * ri, dy * ri, dz * ri};
-    // largest neighbour count in this round (uniform loop bound)
-    int nmax = n_i;
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) nmax = max(nmax, __shfl_xor(nmax, o, kWave));
-
-    // ---- first K loop: zeta_ij -----------------------------------------------
-    const KP &pp = param(ti, tj, tj);
-    const bool in_pair = act && val(r) < pp.rcut;
-    T zeta = Zero<T>::get();
-    T gs[3] = {Zero<T>::get(), Zero<T>::get(), Zero<T>::get()};  // sum over kept k of dzeta/dx_j
-    for (int s = 1; s < nmax; ++s) {
-      const bool keep = kOnePass && s <= kKeep;  // uniform
-      const int kq = q + s < n_i ? q + s : q + s - n_i;
-      const int src = act && s < n_i ? seg0 + kq : lane;
-      const T kx = lane_read(dx, src), ky = lane_read(dy, src), kz = lane_read(dz, src);
-      const T kr = lane_read(r, src), kri = lane_read(ri, src);
-      const T kfc = lane_read(fc, src), kdfc = lane_read(dfc, src);
-      const int tk = NT1 ? 0 : lane_read(tj, src);
-      T gk[3] = {Zero<T>::get(), Zero<T>::get(), Zero<T>::get()};
-      if (in_pair && s < n_i) {
-        const KP &pk = param(ti, tj, tk);
-        if (val(kr) < pk.rcut) {
-          T fck = kfc, dfck = kdfc;
-          if (!a.cut_consistent) fcut(pk, kr, fck, dfck);
-          const T v[3] = {kx * kri, ky * kri, kz * kri};
-          if (keep) {
-            T gj[3], dp[8];
-            zeta += zeta_term<T, B, false>(pk, r, ri, u, kr, kri, v, fck, dfck, gj, gk, dp);
+      for (int u = 0; u < kBatch; ++u) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) gs[c] += gj[c];
+        for (int k = 0; k < 3; ++k) xw[u][k] = a.x[3 * (int64_t)jw[u] + k];
+      }
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) {
+        const int base = base0 + u * kWave;
+        if (base >= total) break;  // uniform
+        const bool valid = cw[u] >= 0;
+        const int at = valid ? cw[u] >> 8 : 0, s = cw[u] & 0xff;
+        const int ti = lane_read(my_t, at), cf = lane_read(my_cf, at);
+        const int e_at = lane_read(my_e, at), c_at = lane_read(my_cnt, at);
+        double d[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) d[k] = sp_sub(xw[u][k], lane_read(my_x[k], at));
+        bool pass = false;
+        const int j = jw[u];
+        if (valid) {
+          min_image(d, cf);
+          const int tj = NT1 ? 0 : species(a.type, j, a.ntypes);
+          const double f2 = NT1 ? filt2_0 : filt2[ti * nt + tj];
+          if constexpr (SP)
+            pass = (float)d[0] * (float)d[0] + (float)d[1] * (float)d[1] + (float)d[2] * (float)d[2] <
+                   (float)f2;
+          else
+            pass = d[0] * d[0] + d[1] * d[1] + d[2] * d[2] < f2;
+          pass = pass || a.no_filter;  // without the filter every entry takes a lane
+        }
+        const uint64_t m = __ballot(pass);
+        // passes of the same atom in lower lanes of this window (e_at <= base + lane)
+        const int lo_lane = max(e_at - base, 0);
+        const uint64_t below = ((1ull << lane) - 1ull) & ~((1ull << lo_lane) - 1ull);
+        const int pos = c_at + __popcll(m & below);
+        if (pass) {
+          if (pos < kNMax) {
+            s_stage[w][at * kNMax + pos] = j;
+            s_slot[w][at * kNMax + pos] = (unsigned char)s;
           } else {
-            zeta += zeta_value<T, B>(pk, r, u, kr, v, fck);
+            atomicOr(a.err, kErrTooManyInCutoff);
           }
+        } else if (valid && rw[u] >= 0) {
+          B *fs = (B *)a.fslot + 3 * (int64_t)rw[u];  // slots hold the base type
+          fs[0] = B(0);
+          fs[1] = B(0);
+          fs[2] = B(0);
+        }
+        const int lo = max(my_e, base), hi = min(my_e + my_lc, base + kWave);
+        if (hi > lo) {
+          const int l0 = lo - base, l1 = hi - base;  // this atom's lanes [l0, l1)
+          const uint64_t mine = (l1 == kWave ? ~0ull : (1ull << l1) - 1ull) & ~((1ull << l0) - 1ull);
+          my_cnt += __popcll(m & mine);
         }
       }
-      if (keep) {
-#pragma unroll
-        for (int c = 0; c < 3; ++c) s_gk[kOnePass ? w : 0][keep ? s - 1 : 0][c][lane] = gk[c];
-      }
+      wave_sync();  // s_map is rewritten by the next batch
     }
-    // pair term V(i, j, zeta)
-    T dzeta = Zero<T>::get();
-    FA f0 = Zero<FA>::get(), f1 = Zero<FA>::get(), f2 = Zero<FA>::get();
-    EA ev = 0;
-    const double eb = DUAL ? (a.ebar_conf ? a.ebar_conf[cf] : a.ebar) : 1.0;
-    if (in_pair) {
-      T fr, fa;
-      AT fre, fae;  // the same for the energy
-      if constexpr (std::is_same<T, float>::value && !SP) {  // mixed: FP64 exponentials
-        const double e1 = exp64(pp.A, pp.A_lo, pp.lam1, pp.lam1_lo, r, rlo);
-        const double e2 = exp64(pp.Bc, pp.B_lo, pp.lam2, pp.lam2_lo, r, rlo);
-        fr = (float)e1;
-        fa = -(float)e2;
-        fre = e1;
-        fae = -e2;
-      } else {
-        fr = scaled_exp(pp.A, pp.A_lo, pp.lam1, pp.lam1_lo, r, rlo);
-        fa = -scaled_exp(pp.Bc, pp.B_lo, pp.lam2, pp.lam2_lo, r, rlo);
-        fre = wide(fr);
-        fae = wide(fa);
-      }
-      T b, db, dbb, dbn;
-      bond<T, B, PG>(pp, zeta, b, db, dbb, dbn);
-      const T vr = fr + b * fa;
-      const AT V = wide(fc) * (fre + wide(b) * fae);
-      const T dVdr = dfc * vr + fc * (-pp.lam1 * fr - pp.lam2 * b * fa);
-      dzeta = B(0.5) * fc * fa * db;
-      const T hp = B(0.5) * dVdr;
-      f0 = to_fa(wide(-(hp * u[0])));
-      f1 = to_fa(wide(-(hp * u[1])));
-      f2 = to_fa(wide(-(hp * u[2])));
-      if (kOnePass) {
-        f0 -= to_fa(wide(dzeta * gs[0]));
-        f1 -= to_fa(wide(dzeta * gs[1]));
-        f2 -= to_fa(wide(dzeta * gs[2]));
-      }
-      ev = 0.5 * val(V);
-      if (PG) {
-        const T h = T(B(0.5)) * fc;
-        T dp[8];
-        dp[0] = h * fr * (B(1) / pp.A);
-        dp[1] = -h * r * fr;
-        dp[2] = h * b * fa * (B(1) / pp.Bc);
-        dp[3] = -h * b * r * fa;
-        dp[4] = h * fa * dbb;
-        dp[5] = h * fa * dbn;
-        dp[6] = -B(0.5) * dfc * vr;
-        dp[7] = -B(0.5) * dfc * (r - pp.R) * (B(1) / pp.D) * vr;
+    const int my_n = lane < na ? min(my_cnt, kNMax) : 0;
+    int incl = my_n;  // inclusive prefix of pair counts over the chunk's atoms
 #pragma unroll
-        for (int f = 0; f < 8; ++f) add_grad(ti, tj, tj, GradSlots::pair[f], out_of(wide(dp[f]), eb));
-      }
-    }
-    // ---- second K loop: dzeta/dx, forces on j (kept) and on k (sent) -----------
-    for (int s = 1; s < nmax; ++s) {
-      const bool live = act && s < n_i;
-      const int kq = q + s < n_i ? q + s : q + s - n_i;      // k this lane treats
-      const int bq = q - s >= 0 ? q - s : q - s + n_i;       // lane whose k is me
-      const int src = live ? seg0 + kq : lane;
-      const int bsrc = live ? seg0 + bq : lane;
-      T cx = Zero<T>::get(), cy = Zero<T>::get(), cz = Zero<T>::get();  // force sent to k
-      if (kOnePass && s <= kKeep) {  // uniform: the term was evaluated in the first loop
-        if (live && in_pair && val(dzeta) != B(0)) {
-          const int sk = kOnePass && s <= kKeep ? s - 1 : 0;
-          cx = -(dzeta * s_gk[kOnePass ? w : 0][sk][0][lane]);
-          cy = -(dzeta * s_gk[kOnePass ? w : 0][sk][1][lane]);
-          cz = -(dzeta * s_gk[kOnePass ? w : 0][sk][2][lane]);
-        }
-      } else {
-      const T kx = lane_read(dx, src), ky = lane_read(dy, src), kz = lane_read(dz, src);
-      const T kr = lane_read(r, src), kri = lane_read(ri, src);
-      const T kfc = lane_read(fc, src), kdfc = lane_read(dfc, src);
-      const int tk = NT1 ? 0 : lane_read(tj, src);
-      if (live && in_pair && val(dzeta) != B(0)) {
-        const KP &pk = param(ti, tj, tk);
-        if (val(kr) < pk.rcut) {
-          T fck = kfc, dfck = kdfc;
-          if (!a.cut_consistent) fcut(pk, kr, fck, dfck);
-          const T v[3] = {kx * kri, ky * kri, kz * kri};
-          T gj[3], gk[3], dp[8];
-          zeta_term<T, B, PG>(pk, r, ri, u, kr, kri, v, fck, dfck, gj, gk, dp);
-          f0 -= to_fa(wide(dzeta * gj[0]));
-          f1 -= to_fa(wide(dzeta * gj[1]));
-          f2 -= to_fa(wide(dzeta * gj[2]));
-          cx = -(dzeta * gk[0]);
-          cy = -(dzeta * gk[1]);
-          cz = -(dzeta * gk[2]);
-          if (PG) {
-#pragma unroll
-            for (int fl = 0; fl < 8; ++fl)
-              add_grad(ti, tj, tk, GradSlots::three[fl], out_of(wide(dzeta * dp[fl]), eb));
-          }
-        }
-      }
-      }
-      // pull the force that lane (i, bq) computed for my atom in this step
-      const T rx = lane_read(cx, bsrc), ry = lane_read(cy, bsrc), rz = lane_read(cz, bsrc);
-      if (live) {
-        f0 += to_fa(wide(rx));
-        f1 += to_fa(wide(ry));
-        f2 += to_fa(wide(rz));
-      }
+    for (int o = 1; o < kWave; o <<= 1) {
+      const int u = __shfl_up(incl, o, kWave);
+      if (lane >= o) incl += u;
     }
 
-    // ---- f_im complete: virial, scatter to j, own force of i ------------------
-    if (!DUAL && a.partials) {
-      EA wv[7] = {ev, 0, 0, 0, 0, 0, 0};
-      if (act && want_w) {
-        const EA ddx = val(wide(dx)), ddy = val(wide(dy)), ddz = val(wide(dz));
-        const EA fx = val(f0), fy = val(f1), fz = val(f2);
-        wv[1] = ddx * fx;
-        wv[2] = ddy * fy;
-        wv[3] = ddz * fz;
-        wv[4] = ddx * fy;
-        wv[5] = ddx * fz;
-        wv[6] = ddy * fz;
+    // ---- rounds: consecutive atoms whose pairs fill at most one wavefront ------
+    int a0 = 0;
+    while (a0 < na) {
+      const int base = a0 > 0 ? __shfl(incl, a0 - 1, kWave) : 0;
+      const uint64_t fits = __ballot(lane >= a0 && lane < na && incl - base <= kWave);
+      const int a1 = a0 + __popcll(fits);  // >= a0 + 1: one atom has at most 32 pairs
+      const int np = __shfl(incl, a1 - 1, kWave) - base;
+      // pair map of this round: an atom's pairs occupy the slots from its start
+      // on, so the atom of slot p is the last one starting at or before p; each
+      // atom marks its start with (start << 8 | atom + 1) and a prefix maximum
+      // over the slots recovers both
+      s_map[w][lane] = 0;
+      wave_sync();
+      if (lane >= a0 && lane < a1 && my_n > 0) {
+        const int b = incl - my_n - base;
+        s_map[w][b] = (unsigned short)((b << 8) | (lane + 1));
       }
-      if (a.conf_of) {
-        // batches: per-configuration energy and virial; one atomic per value
-        // when the round belongs to one configuration, per lane otherwise
-        const int cf0 = __shfl(cf, 0, kWave);
-        if (__ballot(act && cf != cf0) == 0ull) {
+      wave_sync();
+      int pm = s_map[w][lane];
 #pragma unroll
-          for (int k = 0; k < 7; ++k) {
-            const double sum = wave_sum(wv[k]);
-            if (lane == 0) atomic_add(&a.partials[(int64_t)cf0 * 8 + k], (double)sum);
+      for (int o = 1; o < kWave; o <<= 1) {
+        const int u = __shfl_up(pm, o, kWave);
+        if (lane >= o) pm = max(pm, u);
+      }
+      wave_sync();  // s_map is rewritten in the next round
+      const bool act = lane < np;
+      const int at = act ? (pm & 0xff) - 1 : a0;
+      const int q = act ? lane - (pm >> 8) : 0;
+      const int n_i = lane_read(my_n, at);
+      const int seg0 = lane - q;  // first lane of this atom's pairs
+      const int i = lane_read(my_i, at), ti = lane_read(my_t, at), cf = lane_read(my_cf, at);
+      const int ia = lane_read(my_a, at);  // atom of position i
+      const int j = act ? s_stage[w][at * kNMax + q] : ia;  // neighbour's atom
+      const int tj = NT1 ? 0 : (act ? species(a.type, j, a.ntypes) : 0);
+      // incoming slot at j for this pair's force on j, fetched now so that the
+      // load is complete when the force is stored
+      const int r_out = a.rev[act ? (int64_t)i * a.cap + s_slot[w][at * kNMax + q] : 0];
+
+      // pair data in registers: the unit vector u = d / r, r, 1/r, f_C, f_C'
+      // (what the lanes of the other pairs of the atom read in their K loops)
+      T ux, uy, uz, r, ri, fc, dfc;
+      B rlo;
+      {
+        double d[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) d[k] = lane_read(my_x[k], at);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) d[k] = sp_sub(a.x[3 * (int64_t)j + k], d[k]);
+        min_image(d, cf);
+        if (!act) {
+          d[0] = 1.0;
+          d[1] = 0.0;
+          d[2] = 0.0;
+        }
+        T dT[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+          dT[k] = Conv<T>::from(d[k], (DUAL && act) ? (a.fbar[3 * j + k] - a.fbar[3 * ia + k]) : 0.0);
+        r = t_sqrt(dT[0] * dT[0] + dT[1] * dT[1] + dT[2] * dT[2]);
+        if constexpr (SP) {
+          ri = rcp(r);
+          fcut(param(ti, tj, tj), r, fc, dfc);
+          rlo = B(0);
+        } else {
+          const double r64 = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+          set_val(r, r64);
+          ri = rcp(r);
+          fcut64(param(ti, tj, tj), r, r64, fc, dfc);
+          rlo = (B)(r64 - (double)val(r));
+        }
+        ux = dT[0] * ri;
+        uy = dT[1] * ri;
+        uz = dT[2] * ri;
+      }
+      const T u[3] = {ux, uy, uz};
+      // largest neighbour count in this round (uniform loop bound)
+      int nmax = n_i;
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) nmax = max(nmax, __shfl_xor(nmax, o, kWave));
+
+      // ---- first K loop: zeta_ij -----------------------------------------------
+      const KP &pp = param(ti, tj, tj);
+      const bool in_pair = act && val(r) < pp.rcut;
+      T zeta = Zero<T>::get();
+      T gs[3] = {Zero<T>::get(), Zero<T>::get(), Zero<T>::get()};  // sum over kept k of dzeta/dx_j
+      for (int s = 1; s < nmax; ++s) {
+        const bool keep = kOnePass && s <= kKeep;  // uniform
+        const int kq = q + s < n_i ? q + s : q + s - n_i;
+        const int src = act && s < n_i ? seg0 + kq : lane;
+        const T v[3] = {lane_read(ux, src), lane_read(uy, src), lane_read(uz, src)};
+        const T kr = lane_read(r, src), kri = lane_read(ri, src);
+        const T kfc = lane_read(fc, src), kdfc = lane_read(dfc, src);
+        const int tk = NT1 ? 0 : lane_read(tj, src);
+        T gk[3] = {Zero<T>::get(), Zero<T>::get(), Zero<T>::get()};
+        if (in_pair && s < n_i) {
+          const KP &pk = param(ti, tj, tk);
+          if (val(kr) < pk.rcut) {
+            T fck = kfc, dfck = kdfc;
+            if (!a.cut_consistent) fcut(pk, kr, fck, dfck);
+            if (keep) {
+              T gj[3], dp[8];
+              zeta += zeta_term<T, B, false>(pk, r, ri, u, kr, kri, v, fck, dfck, gj, gk, dp);
+#pragma unroll
+              for (int c = 0; c < 3; ++c) gs[c] += gj[c];
+            } else {
+              zeta += zeta_value<T, B>(pk, r, u, kr, v, fck);
+            }
           }
-        } else if (act) {
-#pragma unroll
-          for (int k = 0; k < 7; ++k) atomic_add(&a.partials[(int64_t)cf * 8 + k], wv[k]);
         }
-      } else {
-        eacc += wv[0];
+        if (keep) {
 #pragma unroll
-        for (int k = 0; k < 6; ++k) wacc[k] += wv[k + 1];
-      }
-    }
-    // the force this slot hands to j as stored (rounded to the slot type in
-    // owner-gather mode); i's own force is minus the sum of these, so the
-    // forces of every term cancel exactly in the gathered total
-    double o0 = 0.0, o1 = 0.0, o2 = 0.0;
-    if (act && want_f) {
-      o0 = DUAL ? -out_of(f0, eb) : val(f0);
-      o1 = DUAL ? -out_of(f1, eb) : val(f1);
-      o2 = DUAL ? -out_of(f2, eb) : val(f2);
-      if (a.fslot) {
-        o0 = (double)(B)o0;
-        o1 = (double)(B)o1;
-        o2 = (double)(B)o2;
-        if (r_out >= 0) {
-          B *fs = (B *)a.fslot + 3 * (int64_t)r_out;
-          fs[0] = (B)o0;
-          fs[1] = (B)o1;
-          fs[2] = (B)o2;
+          for (int c = 0; c < 3; ++c) s_gk[kOnePass ? w : 0][keep ? s - 1 : 0][c][lane] = gk[c];
         }
-      } else {
-        double *dst = DUAL ? a.xgrad : a.forces;
-        atomic_add(&dst[3 * (int64_t)j + 0], o0);
-        atomic_add(&dst[3 * (int64_t)j + 1], o1);
-        atomic_add(&dst[3 * (int64_t)j + 2], o2);
       }
-    }
-    // own force of i (minus the sum of its slot forces; segmented sum over the
-    // atom's lanes) and per-atom energy, taken by the atom's first lane
-    EA sx = (EA)o0, sy = (EA)o1, sz = (EA)o2, se = ev;
-    for (int s = 1; s < nmax && (want_f || want_ea); ++s) {
-      const int src = (act && s < n_i) ? seg0 + s : lane;
-      EA tx = 0, ty = 0, tz = 0, te = 0;
-      if (want_f) {
-        tx = lane_read((EA)o0, src);
-        ty = lane_read((EA)o1, src);
-        tz = lane_read((EA)o2, src);
+      // pair term V(i, j, zeta)
+      T dzeta = Zero<T>::get();
+      FA f0 = Zero<FA>::get(), f1 = Zero<FA>::get(), f2 = Zero<FA>::get();
+      EA ev = 0;
+      const double eb = DUAL ? (a.ebar_conf ? a.ebar_conf[cf] : a.ebar) : 1.0;
+      if (in_pair) {
+        T fr, fa;
+        AT fre, fae;  // the same for the energy
+        if constexpr (std::is_same<T, float>::value && !SP) {  // mixed: FP64 exponentials
+          const double e1 = exp64(pp.A, pp.A_lo, pp.lam1, pp.lam1_lo, r, rlo);
+          const double e2 = exp64(pp.Bc, pp.B_lo, pp.lam2, pp.lam2_lo, r, rlo);
+          fr = (float)e1;
+          fa = -(float)e2;
+          fre = e1;
+          fae = -e2;
+        } else {
+          fr = scaled_exp(pp.A, pp.A_lo, pp.lam1, pp.lam1_lo, r, rlo);
+          fa = -scaled_exp(pp.Bc, pp.B_lo, pp.lam2, pp.lam2_lo, r, rlo);
+          fre = wide(fr);
+          fae = wide(fa);
+        }
+        T b, db, dbb, dbn;
+        bond<T, B, PG>(pp, zeta, b, db, dbb, dbn);
+        const T vr = fr + b * fa;
+        const AT V = wide(fc) * (fre + wide(b) * fae);
+        const T dVdr = dfc * vr + fc * (-pp.lam1 * fr - pp.lam2 * b * fa);
+        dzeta = B(0.5) * fc * fa * db;
+        const T hp = B(0.5) * dVdr;
+        f0 = to_fa(wide(-(hp * u[0])));
+        f1 = to_fa(wide(-(hp * u[1])));
+        f2 = to_fa(wide(-(hp * u[2])));
+        if (kOnePass) {
+          f0 -= to_fa(wide(dzeta * gs[0]));
+          f1 -= to_fa(wide(dzeta * gs[1]));
+          f2 -= to_fa(wide(dzeta * gs[2]));
+        }
+        ev = 0.5 * val(V);
+        if (PG) {
+          const T h = T(B(0.5)) * fc;
+          T dp[8];
+          dp[0] = h * fr * (B(1) / pp.A);
+          dp[1] = -h * r * fr;
+          dp[2] = h * b * fa * (B(1) / pp.Bc);
+          dp[3] = -h * b * r * fa;
+          dp[4] = h * fa * dbb;
+          dp[5] = h * fa * dbn;
+          dp[6] = -B(0.5) * dfc * vr;
+          dp[7] = -B(0.5) * dfc * (r - pp.R) * (B(1) / pp.D) * vr;
+#pragma unroll
+          for (int f = 0; f < 8; ++f) add_grad(ti, tj, tj, GradSlots::pair[f], out_of(wide(dp[f]), eb));
+        }
       }
-      if (want_ea) te = lane_read(ev, src);
-      if (act && q == 0 && s < n_i) {
-        sx += tx;
-        sy += ty;
-        sz += tz;
-        se += te;
+      // ---- second K loop: dzeta/dx, forces on j (kept) and on k (sent) -----------
+      for (int s = 1; s < nmax; ++s) {
+        const bool live = act && s < n_i;
+        const int kq = q + s < n_i ? q + s : q + s - n_i;      // k this lane treats
+        const int bq = q - s >= 0 ? q - s : q - s + n_i;       // lane whose k is me
+        const int src = live ? seg0 + kq : lane;
+        const int bsrc = live ? seg0 + bq : lane;
+        T cx = Zero<T>::get(), cy = Zero<T>::get(), cz = Zero<T>::get();  // force sent to k
+        if (kOnePass && s <= kKeep) {  // uniform: the term was evaluated in the first loop
+          if (live && in_pair && val(dzeta) != B(0)) {
+            const int sk = kOnePass && s <= kKeep ? s - 1 : 0;
+            cx = -(dzeta * s_gk[kOnePass ? w : 0][sk][0][lane]);
+            cy = -(dzeta * s_gk[kOnePass ? w : 0][sk][1][lane]);
+            cz = -(dzeta * s_gk[kOnePass ? w : 0][sk][2][lane]);
+          }
+        } else {
+        const T v[3] = {lane_read(ux, src), lane_read(uy, src), lane_read(uz, src)};
+        const T kr = lane_read(r, src), kri = lane_read(ri, src);
+        const T kfc = lane_read(fc, src), kdfc = lane_read(dfc, src);
+        const int tk = NT1 ? 0 : lane_read(tj, src);
+        if (live && in_pair && val(dzeta) != B(0)) {
+          const KP &pk = param(ti, tj, tk);
+          if (val(kr) < pk.rcut) {
+            T fck = kfc, dfck = kdfc;
+            if (!a.cut_consistent) fcut(pk, kr, fck, dfck);
+            T gj[3], gk[3], dp[8];
+            zeta_term<T, B, PG>(pk, r, ri, u, kr, kri, v, fck, dfck, gj, gk, dp);
+            f0 -= to_fa(wide(dzeta * gj[0]));
+            f1 -= to_fa(wide(dzeta * gj[1]));
+            f2 -= to_fa(wide(dzeta * gj[2]));
+            cx = -(dzeta * gk[0]);
+            cy = -(dzeta * gk[1]);
+            cz = -(dzeta * gk[2]);
+            if (PG) {
+#pragma unroll
+              for (int fl = 0; fl < 8; ++fl)
+                add_grad(ti, tj, tk, GradSlots::three[fl], out_of(wide(dzeta * dp[fl]), eb));
+            }
+          }
+        }
+        }
+        // pull the force that lane (i, bq) computed for my atom in this step
+        const T rx = lane_read(cx, bsrc), ry = lane_read(cy, bsrc), rz = lane_read(cz, bsrc);
+        if (live) {
+          f0 += to_fa(wide(rx));
+          f1 += to_fa(wide(ry));
+          f2 += to_fa(wide(rz));
+        }
       }
-    }
-    if (act && q == 0) {
-      if (want_f) {
-        if (a.fown) {  // indexed by position in cell order
-          double *fo = a.fown + 3 * (first + at);
-          fo[0] = -sx;
-          fo[1] = -sy;
-          fo[2] = -sz;
+
+      // ---- f_im complete: virial, scatter to j, own force of i ------------------
+      if (!DUAL && a.partials) {
+        EA wv[7] = {ev, 0, 0, 0, 0, 0, 0};
+        if (act && want_w) {
+          const EA ddx = val(wide(ux * r)), ddy = val(wide(uy * r)), ddz = val(wide(uz * r));
+          const EA fx = val(f0), fy = val(f1), fz = val(f2);
+          wv[1] = ddx * fx;
+          wv[2] = ddy * fy;
+          wv[3] = ddz * fz;
+          wv[4] = ddx * fy;
+          wv[5] = ddx * fz;
+          wv[6] = ddy * fz;
+        }
+        if (a.conf_of) {
+          // batches: per-configuration energy and virial; one atomic per value
+          // when the round belongs to one configuration, per lane otherwise
+          const int cf0 = __shfl(cf, 0, kWave);
+          if (__ballot(act && cf != cf0) == 0ull) {
+#pragma unroll
+            for (int k = 0; k < 7; ++k) {
+              const double sum = wave_sum(wv[k]);
+              if (lane == 0) atomic_add(&a.partials[(int64_t)cf0 * 8 + k], (double)sum);
+            }
+          } else if (act) {
+#pragma unroll
+            for (int k = 0; k < 7; ++k) atomic_add(&a.partials[(int64_t)cf * 8 + k], wv[k]);
+          }
+        } else {
+          eacc += wv[0];
+#pragma unroll
+          for (int k = 0; k < 6; ++k) wacc[k] += wv[k + 1];
+        }
+      }
+      // the force this slot hands to j as stored (rounded to the slot type in
+      // owner-gather mode); i's own force is minus the sum of these, so the
+      // forces of every term cancel exactly in the gathered total
+      double o0 = 0.0, o1 = 0.0, o2 = 0.0;
+      if (act && want_f) {
+        o0 = DUAL ? -out_of(f0, eb) : val(f0);
+        o1 = DUAL ? -out_of(f1, eb) : val(f1);
+        o2 = DUAL ? -out_of(f2, eb) : val(f2);
+        if (a.fslot) {
+          o0 = (double)(B)o0;
+          o1 = (double)(B)o1;
+          o2 = (double)(B)o2;
+          if (r_out >= 0) {
+            B *fs = (B *)a.fslot + 3 * (int64_t)r_out;
+            fs[0] = (B)o0;
+            fs[1] = (B)o1;
+            fs[2] = (B)o2;
+          }
         } else {
           double *dst = DUAL ? a.xgrad : a.forces;
-          atomic_add(&dst[3 * (int64_t)ia + 0], -sx);
-          atomic_add(&dst[3 * (int64_t)ia + 1], -sy);
-          atomic_add(&dst[3 * (int64_t)ia + 2], -sz);
+          atomic_add(&dst[3 * (int64_t)j + 0], o0);
+          atomic_add(&dst[3 * (int64_t)j + 1], o1);
+          atomic_add(&dst[3 * (int64_t)j + 2], o2);
         }
       }
-      if (want_ea) {
-        if (flags & TERS_ACCUMULATE) a.e_atom[ia] += se;
-        else a.e_atom[ia] = se;
+      // own force of i (minus the sum of its slot forces; segmented sum over the
+      // atom's lanes) and per-atom energy, taken by the atom's first lane
+      EA sx = (EA)o0, sy = (EA)o1, sz = (EA)o2, se = ev;
+      for (int s = 1; s < nmax && (want_f || want_ea); ++s) {
+        const int src = (act && s < n_i) ? seg0 + s : lane;
+        EA tx = 0, ty = 0, tz = 0, te = 0;
+        if (want_f) {
+          tx = lane_read((EA)o0, src);
+          ty = lane_read((EA)o1, src);
+          tz = lane_read((EA)o2, src);
+        }
+        if (want_ea) te = lane_read(ev, src);
+        if (act && q == 0 && s < n_i) {
+          sx += tx;
+          sy += ty;
+          sz += tz;
+          se += te;
+        }
       }
-    }
-    // atoms of the chunk without any in-cutoff neighbour: zero per-atom energy
-    // and, in owner-gather mode, zero own force
-    if (lane >= a0 && lane < a1 && my_n == 0) {
-      if (want_ea && !(flags & TERS_ACCUMULATE)) a.e_atom[my_a] = 0.0;
-      if (want_f && a.fown) {
-        double *fo = a.fown + 3 * (first + lane);
-        fo[0] = 0.0;
-        fo[1] = 0.0;
-        fo[2] = 0.0;
+      if (act && q == 0) {
+        if (want_f) {
+          if (a.fown) {  // indexed by position in cell order
+            double *fo = a.fown + 3 * (first + at);
+            fo[0] = -sx;
+            fo[1] = -sy;
+            fo[2] = -sz;
+          } else {
+            double *dst = DUAL ? a.xgrad : a.forces;
+            atomic_add(&dst[3 * (int64_t)ia + 0], -sx);
+            atomic_add(&dst[3 * (int64_t)ia + 1], -sy);
+            atomic_add(&dst[3 * (int64_t)ia + 2], -sz);
+          }
+        }
+        if (want_ea) {
+          if (flags & TERS_ACCUMULATE) a.e_atom[ia] += se;
+          else a.e_atom[ia] = se;
+        }
       }
+      // atoms of the chunk without any in-cutoff neighbour: zero per-atom energy
+      // and, in owner-gather mode, zero own force
+      if (lane >= a0 && lane < a1 && my_n == 0) {
+        if (want_ea && !(flags & TERS_ACCUMULATE)) a.e_atom[my_a] = 0.0;
+        if (want_f && a.fown) {
+          double *fo = a.fown + 3 * (first + lane);
+          fo[0] = 0.0;
+          fo[1] = 0.0;
+          fo[2] = 0.0;
+        }
+      }
+      wave_sync();
+      a0 = a1;
     }
-    wave_sync();
-    a0 = a1;
   }
+  if constexpr (PERSIST) {  // the next chunk, if any
+    ++item;
+    if (item >= run_end && !next_run()) goto done;
+    first = a.items[item].x;
+    na = a.items[item].y;
+    goto again;
+  }
+done:
 
   // ---- workgroup reductions ------------------------------------------------------
   if (!DUAL && a.partials && !a.conf_of) {
@@ -685,15 +746,44 @@ void launch_wave_t(const FwdArgs &a, int A, hipStream_t s) {
   constexpr int kWPB = waves_per_group<PG>();
   if (A <= 0 || A > kAMax) A = 16;
   const int64_t per_block = (int64_t)kWPB * A;
-  const int nb = (int)((a.n + per_block - 1) / per_block);
-  if (nb == 0) return;
-  if (a.ntypes == 1)
+  const int nb = a.items ? a.grid : (int)((a.n + per_block - 1) / per_block);
+  if (nb <= 0 || a.n == 0) return;
+  if (a.items) {
+    if (a.ntypes == 1)
+      k_force_wave<T, true, PG, SP, true><<<nb, kWPB * kWave, 0, s>>>(a, A);
+    else
+      k_force_wave<T, false, PG, SP, true><<<nb, kWPB * kWave, 0, s>>>(a, A);
+  } else if (a.ntypes == 1) {
     k_force_wave<T, true, PG, SP><<<nb, kWPB * kWave, 0, s>>>(a, A);
-  else
+  } else {
     k_force_wave<T, false, PG, SP><<<nb, kWPB * kWave, 0, s>>>(a, A);
+  }
+}
+
+// workgroups of one kernel resident on the whole device at once
+template <class T, bool PG>
+int resident_grid(bool nt1) {
+  int dev = 0, ncu = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  const auto kern = nt1 ? reinterpret_cast<const void *>(&k_force_wave<T, true, PG, false, true>)
+                        : reinterpret_cast<const void *>(&k_force_wave<T, false, PG, false, true>);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, waves_per_group<PG>() * kWave, 0) !=
+      hipSuccess)
+    return 0;
+  return ncu * std::max(per_cu, 1);
 }
 
 }  // namespace
+
+int wave_persistent_grid(int precision, bool adjoint, bool multi_species) {
+  const bool nt1 = !multi_species;
+  if (adjoint)
+    return precision == TERS_FP64 ? resident_grid<Dual<double>, true>(nt1)
+                                  : resident_grid<Dual<float>, true>(nt1);
+  return precision == TERS_FP64 ? resident_grid<double, false>(nt1) : resident_grid<float, false>(nt1);
+}
 
 int wave_blocks(int n, int A, bool pg) {
   if (A <= 0 || A > kAMax) A = 16;

@@ -139,6 +139,15 @@ struct FwdArgs {
   const int32_t *rev;
   int32_t *clear_flag;     // set to 0 by the kernel (molecular dynamics) or null
   uint32_t *err;
+  // persistent form of the wavefront schedule (batches): chunks (first
+  // cell-order position, atoms), items[0, qbound[8]), split into eight work
+  // queues; queue[x] counts what has been taken of [qbound[x], qbound[x + 1])
+  // and starts at 0.  Null: one chunk per wavefront from its workgroup id.
+  const int2 *items;
+  const int32_t *qbound;
+  int32_t *queue;
+  int32_t grid;            // persistent form: workgroups of the launch
+  int32_t grab;            // persistent form: items per atomic take (0: static shares)
 };
 
 // launchers (implemented in the .hip files)
@@ -161,6 +170,8 @@ int forward_blocks(int n, int atoms_per_block);
 void launch_forward_wave(const FwdArgs &a, int precision, int atoms_per_wave, hipStream_t s);
 void launch_adjoint_wave(const FwdArgs &a, int precision, int atoms_per_wave, hipStream_t s);
 int wave_blocks(int n, int atoms_per_wave, bool param_grad);
+// persistent form: workgroups that fill the device at the kernel's occupancy
+int wave_persistent_grid(int precision, bool adjoint, bool multi_species);
 // pair potential (truncated Lennard-Jones) over the list: one thread per atom
 // in cell order, own forces only (full list, no atomics)
 struct PairArgs {

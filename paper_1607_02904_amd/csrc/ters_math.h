@@ -154,12 +154,15 @@ DEV T zeta_term(const KParam<B> &p, T rij, T rinv_ij, const T *u, T rik, T rinv_
   T s2 = fge * de;
   T s3 = dfck * g * e;
   T s32 = s3 - s2;
+  // with d cos / d x_j = (v - cos u) / r_ij and d cos / d x_k = (u - cos v) / r_ik:
+  //   gj = s1 (v - cos u) / r_ij + s2 u = a1 v + b1 u,
+  //   gk = s1 (u - cos v) / r_ik + s32 v = a2 u + b2 v
+  const T a1 = s1 * rinv_ij, a2 = s1 * rinv_ik;
+  const T b1 = s2 - a1 * cs, b2 = s32 - a2 * cs;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    T dcj = (v[c] - cs * u[c]) * rinv_ij;
-    T dck = (u[c] - cs * v[c]) * rinv_ik;
-    gj[c] = s1 * dcj + s2 * u[c];
-    gk[c] = s1 * dck + s32 * v[c];
+    gj[c] = a1 * v[c] + b1 * u[c];
+    gk[c] = a2 * u[c] + b2 * v[c];
   }
   if (PG) {
     T fe = fck * e;

@@ -1,9 +1,11 @@
 """Summaries of rocprofv3 output for the force kernel.
 
-Two reports, both plain text:
+Three reports, all plain text:
 
 * ``stats``: the rows of a ``--kernel-trace --stats`` kernel_stats.csv for the
   kernels whose names contain the given filters;
+* ``mix``: average per dispatch of every counter of one or more ``--pmc``
+  runs (the instruction mix) for one kernel and grid size;
 * ``traffic``: HBM bytes per launch of one kernel from two ``--pmc`` runs
   (``FETCH_SIZE``, then ``WRITE_SIZE``, KiB per dispatch), each scaled by what
   the same counter reads for a plain device copy of known size in the same
@@ -13,6 +15,8 @@ Two reports, both plain text:
     python -m paper_1607_02904_amd.profsum stats STATS_CSV [FILTER ...]
     python -m paper_1607_02904_amd.profsum traffic FETCH_CSV WRITE_CSV \\
         --kernel NAME_PART --grid GRID --copy-bytes BYTES
+    python -m paper_1607_02904_amd.profsum mix PMC_CSV [PMC_CSV ...] \\
+        --kernel NAME_PART --grid GRID
 
 The copy kernel is the dispatch whose name contains ``copyBuffer`` and whose
 ``FETCH_SIZE`` is largest.
@@ -81,6 +85,26 @@ def traffic(fetch_csv, write_csv, kernel, grid, copy_bytes):
     return res
 
 
+def mix(paths, kernel, grid):
+    """{counter: average per dispatch} for the dispatches of one kernel and
+    grid size in one or more ``--pmc`` counter_collection.csv files."""
+    sums, counts = {}, {}
+    for path in paths:
+        per = {}
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                if kernel not in r["Kernel_Name"] or int(r["Grid_Size"]) != grid:
+                    continue
+                key = (r["Counter_Name"], int(r["Dispatch_Id"]))
+                per[key] = per.get(key, 0.0) + float(r["Counter_Value"])
+        for (name, _), v in per.items():
+            sums[name] = sums.get(name, 0.0) + v
+            counts[name] = counts.get(name, 0) + 1
+    if not sums:
+        raise SystemExit("no dispatches of %r (grid %d)" % (kernel, grid))
+    return {k: sums[k] / counts[k] for k in sums}, counts
+
+
 def read_summary(path):
     """key: value lines of a summary file (values as strings)."""
     out = {}
@@ -104,9 +128,21 @@ def main():
     t.add_argument("--kernel", required=True)
     t.add_argument("--grid", type=int, required=True)
     t.add_argument("--copy-bytes", type=float, required=True)
+    m = sub.add_parser("mix")
+    m.add_argument("csv", nargs="+")
+    m.add_argument("--kernel", required=True)
+    m.add_argument("--grid", type=int, required=True)
     a = ap.parse_args()
     if a.cmd == "stats":
         print("\n".join(stats(a.csv, a.filters)))
+    elif a.cmd == "mix":
+        r, counts = mix(a.csv, a.kernel, a.grid)
+        print("kernel: %s" % a.kernel)
+        print("grid: %d" % a.grid)
+        print("kernel_sources_sha256: %s" % kernel_hash())
+        print("dispatches: %d" % max(counts.values()))
+        for k in sorted(r):
+            print("%s: %.6g" % (k, r[k]))
     else:
         r = traffic(a.fetch_csv, a.write_csv, a.kernel, a.grid, a.copy_bytes)
         print("kernel: %s" % a.kernel)

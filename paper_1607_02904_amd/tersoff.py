@@ -420,9 +420,10 @@ class BatchPlan:
             _ptr(x_grad, name="x_grad", rows=N, cols=3), _ptr(param_grad, name="param_grad")))
 
     def schedule(self):
-        out = np.zeros(3)
+        out = np.zeros(6)
         _check(self.model._h, self._L.ters_plan_schedule(self._h, out.ctypes.data_as(ctypes.c_void_p)))
-        return dict(atoms=int(out[0]), kernel=int(out[1]), us=float(out[2]))
+        return dict(atoms=int(out[0]), kernel=int(out[1]), us=float(out[2]),
+                    adjoint_atoms=int(out[3]), adjoint_us=float(out[4]), workgroups=int(out[5]))
 
     def close(self):
         if getattr(self, "_h", None):

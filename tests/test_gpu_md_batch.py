@@ -199,7 +199,9 @@ def test_batch_extreme_sizes(orc, batch_setup):
     assert min(np.min(c[2]) for c in confs) < 8.0
     for precision in (0, 1):
         plan, (xd, td, e, f, w) = _run_plan(model, confs, precision)
-        print("batch extreme sizes, precision %d: schedule %s" % (precision, plan.schedule()))
+        sch = plan.schedule()
+        print("batch extreme sizes, precision %d: schedule %s" % (precision, sch))
+        assert sch["kernel"] == 2 and sch["workgroups"] > 0  # the persistent launch
         _check_batch(orc, confs, plan.offsets, e.cpu().numpy(), f.cpu().numpy(),
                      w.cpu().numpy(), precision)
         plan.close()
