@@ -169,6 +169,7 @@ void nl_setup(NList &nl, int nconf, const int32_t *natoms, const double *boxes, 
   nl.skin = skin;
   nl.conf_h.resize(nconf);
   nl.box_max = 0.0;
+  nl.small_axis = false;
   int64_t cells = 0, atoms = 0;
   for (int c = 0; c < nconf; ++c) {
     ConfDesc d{};
@@ -186,6 +187,7 @@ void nl_setup(NList &nl, int nconf, const int32_t *natoms, const double *boxes, 
     d.atom_off = (int32_t)atoms;
     d.natoms = natoms[c];
     nl.box_max = std::max({nl.box_max, d.box[0], d.box[1], d.box[2]});
+    nl.small_axis |= d.nc[0] < 3 || d.nc[1] < 3 || d.nc[2] < 3;
     cells += (int64_t)d.nc[0] * d.nc[1] * d.nc[2];
     atoms += natoms[c];
     nl.conf_h[c] = d;
@@ -215,9 +217,11 @@ void nl_setup(NList &nl, int nconf, const int32_t *natoms, const double *boxes, 
   nl.xref.ensure(sizeof(double) * 3 * nn);
   nl.xs.ensure(sizeof(float) * 4 * nn);
   nl.pos.ensure(sizeof(int32_t) * nn);
+  nl.cell_at.ensure(sizeof(int32_t) * nn);
+  nl.srange.ensure(sizeof(int32_t) * 2 * nn);
+  nl.plist.ensure(sizeof(int32_t) * nn * nl.cap);
   nl.soff.ensure(sizeof(int32_t) * (nn + 1));
-  nl.loff.ensure(sizeof(int32_t) * nn);
-  nl.bsum.ensure(sizeof(int32_t) * 2 * 4096);
+  nl.bsum.ensure(sizeof(int32_t) * 2 * (nn / 1024 + 1));
   nl.maxcount.ensure(sizeof(int32_t));
   nl.rev.ensure(sizeof(int32_t) * nn * nl.cap);
 }
@@ -245,6 +249,7 @@ void nl_build_sync(ters_ctx *c, NList &nl, const double *x, const int32_t *type,
     nl.cap = cap;
     nl.list.ensure(sizeof(int32_t) * (size_t)std::max(nl.n, 1) * cap);
     nl.rev.ensure(sizeof(int32_t) * (size_t)std::max(nl.n, 1) * cap);
+    nl.plist.ensure(sizeof(int32_t) * (size_t)std::max(nl.n, 1) * cap);
   }
   fail(TERS_ERR_NLIST_OVERFLOW, "neighbour list did not converge");
 }
@@ -300,7 +305,7 @@ std::vector<const void *> graph_key(const ters_ctx *c, const NList &nl) {
           (const void *)(intptr_t)c->cut_consistent, (const void *)(intptr_t)c->kmax,
           (const void *)(intptr_t)c->filter,
           c->partials.p, c->errw.p, c->flag.p, c->rebuilds.p, c->step.p, c->escratch.p,
-          nl.rev.p, nl.xs.p, nl.pos.p, nl.soff.p, nl.loff.p, nl.bsum.p, c->fslot.p, c->fown.p,
+          nl.rev.p, nl.xs.p, nl.pos.p, nl.soff.p, nl.bsum.p, nl.cell_at.p, nl.plist.p, nl.srange.p, c->fslot.p, c->fown.p,
           (const void *)(intptr_t)c->gather};
 }
 
@@ -389,9 +394,10 @@ constexpr size_t al(size_t b) { return (b + kAlign - 1) / kAlign * kAlign; }
 constexpr size_t kN = TERS_STATIC_MAX_ATOMS;
 // bytes of every scratch buffer at the largest size (layout of carve_static)
 constexpr size_t kStaticBytes =
-    al(sizeof(ConfDesc)) + 5 * al(4 * kN) + al(4 * (kN + 1)) + 2 * al(4 * kN * kStaticCap) +
-    2 * al(4 * (kStaticCells + 1)) + al(4 * ((kStaticCells + 1) / 1024 + 2)) + al(24 * kN) +
-    al(16 * kN) + al(4 * 2 * 4096) + al(4) + al(64 * kN) + al(24 * kN * kStaticCap) + al(24 * kN);
+    al(sizeof(ConfDesc)) + 5 * al(4 * kN) + al(8 * kN) + al(4 * (kN + 1)) +
+    3 * al(4 * kN * kStaticCap) + 2 * al(4 * (kStaticCells + 1)) +
+    al(4 * ((kStaticCells + 1) / 1024 + 2)) + al(24 * kN) + al(16 * kN) +
+    al(4 * 2 * (kN / 1024 + 1)) + al(4) + al(64 * kN) + al(24 * kN * kStaticCap) + al(24 * kN);
 
 // One copy per GPU, held until the process ends.  In host code this name is
 // only a stand-in: kernels get the device address from hipGetSymbolAddress.
@@ -485,7 +491,7 @@ ters_status ters_destroy(ters_ctx *c) {
                     &c->nl.conf_of, &c->nl.count, &c->nl.list, &c->nl.order, &c->nl.cell_of,
                     &c->nl.cell_count, &c->nl.cell_start, &c->nl.scan_tmp, &c->nl.xref,
                     &c->nl.maxcount, &c->nl.rev, &c->nl.xs, &c->nl.pos, &c->nl.soff,
-                    &c->nl.loff, &c->nl.bsum};
+                    &c->nl.bsum, &c->nl.cell_at, &c->nl.plist, &c->nl.srange};
   for (DevBuf *b : bufs) b->release();
   delete c;
   return TERS_OK;
@@ -768,16 +774,18 @@ ters_status ters_compute_static(ters_ctx *c, int32_t n, const double *x, const i
     nl.order = cv.take(4 * N);
     nl.cell_of = cv.take(4 * N);
     nl.pos = cv.take(4 * N);
-    nl.loff = cv.take(4 * N);
+    nl.cell_at = cv.take(4 * N);
+    nl.srange = cv.take(8 * N);
     nl.soff = cv.take(4 * (N + 1));
     nl.list = cv.take(4 * N * kStaticCap);
     nl.rev = cv.take(4 * N * kStaticCap);
+    nl.plist = cv.take(4 * N * kStaticCap);
     nl.cell_count = cv.take(4 * (kStaticCells + 1));
     nl.cell_start = cv.take(4 * (kStaticCells + 1));
     nl.scan_tmp = cv.take(4 * ((kStaticCells + 1) / 1024 + 2));
     nl.xref = cv.take(24 * N);
     nl.xs = cv.take(16 * N);
-    nl.bsum = cv.take(4 * 2 * 4096);
+    nl.bsum = cv.take(4 * 2 * (N / 1024 + 1));
     nl.maxcount = cv.take(4);
     DevBuf partials = cv.take(64 * N);
     DevBuf fslot = cv.take(24 * N * kStaticCap);
@@ -791,6 +799,7 @@ ters_status ters_compute_static(ters_ctx *c, int32_t n, const double *x, const i
     nl.skin = 0.0;
     nl.valid = true;
     nl.box_max = std::max({d.box[0], d.box[1], d.box[2]});
+    nl.small_axis = d.nc[0] < 3 || d.nc[1] < 3 || d.nc[2] < 3;
     hipStream_t s = c->stream;
     k_put_conf<<<1, 1, 0, s>>>(d, nl.conf.as<ConfDesc>());
     TERS_HIP_TRY(hipGetLastError());
@@ -1423,7 +1432,7 @@ static void plan_release_device(ters_plan *p) {
                     &p->nl.conf_of, &p->nl.count, &p->nl.list, &p->nl.order, &p->nl.cell_of,
                     &p->nl.cell_count, &p->nl.cell_start, &p->nl.scan_tmp, &p->nl.xref,
                     &p->nl.maxcount, &p->nl.rev, &p->nl.xs, &p->nl.pos, &p->nl.soff,
-                    &p->nl.loff, &p->nl.bsum};
+                    &p->nl.bsum, &p->nl.cell_at, &p->nl.plist, &p->nl.srange};
   for (DevBuf *b : bufs) b->release();
   p->ctx = nullptr;
 }

@@ -425,12 +425,25 @@ again:
 #pragma unroll
         for (int k = 0; k < 3; ++k)
           dT[k] = Conv<T>::from(d[k], (DUAL && act) ? (a.fbar[3 * j + k] - a.fbar[3 * ia + k]) : 0.0);
-        r = t_sqrt(dT[0] * dT[0] + dT[1] * dT[1] + dT[2] * dT[2]);
         if constexpr (SP) {
+          r = t_sqrt(dT[0] * dT[0] + dT[1] * dT[1] + dT[2] * dT[2]);
           ri = rcp(r);
           fcut(param(ti, tj, tj), r, fc, dfc);
           rlo = B(0);
+        } else if constexpr (std::is_same<T, float>::value) {
+          // mixed: the FP64 distance from the hardware FP32 square root and
+          // one Newton step in FP64 (relative error ~1e-14, far below what
+          // the FP32 arithmetic downstream resolves)
+          const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+          const float r32 = __builtin_amdgcn_sqrtf((float)r2);
+          const double rr = (double)r32;
+          const double r64 = fma(fma(-rr, rr, r2), (double)(0.5f * __builtin_amdgcn_rcpf(r32)), rr);
+          r = (float)r64;
+          ri = rcp(r);
+          fcut64(param(ti, tj, tj), r, r64, fc, dfc);
+          rlo = (B)(r64 - (double)r);
         } else {
+          r = t_sqrt(dT[0] * dT[0] + dT[1] * dT[1] + dT[2] * dT[2]);
           const double r64 = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
           set_val(r, r64);
           ri = rcp(r);
@@ -643,11 +656,17 @@ again:
       }
       // own force of i (minus the sum of its slot forces; segmented sum over the
       // atom's lanes) and per-atom energy, taken by the atom's first lane
+      // (slot values rounded to FP32 travel as FP32: one permute each)
+      const bool o32 = std::is_same<B, float>::value && !DUAL && a.fslot != nullptr;
       EA sx = (EA)o0, sy = (EA)o1, sz = (EA)o2, se = ev;
       for (int s = 1; s < nmax && (want_f || want_ea); ++s) {
         const int src = (act && s < n_i) ? seg0 + s : lane;
         EA tx = 0, ty = 0, tz = 0, te = 0;
-        if (want_f) {
+        if (want_f && o32) {
+          tx = (EA)lane_read((float)o0, src);
+          ty = (EA)lane_read((float)o1, src);
+          tz = (EA)lane_read((float)o2, src);
+        } else if (want_f) {
           tx = lane_read((EA)o0, src);
           ty = lane_read((EA)o1, src);
           tz = lane_read((EA)o2, src);

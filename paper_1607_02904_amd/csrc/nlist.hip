@@ -218,15 +218,16 @@ __global__ void k_place(int n, const double *__restrict__ x, const int32_t *__re
 
 // order atoms inside each cell by index, record each atom's position in the
 // cell order (pos, the inverse of order) and copy the positions in that order
-// for the build (xs: FP32, wrapped into the configuration's box; the build's
-// distance test allows for that rounding); the counts (used as placement
-// cursors) are cleared for
-// the next build
+// for the build (xs: FP32, wrapped into the configuration's box, with the
+// atom index in the fourth word; the build's distance test allows for that
+// rounding) together with the cell of each position (cell_at); the counts
+// (used as placement cursors) are cleared for the next build
 __global__ void k_sort_cells(int64_t ncell, const int32_t *__restrict__ cell_start,
                              int32_t *__restrict__ order, int32_t *__restrict__ counts,
                              const double *__restrict__ x, const ConfDesc *__restrict__ conf,
                              const int32_t *__restrict__ conf_of, float4 *__restrict__ xs,
-                             int32_t *__restrict__ pos, const int32_t *cond) {
+                             int32_t *__restrict__ cell_at, int32_t *__restrict__ pos,
+                             const int32_t *cond) {
   if (skip(cond)) return;
   for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < ncell;
        c += (int64_t)gridDim.x * blockDim.x) {
@@ -250,312 +251,338 @@ __global__ void k_sort_cells(int64_t ncell, const int32_t *__restrict__ cell_sta
         const double v = x[3 * i + a];
         w[a] = (float)(v - cf.box[a] * floor(v * cf.inv_box[a]));
       }
-      xs[p] = make_float4(w[0], w[1], w[2], 0.f);
+      xs[p] = make_float4(w[0], w[1], w[2], __int_as_float(i));
+      cell_at[p] = (int32_t)c;
     }
     counts[c] = 0;
   }
 }
 
-DEV int wrap_cell(int q, int nc) { return q < 0 ? q + nc : (q >= nc ? q - nc : q); }
-
-// Seven atoms per wavefront (cell order), nine lanes per atom: lane r of an
-// atom takes the row (oz, oy) = (r / 3 - 1, r % 3 - 1) of neighbour cells
-// (z-major, the order the rows of the list keep; one offset along an axis with
-// fewer than 3 cells).  The cells ox = -1, 0, +1 of a row are consecutive cell
-// indices except across the periodic seam, so their atoms form at most two
-// runs of the cell-ordered position copy xs.  A first pass counts each lane's
-// hits (the first 64 also as a bit mask), an exclusive scan over the atom's
-// nine lanes gives every lane its first position in the row, and a second pass
-// writes the hits there.
+// One thread per atom, taken in cell order; workgroups are dealt to the XCDs
+// in contiguous ranges of the cell order.  For each row (oz, oy) of neighbour
+// cells, walked in z-major order (one offset along an axis with fewer than 3
+// cells), the atom's candidates form a near run (the cells ox = -1, 0, +1 of
+// its own column that lie on the same side of the periodic seam, consecutive
+// in the cell-ordered position copy xs, whose fourth word holds the atom
+// index) and, next to the seam, a far run (the cell across it).  Consecutive
+// threads share most of their candidates, so the fetches of a wavefront fall
+// on a few cache lines.
+//
+// With at least 3 cells along every axis, the periodic image of a candidate
+// is fixed by its cell: the displacement is (x_k - x_i) + s with s = 0 or
+// +-box per axis, taken from the row (y, z) and the run (x); with fewer cells
+// along some axis (MINIMG: some configuration of the set has such an axis)
+// the minimum image is taken per candidate.  Either form is exactly negated
+// for the pair (k, i), so the list is symmetric.
+//
+// Hits are taken in the order (row, near run, far run, position): the
+// neighbour's atom index goes to the list row and its position to the plist
+// row.  With LDSOUT (list capacity up to 16) the rows are collected in LDS and
+// copied out with 16-byte stores; otherwise each entry is stored as found.
 //
 // Rows and counts are indexed by cell-order position: row t lists the
 // neighbours (atom indices) of the atom at position t, so that the rows of a
-// run of atoms that a force wavefront takes are contiguous.
-//
-// Incoming force slots (min(count, cap) per atom) are laid out without row
-// padding: each workgroup numbers its atoms' slots from 0 in processing order
-// (loff, packed with the workgroup's id) and leaves its total and its longest
-// row in bsum; k_reverse turns these into global offsets.  No atomics.
-constexpr int kRows = 9;
-constexpr int kAtomsPerWave = kWave / kRows;  // 7
-constexpr int kBuildMaxBlocks = 4096;         // bsum holds 2 ints per block
-constexpr int kLoffBits = 19;                 // slots numbered within a workgroup
+// run of atoms that a force wavefront takes are contiguous.  The incoming
+// force slots are numbered afterwards by a scan of the row lengths
+// (k_slot_tiles, k_slot_add).
+DEV int wrap_cell(int q, int nc) { return q < 0 ? q + nc : (q >= nc ? q - nc : q); }
+
+template <bool LDSOUT, bool MINIMG>
 __global__ __launch_bounds__(kBS) void k_build(int n, const float4 *__restrict__ xs,
+                                               const int32_t *__restrict__ cell_at,
                                                const ConfDesc *__restrict__ conf,
                                                const int32_t *__restrict__ conf_of,
-                                               const int32_t *__restrict__ order,
-                                               const int32_t *__restrict__ cell_of,
                                                const int32_t *__restrict__ cell_start,
                                                float rl2, int cap, int32_t *__restrict__ count,
                                                int32_t *__restrict__ list,
-                                               int32_t *__restrict__ loff,
-                                               int32_t *__restrict__ bsum, const int32_t *cond,
+                                               int32_t *__restrict__ plist, const int32_t *cond,
                                                uint32_t *err, int64_t *rebuilds) {
   if (skip(cond)) return;
+  extern __shared__ int4 obuf4[];  // LDSOUT: [wave][2][64 * cap] int32: atom indices, positions
   if (blockIdx.x == 0 && threadIdx.x == 0 && rebuilds) *rebuilds += 1;
-  __shared__ int s_wmax[kBS / kWave];
   const int lane = lane_id(), w = threadIdx.x / kWave;
-  const int la = lane / kRows, r = lane - kRows * la;  // atom of the wave (7 = idle lane), row
-  const int last = min(kRows * la + kRows - 1, kWave - 1);  // the atom's row-8 lane
-  constexpr int kWPB = kBS / kWave;
-  const int blk = xcd_block(blockIdx.x, gridDim.x);
-  const int64_t ngroups = (n + kAtomsPerWave - 1) / kAtomsPerWave;
-  // each workgroup takes one contiguous range of groups of atoms in cell order
-  // (so slot numbers, and off, increase along the cell order, and each XCD
-  // works on one contiguous range whose neighbour cells share its L2); every
-  // lane runs the same number of passes (workgroup scan below)
-  const int64_t per_blk = (ngroups + gridDim.x - 1) / gridDim.x;
-  const int iters = (int)((per_blk + kWPB - 1) / kWPB);
-  const int64_t gend = min((int64_t)(blk + 1) * per_blk, ngroups);
-  int worst = 0, run = 0;  // longest row; slots numbered so far in this workgroup
-  for (int it = 0; it < iters; ++it) {
-    const int64_t g = (int64_t)blk * per_blk + (int64_t)it * kWPB + w;
-    const int64_t t64 = g * kAtomsPerWave + la;
-    const bool act = g < gend && la < kAtomsPerWave && t64 < n;
-    const int t = act ? (int)t64 : -1;
-    int i = 0, b0 = 0, e0 = 0, b1 = 0, e1 = 0;
-    float xi = 0.f, yi = 0.f, zi = 0.f;
-    const ConfDesc *c = conf;
-    if (act) {
-      i = order[t];
-      c = conf + conf_index(conf_of, i);
-      const float4 q = xs[t];
-      xi = q.x;
-      yi = q.y;
-      zi = q.z;
-      const int lc = cell_of[i] - c->cell_off;
-      const int nx = c->nc[0], ny = c->nc[1], nz = c->nc[2];
-      const int cx = lc % nx, cy = (lc / nx) % ny, cz = lc / (nx * ny);
-      const int oz = r / 3 - 1, oy = r % 3 - 1;
-      if ((nz >= 3 || oz == 0) && (ny >= 3 || oy == 0)) {
-        const int rc = c->cell_off + (wrap_cell(cz + oz, nz) * ny + wrap_cell(cy + oy, ny)) * nx;
-        int c0, c1, c2 = 0, c3 = 0;  // runs [c0, c1) and [c2, c3) of cells
-        if (nx < 3) {
-          c0 = rc + cx;
-          c1 = c0 + 1;
-        } else if (cx == 0) {
-          c0 = rc + nx - 1;
-          c1 = rc + nx;
-          c2 = rc;
-          c3 = rc + 2;
-        } else if (cx == nx - 1) {
-          c0 = rc + cx - 1;
-          c1 = rc + nx;
-          c2 = rc;
-          c3 = rc + 1;
-        } else {
-          c0 = rc + cx - 1;
-          c1 = rc + cx + 2;
-        }
-        b0 = cell_start[c0];
-        e0 = cell_start[c1];
-        if (c3 > c2) {
-          b1 = cell_start[c2];
-          e1 = cell_start[c3];
-        }
-      }
-    }
-    const int len0 = e0 - b0, len = len0 + (e1 - b1);
-    const float bx = (float)c->box[0], by = (float)c->box[1], bz = (float)c->box[2];
-    const float ibx = (float)c->inv_box[0], iby = (float)c->inv_box[1], ibz = (float)c->inv_box[2];
-    // minimum image in FP32 (the squared radius carries a margin for the
-    // rounding, so the list is a superset of the exact one); exactly negated
-    // for (j, i), so the list is symmetric
-    auto within_at = [&](int p, float px, float py, float pz) {
-      float dx = px - xi, dy = py - yi, dz = pz - zi;
-      dx -= bx * rintf(dx * ibx);
-      dy -= by * rintf(dy * iby);
-      dz -= bz * rintf(dz * ibz);
-      return p != t && dx * dx + dy * dy + dz * dz <= rl2;
-    };
-    auto within = [&](int p) {
-      const float4 q = xs[p];
-      return within_at(p, q.x, q.y, q.z);
-    };
-    // pass 1: count (the first 64 hits of the runs also as a mask); the
-    // positions of four candidates are fetched before any is tested
-    int nhit = 0;
-    uint64_t mask = 0;
-    for (int k0 = 0; k0 < len; k0 += 4) {
-      float4 q[4];
-      int pp[4];
+  const int64_t wbase = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kBS + w * kWave;
+  const bool act = wbase + lane < n;
+  const int t = act ? (int)(wbase + lane) : n - 1;  // idle lanes shadow the last atom, store nothing
+  const float4 qi = xs[t];
+  const int cell = cell_at[t];
+  const ConfDesc &c = conf[conf_index(conf_of, __float_as_int(qi.w))];
+  const int lc = cell - c.cell_off;
+  const int nx = c.nc[0], ny = c.nc[1], nz = c.nc[2];
+  const int cx = lc % nx, cy = (lc / nx) % ny, cz = lc / (nx * ny);
+  const float bx = (float)c.box[0], by = (float)c.box[1], bz = (float)c.box[2];
+  const float ibx = (float)c.inv_box[0], iby = (float)c.inv_box[1], ibz = (float)c.inv_box[2];
+  const bool fixed = nx >= 3 && ny >= 3 && nz >= 3;  // image fixed by the cell
+  const bool kind_a = nx >= 3 && cx == nx - 1, kind_b = nx >= 3 && cx == 0;
+  const float sfx = kind_b ? -bx : (kind_a ? bx : 0.f);  // image shift of the far run
+  int nb[9], ne[9], fb[9], fe[9];  // near and far runs of positions
+  float sy[9], sz[9];              // image shifts of the row
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int k = min(k0 + u, len - 1);
-        pp[u] = k < len0 ? b0 + k : b1 + (k - len0);
-        q[u] = xs[pp[u]];
+  for (int r = 0; r < 9; ++r) {
+    const int oz = r / 3 - 1, oy = r % 3 - 1;
+    nb[r] = ne[r] = fb[r] = fe[r] = 0;
+    sy[r] = cy + oy < 0 ? -by : (cy + oy >= ny ? by : 0.f);
+    sz[r] = cz + oz < 0 ? -bz : (cz + oz >= nz ? bz : 0.f);
+    if ((nz >= 3 || oz == 0) && (ny >= 3 || oy == 0)) {
+      const int rc = c.cell_off + (wrap_cell(cz + oz, nz) * ny + wrap_cell(cy + oy, ny)) * nx;
+      int c0, c1, c2 = 0, c3 = 0;  // near cells [c0, c1), far cells [c2, c3)
+      if (nx < 3) {
+        c0 = rc + cx;
+        c1 = c0 + 1;
+      } else if (kind_b) {
+        c0 = rc;
+        c1 = rc + 2;
+        c2 = rc + nx - 1;
+        c3 = rc + nx;
+      } else if (kind_a) {
+        c0 = rc + cx - 1;
+        c1 = rc + nx;
+        c2 = rc;
+        c3 = rc + 1;
+      } else {
+        c0 = rc + cx - 1;
+        c1 = rc + cx + 2;
       }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int k = k0 + u;
-        if (k < len && within_at(pp[u], q[u].x, q[u].y, q[u].z)) {
-          ++nhit;
-          if (k < 64) mask |= 1ull << k;
-        }
-      }
-    }
-    // exclusive scan over the atom's nine lanes
-    int incl = nhit;
-#pragma unroll
-    for (int o = 1; o < 16; o <<= 1) {
-      const int u = __shfl_up(incl, o, kWave);
-      if (r >= o) incl += u;
-    }
-    const int total = __shfl(incl, last, kWave);
-    // pass 2: write the hits from the row position of this lane on
-    if (act) {
-      int32_t *row = list + (int64_t)t * cap;
-      int pos = incl - nhit;
-      while (mask) {
-        const int k = __ffsll((unsigned long long)mask) - 1;
-        mask &= mask - 1ull;
-        const int p = k < len0 ? b0 + k : b1 + (k - len0);
-        if (pos < cap) row[pos] = order[p];
-        ++pos;
-      }
-      for (int k = 64; k < len; ++k) {  // rows of more than 64 candidates
-        const int p = k < len0 ? b0 + k : b1 + (k - len0);
-        if (within(p)) {
-          if (pos < cap) row[pos] = order[p];
-          ++pos;
-        }
+      nb[r] = cell_start[c0];
+      ne[r] = cell_start[c1];
+      if (c3 > c2) {
+        fb[r] = cell_start[c2];
+        fe[r] = cell_start[c3];
       }
     }
-    const bool owner = act && r == kRows - 1;
-    if (owner) {
-      count[t] = total;
-      if (total > cap) atomicOr(err, kErrNlistOverflow);
-    }
-    worst = max(worst, owner ? total : 0);
-    // slots of this pass, numbered after those of the earlier passes
-    int tot;
-    const int ex = block_excl_scan(owner ? min(total, cap) : 0, &tot);
-    if (owner) loff[t] = (int32_t)(((uint32_t)blk << kLoffBits) | (uint32_t)(run + ex));
-    run += tot;
   }
-  // the workgroup's slot total and longest row
-  int m = worst;
+
+  int32_t *oid = reinterpret_cast<int32_t *>(obuf4) + (size_t)w * 2 * kWave * cap;
+  int32_t *opos = oid + kWave * cap;
+  int32_t *row = list + (int64_t)t * cap;
+  int32_t *prow = plist + (int64_t)t * cap;
+  int cnt = 0;
+  constexpr int U = 4;
+  // one row per pass; the per-row values rotate down so that the body reads slot 0
+#pragma nounroll
+  for (int r = 0; r < 9; ++r) {
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o, kWave));
-  if (lane == 0) s_wmax[w] = m;
+    for (int seg = 0; seg < 2; ++seg) {  // near run, far run
+      const int b = seg ? fb[0] : nb[0], e = seg ? fe[0] : ne[0];
+      const float sx = seg ? sfx : 0.f;
+      for (int k0 = b; k0 < e; k0 += U) {
+        float4 q[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) q[u] = xs[min(k0 + u, e - 1)];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          float dx = q[u].x - qi.x, dy = q[u].y - qi.y, dz = q[u].z - qi.z;
+          if (!MINIMG) {
+            dx += sx;
+            dy += sy[0];
+            dz += sz[0];
+          } else {  // the form is a property of the configuration, the same for (k, i)
+            dx = fixed ? dx + sx : dx - bx * rintf(dx * ibx);
+            dy = fixed ? dy + sy[0] : dy - by * rintf(dy * iby);
+            dz = fixed ? dz + sz[0] : dz - bz * rintf(dz * ibz);
+          }
+          const int p = k0 + u;
+          if (p < e && p != t && dx * dx + dy * dy + dz * dz <= rl2) {
+            if (LDSOUT && cnt < cap) {
+              oid[lane * cap + cnt] = __float_as_int(q[u].w);
+              opos[lane * cap + cnt] = p;
+            } else if (!LDSOUT && act && cnt < cap) {
+              row[cnt] = __float_as_int(q[u].w);
+              prow[cnt] = p;
+            }
+            ++cnt;
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      nb[j] = nb[j + 1];
+      ne[j] = ne[j + 1];
+      fb[j] = fb[j + 1];
+      fe[j] = fe[j + 1];
+      sy[j] = sy[j + 1];
+      sz[j] = sz[j + 1];
+    }
+  }
+  if (act) {
+    count[t] = cnt;
+    if (cnt > cap) atomicOr(err, kErrNlistOverflow);
+  }
+  if (!LDSOUT) return;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    int bm = 0;
-    for (int k = 0; k < kWPB; ++k) bm = max(bm, s_wmax[k]);
-    bsum[2 * blk] = run;
-    bsum[2 * blk + 1] = bm;
+  // copy the wavefront's rows out: rows wbase .. wbase + 63 are contiguous
+  const int rows = (int)min<int64_t>(kWave, n - wbase);
+  const int q4 = cap / 4;  // 16-byte pieces per row
+  int4 *gl = reinterpret_cast<int4 *>(list + wbase * cap);
+  int4 *gp = reinterpret_cast<int4 *>(plist + wbase * cap);
+  const int4 *li = reinterpret_cast<const int4 *>(oid);
+  const int4 *lp = reinterpret_cast<const int4 *>(opos);
+  for (int k = lane; k < rows * q4; k += kWave) {
+    gl[k] = li[k];
+    gp[k] = lp[k];
   }
 }
 
-// Global slot offsets and the reverse map (rows, counts and slot records are
-// indexed by cell-order position, row entries are atoms).  Every workgroup
-// first scans the build's per-workgroup slot totals (nb <= kBuildMaxBlocks,
-// in LDS), so the first slot of the atom at position t is off(t) = (slots of
-// earlier build workgroups) + (t's number within its own); workgroup 0 also
-// stores the longest row.  Then, per position t: soff[t] = off(t) (slots
-// increase along the cell order, so t's are [soff[t], soff[t + 1])), and
-// rev[t*cap + s] = incoming force slot at atom j = list[t*cap + s] that holds
-// the force of t's terms on j: off(pos[j]) + (place of order[t] in row pos[j]).  The list
-// is symmetric by construction (r_ij and r_ji are computed from exactly
-// negated displacements), so the position exists; a missing one is latched as
-// an error.  The rows of 4 neighbours are searched together with 16-byte
-// loads (rows start 16-byte aligned: cap is a multiple of 4).
-__global__ __launch_bounds__(kBS) void k_reverse(int n, int cap, const int32_t *__restrict__ order,
-                                                 const int32_t *__restrict__ pos,
-                                                 const int32_t *__restrict__ count,
-                                                 const int32_t *__restrict__ list,
-                                                 const int32_t *__restrict__ loff,
-                                                 const int32_t *__restrict__ bsum, int nb,
-                                                 int32_t *__restrict__ soff,
-                                                 int32_t *__restrict__ rev,
-                                                 int32_t *__restrict__ maxcount, const int32_t *cond,
-                                                 uint32_t *err) {
+// Incoming force slots, numbered along the cell order without row padding:
+// the atom at position t owns [soff[t], soff[t + 1]) with
+// soff[t] = sum of min(count, cap) over earlier positions; the pair
+// (soff[t], soff[t + 1]) is also kept as one 8-byte word per position (srange)
+// for the reverse map.  Tiles of
+// kScanTile positions: exclusive scan within the tile, tile sums and longest
+// rows in tile_sum[2 * tile], tile_sum[2 * tile + 1]; then every tile adds the
+// sum of the earlier tiles, the last writes soff[n], and tile 0 writes the
+// longest row of all (maxcount).
+__global__ __launch_bounds__(kBS) void k_slot_tiles(const int32_t *__restrict__ count, int cap,
+                                                    int n, int32_t *__restrict__ soff,
+                                                    int32_t *__restrict__ tile_sum,
+                                                    const int32_t *cond) {
   if (skip(cond)) return;
-  __shared__ int s_pre[kBuildMaxBlocks];
-  {
-    constexpr int kPer = kBuildMaxBlocks / kBS;
-    const int b0 = threadIdx.x * kPer;
-    int v[kPer];
-    int sum = 0, mx = 0;
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * kScanPer;
+  int v[kScanPer];
+  int sum = 0, mx = 0;
 #pragma unroll
-    for (int k = 0; k < kPer; ++k) {
-      const bool in = b0 + k < nb;
-      v[k] = in ? bsum[2 * (b0 + k)] : 0;
-      mx = max(mx, in ? bsum[2 * (b0 + k) + 1] : 0);
-      sum += v[k];
-    }
-    int tot;
-    int run = block_excl_scan(sum, &tot);
+  for (int k = 0; k < kScanPer; ++k) {
+    const int c = (base + k < n) ? count[base + k] : 0;
+    mx = max(mx, c);
+    v[k] = min(c, cap);
+    sum += v[k];
+  }
+  int tot;
+  int off = block_excl_scan(sum, &tot);
 #pragma unroll
-    for (int k = 0; k < kPer; ++k) {
-      s_pre[b0 + k] = run;
-      run += v[k];
-    }
+  for (int k = 0; k < kScanPer; ++k) {
+    if (base + k < n) soff[base + k] = off;
+    off += v[k];
+  }
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) mx = max(mx, __shfl_xor(mx, o, kWave));
-    __shared__ int s_mx[kBS / kWave];
-    if (lane_id() == 0) s_mx[threadIdx.x / kWave] = mx;
-    __syncthreads();
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      int m = 0;
-      for (int k = 0; k < kBS / kWave; ++k) m = max(m, s_mx[k]);
-      *maxcount = m;
+  for (int o = 32; o > 0; o >>= 1) mx = max(mx, __shfl_xor(mx, o, kWave));
+  __shared__ int s_mx[kBS / kWave];
+  if (lane_id() == 0) s_mx[threadIdx.x / kWave] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int m = 0;
+    for (int k = 0; k < kBS / kWave; ++k) m = max(m, s_mx[k]);
+    tile_sum[2 * blockIdx.x] = tot;
+    tile_sum[2 * blockIdx.x + 1] = m;
+  }
+}
+
+__global__ __launch_bounds__(kBS) void k_slot_add(int32_t *__restrict__ soff, int n, int cap,
+                                                  const int32_t *__restrict__ count,
+                                                  const int32_t *__restrict__ tile_sum,
+                                                  int2 *__restrict__ srange,
+                                                  int32_t *__restrict__ maxcount,
+                                                  const int32_t *cond) {
+  if (skip(cond)) return;
+  __shared__ int wsum[kBS / kWave], wmax[kBS / kWave];
+  int part = 0, mx = 0;
+  for (int t = threadIdx.x; t < (int)blockIdx.x; t += kBS) part += tile_sum[2 * t];
+  if (blockIdx.x == 0)
+    for (int t = threadIdx.x; t < (int)gridDim.x; t += kBS) mx = max(mx, tile_sum[2 * t + 1]);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    part += __shfl_xor(part, o, kWave);
+    mx = max(mx, __shfl_xor(mx, o, kWave));
+  }
+  if (lane_id() == 0) {
+    wsum[threadIdx.x / kWave] = part;
+    wmax[threadIdx.x / kWave] = mx;
+  }
+  __syncthreads();
+  int off = 0, m = 0;
+#pragma unroll
+  for (int w = 0; w < kBS / kWave; ++w) {
+    off += wsum[w];
+    m = max(m, wmax[w]);
+  }
+  const int64_t base = (int64_t)blockIdx.x * kScanTile;
+  for (int k = threadIdx.x; k < kScanTile; k += kBS) {
+    const int64_t i = base + k;
+    if (i < n) {
+      const int first = soff[i] + off;
+      soff[i] = first;
+      srange[i] = make_int2(first, first + min(count[i], cap));
     }
   }
-  auto offset_of = [&](int a) {
-    const uint32_t v = (uint32_t)loff[a];
-    return s_pre[v >> kLoffBits] + (int)(v & ((1u << kLoffBits) - 1u));
-  };
-  for (int t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x; t < n;
-       t += gridDim.x * blockDim.x) {
-    const int i = order[t];  // the atom, as it appears in its neighbours' rows
-    const int ci = min(count[t], cap);
-    const int oi = offset_of(t);
-    soff[t] = oi;  // slots of the atom at position t: [soff[t], soff[t + 1])
-    if (t == n - 1) soff[n] = oi + ci;
-    const int32_t *row_i = list + (int64_t)t * cap;
-    for (int s0 = 0; s0 < ci; s0 += 4) {
-      int j[4], cj[4], oj[4], found[4];  // j: neighbour's row (its position)
+  if (threadIdx.x == 0) {
+    if (blockIdx.x == gridDim.x - 1) soff[n] = off + tile_sum[2 * blockIdx.x];
+    if (blockIdx.x == 0) *maxcount = m;
+  }
+}
+
+// The reverse map: for row entry (t, s) with neighbour j = list[t*cap + s] at
+// position p = plist[t*cap + s], rev[t*cap + s] = the incoming force slot at j
+// that holds the force of t's terms on j: soff[p] + (place of the atom at t in
+// row p).  The list is symmetric by construction (r_ij and r_ji are computed
+// from exactly negated displacements), so the place exists; a missing one is
+// latched as an error.  One thread per row, eight entries at a time: their
+// positions and slot ranges, then the first eight entries of each of their
+// rows (16-byte loads; rows start 16-byte aligned, cap being a multiple of 8),
+// all fetched before any is searched.
+__global__ __launch_bounds__(kBS) void k_reverse(int n, int cap, const float4 *__restrict__ xs,
+                                                 const int2 *__restrict__ srange,
+                                                 const int32_t *__restrict__ list,
+                                                 const int32_t *__restrict__ plist,
+                                                 int32_t *__restrict__ rev, const int32_t *cond,
+                                                 uint32_t *err) {
+  if (skip(cond)) return;
+  const int64_t t64 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kBS + threadIdx.x;
+  if (t64 >= n) return;
+  const int t = (int)t64;
+  const int i = __float_as_int(xs[t].w);  // the atom, as it appears in its neighbours' rows
+  const int2 rt = srange[t];
+  const int ci = rt.y - rt.x;
+  const int32_t *prow = plist + (int64_t)t * cap;
+  int32_t *rrow = rev + (int64_t)t * cap;
+  for (int s0 = 0; s0 < ci; s0 += 8) {
+    int p[8], cj[8], oj[8], found[8];
+    const int4 pa = *reinterpret_cast<const int4 *>(prow + s0);
+    const int4 pb = *reinterpret_cast<const int4 *>(prow + s0 + 4);
+    p[0] = pa.x, p[1] = pa.y, p[2] = pa.z, p[3] = pa.w;
+    p[4] = pb.x, p[5] = pb.y, p[6] = pb.z, p[7] = pb.w;
 #pragma unroll
-      for (int u = 0; u < 4; ++u) j[u] = s0 + u < ci ? row_i[s0 + u] : i;
+    for (int u = 0; u < 8; ++u) {
+      const bool live = s0 + u < ci;
+      if (!live) p[u] = t;  // entries past the row's end are never written
+      const int2 rg = srange[p[u]];
+      oj[u] = rg.x;
+      cj[u] = live ? rg.y - rg.x : 0;
+      found[u] = -1;
+    }
+    for (int k = 0; k < cap; k += 8) {
+      int4 v[8][2];
+      bool any = false;
 #pragma unroll
-      for (int u = 0; u < 4; ++u) j[u] = pos[j[u]];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const bool live = s0 + u < ci;
-        cj[u] = live ? min(count[j[u]], cap) : 0;
-        oj[u] = live ? offset_of(j[u]) : 0;
-        found[u] = -1;
-      }
-      for (int k = 0; k < cap; k += 4) {
-        int4 v[4];
-        bool any = false;
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          if (found[u] < 0 && k < cj[u]) {
-            v[u] = *reinterpret_cast<const int4 *>(list + (int64_t)j[u] * cap + k);
-            any = true;
-          }
+      for (int u = 0; u < 8; ++u) {
+        if (found[u] < 0 && k < cj[u]) {
+          const int4 *src = reinterpret_cast<const int4 *>(list + (int64_t)p[u] * cap + k);
+          v[u][0] = src[0];
+          v[u][1] = k + 4 < cj[u] ? src[1] : make_int4(-1, -1, -1, -1);
+          any = true;
         }
-        if (!any) break;
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          if (found[u] < 0 && k < cj[u]) {
-            if (v[u].x == i) found[u] = k;
-            else if (k + 1 < cj[u] && v[u].y == i) found[u] = k + 1;
-            else if (k + 2 < cj[u] && v[u].z == i) found[u] = k + 2;
-            else if (k + 3 < cj[u] && v[u].w == i) found[u] = k + 3;
-          }
-        }
       }
+      if (!any) break;
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        if (s0 + u < ci) {
-          if (found[u] < 0) atomicOr(err, kErrListAsymmetric);
-          rev[(int64_t)t * cap + s0 + u] = found[u] < 0 ? -1 : oj[u] + found[u];
+      for (int u = 0; u < 8; ++u) {
+        if (found[u] < 0 && k < cj[u]) {
+          const int w[8] = {v[u][0].x, v[u][0].y, v[u][0].z, v[u][0].w,
+                            v[u][1].x, v[u][1].y, v[u][1].z, v[u][1].w};
+#pragma unroll
+          for (int q = 7; q >= 0; --q)
+            if (k + q < cj[u] && w[q] == i) found[u] = k + q;
         }
       }
     }
+    int o[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      if (s0 + u < ci && found[u] < 0) atomicOr(err, kErrListAsymmetric);
+      o[u] = found[u] < 0 ? -1 : oj[u] + found[u];
+    }
+    // entries past the row's end (set to -1 or junk) are never read
+    *reinterpret_cast<int4 *>(rrow + s0) = make_int4(o[0], o[1], o[2], o[3]);
+    *reinterpret_cast<int4 *>(rrow + s0 + 4) = make_int4(o[4], o[5], o[6], o[7]);
   }
 }
 
@@ -661,26 +688,32 @@ void nlist_build(NList &nl, const double *x, const int32_t *type, int ntypes, co
                                     nl.order.as<int32_t>(), nl.xref.as<double>(), cond);
     k_sort_cells<<<grid(ncell), kBS, 0, s>>>(ncell, cell_start, nl.order.as<int32_t>(), cell_count,
                                              x, conf, conf_of, nl.xs.as<float4>(),
-                                             nl.pos.as<int32_t>(), cond);
-    // the list build is latency-bound: a larger grid than the other kernels
-    const int64_t groups = (n + kAtomsPerWave - 1) / kAtomsPerWave;
-    const int gb = (int)std::min<int64_t>(
-        std::max<int64_t>((groups + kBS / kWave - 1) / (kBS / kWave), 1), kBuildMaxBlocks);
+                                             nl.cell_at.as<int32_t>(), nl.pos.as<int32_t>(), cond);
     // FP32 distance test on positions wrapped into the box: a coordinate is
     // rounded by at most 2^-24 of the longest side, a squared distance by a
     // few units in the last place; the radius grows by a bound of both, so no
     // pair within r_list is missed (the filter applies the exact cutoffs)
     const double lmax = nl.box_max;
     const double rl = nl.rlist + 8.0 * std::ldexp(lmax, -24) + std::ldexp(nl.rlist, -18);
-    k_build<<<gb, kBS, 0, s>>>(n, nl.xs.as<float4>(), conf, conf_of, nl.order.as<int32_t>(),
-                               nl.cell_of.as<int32_t>(), cell_start, (float)(rl * rl), nl.cap,
-                               nl.count.as<int32_t>(), nl.list.as<int32_t>(), nl.loff.as<int32_t>(),
-                               nl.bsum.as<int32_t>(), cond, err, rebuild_counter);
-    k_reverse<<<grid(n), kBS, 0, s>>>(n, nl.cap, nl.order.as<int32_t>(), nl.pos.as<int32_t>(),
-                                      nl.count.as<int32_t>(),
-                                      nl.list.as<int32_t>(), nl.loff.as<int32_t>(),
-                                      nl.bsum.as<int32_t>(), gb, nl.soff.as<int32_t>(),
-                                      nl.rev.as<int32_t>(), nl.maxcount.as<int32_t>(), cond, err);
+    const int gt = grid_for(n, kBS);  // one thread per atom
+    const bool ldsout = nl.cap <= 16;  // rows collected in LDS (at most 32 KB per workgroup)
+    const size_t obytes = ldsout ? sizeof(int32_t) * 2 * kBS * nl.cap : 0;
+    const bool minimg = nl.small_axis;
+    auto kern = ldsout ? (minimg ? k_build<true, true> : k_build<true, false>)
+                       : (minimg ? k_build<false, true> : k_build<false, false>);
+    kern<<<gt, kBS, obytes, s>>>(n, nl.xs.as<float4>(), nl.cell_at.as<int32_t>(), conf, conf_of,
+                                 cell_start, (float)(rl * rl), nl.cap, nl.count.as<int32_t>(),
+                                 nl.list.as<int32_t>(), nl.plist.as<int32_t>(), cond, err,
+                                 rebuild_counter);
+    const int ntile = grid_for(n, kScanTile);
+    k_slot_tiles<<<ntile, kBS, 0, s>>>(nl.count.as<int32_t>(), nl.cap, n, nl.soff.as<int32_t>(),
+                                       nl.bsum.as<int32_t>(), cond);
+    k_slot_add<<<ntile, kBS, 0, s>>>(nl.soff.as<int32_t>(), n, nl.cap, nl.count.as<int32_t>(),
+                                     nl.bsum.as<int32_t>(), nl.srange.as<int2>(),
+                                     nl.maxcount.as<int32_t>(), cond);
+    k_reverse<<<gt, kBS, 0, s>>>(n, nl.cap, nl.xs.as<float4>(), nl.srange.as<int2>(),
+                                 nl.list.as<int32_t>(), nl.plist.as<int32_t>(),
+                                 nl.rev.as<int32_t>(), cond, err);
   }
 }
 

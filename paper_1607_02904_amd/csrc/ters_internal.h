@@ -77,6 +77,7 @@ struct NList {
   int64_t ncell = 0;
   double rlist = 0.0, skin = 0.0;
   double box_max = 0.0;  // longest box side of the set (rounding margin of the FP32 build)
+  bool small_axis = false;  // some configuration has an axis of fewer than 3 cells
   bool valid = false;
   std::vector<ConfDesc> conf_h;
   DevBuf conf;        // ConfDesc[nconf]
@@ -91,11 +92,14 @@ struct NList {
   DevBuf xref;        // double[n][3]
   DevBuf maxcount;    // int32[1]
   DevBuf rev;         // int32[n][cap]: incoming force slot at j of row entry (t, j)
-  DevBuf xs;          // float4[n]: positions at build time, in cell order, wrapped into the box (FP32)
+  DevBuf xs;          // float4[n]: positions at build time, in cell order, wrapped into the box
+                      // (FP32), atom index in the fourth word
   DevBuf pos;         // int32[n]: position of each atom in the cell order (inverse of order)
+  DevBuf cell_at;     // int32[n]: cell of the atom at each cell-order position
+  DevBuf plist;       // int32[n][cap]: positions of the row entries (list build and reverse map)
+  DevBuf srange;      // int2[n]: (soff[t], soff[t + 1])
   DevBuf soff;        // int32[n + 1]: first incoming force slot of the atom at each cell-order position
-  DevBuf loff;        // int32[n]: build workgroup (high bits) and slot number within it
-  DevBuf bsum;        // int32[2 * 4096]: slot total and longest row per build workgroup
+  DevBuf bsum;        // int32[2 * (n / 1024 + 1)]: slot total and longest row per scan tile
 };
 
 // Forward / adjoint launch description.
