@@ -19,6 +19,8 @@
 
 using namespace ters;
 
+constexpr int kMdGraphSteps = 8;  // molecular-dynamics steps per replayed graph
+
 struct ters_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -40,7 +42,8 @@ struct ters_ctx {
   int gather = 1;        // 1: owner-gather forces (deterministic), 0: FP64 atomic scatter
   DevBuf fslot, fown;    // owner-gather buffers
   // molecular-dynamics step graph
-  hipGraphExec_t md_exec = nullptr;
+  hipGraphExec_t md_exec = nullptr;   // one molecular-dynamics step
+  hipGraphExec_t md_exec8 = nullptr;  // kMdGraphSteps of them
   std::vector<const void *> md_key;
   // plans created on this context (released when the context is destroyed)
   std::vector<ters_plan *> plans;
@@ -182,6 +185,8 @@ void nl_setup(NList &nl, int nconf, const int32_t *natoms, const double *boxes, 
       d.inv_box[a] = 1.0 / L;
       int k = (int)std::floor(L / rlist);
       d.nc[a] = k >= 3 ? k : 1;
+      // the build packs cell coordinates in 11 (x, y) and 10 (z) bits
+      if (d.nc[a] > (a == 2 ? 1024 : 2048)) d.nc[a] = a == 2 ? 1024 : 2048;
     }
     d.cell_off = (int32_t)cells;
     d.atom_off = (int32_t)atoms;
@@ -215,7 +220,7 @@ void nl_setup(NList &nl, int nconf, const int32_t *natoms, const double *boxes, 
   nl.cell_start.ensure(sizeof(int32_t) * (cells + 1));
   nl.scan_tmp.ensure(sizeof(int32_t) * ((cells + 1) / 1024 + 2));
   nl.xref.ensure(sizeof(double) * 3 * nn);
-  nl.xs.ensure(sizeof(float) * 4 * nn);
+  nl.xs.ensure(sizeof(float) * 4 * (nn + 3));  // 3 padding entries for the build's fetches
   nl.pos.ensure(sizeof(int32_t) * nn);
   nl.cell_at.ensure(sizeof(int32_t) * nn);
   nl.srange.ensure(sizeof(int32_t) * 2 * nn);
@@ -396,7 +401,7 @@ constexpr size_t kN = TERS_STATIC_MAX_ATOMS;
 constexpr size_t kStaticBytes =
     al(sizeof(ConfDesc)) + 5 * al(4 * kN) + al(8 * kN) + al(4 * (kN + 1)) +
     3 * al(4 * kN * kStaticCap) + 2 * al(4 * (kStaticCells + 1)) +
-    al(4 * ((kStaticCells + 1) / 1024 + 2)) + al(24 * kN) + al(16 * kN) +
+    al(4 * ((kStaticCells + 1) / 1024 + 2)) + al(24 * kN) + al(16 * (kN + 3)) +
     al(4 * 2 * (kN / 1024 + 1)) + al(4) + al(64 * kN) + al(24 * kN * kStaticCap) + al(24 * kN);
 
 // One copy per GPU, held until the process ends.  In host code this name is
@@ -485,6 +490,7 @@ ters_status ters_destroy(ters_ctx *c) {
   for (ters_plan *p : c->plans) plan_release_device(p);
   c->plans.clear();
   if (c->md_exec) hipGraphExecDestroy(c->md_exec);
+  if (c->md_exec8) hipGraphExecDestroy(c->md_exec8);
   if (c->capture_stream) hipStreamDestroy(c->capture_stream);
   DevBuf *bufs[] = {&c->kp64, &c->kp32, &c->kp32s, &c->filt2, &c->mass, &c->partials, &c->errw, &c->flag,
                     &c->rebuilds, &c->step, &c->escratch, &c->fslot, &c->fown, &c->nl.conf,
@@ -753,6 +759,8 @@ ters_status ters_compute_static(ters_ctx *c, int32_t n, const double *x, const i
       d.inv_box[a] = 1.0 / L;
       const int k = (int)std::floor(L / rlist);
       d.nc[a] = k >= 3 ? k : 1;
+      // the build packs cell coordinates in 11 (x, y) and 10 (z) bits
+      if (d.nc[a] > (a == 2 ? 1024 : 2048)) d.nc[a] = a == 2 ? 1024 : 2048;
     }
     for (;;) {
       cells = (int64_t)d.nc[0] * d.nc[1] * d.nc[2];
@@ -784,7 +792,7 @@ ters_status ters_compute_static(ters_ctx *c, int32_t n, const double *x, const i
     nl.cell_start = cv.take(4 * (kStaticCells + 1));
     nl.scan_tmp = cv.take(4 * ((kStaticCells + 1) / 1024 + 2));
     nl.xref = cv.take(24 * N);
-    nl.xs = cv.take(16 * N);
+    nl.xs = cv.take(16 * (N + 3));
     nl.bsum = cv.take(4 * 2 * (N / 1024 + 1));
     nl.maxcount = cv.take(4);
     DevBuf partials = cv.take(64 * N);
@@ -1086,24 +1094,32 @@ ters_status md_run_impl(ters_ctx *c, int32_t n, double *x, double *v, double *f,
                              (const void *)(intptr_t)c->kern[precision]};
       key.insert(key.end(), std::begin(extra), std::end(extra));
       if (!c->md_exec || key != c->md_key) {
-        if (c->md_exec) {
-          TERS_HIP_TRY(hipGraphExecDestroy(c->md_exec));
-          c->md_exec = nullptr;
-        }
+        for (hipGraphExec_t *e : {&c->md_exec, &c->md_exec8})
+          if (*e) {
+            TERS_HIP_TRY(hipGraphExecDestroy(*e));
+            *e = nullptr;
+          }
         if (!c->capture_stream) TERS_HIP_TRY(hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
         sync(c);
-        hipGraph_t g;
-        TERS_HIP_TRY(hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal));
-        step(c->capture_stream, 0, false);
-        TERS_HIP_TRY(hipStreamEndCapture(c->capture_stream, &g));
-        TERS_HIP_TRY(hipGraphInstantiate(&c->md_exec, g, nullptr, nullptr, 0));
-        TERS_HIP_TRY(hipGraphDestroy(g));
+        // the step alone, and kMdGraphSteps steps in one graph (fewer graph
+        // launches, each with its own fixed cost)
+        for (int k : {1, kMdGraphSteps}) {
+          hipGraph_t g;
+          TERS_HIP_TRY(hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal));
+          for (int q = 0; q < k; ++q) step(c->capture_stream, 0, false);
+          TERS_HIP_TRY(hipStreamEndCapture(c->capture_stream, &g));
+          TERS_HIP_TRY(hipGraphInstantiate(k == 1 ? &c->md_exec : &c->md_exec8, g, nullptr, nullptr, 0));
+          TERS_HIP_TRY(hipGraphDestroy(g));
+        }
         c->md_key = key;
       }
       // the captured step carries the next step's half kick and drift; in
       // owner-gather mode the last step is launched directly without it
       const int replays = gather ? nsteps - 1 : nsteps;
-      for (int s = 0; s < replays; ++s) TERS_HIP_TRY(hipGraphLaunch(c->md_exec, c->stream));
+      for (int s = 0; s < replays / kMdGraphSteps; ++s)
+        TERS_HIP_TRY(hipGraphLaunch(c->md_exec8, c->stream));
+      for (int s = 0; s < replays % kMdGraphSteps; ++s)
+        TERS_HIP_TRY(hipGraphLaunch(c->md_exec, c->stream));
       if (gather) step(c->stream, nsteps - 1, true);
     }
     return TERS_OK;

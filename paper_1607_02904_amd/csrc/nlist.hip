@@ -220,8 +220,9 @@ __global__ void k_place(int n, const double *__restrict__ x, const int32_t *__re
 // cell order (pos, the inverse of order) and copy the positions in that order
 // for the build (xs: FP32, wrapped into the configuration's box, with the
 // atom index in the fourth word; the build's distance test allows for that
-// rounding) together with the cell of each position (cell_at); the counts
-// (used as placement cursors) are cleared for the next build
+// rounding) together with the cell coordinates of each position (cell_at:
+// x | y << 11 | z << 22 within the configuration's grid); the counts (used as
+// placement cursors) are cleared for the next build
 __global__ void k_sort_cells(int64_t ncell, const int32_t *__restrict__ cell_start,
                              int32_t *__restrict__ order, int32_t *__restrict__ counts,
                              const double *__restrict__ x, const ConfDesc *__restrict__ conf,
@@ -241,6 +242,12 @@ __global__ void k_sort_cells(int64_t ncell, const int32_t *__restrict__ cell_sta
       }
       order[q + 1] = v;
     }
+    int packed = 0;
+    if (e > b) {
+      const ConfDesc &cf = conf[conf_index(conf_of, order[b])];
+      const int lc = (int)c - cf.cell_off, nx = cf.nc[0], ny = cf.nc[1];
+      packed = (lc % nx) | ((lc / nx) % ny) << 11 | (lc / (nx * ny)) << 22;
+    }
     for (int p = b; p < e; ++p) {
       const int i = order[p];
       pos[i] = p;
@@ -252,7 +259,7 @@ __global__ void k_sort_cells(int64_t ncell, const int32_t *__restrict__ cell_sta
         w[a] = (float)(v - cf.box[a] * floor(v * cf.inv_box[a]));
       }
       xs[p] = make_float4(w[0], w[1], w[2], __int_as_float(i));
-      cell_at[p] = (int32_t)c;
+      cell_at[p] = packed;
     }
     counts[c] = 0;
   }
@@ -305,11 +312,10 @@ __global__ __launch_bounds__(kBS) void k_build(int n, const float4 *__restrict__
   const bool act = wbase + lane < n;
   const int t = act ? (int)(wbase + lane) : n - 1;  // idle lanes shadow the last atom, store nothing
   const float4 qi = xs[t];
-  const int cell = cell_at[t];
+  const int packed = cell_at[t];
   const ConfDesc &c = conf[conf_index(conf_of, __float_as_int(qi.w))];
-  const int lc = cell - c.cell_off;
   const int nx = c.nc[0], ny = c.nc[1], nz = c.nc[2];
-  const int cx = lc % nx, cy = (lc / nx) % ny, cz = lc / (nx * ny);
+  const int cx = packed & 2047, cy = (packed >> 11) & 2047, cz = packed >> 22;
   const float bx = (float)c.box[0], by = (float)c.box[1], bz = (float)c.box[2];
   const float ibx = (float)c.inv_box[0], iby = (float)c.inv_box[1], ibz = (float)c.inv_box[2];
   const bool fixed = nx >= 3 && ny >= 3 && nz >= 3;  // image fixed by the cell
@@ -357,29 +363,31 @@ __global__ __launch_bounds__(kBS) void k_build(int n, const float4 *__restrict__
   int32_t *row = list + (int64_t)t * cap;
   int32_t *prow = plist + (int64_t)t * cap;
   int cnt = 0;
+  // candidates are fetched U at a time from xs[k0 ..]: xs carries U - 1
+  // padding entries past n, and entries at or past the run's end are not taken
   constexpr int U = 4;
-  // one row per pass; the per-row values rotate down so that the body reads slot 0
-#pragma nounroll
+#pragma unroll
   for (int r = 0; r < 9; ++r) {
 #pragma unroll
     for (int seg = 0; seg < 2; ++seg) {  // near run, far run
-      const int b = seg ? fb[0] : nb[0], e = seg ? fe[0] : ne[0];
+      const int b = seg ? fb[r] : nb[r], e = seg ? fe[r] : ne[r];
       const float sx = seg ? sfx : 0.f;
       for (int k0 = b; k0 < e; k0 += U) {
         float4 q[U];
+        const float4 *src = xs + k0;
 #pragma unroll
-        for (int u = 0; u < U; ++u) q[u] = xs[min(k0 + u, e - 1)];
+        for (int u = 0; u < U; ++u) q[u] = src[u];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           float dx = q[u].x - qi.x, dy = q[u].y - qi.y, dz = q[u].z - qi.z;
           if (!MINIMG) {
             dx += sx;
-            dy += sy[0];
-            dz += sz[0];
+            dy += sy[r];
+            dz += sz[r];
           } else {  // the form is a property of the configuration, the same for (k, i)
             dx = fixed ? dx + sx : dx - bx * rintf(dx * ibx);
-            dy = fixed ? dy + sy[0] : dy - by * rintf(dy * iby);
-            dz = fixed ? dz + sz[0] : dz - bz * rintf(dz * ibz);
+            dy = fixed ? dy + sy[r] : dy - by * rintf(dy * iby);
+            dz = fixed ? dz + sz[r] : dz - bz * rintf(dz * ibz);
           }
           const int p = k0 + u;
           if (p < e && p != t && dx * dx + dy * dy + dz * dz <= rl2) {
@@ -394,15 +402,6 @@ __global__ __launch_bounds__(kBS) void k_build(int n, const float4 *__restrict__
           }
         }
       }
-    }
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      nb[j] = nb[j + 1];
-      ne[j] = ne[j + 1];
-      fb[j] = fb[j + 1];
-      fe[j] = fe[j + 1];
-      sy[j] = sy[j + 1];
-      sz[j] = sz[j + 1];
     }
   }
   if (act) {
