@@ -218,15 +218,15 @@ void nl_setup(NList &nl, int nconf, const int32_t *natoms, const double *boxes, 
   nl.cell_of.ensure(sizeof(int32_t) * nn);
   nl.cell_count.ensure(sizeof(int32_t) * (cells + 1));
   nl.cell_start.ensure(sizeof(int32_t) * (cells + 1));
-  nl.scan_tmp.ensure(sizeof(int32_t) * ((cells + 1) / 1024 + 2));
+  nl.lbstate.ensure(sizeof(uint64_t) * (1 + (cells + 1) / 1024 + 1 + (nn + 1) / 1024 + 1));
   nl.xref.ensure(sizeof(double) * 3 * nn);
   nl.xs.ensure(sizeof(float) * 4 * (nn + 3));  // 3 padding entries for the build's fetches
   nl.pos.ensure(sizeof(int32_t) * nn);
   nl.cell_at.ensure(sizeof(int32_t) * nn);
   nl.srange.ensure(sizeof(int32_t) * 2 * nn);
+  nl.srange_a.ensure(sizeof(int32_t) * 2 * nn);
   nl.plist.ensure(sizeof(int32_t) * nn * nl.cap);
   nl.soff.ensure(sizeof(int32_t) * (nn + 1));
-  nl.bsum.ensure(sizeof(int32_t) * 2 * (nn / 1024 + 1));
   nl.maxcount.ensure(sizeof(int32_t));
   nl.rev.ensure(sizeof(int32_t) * nn * nl.cap);
 }
@@ -303,14 +303,14 @@ const void *bits(double v) {
 // allocator hands the same addresses to new tensors).
 std::vector<const void *> graph_key(const ters_ctx *c, const NList &nl) {
   return {nl.conf.p, nl.conf_of.p, nl.count.p, nl.list.p, nl.order.p, nl.cell_of.p,
-          nl.cell_count.p, nl.cell_start.p, nl.scan_tmp.p, nl.xref.p, nl.maxcount.p,
+          nl.cell_count.p, nl.cell_start.p, nl.lbstate.p, nl.xref.p, nl.maxcount.p,
           (const void *)(intptr_t)nl.n, (const void *)(intptr_t)nl.cap,
           (const void *)(intptr_t)nl.ncell, (const void *)(intptr_t)nl.nconf, bits(nl.rlist),
           bits(nl.skin), c->kp64.p, c->kp32.p, c->kp32s.p, c->filt2.p, (const void *)(intptr_t)c->ntypes,
           (const void *)(intptr_t)c->cut_consistent, (const void *)(intptr_t)c->kmax,
           (const void *)(intptr_t)c->filter,
           c->partials.p, c->errw.p, c->flag.p, c->rebuilds.p, c->step.p, c->escratch.p,
-          nl.rev.p, nl.xs.p, nl.pos.p, nl.soff.p, nl.bsum.p, nl.cell_at.p, nl.plist.p, nl.srange.p, c->fslot.p, c->fown.p,
+          nl.rev.p, nl.xs.p, nl.pos.p, nl.soff.p, nl.cell_at.p, nl.plist.p, nl.srange.p, nl.srange_a.p, c->fslot.p, c->fown.p,
           (const void *)(intptr_t)c->gather};
 }
 
@@ -399,10 +399,10 @@ constexpr size_t al(size_t b) { return (b + kAlign - 1) / kAlign * kAlign; }
 constexpr size_t kN = TERS_STATIC_MAX_ATOMS;
 // bytes of every scratch buffer at the largest size (layout of carve_static)
 constexpr size_t kStaticBytes =
-    al(sizeof(ConfDesc)) + 5 * al(4 * kN) + al(8 * kN) + al(4 * (kN + 1)) +
+    al(sizeof(ConfDesc)) + 5 * al(4 * kN) + 2 * al(8 * kN) + al(4 * (kN + 1)) +
     3 * al(4 * kN * kStaticCap) + 2 * al(4 * (kStaticCells + 1)) +
-    al(4 * ((kStaticCells + 1) / 1024 + 2)) + al(24 * kN) + al(16 * (kN + 3)) +
-    al(4 * 2 * (kN / 1024 + 1)) + al(4) + al(64 * kN) + al(24 * kN * kStaticCap) + al(24 * kN);
+    al(8 * (1 + (kStaticCells + 1) / 1024 + 1 + (kN + 1) / 1024 + 1)) + al(24 * kN) +
+    al(16 * (kN + 3)) + al(4) + al(64 * kN) + al(24 * kN * kStaticCap) + al(24 * kN);
 
 // One copy per GPU, held until the process ends.  In host code this name is
 // only a stand-in: kernels get the device address from hipGetSymbolAddress.
@@ -495,9 +495,10 @@ ters_status ters_destroy(ters_ctx *c) {
   DevBuf *bufs[] = {&c->kp64, &c->kp32, &c->kp32s, &c->filt2, &c->mass, &c->partials, &c->errw, &c->flag,
                     &c->rebuilds, &c->step, &c->escratch, &c->fslot, &c->fown, &c->nl.conf,
                     &c->nl.conf_of, &c->nl.count, &c->nl.list, &c->nl.order, &c->nl.cell_of,
-                    &c->nl.cell_count, &c->nl.cell_start, &c->nl.scan_tmp, &c->nl.xref,
+                    &c->nl.cell_count, &c->nl.cell_start, &c->nl.lbstate, &c->nl.xref,
                     &c->nl.maxcount, &c->nl.rev, &c->nl.xs, &c->nl.pos, &c->nl.soff,
-                    &c->nl.bsum, &c->nl.cell_at, &c->nl.plist, &c->nl.srange};
+                    &c->nl.cell_at, &c->nl.plist, &c->nl.srange,
+                    &c->nl.srange_a};
   for (DevBuf *b : bufs) b->release();
   delete c;
   return TERS_OK;
@@ -631,12 +632,14 @@ ters_status ters_nlist_stats(ters_ctx *c, int64_t *out) {
     require(c->nl.valid, TERS_ERR_NO_LIST, "no neighbour list");
     const int n = c->nl.n;
     std::vector<int32_t> cnt(n);
-    int32_t mx = 0;
     if (n) TERS_HIP_TRY(hipMemcpyAsync(cnt.data(), c->nl.count.p, sizeof(int32_t) * n, hipMemcpyDeviceToHost, c->stream));
-    TERS_HIP_TRY(hipMemcpyAsync(&mx, c->nl.maxcount.p, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
     sync(c);
     int64_t tot = 0;
-    for (int v : cnt) tot += v;
+    int32_t mx = 0;
+    for (int v : cnt) {
+      tot += v;
+      mx = std::max(mx, v);
+    }
     out[0] = n;
     out[1] = tot;
     out[2] = mx;
@@ -784,16 +787,16 @@ ters_status ters_compute_static(ters_ctx *c, int32_t n, const double *x, const i
     nl.pos = cv.take(4 * N);
     nl.cell_at = cv.take(4 * N);
     nl.srange = cv.take(8 * N);
+    nl.srange_a = cv.take(8 * N);
     nl.soff = cv.take(4 * (N + 1));
     nl.list = cv.take(4 * N * kStaticCap);
     nl.rev = cv.take(4 * N * kStaticCap);
     nl.plist = cv.take(4 * N * kStaticCap);
     nl.cell_count = cv.take(4 * (kStaticCells + 1));
     nl.cell_start = cv.take(4 * (kStaticCells + 1));
-    nl.scan_tmp = cv.take(4 * ((kStaticCells + 1) / 1024 + 2));
+    nl.lbstate = cv.take(8 * (1 + (kStaticCells + 1) / 1024 + 1 + (N + 1) / 1024 + 1));
     nl.xref = cv.take(24 * N);
     nl.xs = cv.take(16 * (N + 3));
-    nl.bsum = cv.take(4 * 2 * (N / 1024 + 1));
     nl.maxcount = cv.take(4);
     DevBuf partials = cv.take(64 * N);
     DevBuf fslot = cv.take(24 * N * kStaticCap);
@@ -1446,9 +1449,10 @@ static void plan_release_device(ters_plan *p) {
   DevBuf *bufs[] = {&p->partials, &p->ebuf, &p->errw, &p->fslot, &p->fown, &p->items_f,
                     &p->qb_f, &p->items_a, &p->qb_a, &p->queue, &p->nl.conf,
                     &p->nl.conf_of, &p->nl.count, &p->nl.list, &p->nl.order, &p->nl.cell_of,
-                    &p->nl.cell_count, &p->nl.cell_start, &p->nl.scan_tmp, &p->nl.xref,
+                    &p->nl.cell_count, &p->nl.cell_start, &p->nl.lbstate, &p->nl.xref,
                     &p->nl.maxcount, &p->nl.rev, &p->nl.xs, &p->nl.pos, &p->nl.soff,
-                    &p->nl.bsum, &p->nl.cell_at, &p->nl.plist, &p->nl.srange};
+                    &p->nl.cell_at, &p->nl.plist, &p->nl.srange,
+                    &p->nl.srange_a};
   for (DevBuf *b : bufs) b->release();
   p->ctx = nullptr;
 }

@@ -3,15 +3,16 @@
 //
 //   bin     atom -> cell of side >= r_list in its own configuration's grid,
 //           count atoms per cell
-//   scan    exclusive prefix sum of the cell counts (cell_start)
+//   scan    exclusive prefix sum of the cell counts (cell_start), one pass
 //   place   counting-sort the atoms into cells; keep the reference positions
 //           of the rebuild check
 //   sort    order atoms inside each cell by index (run-to-run determinism)
 //           and keep a cell-ordered copy of the positions
 //   build   for each atom scan the 27 surrounding cells (1 along an axis that
 //           holds fewer than 3 cells) and keep j != i with minimum-image
-//           r_ij <= r_list, in a padded row of `cap` entries; hand out each
-//           atom's range of incoming force slots (compact, no row padding)
+//           r_ij <= r_list, in a padded row of `cap` entries
+//   slots   each atom's range of incoming force slots (compact, no row
+//           padding): a one-pass scan of the row lengths
 //   reverse for every row entry (i, j), the slot of i's force on j among j's
 //           incoming slots
 //
@@ -58,12 +59,19 @@ DEV void bin_one(int i, const double *__restrict__ x, const ConfDesc *__restrict
                  const int32_t *__restrict__ conf_of, int32_t *__restrict__ cell_of,
                  int32_t *__restrict__ cell_count, uint32_t *err);
 
-// also checks every species against [0, ntypes) when type is given
+// also checks every species against [0, ntypes) when type is given, and
+// clears the state of this build's one-pass scans (tickets, tile flags, the
+// longest-row register)
 __global__ void k_bin(int n, const double *__restrict__ x, const ConfDesc *__restrict__ conf,
                       const int32_t *__restrict__ conf_of, int32_t *__restrict__ cell_of,
                       int32_t *__restrict__ cell_count, const int32_t *__restrict__ type,
-                      int ntypes, const int32_t *cond, uint32_t *err) {
+                      int ntypes, unsigned long long *__restrict__ lb, int64_t nlb,
+                      int32_t *__restrict__ maxcount, const int32_t *cond, uint32_t *err) {
   if (skip(cond)) return;
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < nlb;
+       k += (int64_t)gridDim.x * blockDim.x)
+    lb[k] = 0ull;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *maxcount = 0;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     bin_one(i, x, conf, conf_of, cell_of, cell_count, err);
     if (type && (unsigned)type[i] >= (unsigned)ntypes) atomicOr(err, kErrBadType);
@@ -92,9 +100,7 @@ DEV void bin_one(int i, const double *__restrict__ x, const ConfDesc *__restrict
   atomicAdd(&cell_count[cell], 1);
 }
 
-// ---- exclusive scan of int32 (tiles of 1024, then tile sums, then add) ----
-constexpr int kScanPer = 4;
-constexpr int kScanTile = kBS * kScanPer;
+// ---- exclusive scans of int32 ----
 
 DEV int wave_incl_scan(int v) {
   int lane = lane_id();
@@ -126,53 +132,106 @@ DEV int block_excl_scan_t(int v, int *total) {
 }
 DEV int block_excl_scan(int v, int *total) { return block_excl_scan_t<kBS>(v, total); }
 
-__global__ __launch_bounds__(kBS) void k_scan_tiles(const int32_t *__restrict__ in,
-                                                    int32_t *__restrict__ out, int64_t m,
-                                                    int32_t *__restrict__ tile_sum,
-                                                    const int32_t *cond) {
-  if (skip(cond)) return;
-  int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * kScanPer;
-  int v[kScanPer];
-  int s = 0;
+DEV int wave_max_i(int v) {
 #pragma unroll
-  for (int k = 0; k < kScanPer; ++k) {
-    v[k] = (base + k < m) ? in[base + k] : 0;
-    s += v[k];
-  }
-  int tot;
-  int off = block_excl_scan(s, &tot);
-#pragma unroll
-  for (int k = 0; k < kScanPer; ++k) {
-    if (base + k < m) out[base + k] = off;
-    off += v[k];
-  }
-  if (threadIdx.x == 0) tile_sum[blockIdx.x] = tot;
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, kWave));
+  return v;
 }
 
-// one workgroup per tile: adds the sum of all earlier tiles (summed here, so
-// no separate pass over the tile sums) and clears the counts (they become
-// the placement cursors)
-__global__ __launch_bounds__(kBS) void k_scan_add(int32_t *out, int64_t m,
-                                                  const int32_t *tile_sum, int32_t *counts,
-                                                  const int32_t *cond) {
-  if (skip(cond)) return;
-  __shared__ int wsum[kBS / kWave];
-  int part = 0;
-  for (int t = threadIdx.x; t < (int)blockIdx.x; t += kBS) part += tile_sum[t];
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, kWave);
-  if (lane_id() == 0) wsum[threadIdx.x / kWave] = part;
+// One-pass exclusive scan (decoupled look-back).  Workgroups take tiles of
+// kLbTile values in the order of a ticket counter, so every tile a
+// workgroup waits for belongs to a workgroup that is already running: the
+// waits end whatever the number of resident workgroups.  Each tile publishes
+// its sum (status 1) as soon as it is known and, once the sum of all earlier
+// tiles is found by walking back over their flags, its inclusive prefix
+// (status 2); a flag holds the status in bits 62-63 and the value in the low
+// 32 bits.  The flags and the ticket are cleared by the binning pass of the
+// same build.
+constexpr unsigned long long kLbSum = 1ull << 62, kLbPrefix = 2ull << 62;
+constexpr int kLbPer = 4;                 // values per thread
+constexpr int kLbTile = kBS * kLbPer;     // values per tile
+
+DEV int scan_ticket(int32_t *ticket) {
+  __shared__ int s_tile;
+  if (threadIdx.x == 0) s_tile = atomicAdd(ticket, 1);
   __syncthreads();
-  int off = 0;
-#pragma unroll
-  for (int w = 0; w < kBS / kWave; ++w) off += wsum[w];
-  const int64_t base = (int64_t)blockIdx.x * kScanTile;
-  for (int k = threadIdx.x; k < kScanTile; k += kBS) {
-    const int64_t i = base + k;
-    if (i < m) {
-      out[i] += off;
-      counts[i] = 0;
+  return s_tile;
+}
+
+// The sum of the tiles before this one, found by the workgroup's first
+// wavefront: lane l reads the flag of tile top - l (64 earlier tiles per
+// read), the nearest inclusive prefix among them ends the walk, and the sums
+// of the tiles in between are added to it; while one of those tiles has not
+// published, the same flags are read again.  Every thread of the first
+// wavefront takes part; the result is valid in all of its lanes.
+DEV int scan_lookback(unsigned long long *flags, int tile, int sum) {
+  const int lane = lane_id();
+  auto put = [&](unsigned long long v) {
+    if (lane == 0) __hip_atomic_store(&flags[tile], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  };
+  if (tile == 0) {
+    put(kLbPrefix | (unsigned)sum);
+    return 0;
+  }
+  put(kLbSum | (unsigned)sum);
+  int excl = 0;
+  for (int top = tile - 1;;) {
+    const int idx = top - lane;
+    // below tile 0: a zero prefix (never reached past tile 0's own prefix)
+    const unsigned long long f =
+        idx >= 0 ? __hip_atomic_load(&flags[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                 : kLbPrefix;
+    const unsigned long long st = f & (3ull << 62);
+    const uint64_t pre = __ballot(st == kLbPrefix), none = __ballot(st == 0ull);
+    const int first = pre ? __builtin_ctzll(pre) : kWave;  // nearest prefix
+    const uint64_t upto = first >= kWave - 1 ? ~0ull : (2ull << first) - 1ull;
+    if (none & upto) {  // a tile in the walk has not published yet (its workgroup is running)
+      __builtin_amdgcn_s_sleep(1);
+      continue;
     }
+    int v = lane <= first ? (int)(unsigned)(f & 0xffffffffull) : 0;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    excl += v;
+    if (first < kWave) break;
+    top -= kWave;
+  }
+  put(kLbPrefix | (unsigned)(excl + sum));
+  return excl;
+}
+
+// cell_start = exclusive scan of the cell counts, which are cleared on the
+// way (they become the placement cursors)
+__global__ __launch_bounds__(kBS) void k_scan_cells(int32_t *__restrict__ counts,
+                                                    int32_t *__restrict__ out, int64_t m,
+                                                    int32_t *ticket, unsigned long long *flags,
+                                                    const int32_t *cond) {
+  if (skip(cond)) return;
+  const int tile = scan_ticket(ticket);
+  const int64_t base = (int64_t)tile * kLbTile + threadIdx.x * kLbPer;
+  int v[kLbPer];
+  int sum = 0;
+#pragma unroll
+  for (int k = 0; k < kLbPer; ++k) {
+    v[k] = (base + k < m) ? counts[base + k] : 0;
+    sum += v[k];
+  }
+  int tot;
+  int off = block_excl_scan(sum, &tot);
+  __shared__ int s_excl;
+  if (threadIdx.x < kWave) {
+    const int e = scan_lookback(flags, tile, tot);
+    if (threadIdx.x == 0) s_excl = e;
+  }
+  __syncthreads();
+  off += s_excl;
+#pragma unroll
+  for (int k = 0; k < kLbPer; ++k) {
+    if (base + k < m) {
+      out[base + k] = off;
+      counts[base + k] = 0;
+    }
+    off += v[k];
   }
 }
 
@@ -290,8 +349,7 @@ __global__ void k_sort_cells(int64_t ncell, const int32_t *__restrict__ cell_sta
 // Rows and counts are indexed by cell-order position: row t lists the
 // neighbours (atom indices) of the atom at position t, so that the rows of a
 // run of atoms that a force wavefront takes are contiguous.  The incoming
-// force slots are numbered afterwards by a scan of the row lengths
-// (k_slot_tiles, k_slot_add).
+// force slots are numbered afterwards by a scan of the row lengths (k_slots).
 DEV int wrap_cell(int q, int nc) { return q < 0 ? q + nc : (q >= nc ? q - nc : q); }
 
 template <bool LDSOUT, bool MINIMG>
@@ -426,22 +484,24 @@ __global__ __launch_bounds__(kBS) void k_build(int n, const float4 *__restrict__
 // Incoming force slots, numbered along the cell order without row padding:
 // the atom at position t owns [soff[t], soff[t + 1]) with
 // soff[t] = sum of min(count, cap) over earlier positions; the pair
-// (soff[t], soff[t + 1]) is also kept as one 8-byte word per position (srange)
-// for the reverse map.  Tiles of
-// kScanTile positions: exclusive scan within the tile, tile sums and longest
-// rows in tile_sum[2 * tile], tile_sum[2 * tile + 1]; then every tile adds the
-// sum of the earlier tiles, the last writes soff[n], and tile 0 writes the
-// longest row of all (maxcount).
-__global__ __launch_bounds__(kBS) void k_slot_tiles(const int32_t *__restrict__ count, int cap,
-                                                    int n, int32_t *__restrict__ soff,
-                                                    int32_t *__restrict__ tile_sum,
-                                                    const int32_t *cond) {
+// (soff[t], soff[t + 1]) is also kept as one 8-byte word per position (srange,
+// for the reverse map) and per atom (srange_a, for the gathers).  One pass
+// (the one-pass scan above) over positions 0 .. n, position n adding zero so
+// that soff[n] is the total; a row longer than cap raises maxcount to its
+// length (only such rows touch it, so the register is not contended).
+__global__ __launch_bounds__(kBS) void k_slots(const int32_t *__restrict__ count, int cap, int n,
+                                               const int32_t *__restrict__ order,
+                                               int32_t *__restrict__ soff, int2 *__restrict__ srange,
+                                               int2 *__restrict__ srange_a,
+                                               int32_t *__restrict__ maxcount, int32_t *ticket,
+                                               unsigned long long *flags, const int32_t *cond) {
   if (skip(cond)) return;
-  const int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * kScanPer;
-  int v[kScanPer];
+  const int tile = scan_ticket(ticket);
+  const int64_t base = (int64_t)tile * kLbTile + threadIdx.x * kLbPer;
+  int v[kLbPer];
   int sum = 0, mx = 0;
 #pragma unroll
-  for (int k = 0; k < kScanPer; ++k) {
+  for (int k = 0; k < kLbPer; ++k) {  // position n closes the scan with a zero
     const int c = (base + k < n) ? count[base + k] : 0;
     mx = max(mx, c);
     v[k] = min(c, cap);
@@ -449,64 +509,25 @@ __global__ __launch_bounds__(kBS) void k_slot_tiles(const int32_t *__restrict__ 
   }
   int tot;
   int off = block_excl_scan(sum, &tot);
-#pragma unroll
-  for (int k = 0; k < kScanPer; ++k) {
-    if (base + k < n) soff[base + k] = off;
-    off += v[k];
+  __shared__ int s_excl;
+  if (threadIdx.x < kWave) {
+    const int e = scan_lookback(flags, tile, tot);
+    if (threadIdx.x == 0) s_excl = e;
   }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) mx = max(mx, __shfl_xor(mx, o, kWave));
-  __shared__ int s_mx[kBS / kWave];
-  if (lane_id() == 0) s_mx[threadIdx.x / kWave] = mx;
+  mx = wave_max_i(mx);
+  if (lane_id() == 0 && mx > cap) atomicMax(maxcount, mx);  // only rows that overflowed
   __syncthreads();
-  if (threadIdx.x == 0) {
-    int m = 0;
-    for (int k = 0; k < kBS / kWave; ++k) m = max(m, s_mx[k]);
-    tile_sum[2 * blockIdx.x] = tot;
-    tile_sum[2 * blockIdx.x + 1] = m;
-  }
-}
-
-__global__ __launch_bounds__(kBS) void k_slot_add(int32_t *__restrict__ soff, int n, int cap,
-                                                  const int32_t *__restrict__ count,
-                                                  const int32_t *__restrict__ tile_sum,
-                                                  int2 *__restrict__ srange,
-                                                  int32_t *__restrict__ maxcount,
-                                                  const int32_t *cond) {
-  if (skip(cond)) return;
-  __shared__ int wsum[kBS / kWave], wmax[kBS / kWave];
-  int part = 0, mx = 0;
-  for (int t = threadIdx.x; t < (int)blockIdx.x; t += kBS) part += tile_sum[2 * t];
-  if (blockIdx.x == 0)
-    for (int t = threadIdx.x; t < (int)gridDim.x; t += kBS) mx = max(mx, tile_sum[2 * t + 1]);
+  off += s_excl;
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    part += __shfl_xor(part, o, kWave);
-    mx = max(mx, __shfl_xor(mx, o, kWave));
-  }
-  if (lane_id() == 0) {
-    wsum[threadIdx.x / kWave] = part;
-    wmax[threadIdx.x / kWave] = mx;
-  }
-  __syncthreads();
-  int off = 0, m = 0;
-#pragma unroll
-  for (int w = 0; w < kBS / kWave; ++w) {
-    off += wsum[w];
-    m = max(m, wmax[w]);
-  }
-  const int64_t base = (int64_t)blockIdx.x * kScanTile;
-  for (int k = threadIdx.x; k < kScanTile; k += kBS) {
+  for (int k = 0; k < kLbPer; ++k) {
     const int64_t i = base + k;
+    if (i <= n) soff[i] = off;
     if (i < n) {
-      const int first = soff[i] + off;
-      soff[i] = first;
-      srange[i] = make_int2(first, first + min(count[i], cap));
+      const int2 rg = make_int2(off, off + v[k]);
+      srange[i] = rg;
+      srange_a[order[i]] = rg;
     }
-  }
-  if (threadIdx.x == 0) {
-    if (blockIdx.x == gridDim.x - 1) soff[n] = off + tile_sum[2 * blockIdx.x];
-    if (blockIdx.x == 0) *maxcount = m;
+    off += v[k];
   }
 }
 
@@ -591,14 +612,14 @@ __global__ __launch_bounds__(kBS) void k_reverse(int n, int cap, const float4 *_
 // FP64.  Thread per atom: the outputs are written contiguously.
 template <class S>
 __global__ void k_gather(int n, const int32_t *__restrict__ pos,
-                         const int32_t *__restrict__ soff, const S *__restrict__ fslot,
+                         const int2 *__restrict__ srange_a, const S *__restrict__ fslot,
                          const double *__restrict__ fown, double *__restrict__ F, int accumulate) {
   int a = blockIdx.x * blockDim.x + threadIdx.x;
   if (a >= n) return;
   const int t = pos[a];
-  const int s0 = soff[t], s1 = soff[t + 1];
+  const int2 rg = srange_a[a];
   double fx = fown[3 * t], fy = fown[3 * t + 1], fz = fown[3 * t + 2];
-  sum_slots(fslot, s0, s1, fx, fy, fz);
+  sum_slots(fslot, rg.x, rg.y, fx, fy, fz);
   if (accumulate) {
     F[3 * a] += fx;
     F[3 * a + 1] += fy;
@@ -672,17 +693,19 @@ void nlist_build(NList &nl, const double *x, const int32_t *type, int ntypes, co
     int g = grid_for(work, kBS);
     return g < 1 ? 1 : (g > gcap ? gcap : g);
   };
-  if (n > 0)
-    k_bin<<<grid(n), kBS, 0, s>>>(n, x, conf, conf_of, nl.cell_of.as<int32_t>(), cell_count, type,
-                                  ntypes, cond, err);
-  if (m <= kScan1Max) {
+  if (n <= 0) return;  // nothing reads the cells of an empty set
+  // one-pass scan state: two tickets, then the tile flags of the cell scan and
+  // of the slot scan
+  const int ntc = grid_for(m, kLbTile), nts = grid_for((int64_t)n + 1, kLbTile);
+  unsigned long long *lb = nl.lbstate.as<unsigned long long>();
+  int32_t *tickets = reinterpret_cast<int32_t *>(lb);
+  k_bin<<<grid(n), kBS, 0, s>>>(n, x, conf, conf_of, nl.cell_of.as<int32_t>(), cell_count, type,
+                                ntypes, lb, 1 + ntc + nts, nl.maxcount.as<int32_t>(), cond, err);
+  if (m <= kScan1Max)
     k_scan_single<<<1, kScan1BS, 0, s>>>(cell_count, cell_start, m, cond);
-  } else {
-    const int ntile = grid_for(m, kScanTile);
-    k_scan_tiles<<<ntile, kBS, 0, s>>>(cell_count, cell_start, m, nl.scan_tmp.as<int32_t>(), cond);
-    k_scan_add<<<ntile, kBS, 0, s>>>(cell_start, m, nl.scan_tmp.as<int32_t>(), cell_count, cond);
-  }
-  if (n > 0) {
+  else
+    k_scan_cells<<<ntc, kBS, 0, s>>>(cell_count, cell_start, m, tickets, lb + 1, cond);
+  {
     k_place<<<grid(n), kBS, 0, s>>>(n, x, nl.cell_of.as<int32_t>(), cell_start, cell_count,
                                     nl.order.as<int32_t>(), nl.xref.as<double>(), cond);
     k_sort_cells<<<grid(ncell), kBS, 0, s>>>(ncell, cell_start, nl.order.as<int32_t>(), cell_count,
@@ -704,12 +727,10 @@ void nlist_build(NList &nl, const double *x, const int32_t *type, int ntypes, co
                                  cell_start, (float)(rl * rl), nl.cap, nl.count.as<int32_t>(),
                                  nl.list.as<int32_t>(), nl.plist.as<int32_t>(), cond, err,
                                  rebuild_counter);
-    const int ntile = grid_for(n, kScanTile);
-    k_slot_tiles<<<ntile, kBS, 0, s>>>(nl.count.as<int32_t>(), nl.cap, n, nl.soff.as<int32_t>(),
-                                       nl.bsum.as<int32_t>(), cond);
-    k_slot_add<<<ntile, kBS, 0, s>>>(nl.soff.as<int32_t>(), n, nl.cap, nl.count.as<int32_t>(),
-                                     nl.bsum.as<int32_t>(), nl.srange.as<int2>(),
-                                     nl.maxcount.as<int32_t>(), cond);
+    k_slots<<<nts, kBS, 0, s>>>(nl.count.as<int32_t>(), nl.cap, n, nl.order.as<int32_t>(),
+                                nl.soff.as<int32_t>(), nl.srange.as<int2>(),
+                                nl.srange_a.as<int2>(), nl.maxcount.as<int32_t>(), tickets + 1,
+                                lb + 1 + ntc, cond);
     k_reverse<<<gt, kBS, 0, s>>>(n, nl.cap, nl.xs.as<float4>(), nl.srange.as<int2>(),
                                  nl.list.as<int32_t>(), nl.plist.as<int32_t>(),
                                  nl.rev.as<int32_t>(), cond, err);
@@ -721,11 +742,11 @@ void launch_gather(const NList &nl, const void *fslot, bool slot_f32, const doub
   if (nl.n <= 0) return;
   if (slot_f32)
     k_gather<float><<<grid_for(nl.n, kBS), kBS, 0, s>>>(
-        nl.n, nl.pos.as<int32_t>(), nl.soff.as<int32_t>(), (const float *)fslot, fown, F,
+        nl.n, nl.pos.as<int32_t>(), nl.srange_a.as<int2>(), (const float *)fslot, fown, F,
         accumulate);
   else
     k_gather<double><<<grid_for(nl.n, kBS), kBS, 0, s>>>(
-        nl.n, nl.pos.as<int32_t>(), nl.soff.as<int32_t>(), (const double *)fslot, fown, F,
+        nl.n, nl.pos.as<int32_t>(), nl.srange_a.as<int2>(), (const double *)fslot, fown, F,
         accumulate);
 }
 

@@ -88,9 +88,9 @@ struct NList {
   DevBuf cell_of;     // int32[n]
   DevBuf cell_count;  // int32[ncell + 1]
   DevBuf cell_start;  // int32[ncell + 1]
-  DevBuf scan_tmp;    // int32 block sums
+  DevBuf lbstate;     // uint64[1 + tiles of the cell scan + tiles of the slot scan]: one-pass scan state
   DevBuf xref;        // double[n][3]
-  DevBuf maxcount;    // int32[1]
+  DevBuf maxcount;    // int32[1]: longest row of the last build if longer than cap, else 0
   DevBuf rev;         // int32[n][cap]: incoming force slot at j of row entry (t, j)
   DevBuf xs;          // float4[n]: positions at build time, in cell order, wrapped into the box
                       // (FP32), atom index in the fourth word
@@ -98,8 +98,8 @@ struct NList {
   DevBuf cell_at;     // int32[n]: cell of the atom at each cell-order position
   DevBuf plist;       // int32[n][cap]: positions of the row entries (list build and reverse map)
   DevBuf srange;      // int2[n]: (soff[t], soff[t + 1])
+  DevBuf srange_a;    // int2[n]: the same by atom, (soff[pos[a]], soff[pos[a] + 1])
   DevBuf soff;        // int32[n + 1]: first incoming force slot of the atom at each cell-order position
-  DevBuf bsum;        // int32[2 * (n / 1024 + 1)]: slot total and longest row per scan tile
 };
 
 // Forward / adjoint launch description.
@@ -163,6 +163,7 @@ void nlist_build(NList &nl, const double *x, const int32_t *type, int ntypes, co
                  uint32_t *err, hipStream_t s, int64_t *rebuild_counter = nullptr);
 void nlist_check(const NList &nl, const double *x, int32_t *flag, hipStream_t s);
 // F[a] (+)= fown[t] + sum of the incoming slots fslot[soff[t] .. soff[t + 1]), t = pos[a]
+// (the range read from srange_a)
 // (FP32 slots when slot_f32), summed in FP64 in slot order
 void launch_gather(const NList &nl, const void *fslot, bool slot_f32, const double *fown,
                    double *F, int accumulate, hipStream_t s);
