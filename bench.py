@@ -224,7 +224,7 @@ def main():
         ach = fl / (us * 1e-6)
         r = {"bound": "alu", "achieved": ach / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
              "frac": ach / peak, "traffic": traffic_of(sch, tname, n),
-             "kernel": ("k_force_wave<%s, true, false, false>" % tname if sch["kernel"] == 2
+             "kernel": ("k_force_wave<%s, true, false, false, false>" % tname if sch["kernel"] == 2
                         else "k_force<%s, true, false, ...>" % tname),
              "kernel_us": us, "kernel_us_timing": "HIP events around each force launch of %d MD "
                                                   "steps" % args.steps,

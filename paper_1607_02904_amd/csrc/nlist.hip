@@ -537,9 +537,9 @@ __global__ __launch_bounds__(kBS) void k_slots(const int32_t *__restrict__ count
 // row p).  The list is symmetric by construction (r_ij and r_ji are computed
 // from exactly negated displacements), so the place exists; a missing one is
 // latched as an error.  One thread per row, eight entries at a time: their
-// positions and slot ranges, then the first eight entries of each of their
-// rows (16-byte loads; rows start 16-byte aligned, cap being a multiple of 8),
-// all fetched before any is searched.
+// positions and slot ranges, then the entries of each of their rows four at a
+// time (16-byte loads; rows start 16-byte aligned, cap being a multiple of 8),
+// the loads of all eight rows in flight together.
 __global__ __launch_bounds__(kBS) void k_reverse(int n, int cap, const float4 *__restrict__ xs,
                                                  const int2 *__restrict__ srange,
                                                  const int32_t *__restrict__ list,
@@ -570,15 +570,15 @@ __global__ __launch_bounds__(kBS) void k_reverse(int n, int cap, const float4 *_
       cj[u] = live ? rg.y - rg.x : 0;
       found[u] = -1;
     }
-    for (int k = 0; k < cap; k += 8) {
-      int4 v[8][2];
+    // four entries of each searched row at a time; the next four only for
+    // the entries not found yet
+    for (int k = 0; k < cap; k += 4) {
+      int4 v[8];
       bool any = false;
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         if (found[u] < 0 && k < cj[u]) {
-          const int4 *src = reinterpret_cast<const int4 *>(list + (int64_t)p[u] * cap + k);
-          v[u][0] = src[0];
-          v[u][1] = k + 4 < cj[u] ? src[1] : make_int4(-1, -1, -1, -1);
+          v[u] = *reinterpret_cast<const int4 *>(list + (int64_t)p[u] * cap + k);
           any = true;
         }
       }
@@ -586,11 +586,10 @@ __global__ __launch_bounds__(kBS) void k_reverse(int n, int cap, const float4 *_
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         if (found[u] < 0 && k < cj[u]) {
-          const int w[8] = {v[u][0].x, v[u][0].y, v[u][0].z, v[u][0].w,
-                            v[u][1].x, v[u][1].y, v[u][1].z, v[u][1].w};
-#pragma unroll
-          for (int q = 7; q >= 0; --q)
-            if (k + q < cj[u] && w[q] == i) found[u] = k + q;
+          if (v[u].x == i) found[u] = k;
+          else if (k + 1 < cj[u] && v[u].y == i) found[u] = k + 1;
+          else if (k + 2 < cj[u] && v[u].z == i) found[u] = k + 2;
+          else if (k + 3 < cj[u] && v[u].w == i) found[u] = k + 3;
         }
       }
     }

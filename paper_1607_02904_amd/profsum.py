@@ -1,6 +1,6 @@
 """Summaries of rocprofv3 output for the force kernel.
 
-Three reports, all plain text:
+Four reports, all plain text:
 
 * ``stats``: the rows of a ``--kernel-trace --stats`` kernel_stats.csv for the
   kernels whose names contain the given filters;
@@ -10,13 +10,19 @@ Three reports, all plain text:
   (``FETCH_SIZE``, then ``WRITE_SIZE``, KiB per dispatch), each scaled by what
   the same counter reads for a plain device copy of known size in the same
   run, with the hash of the kernel's sources so that a reader can tell whether
-  the figure still applies to the kernel as built.
+  the figure still applies to the kernel as built;
+* ``rebuild``: from a ``--kernel-trace`` kernel_trace.csv, the average
+  duration of every list kernel over the molecular-dynamics steps that
+  rebuilt the list and over those that did not (the list kernels of a step
+  run from the binning pass to the next force launch; a step rebuilt when its
+  list build took longer than a threshold).
 
     python -m paper_1607_02904_amd.profsum stats STATS_CSV [FILTER ...]
     python -m paper_1607_02904_amd.profsum traffic FETCH_CSV WRITE_CSV \\
         --kernel NAME_PART --grid GRID --copy-bytes BYTES
     python -m paper_1607_02904_amd.profsum mix PMC_CSV [PMC_CSV ...] \\
         --kernel NAME_PART --grid GRID
+    python -m paper_1607_02904_amd.profsum rebuild TRACE_CSV [--threshold-us US]
 
 The copy kernel is the dispatch whose name contains ``copyBuffer`` and whose
 ``FETCH_SIZE`` is largest.
@@ -115,6 +121,39 @@ def read_summary(path):
                 out[k.strip()] = v.strip()
     return out
 
+def rebuild(path, threshold_us):
+    """Average durations (us) of the list kernels of the steps that rebuilt
+    the list and of those that did not, in launch order."""
+    import re
+    rows = []
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            m = re.search(r"(k_\w+|__amd\w+)", r["Kernel_Name"])
+            dur = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+            rows.append((int(r["Start_Timestamp"]), m.group(1) if m else r["Kernel_Name"][:40], dur))
+    rows.sort()
+    chains = []
+    for i, (_, name, _) in enumerate(rows):
+        if name != "k_bin":
+            continue
+        seq = []
+        for _, n2, d2 in rows[i:]:
+            if n2.startswith("k_force"):
+                break
+            seq.append((n2, d2))
+        chains.append(seq)
+    out = {}
+    for key, sel in (("rebuild", lambda c: any(n == "k_build" and d > threshold_us for n, d in c)),
+                     ("no_rebuild", lambda c: not any(n == "k_build" and d > threshold_us for n, d in c))):
+        cs = [c for c in chains if sel(c)]
+        per = {}
+        for c in cs:
+            for n, d in c:
+                per.setdefault(n, []).append(d)
+        out[key] = (len(cs), {n: sum(v) / len(v) for n, v in per.items()},
+                    sum(sum(d for _, d in c) for c in cs) / max(len(cs), 1))
+    return out
+
 
 def main():
     ap = argparse.ArgumentParser()
@@ -132,9 +171,18 @@ def main():
     m.add_argument("csv", nargs="+")
     m.add_argument("--kernel", required=True)
     m.add_argument("--grid", type=int, required=True)
+    b = sub.add_parser("rebuild")
+    b.add_argument("csv")
+    b.add_argument("--threshold-us", type=float, default=8.0)
     a = ap.parse_args()
     if a.cmd == "stats":
         print("\n".join(stats(a.csv, a.filters)))
+    elif a.cmd == "rebuild":
+        for key, (count, per, total) in rebuild(a.csv, a.threshold_us).items():
+            print("%s_steps: %d" % (key, count))
+            print("%s_total_us: %.1f" % (key, total))
+            for n, d in per.items():
+                print("%s_%s_us: %.1f" % (key, n, d))
     elif a.cmd == "mix":
         r, counts = mix(a.csv, a.kernel, a.grid)
         print("kernel: %s" % a.kernel)
