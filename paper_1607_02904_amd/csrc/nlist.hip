@@ -24,6 +24,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 namespace ters {
 
@@ -422,45 +423,63 @@ __global__ __launch_bounds__(kBS) void k_build(int n, const float4 *__restrict__
   int32_t *prow = plist + (int64_t)t * cap;
   int cnt = 0;
   // candidates are fetched U at a time from xs[k0 ..]: xs carries U - 1
-  // padding entries past n, and entries at or past the run's end are not taken
+  // padding entries past n, and entries at or past the run's end are not
+  // taken.  Image shifts that are zero are not added (adding zero changes no
+  // distance, so the pair (k, i) still sees the negated displacement): the
+  // x shift exists only on far runs, the y and z shifts only in the rows of a
+  // wavefront that touch the box's faces.  Only the near run of the middle
+  // row holds the atom itself.
   constexpr int U = 4;
+  auto walk = [&](auto far_c, auto yz_c, auto mid_c, int r, int b, int e)
+                  __attribute__((always_inline)) {
+    constexpr bool FAR = decltype(far_c)::value, YZ = decltype(yz_c)::value;
+    constexpr bool MID = decltype(mid_c)::value;
+    for (int k0 = b; k0 < e; k0 += U) {
+      float4 q[U];
+      const float4 *src = xs + k0;
 #pragma unroll
-  for (int r = 0; r < 9; ++r) {
+      for (int u = 0; u < U; ++u) q[u] = src[u];
 #pragma unroll
-    for (int seg = 0; seg < 2; ++seg) {  // near run, far run
-      const int b = seg ? fb[r] : nb[r], e = seg ? fe[r] : ne[r];
-      const float sx = seg ? sfx : 0.f;
-      for (int k0 = b; k0 < e; k0 += U) {
-        float4 q[U];
-        const float4 *src = xs + k0;
-#pragma unroll
-        for (int u = 0; u < U; ++u) q[u] = src[u];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          float dx = q[u].x - qi.x, dy = q[u].y - qi.y, dz = q[u].z - qi.z;
-          if (!MINIMG) {
-            dx += sx;
+      for (int u = 0; u < U; ++u) {
+        float dx = q[u].x - qi.x, dy = q[u].y - qi.y, dz = q[u].z - qi.z;
+        if (!MINIMG) {
+          if (FAR) dx += sfx;
+          if (YZ) {
             dy += sy[r];
             dz += sz[r];
-          } else {  // the form is a property of the configuration, the same for (k, i)
-            dx = fixed ? dx + sx : dx - bx * rintf(dx * ibx);
-            dy = fixed ? dy + sy[r] : dy - by * rintf(dy * iby);
-            dz = fixed ? dz + sz[r] : dz - bz * rintf(dz * ibz);
           }
-          const int p = k0 + u;
-          if (p < e && p != t && dx * dx + dy * dy + dz * dz <= rl2) {
-            if (LDSOUT && cnt < cap) {
-              oid[lane * cap + cnt] = __float_as_int(q[u].w);
-              opos[lane * cap + cnt] = p;
-            } else if (!LDSOUT && act && cnt < cap) {
-              row[cnt] = __float_as_int(q[u].w);
-              prow[cnt] = p;
-            }
-            ++cnt;
+        } else {  // the form is a property of the configuration, the same for (k, i)
+          dx = fixed ? dx + (FAR ? sfx : 0.f) : dx - bx * rintf(dx * ibx);
+          dy = fixed ? dy + sy[r] : dy - by * rintf(dy * iby);
+          dz = fixed ? dz + sz[r] : dz - bz * rintf(dz * ibz);
+        }
+        const int p = k0 + u;
+        if (p < e && (!MID || p != t) && dx * dx + dy * dy + dz * dz <= rl2) {
+          if (LDSOUT && cnt < cap) {
+            oid[lane * cap + cnt] = __float_as_int(q[u].w);
+            opos[lane * cap + cnt] = p;
+          } else if (!LDSOUT && act && cnt < cap) {
+            row[cnt] = __float_as_int(q[u].w);
+            prow[cnt] = p;
           }
+          ++cnt;
         }
       }
     }
+  };
+  using TT = std::true_type;
+  using FF = std::false_type;
+#pragma unroll
+  for (int r = 0; r < 9; ++r) {
+    const bool yz = __ballot(sy[r] != 0.f || sz[r] != 0.f) != 0ull;  // uniform
+    if (r == 4) {
+      if (yz) walk(FF(), TT(), TT(), r, nb[r], ne[r]);
+      else walk(FF(), FF(), TT(), r, nb[r], ne[r]);
+    } else {
+      if (yz) walk(FF(), TT(), FF(), r, nb[r], ne[r]);
+      else walk(FF(), FF(), FF(), r, nb[r], ne[r]);
+    }
+    if (__ballot(fe[r] > fb[r]) != 0ull) walk(TT(), TT(), FF(), r, fb[r], fe[r]);
   }
   if (act) {
     count[t] = cnt;
