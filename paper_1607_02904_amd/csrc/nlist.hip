@@ -4,8 +4,9 @@
 //   bin     atom -> cell of side >= r_list in its own configuration's grid,
 //           count atoms per cell
 //   scan    exclusive prefix sum of the cell counts (cell_start), one pass
-//   place   counting-sort the atoms into cells; keep the reference positions
-//           of the rebuild check
+//   place   counting-sort the atoms into cells (each atom's place in its cell
+//           was taken by the binning pass); keep the reference positions of
+//           the rebuild check
 //   sort    order atoms inside each cell by index (run-to-run determinism)
 //           and keep a cell-ordered copy of the positions
 //   build   for each atom scan the 27 surrounding cells (1 along an axis that
@@ -56,16 +57,19 @@ __global__ void k_fill_f64(double *p, double v, int64_t n) {
     p[i] = v;
 }
 
-DEV void bin_one(int i, const double *__restrict__ x, const ConfDesc *__restrict__ conf,
-                 const int32_t *__restrict__ conf_of, int32_t *__restrict__ cell_of,
-                 int32_t *__restrict__ cell_count, uint32_t *err);
+DEV int bin_one(int i, const double *__restrict__ x, const ConfDesc *__restrict__ conf,
+                const int32_t *__restrict__ conf_of, int32_t *__restrict__ cell_of,
+                int32_t *__restrict__ cell_count, uint32_t *err);
 
-// also checks every species against [0, ntypes) when type is given, and
-// clears the state of this build's one-pass scans (tickets, tile flags, the
-// longest-row register)
+// records each atom's place among the atoms of its cell (in slot, in the
+// order the counts were taken; the sort makes the order canonical), also
+// checks every species against [0, ntypes) when type is given, and clears the
+// state of this build's one-pass scans (tickets, tile flags, the longest-row
+// register)
 __global__ void k_bin(int n, const double *__restrict__ x, const ConfDesc *__restrict__ conf,
                       const int32_t *__restrict__ conf_of, int32_t *__restrict__ cell_of,
-                      int32_t *__restrict__ cell_count, const int32_t *__restrict__ type,
+                      int32_t *__restrict__ cell_count, int32_t *__restrict__ slot,
+                      const int32_t *__restrict__ type,
                       int ntypes, unsigned long long *__restrict__ lb, int64_t nlb,
                       int32_t *__restrict__ maxcount, const int32_t *cond, uint32_t *err) {
   if (skip(cond)) return;
@@ -74,14 +78,14 @@ __global__ void k_bin(int n, const double *__restrict__ x, const ConfDesc *__res
     lb[k] = 0ull;
   if (blockIdx.x == 0 && threadIdx.x == 0) *maxcount = 0;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    bin_one(i, x, conf, conf_of, cell_of, cell_count, err);
+    slot[i] = bin_one(i, x, conf, conf_of, cell_of, cell_count, err);
     if (type && (unsigned)type[i] >= (unsigned)ntypes) atomicOr(err, kErrBadType);
   }
 }
 
-DEV void bin_one(int i, const double *__restrict__ x, const ConfDesc *__restrict__ conf,
-                 const int32_t *__restrict__ conf_of, int32_t *__restrict__ cell_of,
-                 int32_t *__restrict__ cell_count, uint32_t *err) {
+DEV int bin_one(int i, const double *__restrict__ x, const ConfDesc *__restrict__ conf,
+                const int32_t *__restrict__ conf_of, int32_t *__restrict__ cell_of,
+                int32_t *__restrict__ cell_count, uint32_t *err) {
   const ConfDesc &c = conf[conf_index(conf_of, i)];
   int q[3];
   bool finite = true;
@@ -98,7 +102,7 @@ DEV void bin_one(int i, const double *__restrict__ x, const ConfDesc *__restrict
   if (!finite) atomicOr(err, kErrNotFinite);
   int cell = c.cell_off + (q[2] * c.nc[1] + q[1]) * c.nc[0] + q[0];
   cell_of[i] = cell;
-  atomicAdd(&cell_count[cell], 1);
+  return atomicAdd(&cell_count[cell], 1);
 }
 
 // ---- exclusive scans of int32 ----
@@ -262,14 +266,12 @@ __global__ __launch_bounds__(kScan1BS) void k_scan_single(int32_t *__restrict__ 
 }
 
 __global__ void k_place(int n, const double *__restrict__ x, const int32_t *__restrict__ cell_of,
-                        const int32_t *__restrict__ cell_start, int32_t *__restrict__ cursor,
+                        const int32_t *__restrict__ cell_start, const int32_t *__restrict__ slot,
                         int32_t *__restrict__ order, double *__restrict__ xref,
                         const int32_t *cond) {
   if (skip(cond)) return;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    int c = cell_of[i];
-    int pos = cell_start[c] + atomicAdd(&cursor[c], 1);
-    order[pos] = i;
+    order[cell_start[cell_of[i]] + slot[i]] = i;
     xref[3 * i + 0] = x[3 * i + 0];
     xref[3 * i + 1] = x[3 * i + 1];
     xref[3 * i + 2] = x[3 * i + 2];
@@ -717,15 +719,19 @@ void nlist_build(NList &nl, const double *x, const int32_t *type, int ntypes, co
   const int ntc = grid_for(m, kLbTile), nts = grid_for((int64_t)n + 1, kLbTile);
   unsigned long long *lb = nl.lbstate.as<unsigned long long>();
   int32_t *tickets = reinterpret_cast<int32_t *>(lb);
-  k_bin<<<grid(n), kBS, 0, s>>>(n, x, conf, conf_of, nl.cell_of.as<int32_t>(), cell_count, type,
-                                ntypes, lb, 1 + ntc + nts, nl.maxcount.as<int32_t>(), cond, err);
+  // the place of each atom in its cell is kept in pos until the sort writes
+  // the atoms' final positions there
+  k_bin<<<grid(n), kBS, 0, s>>>(n, x, conf, conf_of, nl.cell_of.as<int32_t>(), cell_count,
+                                nl.pos.as<int32_t>(), type, ntypes, lb, 1 + ntc + nts,
+                                nl.maxcount.as<int32_t>(), cond, err);
   if (m <= kScan1Max)
     k_scan_single<<<1, kScan1BS, 0, s>>>(cell_count, cell_start, m, cond);
   else
     k_scan_cells<<<ntc, kBS, 0, s>>>(cell_count, cell_start, m, tickets, lb + 1, cond);
   {
-    k_place<<<grid(n), kBS, 0, s>>>(n, x, nl.cell_of.as<int32_t>(), cell_start, cell_count,
-                                    nl.order.as<int32_t>(), nl.xref.as<double>(), cond);
+    k_place<<<grid(n), kBS, 0, s>>>(n, x, nl.cell_of.as<int32_t>(), cell_start,
+                                    nl.pos.as<int32_t>(), nl.order.as<int32_t>(),
+                                    nl.xref.as<double>(), cond);
     k_sort_cells<<<grid(ncell), kBS, 0, s>>>(ncell, cell_start, nl.order.as<int32_t>(), cell_count,
                                              x, conf, conf_of, nl.xs.as<float4>(),
                                              nl.cell_at.as<int32_t>(), nl.pos.as<int32_t>(), cond);
