@@ -346,6 +346,10 @@ def main():
     if not args.md_only:
         print("bench: pair potential", file=sys.stderr, flush=True)
         model.build_nlist(x0, td, box, skin)
+        entries = model.nlist_stats()["entries"]
+        # bytes an evaluation must move at least: the list entries, counts and
+        # cell order, every position once and the forces written
+        lj_bytes = 4.0 * entries + 8.0 * n + 24.0 * n + 24.0 * n
         pl = {}
         for prec, tag in ((MIXED, "mixed"), (FP64, "fp64")):
             model.pair_compute(x0, box, 0.05, 2.1, 3.0, prec)
@@ -356,10 +360,24 @@ def main():
                 model.pair_compute(x0, box, 0.05, 2.1, 3.0, prec)
             torch.cuda.synchronize()
             el = (time.perf_counter() - t0) / reps
-            pl[tag] = {"value": n / el, "unit": "atom-steps/s", "ms_per_eval": el * 1e3}
+            # device time of an evaluation (kernel and energy reduction, stream order)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                model.pair_compute(x0, box, 0.05, 2.1, 3.0, prec)
+            e1.record()
+            torch.cuda.synchronize()
+            dus = e0.elapsed_time(e1) / reps * 1e3
+            pl[tag] = {"value": n / el, "unit": "atom-steps/s", "ms_per_eval": el * 1e3,
+                       "device_us_per_eval": dus,
+                       "roofline": {"bound": "hbm", "achieved": lj_bytes / (dus * 1e-6) / 1e9,
+                                    "peak": 8000.0, "unit": "GB/s",
+                                    "frac": lj_bytes / (dus * 1e-6) / 8e12, "traffic": None,
+                                    "algorithmic_bytes": lj_bytes}}
         out["pair_lj"] = dict(pl, note="truncated Lennard-Jones (eps 0.05 eV, sigma 2.1 A, "
                                        "r_c 3.0 A) over the Tersoff list of the headline "
-                                       "configuration; one evaluation, outputs allocated per call")
+                                       "configuration; one evaluation, outputs allocated per call; "
+                                       "algorithmic bytes = 4 per list entry + 56 per atom")
 
     # ---- two-species SiC, 1,000,000 atoms, one mixed evaluation ----------------
     if not args.quick and not args.md_only:

@@ -6,7 +6,10 @@
 // position, full list: j in i's row and i in j's).  One thread per atom in
 // cell order walks its row and sums the forces on its own atom, so every atom's
 // force is written once, without atomics; the energy and virial halves of a
-// pair are counted from both ends.  The list's radius must be at least r_c
+// pair are counted from both ends.  The row is taken eight entries at a time:
+// their indices (two 16-byte loads; rows are 16-byte aligned, cap being a
+// multiple of 8), then all eight neighbours' positions, then the arithmetic,
+// so that a thread has one round of dependent loads per eight neighbours.  The list's radius must be at least r_c
 // (entries beyond r_c are skipped, as the filter of Section IV-B does).
 // Precision: FP64, or FP32 arithmetic with FP64 displacements, distances and
 // accumulators.
@@ -33,12 +36,24 @@ __global__ __launch_bounds__(kPBS) void k_pair_lj(PairArgs p) {
     for (int k = 0; k < 3; ++k) xi[k] = p.x[3 * (int64_t)i + k];
     const T eps4 = (T)(4.0 * p.eps), eps24 = (T)(24.0 * p.eps), sig2 = (T)(p.sigma * p.sigma);
     double fi[3] = {0.0, 0.0, 0.0};
-    for (int s = 0; s < cnt; ++s) {
-      const int j = row[s];
+    for (int s0 = 0; s0 < cnt; s0 += 8) {
+      const int4 ja = *reinterpret_cast<const int4 *>(row + s0);
+      const int4 jb = *reinterpret_cast<const int4 *>(row + s0 + 4);
+      const int jj[8] = {ja.x, ja.y, ja.z, ja.w, jb.x, jb.y, jb.z, jb.w};
+      double xj[8][3];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int j = s0 + u < cnt ? jj[u] : i;  // entries past the row's end: the atom itself
+#pragma unroll
+        for (int k = 0; k < 3; ++k) xj[u][k] = p.x[3 * (int64_t)j + k];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+      if (s0 + u >= cnt) break;
       double d[3];
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
-        const double dd = p.x[3 * (int64_t)j + k] - xi[k];
+        const double dd = xj[u][k] - xi[k];
         d[k] = dd - c.box[k] * rint(dd * c.inv_box[k]);
       }
       const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
@@ -58,6 +73,7 @@ __global__ __launch_bounds__(kPBS) void k_pair_lj(PairArgs p) {
       w[3] += 0.5 * g * d[0] * d[1];
       w[4] += 0.5 * g * d[0] * d[2];
       w[5] += 0.5 * g * d[1] * d[2];
+      }
     }
     if (p.forces) {
 #pragma unroll
