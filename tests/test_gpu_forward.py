@@ -476,6 +476,42 @@ def test_list_is_the_exact_list_up_to_the_rounding_margin(sic_model, skin):
     assert exact <= entries <= wide, (exact, entries, wide)
 
 
+# diamond Si boxes (conventional cells per axis) for the list build's cell
+# grid: with a 3.5 A list radius a side of two cells (10.86 A) holds exactly
+# three grid cells, the smallest grid the build treats with cell-fixed images
+CELL_GRIDS = {"three_cells_per_axis": (2, 2, 2), "elongated": (2, 5, 3), "slab": (5, 4, 2)}
+
+
+@pytest.mark.parametrize("shape", list(CELL_GRIDS))
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
+def test_list_build_cell_grids(orc, si_model, shape, precision):
+    """The list build takes each candidate's periodic image from the cell grid
+    (a near run of cells and, across the periodic seam, a far run per row):
+    boxes with exactly three grid cells along an axis, elongated boxes and
+    every seam, with a skin, against the oracle."""
+    nx, ny, nz = CELL_GRIDS[shape]
+    rng = np.random.default_rng(inputs.seed_for(9, 100 * nx + 10 * ny + nz))
+    x, box = inputs.diamond(nx, 5.431, ny, nz)
+    x = inputs.wrap(inputs.perturb(x, 0.1, rng), box)
+    t = np.zeros(len(x), dtype=np.int32)
+    ref = orc.compute(x, t, box, _si_table_oracle())
+    _check(gpu_eval(si_model, x, t, box, precision, skin=0.5), ref, precision)
+
+
+@pytest.mark.parametrize("seed,nmin", [(12, 80), (15, 80)])
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
+def test_list_build_single_cell_axes(orc, sic_model, seed, nmin, precision):
+    """Boxes with sides between two and three list radii hold a single grid
+    cell along those axes; there the build takes the minimum image of every
+    candidate.  Disordered SiC cells with one or two such axes and one axis of
+    three cells, with a skin, against the oracle."""
+    x, t, box = inputs.sic_liquid_batch(nconf=1, nmin=nmin, nmax=nmin + 8, seed=seed)[0]
+    cells = [int(np.floor(b / 3.5)) for b in box]
+    assert min(cells) < 3 <= max(cells), (box, cells)
+    ref = orc.compute(x, t, box, params.sic())
+    _check(gpu_eval(sic_model, x, t, box, precision, skin=0.5), ref, precision)
+
+
 def test_thread_schedule_is_forward_only(si_model):
     """The thread-per-atom schedule has no adjoint: ters_backward refuses it
     with TERS_ERR_UNSUPPORTED (7)."""
