@@ -54,14 +54,15 @@ def build_threads():
     return _LIB_THREADS
 
 
-def compute_threads(x, types, box, table, nlist):
+def compute_threads(x, types, box, table, nlist, threads=0):
     """Energy, forces and virial over a prebuilt list with the centres shared
-    among the OpenMP threads (OMP_NUM_THREADS); returns (E, F, W, threads)."""
+    among the OpenMP threads (OMP_NUM_THREADS, or at most `threads` when it is
+    positive); returns (E, F, W, threads used)."""
     global _lib_threads
     if _lib_threads is None:
         L = ctypes.CDLL(build_threads())
         P, I = ctypes.c_void_p, ctypes.c_int
-        L.orc_tersoff_threads.argtypes = [I, P, P, P, I, P, P, P, I, P, P, P]
+        L.orc_tersoff_threads.argtypes = [I, P, P, P, I, P, P, P, I, I, P, P, P]
         L.orc_tersoff_threads.restype = I
         _lib_threads = L
     x = _f64(x, (-1, 3))
@@ -74,7 +75,8 @@ def compute_threads(x, types, box, table, nlist):
     f = np.zeros((n, 3))
     w = np.zeros(6)
     nthr = _lib_threads.orc_tersoff_threads(n, _p(x), _p(types), _p(box), table.shape[0], _p(table),
-                                            _p(count), _p(lst), lst.shape[1], _p(e), _p(f), _p(w))
+                                            _p(count), _p(lst), lst.shape[1], int(threads), _p(e),
+                                            _p(f), _p(w))
     if nthr <= 0:
         raise RuntimeError("oracle threaded compute failed (%d)" % nthr)
     return float(e[0]), f, w, nthr

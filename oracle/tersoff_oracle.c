@@ -410,20 +410,22 @@ int orc_tersoff_images(int n, const double *x, const int *type, const double *bo
  * The list-based evaluation above, with the centres shared among OpenMP
  * threads (each thread sums into its own force array, energy and virial,
  * added up at the end).  Same arithmetic per centre; only the order of the
- * final sums differs.  Built only for timing the oracle on all host cores
- * (compiled with -fopenmp); without OpenMP it runs on one thread.  Returns
- * the number of threads used.
+ * final sums differs.  Built only for timing the oracle on the host's cores
+ * (compiled with -fopenmp); without OpenMP it runs on one thread.  threads
+ * > 0 caps the number of threads (0: all OpenMP offers).  Returns the number
+ * of threads used.
  * ------------------------------------------------------------------------- */
 #ifdef _OPENMP
 #include <omp.h>
 #endif
 int orc_tersoff_threads(int n, const double *x, const int *type, const double *box, int nt,
                         const double *table, const int *count, const int *list, int cap,
-                        double *energy, double *forces, double *virial) {
+                        int threads, double *energy, double *forces, double *virial) {
   if (n < 0 || nt <= 0) return -ORC_ERR_ARG;
   int nthr = 1;
 #ifdef _OPENMP
   nthr = omp_get_max_threads();
+  if (threads > 0 && threads < nthr) nthr = threads;
 #endif
   double *fth = (double *)calloc((size_t)nthr * 3 * (size_t)(n > 0 ? n : 1), sizeof(double));
   double *eth = (double *)calloc((size_t)nthr * 7, sizeof(double));
