@@ -498,6 +498,20 @@ def test_list_build_cell_grids(orc, si_model, shape, precision):
     _check(gpu_eval(si_model, x, t, box, precision, skin=0.5), ref, precision)
 
 
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
+def test_list_capacity_growth_to_64(orc, si_model, precision):
+    """A 2.6 A skin gives every Si atom 33 or 34 list neighbours (the shells at
+    2.35, 3.84, 4.50 and 5.43 A lie within r_list = 5.6 A): the capacity
+    grows to 64 and the build stores the entries as it finds them instead of
+    collecting them in LDS; the forces only see the in-cutoff pairs."""
+    x, t, box = inputs.si_small()
+    ref = orc.compute(x, t, box, _si_table_oracle())
+    got = gpu_eval(si_model, x, t, box, precision, skin=2.6)
+    st = si_model.nlist_stats()
+    assert st["capacity"] == 64 and 32 < st["longest"] <= 64, st
+    _check(got, ref, precision)
+
+
 @pytest.mark.parametrize("seed,nmin", [(12, 80), (15, 80)])
 @pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
 def test_list_build_single_cell_axes(orc, sic_model, seed, nmin, precision):
