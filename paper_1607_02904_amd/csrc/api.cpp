@@ -215,6 +215,7 @@ void nl_setup(NList &nl, int nconf, const int32_t *natoms, const double *boxes, 
   nl.count.ensure(sizeof(int32_t) * nn);
   nl.list.ensure(sizeof(int32_t) * nn * nl.cap);
   nl.order.ensure(sizeof(int32_t) * nn);
+  nl.order_u.ensure(sizeof(int32_t) * nn);
   nl.cell_of.ensure(sizeof(int32_t) * nn);
   nl.cell_count.ensure(sizeof(int32_t) * (cells + 1));
   nl.cell_start.ensure(sizeof(int32_t) * (cells + 1));
@@ -310,7 +311,7 @@ std::vector<const void *> graph_key(const ters_ctx *c, const NList &nl) {
           (const void *)(intptr_t)c->cut_consistent, (const void *)(intptr_t)c->kmax,
           (const void *)(intptr_t)c->filter,
           c->partials.p, c->errw.p, c->flag.p, c->rebuilds.p, c->step.p, c->escratch.p,
-          nl.rev.p, nl.xs.p, nl.pos.p, nl.soff.p, nl.cell_at.p, nl.plist.p, nl.srange.p, nl.srange_a.p, c->fslot.p, c->fown.p,
+          nl.rev.p, nl.xs.p, nl.pos.p, nl.soff.p, nl.cell_at.p, nl.order_u.p, nl.plist.p, nl.srange.p, nl.srange_a.p, c->fslot.p, c->fown.p,
           (const void *)(intptr_t)c->gather};
 }
 
@@ -399,7 +400,7 @@ constexpr size_t al(size_t b) { return (b + kAlign - 1) / kAlign * kAlign; }
 constexpr size_t kN = TERS_STATIC_MAX_ATOMS;
 // bytes of every scratch buffer at the largest size (layout of carve_static)
 constexpr size_t kStaticBytes =
-    al(sizeof(ConfDesc)) + 5 * al(4 * kN) + 2 * al(8 * kN) + al(4 * (kN + 1)) +
+    al(sizeof(ConfDesc)) + 6 * al(4 * kN) + 2 * al(8 * kN) + al(4 * (kN + 1)) +
     3 * al(4 * kN * kStaticCap) + 2 * al(4 * (kStaticCells + 1)) +
     al(8 * (1 + (kStaticCells + 1) / 1024 + 1 + (kN + 1) / 1024 + 1)) + al(24 * kN) +
     al(16 * (kN + 3)) + al(4) + al(64 * kN) + al(24 * kN * kStaticCap) + al(24 * kN);
@@ -497,7 +498,7 @@ ters_status ters_destroy(ters_ctx *c) {
                     &c->nl.conf_of, &c->nl.count, &c->nl.list, &c->nl.order, &c->nl.cell_of,
                     &c->nl.cell_count, &c->nl.cell_start, &c->nl.lbstate, &c->nl.xref,
                     &c->nl.maxcount, &c->nl.rev, &c->nl.xs, &c->nl.pos, &c->nl.soff,
-                    &c->nl.cell_at, &c->nl.plist, &c->nl.srange,
+                    &c->nl.cell_at, &c->nl.plist, &c->nl.order_u, &c->nl.srange,
                     &c->nl.srange_a};
   for (DevBuf *b : bufs) b->release();
   delete c;
@@ -783,6 +784,7 @@ ters_status ters_compute_static(ters_ctx *c, int32_t n, const double *x, const i
     nl.conf = cv.take(sizeof(ConfDesc));
     nl.count = cv.take(4 * N);
     nl.order = cv.take(4 * N);
+    nl.order_u = cv.take(4 * N);
     nl.cell_of = cv.take(4 * N);
     nl.pos = cv.take(4 * N);
     nl.cell_at = cv.take(4 * N);
@@ -1451,7 +1453,7 @@ static void plan_release_device(ters_plan *p) {
                     &p->nl.conf_of, &p->nl.count, &p->nl.list, &p->nl.order, &p->nl.cell_of,
                     &p->nl.cell_count, &p->nl.cell_start, &p->nl.lbstate, &p->nl.xref,
                     &p->nl.maxcount, &p->nl.rev, &p->nl.xs, &p->nl.pos, &p->nl.soff,
-                    &p->nl.cell_at, &p->nl.plist, &p->nl.srange,
+                    &p->nl.cell_at, &p->nl.plist, &p->nl.order_u, &p->nl.srange,
                     &p->nl.srange_a};
   for (DevBuf *b : bufs) b->release();
   p->ctx = nullptr;

@@ -7,8 +7,9 @@
 //   place   counting-sort the atoms into cells (each atom's place in its cell
 //           was taken by the binning pass); keep the reference positions of
 //           the rebuild check
-//   sort    order atoms inside each cell by index (run-to-run determinism)
-//           and keep a cell-ordered copy of the positions
+//   sort    order atoms inside each cell by index (run-to-run determinism:
+//           each atom's rank among its cell's atoms) and keep a cell-ordered
+//           copy of the positions
 //   build   for each atom scan the 27 surrounding cells (1 along an axis that
 //           holds fewer than 3 cells) and keep j != i with minimum-image
 //           r_ij <= r_list, in a padded row of `cap` entries
@@ -267,63 +268,53 @@ __global__ __launch_bounds__(kScan1BS) void k_scan_single(int32_t *__restrict__ 
 
 __global__ void k_place(int n, const double *__restrict__ x, const int32_t *__restrict__ cell_of,
                         const int32_t *__restrict__ cell_start, const int32_t *__restrict__ slot,
-                        int32_t *__restrict__ order, double *__restrict__ xref,
+                        int32_t *__restrict__ order_u, double *__restrict__ xref,
                         const int32_t *cond) {
   if (skip(cond)) return;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    order[cell_start[cell_of[i]] + slot[i]] = i;
+    order_u[cell_start[cell_of[i]] + slot[i]] = i;
     xref[3 * i + 0] = x[3 * i + 0];
     xref[3 * i + 1] = x[3 * i + 1];
     xref[3 * i + 2] = x[3 * i + 2];
   }
 }
 
-// order atoms inside each cell by index, record each atom's position in the
-// cell order (pos, the inverse of order) and copy the positions in that order
-// for the build (xs: FP32, wrapped into the configuration's box, with the
-// atom index in the fourth word; the build's distance test allows for that
-// rounding) together with the cell coordinates of each position (cell_at:
-// x | y << 11 | z << 22 within the configuration's grid); the counts (used as
-// placement cursors) are cleared for the next build
-__global__ void k_sort_cells(int64_t ncell, const int32_t *__restrict__ cell_start,
-                             int32_t *__restrict__ order, int32_t *__restrict__ counts,
+// order atoms inside each cell by index: the atom placed at position p of its
+// cell's range [b, e) goes to b + (number of the cell's atoms with a smaller
+// index), one thread per atom, so that a crowded cell costs its size per
+// atom, not its square on one thread.  Records each atom's position in the
+// cell order (pos, the inverse of order) and copies the positions in that
+// order for the build (xs: FP32, wrapped into the configuration's box, with
+// the atom index in the fourth word; the build's distance test allows for
+// that rounding) together with the cell coordinates of each position
+// (cell_at: x | y << 11 | z << 22 within the configuration's grid).
+__global__ void k_sort_cells(int n, const int32_t *__restrict__ cell_start,
+                             const int32_t *__restrict__ cell_of,
+                             const int32_t *__restrict__ order_u, int32_t *__restrict__ order,
                              const double *__restrict__ x, const ConfDesc *__restrict__ conf,
                              const int32_t *__restrict__ conf_of, float4 *__restrict__ xs,
                              int32_t *__restrict__ cell_at, int32_t *__restrict__ pos,
                              const int32_t *cond) {
   if (skip(cond)) return;
-  for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < ncell;
-       c += (int64_t)gridDim.x * blockDim.x) {
-    int b = cell_start[c], e = cell_start[c + 1];
-    for (int p = b + 1; p < e; ++p) {
-      int v = order[p];
-      int q = p - 1;
-      while (q >= b && order[q] > v) {
-        order[q + 1] = order[q];
-        --q;
-      }
-      order[q + 1] = v;
-    }
-    int packed = 0;
-    if (e > b) {
-      const ConfDesc &cf = conf[conf_index(conf_of, order[b])];
-      const int lc = (int)c - cf.cell_off, nx = cf.nc[0], ny = cf.nc[1];
-      packed = (lc % nx) | ((lc / nx) % ny) << 11 | (lc / (nx * ny)) << 22;
-    }
-    for (int p = b; p < e; ++p) {
-      const int i = order[p];
-      pos[i] = p;
-      const ConfDesc &cf = conf[conf_index(conf_of, i)];
-      float w[3];
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gridDim.x * blockDim.x) {
+    const int i = order_u[p];
+    const int c = cell_of[i];
+    const int b = cell_start[c], e = cell_start[c + 1];
+    int rank = 0;
+    for (int q = b; q < e; ++q) rank += order_u[q] < i;
+    const int t = b + rank;
+    order[t] = i;
+    pos[i] = t;
+    const ConfDesc &cf = conf[conf_index(conf_of, i)];
+    float w[3];
 #pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        const double v = x[3 * i + a];
-        w[a] = (float)(v - cf.box[a] * floor(v * cf.inv_box[a]));
-      }
-      xs[p] = make_float4(w[0], w[1], w[2], __int_as_float(i));
-      cell_at[p] = packed;
+    for (int a = 0; a < 3; ++a) {
+      const double v = x[3 * i + a];
+      w[a] = (float)(v - cf.box[a] * floor(v * cf.inv_box[a]));
     }
-    counts[c] = 0;
+    xs[t] = make_float4(w[0], w[1], w[2], __int_as_float(i));
+    const int lc = c - cf.cell_off, nx = cf.nc[0], ny = cf.nc[1];
+    cell_at[t] = (lc % nx) | ((lc / nx) % ny) << 11 | (lc / (nx * ny)) << 22;
   }
 }
 
@@ -730,11 +721,12 @@ void nlist_build(NList &nl, const double *x, const int32_t *type, int ntypes, co
     k_scan_cells<<<ntc, kBS, 0, s>>>(cell_count, cell_start, m, tickets, lb + 1, cond);
   {
     k_place<<<grid(n), kBS, 0, s>>>(n, x, nl.cell_of.as<int32_t>(), cell_start,
-                                    nl.pos.as<int32_t>(), nl.order.as<int32_t>(),
+                                    nl.pos.as<int32_t>(), nl.order_u.as<int32_t>(),
                                     nl.xref.as<double>(), cond);
-    k_sort_cells<<<grid(ncell), kBS, 0, s>>>(ncell, cell_start, nl.order.as<int32_t>(), cell_count,
-                                             x, conf, conf_of, nl.xs.as<float4>(),
-                                             nl.cell_at.as<int32_t>(), nl.pos.as<int32_t>(), cond);
+    k_sort_cells<<<grid(n), kBS, 0, s>>>(n, cell_start, nl.cell_of.as<int32_t>(),
+                                         nl.order_u.as<int32_t>(), nl.order.as<int32_t>(), x, conf,
+                                         conf_of, nl.xs.as<float4>(), nl.cell_at.as<int32_t>(),
+                                         nl.pos.as<int32_t>(), cond);
     // FP32 distance test on positions wrapped into the box: a coordinate is
     // rounded by at most 2^-24 of the longest side, a squared distance by a
     // few units in the last place; the radius grows by a bound of both, so no

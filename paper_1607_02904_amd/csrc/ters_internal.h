@@ -85,6 +85,7 @@ struct NList {
   DevBuf count;       // int32[n]: row lengths, by cell-order position
   DevBuf list;        // int32[n][cap]: row t = neighbours (atoms) of the atom at position t
   DevBuf order;       // int32[n]: atoms in cell order
+  DevBuf order_u;     // int32[n]: the same before the order inside each cell is fixed
   DevBuf cell_of;     // int32[n]
   DevBuf cell_count;  // int32[ncell + 1]
   DevBuf cell_start;  // int32[ncell + 1]
