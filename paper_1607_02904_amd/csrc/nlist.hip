@@ -337,8 +337,10 @@ __global__ void k_sort_cells(int n, const int32_t *__restrict__ cell_start,
 //
 // Hits are taken in the order (row, near run, far run, position): the
 // neighbour's atom index goes to the list row and its position to the plist
-// row.  With LDSOUT (list capacity up to 16) the rows are collected in LDS and
-// copied out with 16-byte stores; otherwise each entry is stored as found.
+// row.  With LDSOUT (list capacity up to 32) the rows are collected in LDS and
+// copied out with 16-byte stores (workgroups of BS = 256 threads for a
+// capacity of 16, 128 for 32: 32 KB of LDS either way); otherwise each entry
+// is stored as found.
 //
 // Rows and counts are indexed by cell-order position: row t lists the
 // neighbours (atom indices) of the atom at position t, so that the rows of a
@@ -346,8 +348,8 @@ __global__ void k_sort_cells(int n, const int32_t *__restrict__ cell_start,
 // force slots are numbered afterwards by a scan of the row lengths (k_slots).
 DEV int wrap_cell(int q, int nc) { return q < 0 ? q + nc : (q >= nc ? q - nc : q); }
 
-template <bool LDSOUT, bool MINIMG>
-__global__ __launch_bounds__(kBS) void k_build(int n, const float4 *__restrict__ xs,
+template <bool LDSOUT, bool MINIMG, int BS>
+__global__ __launch_bounds__(BS) void k_build(int n, const float4 *__restrict__ xs,
                                                const int32_t *__restrict__ cell_at,
                                                const ConfDesc *__restrict__ conf,
                                                const int32_t *__restrict__ conf_of,
@@ -360,7 +362,7 @@ __global__ __launch_bounds__(kBS) void k_build(int n, const float4 *__restrict__
   extern __shared__ int4 obuf4[];  // LDSOUT: [wave][2][64 * cap] int32: atom indices, positions
   if (blockIdx.x == 0 && threadIdx.x == 0 && rebuilds) *rebuilds += 1;
   const int lane = lane_id(), w = threadIdx.x / kWave;
-  const int64_t wbase = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kBS + w * kWave;
+  const int64_t wbase = (int64_t)xcd_block(blockIdx.x, gridDim.x) * BS + w * kWave;
   const bool act = wbase + lane < n;
   const int t = act ? (int)(wbase + lane) : n - 1;  // idle lanes shadow the last atom, store nothing
   const float4 qi = xs[t];
@@ -734,12 +736,29 @@ void nlist_build(NList &nl, const double *x, const int32_t *type, int ntypes, co
     const double lmax = nl.box_max;
     const double rl = nl.rlist + 8.0 * std::ldexp(lmax, -24) + std::ldexp(nl.rlist, -18);
     const int gt = grid_for(n, kBS);  // one thread per atom
-    const bool ldsout = nl.cap <= 16;  // rows collected in LDS (at most 32 KB per workgroup)
-    const size_t obytes = ldsout ? sizeof(int32_t) * 2 * kBS * nl.cap : 0;
+    // the workgroup size of the launch is the kernel's BS: rows collected in
+    // LDS (32 KB per workgroup) with 256 threads up to a capacity of 16 and
+    // 128 up to 32; beyond that stored as found, 256 threads
     const bool minimg = nl.small_axis;
-    auto kern = ldsout ? (minimg ? k_build<true, true> : k_build<true, false>)
-                       : (minimg ? k_build<false, true> : k_build<false, false>);
-    kern<<<gt, kBS, obytes, s>>>(n, nl.xs.as<float4>(), nl.cell_at.as<int32_t>(), conf, conf_of,
+    void (*kern)(int, const float4 *, const int32_t *, const ConfDesc *, const int32_t *,
+                 const int32_t *, float, int, int32_t *, int32_t *, int32_t *, const int32_t *,
+                 uint32_t *, int64_t *);
+    int bs;
+    size_t obytes;
+    if (nl.cap <= 16) {
+      kern = minimg ? k_build<true, true, kBS> : k_build<true, false, kBS>;
+      bs = kBS;
+      obytes = sizeof(int32_t) * 2 * kBS * nl.cap;
+    } else if (nl.cap <= 32) {
+      kern = minimg ? k_build<true, true, kBS / 2> : k_build<true, false, kBS / 2>;
+      bs = kBS / 2;
+      obytes = sizeof(int32_t) * 2 * (kBS / 2) * nl.cap;
+    } else {
+      kern = minimg ? k_build<false, true, kBS> : k_build<false, false, kBS>;
+      bs = kBS;
+      obytes = 0;
+    }
+    kern<<<grid_for(n, bs), bs, obytes, s>>>(n, nl.xs.as<float4>(), nl.cell_at.as<int32_t>(), conf, conf_of,
                                  cell_start, (float)(rl * rl), nl.cap, nl.count.as<int32_t>(),
                                  nl.list.as<int32_t>(), nl.plist.as<int32_t>(), cond, err,
                                  rebuild_counter);
