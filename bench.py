@@ -175,6 +175,14 @@ def main():
         us = model.autotune(x0, td, box, prec)
         tuned[prec] = us
 
+    mass = 28.0855
+    # (g/mol) (A/ps)^2 in eV: 1e4 amu m^2 s^-2 / e
+    mvv2e = 1.66053906660e-27 * 1e4 / 1.602176634e-19
+    etot = []
+
+    def kinetic(v):
+        return 0.5 * mass * mvv2e * float((v * v).sum().item())
+
     def run_md(precision, skin=skin, kernel_times=True):
         xd = x0.clone()
         v = torch.zeros_like(xd)
@@ -184,6 +192,12 @@ def main():
         trace = torch.empty(max(args.warmup, args.steps, 1), dtype=torch.float64, device=dev)
         model.md_run(xd, v, f, td, box, dt, args.warmup, skin, precision, trace=trace)
         torch.cuda.synchronize()
+        # total energy (potential after the last step + kinetic, whose
+        # velocities are those of the same instant) before and after the timed
+        # steps, read outside the timed region
+        e0 = None
+        if args.warmup > 0:
+            e0 = float(trace[args.warmup - 1].item()) + kinetic(v)
         r0 = model.rebuilds()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -193,6 +207,8 @@ def main():
         model.sync()
         reb = model.rebuilds() - r0
         tr = trace[:args.steps].cpu().numpy()
+        etot.append(None if e0 is None else
+                    (float(tr[-1]) + kinetic(v) - e0) / n)
         if not kernel_times:
             return el, reb, tr, None
         # force-kernel duration: HIP events on the library's stream around every
@@ -204,8 +220,10 @@ def main():
 
     print("bench: MD fp64", file=sys.stderr, flush=True)
     el64, reb64, tr64, f64us = run_md(FP64)
+    etot64 = etot[-1]
     print("bench: MD mixed", file=sys.stderr, flush=True)
     elmx, rebmx, trmx, fmxus = run_md(MIXED)
+    etotmx = etot[-1]
     elsp = None
     if not args.md_only:
         print("bench: MD single", file=sys.stderr, flush=True)
@@ -323,7 +341,9 @@ def main():
             "note": "all-FP32 mode (FP32 positions and accumulators), the paper's Opt-S"},
         "ablation": ablation,
         "mixed": {"rebuilds": rebmx, "schedule": sched["mixed"],
-                  "energy_drift_per_atom": float((trmx[-1] - trmx[0]) / n),
+                  "potential_energy_change_per_atom": float((trmx[-1] - trmx[0]) / n),
+                  "total_energy_drift_per_atom": etotmx,
+                  "fp64_total_energy_drift_per_atom": etot64,
                   "fp64_vs_mixed_energy_rel": float(abs(trmx[-1] - tr64[-1]) / abs(tr64[-1]))},
     }
 
