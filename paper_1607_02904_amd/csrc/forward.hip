@@ -502,8 +502,8 @@ __global__ __launch_bounds__(BS) void k_force(FwdArgs a, int A) {
         const double o0 = DUAL ? -out_of(fx, eb) : val(fx);
         const double o1 = DUAL ? -out_of(fy, eb) : val(fy);
         const double o2 = DUAL ? -out_of(fz, eb) : val(fz);
-        if (a.fown) {  // indexed by position in cell order
-          double *fo = a.fown + 3 * (first + at);
+        if (a.fown) {  // indexed by atom
+          double *fo = a.fown + 3 * (int64_t)i;
           fo[0] = o0;
           fo[1] = o1;
           fo[2] = o2;

@@ -681,8 +681,8 @@ again:
       }
       if (act && q == 0) {
         if (want_f) {
-          if (a.fown) {  // indexed by position in cell order
-            double *fo = a.fown + 3 * (first + at);
+          if (a.fown) {  // indexed by atom
+            double *fo = a.fown + 3 * (int64_t)ia;
             fo[0] = -sx;
             fo[1] = -sy;
             fo[2] = -sz;
@@ -703,7 +703,7 @@ again:
       if (lane >= a0 && lane < a1 && my_n == 0) {
         if (want_ea && !(flags & TERS_ACCUMULATE)) a.e_atom[my_a] = 0.0;
         if (want_f && a.fown) {
-          double *fo = a.fown + 3 * (first + lane);
+          double *fo = a.fown + 3 * (int64_t)my_a;
           fo[0] = 0.0;
           fo[1] = 0.0;
           fo[2] = 0.0;

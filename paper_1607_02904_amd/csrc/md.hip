@@ -97,16 +97,14 @@ DEV void reduce_energy(const double *__restrict__ partials, int nblocks, double 
 }
 
 // Owner gather of the forces (FP64 sums, in slot order, of the incoming
-// slots of the atom, [soff[t], soff[t + 1]) with t = pos[i], kept per atom in
-// srange_a), the second half
+// slots of the atom, [soff[i], soff[i + 1]) kept in srange_a[i]), the second half
 // kick of this step and, with do_next, the first half kick, drift and rebuild
 // test of the next one (the operations of k_vv_first, in the same order).
 // The forces are stored in F only on the last step (without do_next): the
 // steps in between use them in registers.  Thread per atom.  With a trace,
 // the first workgroups also sum the force kernel's energy partials.
 template <class S>
-__global__ void k_vv_gather_kick_drift(int n, const int32_t *__restrict__ pos,
-                                       const int2 *__restrict__ srange_a,
+__global__ void k_vv_gather_kick_drift(int n, const int2 *__restrict__ srange_a,
                                        const S *__restrict__ fslot,
                                        const double *__restrict__ fown, double *__restrict__ F,
                                        double *__restrict__ v, double *__restrict__ x,
@@ -121,9 +119,8 @@ __global__ void k_vv_gather_kick_drift(int n, const int32_t *__restrict__ pos,
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   bool over = false;
   if (i < n) {
-    const int t = pos[i];
     const int2 rg = srange_a[i];
-    double fv[3] = {fown[3 * t], fown[3 * t + 1], fown[3 * t + 2]};
+    double fv[3] = {fown[3 * i], fown[3 * i + 1], fown[3 * i + 2]};
     sum_slots(fslot, rg.x, rg.y, fv[0], fv[1], fv[2]);
     const double s = 0.5 * dt * kFtm2v / mass[species(type, i, nt)];
     const ConfDesc &c = conf[0];
@@ -163,12 +160,12 @@ void launch_vv_gather_kick_drift(const NList &nl, double *x, double *v, double *
   int32_t *count = (int32_t *)(energy + 8 + kRedBlocks);
   if (slot_f32)
     k_vv_gather_kick_drift<float><<<g, kBS, 0, s>>>(
-        n, nl.pos.as<int32_t>(), nl.srange_a.as<int2>(), (const float *)fslot, fown, F, v, x,
+        n, nl.srange_a.as<int2>(), (const float *)fslot, fown, F, v, x,
         type, mass, nt, dt, nl.xref.as<double>(), nl.conf.as<ConfDesc>(), half * half, flag, do_next,
         partials, nblocks, esum, count, energy, trace, step);
   else
     k_vv_gather_kick_drift<double><<<g, kBS, 0, s>>>(
-        n, nl.pos.as<int32_t>(), nl.srange_a.as<int2>(), (const double *)fslot, fown, F, v, x,
+        n, nl.srange_a.as<int2>(), (const double *)fslot, fown, F, v, x,
         type, mass, nt, dt, nl.xref.as<double>(), nl.conf.as<ConfDesc>(), half * half, flag, do_next,
         partials, nblocks, esum, count, energy, trace, step);
 }

@@ -495,16 +495,17 @@ __global__ __launch_bounds__(BS) void k_build(int n, const float4 *__restrict__ 
   }
 }
 
-// Incoming force slots, numbered along the cell order without row padding:
-// the atom at position t owns [soff[t], soff[t + 1]) with
-// soff[t] = sum of min(count, cap) over earlier positions; the pair
-// (soff[t], soff[t + 1]) is also kept as one 8-byte word per position (srange,
-// for the reverse map) and per atom (srange_a, for the gathers).  One pass
-// (the one-pass scan above) over positions 0 .. n, position n adding zero so
+// Incoming force slots, numbered along the atom order without row padding:
+// atom a owns [soff[a], soff[a + 1]) with soff[a] = sum of min(count, cap)
+// over the rows of earlier atoms, so that the gathers (a thread per atom) read
+// the slots of consecutive atoms from consecutive addresses; the pair
+// (soff[a], soff[a + 1]) is also kept as one 8-byte word per atom (srange_a,
+// for the gathers) and per cell-order position (srange, for the reverse map).
+// One pass (the one-pass scan above) over atoms 0 .. n, atom n adding zero so
 // that soff[n] is the total; a row longer than cap raises maxcount to its
 // length (only such rows touch it, so the register is not contended).
 __global__ __launch_bounds__(kBS) void k_slots(const int32_t *__restrict__ count, int cap, int n,
-                                               const int32_t *__restrict__ order,
+                                               const int32_t *__restrict__ pos,
                                                int32_t *__restrict__ soff, int2 *__restrict__ srange,
                                                int2 *__restrict__ srange_a,
                                                int32_t *__restrict__ maxcount, int32_t *ticket,
@@ -512,11 +513,13 @@ __global__ __launch_bounds__(kBS) void k_slots(const int32_t *__restrict__ count
   if (skip(cond)) return;
   const int tile = scan_ticket(ticket);
   const int64_t base = (int64_t)tile * kLbTile + threadIdx.x * kLbPer;
-  int v[kLbPer];
+  int v[kLbPer], p[kLbPer];
   int sum = 0, mx = 0;
 #pragma unroll
-  for (int k = 0; k < kLbPer; ++k) {  // position n closes the scan with a zero
-    const int c = (base + k < n) ? count[base + k] : 0;
+  for (int k = 0; k < kLbPer; ++k) p[k] = (base + k < n) ? pos[base + k] : 0;
+#pragma unroll
+  for (int k = 0; k < kLbPer; ++k) {  // atom n closes the scan with a zero
+    const int c = (base + k < n) ? count[p[k]] : 0;
     mx = max(mx, c);
     v[k] = min(c, cap);
     sum += v[k];
@@ -538,8 +541,8 @@ __global__ __launch_bounds__(kBS) void k_slots(const int32_t *__restrict__ count
     if (i <= n) soff[i] = off;
     if (i < n) {
       const int2 rg = make_int2(off, off + v[k]);
-      srange[i] = rg;
-      srange_a[order[i]] = rg;
+      srange_a[i] = rg;
+      srange[p[k]] = rg;
     }
     off += v[k];
   }
@@ -620,18 +623,16 @@ __global__ __launch_bounds__(kBS) void k_reverse(int n, int cap, const float4 *_
 }
 
 // owner gather: fixed-order sum of the forces that every neighbour's terms put
-// on atom a (its incoming slots [soff[t], soff[t + 1]) for t = pos[a], the
-// position of a in cell order; FP32 in the mixed path), plus a's own part, in
-// FP64.  Thread per atom: the outputs are written contiguously.
+// on atom a (its incoming slots [soff[a], soff[a + 1]); FP32 in the mixed
+// path), plus a's own part, in FP64.  Thread per atom: slots, own forces and
+// outputs of consecutive atoms are contiguous.
 template <class S>
-__global__ void k_gather(int n, const int32_t *__restrict__ pos,
-                         const int2 *__restrict__ srange_a, const S *__restrict__ fslot,
+__global__ void k_gather(int n, const int2 *__restrict__ srange_a, const S *__restrict__ fslot,
                          const double *__restrict__ fown, double *__restrict__ F, int accumulate) {
   int a = blockIdx.x * blockDim.x + threadIdx.x;
   if (a >= n) return;
-  const int t = pos[a];
   const int2 rg = srange_a[a];
-  double fx = fown[3 * t], fy = fown[3 * t + 1], fz = fown[3 * t + 2];
+  double fx = fown[3 * a], fy = fown[3 * a + 1], fz = fown[3 * a + 2];
   sum_slots(fslot, rg.x, rg.y, fx, fy, fz);
   if (accumulate) {
     F[3 * a] += fx;
@@ -762,7 +763,7 @@ void nlist_build(NList &nl, const double *x, const int32_t *type, int ntypes, co
                                  cell_start, (float)(rl * rl), nl.cap, nl.count.as<int32_t>(),
                                  nl.list.as<int32_t>(), nl.plist.as<int32_t>(), cond, err,
                                  rebuild_counter);
-    k_slots<<<nts, kBS, 0, s>>>(nl.count.as<int32_t>(), nl.cap, n, nl.order.as<int32_t>(),
+    k_slots<<<nts, kBS, 0, s>>>(nl.count.as<int32_t>(), nl.cap, n, nl.pos.as<int32_t>(),
                                 nl.soff.as<int32_t>(), nl.srange.as<int2>(),
                                 nl.srange_a.as<int2>(), nl.maxcount.as<int32_t>(), tickets + 1,
                                 lb + 1 + ntc, cond);
@@ -777,11 +778,11 @@ void launch_gather(const NList &nl, const void *fslot, bool slot_f32, const doub
   if (nl.n <= 0) return;
   if (slot_f32)
     k_gather<float><<<grid_for(nl.n, kBS), kBS, 0, s>>>(
-        nl.n, nl.pos.as<int32_t>(), nl.srange_a.as<int2>(), (const float *)fslot, fown, F,
+        nl.n, nl.srange_a.as<int2>(), (const float *)fslot, fown, F,
         accumulate);
   else
     k_gather<double><<<grid_for(nl.n, kBS), kBS, 0, s>>>(
-        nl.n, nl.pos.as<int32_t>(), nl.srange_a.as<int2>(), (const double *)fslot, fown, F,
+        nl.n, nl.srange_a.as<int2>(), (const double *)fslot, fown, F,
         accumulate);
 }
 

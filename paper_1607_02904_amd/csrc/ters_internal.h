@@ -98,9 +98,9 @@ struct NList {
   DevBuf pos;         // int32[n]: position of each atom in the cell order (inverse of order)
   DevBuf cell_at;     // int32[n]: cell of the atom at each cell-order position
   DevBuf plist;       // int32[n][cap]: positions of the row entries (list build and reverse map)
-  DevBuf srange;      // int2[n]: (soff[t], soff[t + 1])
-  DevBuf srange_a;    // int2[n]: the same by atom, (soff[pos[a]], soff[pos[a] + 1])
-  DevBuf soff;        // int32[n + 1]: first incoming force slot of the atom at each cell-order position
+  DevBuf srange;      // int2[n]: (soff[a], soff[a + 1]) of the atom a at each cell-order position
+  DevBuf srange_a;    // int2[n]: the same by atom, (soff[a], soff[a + 1])
+  DevBuf soff;        // int32[n + 1]: first incoming force slot of each atom (atom order)
 };
 
 // Forward / adjoint launch description.
@@ -136,8 +136,8 @@ struct FwdArgs {
   // terms rooted at the atom at position t exert on its list neighbour j
   // (slot s of row t) goes to j's incoming slot fslot[rev[t*cap + s]*3 ..]
   // (zero when the pair is outside the cutoff) and the force on the atom
-  // itself to fown[t*3 ..]; the incoming forces of the atom at position t then
-  // sit contiguously in slots [soff[t], soff[t + 1]) for the gather.
+  // itself to fown[a*3 ..] (a = order[t], the atom); the incoming forces of
+  // atom a then sit contiguously in slots [soff[a], soff[a + 1]) for the gather.
   // Slots hold the kernel's base type: FP64, or FP32 in the mixed path.
   void *fslot;
   double *fown;
@@ -163,7 +163,7 @@ void launch_fill_f64(double *p, double v, int64_t n, hipStream_t s);
 void nlist_build(NList &nl, const double *x, const int32_t *type, int ntypes, const int32_t *cond,
                  uint32_t *err, hipStream_t s, int64_t *rebuild_counter = nullptr);
 void nlist_check(const NList &nl, const double *x, int32_t *flag, hipStream_t s);
-// F[a] (+)= fown[t] + sum of the incoming slots fslot[soff[t] .. soff[t + 1]), t = pos[a]
+// F[a] (+)= fown[a] + sum of the incoming slots fslot[soff[a] .. soff[a + 1])
 // (the range read from srange_a)
 // (FP32 slots when slot_f32), summed in FP64 in slot order
 void launch_gather(const NList &nl, const void *fslot, bool slot_f32, const double *fown,
