@@ -216,10 +216,12 @@ void nl_setup(NList &nl, int nconf, const int32_t *natoms, const double *boxes, 
   nl.list.ensure(sizeof(int32_t) * nn * nl.cap);
   nl.order.ensure(sizeof(int32_t) * nn);
   nl.order_u.ensure(sizeof(int32_t) * nn);
-  nl.cell_of.ensure(sizeof(int32_t) * nn);
+  nl.cell_next.ensure(sizeof(int32_t) * nn);
+  nl.cell_head.ensure(sizeof(int32_t) * (cells + 1));
   nl.cell_count.ensure(sizeof(int32_t) * (cells + 1));
+  nl.cell_bucket.ensure(sizeof(int32_t) * kCellBucket * (cells + 1));
   nl.cell_start.ensure(sizeof(int32_t) * (cells + 1));
-  nl.lbstate.ensure(sizeof(uint64_t) * (1 + (cells + 1) / 1024 + 1 + (nn + 1) / 1024 + 1));
+  nl.lbstate.ensure(sizeof(uint64_t) * lb_words(cells + 1, nn));
   nl.xref.ensure(sizeof(double) * 3 * nn);
   nl.xs.ensure(sizeof(float) * 4 * (nn + 3));  // 3 padding entries for the build's fetches
   nl.pos.ensure(sizeof(int32_t) * nn);
@@ -303,8 +305,8 @@ const void *bits(double v) {
 // key is unchanged (device addresses alone are not enough: a caching
 // allocator hands the same addresses to new tensors).
 std::vector<const void *> graph_key(const ters_ctx *c, const NList &nl) {
-  return {nl.conf.p, nl.conf_of.p, nl.count.p, nl.list.p, nl.order.p, nl.cell_of.p,
-          nl.cell_count.p, nl.cell_start.p, nl.lbstate.p, nl.xref.p, nl.maxcount.p,
+  return {nl.conf.p, nl.conf_of.p, nl.count.p, nl.list.p, nl.order.p, nl.cell_next.p,
+          nl.cell_head.p, nl.cell_count.p, nl.cell_bucket.p, nl.cell_start.p, nl.lbstate.p, nl.xref.p, nl.maxcount.p,
           (const void *)(intptr_t)nl.n, (const void *)(intptr_t)nl.cap,
           (const void *)(intptr_t)nl.ncell, (const void *)(intptr_t)nl.nconf, bits(nl.rlist),
           bits(nl.skin), c->kp64.p, c->kp32.p, c->kp32s.p, c->filt2.p, (const void *)(intptr_t)c->ntypes,
@@ -401,8 +403,9 @@ constexpr size_t kN = TERS_STATIC_MAX_ATOMS;
 // bytes of every scratch buffer at the largest size (layout of carve_static)
 constexpr size_t kStaticBytes =
     al(sizeof(ConfDesc)) + 6 * al(4 * kN) + 2 * al(8 * kN) + al(4 * (kN + 1)) +
-    3 * al(4 * kN * kStaticCap) + 2 * al(4 * (kStaticCells + 1)) +
-    al(8 * (1 + (kStaticCells + 1) / 1024 + 1 + (kN + 1) / 1024 + 1)) + al(24 * kN) +
+    3 * al(4 * kN * kStaticCap) + 3 * al(4 * (kStaticCells + 1)) +
+    al(4 * kCellBucket * (kStaticCells + 1)) +
+    al(8 * lb_words(kStaticCells + 1, kN)) + al(24 * kN) +
     al(16 * (kN + 3)) + al(4) + al(64 * kN) + al(24 * kN * kStaticCap) + al(24 * kN);
 
 // One copy per GPU, held until the process ends.  In host code this name is
@@ -495,8 +498,9 @@ ters_status ters_destroy(ters_ctx *c) {
   if (c->capture_stream) hipStreamDestroy(c->capture_stream);
   DevBuf *bufs[] = {&c->kp64, &c->kp32, &c->kp32s, &c->filt2, &c->mass, &c->partials, &c->errw, &c->flag,
                     &c->rebuilds, &c->step, &c->escratch, &c->fslot, &c->fown, &c->nl.conf,
-                    &c->nl.conf_of, &c->nl.count, &c->nl.list, &c->nl.order, &c->nl.cell_of,
-                    &c->nl.cell_count, &c->nl.cell_start, &c->nl.lbstate, &c->nl.xref,
+                    &c->nl.conf_of, &c->nl.count, &c->nl.list, &c->nl.order, &c->nl.cell_next,
+                    &c->nl.cell_head, &c->nl.cell_count, &c->nl.cell_bucket,
+                    &c->nl.cell_start, &c->nl.lbstate, &c->nl.xref,
                     &c->nl.maxcount, &c->nl.rev, &c->nl.xs, &c->nl.pos, &c->nl.soff,
                     &c->nl.cell_at, &c->nl.plist, &c->nl.order_u, &c->nl.srange,
                     &c->nl.srange_a};
@@ -785,7 +789,7 @@ ters_status ters_compute_static(ters_ctx *c, int32_t n, const double *x, const i
     nl.count = cv.take(4 * N);
     nl.order = cv.take(4 * N);
     nl.order_u = cv.take(4 * N);
-    nl.cell_of = cv.take(4 * N);
+    nl.cell_next = cv.take(4 * N);
     nl.pos = cv.take(4 * N);
     nl.cell_at = cv.take(4 * N);
     nl.srange = cv.take(8 * N);
@@ -794,9 +798,11 @@ ters_status ters_compute_static(ters_ctx *c, int32_t n, const double *x, const i
     nl.list = cv.take(4 * N * kStaticCap);
     nl.rev = cv.take(4 * N * kStaticCap);
     nl.plist = cv.take(4 * N * kStaticCap);
+    nl.cell_head = cv.take(4 * (kStaticCells + 1));
     nl.cell_count = cv.take(4 * (kStaticCells + 1));
+    nl.cell_bucket = cv.take(4 * kCellBucket * (kStaticCells + 1));
     nl.cell_start = cv.take(4 * (kStaticCells + 1));
-    nl.lbstate = cv.take(8 * (1 + (kStaticCells + 1) / 1024 + 1 + (N + 1) / 1024 + 1));
+    nl.lbstate = cv.take(8 * lb_words(kStaticCells + 1, N));
     nl.xref = cv.take(24 * N);
     nl.xs = cv.take(16 * (N + 3));
     nl.maxcount = cv.take(4);
@@ -1450,8 +1456,9 @@ static void plan_release_device(ters_plan *p) {
   p->exec = nullptr;
   DevBuf *bufs[] = {&p->partials, &p->ebuf, &p->errw, &p->fslot, &p->fown, &p->items_f,
                     &p->qb_f, &p->items_a, &p->qb_a, &p->queue, &p->nl.conf,
-                    &p->nl.conf_of, &p->nl.count, &p->nl.list, &p->nl.order, &p->nl.cell_of,
-                    &p->nl.cell_count, &p->nl.cell_start, &p->nl.lbstate, &p->nl.xref,
+                    &p->nl.conf_of, &p->nl.count, &p->nl.list, &p->nl.order, &p->nl.cell_next,
+                    &p->nl.cell_head, &p->nl.cell_count, &p->nl.cell_bucket,
+                    &p->nl.cell_start, &p->nl.lbstate, &p->nl.xref,
                     &p->nl.maxcount, &p->nl.rev, &p->nl.xs, &p->nl.pos, &p->nl.soff,
                     &p->nl.cell_at, &p->nl.plist, &p->nl.order_u, &p->nl.srange,
                     &p->nl.srange_a};

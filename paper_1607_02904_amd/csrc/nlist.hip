@@ -2,14 +2,12 @@
 // and Section III skin list S_i), for one configuration or a batch of them.
 //
 //   bin     atom -> cell of side >= r_list in its own configuration's grid,
-//           count atoms per cell
-//   scan    exclusive prefix sum of the cell counts (cell_start), one pass
-//   place   counting-sort the atoms into cells (each atom's place in its cell
-//           was taken by the binning pass); keep the reference positions of
-//           the rebuild check
-//   sort    order atoms inside each cell by index (run-to-run determinism:
-//           each atom's rank among its cell's atoms) and keep a cell-ordered
-//           copy of the positions
+//           a place in its cell's bucket (or overflow list)
+//   cells   one pass over the cells: read each bucket, exclusive prefix sum of
+//           the cell sizes (cell_start, one-pass scan), each atom placed at
+//           its rank by index among its cell's atoms (run-to-run
+//           determinism), with the reference positions of the rebuild check
+//           and a cell-ordered copy of the positions
 //   build   for each atom scan the 27 surrounding cells (1 along an axis that
 //           holds fewer than 3 cells) and keep j != i with minimum-image
 //           r_ij <= r_list, in a padded row of `cap` entries
@@ -44,12 +42,17 @@ __global__ void k_fill_i32(int32_t *p, int32_t v, int64_t n, const int32_t *cond
     p[i] = v;
 }
 
-// zero the cell counts and the longest-row register in one launch
-__global__ void k_zero_cells(int32_t *cell_count, int64_t m, int32_t *maxcount, const int32_t *cond) {
+// empty every cell (zero counts, empty overflow lists) and zero the
+// longest-row register in one launch
+__global__ void k_clear_cells(int32_t *cell_count, int32_t *cell_head, int64_t m,
+                              int32_t *maxcount, const int32_t *cond) {
   if (skip(cond)) return;
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i == 0) *maxcount = 0;
-  for (; i < m; i += (int64_t)gridDim.x * blockDim.x) cell_count[i] = 0;
+  for (; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+    cell_count[i] = 0;
+    cell_head[i] = -1;
+  }
 }
 
 __global__ void k_fill_f64(double *p, double v, int64_t n) {
@@ -58,19 +61,21 @@ __global__ void k_fill_f64(double *p, double v, int64_t n) {
     p[i] = v;
 }
 
-DEV int bin_one(int i, const double *__restrict__ x, const ConfDesc *__restrict__ conf,
-                const int32_t *__restrict__ conf_of, int32_t *__restrict__ cell_of,
-                int32_t *__restrict__ cell_count, uint32_t *err);
+DEV int cell_of_atom(int i, const double *__restrict__ x, const ConfDesc *__restrict__ conf,
+                     const int32_t *__restrict__ conf_of, uint32_t *err);
 
-// records each atom's place among the atoms of its cell (in slot, in the
-// order the counts were taken; the sort makes the order canonical), also
-// checks every species against [0, ntypes) when type is given, and clears the
-// state of this build's one-pass scans (tickets, tile flags, the longest-row
-// register)
+// Each atom takes a place in its cell (a counter per cell): the first
+// kCellReg atoms of a cell go to the cell's bucket of kCellReg entries, any
+// further one is linked into the cell's overflow list (cell_head[c] -> atom ->
+// next[atom] -> ... -> -1).  The order the places are taken in does not
+// matter: the cell pass ranks each cell's atoms by index.  Also checks every
+// species against [0, ntypes) when type is given, and clears the state of
+// this build's one-pass scans (tickets, tile flags, the longest-row register).
+constexpr int kCellReg = 8;
 __global__ void k_bin(int n, const double *__restrict__ x, const ConfDesc *__restrict__ conf,
-                      const int32_t *__restrict__ conf_of, int32_t *__restrict__ cell_of,
-                      int32_t *__restrict__ cell_count, int32_t *__restrict__ slot,
-                      const int32_t *__restrict__ type,
+                      const int32_t *__restrict__ conf_of, int32_t *__restrict__ cell_count,
+                      int32_t *__restrict__ bucket, int32_t *__restrict__ cell_head,
+                      int32_t *__restrict__ next, const int32_t *__restrict__ type,
                       int ntypes, unsigned long long *__restrict__ lb, int64_t nlb,
                       int32_t *__restrict__ maxcount, const int32_t *cond, uint32_t *err) {
   if (skip(cond)) return;
@@ -79,14 +84,16 @@ __global__ void k_bin(int n, const double *__restrict__ x, const ConfDesc *__res
     lb[k] = 0ull;
   if (blockIdx.x == 0 && threadIdx.x == 0) *maxcount = 0;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    slot[i] = bin_one(i, x, conf, conf_of, cell_of, cell_count, err);
+    const int c = cell_of_atom(i, x, conf, conf_of, err);
+    const int slot = atomicAdd(&cell_count[c], 1);
+    if (slot < kCellReg) bucket[(int64_t)c * kCellReg + slot] = i;
+    else next[i] = atomicExch(&cell_head[c], i);
     if (type && (unsigned)type[i] >= (unsigned)ntypes) atomicOr(err, kErrBadType);
   }
 }
 
-DEV int bin_one(int i, const double *__restrict__ x, const ConfDesc *__restrict__ conf,
-                const int32_t *__restrict__ conf_of, int32_t *__restrict__ cell_of,
-                int32_t *__restrict__ cell_count, uint32_t *err) {
+DEV int cell_of_atom(int i, const double *__restrict__ x, const ConfDesc *__restrict__ conf,
+                     const int32_t *__restrict__ conf_of, uint32_t *err) {
   const ConfDesc &c = conf[conf_index(conf_of, i)];
   int q[3];
   bool finite = true;
@@ -101,9 +108,7 @@ DEV int bin_one(int i, const double *__restrict__ x, const ConfDesc *__restrict_
     q[a] = finite ? k : 0;
   }
   if (!finite) atomicOr(err, kErrNotFinite);
-  int cell = c.cell_off + (q[2] * c.nc[1] + q[1]) * c.nc[0] + q[0];
-  cell_of[i] = cell;
-  return atomicAdd(&cell_count[cell], 1);
+  return c.cell_off + (q[2] * c.nc[1] + q[1]) * c.nc[0] + q[0];
 }
 
 // ---- exclusive scans of int32 ----
@@ -154,8 +159,10 @@ DEV int wave_max_i(int v) {
 // 32 bits.  The flags and the ticket are cleared by the binning pass of the
 // same build.
 constexpr unsigned long long kLbSum = 1ull << 62, kLbPrefix = 2ull << 62;
-constexpr int kLbPer = 4;                 // values per thread
-constexpr int kLbTile = kBS * kLbPer;     // values per tile
+constexpr int kScanBS = 1024;              // workgroup size of the one-pass scans (few
+                                           // workgroups: one ticket each)
+constexpr int kLbPer = 4;                  // values per thread of the slot scan
+constexpr int kLbTile = kScanBS * kLbPer;  // values per tile of the slot scan
 
 DEV int scan_ticket(int32_t *ticket) {
   __shared__ int s_tile;
@@ -164,16 +171,22 @@ DEV int scan_ticket(int32_t *ticket) {
   return s_tile;
 }
 
-// The sum of the tiles before this one, found by the workgroup's first
-// wavefront: lane l reads the flag of tile top - l (64 earlier tiles per
-// read), the nearest inclusive prefix among them ends the walk, and the sums
-// of the tiles in between are added to it; while one of those tiles has not
-// published, the same flags are read again.  Every thread of the first
-// wavefront takes part; the result is valid in all of its lanes.
+// The sum of the tiles before this one, found by the whole workgroup: lane l
+// of wavefront w reads the flag of tile top - 64 w - l (BS earlier tiles per
+// round, their loads in flight together: a flag read goes out to memory, so
+// the walk costs one memory latency per round); the nearest inclusive prefix
+// among them ends the walk, and the sums of the tiles in between are added
+// to it.  While a tile in the walk has not published, the walk resumes at the
+// wavefront window that holds it.  Every thread of the workgroup calls it;
+// the result is valid in all of them.
+template <int BS>
 DEV int scan_lookback(unsigned long long *flags, int tile, int sum) {
-  const int lane = lane_id();
+  constexpr int kNW = BS / kWave;
+  __shared__ int s_first[kNW], s_sum[kNW], s_open[kNW];
+  const int lane = lane_id(), w = threadIdx.x / kWave;
   auto put = [&](unsigned long long v) {
-    if (lane == 0) __hip_atomic_store(&flags[tile], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (threadIdx.x == 0)
+      __hip_atomic_store(&flags[tile], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   };
   if (tile == 0) {
     put(kLbPrefix | (unsigned)sum);
@@ -182,139 +195,185 @@ DEV int scan_lookback(unsigned long long *flags, int tile, int sum) {
   put(kLbSum | (unsigned)sum);
   int excl = 0;
   for (int top = tile - 1;;) {
-    const int idx = top - lane;
+    const int idx = top - w * kWave - lane;
     // below tile 0: a zero prefix (never reached past tile 0's own prefix)
     const unsigned long long f =
         idx >= 0 ? __hip_atomic_load(&flags[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
                  : kLbPrefix;
     const unsigned long long st = f & (3ull << 62);
     const uint64_t pre = __ballot(st == kLbPrefix), none = __ballot(st == 0ull);
-    const int first = pre ? __builtin_ctzll(pre) : kWave;  // nearest prefix
+    const int first = pre ? __builtin_ctzll(pre) : kWave;  // nearest prefix of the window
     const uint64_t upto = first >= kWave - 1 ? ~0ull : (2ull << first) - 1ull;
-    if (none & upto) {  // a tile in the walk has not published yet (its workgroup is running)
-      __builtin_amdgcn_s_sleep(1);
-      continue;
-    }
     int v = lane <= first ? (int)(unsigned)(f & 0xffffffffull) : 0;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-    excl += v;
-    if (first < kWave) break;
-    top -= kWave;
+    if (lane == 0) {
+      s_first[w] = first;
+      s_sum[w] = v;
+      s_open[w] = (none & upto) != 0ull;  // a tile of the walk has not published yet
+    }
+    __syncthreads();
+    // windows in order of distance: add the complete ones up to the first
+    // prefix; stop at a window that is still open
+    int acc = 0, stop = kNW;
+    bool found = false;
+    for (int u = 0; u < kNW; ++u) {
+      if (s_open[u]) {
+        stop = u;
+        break;
+      }
+      acc += s_sum[u];
+      if (s_first[u] < kWave) {
+        found = true;
+        break;
+      }
+    }
+    __syncthreads();  // the next round rewrites the window results
+    excl += acc;
+    if (found) break;
+    top -= stop * kWave;
+    if (stop < kNW) __builtin_amdgcn_s_sleep(1);  // resume at the open window
   }
   put(kLbPrefix | (unsigned)(excl + sum));
   return excl;
 }
 
-// cell_start = exclusive scan of the cell counts, which are cleared on the
-// way (they become the placement cursors)
-__global__ __launch_bounds__(kBS) void k_scan_cells(int32_t *__restrict__ counts,
-                                                    int32_t *__restrict__ out, int64_t m,
-                                                    int32_t *ticket, unsigned long long *flags,
-                                                    const int32_t *cond) {
+// The atom placed at position t of the cell order: its index (order, and pos
+// for the inverse), the reference position of the rebuild test (xref), and
+// the copy of its position that the build reads (xs: FP32, wrapped into the
+// configuration's box, with the atom index in the fourth word; the build's
+// distance test allows for that rounding) together with the cell coordinates
+// of the position (cell_at, packed by pack_cell).
+DEV int pack_cell(int64_t c, const ConfDesc &cf) {  // x | y << 11 | z << 22 in the grid
+  const int lc = (int)(c - cf.cell_off), nx = cf.nc[0], ny = cf.nc[1];
+  return (lc % nx) | ((lc / nx) % ny) << 11 | (lc / (nx * ny)) << 22;
+}
+DEV void place_atom(int i, int t, int packed, int32_t *__restrict__ order,
+                    int32_t *__restrict__ pos, const double *__restrict__ x,
+                    const ConfDesc *__restrict__ conf, const int32_t *__restrict__ conf_of,
+                    float4 *__restrict__ xs, int32_t *__restrict__ cell_at,
+                    double *__restrict__ xref) {
+  order[t] = i;
+  pos[i] = t;
+  const ConfDesc &cf = conf[conf_index(conf_of, i)];
+  float w[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double v = x[3 * i + a];
+    xref[3 * i + a] = v;
+    w[a] = (float)(v - cf.box[a] * floor(v * cf.inv_box[a]));
+  }
+  xs[t] = make_float4(w[0], w[1], w[2], __int_as_float(i));
+  cell_at[t] = packed;
+}
+
+// Counting sort of the atoms into cells, canonical inside each cell, in one
+// pass over the cells: a thread per cell, workgroups of kScanBS threads taking
+// tiles of kScanBS cells in ticket order.  Each thread reads its cell's count
+// and bucket (two 16-byte loads) and empties the cell for the next build; the
+// counts are scanned (block scan, then the one-pass look-back over the
+// earlier tiles) into cell_start (m = cells + 1 values, the last one the
+// total); each atom of the cell goes to position start + (number of the
+// cell's atoms with a smaller index), so the order depends only on which
+// atoms share a cell.  Cells of up to kCellReg atoms are ranked in registers
+// by their thread and staged in LDS by position within the tile, and the
+// workgroup then places them a thread per position (every lane busy, however
+// unevenly the atoms fill the cells); larger cells are copied to order_u
+// (bucket, then overflow list) and ranked by the whole workgroup, a thread
+// per atom, so that a crowded cell costs its size per atom, not its square on
+// one thread.
+constexpr int kStage = 4096;  // positions staged per round
+__global__ __launch_bounds__(kScanBS) void k_cells(
+    int64_t m, int32_t *__restrict__ cell_count, const int32_t *__restrict__ bucket,
+    int32_t *__restrict__ cell_head, const int32_t *__restrict__ next,
+    int32_t *__restrict__ cell_start, int32_t *__restrict__ order_u, int32_t *__restrict__ order,
+    int32_t *__restrict__ pos, const double *__restrict__ x, const ConfDesc *__restrict__ conf,
+    const int32_t *__restrict__ conf_of, float4 *__restrict__ xs, int32_t *__restrict__ cell_at,
+    double *__restrict__ xref, int32_t *ticket, unsigned long long *flags, const int32_t *cond) {
   if (skip(cond)) return;
-  const int tile = scan_ticket(ticket);
-  const int64_t base = (int64_t)tile * kLbTile + threadIdx.x * kLbPer;
-  int v[kLbPer];
-  int sum = 0;
-#pragma unroll
-  for (int k = 0; k < kLbPer; ++k) {
-    v[k] = (base + k < m) ? counts[base + k] : 0;
-    sum += v[k];
-  }
-  int tot;
-  int off = block_excl_scan(sum, &tot);
-  __shared__ int s_excl;
-  if (threadIdx.x < kWave) {
-    const int e = scan_lookback(flags, tile, tot);
-    if (threadIdx.x == 0) s_excl = e;
-  }
-  __syncthreads();
-  off += s_excl;
-#pragma unroll
-  for (int k = 0; k < kLbPer; ++k) {
-    if (base + k < m) {
-      out[base + k] = off;
-      counts[base + k] = 0;
+  constexpr int BS = kScanBS;
+  __shared__ int s_nq;                        // crowded cells of the tile
+  __shared__ int s_q[BS];                     // their threads
+  __shared__ int s_b[BS], s_k[BS];            // first position and size, by thread
+  __shared__ int s_pack[BS];                  // packed cell coordinates, by thread
+  __shared__ int s_at[kStage];                // staged atoms by position in the tile
+  __shared__ unsigned short s_cl[kStage];     // and the thread of their cell
+  if (threadIdx.x == 0) s_nq = 0;
+  const int tile = scan_ticket(ticket);  // (its barrier also publishes s_nq)
+  const int64_t c = (int64_t)tile * BS + threadIdx.x;
+  const int k = c < m - 1 ? cell_count[c] : 0;
+  int a[kCellReg], r[kCellReg];
+  {
+    static_assert(kCellReg == 8, "two 16-byte loads per bucket");
+    int4 q0 = make_int4(-1, -1, -1, -1), q1 = q0;
+    if (k > 0) {
+      const int4 *bk = reinterpret_cast<const int4 *>(bucket + c * kCellReg);
+      q0 = bk[0];
+      if (k > 4) q1 = bk[1];
     }
-    off += v[k];
-  }
-}
-
-// whole exclusive scan in one workgroup (used when the cell count is moderate):
-// contiguous chunks per thread, one block scan of the chunk sums; the counts
-// are cleared on the way (they become the placement cursors)
-constexpr int kScan1BS = 1024;
-constexpr int64_t kScan1Max = 8192;  // above this the two-launch parallel scan wins
-__global__ __launch_bounds__(kScan1BS) void k_scan_single(int32_t *__restrict__ counts,
-                                                          int32_t *__restrict__ out, int64_t m,
-                                                          const int32_t *cond) {
-  if (skip(cond)) return;
-  const int64_t per = (m + kScan1BS - 1) / kScan1BS;
-  const int64_t b = threadIdx.x * per;
-  const int64_t e = b + per < m ? b + per : m;
-  int s = 0;
-#pragma unroll 8
-  for (int64_t i = b; i < e; ++i) s += counts[i];
-  int tot;
-  int off = block_excl_scan_t<kScan1BS>(s, &tot);
-  for (int64_t i = b; i < e; ++i) {
-    int c = counts[i];
-    out[i] = off;
-    off += c;
-    counts[i] = 0;
-  }
-}
-
-__global__ void k_place(int n, const double *__restrict__ x, const int32_t *__restrict__ cell_of,
-                        const int32_t *__restrict__ cell_start, const int32_t *__restrict__ slot,
-                        int32_t *__restrict__ order_u, double *__restrict__ xref,
-                        const int32_t *cond) {
-  if (skip(cond)) return;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    order_u[cell_start[cell_of[i]] + slot[i]] = i;
-    xref[3 * i + 0] = x[3 * i + 0];
-    xref[3 * i + 1] = x[3 * i + 1];
-    xref[3 * i + 2] = x[3 * i + 2];
-  }
-}
-
-// order atoms inside each cell by index: the atom placed at position p of its
-// cell's range [b, e) goes to b + (number of the cell's atoms with a smaller
-// index), one thread per atom, so that a crowded cell costs its size per
-// atom, not its square on one thread.  Records each atom's position in the
-// cell order (pos, the inverse of order) and copies the positions in that
-// order for the build (xs: FP32, wrapped into the configuration's box, with
-// the atom index in the fourth word; the build's distance test allows for
-// that rounding) together with the cell coordinates of each position
-// (cell_at: x | y << 11 | z << 22 within the configuration's grid).
-__global__ void k_sort_cells(int n, const int32_t *__restrict__ cell_start,
-                             const int32_t *__restrict__ cell_of,
-                             const int32_t *__restrict__ order_u, int32_t *__restrict__ order,
-                             const double *__restrict__ x, const ConfDesc *__restrict__ conf,
-                             const int32_t *__restrict__ conf_of, float4 *__restrict__ xs,
-                             int32_t *__restrict__ cell_at, int32_t *__restrict__ pos,
-                             const int32_t *cond) {
-  if (skip(cond)) return;
-  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gridDim.x * blockDim.x) {
-    const int i = order_u[p];
-    const int c = cell_of[i];
-    const int b = cell_start[c], e = cell_start[c + 1];
-    int rank = 0;
-    for (int q = b; q < e; ++q) rank += order_u[q] < i;
-    const int t = b + rank;
-    order[t] = i;
-    pos[i] = t;
-    const ConfDesc &cf = conf[conf_index(conf_of, i)];
-    float w[3];
+    const int raw[kCellReg] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const double v = x[3 * i + a];
-      w[a] = (float)(v - cf.box[a] * floor(v * cf.inv_box[a]));
+    for (int u = 0; u < kCellReg; ++u) a[u] = u < k ? raw[u] : -1;
+  }
+#pragma unroll
+  for (int u = 0; u < kCellReg; ++u) {
+    r[u] = 0;  // empty registers hold -1, above every index as unsigned
+#pragma unroll
+    for (int v = 0; v < kCellReg; ++v) r[u] += (unsigned)a[v] < (unsigned)a[u];
+  }
+  if (k > 0) s_pack[threadIdx.x] = pack_cell(c, conf[conf_index(conf_of, a[0])]);
+  int tot;
+  const int off = block_excl_scan_t<BS>(k, &tot);
+  const int base = scan_lookback<BS>(flags, tile, tot);  // first position of the tile
+  const int b = base + off;
+  if (c < m) cell_start[c] = b;
+  if (c < m - 1) cell_count[c] = 0;
+  const bool crowded = k > kCellReg;
+  if (crowded) {
+#pragma unroll
+    for (int u = 0; u < kCellReg; ++u) order_u[b + u] = a[u];
+    int j = b + kCellReg;
+    for (int q = cell_head[c]; q >= 0; q = next[q]) order_u[j++] = q;
+    cell_head[c] = -1;
+    s_b[threadIdx.x] = b;
+    s_k[threadIdx.x] = k;
+    s_q[atomicAdd(&s_nq, 1)] = threadIdx.x;
+  }
+  for (int lo = 0; lo < tot; lo += kStage) {  // (tot is the same in every thread)
+    if (crowded) {  // its positions are left to the workgroup pass below
+      for (int rel = max(off - lo, 0); rel < min(off + k - lo, kStage); ++rel) s_at[rel] = -1;
+    } else {
+#pragma unroll
+      for (int u = 0; u < kCellReg; ++u) {
+        const int rel = off + r[u] - lo;
+        if (u < k && rel >= 0 && rel < kStage) {
+          s_at[rel] = a[u];
+          s_cl[rel] = (unsigned short)threadIdx.x;
+        }
+      }
     }
-    xs[t] = make_float4(w[0], w[1], w[2], __int_as_float(i));
-    const int lc = c - cf.cell_off, nx = cf.nc[0], ny = cf.nc[1];
-    cell_at[t] = (lc % nx) | ((lc / nx) % ny) << 11 | (lc / (nx * ny)) << 22;
+    __syncthreads();
+    const int cnt = min(kStage, tot - lo);
+    for (int j = threadIdx.x; j < cnt; j += BS) {
+      const int i = s_at[j];
+      if (i >= 0)
+        place_atom(i, base + lo + j, s_pack[s_cl[j]], order, pos, x, conf, conf_of, xs, cell_at,
+                   xref);
+    }
+    __syncthreads();
+  }
+  // crowded cells (a tile with one has atoms, so the rounds above ordered
+  // these reads after the copies to order_u and after every s_nq update)
+  const int nq = s_nq;
+  for (int e = 0; e < nq; ++e) {
+    const int tq = s_q[e];
+    const int bq = s_b[tq], kq = s_k[tq], pk = s_pack[tq];
+    for (int idx = threadIdx.x; idx < kq; idx += BS) {
+      const int i = order_u[bq + idx];
+      int rk = 0;
+      for (int q = 0; q < kq; ++q) rk += order_u[bq + q] < i;
+      place_atom(i, bq + rk, pk, order, pos, x, conf, conf_of, xs, cell_at, xref);
+    }
   }
 }
 
@@ -504,7 +563,7 @@ __global__ __launch_bounds__(BS) void k_build(int n, const float4 *__restrict__ 
 // One pass (the one-pass scan above) over atoms 0 .. n, atom n adding zero so
 // that soff[n] is the total; a row longer than cap raises maxcount to its
 // length (only such rows touch it, so the register is not contended).
-__global__ __launch_bounds__(kBS) void k_slots(const int32_t *__restrict__ count, int cap, int n,
+__global__ __launch_bounds__(kScanBS) void k_slots(const int32_t *__restrict__ count, int cap, int n,
                                                const int32_t *__restrict__ pos,
                                                int32_t *__restrict__ soff, int2 *__restrict__ srange,
                                                int2 *__restrict__ srange_a,
@@ -525,16 +584,10 @@ __global__ __launch_bounds__(kBS) void k_slots(const int32_t *__restrict__ count
     sum += v[k];
   }
   int tot;
-  int off = block_excl_scan(sum, &tot);
-  __shared__ int s_excl;
-  if (threadIdx.x < kWave) {
-    const int e = scan_lookback(flags, tile, tot);
-    if (threadIdx.x == 0) s_excl = e;
-  }
+  int off = block_excl_scan_t<kScanBS>(sum, &tot);
+  off += scan_lookback<kScanBS>(flags, tile, tot);
   mx = wave_max_i(mx);
   if (lane_id() == 0 && mx > cap) atomicMax(maxcount, mx);  // only rows that overflowed
-  __syncthreads();
-  off += s_excl;
 #pragma unroll
   for (int k = 0; k < kLbPer; ++k) {
     const int64_t i = base + k;
@@ -690,15 +743,18 @@ void nlist_build(NList &nl, const double *x, const int32_t *type, int ntypes, co
   const int n = nl.n;
   const int64_t ncell = nl.ncell;
   int32_t *cell_count = nl.cell_count.as<int32_t>();
+  int32_t *cell_head = nl.cell_head.as<int32_t>();
+  int32_t *bucket = nl.cell_bucket.as<int32_t>();
   int32_t *cell_start = nl.cell_start.as<int32_t>();
   const ConfDesc *conf = nl.conf.as<ConfDesc>();
   const int32_t *conf_of = nl.nconf > 1 ? nl.conf_of.as<int32_t>() : nullptr;
   const int64_t m = ncell + 1;
-  // Cell counts are zero between builds (the sort step clears them); a build
-  // started from the host clears them once more, since the buffer may be new.
+  // Cells are empty between builds (the cell pass empties them); a build
+  // started from the host empties them once more, since the buffers may be new.
   if (cond == nullptr) {
     int g = grid_for(m, kBS);
-    k_zero_cells<<<g > 4096 ? 4096 : g, kBS, 0, s>>>(cell_count, m, nl.maxcount.as<int32_t>(), cond);
+    k_clear_cells<<<g > 4096 ? 4096 : g, kBS, 0, s>>>(cell_count, cell_head, m,
+                                                       nl.maxcount.as<int32_t>(), cond);
   }
   // grids are capped (grid-stride loops): a skipped rebuild then costs one
   // short dispatch per kernel
@@ -708,28 +764,22 @@ void nlist_build(NList &nl, const double *x, const int32_t *type, int ntypes, co
     return g < 1 ? 1 : (g > gcap ? gcap : g);
   };
   if (n <= 0) return;  // nothing reads the cells of an empty set
-  // one-pass scan state: two tickets, then the tile flags of the cell scan and
+  // one-pass scan state: two tickets, then the tile flags of the cell pass and
   // of the slot scan
-  const int ntc = grid_for(m, kLbTile), nts = grid_for((int64_t)n + 1, kLbTile);
+  static_assert(kCellTile == kScanBS && kSlotTile == kLbTile, "tile sizes of the one-pass scans");
+  const int ntc = grid_for(m, kCellTile), nts = grid_for((int64_t)n + 1, kSlotTile);
   unsigned long long *lb = nl.lbstate.as<unsigned long long>();
   int32_t *tickets = reinterpret_cast<int32_t *>(lb);
-  // the place of each atom in its cell is kept in pos until the sort writes
-  // the atoms' final positions there
-  k_bin<<<grid(n), kBS, 0, s>>>(n, x, conf, conf_of, nl.cell_of.as<int32_t>(), cell_count,
-                                nl.pos.as<int32_t>(), type, ntypes, lb, 1 + ntc + nts,
+  static_assert(kCellReg == kCellBucket, "bucket size");
+  k_bin<<<grid(n), kBS, 0, s>>>(n, x, conf, conf_of, cell_count, bucket, cell_head,
+                                nl.cell_next.as<int32_t>(), type, ntypes, lb, lb_words(m, n),
                                 nl.maxcount.as<int32_t>(), cond, err);
-  if (m <= kScan1Max)
-    k_scan_single<<<1, kScan1BS, 0, s>>>(cell_count, cell_start, m, cond);
-  else
-    k_scan_cells<<<ntc, kBS, 0, s>>>(cell_count, cell_start, m, tickets, lb + 1, cond);
+  k_cells<<<ntc, kScanBS, 0, s>>>(m, cell_count, bucket, cell_head, nl.cell_next.as<int32_t>(), cell_start,
+                              nl.order_u.as<int32_t>(), nl.order.as<int32_t>(),
+                              nl.pos.as<int32_t>(), x, conf, conf_of, nl.xs.as<float4>(),
+                              nl.cell_at.as<int32_t>(), nl.xref.as<double>(), tickets, lb + 1,
+                              cond);
   {
-    k_place<<<grid(n), kBS, 0, s>>>(n, x, nl.cell_of.as<int32_t>(), cell_start,
-                                    nl.pos.as<int32_t>(), nl.order_u.as<int32_t>(),
-                                    nl.xref.as<double>(), cond);
-    k_sort_cells<<<grid(n), kBS, 0, s>>>(n, cell_start, nl.cell_of.as<int32_t>(),
-                                         nl.order_u.as<int32_t>(), nl.order.as<int32_t>(), x, conf,
-                                         conf_of, nl.xs.as<float4>(), nl.cell_at.as<int32_t>(),
-                                         nl.pos.as<int32_t>(), cond);
     // FP32 distance test on positions wrapped into the box: a coordinate is
     // rounded by at most 2^-24 of the longest side, a squared distance by a
     // few units in the last place; the radius grows by a bound of both, so no
@@ -763,7 +813,7 @@ void nlist_build(NList &nl, const double *x, const int32_t *type, int ntypes, co
                                  cell_start, (float)(rl * rl), nl.cap, nl.count.as<int32_t>(),
                                  nl.list.as<int32_t>(), nl.plist.as<int32_t>(), cond, err,
                                  rebuild_counter);
-    k_slots<<<nts, kBS, 0, s>>>(nl.count.as<int32_t>(), nl.cap, n, nl.pos.as<int32_t>(),
+    k_slots<<<nts, kScanBS, 0, s>>>(nl.count.as<int32_t>(), nl.cap, n, nl.pos.as<int32_t>(),
                                 nl.soff.as<int32_t>(), nl.srange.as<int2>(),
                                 nl.srange_a.as<int2>(), nl.maxcount.as<int32_t>(), tickets + 1,
                                 lb + 1 + ntc, cond);

@@ -70,6 +70,16 @@ enum : uint32_t {
   kErrBadType = 16u
 };
 
+// One-pass scans of the list build: the cell pass takes tiles of kCellTile
+// cells, the slot scan tiles of kSlotTile atoms.  lb_words(m, n): 8-byte
+// words of scan state for m = cells + 1 and n atoms (one word of two ticket
+// counters, then one flag per tile of each scan).
+constexpr int64_t kCellTile = 1024, kSlotTile = 4096;
+constexpr int kCellBucket = 8;  // atoms per cell held in the cell's bucket
+constexpr int64_t lb_words(int64_t m, int64_t n) {
+  return 1 + (m + kCellTile - 1) / kCellTile + (n + 1 + kSlotTile - 1) / kSlotTile;
+}
+
 // Neighbour list state.  One list per configuration set (a single system is
 // a set of one).
 struct NList {
@@ -85,11 +95,13 @@ struct NList {
   DevBuf count;       // int32[n]: row lengths, by cell-order position
   DevBuf list;        // int32[n][cap]: row t = neighbours (atoms) of the atom at position t
   DevBuf order;       // int32[n]: atoms in cell order
-  DevBuf order_u;     // int32[n]: the same before the order inside each cell is fixed
-  DevBuf cell_of;     // int32[n]
-  DevBuf cell_count;  // int32[ncell + 1]
+  DevBuf order_u;     // int32[n]: the atoms of crowded cells before their order is fixed
+  DevBuf cell_count;  // int32[ncell + 1]: atoms per cell during a build, zero between builds
+  DevBuf cell_bucket; // int32[ncell][kCellBucket]: the first atoms of each cell
+  DevBuf cell_next;   // int32[n]: the next atom of the atom's overflow list, or -1
+  DevBuf cell_head;   // int32[ncell + 1]: first atom of each overflow list, -1 if empty
   DevBuf cell_start;  // int32[ncell + 1]
-  DevBuf lbstate;     // uint64[1 + tiles of the cell scan + tiles of the slot scan]: one-pass scan state
+  DevBuf lbstate;     // uint64[lb_words(ncell + 1, n)]: one-pass scan state
   DevBuf xref;        // double[n][3]
   DevBuf maxcount;    // int32[1]: longest row of the last build if longer than cap, else 0
   DevBuf rev;         // int32[n][cap]: incoming force slot at j of row entry (t, j)
