@@ -15,7 +15,9 @@ namespace {
 constexpr double kFtm2v = 9648.533215665328;
 constexpr int kBS = 256;
 
-// v += dt/2 F/m; x += dt v; F = 0 when the force kernel accumulates into it
+// v += dt/2 F/m; x += dt v (each a fused multiply-add, in every MD kernel,
+// so that the rounding does not depend on the compiler's contraction
+// choices); F = 0 when the force kernel accumulates into it
 // (atomic scatter); flag = 1 if any atom moved more than skin/2 since the last
 // list build (FP64, minimum image)
 __global__ void k_vv_first(int n, double *__restrict__ x, double *__restrict__ v,
@@ -31,8 +33,8 @@ __global__ void k_vv_first(int n, double *__restrict__ x, double *__restrict__ v
     double r2 = 0.0;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      double vv = v[3 * i + a] + s * f[3 * i + a];
-      double xx = x[3 * i + a] + dt * vv;
+      double vv = fma(s, f[3 * i + a], v[3 * i + a]);
+      double xx = fma(dt, vv, x[3 * i + a]);
       v[3 * i + a] = vv;
       x[3 * i + a] = xx;
       if (zero_f) f[3 * i + a] = 0.0;
@@ -53,9 +55,9 @@ __global__ void k_vv_second(int n, double *__restrict__ v, const double *__restr
   if (i == 0 && flag) *flag = 0;
   if (i >= n) return;
   const double s = 0.5 * dt * kFtm2v / mass[species(type, i, nt)];
-  v[3 * i + 0] += s * f[3 * i + 0];
-  v[3 * i + 1] += s * f[3 * i + 1];
-  v[3 * i + 2] += s * f[3 * i + 2];
+  v[3 * i + 0] = fma(s, f[3 * i + 0], v[3 * i + 0]);
+  v[3 * i + 1] = fma(s, f[3 * i + 1], v[3 * i + 1]);
+  v[3 * i + 2] = fma(s, f[3 * i + 2], v[3 * i + 2]);
 }
 
 
@@ -98,12 +100,15 @@ DEV void reduce_energy(const double *__restrict__ partials, int nblocks, double 
 
 // Owner gather of the forces (FP64 sums, in slot order, of the incoming
 // slots of the atom, [soff[i], soff[i + 1]) kept in srange_a[i]), the second half
-// kick of this step and, with do_next, the first half kick, drift and rebuild
+// kick of this step and, with NEXT, the first half kick, drift and rebuild
 // test of the next one (the operations of k_vv_first, in the same order).
-// The forces are stored in F only on the last step (without do_next): the
-// steps in between use them in registers.  Thread per atom.  With a trace,
-// the first workgroups also sum the force kernel's energy partials.
-template <class S>
+// The forces are stored in F only on the last step (without NEXT): the
+// steps in between use them in registers.  Thread per atom: every load of
+// the atom is issued before the arithmetic and its stores go out back to
+// back, so that each thread waits for memory once and writes whole lines at
+// a time.  With a trace, the first workgroups also sum the force kernel's
+// energy partials.
+template <class S, bool NEXT>
 __global__ void k_vv_gather_kick_drift(int n, const int2 *__restrict__ srange_a,
                                        const S *__restrict__ fslot,
                                        const double *__restrict__ fown, double *__restrict__ F,
@@ -112,34 +117,49 @@ __global__ void k_vv_gather_kick_drift(int n, const int2 *__restrict__ srange_a,
                                        const double *__restrict__ mass, int nt, double dt,
                                        const double *__restrict__ xref,
                                        const ConfDesc *__restrict__ conf, double lim2,
-                                       int32_t *flag, int do_next,
-                                       const double *__restrict__ partials, int nblocks,
-                                       double *esum, int32_t *count, double *energy,
+                                       int32_t *flag, const double *__restrict__ partials,
+                                       int nblocks, double *esum, int32_t *count, double *energy,
                                        double *trace, int32_t *step) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   bool over = false;
   if (i < n) {
     const int2 rg = srange_a[i];
-    double fv[3] = {fown[3 * i], fown[3 * i + 1], fown[3 * i + 2]};
-    sum_slots(fslot, rg.x, rg.y, fv[0], fv[1], fv[2]);
+    double fv[3], vv[3], xx[3], xr[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      fv[a] = fown[3 * i + a];
+      vv[a] = v[3 * i + a];
+      if (NEXT) {
+        xx[a] = x[3 * i + a];
+        xr[a] = xref[3 * i + a];
+      }
+    }
     const double s = 0.5 * dt * kFtm2v / mass[species(type, i, nt)];
+    sum_slots(fslot, rg.x, rg.y, fv[0], fv[1], fv[2]);
     const ConfDesc &c = conf[0];
     double r2 = 0.0;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      if (!do_next) F[3 * i + a] = fv[a];
-      double vv = v[3 * i + a] + s * fv[a];
-      if (do_next) {
-        vv = vv + s * fv[a];
-        const double xx = x[3 * i + a] + dt * vv;
-        x[3 * i + a] = xx;
-        double d = xx - xref[3 * i + a];
+      vv[a] = fma(s, fv[a], vv[a]);
+      if (NEXT) {
+        vv[a] = fma(s, fv[a], vv[a]);
+        xx[a] = fma(dt, vv[a], xx[a]);
+        double d = xx[a] - xr[a];
         d -= c.box[a] * rint(d * c.inv_box[a]);
         r2 += d * d;
       }
-      v[3 * i + a] = vv;
     }
-    over = do_next && !(r2 <= lim2);  // NaN counts as moved
+    if (!NEXT) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) F[3 * i + a] = fv[a];
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) v[3 * i + a] = vv[a];
+    if (NEXT) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) x[3 * i + a] = xx[a];
+    }
+    over = NEXT && !(r2 <= lim2);  // NaN counts as moved
   }
   if (__ballot(over) != 0ull && lane_id() == 0) *flag = 1;
   if (blockIdx.x < kRedBlocks && trace)
@@ -158,16 +178,20 @@ void launch_vv_gather_kick_drift(const NList &nl, double *x, double *v, double *
   const double half = 0.5 * nl.skin;
   double *esum = energy + 8;  // the energy scratch holds 8 + kRedBlocks doubles
   int32_t *count = (int32_t *)(energy + 8 + kRedBlocks);
-  if (slot_f32)
-    k_vv_gather_kick_drift<float><<<g, kBS, 0, s>>>(
-        n, nl.srange_a.as<int2>(), (const float *)fslot, fown, F, v, x,
-        type, mass, nt, dt, nl.xref.as<double>(), nl.conf.as<ConfDesc>(), half * half, flag, do_next,
-        partials, nblocks, esum, count, energy, trace, step);
-  else
-    k_vv_gather_kick_drift<double><<<g, kBS, 0, s>>>(
-        n, nl.srange_a.as<int2>(), (const double *)fslot, fown, F, v, x,
-        type, mass, nt, dt, nl.xref.as<double>(), nl.conf.as<ConfDesc>(), half * half, flag, do_next,
-        partials, nblocks, esum, count, energy, trace, step);
+  auto launch = [&](auto kern, auto slots) {
+    kern<<<g, kBS, 0, s>>>(n, nl.srange_a.as<int2>(), slots, fown, F, v, x, type, mass, nt, dt,
+                           nl.xref.as<double>(), nl.conf.as<ConfDesc>(), half * half, flag,
+                           partials, nblocks, esum, count, energy, trace, step);
+  };
+  if (slot_f32) {
+    const float *fs = (const float *)fslot;
+    if (do_next) launch(k_vv_gather_kick_drift<float, true>, fs);
+    else launch(k_vv_gather_kick_drift<float, false>, fs);
+  } else {
+    const double *fs = (const double *)fslot;
+    if (do_next) launch(k_vv_gather_kick_drift<double, true>, fs);
+    else launch(k_vv_gather_kick_drift<double, false>, fs);
+  }
 }
 
 void launch_vv_first(int n, double *x, double *v, double *f, const int32_t *type,
