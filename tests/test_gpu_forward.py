@@ -498,6 +498,44 @@ def test_list_build_cell_grids(orc, si_model, shape, precision):
     _check(gpu_eval(si_model, x, t, box, precision, skin=0.5), ref, precision)
 
 
+@pytest.mark.parametrize("skin", [2.0, 3.0])
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
+def test_list_build_crowded_cells(orc, skin, precision):
+    """Large cells (a wide skin) on 8,000 Si atoms, each case on a model of
+    its own (list capacity from 16): with skin 2.0 A about eight atoms per
+    cell, so cells on both sides of the binning pass's eight-atom bucket, and
+    capacity 32; with skin 3.0 A about eleven per cell, most of them past the
+    bucket, and capacity 64.  Either way one tile of the cell pass holds all
+    the atoms, more than it stages at a time.  The list holds every pair
+    within r_list and nothing beyond r_list + 1e-3 A (k-d tree count in
+    FP64), and the evaluation matches the oracle."""
+    from scipy.spatial import cKDTree
+    from paper_1607_02904_amd.tersoff import Tersoff, table_element
+    tab = table_element("Si(B)")
+    tab[0, 0, 0, params.IDX["R"]] = 2.85
+    tab[0, 0, 0, params.IDX["D"]] = 0.15
+    model = Tersoff(tab, masses=[28.0855])
+    try:
+        rng = np.random.default_rng(inputs.seed_for(13, int(skin * 10)))
+        x, box = inputs.diamond(10, 5.431)
+        x = inputs.wrap(inputs.perturb(x, 0.1, rng), box)
+        t = np.zeros(len(x), dtype=np.int32)
+        xd, td = _dev(x), _dev(t, torch.int32)
+        model.build_nlist(xd, td, box, skin)
+        st = model.nlist_stats()
+        rlist = 3.0 + skin
+        tree = cKDTree(x, boxsize=box)
+        exact = 2 * len(tree.query_pairs(rlist))
+        wide = 2 * len(tree.query_pairs(rlist + 1e-3))
+        assert st["n"] == len(x) and st["longest"] <= st["capacity"]
+        assert exact <= st["entries"] <= wide, (exact, st["entries"], wide)
+        assert st["capacity"] == (32 if skin == 2.0 else 64), st
+        ref = orc.compute(x, t, box, _si_table_oracle())
+        _check(gpu_eval(model, x, t, box, precision, skin=skin), ref, precision)
+    finally:
+        model.close()
+
+
 @pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
 def test_list_capacity_growth_to_64(orc, si_model, precision):
     """A 2.6 A skin gives every Si atom 33 or 34 list neighbours (the shells at
