@@ -141,7 +141,6 @@ DEV int block_excl_scan_t(int v, int *total) {
   if (total) *total = tot;
   return off + inc - v;
 }
-DEV int block_excl_scan(int v, int *total) { return block_excl_scan_t<kBS>(v, total); }
 
 DEV int wave_max_i(int v) {
 #pragma unroll
