@@ -338,6 +338,62 @@ def test_si_512k_full_size(si512k, precision, kernel, atoms):
     assert np.linalg.norm(f.sum(0)) <= 1e-9 * len(x) ** 0.5
 
 
+def test_si_512k_md_full_size(orc, si512k):
+    """20 velocity-Verlet steps (1 fs) of the 512,000-atom Si workload in the
+    benchmark's launch configuration (wavefront schedule, 32 atoms per
+    wavefront, skin 0.5, eight steps per graph launch, rebuilds on the
+    device), in FP64 and in mixed precision from the same start: the forces
+    on the sampled atoms and the energy of each end state agree with the
+    oracle's evaluation of that state, the two precisions follow the same
+    trajectory, the list was rebuilt on the device, and the total energy is
+    conserved to within the integrator's fluctuation (1e-3 eV per atom; a
+    wrong kick or drift factor moves it by far more)."""
+    from oracle import oracle as O
+    x, t, box, sample, fs, es, eref, wref, m = si512k
+    tab = params.single(params.SI_B)
+    mass = 28.0855
+    n = len(x)
+    td = _dev(t, torch.int32)
+    ends = {}
+    m.set_schedule(2, 32, 0)
+    try:
+        for prec in (0, 1):
+            xd = _dev(x).clone()
+            v = torch.zeros_like(xd)
+            f = torch.empty_like(xd)
+            m.build_nlist(xd, td, box, 0.5)
+            m.compute(xd, td, box, prec, energy=False, virial=False, out={"forces": f})
+            r0 = m.rebuilds()
+            tr = m.md_run(xd, v, f, td, box, 0.001, 20, 0.5, prec)
+            torch.cuda.synchronize()
+            m.sync()
+            ends[prec] = (xd.cpu().numpy(), v.cpu().numpy(), f.cpu().numpy(),
+                          float(tr[19].item()), m.rebuilds() - r0)
+    finally:
+        m.set_schedule(0, 0, 0)
+    for prec in (0, 1):
+        xe, ve, fe, epot, reb = ends[prec]
+        assert reb >= 1, reb
+        nl = orc.neighbours(xe, box, 3.2 + 0.5)
+        fs_e, _ = orc.forces_on(xe, t, box, tab, sample, nlist=nl)
+        e_ref, _, _, _ = orc.compute(xe, t, box, tab, nlist=nl)
+        if prec == 0:
+            assert _rel(fe[sample], fs_e) <= FP64_TOL
+            assert abs(epot - e_ref) <= FP64_TOL * abs(e_ref), (epot, e_ref)
+        else:
+            assert _rel(fe[sample], fs_e) <= MIX_F_TOL
+            assert mixed_energy_ok(epot, e_ref, n, "Si 512k MD")
+        ekin = 0.5 * mass * float((ve * ve).sum()) / O.FTM2V
+        print("precision %d: rebuilds %d, sampled force error %.2e, energy error %.2e, "
+              "total energy change %.2e eV/atom" % (prec, reb, _rel(fe[sample], fs_e),
+                                                    abs(epot - e_ref) / abs(e_ref),
+                                                    (epot + ekin - eref) / n))
+        assert abs(epot + ekin - eref) / n <= 1e-3, (epot + ekin - eref) / n
+    dx = np.max(np.abs(ends[1][0] - ends[0][0]))
+    print("mixed vs FP64 position difference after 20 steps: %.2e A" % dx)
+    assert dx <= 1e-6
+
+
 @pytest.fixture(scope="module")
 def sic1m(orc):
     """SiC zincblende 50^3 cells = 1,000,000 atoms, 10 % antisites, sigma 0.1,
