@@ -240,6 +240,13 @@ __global__ __launch_bounds__(BS) void k_force(FwdArgs a, int A) {
   const bool want_f = DUAL ? (a.xgrad != nullptr) : ((flags & TERS_FORCES) && a.forces);
   const bool want_w = !DUAL && (flags & TERS_VIRIAL);
   const bool want_ea = !DUAL && (flags & TERS_PER_ATOM_E) && a.e_atom;
+  // mixed path with a two-species table: the energy takes b from an FP64 sum
+  // of the FP32 zeta terms, evaluated in FP64 (bond_value_d), when an energy
+  // is asked for (disordered two-species cells cancel their repulsive and
+  // attractive parts to a few per cent; single-species cells keep the FP32
+  // bond order, as in the wavefront kernel)
+  constexpr bool kE64 = std::is_same<T, float>::value && !NT1;
+  const bool want_e = !DUAL && (a.partials != nullptr || want_ea);
 
   const int nsub = s_nsub;
   for (int sc = 0; sc < nsub; ++sc) {
@@ -305,6 +312,7 @@ __global__ __launch_bounds__(BS) void k_force(FwdArgs a, int A) {
         const T rinv = s_ri[p];
         const T u[3] = {s_dx[p] * rinv, s_dy[p] * rinv, s_dz[p] * rinv};
         T zeta = Zero<T>::get();
+        double zeta64 = 0.0;  // kE64: the same terms summed in FP64
         T gj[3] = {Zero<T>::get(), Zero<T>::get(), Zero<T>::get()};
         int kk = 0;
         for (int kq = 0; kq < nA; ++kq) {
@@ -325,6 +333,7 @@ __global__ __launch_bounds__(BS) void k_force(FwdArgs a, int A) {
             T gjt[3], gkt[3];
             T z = zeta_term<T, B, false>(pk, rij, rinv, u, rik, rki, v, fck, dfck, gjt, gkt, nullptr);
             zeta += z;
+            if constexpr (kE64) zeta64 += (double)z;
             gj[0] += gjt[0];
             gj[1] += gjt[1];
             gj[2] += gjt[2];
@@ -359,7 +368,11 @@ __global__ __launch_bounds__(BS) void k_force(FwdArgs a, int A) {
         const T vr = fr + b * fa;
         // the energy itself is assembled in FP64 from the factors (the FP32
         // path's large repulsive and attractive parts cancel at close contacts)
-        const AT V = widen(fcij) * (fre + widen(b) * fae);
+        AT bE = widen(b);
+        if constexpr (kE64) {
+          if (want_e) bE = bond_value_d(pp, zeta64);
+        }
+        const AT V = widen(fcij) * (fre + bE * fae);
         const T dVdr = dfcij * vr + fcij * (-pp.lam1 * fr - pp.lam2 * b * fa);
         dzeta = B(0.5) * fcij * fa * db;
         const T hp = B(0.5) * dVdr;

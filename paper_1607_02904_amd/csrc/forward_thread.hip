@@ -39,6 +39,13 @@ __global__ __launch_bounds__(kTBS) void k_force_thread(FwdArgs a) {
   const bool want_f = (flags & TERS_FORCES) && a.forces;
   const bool want_w = (flags & TERS_VIRIAL) != 0;
   const bool want_ea = (flags & TERS_PER_ATOM_E) && a.e_atom;
+  // mixed path with a two-species table: the energy takes b from an FP64 sum
+  // of the FP32 zeta terms, evaluated in FP64 (bond_value_d), when an energy
+  // is asked for (disordered two-species cells cancel their repulsive and
+  // attractive parts to a few per cent; single-species cells keep the FP32
+  // bond order, as in the wavefront kernel)
+  constexpr bool kE64 = std::is_same<T, float>::value && !NT1;
+  const bool want_e = a.partials != nullptr || want_ea;
 
   double eacc = 0.0, wacc[6] = {0, 0, 0, 0, 0, 0};
   const int t = blockIdx.x * kTBS + threadIdx.x;
@@ -96,6 +103,7 @@ __global__ __launch_bounds__(kTBS) void k_force_thread(FwdArgs a) {
 
       // first K loop: zeta_ij
       T zeta = T(B(0));
+      double zeta64 = 0.0;  // kE64: the same terms summed in FP64
       for (int s2 = 0; s2 < cnt; ++s2) {
         if (s2 == s) continue;
         const int k = row[s2];
@@ -107,7 +115,9 @@ __global__ __launch_bounds__(kTBS) void k_force_thread(FwdArgs a) {
         T fck = nk.fc, dfck = nk.dfc;
         if (!a.cut_consistent) fcut(pk, nk.r, fck, dfck);
         const T v[3] = {nk.d[0] * nk.ri, nk.d[1] * nk.ri, nk.d[2] * nk.ri};
-        zeta += zeta_value<T, B>(pk, nj.r, u, nk.r, v, fck);
+        const T zt = zeta_value<T, B>(pk, nj.r, u, nk.r, v, fck);
+        zeta += zt;
+        if constexpr (kE64) zeta64 += (double)zt;
       }
 
       // pair term
@@ -129,7 +139,11 @@ __global__ __launch_bounds__(kTBS) void k_force_thread(FwdArgs a) {
       T b, db, dbb, dbn;
       bond<T, B, false>(pp, zeta, b, db, dbb, dbn);
       const T vr = fr + b * fa;
-      const AT V = widen(nj.fc) * (fre + widen(b) * fae);
+      AT bE = widen(b);
+      if constexpr (kE64) {
+        if (want_e) bE = bond_value_d(pp, zeta64);
+      }
+      const AT V = widen(nj.fc) * (fre + bE * fae);
       const T dVdr = nj.dfc * vr + nj.fc * (-pp.lam1 * fr - pp.lam2 * b * fa);
       const T dzeta = B(0.5) * nj.fc * fa * db;
       const T hp = B(0.5) * dVdr;

@@ -168,6 +168,16 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEu<T, PG>::value))) void k_force_wave
   const bool want_f = DUAL ? (a.xgrad != nullptr) : ((flags & TERS_FORCES) && a.forces);
   const bool want_w = !DUAL && (flags & TERS_VIRIAL);
   const bool want_ea = !DUAL && (flags & TERS_PER_ATOM_E) && a.e_atom;
+  // mixed path with a two-species table: the energy takes b from an FP64 sum
+  // of the FP32 zeta terms, evaluated in FP64 (bond_value_d), when an energy
+  // is asked for.  Disordered two-species cells (SiC) cancel their repulsive
+  // and attractive parts to a few per cent, so the FP32 bond order's error
+  // (a few parts in 1e7 of b) would reach 1e-7 of the energy per atom.  The
+  // single-species kernel holds its parameter record in registers, where the
+  // FP64 evaluation would push values out to scratch memory; single-species
+  // cells keep the FP32 bond order.
+  constexpr bool kE64 = std::is_same<T, float>::value && !SP && !NT1;
+  const bool want_e = !DUAL && (a.partials != nullptr || want_ea);
 
   // periodic box: one record for a single system (uniform, read once),
   // the configuration's own record per lane for a batch
@@ -464,6 +474,7 @@ again:
       const KP &pp = param(ti, tj, tj);
       const bool in_pair = act && val(r) < pp.rcut;
       T zeta = Zero<T>::get();
+      double zeta64 = 0.0;  // kE64: the same terms summed in FP64
       T gs[3] = {Zero<T>::get(), Zero<T>::get(), Zero<T>::get()};  // sum over kept k of dzeta/dx_j
       for (int s = 1; s < nmax; ++s) {
         const bool keep = kOnePass && s <= kKeep;  // uniform
@@ -479,14 +490,17 @@ again:
           if (val(kr) < pk.rcut) {
             T fck = kfc, dfck = kdfc;
             if (!a.cut_consistent) fcut(pk, kr, fck, dfck);
+            T zt;
             if (keep) {
               T gj[3], dp[8];
-              zeta += zeta_term<T, B, false>(pk, r, ri, u, kr, kri, v, fck, dfck, gj, gk, dp);
+              zt = zeta_term<T, B, false>(pk, r, ri, u, kr, kri, v, fck, dfck, gj, gk, dp);
 #pragma unroll
               for (int c = 0; c < 3; ++c) gs[c] += gj[c];
             } else {
-              zeta += zeta_value<T, B>(pk, r, u, kr, v, fck);
+              zt = zeta_value<T, B>(pk, r, u, kr, v, fck);
             }
+            zeta += zt;
+            if constexpr (kE64) zeta64 += (double)zt;
           }
         }
         if (keep) {
@@ -498,6 +512,8 @@ again:
       T dzeta = Zero<T>::get();
       FA f0 = Zero<FA>::get(), f1 = Zero<FA>::get(), f2 = Zero<FA>::get();
       EA ev = 0;
+      double e_cfa = 0.0;  // kE64: 0.5 f_C f_A and the FP32 b, for the energy's
+      float e_b32 = 0.f;   // correction to the FP64 bond order after the K loops
       const double eb = DUAL ? (a.ebar_conf ? a.ebar_conf[cf] : a.ebar) : 1.0;
       if (in_pair) {
         T fr, fa;
@@ -531,6 +547,10 @@ again:
           f2 -= to_fa(wide(dzeta * gs[2]));
         }
         ev = 0.5 * val(V);
+        if constexpr (kE64) {
+          e_cfa = 0.5 * wide(fc) * fae;
+          e_b32 = b;
+        }
         if (PG) {
           const T h = T(B(0.5)) * fc;
           T dp[8];
@@ -594,6 +614,12 @@ again:
           f1 += to_fa(wide(ry));
           f2 += to_fa(wide(rz));
         }
+      }
+
+      // mixed path: the energy's bond order in FP64, evaluated here, where the
+      // K loops' registers are free: ev += 0.5 f_C f_A (b64 - b32)
+      if constexpr (kE64) {
+        if (want_e && in_pair) ev += e_cfa * (bond_value_d(pp, zeta64) - (double)e_b32);
       }
 
       // ---- f_im complete: virial, scatter to j, own force of i ------------------

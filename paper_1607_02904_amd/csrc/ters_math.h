@@ -104,6 +104,23 @@ DEV void bond(const KParam<B> &p, T z, T &b, T &db, T &dbeta, T &dn) {
   }
 }
 
+// b(zeta) in FP64 from the FP32 parameter record's hi/lo pairs, for the
+// energy of the mixed path: the FP32 evaluation above (a logarithm and two
+// exponentials of FP32 arguments, then a power) errs by a few parts in 1e7
+// of b, and in disordered cells the attractive and repulsive parts of the
+// energy are each about ten times the energy itself, so that error would
+// reach the energy at 1e-7 per atom; zeta is then the FP64 sum of the same
+// FP32 terms.  Same steps as bond(): s = n ln(beta zeta), ln(1 + e^s) =
+// max(s, 0) + ln(1 + e^-|s|), b = e^(-ln(1 + e^s)/(2n)).
+DEV double bond_value_d(const KParam<float> &p, double z) {
+  if (z <= 0.0) return 1.0;
+  const double lz = log_d((double)p.beta * z) + (double)p.lbeta_lo;
+  const double s = ((double)p.n + (double)p.n_lo) * lz;
+  const double em = exp_d(-fabs(s));
+  const double l1p = fmax(s, 0.0) + log1p01_d(em);
+  return exp_d(-((double)p.inv2n + (double)p.inv2n_lo) * l1p);
+}
+
 // zeta(i,j,k) alone (the first K loop of Algorithm 2 needs only the value).
 template <class T, class B>
 DEV T zeta_value(const KParam<B> &p, T rij, const T *u, T rik, const T *v, T fck) {

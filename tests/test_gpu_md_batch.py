@@ -242,6 +242,58 @@ def test_batch_mixed_adjoint_matches_single_calls(batch_setup):
     plan.close()
 
 
+def test_batch_full_size(orc, batch_setup):
+    """The benchmark's batched workload at full size (1,024 SiC configurations
+    of 64-4,096 atoms, 1,026,326 atoms), mixed forward + adjoint in the plan's
+    autotuned schedule: 16 sampled configurations (the smallest and the
+    largest among them) against the oracle (energy, forces, virial) and
+    their position gradients against per-configuration calls of the
+    single-system entry points in the same schedule; the parameter gradient
+    (a sum over every configuration) against the sum of all 1,024
+    per-configuration calls."""
+    _, model = batch_setup
+    confs = inputs.sic_liquid_batch(nconf=1024)
+    sizes = np.array([len(c[1]) for c in confs])
+    assert sizes.sum() == 1026326
+    rng = np.random.default_rng(17)
+    pick = sorted({int(np.argmin(sizes)), int(np.argmax(sizes))}
+                  | set(int(v) for v in rng.choice(len(confs), size=14, replace=False)))
+    plan, args = _run_plan(model, confs, 1, adjoint=True)
+    xd, td, e, f, w, eb, fb, xg, pg = args
+    sch = plan.schedule()
+    print("full-size batch schedule:", sch)
+    off = plan.offsets
+    e_all, f_all, w_all, xg_all = (a.cpu().numpy() for a in (e, f, w, xg))
+    sub = [confs[c] for c in pick]
+    sub_off = [0]
+    for c in pick:
+        sub_off.append(sub_off[-1] + len(confs[c][1]))
+    f_sub = np.concatenate([f_all[off[c]:off[c + 1]] for c in pick])
+    _check_batch(orc, sub, sub_off, e_all[pick], f_sub, w_all[pick], 1)
+    pg_sum = np.zeros((2, 2, 2, 14))
+    model.set_schedule(sch["kernel"], sch["atoms"], 0)
+    try:
+        worst = 0.0
+        for c, (xc, tc, bc) in enumerate(confs):
+            xcd = torch.as_tensor(xc, device="cuda")
+            tcd = torch.as_tensor(tc, device="cuda")
+            model.build_nlist(xcd, tcd, bc, 0.0)
+            xgc, pgc = model.backward(xcd, tcd, bc, float(eb[c].item()),
+                                      fb[off[c]:off[c + 1]].contiguous(), 1)
+            pg_sum += pgc.cpu().numpy()
+            if c in pick:
+                a, b = xg_all[off[c]:off[c + 1]], xgc.cpu().numpy()
+                rel = np.linalg.norm(a - b) / np.linalg.norm(b)
+                worst = max(worst, rel)
+                assert rel <= 1e-6, (c, rel)
+    finally:
+        model.set_schedule(0, 0, 0)
+    relp = np.linalg.norm(pg.cpu().numpy() - pg_sum) / np.linalg.norm(pg_sum)
+    print("full-size batch vs single mixed adjoint: x %.2e, params %.2e" % (worst, relp))
+    assert relp <= 1e-6
+    plan.close()
+
+
 def test_batch_graph_replays_and_adjoint(batch_setup):
     """Three graph replays with eager work in between give identical results;
     the batched adjoint equals per-configuration adjoints summed."""
