@@ -99,19 +99,26 @@ static double expo_d(double dr, const double *p) {
 }
 
 /* Bond order b(zeta) and db/dzeta.  b = 1 when zeta == 0 (no third atom),
- * and the derivative is then taken as 0 because it multiplies an empty sum. */
+ * and the derivative is then taken as 0 because it multiplies an empty sum.
+ * With s = n ln(beta zeta) and y = e^s = (beta zeta)^n, ln(1 + y) is formed as
+ * s + ln(1 + e^-s) for s > 0 and y / (1 + y) as 1 / (1 + e^-s): y itself leaves
+ * the FP64 range once s > 709, which close contacts reach (there the
+ * three-body exponential makes zeta huge), and would turn b into 0 and
+ * db/dzeta into inf / inf. */
+static double log1p_exp(double s) { return s > 0.0 ? s + log1p(exp(-s)) : log1p(exp(s)); }
 static double bond(double z, const double *p) {
   if (z <= 0.0) return 1.0;
   double n = p[F_N];
-  double y = exp(n * log(p[F_BETA] * z));
-  return exp(-log1p(y) / (2.0 * n));
+  double s = n * log(p[F_BETA] * z);
+  return exp(-log1p_exp(s) / (2.0 * n));
 }
 static double bond_d(double z, const double *p) {
   if (z <= 0.0) return 0.0;
   double n = p[F_N];
-  double y = exp(n * log(p[F_BETA] * z));
-  double b = exp(-log1p(y) / (2.0 * n));
-  return -0.5 * b * y / (z * (1.0 + y));
+  double s = n * log(p[F_BETA] * z);
+  double b = exp(-log1p_exp(s) / (2.0 * n));
+  double w = s > 0.0 ? 1.0 / (1.0 + exp(-s)) : exp(s) / (1.0 + exp(s)); /* y / (1 + y) */
+  return -0.5 * b * w / z;
 }
 
 /* zeta(i,j,k) and its gradients wrt x_i, x_j, x_k.

@@ -480,6 +480,65 @@ def test_equilateral_trimer_closed_form(orc):
     assert np.linalg.norm(f.sum(0)) < 1e-12
 
 
+def test_bond_order_close_contact(orc):
+    """Three Si(B) atoms with a 0.3 A contact at a right angle to a 2.75 A
+    bond: for the pair (i, j) the three-body exponential exp((lambda3 (r_ij -
+    r_ik))^3) is about 1e14, so (beta zeta)^n exceeds the FP64 range (n ln(beta
+    zeta) > 709) while b itself is about (beta zeta)^(-1/2).  The oracle's
+    energy equals the definition (Tersoff's b = (1 + (beta zeta)^n)^(-1/(2n)),
+    zeta = sum f_C g exp(lambda3^m (r_ij - r_ik)^m)) evaluated in 60-digit
+    decimal arithmetic, and its forces are finite and equal central
+    differences of its energy.  Every distance lies below R - D (f_C = 1) and
+    the right angle gives g = 1 (h = 0)."""
+    from decimal import Decimal, getcontext
+    getcontext().prec = 60
+    el = params.SI_B
+    tab = params.single(el)
+    P = {k: Decimal(repr(float(tab[0, 0, 0, v]))) for k, v in params.IDX.items()}
+    pos = np.array([[0.0, 0.0, 0.0], [0.3, 0.0, 0.0], [0.0, 2.75, 0.0]]) + 10.0
+    box = np.array([30.0, 30.0, 30.0])
+    t = np.zeros(3, np.int32)
+    e, f, _, _ = orc.compute(pos, t, box, tab)
+    assert np.isfinite(e) and np.all(np.isfinite(f))
+    X = [[Decimal(repr(float(v))) for v in row] for row in pos]
+
+    def vec(a, b):
+        return [X[b][q] - X[a][q] for q in range(3)]
+
+    def dot(u, v):
+        return sum(u[q] * v[q] for q in range(3))
+
+    rmax = (P["R"] - P["D"])
+    want = Decimal(0)
+    big = 0.0
+    for i in range(3):
+        for j in range(3):
+            if j == i:
+                continue
+            k = 3 - i - j
+            dij, dik = vec(i, j), vec(i, k)
+            rij, rik = dot(dij, dij).sqrt(), dot(dik, dik).sqrt()
+            assert rij < rmax and rik < rmax  # f_C = 1
+            cos = dot(dij, dik) / (rij * rik)
+            g = P["gamma"] * (1 + P["c"] ** 2 / P["d"] ** 2
+                              - P["c"] ** 2 / (P["d"] ** 2 + (P["h"] - cos) ** 2))
+            zeta = g * ((P["lam3"] * (rij - rik)) ** 3).exp()
+            s_ = P["n"] * (P["beta"] * zeta).ln()
+            big = max(big, float(s_))
+            b = (1 + s_.exp()) ** (-1 / (2 * P["n"]))
+            want += (P["A"] * (-P["lam1"] * rij).exp() - b * P["B"] * (-P["lam2"] * rij).exp()) / 2
+    assert big > 709.8  # (beta zeta)^n beyond the FP64 range for some pair
+    assert abs(e - float(want)) <= 1e-13 * abs(float(want)), (e, float(want))
+    h = 1e-6
+    for a in range(3):
+        for q in range(3):
+            xp, xm = pos.copy(), pos.copy()
+            xp[a, q] += h
+            xm[a, q] -= h
+            fd = -(orc.compute(xp, t, box, tab)[0] - orc.compute(xm, t, box, tab)[0]) / (2 * h)
+            assert abs(f[a, q] - fd) <= 1e-6 * max(1.0, abs(fd)), (a, q, f[a, q], fd)
+
+
 def test_isolated_atom_and_zeta_zero(orc):
     tab = params.single(params.SI_C)  # n < 1: db/dzeta is singular at zeta -> 0
     box = np.array([30.0] * 3)
