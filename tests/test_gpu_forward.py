@@ -554,6 +554,26 @@ def test_list_build_cell_grids(orc, si_model, shape, precision):
     _check(gpu_eval(si_model, x, t, box, precision, skin=0.5), ref, precision)
 
 
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
+def test_disordered_si_close_contacts(orc, precision):
+    """Disordered single-species Si cells (the batched recipe with Si's
+    lattice constant: sites thinned, sigma 0.3 A), four with contacts of
+    0.28-0.52 A, where (beta zeta)^n of Si(B) leaves the FP64 range and b is
+    about (beta zeta)^(-1/2): energy, forces, virial and per-atom energies
+    against the oracle."""
+    from paper_1607_02904_amd.tersoff import Tersoff, table_element
+    confs = inputs.sic_liquid_batch(nconf=256, a=5.431, seed=77)
+    model = Tersoff(table_element("Si(B)"), masses=[28.0855])
+    try:
+        for c in (174, 100, 222, 50):
+            x, _, box = confs[c]
+            t = np.zeros(len(x), dtype=np.int32)
+            ref = orc.compute(x, t, box, params.single(params.SI_B))
+            _check(gpu_eval(model, x, t, box, precision), ref, precision)
+    finally:
+        model.close()
+
+
 @pytest.mark.parametrize("skin", [2.0, 3.0])
 @pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
 def test_list_build_crowded_cells(orc, skin, precision):
