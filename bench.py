@@ -140,7 +140,7 @@ def traffic_of(sched, tname, n):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU; --gpus %d is not supported "
+        print("bench.py: the library runs on one GPU; --gpus %d is not supported "
               "(multi-GPU spatial decomposition is design only)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     import torch

@@ -46,7 +46,7 @@ typedef enum {
   TERS_ERR_PARAMS = 4,         /* parameter table fails validation */
   TERS_ERR_NOT_FINITE = 5,     /* non-finite position or result */
   TERS_ERR_HIP = 6,            /* a HIP runtime call failed */
-  TERS_ERR_UNSUPPORTED = 7,    /* valid request this build does not handle */
+  TERS_ERR_UNSUPPORTED = 7,    /* valid request the library does not handle */
   TERS_ERR_NO_LIST = 8         /* compute before ters_build_nlist, or n changed */
 } ters_status;
 

@@ -70,7 +70,7 @@ DEV int cell_of_atom(int i, const double *__restrict__ x, const ConfDesc *__rest
 // next[atom] -> ... -> -1).  The order the places are taken in does not
 // matter: the cell pass ranks each cell's atoms by index.  Also checks every
 // species against [0, ntypes) when type is given, and clears the state of
-// this build's one-pass scans (tickets, tile flags, the longest-row register).
+// the current list build's one-pass scans (tickets, tile flags, the longest-row register).
 constexpr int kCellReg = 8;
 __global__ void k_bin(int n, const double *__restrict__ x, const ConfDesc *__restrict__ conf,
                       const int32_t *__restrict__ conf_of, int32_t *__restrict__ cell_count,
