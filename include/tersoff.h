@@ -145,7 +145,7 @@ ters_status ters_compute(ters_ctx *ctx, int32_t n, const double *x, const int32_
  * context's schedule and force mode), with every work buffer (cell bins,
  * list of at most TERS_STATIC_CAP entries per atom, reverse map, force slots,
  * partial sums) in one static device array of the library, of fixed size
- * (about 20 MB), that each GPU holds from the first ters_create on it until
+ * (about 23 MB), that each GPU holds from the first ters_create on it until
  * the process ends.  It calls no hipMalloc, hipFree or other allocating
  * routine and does not synchronise.  Limits: n <= TERS_STATIC_MAX_ATOMS
  * (TERS_ERR_UNSUPPORTED beyond); at most TERS_STATIC_CAP list entries per
