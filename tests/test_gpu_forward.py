@@ -338,6 +338,26 @@ def test_si_512k_full_size(si512k, precision, kernel, atoms):
     assert np.linalg.norm(f.sum(0)) <= 1e-9 * len(x) ** 0.5
 
 
+def test_si_512k_full_size_single(si512k):
+    """The single mode (all FP32, the paper's all-single mode) on the
+    512,000-atom Si workload in the launch configuration the benchmark times
+    for it (wavefront schedule, 32 atoms per wavefront, skin 0.5): energy,
+    virial, and forces and per-atom energies of the sampled atoms against
+    the oracle, at the single mode's bars."""
+    x, t, box, sample, fs, es, eref, wref, m = si512k
+    m.set_schedule(2, 32, 0)
+    try:
+        e, f, w, ea = gpu_eval(m, x, t, box, 2, skin=0.5)
+    finally:
+        m.set_schedule(0, 0, 0)
+    print("single 512k: |dE|/|E| = %.2e, forces %.2e, per-atom %.2e, virial %.2e"
+          % (abs(e - eref) / abs(eref), _rel(f[sample], fs), _rel(ea[sample], es), _rel(w, wref)))
+    assert abs(e - eref) <= SP_E_TOL * abs(eref)
+    assert _rel(f[sample], fs) <= SP_F_TOL
+    assert _rel(ea[sample], es) <= SP_F_TOL
+    assert _rel(w, wref) <= SP_F_TOL
+
+
 def test_si_512k_md_full_size(orc, si512k):
     """20 velocity-Verlet steps (1 fs) of the 512,000-atom Si workload in the
     benchmark's launch configuration (wavefront schedule, 32 atoms per
