@@ -52,3 +52,32 @@ def lj_compute(x, box, eps, sigma, rc):
                        np.sum(dm[:, 2] * fj[:, 2]), np.sum(dm[:, 0] * fj[:, 1]),
                        np.sum(dm[:, 0] * fj[:, 2]), np.sum(dm[:, 1] * fj[:, 2])])
     return e, f, w
+
+
+def lj_compute_pairs(x, box, eps, sigma, rc):
+    """The same energy, forces and virial as lj_compute, with the pairs
+    within r_c enumerated by a k-d tree over the periodic box (a library
+    primitive standing in for the loop over all pairs, for systems too large
+    for it); the sums are the definition's, pair by pair."""
+    from scipy.spatial import cKDTree
+    x = np.asarray(x, dtype=np.float64)
+    box = np.asarray(box, dtype=np.float64)
+    n = len(x)
+    xw = x - np.floor(x / box) * box
+    pairs = cKDTree(xw, boxsize=box).query_pairs(rc, output_type="ndarray")
+    f = np.zeros((n, 3))
+    if len(pairs) == 0:
+        return 0.0, f, np.zeros(6)
+    i, j = pairs[:, 0], pairs[:, 1]
+    d = x[j] - x[i]
+    d -= box * np.round(d / box)
+    r = np.sqrt(np.sum(d * d, axis=1))
+    m = r < rc
+    i, j, d, r = i[m], j[m], d[m], r[m]
+    v, g = lj_pair(r, eps, sigma)
+    fj = g[:, None] * d
+    np.add.at(f, j, fj)
+    np.add.at(f, i, -fj)
+    w = np.array([np.sum(d[:, 0] * fj[:, 0]), np.sum(d[:, 1] * fj[:, 1]), np.sum(d[:, 2] * fj[:, 2]),
+                  np.sum(d[:, 0] * fj[:, 1]), np.sum(d[:, 0] * fj[:, 2]), np.sum(d[:, 1] * fj[:, 2])])
+    return float(np.sum(v)), f, w

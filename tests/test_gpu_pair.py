@@ -82,3 +82,22 @@ def test_pair_cutoff_beyond_the_list_is_refused(model):
     with pytest.raises(TersoffError) as ei:
         model.pair_compute(xd, box, EPS, SIG, 3.6)  # beyond the Tersoff cutoff (3.0 or 3.2 A)
     assert ei.value.name == "TERS_ERR_INVALID_ARG"
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
+def test_pair_full_size(model, precision):
+    """The benchmark's pair-potential evaluation: 512,000-atom Si over the
+    list of skin 0.5, against the oracle with its pairs enumerated by a k-d
+    tree (every atom's force, the energy and the virial)."""
+    x, t, box = inputs.si_bulk(40)
+    e, f, w = _run(model, x, t, box, precision, 0.5)
+    er, fr, wr = pair.lj_compute_pairs(x, box, EPS, SIG, RC)
+    if precision == 0:
+        assert abs(e - er) <= 1e-12 * abs(er)
+        assert _rel(f, fr) <= 1e-12
+        assert _rel(w, wr) <= 1e-12
+    else:
+        assert abs(e - er) <= 1e-6 * abs(er), (e, er)
+        assert _rel(f, fr) <= 1e-5
+        assert _rel(w, wr) <= 1e-5
+

@@ -80,3 +80,23 @@ def test_virial_is_minus_the_strain_derivative():
         s[k] = 1 - h
         em = pair.lj_compute(x * s, box * s, EPS, SIG, rc)[0]
         assert abs(-(ep - em) / (2 * h) - w[k]) <= 1e-7 * max(1.0, abs(w[k])), (k, w[k])
+
+
+def test_pair_enumeration_equals_the_loop_over_all_pairs():
+    """lj_compute_pairs (pairs within r_c found by a k-d tree, for large
+    systems) gives the energy, forces and virial of lj_compute (every pair
+    visited), on a perturbed lattice and on a dense random gas."""
+    rng = np.random.default_rng(12)
+    a = 3.8
+    g = np.arange(8) * a
+    x1 = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3) + rng.normal(0, 0.3, (512, 3))
+    box1 = np.full(3, 8 * a)
+    box2 = np.array([22.0, 25.0, 21.0])
+    x2 = rng.uniform(0, 1, (400, 3)) * box2
+    for x, box, rc in ((x1, box1, 8.5), (x2, box2, 9.0)):
+        e, f, w = pair.lj_compute(x, box, EPS, SIG, rc)
+        e2, f2, w2 = pair.lj_compute_pairs(x, box, EPS, SIG, rc)
+        assert abs(e2 - e) <= 1e-12 * abs(e)
+        assert np.linalg.norm(f2 - f) <= 1e-12 * np.linalg.norm(f)
+        assert np.linalg.norm(w2 - w) <= 1e-12 * np.linalg.norm(w)
+
