@@ -111,7 +111,12 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEu<T, PG>::value))) void k_force_wave
   __shared__ unsigned char s_slot[kWPB][kAMax * kNMax];  // list slot of each staged neighbour
   __shared__ unsigned short s_map[kWPB][kBatch * kWave];  // filter: (atom << 8) | slot
   __shared__ KP s_kp[NT1 ? 1 : NTL];
-  __shared__ double s_g[PG && !NT1 ? NTL * kNField : 1];
+  // parameter gradient with a multi-species table: kGCopies copies of the
+  // accumulator (lane l adds to copy l % kGCopies), so that the lanes of a
+  // wavefront adding to the entry of one species triple rarely meet on the
+  // same LDS word; summed over the copies at the end
+  constexpr int kGCopies = 8;
+  __shared__ double s_g[PG && !NT1 ? kGCopies * NTL * kNField : 1];
   __shared__ double s_red[kWPB][8];
   // Without the parameter gradient the first K loop already evaluates the
   // whole three-body term (value and both gradients); the gradient wrt x_k of
@@ -141,7 +146,7 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEu<T, PG>::value))) void k_force_wave
   }
   const bool grad_in_lds = !NT1 && PG && nt * nt * nt <= NTL;
   if (grad_in_lds)
-    for (int e = tid; e < NTL * kNField; e += kWPB * kWave) s_g[e] = 0.0;
+    for (int e = tid; e < kGCopies * NTL * kNField; e += kWPB * kWave) s_g[e] = 0.0;
   if (!NT1) __syncthreads();  // the only workgroup barrier before the final reductions
 
   // one species: the record is read once into registers (uniform, scalar
@@ -159,7 +164,8 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEu<T, PG>::value))) void k_force_wave
   }
   auto add_grad = [&](int ti, int tj, int tk, int field, double v) {
     if (NT1) gacc[field] += v;
-    else if (grad_in_lds) unsafeAtomicAdd(&s_g[((ti * nt + tj) * nt + tk) * kNField + field], v);
+    else if (grad_in_lds)
+      unsafeAtomicAdd(&s_g[((lane % kGCopies) * NTL + (ti * nt + tj) * nt + tk) * kNField + field], v);
     else atomic_add(&a.pgrad[((ti * nt + tj) * nt + tk) * kNField + field], v);
   };
 
@@ -780,8 +786,11 @@ done:
       }
     } else if (grad_in_lds) {
       __syncthreads();
-      for (int e = tid; e < nt * nt * nt * kNField; e += kWPB * kWave)
-        if (s_g[e] != 0.0) atomic_add(&a.pgrad[e], s_g[e]);
+      for (int e = tid; e < nt * nt * nt * kNField; e += kWPB * kWave) {
+        double sum = 0.0;
+        for (int c = 0; c < kGCopies; ++c) sum += s_g[c * NTL * kNField + e];
+        if (sum != 0.0) atomic_add(&a.pgrad[e], sum);
+      }
     }
   }
 }
