@@ -238,9 +238,11 @@ ters_status ters_md_rebuilds(ters_ctx *ctx, int64_t *out);
  * configurations, from eight work queues (one per XCD, atomic counters reset
  * at the start of the graph) until all are done, and, with f_bar, one such
  * launch of the adjoint kernel.  The atoms per chunk of each pass are timed
- * on the data of the first run that needs the pass (synchronising).  Pointers
- * given to the first run are baked into the graph; later runs with other
- * pointers re-capture it.  Errors latched by the graph (list overflow,
+ * on the data of the first run that needs the pass (synchronising).  The
+ * pointers of a run are baked into its graph: the plan keeps the graphs of
+ * the four most recently used argument sets (a forward-only run and a run
+ * with the adjoint, alternating, replay two graphs), and a run with another
+ * set captures a new one in place of the least recently launched.  Errors latched by the graph (list overflow,
  * non-finite positions, species outside the table) are reported by
  * ters_sync.  A plan refuses runs once ters_set_params changed the number of
  * species or raised a cutoff beyond the plan's list radius. */
@@ -258,7 +260,8 @@ ters_status ters_plan_destroy(ters_plan *plan);
  * per chunk of the forward pass, out[1] = kernel (2: the wavefront schedule,
  * persistent form), out[2] = measured microseconds of the forward pass,
  * out[3] = atoms per chunk of the adjoint pass (0 until a run with f_bar),
- * out[4] = its microseconds, out[5] = workgroups of the forward launch. */
+ * out[4] = its microseconds, out[5] = workgroups of the forward launch (those
+ * that fill the device, or fewer when the chunks are fewer). */
 ters_status ters_plan_schedule(const ters_plan *plan, double *out6);
 
 /* ---- schedule control ------------------------------------------------------

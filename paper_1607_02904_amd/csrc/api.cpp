@@ -20,6 +20,7 @@
 using namespace ters;
 
 constexpr int kMdGraphSteps = 8;  // molecular-dynamics steps per replayed graph
+constexpr int kPlanGraphs = 4;    // instantiated evaluation graphs kept per batch plan
 
 struct ters_ctx {
   int device = 0;
@@ -59,11 +60,20 @@ struct ters_plan {
   // persistent wavefront schedule of the forward (f) and adjoint (a) pass:
   // atoms per chunk, chunk items with their eight queue ranges, workgroups
   int A = 0, A_adj = 0, gather = 1, grid_f = 0, grid_a = 0, grab_f = 1, grab_a = 1;
+  int nitems_f = 0, nitems_a = 0;
   DevBuf items_f, qb_f, items_a, qb_a, queue;  // queue: 8 counters per pass
   double best_us = 0.0, best_adj_us = 0.0;
   bool tuned = false, tuned_adj = false;
-  hipGraphExec_t exec = nullptr;
-  std::vector<const void *> key;
+  // instantiated graphs of the evaluation, one per distinct argument set (a
+  // forward-only run and a run with the adjoint alternate in a fitting loop),
+  // at most kPlanGraphs, the least recently launched replaced first
+  struct Graph {
+    hipGraphExec_t exec = nullptr;
+    std::vector<const void *> key;
+    uint64_t used = 0;
+  };
+  std::vector<Graph> graphs;
+  uint64_t launches = 0;
 };
 
 namespace {
@@ -1179,7 +1189,7 @@ __global__ void k_split_partials(const double *partials, int nconf, double *e, d
 // Chunks of A atoms that never straddle two configurations (the atoms of
 // configuration c occupy cell-order positions [off_c, off_c + n_c)), dealt to
 // eight queues as contiguous ranges; uploaded to items / qb.
-void make_items(ters_plan *p, int A, DevBuf &items, DevBuf &qb, hipStream_t s) {
+int make_items(ters_plan *p, int A, DevBuf &items, DevBuf &qb, hipStream_t s) {
   std::vector<int2> it;
   for (int c = 0; c < p->nconf; ++c)
     for (int k = 0; k < p->natoms[c]; k += A)
@@ -1192,6 +1202,7 @@ void make_items(ters_plan *p, int A, DevBuf &items, DevBuf &qb, hipStream_t s) {
   TERS_HIP_TRY(hipMemcpyAsync(items.p, it.data(), sizeof(int2) * ni, hipMemcpyHostToDevice, s));
   TERS_HIP_TRY(hipMemcpyAsync(qb.p, b.data(), sizeof(int32_t) * 9, hipMemcpyHostToDevice, s));
   TERS_HIP_TRY(hipStreamSynchronize(s));  // the host vectors go out of scope
+  return ni;
 }
 
 
@@ -1209,6 +1220,7 @@ FwdArgs batch_fwd_args(ters_plan *p, const double *x, const int32_t *type, doubl
   a.items = p->items_f.as<int2>();
   a.qbound = p->qb_f.as<int32_t>();
   a.queue = p->queue.as<int32_t>();
+  a.nitems = p->nitems_f;
   a.grid = p->grid_f;
   a.grab = p->grab_f;
   return a;
@@ -1232,6 +1244,7 @@ FwdArgs batch_adj_args(ters_plan *p, const double *x, const int32_t *type, const
   b.items = p->items_a.as<int2>();
   b.qbound = p->qb_a.as<int32_t>();
   b.queue = p->queue.as<int32_t>() + 8;
+  b.nitems = p->nitems_a;
   b.grid = p->grid_a;
   b.grab = p->grab_a;
   return b;
@@ -1368,7 +1381,7 @@ ters_status ters_batch_run(ters_plan *p, const double *x, const int32_t *type, d
       int bestA = 16, bestG = 1;
       for (const auto &cd : cands) {
         const int A = cd[0];
-        make_items(p, A, p->items_f, p->qb_f, c->stream);
+        p->nitems_f = make_items(p, A, p->items_f, p->qb_f, c->stream);
         p->grab_f = cd[1];
         FwdArgs a = batch_fwd_args(p, x, type, ft.as<double>());
         const double us = time_us([&]() {
@@ -1382,7 +1395,7 @@ ters_status ters_batch_run(ters_plan *p, const double *x, const int32_t *type, d
         }
       }
       ft.release();
-      make_items(p, bestA, p->items_f, p->qb_f, c->stream);
+      p->nitems_f = make_items(p, bestA, p->items_f, p->qb_f, c->stream);
       p->grab_f = bestG;
       p->A = bestA;
       p->best_us = best;
@@ -1398,7 +1411,7 @@ ters_status ters_batch_run(ters_plan *p, const double *x, const int32_t *type, d
       int bestA = 16, bestG = 1;
       for (const auto &cd : cands) {
         const int A = cd[0];
-        make_items(p, A, p->items_a, p->qb_a, c->stream);
+        p->nitems_a = make_items(p, A, p->items_a, p->qb_a, c->stream);
         p->grab_a = cd[1];
         FwdArgs b = batch_adj_args(p, x, type, e_bar, f_bar, xt.as<double>(), pt.as<double>());
         const double us = time_us([&]() {
@@ -1413,7 +1426,7 @@ ters_status ters_batch_run(ters_plan *p, const double *x, const int32_t *type, d
       }
       xt.release();
       pt.release();
-      make_items(p, bestA, p->items_a, p->qb_a, c->stream);
+      p->nitems_a = make_items(p, bestA, p->items_a, p->qb_a, c->stream);
       p->grab_a = bestG;
       p->A_adj = bestA;
       p->best_adj_us = best;
@@ -1428,22 +1441,40 @@ ters_status ters_batch_run(ters_plan *p, const double *x, const int32_t *type, d
                            (const void *)(intptr_t)p->grid_a, (const void *)(intptr_t)p->grab_f,
                            (const void *)(intptr_t)p->grab_a};
     key.insert(key.end(), std::begin(extra), std::end(extra));
-    if (!p->exec || key != p->key) {
-      if (p->exec) {
-        TERS_HIP_TRY(hipGraphExecDestroy(p->exec));
-        p->exec = nullptr;
+    ters_plan::Graph *gr = nullptr;
+    for (auto &cand : p->graphs)
+      if (cand.key == key) gr = &cand;
+    if (!gr) {
+      if ((int)p->graphs.size() < kPlanGraphs) {
+        p->graphs.emplace_back();
+        gr = &p->graphs.back();
+      } else {
+        gr = &p->graphs[0];
+        for (auto &cand : p->graphs)
+          if (cand.used < gr->used) gr = &cand;
       }
+      if (gr->exec) {
+        sync(c);
+        TERS_HIP_TRY(hipGraphExecDestroy(gr->exec));
+        gr->exec = nullptr;
+      }
+      gr->key.clear();
       if (!c->capture_stream) TERS_HIP_TRY(hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
       sync(c);
       hipGraph_t g;
       TERS_HIP_TRY(hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal));
       batch_enqueue(p, x, type, e, f, w, e_bar, f_bar, xg, pg, c->capture_stream);
       TERS_HIP_TRY(hipStreamEndCapture(c->capture_stream, &g));
-      TERS_HIP_TRY(hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0));
-      TERS_HIP_TRY(hipGraphDestroy(g));
-      p->key = key;
+      const hipError_t ie = hipGraphInstantiate(&gr->exec, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (ie != hipSuccess) {
+        gr->exec = nullptr;
+        TERS_HIP_TRY(ie);
+      }
+      gr->key = key;
     }
-    TERS_HIP_TRY(hipGraphLaunch(p->exec, c->stream));
+    gr->used = ++p->launches;
+    TERS_HIP_TRY(hipGraphLaunch(gr->exec, c->stream));
     return TERS_OK;
   });
 }
@@ -1452,8 +1483,9 @@ static void plan_release_device(ters_plan *p) {
   if (!p->ctx) return;
   hipSetDevice(p->ctx->device);
   hipStreamSynchronize(p->ctx->stream);
-  if (p->exec) hipGraphExecDestroy(p->exec);
-  p->exec = nullptr;
+  for (auto &g : p->graphs)
+    if (g.exec) hipGraphExecDestroy(g.exec);
+  p->graphs.clear();
   DevBuf *bufs[] = {&p->partials, &p->ebuf, &p->errw, &p->fslot, &p->fown, &p->items_f,
                     &p->qb_f, &p->items_a, &p->qb_a, &p->queue, &p->nl.conf,
                     &p->nl.conf_of, &p->nl.count, &p->nl.list, &p->nl.order, &p->nl.cell_next,
@@ -1484,7 +1516,7 @@ ters_status ters_plan_schedule(const ters_plan *p, double *out6) {
   out6[2] = p->best_us;
   out6[3] = p->A_adj;
   out6[4] = p->best_adj_us;
-  out6[5] = p->grid_f;
+  out6[5] = wave_persistent_launch(p->grid_f, p->nitems_f, p->grab_f, false);
   return TERS_OK;
 }
 

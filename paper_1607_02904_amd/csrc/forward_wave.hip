@@ -116,7 +116,8 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEu<T, PG>::value))) void k_force_wave
   // wavefront adding to the entry of one species triple rarely meet on the
   // same LDS word; summed over the copies at the end
   constexpr int kGCopies = 8;
-  __shared__ double s_g[PG && !NT1 ? kGCopies * NTL * kNField : 1];
+  // (one species: each wavefront's sums, added over the workgroup at the end)
+  __shared__ double s_g[PG ? (NT1 ? kWPB * kNField : kGCopies * NTL * kNField) : 1];
   __shared__ double s_red[kWPB][8];
   // Without the parameter gradient the first K loop already evaluates the
   // whole three-body term (value and both gradients); the gradient wrt x_k of
@@ -240,7 +241,12 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEu<T, PG>::value))) void k_force_wave
       for (int k = 0; k < 8; ++k) {
         const int xq = (home + k) & 7;
         const int len = a.qbound[xq + 1] - a.qbound[xq];
-        if (len <= 0) continue;
+        // a queue already used up is skipped on a plain read: the counters are
+        // a few words that every wavefront of the launch comes back to, and
+        // adds to one word serialise
+        if (len <= 0 ||
+            __hip_atomic_load(&a.queue[xq], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= len)
+          continue;
         const int got = atomicAdd(&a.queue[xq], a.grab);
         if (got < len) {
           v = a.qbound[xq] + got;
@@ -641,9 +647,11 @@ again:
           wv[5] = ddx * fz;
           wv[6] = ddy * fz;
         }
-        if (a.conf_of) {
+        if (a.conf_of && !PERSIST) {
           // batches: per-configuration energy and virial; one atomic per value
           // when the round belongs to one configuration, per lane otherwise
+          // (the persistent form sums a chunk, which lies in one configuration,
+          // and adds it when the chunk is done)
           const int cf0 = __shfl(cf, 0, kWave);
           if (__ballot(act && cf != cf0) == 0ull) {
 #pragma unroll
@@ -746,6 +754,19 @@ again:
     }
   }
   if constexpr (PERSIST) {  // the next chunk, if any
+    if (!DUAL && a.partials && a.conf_of) {
+      // the chunk's energy and virial to its configuration: one atomic per value
+      const int cfc = a.conf_of[a.order[first]];
+      EA vals[7] = {eacc, wacc[0], wacc[1], wacc[2], wacc[3], wacc[4], wacc[5]};
+#pragma unroll
+      for (int k = 0; k < 7; ++k) {
+        const double sum = wave_sum(vals[k]);
+        if (lane == 0) atomic_add(&a.partials[(int64_t)cfc * 8 + k], sum);
+      }
+      eacc = 0;
+#pragma unroll
+      for (int k = 0; k < 6; ++k) wacc[k] = 0;
+    }
     ++item;
     if (item >= run_end && !next_run()) goto done;
     first = a.items[item].x;
@@ -779,10 +800,18 @@ done:
   }
   if (PG) {
     if (NT1) {
+      // the workgroup's sum, one atomic per field: every workgroup adds to the
+      // same 14 words, and adds to one word serialise
 #pragma unroll
       for (int f = 0; f < kNField; ++f) {
         double sum = wave_sum(gacc[f]);
-        if (lane == 0) atomic_add(&a.pgrad[f], sum);
+        if (lane == 0) s_g[w * kNField + f] = sum;
+      }
+      __syncthreads();
+      if (tid < kNField) {
+        double sum = 0.0;
+        for (int q = 0; q < kWPB; ++q) sum += s_g[q * kNField + tid];
+        if (sum != 0.0) atomic_add(&a.pgrad[tid], sum);
       }
     } else if (grad_in_lds) {
       __syncthreads();
@@ -800,7 +829,8 @@ void launch_wave_t(const FwdArgs &a, int A, hipStream_t s) {
   constexpr int kWPB = waves_per_group<PG>();
   if (A <= 0 || A > kAMax) A = 16;
   const int64_t per_block = (int64_t)kWPB * A;
-  const int nb = a.items ? a.grid : (int)((a.n + per_block - 1) / per_block);
+  const int nb = a.items ? wave_persistent_launch(a.grid, a.nitems, a.grab, PG)
+                         : (int)((a.n + per_block - 1) / per_block);
   if (nb <= 0 || a.n == 0) return;
   if (a.items) {
     if (a.ntypes == 1)
@@ -837,6 +867,15 @@ int wave_persistent_grid(int precision, bool adjoint, bool multi_species) {
     return precision == TERS_FP64 ? resident_grid<Dual<double>, true>(nt1)
                                   : resident_grid<Dual<float>, true>(nt1);
   return precision == TERS_FP64 ? resident_grid<double, false>(nt1) : resident_grid<float, false>(nt1);
+}
+
+int wave_persistent_launch(int grid, int nitems, int grab, bool pg) {
+  if (nitems <= 0) return grid;
+  // no more workgroups than take a run of items each at the start (at least
+  // one per XCD queue): the others would only find the queues empty
+  const int wpb = pg ? waves_per_group<true>() : waves_per_group<false>();
+  const int64_t runs = (nitems + std::max(grab, 1) - 1) / std::max(grab, 1);
+  return (int)std::min<int64_t>(grid, std::max<int64_t>(8, (runs + wpb - 1) / wpb));
 }
 
 int wave_blocks(int n, int A, bool pg) {

@@ -163,7 +163,9 @@ struct FwdArgs {
   const int2 *items;
   const int32_t *qbound;
   int32_t *queue;
-  int32_t grid;            // persistent form: workgroups of the launch
+  int32_t nitems;          // persistent form: items (qbound[8]); the launch takes at most
+                           // the workgroups that these keep busy
+  int32_t grid;            // persistent form: workgroups of the launch (at most)
   int32_t grab;            // persistent form: items per atomic take (0: static shares)
 };
 
@@ -190,6 +192,9 @@ void launch_adjoint_wave(const FwdArgs &a, int precision, int atoms_per_wave, hi
 int wave_blocks(int n, int atoms_per_wave, bool param_grad);
 // persistent form: workgroups that fill the device at the kernel's occupancy
 int wave_persistent_grid(int precision, bool adjoint, bool multi_species);
+// persistent form: workgroups launched for nitems items taken grab at a time,
+// at most grid (pg: the parameter-gradient kernel's workgroup size)
+int wave_persistent_launch(int grid, int nitems, int grab, bool pg);
 // pair potential (truncated Lennard-Jones) over the list: one thread per atom
 // in cell order, own forces only (full list, no atomics)
 struct PairArgs {

@@ -337,6 +337,63 @@ def test_batch_graph_replays_and_adjoint(batch_setup):
     plan.close()
 
 
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
+def test_batch_alternating_runs_replay_their_own_graphs(batch_setup, precision):
+    """Forward-only runs and runs with the adjoint alternate on one plan (the
+    fitting loop): each replays the graph of its own argument set, also after
+    runs with four other argument sets have replaced both graphs in the
+    plan's cache, and gives the results of its first run."""
+    from paper_1607_02904_amd.tersoff import BatchPlan
+    confs, model = batch_setup
+    nat, boxes, x, t = _cat(confs)
+    plan = BatchPlan(model, nat, boxes, precision=precision)
+    N, C = int(nat.sum()), len(confs)
+    xd = torch.as_tensor(x, device="cuda")
+    td = torch.as_tensor(t, device="cuda")
+    g = torch.Generator("cuda").manual_seed(5)
+    eb = torch.rand(C, dtype=torch.float64, device="cuda", generator=g) * 1e-3
+    fb = torch.randn((N, 3), dtype=torch.float64, device="cuda", generator=g) * 0.1
+
+    def bufs():
+        return (torch.empty(C, dtype=torch.float64, device="cuda"),
+                torch.empty((N, 3), dtype=torch.float64, device="cuda"),
+                torch.empty((C, 6), dtype=torch.float64, device="cuda"),
+                torch.empty((N, 3), dtype=torch.float64, device="cuda"),
+                torch.empty((2, 2, 2, 14), dtype=torch.float64, device="cuda"))
+
+    e, f, w, xg, pg = bufs()
+
+    def run(adjoint):
+        for a in (e, f, w, xg, pg):
+            a.fill_(float("nan"))
+        if adjoint:
+            plan.run(xd, td, e, f, w, eb, fb, xg, pg)
+        else:
+            plan.run(xd, td, e, f, w)
+        torch.cuda.synchronize()
+        return [a.cpu().numpy().copy() for a in ((e, f, w, xg, pg) if adjoint else (e, f, w))]
+
+    first_f, first_a = run(False), run(True)
+    for k in range(3):
+        assert np.allclose(first_a[k], first_f[k], rtol=1e-13, atol=1e-13)
+    for rep in range(2):
+        for _ in range(2):
+            got_f, got_a = run(False), run(True)
+            for k in range(3):
+                assert np.allclose(got_f[k], first_f[k], rtol=1e-13, atol=1e-13)
+            for k in range(5):
+                assert np.isfinite(got_a[k]).all()
+                assert np.allclose(got_a[k], first_a[k], rtol=1e-13, atol=1e-13)
+        if rep == 0:
+            held = [bufs() for _ in range(4)]  # four other argument sets (all live)
+            for e2, f2, w2, xg2, pg2 in held:
+                plan.run(xd, td, e2, f2, w2, eb, fb, xg2, pg2)
+                torch.cuda.synchronize()
+                assert np.allclose(xg2.cpu().numpy(), first_a[3], rtol=1e-13, atol=1e-13)
+            del held
+    plan.close()
+
+
 def test_md_run_timed_matches_md_run(si_model):
     """The timed MD entry point runs the same steps (launched one by one, with
     events around the force kernel) and reports a positive kernel time."""
