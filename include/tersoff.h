@@ -231,7 +231,11 @@ ters_status ters_md_rebuilds(ters_ctx *ctx, int64_t *out);
  * (device, FP64; any may be NULL).  If f_bar is non-NULL the graph also runs
  * the adjoint with per-configuration e_bar[nconf] (device) and f_bar_cat
  * [N][3] (device), writing x_grad_cat [N][3] and param_grad (summed over
- * configurations) [ntypes^3][14].  x_cat, type_cat device.  Inside the
+ * configurations) [ntypes^3][14]; with f_bar set and e, f_cat and w all
+ * NULL the forward pass is left out (the adjoint does not need its
+ * results: a fitting loop that has the energies and forces of these
+ * positions from a forward-only run asks for the gradients alone).
+ * x_cat, type_cat device.  Inside the
  * graph: the lists of all configurations (one set of launches), then one
  * persistent launch of the wavefront force kernel whose workgroups (as many
  * as stay resident on the device) take chunks of atoms, never spanning two

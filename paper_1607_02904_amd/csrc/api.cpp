@@ -1252,7 +1252,9 @@ FwdArgs batch_adj_args(ters_plan *p, const double *x, const int32_t *type, const
 
 // One batch evaluation: list build, queue reset, the persistent forward
 // launch (and gather), per-configuration energies and virials, then with
-// f_bar the persistent adjoint launch (and gather).  Captured in a graph.
+// f_bar the persistent adjoint launch (and gather).  The forward pass is left
+// out when f_bar is set and none of e, f, w is asked for (the adjoint
+// recomputes what it needs).  Captured in a graph.
 void batch_enqueue(ters_plan *p, const double *x, const int32_t *type, double *e, double *f,
                    double *w, const double *e_bar, const double *f_bar, double *xg, double *pg,
                    hipStream_t s) {
@@ -1260,13 +1262,15 @@ void batch_enqueue(ters_plan *p, const double *x, const int32_t *type, double *e
   NList &nl = p->nl;
   nlist_build(nl, x, type, c->ntypes, nullptr, p->errw.as<uint32_t>(), s);
   launch_fill_i32(p->queue.as<int32_t>(), 0, 16, nullptr, s);
-  FwdArgs a = batch_fwd_args(p, x, type, f);
-  launch_fill_f64(p->partials.as<double>(), 0.0, 8 * (int64_t)p->nconf, s);
-  if (f && !p->gather) launch_fill_f64(f, 0.0, 3 * (int64_t)p->N, s);
-  launch_forward_wave(a, p->precision, p->A, s);
-  if (f && p->gather) launch_gather(nl, a.fslot, p->precision == TERS_MIXED, a.fown, f, 0, s);
-  if (e || w)
-    k_split_partials<<<(p->nconf + 255) / 256, 256, 0, s>>>(p->partials.as<double>(), p->nconf, e, w);
+  if (e || f || w || !f_bar) {
+    FwdArgs a = batch_fwd_args(p, x, type, f);
+    launch_fill_f64(p->partials.as<double>(), 0.0, 8 * (int64_t)p->nconf, s);
+    if (f && !p->gather) launch_fill_f64(f, 0.0, 3 * (int64_t)p->N, s);
+    launch_forward_wave(a, p->precision, p->A, s);
+    if (f && p->gather) launch_gather(nl, a.fslot, p->precision == TERS_MIXED, a.fown, f, 0, s);
+    if (e || w)
+      k_split_partials<<<(p->nconf + 255) / 256, 256, 0, s>>>(p->partials.as<double>(), p->nconf, e, w);
+  }
   if (f_bar) {
     FwdArgs b = batch_adj_args(p, x, type, e_bar, f_bar, xg, pg);
     const int nt = c->ntypes;

@@ -342,7 +342,8 @@ def test_batch_alternating_runs_replay_their_own_graphs(batch_setup, precision):
     """Forward-only runs and runs with the adjoint alternate on one plan (the
     fitting loop): each replays the graph of its own argument set, also after
     runs with four other argument sets have replaced both graphs in the
-    plan's cache, and gives the results of its first run."""
+    plan's cache, and gives the results of its first run; a run that asks
+    for the gradients alone gives those of a run with the forward pass."""
     from paper_1607_02904_amd.tersoff import BatchPlan
     confs, model = batch_setup
     nat, boxes, x, t = _cat(confs)
@@ -376,6 +377,13 @@ def test_batch_alternating_runs_replay_their_own_graphs(batch_setup, precision):
     first_f, first_a = run(False), run(True)
     for k in range(3):
         assert np.allclose(first_a[k], first_f[k], rtol=1e-13, atol=1e-13)
+    # gradients alone (no forward outputs: the graph leaves the forward pass out)
+    xg.fill_(float("nan"))
+    pg.fill_(float("nan"))
+    plan.run(xd, td, None, None, None, eb, fb, xg, pg)
+    torch.cuda.synchronize()
+    assert np.allclose(xg.cpu().numpy(), first_a[3], rtol=1e-13, atol=1e-13)
+    assert np.allclose(pg.cpu().numpy(), first_a[4], rtol=1e-13, atol=1e-13)
     for rep in range(2):
         for _ in range(2):
             got_f, got_a = run(False), run(True)
