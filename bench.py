@@ -59,6 +59,9 @@ def parse():
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration)")
     ap.add_argument("--md-only", action="store_true", help="only the headline MD workload")
+    ap.add_argument("--workload", choices=["batch", "fitting"],
+                    help="run one of the other workloads alone and print its figures as one "
+                         "JSON object (no headline line; for kernel traces of that workload)")
     return ap.parse_args()
 
 
@@ -150,6 +153,15 @@ def main():
                                               table_element, table_sic)
 
     dev = "cuda"
+    if args.workload:
+        out = {}
+        if args.workload == "batch":
+            run_batch(args, out, dev)
+        else:
+            print("bench: fitting frames", file=sys.stderr, flush=True)
+            out["fitting_64x512"] = run_fitting(dev)
+        print(json.dumps(out), flush=True)
+        return
     if args.copy_probe:
         # plain copy of known size: 256 MiB read + 256 MiB written per launch
         a = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device=dev)

@@ -11,6 +11,10 @@ Four reports, all plain text:
   the same counter reads for a plain device copy of known size in the same
   run, with the hash of the kernel's sources so that a reader can tell whether
   the figure still applies to the kernel as built;
+* ``tail``: from a ``--kernel-trace`` kernel_trace.csv, the last N
+  dispatches of every kernel whose name contains one of the filters (the
+  timed launches of a run come last, after its autotuner's candidates):
+  count, average, minimum and maximum duration, by total time;
 * ``rebuild``: from a ``--kernel-trace`` kernel_trace.csv, the average
   duration of every list kernel over the molecular-dynamics steps that
   rebuilt the list and over those that did not (the list kernels of a step
@@ -23,6 +27,7 @@ Four reports, all plain text:
     python -m paper_1607_02904_amd.profsum mix PMC_CSV [PMC_CSV ...] \\
         --kernel NAME_PART --grid GRID
     python -m paper_1607_02904_amd.profsum rebuild TRACE_CSV [--threshold-us US]
+    python -m paper_1607_02904_amd.profsum tail TRACE_CSV [FILTER ...] --last N
 
 The copy kernel is the dispatch whose name contains ``copyBuffer`` and whose
 ``FETCH_SIZE`` is largest.
@@ -155,6 +160,26 @@ def rebuild(path, threshold_us):
     return out
 
 
+def tail(path, filters, last):
+    """Durations (us) of the last `last` dispatches of each kernel whose
+    name contains one of the filters, one line per kernel, by total time."""
+    per = {}
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            name = r["Kernel_Name"]
+            if filters and not any(flt in name for flt in filters):
+                continue
+            t0, t1 = int(r["Start_Timestamp"]), int(r["End_Timestamp"])
+            per.setdefault(name, []).append((t0, (t1 - t0) / 1e3))
+    lines = []
+    for name, v in per.items():
+        v.sort()
+        d = [x for _, x in v[-last:]]
+        lines.append((sum(d), "%-90.90s dispatches %4d  avg_us %9.2f  min_us %9.2f  max_us %9.2f"
+                      % (name, len(d), sum(d) / len(d), min(d), max(d))))
+    return [line for _, line in sorted(lines, reverse=True)]
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -174,9 +199,15 @@ def main():
     b = sub.add_parser("rebuild")
     b.add_argument("csv")
     b.add_argument("--threshold-us", type=float, default=8.0)
+    l = sub.add_parser("tail")
+    l.add_argument("csv")
+    l.add_argument("filters", nargs="*")
+    l.add_argument("--last", type=int, required=True)
     a = ap.parse_args()
     if a.cmd == "stats":
         print("\n".join(stats(a.csv, a.filters)))
+    elif a.cmd == "tail":
+        print("\n".join(tail(a.csv, a.filters, a.last)))
     elif a.cmd == "rebuild":
         for key, (count, per, total) in rebuild(a.csv, a.threshold_us).items():
             print("%s_steps: %d" % (key, count))
