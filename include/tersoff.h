@@ -225,31 +225,33 @@ ters_status ters_md_rebuilds(ters_ctx *ctx, int64_t *out);
  * A plan covers nconf configurations concatenated along the atom axis:
  * natoms_host[c] atoms each (config c occupies rows off_c .. off_c+n_c-1 with
  * off_c = sum of earlier n), boxes_host [nconf][3].  Lists are built with
- * skin 0.  The plan owns device scratch, the autotuned schedule and a hipGraph
- * of the whole evaluation.  ters_batch_run evaluates all configurations with
- * one graph launch: energies e[nconf], forces f_cat[N][3], virials w[nconf][6]
- * (device, FP64; any may be NULL).  If f_bar is non-NULL the graph also runs
- * the adjoint with per-configuration e_bar[nconf] (device) and f_bar_cat
- * [N][3] (device), writing x_grad_cat [N][3] and param_grad (summed over
- * configurations) [ntypes^3][14]; with f_bar set and e, f_cat and w all
- * NULL the forward pass is left out (the adjoint does not need its
+ * skin 0.  The plan owns device scratch, the autotuned schedule and the
+ * hipGraphs of the evaluation.  ters_batch_run evaluates all configurations
+ * with one graph launch: energies e[nconf], forces f_cat[N][3], virials
+ * w[nconf][6] (device, FP64; any may be NULL).  If f_bar is non-NULL the
+ * graph also runs the adjoint with per-configuration e_bar[nconf] (device)
+ * and f_bar_cat [N][3] (device), writing x_grad_cat [N][3] and param_grad
+ * (summed over configurations) [ntypes^3][14]; with f_bar set and e, f_cat
+ * and w all NULL the forward pass is left out (the adjoint does not need its
  * results: a fitting loop that has the energies and forces of these
- * positions from a forward-only run asks for the gradients alone).
- * x_cat, type_cat device.  Inside the
- * graph: the lists of all configurations (one set of launches), then one
- * persistent launch of the wavefront force kernel whose workgroups (as many
- * as stay resident on the device) take chunks of atoms, never spanning two
- * configurations, from eight work queues (one per XCD, atomic counters reset
- * at the start of the graph) until all are done, and, with f_bar, one such
- * launch of the adjoint kernel.  The atoms per chunk of each pass are timed
- * on the data of the first run that needs the pass (synchronising).  The
- * pointers of a run are baked into its graph: the plan keeps the graphs of
- * the four most recently used argument sets (a forward-only run and a run
+ * positions from a forward-only run asks for the gradients alone).  x_cat,
+ * type_cat device.
+ * Inside the graph: the lists of all configurations (one set of launches),
+ * then one persistent launch of the wavefront force kernel whose workgroups
+ * (as many as stay resident on the device, or as the chunks keep busy when
+ * they are fewer) take chunks of atoms, never spanning two configurations,
+ * from eight work queues (one per XCD, atomic counters reset at the start of
+ * the graph) until all are done, and, with f_bar, one such launch of the
+ * adjoint kernel.  The atoms per chunk of each pass are timed on the data of
+ * the first run that needs the pass (synchronising).
+ * The pointers of a run are baked into its graph: the plan keeps the graphs
+ * of the four most recently used argument sets (a forward-only run and a run
  * with the adjoint, alternating, replay two graphs), and a run with another
- * set captures a new one in place of the least recently launched.  Errors latched by the graph (list overflow,
- * non-finite positions, species outside the table) are reported by
- * ters_sync.  A plan refuses runs once ters_set_params changed the number of
- * species or raised a cutoff beyond the plan's list radius. */
+ * set captures a new one in place of the least recently launched.  Errors
+ * latched by the graph (list overflow, non-finite positions, species outside
+ * the table) are reported by ters_sync.  A plan refuses runs once
+ * ters_set_params changed the number of species or raised a cutoff beyond
+ * the plan's list radius. */
 ters_status ters_batch_plan(ters_ctx *ctx, int32_t nconf, const int32_t *natoms_host,
                             const double *boxes_host, int precision, uint32_t flags,
                             ters_plan **out);
