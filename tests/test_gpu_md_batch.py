@@ -207,6 +207,54 @@ def test_batch_extreme_sizes(orc, batch_setup):
         plan.close()
 
 
+@pytest.mark.parametrize("nconf", [1, 3])
+def test_batch_few_chunks(orc, batch_setup, nconf):
+    """Batches of one and of three 64-atom configurations: far fewer chunks
+    than the device holds wavefronts, so the persistent launches take a grid
+    sized to the chunks (one workgroup per chunk of the forward pass, at least
+    eight: one per XCD queue), and wavefronts find queues used up while others
+    still work.  Forward against the oracle, FP64 and mixed; the adjoint
+    against the single-system entry points."""
+    _, model = batch_setup
+    confs = inputs.sic_liquid_batch(nconf=nconf, nmin=64, nmax=64, seed=70 + nconf)
+    for precision in (0, 1):
+        plan, out = _run_plan(model, confs, precision, adjoint=True, seed=9)
+        xd, td, e, f, w, eb, fb, xg, pg = out
+        sch = plan.schedule()
+        chunks = nconf * -(-64 // sch["atoms"])
+        assert 8 <= sch["workgroups"] <= max(8, chunks), (sch, chunks)
+        _check_batch(orc, confs, plan.offsets, e.cpu().numpy(), f.cpu().numpy(),
+                     w.cpu().numpy(), precision)
+        off = plan.offsets
+        pg_sum = np.zeros((2, 2, 2, 14))
+        xg_all = xg.cpu().numpy()
+        # FP64 element by element; mixed as the norm of the difference (the
+        # same schedule, FP32 sums in another order)
+        model.set_schedule(sch["kernel"], sch["atoms"], 0)
+        try:
+            for c, (xc, tc, bc) in enumerate(confs):
+                xcd = torch.as_tensor(xc, device="cuda")
+                tcd = torch.as_tensor(tc, device="cuda")
+                model.build_nlist(xcd, tcd, bc, 0.0)
+                xgc, pgc = model.backward(xcd, tcd, bc, float(eb[c].item()),
+                                          fb[off[c]:off[c + 1]].contiguous(), precision)
+                torch.cuda.synchronize()
+                pg_sum += pgc.cpu().numpy()
+                a, b = xg_all[off[c]:off[c + 1]], xgc.cpu().numpy()
+                if precision == 0:
+                    assert np.allclose(a, b, rtol=1e-11, atol=1e-12)
+                else:
+                    assert np.linalg.norm(a - b) <= 1e-6 * np.linalg.norm(b)
+        finally:
+            model.set_schedule(0, 0, 0)
+        a = pg.cpu().numpy()
+        if precision == 0:
+            assert np.allclose(a, pg_sum, rtol=1e-11, atol=1e-12)
+        else:
+            assert np.linalg.norm(a - pg_sum) <= 1e-6 * np.linalg.norm(pg_sum)
+        plan.close()
+
+
 def test_batch_mixed_adjoint_matches_single_calls(batch_setup):
     """The batched mixed forward + adjoint (the benchmark's batched figure, in
     the plan's autotuned schedule) equals per-configuration calls of the
