@@ -411,6 +411,10 @@ class BatchPlan:
 
     def run(self, x, types, e=None, f=None, w=None, e_bar=None, f_bar=None, x_grad=None,
             param_grad=None):
+        """Evaluate every configuration (ters_batch_run): energies e, forces f
+        and virials w, any of them None; with f_bar (and e_bar, x_grad,
+        param_grad) also the adjoint.  With f_bar given and e, f, w all None
+        the graph runs the list build and the adjoint alone."""
         self.model._bind_stream()
         N = int(self.offsets[-1])
         _check(self.model._h, self._L.ters_batch_run(
