@@ -1186,6 +1186,17 @@ __global__ void k_split_partials(const double *partials, int nconf, double *e, d
     for (int k = 0; k < 6; ++k) w[(int64_t)c * 6 + k] = partials[(int64_t)c * 8 + 1 + k];
 }
 
+// Start of a batch evaluation: the 16 queue counters, the per-configuration
+// energy and virial records [npart] and, when set, the parameter gradient
+// [npg] set to zero by one launch.
+__global__ void k_batch_clear(int32_t *queue, double *partials, int64_t npart, double *pg,
+                              int64_t npg) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < 16) queue[i] = 0;
+  if (i < npart) partials[i] = 0.0;
+  if (pg && i < npg) pg[i] = 0.0;
+}
+
 // Chunks of A atoms that never straddle two configurations (the atoms of
 // configuration c occupy cell-order positions [off_c, off_c + n_c)), dealt to
 // eight queues as contiguous ranges; uploaded to items / qb.
@@ -1261,10 +1272,16 @@ void batch_enqueue(ters_plan *p, const double *x, const int32_t *type, double *e
   ters_ctx *c = p->ctx;
   NList &nl = p->nl;
   nlist_build(nl, x, type, c->ntypes, nullptr, p->errw.as<uint32_t>(), s);
-  launch_fill_i32(p->queue.as<int32_t>(), 0, 16, nullptr, s);
+  {
+    const int nt = c->ntypes;
+    const int64_t npart = 8 * (int64_t)p->nconf;
+    const int64_t npg = f_bar ? (int64_t)nt * nt * nt * kNField : 0;
+    const int64_t m = std::max<int64_t>(16, std::max(npart, npg));
+    k_batch_clear<<<(unsigned)((m + 255) / 256), 256, 0, s>>>(p->queue.as<int32_t>(), p->partials.as<double>(),
+                                                             npart, f_bar ? pg : nullptr, npg);
+  }
   if (e || f || w || !f_bar) {
     FwdArgs a = batch_fwd_args(p, x, type, f);
-    launch_fill_f64(p->partials.as<double>(), 0.0, 8 * (int64_t)p->nconf, s);
     if (f && !p->gather) launch_fill_f64(f, 0.0, 3 * (int64_t)p->N, s);
     launch_forward_wave(a, p->precision, p->A, s);
     if (f && p->gather) launch_gather(nl, a.fslot, p->precision == TERS_MIXED, a.fown, f, 0, s);
@@ -1273,8 +1290,6 @@ void batch_enqueue(ters_plan *p, const double *x, const int32_t *type, double *e
   }
   if (f_bar) {
     FwdArgs b = batch_adj_args(p, x, type, e_bar, f_bar, xg, pg);
-    const int nt = c->ntypes;
-    launch_fill_f64(pg, 0.0, (int64_t)nt * nt * nt * kNField, s);
     if (!p->gather) launch_fill_f64(xg, 0.0, 3 * (int64_t)p->N, s);
     launch_adjoint_wave(b, p->precision, p->A_adj, s);
     if (p->gather) launch_gather(nl, b.fslot, p->precision == TERS_MIXED, b.fown, xg, 0, s);
