@@ -94,3 +94,17 @@ def test_traffic_scales_each_counter_by_the_copy_kernel(tmp_path):
     assert r["fetch_dispatches"] == 2 and r["fetch_kib_per_launch"] == 200.0
     assert r["fetch_scale"] == 2.0 and r["write_scale"] == 1.0
     assert r["traffic_bytes_per_launch"] == 1024.0 * (200.0 * 2.0 + 40.0 * 1.0)
+
+
+def test_mix_averages_each_counter_per_dispatch_over_runs(tmp_path):
+    # two counter runs of the same kernel: run a has two dispatches (the
+    # counter reported in two instances for the first), run b one dispatch
+    a = [(1, "k_force_wave<float>", 640, "SQ_INSTS_VALU", 70), (1, "k_force_wave<float>", 640, "SQ_INSTS_VALU", 30),
+         (2, "k_force_wave<float>", 640, "SQ_INSTS_VALU", 300), (3, "k_build", 640, "SQ_INSTS_VALU", 5)]
+    b = [(1, "k_force_wave<float>", 640, "SQ_INSTS_LDS", 12), (2, "k_force_wave<float>", 128, "SQ_INSTS_LDS", 99)]
+    pa, pb = tmp_path / "a.csv", tmp_path / "b.csv"
+    _counters(pa, a)
+    _counters(pb, b)
+    r, counts = profsum.mix([str(pa), str(pb)], "k_force_wave<float>", 640)
+    assert r == {"SQ_INSTS_VALU": 200.0, "SQ_INSTS_LDS": 12.0}
+    assert counts == {"SQ_INSTS_VALU": 2, "SQ_INSTS_LDS": 1}
