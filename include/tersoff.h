@@ -225,7 +225,11 @@ ters_status ters_md_rebuilds(ters_ctx *ctx, int64_t *out);
  * A plan covers nconf configurations concatenated along the atom axis:
  * natoms_host[c] atoms each (config c occupies rows off_c .. off_c+n_c-1 with
  * off_c = sum of earlier n), boxes_host [nconf][3].  Lists are built with
- * skin 0.  The plan owns device scratch, the autotuned schedule and the
+ * skin 0, inside each run's graph, and only when an atom is not where the
+ * last build found it (bitwise, up to whole box vectors), a species lies
+ * outside the table or the last build overflowed a row: a fitting loop over
+ * fixed frames builds them once.  The plan owns device scratch, the
+ * autotuned schedule and the
  * hipGraphs of the evaluation.  ters_batch_run evaluates all configurations
  * with one graph launch: energies e[nconf], forces f_cat[N][3], virials
  * w[nconf][6] (device, FP64; any may be NULL).  If f_bar is non-NULL the

@@ -19,6 +19,14 @@
 
 using namespace ters;
 
+namespace ters {
+// (nlist.hip) flag, zeroed by the caller, <- 1 when any atom is not where the
+// last build found it (minimum image), a species lies outside [0, ntypes) or
+// the last build overflowed a row: a build is due (batch lists have no skin)
+void nlist_check_moved(const NList &nl, const double *x, const int32_t *type, int ntypes,
+                       int32_t *flag, hipStream_t s);
+}  // namespace ters
+
 constexpr int kMdGraphSteps = 8;  // molecular-dynamics steps per replayed graph
 constexpr int kPlanGraphs = 4;    // instantiated evaluation graphs kept per batch plan
 
@@ -57,6 +65,7 @@ struct ters_plan {
   std::vector<int32_t> natoms, off;
   NList nl;
   DevBuf partials, ebuf, errw, fslot, fown;
+  DevBuf rflag;  // int32: a list build is due in this evaluation
   // persistent wavefront schedule of the forward (f) and adjoint (a) pass:
   // atoms per chunk, chunk items with their eight queue ranges, workgroups
   int A = 0, A_adj = 0, gather = 1, grid_f = 0, grid_a = 0, grab_f = 1, grab_a = 1;
@@ -1186,12 +1195,13 @@ __global__ void k_split_partials(const double *partials, int nconf, double *e, d
     for (int k = 0; k < 6; ++k) w[(int64_t)c * 6 + k] = partials[(int64_t)c * 8 + 1 + k];
 }
 
-// Start of a batch evaluation: the 16 queue counters, the per-configuration
-// energy and virial records [npart] and, when set, the parameter gradient
-// [npg] set to zero by one launch.
+// Start of a batch evaluation: the rebuild flag, the 16 queue counters, the
+// per-configuration energy and virial records [npart] and, when set, the
+// parameter gradient [npg] set to zero by one launch.
 __global__ void k_batch_clear(int32_t *queue, double *partials, int64_t npart, double *pg,
-                              int64_t npg) {
+                              int64_t npg, int32_t *rflag) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) *rflag = 0;
   if (i < 16) queue[i] = 0;
   if (i < npart) partials[i] = 0.0;
   if (pg && i < npg) pg[i] = 0.0;
@@ -1271,15 +1281,19 @@ void batch_enqueue(ters_plan *p, const double *x, const int32_t *type, double *e
                    hipStream_t s) {
   ters_ctx *c = p->ctx;
   NList &nl = p->nl;
-  nlist_build(nl, x, type, c->ntypes, nullptr, p->errw.as<uint32_t>(), s);
   {
     const int nt = c->ntypes;
     const int64_t npart = 8 * (int64_t)p->nconf;
     const int64_t npg = f_bar ? (int64_t)nt * nt * nt * kNField : 0;
     const int64_t m = std::max<int64_t>(16, std::max(npart, npg));
     k_batch_clear<<<(unsigned)((m + 255) / 256), 256, 0, s>>>(p->queue.as<int32_t>(), p->partials.as<double>(),
-                                                             npart, f_bar ? pg : nullptr, npg);
+                                                             npart, f_bar ? pg : nullptr, npg,
+                                                             p->rflag.as<int32_t>());
   }
+  // the lists are built again only when an atom is not where the last build
+  // found it (or a species is out of range, or the last build overflowed)
+  nlist_check_moved(nl, x, type, c->ntypes, p->rflag.as<int32_t>(), s);
+  nlist_build(nl, x, type, c->ntypes, p->rflag.as<int32_t>(), p->errw.as<uint32_t>(), s);
   if (e || f || w || !f_bar) {
     FwdArgs a = batch_fwd_args(p, x, type, f);
     if (f && !p->gather) launch_fill_f64(f, 0.0, 3 * (int64_t)p->N, s);
@@ -1339,6 +1353,7 @@ ters_status ters_batch_plan(ters_ctx *c, int32_t nconf, const int32_t *natoms,
     p->partials.ensure(sizeof(double) * 8 * nconf);
     p->errw.ensure(64);
     TERS_HIP_TRY(hipMemsetAsync(p->errw.p, 0, 64, c->stream));
+    p->rflag.ensure(64);
     sync(c);
     return TERS_OK;
   });
@@ -1452,7 +1467,7 @@ ters_status ters_batch_run(ters_plan *p, const double *x, const int32_t *type, d
       p->tuned_adj = true;
     }
     std::vector<const void *> key = graph_key(c, nl);
-    const void *extra[] = {x, type, e, f, w, e_bar, f_bar, xg, pg, p->partials.p, p->errw.p,
+    const void *extra[] = {x, type, e, f, w, e_bar, f_bar, xg, pg, p->partials.p, p->errw.p, p->rflag.p,
                            (const void *)(intptr_t)p->A, (const void *)(intptr_t)p->precision,
                            (const void *)(intptr_t)p->A_adj, p->fslot.p, p->fown.p,
                            (const void *)(intptr_t)p->gather, p->items_f.p, p->qb_f.p, p->items_a.p,
@@ -1505,7 +1520,7 @@ static void plan_release_device(ters_plan *p) {
   for (auto &g : p->graphs)
     if (g.exec) hipGraphExecDestroy(g.exec);
   p->graphs.clear();
-  DevBuf *bufs[] = {&p->partials, &p->ebuf, &p->errw, &p->fslot, &p->fown, &p->items_f,
+  DevBuf *bufs[] = {&p->partials, &p->ebuf, &p->errw, &p->rflag, &p->fslot, &p->fown, &p->items_f,
                     &p->qb_f, &p->items_a, &p->qb_a, &p->queue, &p->nl.conf,
                     &p->nl.conf_of, &p->nl.count, &p->nl.list, &p->nl.order, &p->nl.cell_next,
                     &p->nl.cell_head, &p->nl.cell_count, &p->nl.cell_bucket,

@@ -697,9 +697,14 @@ __global__ void k_gather(int n, const int2 *__restrict__ srange_a, const S *__re
   }
 }
 
+// flag <- 1 when an atom moved farther than sqrt(lim2) (minimum image) since
+// the last build; with type set also when a species lies outside [0, ntypes),
+// and with maxcount set when the last build overflowed a row (so that the
+// build runs again and reports it)
 __global__ void k_check(int n, const double *__restrict__ x, const double *__restrict__ xref,
                         const ConfDesc *__restrict__ conf, const int32_t *__restrict__ conf_of,
-                        double lim2, int32_t *flag) {
+                        double lim2, int32_t *flag, const int32_t *__restrict__ type, int ntypes,
+                        const int32_t *maxcount) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   bool over = false;
   if (i < n) {
@@ -712,7 +717,9 @@ __global__ void k_check(int n, const double *__restrict__ x, const double *__res
       r2 += d * d;
     }
     over = !(r2 <= lim2);  // NaN counts as moved
+    if (type && (unsigned)type[i] >= (unsigned)ntypes) over = true;
   }
+  if (maxcount && i == 0 && *maxcount > 0) over = true;
   if (__ballot(over) != 0ull && lane_id() == 0) *flag = 1;
 }
 
@@ -841,7 +848,16 @@ void nlist_check(const NList &nl, const double *x, int32_t *flag, hipStream_t s)
   k_check<<<grid_for(nl.n, kBS), kBS, 0, s>>>(nl.n, x, nl.xref.as<double>(),
                                               nl.conf.as<ConfDesc>(),
                                               nl.nconf > 1 ? nl.conf_of.as<int32_t>() : nullptr,
-                                              half * half, flag);
+                                              half * half, flag, nullptr, 0, nullptr);
+}
+
+void nlist_check_moved(const NList &nl, const double *x, const int32_t *type, int ntypes,
+                       int32_t *flag, hipStream_t s) {
+  if (nl.n <= 0) return;
+  k_check<<<grid_for(nl.n, kBS), kBS, 0, s>>>(nl.n, x, nl.xref.as<double>(),
+                                              nl.conf.as<ConfDesc>(),
+                                              nl.nconf > 1 ? nl.conf_of.as<int32_t>() : nullptr,
+                                              0.0, flag, type, ntypes, nl.maxcount.as<int32_t>());
 }
 
 }  // namespace ters

@@ -505,6 +505,59 @@ def test_long_run_total_energy_tracks_fp64(si_model, precision):
         assert (e[1:].max() - e[1:].min()) / n < 1e-4
 
 
+def test_batch_builds_lists_only_when_atoms_moved(orc, batch_setup):
+    """A plan builds its lists again only when an atom is not where the last
+    build found it.  The same positions again: the same results (lists
+    reused).  Positions permuted within every configuration (types kept): the
+    oracle's results for the new positions, which a reused list would miss
+    entirely.  A species out of range with unchanged positions, and a list
+    that overflowed, are still reported by every run."""
+    from paper_1607_02904_amd.tersoff import TersoffError
+    confs, model = batch_setup
+    confs = confs[:6]
+    plan, (xd, td, e, f, w) = _run_plan(model, confs, 0)
+    first = [a.cpu().numpy().copy() for a in (e, f, w)]
+    plan.run(xd, td, e, f, w)
+    model.sync()
+    for a, b in zip(first, (e, f, w)):
+        assert np.allclose(a, b.cpu().numpy(), rtol=1e-13, atol=1e-13)
+    nat, boxes, x, t = _cat(confs)
+    off = plan.offsets
+    xp = x.copy()
+    for c in range(len(confs)):  # reverse the atoms' positions in each configuration
+        xp[off[c]:off[c + 1]] = x[off[c]:off[c + 1]][::-1]
+    xd.copy_(torch.as_tensor(xp, device="cuda"))
+    plan.run(xd, td, e, f, w)
+    model.sync()
+    moved = [(xp[off[c]:off[c + 1]], confs[c][1], confs[c][2]) for c in range(len(confs))]
+    _check_batch(orc, moved, off, e.cpu().numpy(), f.cpu().numpy(), w.cpu().numpy(), 0)
+    # a species outside the table, positions unchanged
+    tbad = td.clone()
+    tbad[3] = 7
+    plan.run(xd, tbad, e, f, w)
+    with pytest.raises(TersoffError) as ei:
+        model.sync()
+    assert ei.value.name == "TERS_ERR_INVALID_ARG"
+    plan.run(xd, td, e, f, w)
+    model.sync()
+    # an overflowing list is reported by the run that builds it and, with the
+    # positions unchanged, by the next run too
+    xs = xp.copy()
+    for c in range(len(confs)):
+        xs[off[c]:off[c + 1]] = 0.7 * inputs.wrap(xp[off[c]:off[c + 1]], boxes[c])
+    xd.copy_(torch.as_tensor(xs, device="cuda"))
+    for _ in range(2):
+        plan.run(xd, td, e, f, w)
+        with pytest.raises(TersoffError) as ei:
+            model.sync()
+        assert ei.value.name == "TERS_ERR_NLIST_OVERFLOW"
+    xd.copy_(torch.as_tensor(x, device="cuda"))
+    plan.run(xd, td, e, f, w)
+    model.sync()
+    _check_batch(orc, confs, off, e.cpu().numpy(), f.cpu().numpy(), w.cpu().numpy(), 0)
+    plan.close()
+
+
 def test_batch_run_reports_list_overflow(batch_setup):
     """A plan sizes its list on its first run; a later run whose atoms are
     packed more densely overflows the rows.  The graph latches the error in
