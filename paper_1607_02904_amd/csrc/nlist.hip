@@ -483,10 +483,13 @@ __global__ __launch_bounds__(BS) void k_build(int n, const float4 *__restrict__ 
   // wavefront that touch the box's faces.  Only the near run of the middle
   // row holds the atom itself.
   constexpr int U = 4;
-  auto walk = [&](auto far_c, auto yz_c, auto mid_c, int r, int b, int e)
+  // MI: the minimum image per candidate; a wavefront whose atoms all lie in
+  // configurations of at least three cells per axis takes the cell's fixed
+  // image instead (the same arithmetic as the MI form gives them)
+  auto walk = [&](auto far_c, auto yz_c, auto mid_c, auto mi_c, int r, int b, int e)
                   __attribute__((always_inline)) {
     constexpr bool FAR = decltype(far_c)::value, YZ = decltype(yz_c)::value;
-    constexpr bool MID = decltype(mid_c)::value;
+    constexpr bool MID = decltype(mid_c)::value, MI = decltype(mi_c)::value;
     for (int k0 = b; k0 < e; k0 += U) {
       float4 q[U];
       const float4 *src = xs + k0;
@@ -495,7 +498,7 @@ __global__ __launch_bounds__(BS) void k_build(int n, const float4 *__restrict__ 
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         float dx = q[u].x - qi.x, dy = q[u].y - qi.y, dz = q[u].z - qi.z;
-        if (!MINIMG) {
+        if (!MI) {
           if (FAR) dx += sfx;
           if (YZ) {
             dy += sy[r];
@@ -522,17 +525,26 @@ __global__ __launch_bounds__(BS) void k_build(int n, const float4 *__restrict__ 
   };
   using TT = std::true_type;
   using FF = std::false_type;
+  auto walk_rows = [&](auto mi_c) __attribute__((always_inline)) {
 #pragma unroll
-  for (int r = 0; r < 9; ++r) {
-    const bool yz = __ballot(sy[r] != 0.f || sz[r] != 0.f) != 0ull;  // uniform
-    if (r == 4) {
-      if (yz) walk(FF(), TT(), TT(), r, nb[r], ne[r]);
-      else walk(FF(), FF(), TT(), r, nb[r], ne[r]);
-    } else {
-      if (yz) walk(FF(), TT(), FF(), r, nb[r], ne[r]);
-      else walk(FF(), FF(), FF(), r, nb[r], ne[r]);
+    for (int r = 0; r < 9; ++r) {
+      const bool yz = __ballot(sy[r] != 0.f || sz[r] != 0.f) != 0ull;  // uniform
+      if (r == 4) {
+        if (yz) walk(FF(), TT(), TT(), mi_c, r, nb[r], ne[r]);
+        else walk(FF(), FF(), TT(), mi_c, r, nb[r], ne[r]);
+      } else {
+        if (yz) walk(FF(), TT(), FF(), mi_c, r, nb[r], ne[r]);
+        else walk(FF(), FF(), FF(), mi_c, r, nb[r], ne[r]);
+      }
+      if (__ballot(fe[r] > fb[r]) != 0ull) walk(TT(), TT(), FF(), mi_c, r, fb[r], fe[r]);
     }
-    if (__ballot(fe[r] > fb[r]) != 0ull) walk(TT(), TT(), FF(), r, fb[r], fe[r]);
+  };
+  if constexpr (!MINIMG) {
+    walk_rows(FF());
+  } else if (__ballot(act && !fixed) == 0ull) {  // uniform: every atom's image is fixed
+    walk_rows(FF());
+  } else {
+    walk_rows(TT());
   }
   if (act) {
     count[t] = cnt;
